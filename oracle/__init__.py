@@ -1,0 +1,210 @@
+"""FP64 CPU oracle for the SU(2) pf-FRG flow (arXiv:2109.13317).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` may import this package; the GPU library and its
+Python binding never do.  It shares no code with the GPU path.
+
+Contents
+  ``pffrg_oracle.c``   plain C right-hand side and correlations on the
+                       unreduced (translation-only) lattice, see its header;
+  ``sites.py``         the unreduced lattice: every site within the
+                       bond-distance range of each basis site (Sec. 4.1);
+  ``literal.py``       a second, independent evaluation of the explicit
+                       spin-index flow equations with 2x2 spin tensors and
+                       complex propagators, for tiny grids;
+  this module          the ctypes binding, initial conditions and the
+                       explicit ODE steppers (Euler, classical RK4,
+                       Dormand-Prince 5(4)).
+
+Parity status of each function is recorded in the design notes; the pins
+live in ``tests/test_oracle_*.py``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+from .sites import UnreducedLattice
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pffrg_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (FP64, no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Lat(ctypes.Structure):
+    _fields_ = [("nf", ctypes.c_int), ("w", ctypes.c_void_p), ("nb", ctypes.c_int),
+                ("ns", ctypes.c_int), ("nsites", ctypes.c_void_p), ("cell", ctypes.c_void_p),
+                ("bas", ctypes.c_void_p), ("rm", ctypes.c_int), ("lookup", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        D = ctypes.c_double
+        I = ctypes.c_int
+        lib.orc_state_size.restype = ctypes.c_long
+        lib.orc_state_size.argtypes = [P]
+        lib.orc_sigma_rhs.argtypes = [P, D, P, P]
+        lib.orc_sigma_rhs.restype = None
+        lib.orc_rhs.argtypes = [P, D, P, P, I]
+        lib.orc_rhs.restype = None
+        lib.orc_vertex_rhs_element.argtypes = [P, D, P, P, I, I, I, I, I, P]
+        lib.orc_vertex_rhs_element.restype = None
+        lib.orc_vertex_rhs_triples.argtypes = [P, D, P, P, I, P, P, P, P, I]
+        lib.orc_vertex_rhs_triples.restype = None
+        lib.orc_chi.argtypes = [P, D, P, P, P]
+        lib.orc_chi.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Oracle:
+    """The oracle on one lattice model and one frequency mesh.
+
+    State layout (oracle-private): sig[nf] | Gs[nb][n_su][nf][ns] | Gd[...]
+    where n_su enumerates mesh index pairs a >= c of (s, u) as a(a+1)/2 + c
+    and ns pads every basis site's site list to the same length.
+    """
+
+    def __init__(self, model, lattice_range: int, mesh: np.ndarray, threads: int = 0):
+        self.lat = UnreducedLattice(model, lattice_range)
+        self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
+        self.nf = len(self.mesh)
+        self.threads = int(threads)
+        lat = self.lat
+        self._keep = [self.mesh, lat.nsites, lat.cell, lat.bas, lat.lookup]
+        self._s = _Lat(self.nf, self.mesh.ctypes.data, lat.nb, lat.ns, lat.nsites.ctypes.data,
+                       lat.cell.ctypes.data, lat.bas.ctypes.data, lat.rm, lat.lookup.ctypes.data)
+        self._p = ctypes.byref(self._s)
+        self.lib = _load()
+        self.n_su = self.nf * (self.nf + 1) // 2
+        self.size = int(self.lib.orc_state_size(self._p))
+        self.vsize = lat.nb * self.n_su * self.nf * lat.ns
+
+    # ---------------------------------------------------------- layout --
+    def split(self, x: np.ndarray):
+        """Views (sig, Gs, Gd) with Gs/Gd shaped [nb, n_su, nf, ns]."""
+        lat = self.lat
+        sig = x[: self.nf]
+        gs = x[self.nf: self.nf + self.vsize].reshape(lat.nb, self.n_su, self.nf, lat.ns)
+        gd = x[self.nf + self.vsize:].reshape(lat.nb, self.n_su, self.nf, lat.ns)
+        return sig, gs, gd
+
+    def initial_state(self) -> np.ndarray:
+        """Sigma = 0, spin vertex = J_ij/4, density vertex = 0 (Eq. 14, Eq. 21)."""
+        x = np.zeros(self.size)
+        _, gs, _ = self.split(x)
+        gs[...] = (self.lat.coupling / 4.0)[:, None, None, :]
+        return x
+
+    # ------------------------------------------------------------- RHS --
+    def sigma_rhs(self, lam: float, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(self.nf)
+        self.lib.orc_sigma_rhs(self._p, float(lam), _ptr(x), _ptr(out))
+        return out
+
+    def rhs(self, lam: float, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(self.size)
+        self.lib.orc_rhs(self._p, float(lam), _ptr(x), _ptr(out), self.threads)
+        return out
+
+    def vertex_rhs_element(self, lam, x, dsig, b, k, a, t, c):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        dsig = np.ascontiguousarray(dsig, dtype=np.float64)
+        out = np.zeros(2)
+        self.lib.orc_vertex_rhs_element(self._p, float(lam), _ptr(x), _ptr(dsig),
+                                        int(b), int(k), int(a), int(t), int(c), _ptr(out))
+        return out
+
+    def vertex_rhs_triples(self, lam, x, dsig, triples) -> np.ndarray:
+        """Flow of every (basis, site) element at each (a, t, c) triple:
+        returns [nq, nb, ns, 2]."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        dsig = np.ascontiguousarray(dsig, dtype=np.float64)
+        tr = np.asarray(triples, dtype=np.int32).reshape(-1, 3)
+        a = np.ascontiguousarray(tr[:, 0]); t = np.ascontiguousarray(tr[:, 1])
+        c = np.ascontiguousarray(tr[:, 2])
+        out = np.zeros((len(tr), self.lat.nb, self.lat.ns, 2))
+        self.lib.orc_vertex_rhs_triples(self._p, float(lam), _ptr(x), _ptr(dsig), len(tr),
+                                        _ptr(a), _ptr(t), _ptr(c), _ptr(out), self.threads)
+        return out
+
+    def chi(self, lam: float, x: np.ndarray):
+        """(chi_zz, chi_dd), each [nb, ns] over the unreduced site lists."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        zz = np.zeros((self.lat.nb, self.lat.ns))
+        dd = np.zeros((self.lat.nb, self.lat.ns))
+        self.lib.orc_chi(self._p, float(lam), _ptr(x), _ptr(zz), _ptr(dd))
+        return zz, dd
+
+    def chi_k(self, chi_zz: np.ndarray, kpts: np.ndarray) -> np.ndarray:
+        """Structure factor (Eq. 31) per unit cell:
+        (1/nb) sum_b sum_{j in range of b} cos(k.(r_b - r_j)) 3 chi^zz_bj."""
+        kpts = np.asarray(kpts, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros(len(kpts))
+        lat = self.lat
+        for b in range(lat.nb):
+            n = lat.nsites[b]
+            dr = lat.basis_pos[b][None, :] - lat.site_pos[b, :n]
+            phase = kpts @ dr.T
+            out += np.cos(phase) @ (3.0 * chi_zz[b, :n])
+        return out / lat.nb
+
+    # ----------------------------------------------------------- flows --
+    def euler_step(self, lam0, lam1, x):
+        """One Euler step (Eq. 42): x(lam1) = x(lam0) + (lam1 - lam0) dx/dlam."""
+        return x + (lam1 - lam0) * self.rhs(lam0, x)
+
+    def rk4_step(self, lam0, lam1, x):
+        """Classical fourth-order Runge-Kutta step in Lambda from lam0 to lam1."""
+        h = lam1 - lam0
+        lm = lam0 + 0.5 * h
+        k1 = self.rhs(lam0, x)
+        k2 = self.rhs(lm, x + (0.5 * h) * k1)
+        k3 = self.rhs(lm, x + (0.5 * h) * k2)
+        k4 = self.rhs(lam1, x + h * k3)
+        return x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+    def flow(self, schedule, x0=None, scheme="rk4", observer=None):
+        """Integrate along a fixed cutoff schedule; observer(lam, x) after each step."""
+        x = self.initial_state() if x0 is None else np.array(x0, dtype=np.float64)
+        step = {"rk4": self.rk4_step, "euler": self.euler_step}[scheme]
+        for i in range(len(schedule) - 1):
+            x = step(float(schedule[i]), float(schedule[i + 1]), x)
+            if observer is not None:
+                observer(float(schedule[i + 1]), x)
+        return x
+
+
+def timed(fn, *a, **kw):
+    t0 = time.perf_counter()
+    r = fn(*a, **kw)
+    return r, time.perf_counter() - t0

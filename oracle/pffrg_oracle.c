@@ -1,0 +1,529 @@
+/*
+ * pffrg_oracle.c -- plain, slow, FP64 reference implementation of the SU(2)
+ * pseudofermion-FRG flow right-hand side and two-spin correlations.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this file's library.  It shares no
+ * code, header or table with the GPU library.
+ *
+ * What it computes, with the passage of arXiv:2109.13317 that defines it:
+ *   - Self-energy flow, Sec. 3 explicit one-particle flow (Eq. 23), with the
+ *     single-scale propagator S (Eq. 12) collapsing the frequency integral to
+ *     the two points |w| = Lambda.
+ *   - Vertex flow, Sec. 3 explicit two-particle flow (Eq. 24): s, t (RPA plus
+ *     two vertex corrections) and u channels, Katanin propagator (Eq. 13).
+ *   - SU(2) vertex: Gamma^{11}=Gamma^{22}=Gamma^{33} ("spin" strain) and
+ *     Gamma^{00} ("density" strain), other components zero (Sec. 3, SU(2)
+ *     constraint).  The spin contractions of Eq. 24 with Eq. 25 are done by
+ *     hand; the coefficients are the Pauli-algebra results
+ *     sum_k s^k s^l s^k = -s^l, (s.s)x(s.s) = 3 1x1 -+ 2 s.s, etc.
+ *   - Vertex symmetries (Eq. 18 with xi of Eq. 19), octant storage s>=u,
+ *     t>=0 (Sec. 4.2) and trilinear interpolation with constant
+ *     extrapolation (Eq. 37); Sigma odd with linear interpolation (Eq. 36).
+ *   - Lattice: translations only.  For every basis site b the vertex is kept
+ *     for every site within the bond-distance truncation range (Eq. 34);
+ *     no point-group reduction is used, so the oracle trusts no symmetry
+ *     table.  Lattice sums run over every site in range of both ends.
+ *   - Correlations chi^{zz} and chi^{00} (Eq. 30).
+ *
+ * Readings where the paper is silent (also listed in the design notes):
+ *   R1 (delta parts) S and the S-part of S_kat are integrated analytically at
+ *      w = +-Lambda; only the Katanin part -G^2 dSigma/dLambda is integrated
+ *      numerically.
+ *   R2 (quadrature) the Katanin integral runs over
+ *      D = {|w| >= Lambda, |partner(w)| >= Lambda} within [-wmax, wmax];
+ *      nodes are the finite endpoints of each connected piece of D plus every
+ *      mesh point +-w_n strictly inside it; trapezoid rule inside each piece
+ *      (Sec. 4.2: trapezoid nodes coincide with the mesh).  Same rule for the
+ *      correlation integrals, tensor-product in two dimensions.
+ *   R3 (theta ties) inside D the step function is 1 at its edge; a
+ *      propagator G evaluated at a delta point with |argument| == Lambda
+ *      exactly takes theta = 1/2.
+ *   R4 interpolation corners with s < u are read through the s<->u relation.
+ *   R5 chi: the one-loop term carries delta_ij.
+ *
+ * Real form.  Sigma = i*sig with sig real and odd (Eq. 15).  With
+ * g(w) = theta(|w|-Lambda)/(w - sig(w)) one has G = -i g, and the channel
+ * bubble [G(w) Skat(p) + G(p) Skat(w)] is real:
+ *   -g(w) d(|p|-L)/(p - sig(p)) - g(p) d(|w|-L)/(w - sig(w))
+ *   + g(w) g(p)^2 sig'(p) + g(p) g(w)^2 sig'(w).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define TWO_PI 6.283185307179586476925286766559
+
+typedef struct {
+    int nf;              /* number of positive mesh frequencies */
+    const double *w;     /* ascending positive mesh, nf entries */
+    int nb;              /* basis sites */
+    int ns;              /* padded length of each basis site's site list */
+    const int *nsites;   /* [nb] sites within range of basis site b */
+    const int *cell;     /* [nb][ns][3] cell offset of each listed site */
+    const int *bas;      /* [nb][ns]   basis index of each listed site */
+    int rm;              /* half-width of the offset lookup box */
+    const int *lookup;   /* [nb][2rm+1][2rm+1][2rm+1][nb] -> list index or -1 */
+} orc_lattice;
+
+/* ------------------------------------------------------------ layout --- */
+
+static long su_index(int a, int c) { return (long)a * (a + 1) / 2 + c; }
+
+static long n_su(const orc_lattice *L) { return su_index(L->nf, 0); }
+
+/* Offset of strain `comp` (0 spin, 1 density) in the state vector. */
+static long strain_offset(const orc_lattice *L, int comp)
+{
+    return L->nf + (long)comp * L->nb * n_su(L) * L->nf * L->ns;
+}
+
+long orc_state_size(const orc_lattice *L)
+{
+    return L->nf + 2L * L->nb * n_su(L) * L->nf * L->ns;
+}
+
+/* Index of vertex value (comp, basis b, s-index a, t-index t, u-index c, site k), a>=c. */
+static long vidx(const orc_lattice *L, int comp, int b, int a, int t, int c, int k)
+{
+    return strain_offset(L, comp) + (((long)b * n_su(L) + su_index(a, c)) * L->nf + t) * L->ns + k;
+}
+
+/* --------------------------------------------------------- lattice ----- */
+
+static int site_of(const orc_lattice *L, int b1, const int d[3], int b2)
+{
+    int W = 2 * L->rm + 1;
+    for (int i = 0; i < 3; ++i)
+        if (d[i] < -L->rm || d[i] > L->rm) return -1;
+    long idx = ((((long)b1 * W + (d[0] + L->rm)) * W + (d[1] + L->rm)) * W + (d[2] + L->rm)) * L->nb + b2;
+    return L->lookup[idx];
+}
+
+/* ---------------------------------------------------- interpolation ---- */
+
+/* Bracketing mesh points and weights of x >= 0, constant outside the mesh. */
+static void bracket(const orc_lattice *L, double x, int *i0, int *i1, double *f0, double *f1)
+{
+    const double *w = L->w;
+    int n = L->nf;
+    if (x <= w[0]) { *i0 = *i1 = 0; *f0 = 1.0; *f1 = 0.0; return; }
+    if (x >= w[n - 1]) { *i0 = *i1 = n - 1; *f0 = 1.0; *f1 = 0.0; return; }
+    int lo = 0;
+    while (w[lo + 1] <= x) ++lo;
+    double h = w[lo + 1] - w[lo];
+    *i0 = lo; *i1 = lo + 1;
+    *f0 = (w[lo + 1] - x) / h;
+    *f1 = (x - w[lo]) / h;
+}
+
+/* Odd function of frequency given on the positive mesh (Eq. 15, Eq. 36). */
+static double odd_interp(const orc_lattice *L, const double *v, double x)
+{
+    double sgn = 1.0;
+    if (x < 0.0) { x = -x; sgn = -1.0; }
+    int i0, i1; double f0, f1;
+    bracket(L, x, &i0, &i1, &f0, &f1);
+    return sgn * (f0 * v[i0] + f1 * v[i1]);
+}
+
+/*
+ * Vertex strain `comp` between site (b1, cell 0) and site (b2, cell d) at
+ * transfer frequencies (s,t,u).  Eq. 18 with xi(0)=+1, xi(3)=-1:
+ *   s -> -s swaps the two sites; t -> -t is free; u -> -u swaps the sites;
+ *   s <-> u is free for the spin strain and flips the density strain.
+ * Outside the truncation range the vertex is zero (Eq. 34).
+ */
+static double vertex(const orc_lattice *L, const double *x, int comp,
+                     int b1, const int dR[3], int b2, double s, double t, double u)
+{
+    int d[3] = {dR[0], dR[1], dR[2]};
+    double sign = 1.0;
+    if (s < 0.0) { s = -s; int tb = b1; b1 = b2; b2 = tb; d[0] = -d[0]; d[1] = -d[1]; d[2] = -d[2]; }
+    if (t < 0.0) t = -t;
+    if (u < 0.0) { u = -u; int tb = b1; b1 = b2; b2 = tb; d[0] = -d[0]; d[1] = -d[1]; d[2] = -d[2]; }
+    if (s < u) { double q = s; s = u; u = q; if (comp == 1) sign = -sign; }
+    int k = site_of(L, b1, d, b2);
+    if (k < 0) return 0.0;
+
+    int sa[2], ta[2], ua[2];
+    double fs[2], ft[2], fu[2];
+    bracket(L, s, &sa[0], &sa[1], &fs[0], &fs[1]);
+    bracket(L, t, &ta[0], &ta[1], &ft[0], &ft[1]);
+    bracket(L, u, &ua[0], &ua[1], &fu[0], &fu[1]);
+    double acc = 0.0;
+    for (int iu = 0; iu < 2; ++iu)
+        for (int it = 0; it < 2; ++it)
+            for (int is = 0; is < 2; ++is) {
+                double wgt = fu[iu] * ft[it] * fs[is];
+                if (wgt == 0.0) continue;
+                int a = sa[is], c = ua[iu];
+                double v;
+                if (a >= c) v = x[vidx(L, comp, b1, a, ta[it], c, k)];
+                else v = (comp == 1 ? -1.0 : 1.0) * x[vidx(L, comp, b1, c, ta[it], a, k)];
+                acc += wgt * v;
+            }
+    return sign * acc;
+}
+
+/* ----------------------------------------------------- propagators ---- */
+
+typedef struct {
+    const orc_lattice *L;
+    const double *x;       /* state */
+    const double *dsig;    /* d sig / d Lambda on the positive mesh */
+    double lam;
+} orc_eval;
+
+static double sig_at(const orc_eval *E, double w) { return odd_interp(E->L, E->x, w); }
+static double dsig_at(const orc_eval *E, double w) { return odd_interp(E->L, E->dsig, w); }
+
+/* 1/(w - sig(w)): the dressed propagator without its step function. */
+static double gbare(const orc_eval *E, double w) { return 1.0 / (w - sig_at(E, w)); }
+
+/* Step function at a delta point: 1 outside, 1/2 exactly on the edge (R3). */
+static double theta_half(double y, double lam)
+{
+    double a = fabs(y);
+    if (a > lam) return 1.0;
+    if (a == lam) return 0.5;
+    return 0.0;
+}
+
+/* ----------------------------------------------------- quadrature ----- */
+
+#define MAXPIECE 3
+
+/*
+ * Connected pieces of D = [-wmax, wmax] minus (-lam, lam) minus (c-lam, c+lam)
+ * (R2).  c is the frequency where the partner propagator's argument vanishes.
+ */
+static int pieces(double c, double lam, double wmax, double lo[MAXPIECE], double hi[MAXPIECE])
+{
+    double a0[2] = {-wmax, lam}, b0[2] = {-lam, wmax};
+    double e0 = c - lam, e1 = c + lam;
+    int n = 0;
+    for (int i = 0; i < 2; ++i) {
+        double a = a0[i], b = b0[i];
+        if (!(a < b)) continue;
+        double l1 = a, h1 = (b < e0 ? b : e0);
+        double l2 = (a > e1 ? a : e1), h2 = b;
+        if (l1 < h1) { lo[n] = l1; hi[n] = h1; ++n; }
+        if (l2 < h2) { lo[n] = l2; hi[n] = h2; ++n; }
+    }
+    return n;
+}
+
+/* Sorted nodes of one piece: lo, every +-w_n strictly inside, hi. */
+static int piece_nodes(const orc_lattice *L, double lo, double hi, double *nodes)
+{
+    int n = 0;
+    nodes[n++] = lo;
+    for (int i = L->nf - 1; i >= 0; --i) {
+        double v = -L->w[i];
+        if (v > lo && v < hi) nodes[n++] = v;
+    }
+    for (int i = 0; i < L->nf; ++i) {
+        double v = L->w[i];
+        if (v > lo && v < hi) nodes[n++] = v;
+    }
+    nodes[n++] = hi;
+    return n;
+}
+
+/* ------------------------------------------------------- sigma flow --- */
+
+/*
+ * d sig/dLambda(w) = (1/2pi) sum_{x=+-Lambda} F(w,x) / (x - sig(x)) with
+ * F = 2 sum_j Gd_{0j}(w+x, 0, w-x) - (3 Gs_{00} + Gd_{00})(w+x, x-w, 0)
+ * (Eq. 23 contracted with Eq. 25; the sum over j covers every site in range
+ * of the reference site, which is basis site 0).
+ */
+double orc_sigma_rhs_at(const orc_lattice *L, double lam, const double *x, double w)
+{
+    orc_eval E = {L, x, NULL, lam};
+    const int zero[3] = {0, 0, 0};
+    double acc = 0.0;
+    for (int sx = 0; sx < 2; ++sx) {
+        double xx = sx == 0 ? lam : -lam;
+        double f = 0.0;
+        for (int k = 0; k < L->nsites[0]; ++k) {
+            const int *cr = &L->cell[(long)k * 3];
+            f += 2.0 * vertex(L, x, 1, 0, cr, L->bas[k], w + xx, 0.0, w - xx);
+        }
+        f -= 3.0 * vertex(L, x, 0, 0, zero, 0, w + xx, xx - w, 0.0);
+        f -= vertex(L, x, 1, 0, zero, 0, w + xx, xx - w, 0.0);
+        acc += f / (xx - sig_at(&E, xx));
+    }
+    return acc / TWO_PI;
+}
+
+void orc_sigma_rhs(const orc_lattice *L, double lam, const double *x, double *dsig)
+{
+    for (int n = 0; n < L->nf; ++n) dsig[n] = orc_sigma_rhs_at(L, lam, x, L->w[n]);
+}
+
+/* ------------------------------------------------------ vertex flow --- */
+
+typedef struct {
+    int b, k;            /* output pair: basis site b at cell 0, listed site k */
+    int bk;              /* basis index of site k */
+    int dk[3];           /* cell offset of site k */
+    double s, t, u;      /* transfer frequencies */
+    double w1p, w2p, w1, w2;   /* external frequencies (Eq. 17 inverted) */
+} orc_out;
+
+/* The channel integrands: out[0] += spin part, out[1] += density part,
+ * for one frequency w of the loop, already multiplied by `wt`. */
+static void integrand_s(const orc_eval *E, const orc_out *o, double w, double wt, double acc[2])
+{
+    const orc_lattice *L = E->L;
+    double As = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->s, o->w1p - w, w - o->w2p);
+    double Ad = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->s, o->w1p - w, w - o->w2p);
+    double Bs = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->s, w - o->w1, w - o->w2);
+    double Bd = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->s, w - o->w1, w - o->w2);
+    acc[0] += wt * (-2.0 * As * Bs + As * Bd + Ad * Bs);
+    acc[1] += wt * (3.0 * As * Bs + Ad * Bd);
+}
+
+static void integrand_t(const orc_eval *E, const orc_out *o, double w, double wt, double acc[2])
+{
+    const orc_lattice *L = E->L;
+    const int zero[3] = {0, 0, 0};
+    /* particle-hole RPA term: -sum_j Gamma_{i1 j} Gamma_{j i2}, j in range of both */
+    double rs = 0.0, rd = 0.0;
+    for (int j = 0; j < L->nsites[o->b]; ++j) {
+        const int *cj = &L->cell[((long)o->b * L->ns + j) * 3];
+        int bj = L->bas[(long)o->b * L->ns + j];
+        int d2[3] = {o->dk[0] - cj[0], o->dk[1] - cj[1], o->dk[2] - cj[2]};
+        if (site_of(L, bj, d2, o->bk) < 0) continue;
+        double as = vertex(L, E->x, 0, o->b, cj, bj, o->w1 + w, o->t, o->w1p - w);
+        double ad = vertex(L, E->x, 1, o->b, cj, bj, o->w1 + w, o->t, o->w1p - w);
+        double bs = vertex(L, E->x, 0, bj, d2, o->bk, w + o->w2p, o->t, w - o->w2);
+        double bd = vertex(L, E->x, 1, bj, d2, o->bk, w + o->w2p, o->t, w - o->w2);
+        rs += as * bs;
+        rd += ad * bd;
+    }
+    /* vertex corrections with the on-site vertex at i2 and at i1 */
+    double As = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->w1 + w, o->t, o->w1p - w);
+    double Ad = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->w1 + w, o->t, o->w1p - w);
+    double O1s = vertex(L, E->x, 0, o->bk, zero, o->bk, o->w2p + w, o->w2 - w, -o->t);
+    double O1d = vertex(L, E->x, 1, o->bk, zero, o->bk, o->w2p + w, o->w2 - w, -o->t);
+    double O2s = vertex(L, E->x, 0, o->b, zero, o->b, o->w1 + w, w - o->w1p, -o->t);
+    double O2d = vertex(L, E->x, 1, o->b, zero, o->b, o->w1 + w, w - o->w1p, -o->t);
+    double Bs = vertex(L, E->x, 0, o->b, o->dk, o->bk, w + o->w2p, o->t, w - o->w2);
+    double Bd = vertex(L, E->x, 1, o->b, o->dk, o->bk, w + o->w2p, o->t, w - o->w2);
+    double gs = -2.0 * rs - As * O1s + As * O1d - O2s * Bs + O2d * Bs;
+    double gd = -2.0 * rd + 3.0 * Ad * O1s + Ad * O1d + 3.0 * O2s * Bd + O2d * Bd;
+    acc[0] += wt * gs;
+    acc[1] += wt * gd;
+}
+
+static void integrand_u(const orc_eval *E, const orc_out *o, double w, double wt, double acc[2])
+{
+    const orc_lattice *L = E->L;
+    double As = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->w1 + w, w - o->w2p, o->u);
+    double Ad = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->w1 + w, w - o->w2p, o->u);
+    double Bs = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->w1p + w, o->w2 - w, o->u);
+    double Bd = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->w1p + w, o->w2 - w, o->u);
+    acc[0] += wt * (2.0 * As * Bs + As * Bd + Ad * Bs);
+    acc[1] += wt * (3.0 * As * Bs + Ad * Bd);
+}
+
+typedef void (*integrand_fn)(const orc_eval *, const orc_out *, double, double, double[2]);
+
+/*
+ * One channel: (1/2pi) * integral of the bubble times the channel integrand.
+ * partner(w) = ps * w + pc  (s: pc - w; t: w - t; u: u + w) and its zero c.
+ */
+static void channel(const orc_eval *E, const orc_out *o, integrand_fn fn,
+                    double ps, double pc, double acc[2])
+{
+    const orc_lattice *L = E->L;
+    double lam = E->lam;
+    double loc[2] = {0.0, 0.0};
+
+    /* delta parts (R1): the S in Skat(partner) and the S in Skat(w) */
+    for (int sx = 0; sx < 2; ++sx) {
+        double xx = sx == 0 ? lam : -lam;
+        double st = 1.0 / (xx - sig_at(E, xx));
+        double winv = (xx - pc) / ps;        /* partner(winv) == xx */
+        double pxx = ps * xx + pc;           /* partner of w == xx */
+        double g1 = theta_half(winv, lam);     /* the propagator vanishes where theta does */
+        double g2 = theta_half(pxx, lam);
+        if (g1 != 0.0) g1 *= gbare(E, winv);
+        if (g2 != 0.0) g2 *= gbare(E, pxx);
+        if (g1 != 0.0) fn(E, o, winv, -st * g1, loc);
+        if (g2 != 0.0) fn(E, o, xx, -st * g2, loc);
+    }
+
+    /* Katanin part (R2): trapezoid over the pieces of the domain */
+    double c = -pc / ps;
+    double lo[MAXPIECE], hi[MAXPIECE];
+    int np = pieces(c, lam, L->w[L->nf - 1], lo, hi);
+    double *nodes = (double *)malloc(sizeof(double) * (2 * L->nf + 4));
+    for (int ip = 0; ip < np; ++ip) {
+        int nn = piece_nodes(L, lo[ip], hi[ip], nodes);
+        for (int i = 0; i < nn; ++i) {
+            double wl = i > 0 ? 0.5 * (nodes[i] - nodes[i - 1]) : 0.0;
+            double wr = i + 1 < nn ? 0.5 * (nodes[i + 1] - nodes[i]) : 0.0;
+            double w = nodes[i];
+            double p = ps * w + pc;
+            double gw = gbare(E, w), gp = gbare(E, p);
+            double kat = gw * gp * gp * dsig_at(E, p) + gp * gw * gw * dsig_at(E, w);
+            fn(E, o, w, (wl + wr) * kat, loc);
+        }
+    }
+    free(nodes);
+    acc[0] += loc[0] / TWO_PI;
+    acc[1] += loc[1] / TWO_PI;
+}
+
+/*
+ * Flow of the vertex element (basis b, listed site k) at mesh indices
+ * s = w[a], t = w[it], u = w[c] with a >= c.  `dsig` must hold the
+ * self-energy flow of the same state at the same Lambda (Katanin term).
+ */
+void orc_vertex_rhs_element(const orc_lattice *L, double lam, const double *x, const double *dsig,
+                            int b, int k, int a, int it, int c, double out[2])
+{
+    orc_eval E = {L, x, dsig, lam};
+    orc_out o;
+    o.b = b; o.k = k;
+    o.bk = L->bas[(long)b * L->ns + k];
+    for (int i = 0; i < 3; ++i) o.dk[i] = L->cell[((long)b * L->ns + k) * 3 + i];
+    o.s = L->w[a]; o.t = L->w[it]; o.u = L->w[c];
+    /* s = w1'+w2', t = w1'-w1, u = w1'-w2 and w1'+w2' = w1+w2 (Eq. 17) */
+    o.w1p = 0.5 * (o.s + o.t + o.u);
+    o.w2p = 0.5 * (o.s - o.t - o.u);
+    o.w1 = 0.5 * (o.s - o.t + o.u);
+    o.w2 = 0.5 * (o.s + o.t - o.u);
+    double acc[2] = {0.0, 0.0};
+    channel(&E, &o, integrand_s, -1.0, o.s, acc);   /* partner s - w */
+    channel(&E, &o, integrand_t, 1.0, -o.t, acc);   /* partner w - t */
+    channel(&E, &o, integrand_u, 1.0, o.u, acc);    /* partner u + w */
+    out[0] = acc[0];
+    out[1] = acc[1];
+}
+
+/* Full right-hand side: sigma flow, then every vertex element. */
+void orc_rhs(const orc_lattice *L, double lam, const double *x, double *dx, int nthreads)
+{
+    double *dsig = dx;   /* the sigma part of the output doubles as dsig */
+    orc_sigma_rhs(L, lam, x, dsig);
+    long nsu = n_su(L);
+    long total = (long)L->nb * nsu * L->nf;
+    memset(dx + L->nf, 0, sizeof(double) * (size_t)(orc_state_size(L) - L->nf));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (long q = 0; q < total; ++q) {
+        int b = (int)(q / (nsu * L->nf));
+        long r = q % (nsu * L->nf);
+        int su = (int)(r / L->nf), it = (int)(r % L->nf);
+        int a = 0;
+        while (su_index(a + 1, 0) <= su) ++a;
+        int c = su - (int)su_index(a, 0);
+        for (int k = 0; k < L->nsites[b]; ++k) {
+            double out[2];
+            orc_vertex_rhs_element(L, lam, x, dsig, b, k, a, it, c, out);
+            dx[vidx(L, 0, b, a, it, c, k)] = out[0];
+            dx[vidx(L, 1, b, a, it, c, k)] = out[1];
+        }
+    }
+}
+
+/*
+ * Every vertex element of a list of frequency triples (all basis sites and
+ * listed sites), written to out[q][b][k][2].  Used for sampled comparisons
+ * and for the CPU baseline timing.
+ */
+void orc_vertex_rhs_triples(const orc_lattice *L, double lam, const double *x, const double *dsig,
+                            int nq, const int *a_list, const int *t_list, const int *c_list,
+                            double *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+#endif
+    for (int q = 0; q < nq; ++q)
+        for (int b = 0; b < L->nb; ++b)
+            for (int k = 0; k < L->nsites[b]; ++k)
+                orc_vertex_rhs_element(L, lam, x, dsig, b, k, a_list[q], t_list[q], c_list[q],
+                                       &out[(((long)q * L->nb + b) * L->ns + k) * 2]);
+}
+
+/* ------------------------------------------------------- correlations -- */
+
+/*
+ * chi^{zz}_{bk} and chi^{00}_{bk} (Eq. 30 contracted with Eq. 25, R5):
+ *   chi^zz = d_ij (1/4pi) I g^2 - (1/16pi^2) II g1^2 g2^2
+ *            [4 Gs_ij(w1+w2, 0, w1-w2) + d_ij (2Gs_ii - 2Gd_ii)(w1+w2, w2-w1, 0)]
+ *   chi^00 = d_ij (1/4pi) I g^2 - (1/16pi^2) II g1^2 g2^2
+ *            [4 Gd_ij(w1+w2, 0, w1-w2) - d_ij (6Gs_ii + 2Gd_ii)(w1+w2, w2-w1, 0)]
+ * with g = 1/(w - sig(w)) on |w| >= Lambda (G^2 = -g^2).
+ */
+void orc_chi(const orc_lattice *L, double lam, const double *x, double *chi_zz, double *chi_dd)
+{
+    orc_eval E = {L, x, NULL, lam};
+    double wmax = L->w[L->nf - 1];
+    int cap = 2 * (2 * L->nf + 4);
+    double *nw = (double *)malloc(sizeof(double) * cap);
+    double *ww = (double *)malloc(sizeof(double) * cap);
+    double *g2 = (double *)malloc(sizeof(double) * cap);
+    double *tmp = (double *)malloc(sizeof(double) * (2 * L->nf + 4));
+    int n = 0;
+    double lo[2] = {-wmax, lam}, hi[2] = {-lam, wmax};
+    for (int ip = 0; ip < 2; ++ip) {
+        if (!(lo[ip] < hi[ip])) continue;
+        int nn = piece_nodes(L, lo[ip], hi[ip], tmp);
+        for (int i = 0; i < nn; ++i) {
+            double wl = i > 0 ? 0.5 * (tmp[i] - tmp[i - 1]) : 0.0;
+            double wr = i + 1 < nn ? 0.5 * (tmp[i + 1] - tmp[i]) : 0.0;
+            nw[n] = tmp[i];
+            ww[n] = wl + wr;
+            double g = gbare(&E, tmp[i]);
+            g2[n] = g * g;
+            ++n;
+        }
+    }
+    double bubble = 0.0;
+    for (int i = 0; i < n; ++i) bubble += ww[i] * g2[i];
+    bubble /= 2.0 * TWO_PI;
+    const double pref = 1.0 / (4.0 * TWO_PI * TWO_PI);   /* 1/(16 pi^2) */
+    const int zero[3] = {0, 0, 0};
+    for (int b = 0; b < L->nb; ++b)
+        for (int k = 0; k < L->nsites[b]; ++k) {
+            const int *ck = &L->cell[((long)b * L->ns + k) * 3];
+            int bk = L->bas[(long)b * L->ns + k];
+            int onsite = (k == 0);
+            double zz = 0.0, dd = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double w1 = nw[i], w2 = nw[j];
+                    double f = ww[i] * ww[j] * g2[i] * g2[j];
+                    double ds = vertex(L, x, 0, b, ck, bk, w1 + w2, 0.0, w1 - w2);
+                    double dd_ = vertex(L, x, 1, b, ck, bk, w1 + w2, 0.0, w1 - w2);
+                    double tz = 4.0 * ds, td = 4.0 * dd_;
+                    if (onsite) {
+                        double es = vertex(L, x, 0, b, zero, b, w1 + w2, w2 - w1, 0.0);
+                        double ed = vertex(L, x, 1, b, zero, b, w1 + w2, w2 - w1, 0.0);
+                        tz += 2.0 * es - 2.0 * ed;
+                        td -= 6.0 * es + 2.0 * ed;
+                    }
+                    zz += f * tz;
+                    dd += f * td;
+                }
+            zz *= -pref;
+            dd *= -pref;
+            if (onsite) { zz += bubble; dd += bubble; }
+            chi_zz[(long)b * L->ns + k] = zz;
+            chi_dd[(long)b * L->ns + k] = dd;
+        }
+    free(nw); free(ww); free(g2); free(tmp);
+}
