@@ -1,0 +1,193 @@
+/*
+ * pffrg.h -- C ABI of the MI355X pf-FRG flow library (libpffrg.so).
+ *
+ * The library computes the SU(2) pseudofermion functional-renormalization-
+ * group flow of arXiv:2109.13317: the right-hand side of the self-energy and
+ * two-particle-vertex flow equations at cutoff Lambda (Sec. 3, Eq. 23 and
+ * Eq. 24 with the Katanin propagator of Eq. 13), explicit Runge-Kutta
+ * integration in Lambda (Sec. 4.3), and the two-spin correlations chi_ij and
+ * chi(k) (Eq. 30, Eq. 31).  All arithmetic runs in HIP kernels on the GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers named d_* are device pointers to memory the caller owns (for
+ * example a torch tensor's data_ptr()).  The library never frees them and
+ * never keeps them after the call returns.  Host arrays passed to
+ * pffrg_create are copied; the caller may free them afterwards.
+ *
+ * Every call returns a pffrg_status.  On failure a message is available
+ * from pffrg_last_error() (thread-local, valid until the next call on the
+ * same thread).  No C++ exception crosses this boundary.
+ *
+ * Work is enqueued on the context's stream (a hipStream_t, passed here as
+ * void*; NULL means the default stream) and is asynchronous unless stated.
+ * All device memory a context needs is allocated in pffrg_create; no later
+ * call allocates.
+ *
+ * Flow state layout (FP64, n_freq = Nw, n_pairs = Ns):
+ *   state[0 .. Nw)              sig(w_n) = Im Sigma(w_n) on the positive mesh
+ *                               (Sigma is purely imaginary and odd, Eq. 15)
+ *   state[Nw + V*0 .. )         spin vertex   Gs = Gamma^{33} (= 11 = 22)
+ *   state[Nw + V*1 .. )         density vertex Gd = Gamma^{00}
+ * with V = T*Ns and T = Nw*Nw*(Nw+1)/2.  Inside each strain the index of
+ * (s = w_a, t = w_t, u = w_c), a >= c, pair p is
+ *   ((a*(a+1)/2 + c) * Nw + t) * Ns + p,
+ * i.e. the (s,u) wedge outermost, then t, then the pair (the memory layout
+ * of Sec. 4.4 for the two SU(2) strains).  Values at other frequencies
+ * follow from the symmetry relations (Eq. 18) and trilinear interpolation
+ * with constant extrapolation (Eq. 37).
+ */
+#ifndef PFFRG_H
+#define PFFRG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PFFRG_OK = 0,
+    PFFRG_EINVAL = -1,        /* bad table, mesh, size, pointer or Lambda <= 0 */
+    PFFRG_EHIP = -2,          /* HIP runtime failure */
+    PFFRG_ENOMEM = -3,        /* device allocation failed in pffrg_create */
+    PFFRG_EDIVERGED = -4,     /* NaN/Inf in the state, or step size below hmin */
+    PFFRG_EUNSUPPORTED = -5   /* option not available in this build */
+} pffrg_status;
+
+typedef enum {
+    PFFRG_FP64 = 0,           /* every kernel in FP64 */
+    PFFRG_FP32 = 1            /* vertex quadrature and lattice sums in FP32 with
+                                 compensated accumulation; state, propagators,
+                                 self-energy flow, steps and chi in FP64 */
+} pffrg_precision;
+
+typedef struct pffrg_ctx pffrg_ctx;
+
+/*
+ * Symmetry-reduced lattice (Sec. 4.1).  The reference site is basis site 0;
+ * pair p stands for the orbit of site j_p under the point group fixing the
+ * reference site, truncated at bond distance L (Eq. 34).  Pair 0 must be the
+ * on-site pair.
+ *   swap[p]      pair of (j_p, i_ref), i.e. Gamma_{j i} for Gamma_{i j}
+ *   mult[p]      number of sites in the orbit of pair p (>= 1)
+ *   rpa_*        tabulated lattice sums: for output pair p, the terms
+ *                rpa_off[p] <= q < rpa_off[p+1] contribute
+ *                rpa_cnt[q] * Gamma_{rpa_ka[q]} * Gamma_{rpa_kb[q]} to
+ *                sum_j Gamma_{i_ref j} Gamma_{j j_p}
+ *   coupling[p]  Heisenberg coupling J of the bond (i_ref, j_p), 0 if none;
+ *                each unordered bond counted once (Eq. 21: Gs = J/4)
+ *   n_basis, n_sites_total, site_pair[b*n_sites_total + k], site_pos[..*3]
+ *                for every basis site b the sites within range of b, their
+ *                reduced pair (-1 pads short lists) and Cartesian position;
+ *   basis_pos    [n_basis*3] Cartesian basis-site positions (chi(k))
+ */
+typedef struct {
+    int n_pairs;
+    const int *swap;
+    const int *mult;
+    const int *rpa_off;
+    const int *rpa_ka;
+    const int *rpa_kb;
+    const int *rpa_cnt;
+    const double *coupling;
+    int n_basis;
+    int n_sites_total;
+    const int *site_pair;
+    const double *site_pos;
+    const double *basis_pos;
+} pffrg_lattice;
+
+/* Positive frequency mesh, strictly ascending, n_freq >= 2, omega[0] > 0
+ * (Sec. 4.2; negative frequencies are implied by symmetry). */
+typedef struct {
+    int n_freq;
+    const double *omega;
+} pffrg_mesh;
+
+/* ---------------------------------------------------------- lifecycle -- */
+
+/* Copy the tables to the device and allocate every buffer the context will
+ * use.  `stream` is a hipStream_t or NULL. */
+pffrg_status pffrg_create(const pffrg_lattice *lat, const pffrg_mesh *mesh,
+                          pffrg_precision prec, void *stream, pffrg_ctx **out);
+pffrg_status pffrg_destroy(pffrg_ctx *ctx);
+pffrg_status pffrg_set_stream(pffrg_ctx *ctx, void *stream);
+
+/* Number of doubles in one flow state (layout above). */
+pffrg_status pffrg_state_size(const pffrg_ctx *ctx, size_t *n_doubles);
+
+/* Initial condition at infinite cutoff (Eq. 14, Eq. 21): sig = 0,
+ * Gs = coupling/4 for every frequency, Gd = 0. */
+pffrg_status pffrg_init_state(pffrg_ctx *ctx, double *d_state);
+
+/* ---------------------------------------------------------- the flow --- */
+
+/* d_dstate = d state / d Lambda at cutoff `lambda` > 0: the self-energy flow
+ * (Eq. 23) first, then the vertex flow (Eq. 24) whose Katanin term uses it.
+ * d_state and d_dstate must not overlap. */
+pffrg_status pffrg_rhs(pffrg_ctx *ctx, double lambda, const double *d_state, double *d_dstate);
+
+/* Self-energy part only: d_dsig[Nw] = d sig/d Lambda (Eq. 23). */
+pffrg_status pffrg_sigma_rhs(pffrg_ctx *ctx, double lambda, const double *d_state, double *d_dsig);
+
+/* One explicit step from lam0 to lam1 (lam1 < lam0 for a downward flow),
+ * updating d_state in place.  PFFRG_EULER is the paper's scheme (Eq. 42);
+ * PFFRG_RK4 is the classical fourth-order Runge-Kutta step in Lambda with
+ * stages at lam0, lam0 + h/2, lam0 + h/2, lam1 (h = lam1 - lam0). */
+typedef enum { PFFRG_EULER = 0, PFFRG_RK4 = 1, PFFRG_DOPRI54 = 2 } pffrg_scheme;
+pffrg_status pffrg_step(pffrg_ctx *ctx, pffrg_scheme scheme, double lam0, double lam1, double *d_state);
+
+/* Observer called after every accepted step with the new cutoff and device
+ * pointers to chi per pair ([2][Ns]: zz then density) and chi(k) (or NULL
+ * when no k-points were given).  It runs on the host after the stream has
+ * been synchronised; a non-zero return stops the flow with PFFRG_OK. */
+typedef int (*pffrg_observer)(double lambda, const double *d_chi_pairs, const double *d_chi_k,
+                              void *user);
+
+typedef struct {
+    pffrg_scheme scheme;
+    /* fixed-step schedules (EULER, RK4): the cutoff values, first = start */
+    int n_lambda;
+    const double *lambdas;      /* host array */
+    /* adaptive (DOPRI54): Dormand-Prince 5(4) in l = ln Lambda from
+     * lam_start down to lam_stop with mixed tolerance atol + rtol*|x| in the
+     * max norm, first step h0 (in l, > 0), minimal step hmin */
+    double lam_start, lam_stop, rtol, atol, h0, hmin;
+    int max_steps;
+    /* measurements after each accepted step: chi per pair always when an
+     * observer is given; chi(k) at n_k points d_k[3*n_k] (device) if n_k > 0 */
+    int n_k;
+    const double *d_k;
+    double *d_chi_k;            /* device output [n_k], passed to the observer */
+} pffrg_flow_opts;
+
+/* Integrate d_state along the options' schedule.  Returns PFFRG_EDIVERGED
+ * (with d_state holding the last finite state) if the state stops being
+ * finite or the adaptive step falls below hmin.  The number of accepted
+ * steps is written to *n_steps if it is not NULL. */
+pffrg_status pffrg_flow(pffrg_ctx *ctx, const pffrg_flow_opts *opts, double *d_state,
+                        pffrg_observer cb, void *user, int *n_steps);
+
+/* --------------------------------------------------------- observables - */
+
+/* Two-spin correlations per reduced pair at cutoff lambda (Eq. 30):
+ * d_chi[0*Ns + p] = chi^{zz}_{i_ref j_p}, d_chi[1*Ns + p] = chi^{00}. */
+pffrg_status pffrg_chi(pffrg_ctx *ctx, double lambda, const double *d_state, double *d_chi);
+
+/* Structure factor (Eq. 31) per unit cell from chi per pair:
+ * d_chi_k[q] = (1/n_basis) sum_b sum_j cos(k_q . (r_b - r_j)) 3 chi^{zz}_{b j}
+ * for the n_k points d_k[3*q .. 3*q+2]. */
+pffrg_status pffrg_chi_k(pffrg_ctx *ctx, const double *d_chi, int n_k, const double *d_k,
+                         double *d_chi_k);
+
+/* -------------------------------------------------------------- errors -- */
+
+const char *pffrg_last_error(void);
+const char *pffrg_status_string(pffrg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFFRG_H */

@@ -1,0 +1,19 @@
+"""MI355X-native SU(2) pseudofermion-FRG flow engine (arXiv:2109.13317).
+
+The flow right-hand side, Runge-Kutta steps and correlations run in HIP
+kernels behind the C ABI of include/pffrg.h (libpffrg.so, built in this
+directory).  This package holds the Python binding (``flow.Context``), the
+lattice front end that produces the ABI's symmetry-reduced tables
+(``lattice.build_tables``) and the build script.
+"""
+
+from .lattice import LatticeTables, build_tables
+
+__all__ = ["LatticeTables", "build_tables", "Context"]
+
+
+def __getattr__(name):
+    if name == "Context":
+        from .flow import Context
+        return Context
+    raise AttributeError(name)

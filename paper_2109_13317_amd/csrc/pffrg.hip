@@ -1,0 +1,545 @@
+// pffrg.hip -- host side of the C ABI declared in include/pffrg.h.
+//
+// A context owns device copies of the lattice and mesh tables and every
+// scratch buffer, all allocated in pffrg_create.  The flow kernels live in
+// kernels_flow.h, correlations and Runge-Kutta vector kernels in
+// kernels_obs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pffrg.h"
+#include "kernels_flow.h"
+#include "kernels_obs.h"
+
+using namespace pffrg;
+
+namespace {
+
+thread_local std::string g_err;
+
+pffrg_status fail(pffrg_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(PFFRG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)                              \
+    do {                                       \
+        pffrg_status s_ = (expr);              \
+        if (s_ != PFFRG_OK) return s_;         \
+    } while (0)
+
+constexpr int kNumK = 7;     // Dormand-Prince stages (RK4 uses the first three)
+constexpr int kRedBlocks = 512;
+
+}  // namespace
+
+struct pffrg_ctx {
+    int nf = 0, ns = 0, nq = 0, nsu = 0;
+    long vsz = 0, size = 0;
+    pffrg_precision prec = PFFRG_FP64;
+    hipStream_t stream = nullptr;
+    int device = 0;
+
+    // tables
+    double* w = nullptr;
+    int *swap = nullptr, *mult = nullptr, *rpa_off = nullptr, *rpa_ka = nullptr,
+        *rpa_kb = nullptr, *rpa_cnt = nullptr, *su_a = nullptr, *su_c = nullptr;
+    double* coupling = nullptr;
+    int nb = 0, nterm = 0;          // chi(k) terms: (basis, site) pairs in range
+    int* chi_pair = nullptr;        // [nterm]
+    double* chi_dr = nullptr;       // [nterm*3]  r_b - r_j
+
+    // scratch
+    int* tab_n = nullptr;
+    double *tab_w = nullptr, *tab_g = nullptr, *dsig = nullptr;
+    double* k[kNumK] = {};
+    double *ybuf = nullptr, *ebuf = nullptr;
+    double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
+    int* cn = nullptr;
+    double* chi = nullptr;          // [2*ns]
+    double* part = nullptr;         // [2*kRedBlocks]
+    double* red = nullptr;          // [2]
+    double* host_red = nullptr;     // pinned [2]
+
+    std::vector<void*> allocs;
+
+    FlowArgs args() const {
+        FlowArgs A;
+        A.w = w; A.nf = nf; A.ns = ns; A.nq = nq;
+        A.swap = swap; A.mult = mult; A.rpa_off = rpa_off; A.rpa_ka = rpa_ka;
+        A.rpa_kb = rpa_kb; A.rpa_cnt = rpa_cnt; A.su_a = su_a; A.su_c = su_c;
+        A.tab_n = tab_n; A.tab_w = tab_w; A.tab_g = tab_g;
+        return A;
+    }
+};
+
+namespace {
+
+template <class T>
+pffrg_status dev_alloc(pffrg_ctx* c, T** p, size_t n) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, n * sizeof(T) > 0 ? n * sizeof(T) : 8);
+    if (e != hipSuccess) return fail(PFFRG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return PFFRG_OK;
+}
+
+template <class T>
+pffrg_status upload(pffrg_ctx* c, T** p, const T* src, size_t n) {
+    TRY(dev_alloc(c, p, n));
+    if (n) HIP_TRY(hipMemcpy(*p, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return PFFRG_OK;
+}
+
+void release(pffrg_ctx* c) {
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    if (c->host_red) (void)hipHostFree(c->host_red);
+    c->host_red = nullptr;
+}
+
+pffrg_status check_ctx(const pffrg_ctx* c) {
+    if (!c) return fail(PFFRG_EINVAL, "null context");
+    return PFFRG_OK;
+}
+
+pffrg_status launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PFFRG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return PFFRG_OK;
+}
+
+int grid_for(long n, int threads) {
+    long b = (n + threads - 1) / threads;
+    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// ------------------------------------------------------------ one RHS ---
+
+pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
+    FlowArgs A = c->args();
+    hipLaunchKernelGGL(k_sigma_rhs, dim3((c->nf + 63) / 64), dim3(64), 0, c->stream, A, lam, x, dsig);
+    return launch_check("k_sigma_rhs");
+}
+
+pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
+    if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    FlowArgs A = c->args();
+    TRY(sigma_rhs(c, lam, x, dx));          // the sigma part of dx is dsig
+    hipLaunchKernelGGL(k_node_tables, dim3((3 * c->nf + 63) / 64), dim3(64), 0, c->stream, A, lam, x,
+                       (const double*)dx);
+    TRY(launch_check("k_node_tables"));
+    const VertexLds L{c->nq, c->ns};
+    hipLaunchKernelGGL(k_vertex_rhs, dim3(c->nsu * c->nf), dim3(kThreads), L.total(), c->stream, A, x, dx);
+    return launch_check("k_vertex_rhs");
+}
+
+// max-norm error / finiteness readback (synchronises the stream)
+pffrg_status reduce_err(pffrg_ctx* c, const double* x, const double* y, const double* e, double atol,
+                        double rtol, double* err, bool* finite) {
+    hipLaunchKernelGGL(k_err_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, c->stream, (long)c->size, x, y, e,
+                       atol, rtol, c->part);
+    TRY(launch_check("k_err_norm"));
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(1), 0, c->stream, kRedBlocks, (const double*)c->part, c->red);
+    TRY(launch_check("k_err_final"));
+    HIP_TRY(hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (err) *err = c->host_red[0];
+    if (finite) *finite = c->host_red[1] == 0.0;
+    return PFFRG_OK;
+}
+
+pffrg_status combine(pffrg_ctx* c, const double* x, const double* const* ks, const double* cs, int m,
+                     double* y) {
+    Combo C{};
+    C.m = m;
+    for (int j = 0; j < m; ++j) { C.k[j] = ks[j]; C.c[j] = cs[j]; }
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size, x, C, y);
+    return launch_check("k_combine");
+}
+
+pffrg_status step_euler(pffrg_ctx* c, double l0, double l1, double* x) {
+    TRY(rhs(c, l0, x, c->k[0]));
+    const double* ks[1] = {c->k[0]};
+    const double cs[1] = {l1 - l0};
+    return combine(c, x, ks, cs, 1, x);
+}
+
+// classical RK4 in Lambda: stages at l0, l0+h/2, l0+h/2, l1
+pffrg_status step_rk4(pffrg_ctx* c, double l0, double l1, double* x) {
+    const double h = l1 - l0;
+    const double lm = l0 + 0.5 * h;
+    double* K = c->k[0];
+    double* Y = c->k[1];
+    double* Acc = c->k[2];
+    const long n = c->size;
+    const int gb = grid_for(n, 256);
+    TRY(rhs(c, l0, x, K));
+    hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, (const double*)x, (const double*)K,
+                       0.5 * h, Y, h / 6.0, Acc, 1);
+    TRY(launch_check("k_rk_stage"));
+    TRY(rhs(c, lm, Y, K));
+    hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, (const double*)x, (const double*)K,
+                       0.5 * h, Y, h / 3.0, Acc, 0);
+    TRY(launch_check("k_rk_stage"));
+    TRY(rhs(c, lm, Y, K));
+    hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, (const double*)x, (const double*)K,
+                       h, Y, h / 3.0, Acc, 0);
+    TRY(launch_check("k_rk_stage"));
+    TRY(rhs(c, l1, Y, K));
+    hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, (const double*)Acc, (const double*)K,
+                       0.0, (double*)nullptr, h / 6.0, x, 1);
+    return launch_check("k_rk_stage");
+}
+
+// Dormand-Prince 5(4) (Dormand & Prince 1980) in l = ln Lambda: dx/dl = Lambda dx/dLambda.
+struct Dopri {
+    static constexpr double c[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+    static constexpr double a[7][6] = {
+        {0, 0, 0, 0, 0, 0},
+        {1.0 / 5, 0, 0, 0, 0, 0},
+        {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+        {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+        {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+        {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+        {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+    static constexpr double e[7] = {35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695,
+                                    125.0 / 192 - 393.0 / 640, -2187.0 / 6784 + 92097.0 / 339200,
+                                    11.0 / 84 - 187.0 / 2100, -1.0 / 40};
+};
+constexpr double Dopri::c[7];
+constexpr double Dopri::a[7][6];
+constexpr double Dopri::e[7];
+
+// One attempted Dormand-Prince step from l0 with signed step dl.  On entry
+// k[0] holds dx/dLambda at (exp(l0), x) (first-same-as-last).  Writes the
+// candidate to ybuf, the stage derivatives to k[1..6] and returns the error
+// norm.  lam_j are the stage cutoffs.
+pffrg_status dopri_attempt(pffrg_ctx* c, double l0, double dl, const double* x, double atol, double rtol,
+                           double* err, bool* finite, double lam_out[7]) {
+    double lam[7];
+    for (int j = 0; j < 7; ++j) lam[j] = std::exp(l0 + Dopri::c[j] * dl);
+    for (int i = 1; i < 7; ++i) {
+        const double* ks[6];
+        double cs[6];
+        for (int j = 0; j < i; ++j) { ks[j] = c->k[j]; cs[j] = dl * Dopri::a[i][j] * lam[j]; }
+        TRY(combine(c, x, ks, cs, i, c->ybuf));
+        TRY(rhs(c, lam[i], c->ybuf, c->k[i]));
+    }
+    // ybuf holds the 5th-order solution (stage 7 input equals it); error vector
+    const double* ks[7];
+    double cs[7];
+    for (int j = 0; j < 7; ++j) { ks[j] = c->k[j]; cs[j] = dl * Dopri::e[j] * lam[j]; }
+    Combo C{};
+    C.m = 7;
+    for (int j = 0; j < 7; ++j) { C.k[j] = ks[j]; C.c[j] = cs[j]; }
+    hipLaunchKernelGGL(k_combine, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size,
+                       (const double*)nullptr, C, c->ebuf);
+    TRY(launch_check("k_combine"));
+    TRY(reduce_err(c, x, c->ybuf, c->ebuf, atol, rtol, err, finite));
+    for (int j = 0; j < 7; ++j) lam_out[j] = lam[j];
+    return PFFRG_OK;
+}
+
+pffrg_status observe(pffrg_ctx* c, const pffrg_flow_opts* o, double lam, const double* x, pffrg_observer cb,
+                     void* user, int* stop) {
+    *stop = 0;
+    if (!cb) return PFFRG_OK;
+    TRY(pffrg_chi(c, lam, x, c->chi));
+    const double* dk = nullptr;
+    if (o->n_k > 0) {
+        TRY(pffrg_chi_k(c, c->chi, o->n_k, o->d_k, o->d_chi_k));
+        dk = o->d_chi_k;
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *stop = cb(lam, c->chi, dk, user);
+    return PFFRG_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* pffrg_last_error(void) { return g_err.c_str(); }
+
+const char* pffrg_status_string(pffrg_status s) {
+    switch (s) {
+        case PFFRG_OK: return "PFFRG_OK";
+        case PFFRG_EINVAL: return "PFFRG_EINVAL";
+        case PFFRG_EHIP: return "PFFRG_EHIP";
+        case PFFRG_ENOMEM: return "PFFRG_ENOMEM";
+        case PFFRG_EDIVERGED: return "PFFRG_EDIVERGED";
+        case PFFRG_EUNSUPPORTED: return "PFFRG_EUNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffrg_precision prec, void* stream,
+                          pffrg_ctx** out) {
+    if (!out) return fail(PFFRG_EINVAL, "out is null");
+    *out = nullptr;
+    if (!lat || !mesh) return fail(PFFRG_EINVAL, "lattice or mesh is null");
+    const int nf = mesh->n_freq, ns = lat->n_pairs;
+    if (nf < 2 || !mesh->omega) return fail(PFFRG_EINVAL, "mesh needs n_freq >= 2 frequencies");
+    for (int i = 0; i < nf; ++i) {
+        if (!(mesh->omega[i] > 0.0) || !std::isfinite(mesh->omega[i]))
+            return fail(PFFRG_EINVAL, "mesh frequencies must be finite and > 0");
+        if (i > 0 && !(mesh->omega[i] > mesh->omega[i - 1]))
+            return fail(PFFRG_EINVAL, "mesh must be strictly ascending");
+    }
+    if (ns < 1 || !lat->swap || !lat->mult || !lat->rpa_off || !lat->coupling)
+        return fail(PFFRG_EINVAL, "lattice tables incomplete");
+    if (ns * ns > 4 * kThreads)
+        return fail(PFFRG_EUNSUPPORTED, "more than 32 reduced pairs is not supported by this kernel build");
+    if (prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "only PFFRG_FP64 is available in this build");
+    if (lat->swap[0] != 0) return fail(PFFRG_EINVAL, "pair 0 must be the on-site pair (swap[0] == 0)");
+    const int nterms = lat->rpa_off[ns];
+    if (lat->rpa_off[0] != 0 || nterms < 0) return fail(PFFRG_EINVAL, "bad rpa_off");
+    for (int p = 0; p < ns; ++p) {
+        if (lat->swap[p] < 0 || lat->swap[p] >= ns) return fail(PFFRG_EINVAL, "swap out of range");
+        if (lat->mult[p] < 1) return fail(PFFRG_EINVAL, "mult must be >= 1");
+        if (lat->rpa_off[p + 1] < lat->rpa_off[p]) return fail(PFFRG_EINVAL, "rpa_off not ascending");
+    }
+    for (int q = 0; q < nterms; ++q)
+        if (lat->rpa_ka[q] < 0 || lat->rpa_ka[q] >= ns || lat->rpa_kb[q] < 0 || lat->rpa_kb[q] >= ns)
+            return fail(PFFRG_EINVAL, "rpa term pair out of range");
+    if (lat->n_basis < 1 || lat->n_sites_total < 1 || !lat->site_pair || !lat->site_pos || !lat->basis_pos)
+        return fail(PFFRG_EINVAL, "site map incomplete");
+
+    pffrg_ctx* c = new (std::nothrow) pffrg_ctx;
+    if (!c) return fail(PFFRG_ENOMEM, "host allocation failed");
+    c->nf = nf;
+    c->ns = ns;
+    c->nq = 2 * nf + 10;
+    c->nsu = nf * (nf + 1) / 2;
+    c->vsz = (long)c->nsu * nf * ns;
+    c->size = nf + 2 * c->vsz;
+    c->prec = prec;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->nb = lat->n_basis;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return fail(PFFRG_EHIP, "no HIP device"); }
+
+    auto body = [&]() -> pffrg_status {
+        TRY(upload(c, &c->w, mesh->omega, (size_t)nf));
+        TRY(upload(c, &c->swap, lat->swap, (size_t)ns));
+        TRY(upload(c, &c->mult, lat->mult, (size_t)ns));
+        TRY(upload(c, &c->rpa_off, lat->rpa_off, (size_t)ns + 1));
+        TRY(upload(c, &c->rpa_ka, lat->rpa_ka, (size_t)nterms));
+        TRY(upload(c, &c->rpa_kb, lat->rpa_kb, (size_t)nterms));
+        TRY(upload(c, &c->rpa_cnt, lat->rpa_cnt, (size_t)nterms));
+        TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
+        std::vector<int> sa(c->nsu), sc(c->nsu);
+        for (int a = 0; a < nf; ++a)
+            for (int cc = 0; cc <= a; ++cc) { sa[a * (a + 1) / 2 + cc] = a; sc[a * (a + 1) / 2 + cc] = cc; }
+        TRY(upload(c, &c->su_a, sa.data(), sa.size()));
+        TRY(upload(c, &c->su_c, sc.data(), sc.size()));
+        std::vector<int> cp;
+        std::vector<double> dr;
+        for (int b = 0; b < lat->n_basis; ++b)
+            for (int k = 0; k < lat->n_sites_total; ++k) {
+                const int pr = lat->site_pair[b * lat->n_sites_total + k];
+                if (pr < 0) continue;
+                if (pr >= ns) return fail(PFFRG_EINVAL, "site_pair out of range");
+                cp.push_back(pr);
+                for (int d = 0; d < 3; ++d)
+                    dr.push_back(lat->basis_pos[3 * b + d] - lat->site_pos[3 * (b * lat->n_sites_total + k) + d]);
+            }
+        c->nterm = (int)cp.size();
+        TRY(upload(c, &c->chi_pair, cp.data(), cp.size()));
+        TRY(upload(c, &c->chi_dr, dr.data(), dr.size()));
+        TRY(dev_alloc(c, &c->tab_n, (size_t)3 * nf));
+        TRY(dev_alloc(c, &c->tab_w, (size_t)3 * nf * c->nq));
+        TRY(dev_alloc(c, &c->tab_g, (size_t)3 * nf * c->nq));
+        TRY(dev_alloc(c, &c->dsig, (size_t)nf));
+        for (int j = 0; j < kNumK; ++j) TRY(dev_alloc(c, &c->k[j], (size_t)c->size));
+        TRY(dev_alloc(c, &c->ybuf, (size_t)c->size));
+        TRY(dev_alloc(c, &c->ebuf, (size_t)c->size));
+        TRY(dev_alloc(c, &c->cw, (size_t)c->nq));
+        TRY(dev_alloc(c, &c->cq, (size_t)c->nq));
+        TRY(dev_alloc(c, &c->cg2, (size_t)c->nq));
+        TRY(dev_alloc(c, &c->cn, 1));
+        TRY(dev_alloc(c, &c->chi, (size_t)2 * ns));
+        TRY(dev_alloc(c, &c->part, (size_t)2 * kRedBlocks));
+        TRY(dev_alloc(c, &c->red, 2));
+        HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
+        const VertexLds L{c->nq, c->ns};
+        if (L.total() > 64 * 1024) return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
+        return PFFRG_OK;
+    };
+    pffrg_status st = body();
+    if (st != PFFRG_OK) {
+        release(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_destroy(pffrg_ctx* c) {
+    if (!c) return PFFRG_OK;
+    (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_set_stream(pffrg_ctx* c, void* stream) {
+    TRY(check_ctx(c));
+    c->stream = static_cast<hipStream_t>(stream);
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_state_size(const pffrg_ctx* c, size_t* n) {
+    TRY(check_ctx(c));
+    if (!n) return fail(PFFRG_EINVAL, "null output");
+    *n = (size_t)c->size;
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_init_state(pffrg_ctx* c, double* x) {
+    TRY(check_ctx(c));
+    if (!x) return fail(PFFRG_EINVAL, "null state");
+    hipLaunchKernelGGL(k_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size, c->nf,
+                       c->ns, (const double*)c->coupling, x);
+    return launch_check("k_init_state");
+}
+
+pffrg_status pffrg_rhs(pffrg_ctx* c, double lambda, const double* x, double* dx) {
+    TRY(check_ctx(c));
+    if (!x || !dx) return fail(PFFRG_EINVAL, "null state");
+    if (x == dx) return fail(PFFRG_EINVAL, "state and derivative must not overlap");
+    return rhs(c, lambda, x, dx);
+}
+
+pffrg_status pffrg_sigma_rhs(pffrg_ctx* c, double lambda, const double* x, double* dsig) {
+    TRY(check_ctx(c));
+    if (!x || !dsig) return fail(PFFRG_EINVAL, "null pointer");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    return sigma_rhs(c, lambda, x, dsig);
+}
+
+pffrg_status pffrg_step(pffrg_ctx* c, pffrg_scheme scheme, double l0, double l1, double* x) {
+    TRY(check_ctx(c));
+    if (!x) return fail(PFFRG_EINVAL, "null state");
+    if (!(l0 > 0.0) || !(l1 > 0.0) || !std::isfinite(l0) || !std::isfinite(l1))
+        return fail(PFFRG_EINVAL, "cutoffs must be finite and > 0");
+    switch (scheme) {
+        case PFFRG_EULER: return step_euler(c, l0, l1, x);
+        case PFFRG_RK4: return step_rk4(c, l0, l1, x);
+        default: return fail(PFFRG_EINVAL, "pffrg_step takes PFFRG_EULER or PFFRG_RK4");
+    }
+}
+
+pffrg_status pffrg_chi(pffrg_ctx* c, double lambda, const double* x, double* chi) {
+    TRY(check_ctx(c));
+    if (!x || !chi) return fail(PFFRG_EINVAL, "null pointer");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(1), 0, c->stream, (const double*)c->w, c->nf, lambda, x, c->cw,
+                       c->cq, c->cg2, c->cn);
+    TRY(launch_check("k_chi_nodes"));
+    hipLaunchKernelGGL(k_chi_pairs, dim3(c->ns), dim3(kChiThreads), 0, c->stream, (const double*)c->w, c->nf, c->ns,
+                       (const int*)c->swap, x, (const double*)c->cw, (const double*)c->cq,
+                       (const double*)c->cg2, (const int*)c->cn, chi);
+    return launch_check("k_chi_pairs");
+}
+
+pffrg_status pffrg_chi_k(pffrg_ctx* c, const double* chi, int nk, const double* kp, double* out) {
+    TRY(check_ctx(c));
+    if (nk < 0 || (nk > 0 && (!chi || !kp || !out))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
+    if (nk == 0) return PFFRG_OK;
+    hipLaunchKernelGGL(k_chi_k, dim3((nk + 127) / 128), dim3(128), 0, c->stream, c->nterm,
+                       (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, chi, nk, kp, out);
+    return launch_check("k_chi_k");
+}
+
+pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg_observer cb, void* user,
+                        int* n_steps) {
+    TRY(check_ctx(c));
+    if (!o || !x) return fail(PFFRG_EINVAL, "null options or state");
+    if (o->n_k < 0 || (o->n_k > 0 && (!o->d_k || !o->d_chi_k))) return fail(PFFRG_EINVAL, "bad k-point arguments");
+    int steps = 0;
+    if (n_steps) *n_steps = 0;
+    if (o->scheme == PFFRG_EULER || o->scheme == PFFRG_RK4) {
+        if (o->n_lambda < 2 || !o->lambdas) return fail(PFFRG_EINVAL, "fixed schedule needs >= 2 cutoffs");
+        for (int i = 0; i < o->n_lambda; ++i)
+            if (!(o->lambdas[i] > 0.0) || !std::isfinite(o->lambdas[i]))
+                return fail(PFFRG_EINVAL, "cutoffs must be finite and > 0");
+        for (int i = 0; i + 1 < o->n_lambda; ++i) {
+            HIP_TRY(hipMemcpyAsync(c->ybuf, x, sizeof(double) * c->size, hipMemcpyDeviceToDevice, c->stream));
+            TRY(pffrg_step(c, o->scheme, o->lambdas[i], o->lambdas[i + 1], x));
+            bool fin = true;
+            TRY(reduce_err(c, nullptr, x, nullptr, 0.0, 0.0, nullptr, &fin));
+            if (!fin) {
+                HIP_TRY(hipMemcpyAsync(x, c->ybuf, sizeof(double) * c->size, hipMemcpyDeviceToDevice, c->stream));
+                HIP_TRY(hipStreamSynchronize(c->stream));
+                if (n_steps) *n_steps = steps;
+                return fail(PFFRG_EDIVERGED, "state not finite after step to lambda = " +
+                                                 std::to_string(o->lambdas[i + 1]));
+            }
+            ++steps;
+            if (n_steps) *n_steps = steps;
+            int stop = 0;
+            TRY(observe(c, o, o->lambdas[i + 1], x, cb, user, &stop));
+            if (stop) break;
+        }
+        return PFFRG_OK;
+    }
+    if (o->scheme != PFFRG_DOPRI54) return fail(PFFRG_EINVAL, "unknown scheme");
+    if (!(o->lam_start > o->lam_stop) || !(o->lam_stop > 0.0) || !(o->h0 > 0.0) || !(o->hmin > 0.0) ||
+        !(o->rtol >= 0.0) || !(o->atol >= 0.0) || !(o->rtol + o->atol > 0.0))
+        return fail(PFFRG_EINVAL, "bad adaptive options");
+    const double lend = std::log(o->lam_stop);
+    double l = std::log(o->lam_start);
+    double h = o->h0;
+    const int maxs = o->max_steps > 0 ? o->max_steps : 1000000;
+    TRY(rhs(c, std::exp(l), x, c->k[0]));
+    int attempts = 0;
+    while (l > lend) {
+        if (++attempts > 50 * maxs) return fail(PFFRG_EDIVERGED, "too many rejected steps");
+        double dl = -h;
+        bool last = false;
+        if (l + dl <= lend) { dl = lend - l; last = true; }
+        double err = 0.0;
+        bool fin = true;
+        double lam[7];
+        TRY(dopri_attempt(c, l, dl, x, o->atol, o->rtol, &err, &fin, lam));
+        if (fin && err <= 1.0) {
+            // accept: x <- y, k0 <- k6 (first-same-as-last)
+            HIP_TRY(hipMemcpyAsync(x, c->ybuf, sizeof(double) * c->size, hipMemcpyDeviceToDevice, c->stream));
+            std::swap(c->k[0], c->k[6]);
+            l = last ? lend : l + dl;
+            ++steps;
+            if (n_steps) *n_steps = steps;
+            int stop = 0;
+            TRY(observe(c, o, std::exp(l), x, cb, user, &stop));
+            if (stop || steps >= maxs) break;
+            const double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 5.0;
+            h = std::fabs(dl) * std::fmin(5.0, std::fmax(0.2, fac));
+        } else {
+            const double fac = (fin && err > 0.0) ? 0.9 * std::pow(err, -0.2) : 0.2;
+            h = std::fabs(dl) * std::fmin(1.0, std::fmax(0.2, fac));
+        }
+        if (h < o->hmin && l > lend)
+            return fail(PFFRG_EDIVERGED, "adaptive step fell below hmin at lambda = " + std::to_string(std::exp(l)));
+    }
+    return PFFRG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+"""Python face of libpffrg: same names as the C ABI, argument marshalling only.
+
+Device memory and streams come from PyTorch (float64 CUDA tensors on ROCm);
+every step of the flow runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from .lattice import LatticeTables, build_tables
+
+
+def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A ``pffrg_ctx``: one lattice model on one frequency mesh."""
+
+    def __init__(self, tables: LatticeTables, mesh, precision: str = "fp64", stream=None):
+        self.lib = _lib.load()
+        self.tables = tables
+        self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
+        self.nf = len(self.mesh)
+        self.ns = tables.n_pairs
+        t = tables
+        keep = [np.ascontiguousarray(a) for a in (t.swap, t.mult, t.rpa_off, t.rpa_ka, t.rpa_kb,
+                                                  t.rpa_cnt)]
+        keep += [np.ascontiguousarray(t.coupling, dtype=np.float64),
+                 np.ascontiguousarray(t.site_pair, dtype=np.int32),
+                 np.ascontiguousarray(t.site_pos, dtype=np.float64),
+                 np.ascontiguousarray(t.basis_pos, dtype=np.float64)]
+        ptr = [ctypes.c_void_p(a.ctypes.data) for a in keep]
+        lat = _lib.Lattice(t.n_pairs, ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6],
+                           t.n_basis, t.n_sites_total, ptr[7], ptr[8], ptr[9])
+        msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
+        prec = {"fp64": _lib.FP64, "fp32": _lib.FP32}[precision]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.pffrg_create(ctypes.byref(lat), ctypes.byref(msh), prec,
+                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        n = ctypes.c_size_t()
+        _lib.check(self.lib.pffrg_state_size(self.handle, ctypes.byref(n)))
+        self.size = int(n.value)
+        self.n_su = self.nf * (self.nf + 1) // 2
+        self.vsize = self.n_su * self.nf * self.ns
+
+    @classmethod
+    def from_model(cls, model, lattice_range, mesh, **kw):
+        return cls(build_tables(model, lattice_range), mesh, **kw)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.check(self.lib.pffrg_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ state --
+    def new_state(self) -> torch.Tensor:
+        return torch.empty(self.size, dtype=torch.float64, device="cuda")
+
+    def split(self, x: torch.Tensor):
+        """Views (sig[nf], Gs[n_su, nf, ns], Gd[n_su, nf, ns])."""
+        nf, v = self.nf, self.vsize
+        return (x[:nf], x[nf:nf + v].view(self.n_su, nf, self.ns),
+                x[nf + v:].view(self.n_su, nf, self.ns))
+
+    def init_state(self, x: torch.Tensor | None = None) -> torch.Tensor:
+        x = self.new_state() if x is None else x
+        _lib.check(self.lib.pffrg_init_state(self.handle, _dptr(x)))
+        return x
+
+    # -------------------------------------------------------------- flow --
+    def rhs(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.new_state() if out is None else out
+        _lib.check(self.lib.pffrg_rhs(self.handle, float(lam), _dptr(x), _dptr(out)))
+        return out
+
+    def sigma_rhs(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty(self.nf, dtype=torch.float64, device="cuda") if out is None else out
+        _lib.check(self.lib.pffrg_sigma_rhs(self.handle, float(lam), _dptr(x), _dptr(out)))
+        return out
+
+    def step(self, scheme: str, lam0: float, lam1: float, x: torch.Tensor) -> torch.Tensor:
+        sc = {"euler": _lib.EULER, "rk4": _lib.RK4}[scheme]
+        _lib.check(self.lib.pffrg_step(self.handle, sc, float(lam0), float(lam1), _dptr(x)))
+        return x
+
+    def flow(self, x: torch.Tensor, *, schedule=None, scheme: str = "rk4", lam_start=None,
+             lam_stop=None, rtol=1e-6, atol=1e-10, h0=0.05, hmin=1e-8, max_steps=0,
+             kpoints: torch.Tensor | None = None, observer=None) -> int:
+        """Integrate x in place; observer(lam, chi_pairs[2, ns], chi_k or None)
+        receives torch views of the library's device buffers (copy to keep)."""
+        o = _lib.FlowOpts()
+        o.scheme = {"euler": _lib.EULER, "rk4": _lib.RK4, "dopri54": _lib.DOPRI54}[scheme]
+        sched = None
+        if scheme in ("euler", "rk4"):
+            sched = np.ascontiguousarray(schedule, dtype=np.float64)
+            o.n_lambda = len(sched)
+            o.lambdas = ctypes.c_void_p(sched.ctypes.data)
+        else:
+            o.lam_start, o.lam_stop = float(lam_start), float(lam_stop)
+        o.rtol, o.atol, o.h0, o.hmin, o.max_steps = rtol, atol, h0, hmin, int(max_steps)
+        chik = None
+        if kpoints is not None:
+            kp = kpoints.contiguous()
+            chik = torch.empty(kp.shape[0], dtype=torch.float64, device="cuda")
+            o.n_k, o.d_k, o.d_chi_k = int(kp.shape[0]), _dptr(kp), _dptr(chik)
+        ns = self.ns
+
+        def _cb(lam, dchi, dchik, _user):
+            if observer is None:
+                return 0
+            chi = _wrap(dchi, 2 * ns).view(2, ns)
+            ck = chik if dchik else None
+            return int(bool(observer(lam, chi, ck)))
+
+        cb = _lib.OBSERVER(_cb) if observer is not None else _lib.OBSERVER()
+        nsteps = ctypes.c_int()
+        _lib.check(self.lib.pffrg_flow(self.handle, ctypes.byref(o), _dptr(x), cb, None,
+                                       ctypes.byref(nsteps)))
+        del sched
+        return int(nsteps.value)
+
+    # ------------------------------------------------------- observables --
+    def chi(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """[2, ns]: chi^{zz} and chi^{00} per reduced pair."""
+        out = torch.empty(2 * self.ns, dtype=torch.float64, device="cuda") if out is None else out
+        _lib.check(self.lib.pffrg_chi(self.handle, float(lam), _dptr(x), _dptr(out)))
+        return out.view(2, self.ns)
+
+    def chi_k(self, chi: torch.Tensor, kpoints: torch.Tensor, out: torch.Tensor | None = None):
+        kp = kpoints.contiguous()
+        out = torch.empty(kp.shape[0], dtype=torch.float64, device="cuda") if out is None else out
+        _lib.check(self.lib.pffrg_chi_k(self.handle, _dptr(chi.contiguous()), int(kp.shape[0]),
+                                        _dptr(kp), _dptr(out)))
+        return out
+
+
+def _wrap(ptr: int, n: int) -> torch.Tensor:
+    """A float64 torch view of n doubles of library-owned device memory."""
+    # torch has no public from-pointer constructor for device memory; go via
+    # the CUDA array interface.
+    class _Holder:
+        __cuda_array_interface__ = {"shape": (n,), "typestr": "<f8", "data": (ptr, False), "version": 2}
+    return torch.as_tensor(_Holder(), device="cuda")

@@ -1,0 +1,286 @@
+"""Symmetry-reduced lattice tables for the flow library (Sec. 4.1).
+
+This is the input front end of the library: it turns a unit cell, a coupling
+model and a truncation range into the integer tables that the C-ABI
+``pffrg_create`` consumes.  It runs once per lattice on the host; none of the
+flow arithmetic happens here.
+
+Construction (Sec. 4.1):
+  * reference site i_ref = basis site 0 of cell 0;
+  * lattice symmetries are Euclidean isometries x -> O x + v that map the
+    lattice to itself, bonds to bonds and couplings to equal couplings; they
+    are found by mapping the nearest-neighbour bond vectors of one site onto
+    those of another and validating the candidate on the unit cell;
+  * for every basis site b one symmetry T_b with T_b(r_b) = r_ref, so any
+    pair (i1, i2) maps to (i_ref, T(i2)) (Eq. 33);
+  * sites within bond distance L of i_ref (Eq. 34) split into orbits of the
+    stabiliser of i_ref (Eq. 35 without spin permutations, which SU(2) does
+    not need); each orbit is one reduced pair, pair 0 is on-site;
+  * tabulated lattice sums: for output pair p = (i_ref, j_p), every site k
+    within range of both ends contributes Gamma_{i_ref k} Gamma_{k j_p}; k maps
+    to pair ka and (k, j_p) maps, via T_k, to pair kb.  Equal (ka, kb) are
+    merged with a multiplicity.
+"""
+
+from __future__ import annotations
+
+from collections import deque
+from dataclasses import dataclass
+import itertools
+
+import numpy as np
+
+EPS = 1e-5      # real-space precision of the symmetry search (Sec. 4.1)
+
+
+@dataclass
+class LatticeTables:
+    """Everything ``pffrg_create`` needs about the lattice, as flat arrays."""
+    n_pairs: int
+    swap: np.ndarray            # int32 [n_pairs]
+    mult: np.ndarray            # int32 [n_pairs]
+    rpa_off: np.ndarray         # int32 [n_pairs+1]
+    rpa_ka: np.ndarray          # int32 [n_terms]
+    rpa_kb: np.ndarray          # int32 [n_terms]
+    rpa_cnt: np.ndarray         # int32 [n_terms]
+    coupling: np.ndarray        # float64 [n_pairs], J of the bond (i_ref, j_p)
+    n_basis: int
+    n_sites_total: int
+    site_pair: np.ndarray       # int32 [n_basis, n_sites_total]
+    site_pos: np.ndarray        # float64 [n_basis, n_sites_total, 3]
+    basis_pos: np.ndarray       # float64 [n_basis, 3]
+    pair_rep: np.ndarray        # int32 [n_pairs, 4]: (cell0, cell1, cell2, basis)
+    stabiliser_order: int
+
+    @property
+    def n_terms(self) -> int:
+        return int(self.rpa_off[-1])
+
+
+class _Lattice:
+    def __init__(self, cell, interactions, params):
+        self.A = np.asarray(cell.primitives, dtype=np.float64)
+        self.Ainv = np.linalg.inv(self.A)
+        self.basis = np.asarray(cell.basis, dtype=np.float64)
+        self.nb = len(self.basis)
+        self.bonds = set()
+        self.nbrs = [[] for _ in range(self.nb)]
+        for (f, t, d0, d1, d2) in cell.bonds:
+            d = (d0, d1, d2)
+            self.bonds.add((f, t, d))
+            self.bonds.add((t, f, (-d0, -d1, -d2)))
+            self.nbrs[f].append((d, t))
+            self.nbrs[t].append(((-d0, -d1, -d2), f))
+        self.J = {}
+        for (pname, f, t, d0, d1, d2) in interactions:
+            val = float(params.get(pname, 0.0))
+            for key in ((f, t, (d0, d1, d2)), (t, f, (-d0, -d1, -d2))):
+                self.J[key] = self.J.get(key, 0.0) + val
+
+    def pos(self, cell, b):
+        return np.asarray(cell, dtype=np.float64) @ self.A + self.basis[b]
+
+    def locate(self, p):
+        """(cell, basis) of the lattice site at position p, or None."""
+        for b in range(self.nb):
+            f = (p - self.basis[b]) @ self.Ainv
+            r = np.rint(f)
+            if np.abs(f - r).max() < EPS:
+                return (int(r[0]), int(r[1]), int(r[2])), b
+        return None
+
+    def coupling(self, c1, b1, c2, b2):
+        d = (c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2])
+        return self.J.get((b1, b2, d), 0.0)
+
+    def bonded(self, c1, b1, c2, b2):
+        d = (c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2])
+        return (b1, b2, d) in self.bonds
+
+    def ball(self, b, L):
+        """Sites within bond distance L of (cell 0, b), BFS order, with distances."""
+        start = ((0, 0, 0), b)
+        dist = {start: 0}
+        order = [start]
+        q = deque([start])
+        while q:
+            node = q.popleft()
+            if dist[node] == L:
+                continue
+            (c, bb) = node
+            for (d, b2) in self.nbrs[bb]:
+                nxt = ((c[0] + d[0], c[1] + d[1], c[2] + d[2]), b2)
+                if nxt not in dist:
+                    dist[nxt] = dist[node] + 1
+                    order.append(nxt)
+                    q.append(nxt)
+        return order, dist
+
+
+class _Iso:
+    """x -> O x + v."""
+
+    def __init__(self, O, v):
+        self.O, self.v = O, v
+
+    def apply(self, lat, site):
+        c, b = site
+        return lat.locate(self.O @ lat.pos(c, b) + self.v)
+
+
+def _frame(vecs):
+    """Three independent vectors from a neighbour-vector list (normal added
+    for planar stars); returns (indices, matrix) or raises."""
+    vecs = [np.asarray(v) for v in vecs]
+    for i, j in itertools.permutations(range(len(vecs)), 2):
+        n = np.cross(vecs[i], vecs[j])
+        if np.linalg.norm(n) < EPS:
+            continue
+        for k in range(len(vecs)):
+            if abs(np.dot(n, vecs[k])) > EPS:
+                return (i, j, k), np.array([vecs[i], vecs[j], vecs[k]])
+        return (i, j, -1), np.array([vecs[i], vecs[j], n / np.linalg.norm(n)])
+    raise ValueError("bond star does not span two dimensions")
+
+
+def _symmetries_onto(lat, b_from, b_to):
+    """All lattice symmetries g with g(r_{b_from}) = r_{b_to} (both in cell 0)."""
+    src = [lat.pos(d, t) - lat.pos((0, 0, 0), b_from) for (d, t) in lat.nbrs[b_from]]
+    dst = [lat.pos(d, t) - lat.pos((0, 0, 0), b_to) for (d, t) in lat.nbrs[b_to]]
+    (i, j, k), X = _frame(src)
+    r_from, r_to = lat.pos((0, 0, 0), b_from), lat.pos((0, 0, 0), b_to)
+    out = []
+    cand_k = range(len(dst)) if k >= 0 else (None,)
+    for ii, jj in itertools.permutations(range(len(dst)), 2):
+        for kk in cand_k:
+            rows = [dst[ii], dst[jj]]
+            if kk is None:
+                n = np.cross(dst[ii], dst[jj])
+                if np.linalg.norm(n) < EPS:
+                    continue
+                n = n / np.linalg.norm(n)
+                choices = [rows + [n], rows + [-n]]
+            else:
+                if kk in (ii, jj):
+                    continue
+                choices = [rows + [dst[kk]]]
+            for Yr in choices:
+                Y = np.array(Yr)
+                try:
+                    O = np.linalg.solve(X, Y).T        # O X^T = Y^T
+                except np.linalg.LinAlgError:
+                    continue
+                if np.abs(O.T @ O - np.eye(3)).max() > EPS:
+                    continue
+                g = _Iso(O, r_to - O @ r_from)
+                if _valid(lat, g) and not any(np.abs(O - h.O).max() < EPS for h in out):
+                    out.append(g)
+    return out
+
+
+def _valid(lat, g):
+    """g maps lattice translations to translations, basis sites to sites,
+    and every bond / coupling of the unit cell to an equal one."""
+    for a in lat.A:
+        f = (g.O @ a) @ lat.Ainv
+        if np.abs(f - np.rint(f)).max() > EPS:
+            return False
+    img = {}
+    for b in range(lat.nb):
+        s = g.apply(lat, ((0, 0, 0), b))
+        if s is None:
+            return False
+        img[b] = s
+    keys = set(lat.bonds) | set(lat.J)
+    for (b1, b2, d) in keys:
+        s1 = img[b1]
+        s2 = g.apply(lat, (d, b2))
+        if s2 is None:
+            return False
+        if lat.bonded(s1[0], s1[1], s2[0], s2[1]) != ((b1, b2, d) in lat.bonds):
+            return False
+        if abs(lat.coupling(s1[0], s1[1], s2[0], s2[1]) - lat.J.get((b1, b2, d), 0.0)) > 1e-12:
+            return False
+    return True
+
+
+def build_tables(model, L: int) -> LatticeTables:
+    """Reduced pair tables for ``model`` (a ``workloads.Model``) at range L."""
+    lat = _Lattice(model.cell, model.interactions, model.params)
+    L = int(L)
+    stab = _symmetries_onto(lat, 0, 0)
+    to_ref = []
+    for b in range(lat.nb):
+        gs = _symmetries_onto(lat, b, 0)
+        if not gs:
+            raise ValueError(f"basis site {b} is not equivalent to the reference site")
+        to_ref.append(gs[0])
+
+    ball0, dist0 = lat.ball(0, L)
+    in_ball = set(ball0)
+    orbit_of = {}
+    reps = []
+    mult = []
+    for site in ball0:
+        if site in orbit_of:
+            continue
+        p = len(reps)
+        reps.append(site)
+        members = {site}
+        for g in stab:
+            im = g.apply(lat, site)
+            members.add(im)
+        for m in members:
+            if m not in in_ball:
+                raise RuntimeError("stabiliser does not preserve the truncation ball")
+            orbit_of[m] = p
+        mult.append(len(members))
+    n_pairs = len(reps)
+
+    def to_reference(site_a, site_b):
+        """Reduced pair of (site_a, site_b), or -1 if out of range."""
+        (ca, ba) = site_a
+        (cb, bb) = site_b
+        shifted = ((cb[0] - ca[0], cb[1] - ca[1], cb[2] - ca[2]), bb)
+        im = to_ref[ba].apply(lat, shifted)
+        return orbit_of.get(im, -1)
+
+    swap = np.array([to_reference(r, ((0, 0, 0), 0)) for r in reps], dtype=np.int32)
+    if (swap < 0).any():
+        raise RuntimeError("pair swap left the truncation range")
+
+    off = [0]
+    ka_l, kb_l, cnt_l = [], [], []
+    for p, rep in enumerate(reps):
+        terms = {}
+        for k in ball0:
+            kb = to_reference(k, rep)
+            if kb < 0:
+                continue
+            key = (orbit_of[k], kb)
+            terms[key] = terms.get(key, 0) + 1
+        for (a, b), n in sorted(terms.items()):
+            ka_l.append(a); kb_l.append(b); cnt_l.append(n)
+        off.append(len(ka_l))
+
+    coupling = np.array([lat.coupling((0, 0, 0), 0, r[0], r[1]) for r in reps])
+
+    balls = [lat.ball(b, L)[0] for b in range(lat.nb)]
+    ntot = max(len(bl) for bl in balls)
+    site_pair = np.full((lat.nb, ntot), -1, dtype=np.int32)
+    site_pos = np.zeros((lat.nb, ntot, 3))
+    for b, bl in enumerate(balls):
+        for k, site in enumerate(bl):
+            site_pair[b, k] = to_reference(((0, 0, 0), b), site)
+            site_pos[b, k] = lat.pos(*site)
+    if (site_pair[site_pair != -1] < 0).any():
+        raise RuntimeError("site map incomplete")
+
+    return LatticeTables(
+        n_pairs=n_pairs, swap=swap, mult=np.array(mult, dtype=np.int32),
+        rpa_off=np.array(off, dtype=np.int32), rpa_ka=np.array(ka_l, dtype=np.int32),
+        rpa_kb=np.array(kb_l, dtype=np.int32), rpa_cnt=np.array(cnt_l, dtype=np.int32),
+        coupling=coupling, n_basis=lat.nb, n_sites_total=ntot, site_pair=site_pair,
+        site_pos=site_pos, basis_pos=lat.basis.copy(),
+        pair_rep=np.array([[r[0][0], r[0][1], r[0][2], r[1]] for r in reps], dtype=np.int32),
+        stabiliser_order=len(stab))

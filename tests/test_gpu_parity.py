@@ -1,0 +1,147 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Bar (FP64): max |gpu - oracle| / max |oracle| <= 1e-10 over every element
+(the oracle's unreduced elements, matched to the library's reduced pairs by
+site position).  Sizes span several workgroups per launch and the lattices
+with non-trivial pair exchange (honeycomb, pyrochlore).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import compare_chi, compare_triples, compare_vertex, expand_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+CASES = {
+    # name: (lattice, params, range, mesh)
+    "square_L2_N8": ("square", dict(j1=1.0), 2, W.log_mesh(0.005, 50.0, 8)),
+    "square_j1j2_L3_N7": ("square", dict(j1=1.0, j2=0.5), 3, W.log_mesh(1e-3, 100.0, 7)),
+    "honeycomb_L3_N6": ("honeycomb", dict(j1=0.6, j2=0.3, j3=0.45), 3, W.log_mesh(1e-3, 100.0, 6)),
+    "pyrochlore_L2_N5": ("pyrochlore", dict(j1=1.0), 2, W.log_mesh(1e-3, 100.0, 5)),
+}
+
+
+def _setup(name):
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    lat, params, L, mesh = CASES[name]
+    model = W.model(lat, **params)
+    tables = build_tables(model, L)
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, L, mesh, threads=0)
+    return torch, tables, ctx, orc
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("lam_kind", ["low", "mid", "mesh", "high"])
+def test_rhs_random_state(name, lam_kind):
+    torch, tables, ctx, orc = _setup(name)
+    mesh = ctx.mesh
+    lam = {"low": 0.5 * mesh[0], "mid": 0.37, "mesh": float(mesh[len(mesh) // 2]),
+           "high": 1.7 * mesh[-1]}[lam_kind]
+    x = W.random_state(ctx.nf, ctx.ns, seed=hash((name, lam_kind)) % 1000)
+    _say(f"rhs {name} lam={lam}")
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = orc.rhs(lam, expand_state(orc, tables, x))
+    err = compare_vertex(orc, tables, ref, d)
+    assert err <= TOL, err
+
+
+@pytest.mark.parametrize("name", ["square_L2_N8", "honeycomb_L3_N6"])
+def test_rhs_initial_state_and_init_kernel(name):
+    torch, tables, ctx, orc = _setup(name)
+    x = ctx.init_state()
+    x0 = orc.initial_state()
+    assert compare_vertex(orc, tables, x0, x.cpu().numpy()) == 0.0
+    for lam in (0.05, 2.0):
+        d = ctx.rhs(lam, x).cpu().numpy()
+        assert compare_vertex(orc, tables, orc.rhs(lam, x0), d) <= 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_chi_and_structure_factor(name):
+    torch, tables, ctx, orc = _setup(name)
+    x = W.random_state(ctx.nf, ctx.ns, seed=3)
+    xo = expand_state(orc, tables, x)
+    for lam in (0.02, 0.7):
+        _say(f"chi {name} lam={lam}")
+        chi = ctx.chi(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+        zz, dd = orc.chi(lam, xo)
+        assert compare_chi(orc, tables, zz, dd, chi) <= TOL
+        kp = np.random.default_rng(1).uniform(-math.pi, math.pi, (37, 3))
+        kp[:, 2] = 0.0 if name.startswith(("square", "honeycomb")) else kp[:, 2]
+        ck = ctx.chi_k(torch.from_numpy(chi.reshape(-1)).cuda(), torch.from_numpy(kp).cuda()).cpu().numpy()
+        ref = orc.chi_k(zz, kp)
+        assert np.abs(ck - ref).max() <= TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("scheme", ["euler", "rk4"])
+def test_single_steps(scheme):
+    torch, tables, ctx, orc = _setup("honeycomb_L3_N6")
+    x = W.random_state(ctx.nf, ctx.ns, seed=21, scale=0.1)
+    xd = torch.from_numpy(x).cuda()
+    xo = expand_state(orc, tables, x)
+    l0, l1 = 0.9, 0.8
+    ctx.step(scheme, l0, l1, xd)
+    ref = orc.euler_step(l0, l1, xo) if scheme == "euler" else orc.rk4_step(l0, l1, xo)
+    assert compare_vertex(orc, tables, ref, xd.cpu().numpy()) <= TOL
+
+
+def test_rk4_flow_square_tiny_with_chi_every_step():
+    """The small workload end to end: square L=2, 8 frequencies, 40 RK4 steps
+    from Lambda=50 to 0.5, chi compared at every step."""
+    torch, tables, ctx, orc = _setup("square_L2_N8")
+    wl = W.workload("square_tiny")
+    x = ctx.init_state()
+    got = []
+    ctx.flow(x, schedule=wl.schedule, scheme="rk4",
+             observer=lambda lam, chi, ck: got.append((lam, chi.cpu().numpy().copy())) and 0)
+    ref_chi = []
+    xo = orc.flow(wl.schedule, observer=lambda lam, xs: ref_chi.append((lam, orc.chi(lam, xs))))
+    assert compare_vertex(orc, tables, xo, x.cpu().numpy()) <= TOL
+    assert len(got) == len(ref_chi) == len(wl.schedule) - 1
+    for (lg, cg), (lr, (zz, dd)) in zip(got, ref_chi):
+        assert lg == lr
+        assert compare_chi(orc, tables, zz, dd, cg) <= TOL
+
+
+@pytest.mark.parametrize("which", ["square_j1j2", "pyrochlore"])
+def test_full_size_rhs_sampled(which):
+    """The library at full workload size; the oracle computes every element of
+    a sample of frequency triples (mesh corners, diagonal, random)."""
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    wl = W.workload(which)
+    model = wl.model()
+    tables = build_tables(model, wl.range)
+    ctx = Context(tables, wl.mesh)
+    orc = oracle.Oracle(model, wl.range, wl.mesh, threads=0)
+    nf = ctx.nf
+    x = W.random_state(nf, ctx.ns, seed=5, scale=0.2)
+    lam = 0.21
+    _say(f"full-size rhs {which} nf={nf} ns={ctx.ns}")
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    xo = expand_state(orc, tables, x)
+    dsig = orc.sigma_rhs(lam, xo)
+    assert np.abs(dsig - d[:nf]).max() <= TOL * np.abs(dsig).max()
+    rng = np.random.default_rng(2)
+    tri = [(0, 0, 0), (nf - 1, nf - 1, nf - 1), (nf - 1, 0, 0), (nf - 1, nf // 2, nf - 1)]
+    for _ in range(4 if which == "pyrochlore" else 8):
+        a = int(rng.integers(nf)); c = int(rng.integers(a + 1)); t = int(rng.integers(nf))
+        tri.append((a, t, c))
+    ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
+    assert compare_triples(orc, tables, tri, ref, d) <= TOL
