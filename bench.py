@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Benchmark of the SU(2) pf-FRG flow hot path on one MI355X.
+
+Workload: square-lattice J1-J2 Heisenberg model, J2/J1 = 0.5, vertex range 7
+bonds (20 symmetry-reduced pairs, 113 sites in range), 32 positive Matsubara
+frequencies log-spaced 1e-3..100, FP64.  Synthetic input: the flow state is
+the physical flow from the initial condition (Lambda 100 -> 1 in 40 RK4
+steps, untimed setup); no datasets or trained weights are involved.
+
+One timed step = one pass of the whole hot path: a classical RK4 step
+(4 self-energy + 4 vertex right-hand sides and the stage combinations) from
+Lambda to 0.95 Lambda, then chi per pair and chi(k) on a 64x64 k-grid.
+`value` = vertex-RHS elements per second = 4 * E / step time, with
+E = 2 * pairs * triples = 675,840 vertex elements per right-hand side.
+
+Also reported: the dominant kernel's roofline position (algorithmic FP64
+flops per launch over its HIP-event duration), the whole adaptive flow
+(Dormand-Prince 5(4), Lambda 100 -> 0.01, chi(k) every accepted step), and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+PEAK_FP64_VECTOR_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(f"[bench {time.strftime('%H:%M:%S')}]", *a, file=sys.stderr, flush=True)
+
+
+def node_counts(mesh: np.ndarray, lam: float) -> np.ndarray:
+    """Evaluation points per channel (s, t, u) and transfer frequency index:
+    delta points of the single-scale propagator plus trapezoid nodes of the
+    Katanin domain (same rule as the kernels; counting only)."""
+    nf = len(mesh)
+    wmax = mesh[-1]
+    full = np.concatenate([-mesh[::-1], mesh])
+    out = np.zeros((3, nf), dtype=np.int64)
+    for ch in range(3):
+        for iv, nu in enumerate(mesh):
+            n = 0
+            for x in (lam, -lam):
+                winv = nu - x if ch == 0 else (x + nu if ch == 1 else x - nu)
+                px = nu - x if ch == 0 else (x - nu if ch == 1 else nu + x)
+                n += int(abs(winv) >= lam) + int(abs(px) >= lam)
+            c = nu if ch < 2 else -nu
+            e0, e1 = c - lam, c + lam
+            for a, b in ((-wmax, -lam), (lam, wmax)):
+                if not a < b:
+                    continue
+                for lo, hi in ((a, min(b, e0)), (max(a, e1), b)):
+                    if lo < hi:
+                        n += 2 + int(np.count_nonzero((full > lo) & (full < hi)))
+            out[ch, iv] = n
+    return out
+
+
+def vertex_flops(mesh: np.ndarray, lam: float, ns: int, n_terms: int) -> float:
+    """Algorithmic FP64 flops of one vertex right-hand side at cutoff lam.
+
+    Per triple (s,t,u) with n_s, n_t, n_u evaluation points:
+      interpolation 16 flops per pair and vertex vector (2 strains x 4 corners
+      FMA), two vectors per point in every channel, plus 32 flops for the two
+      on-site vertices of the t channel; channel products 13 (s,u) and 20 (t)
+      flops per pair and point; particle-hole lattice sum 4 ns^2 flops per t
+      point (two strains, GEMM form); tabulated terms 4 flops each.
+    """
+    nc = node_counts(mesh, lam)
+    nf = len(mesh)
+    tot = 0.0
+    for a in range(nf):
+        for c in range(a + 1):
+            ns_u = nc[0, a] + nc[2, c]
+            for t in range(nf):
+                nt = nc[1, t]
+                tot += ns * (45 * ns_u + 52 * nt) + 4 * ns * ns * nt + 32 * nt + 4 * n_terms
+    return float(tot)
+
+
+def kgrid(n: int) -> np.ndarray:
+    m = (np.arange(n) / n - 0.5) * 2 * math.pi
+    kx, ky = np.meshgrid(m, m, indexing="ij")
+    return np.stack([kx.ravel(), ky.ravel(), np.zeros(n * n)], axis=1)
+
+
+def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
+    """The oracle on a bounded sample: every vertex element of a set of
+    frequency triples (plus the self-energy flow), timed on the host cores;
+    scaled to vertex-RHS elements per second of the reduced workload."""
+    import oracle
+    from tests.parity import expand_state
+    threads = os.cpu_count() or 1
+    orc = oracle.Oracle(model, wl.range, wl.mesh, threads=threads)
+    xo = expand_state(orc, tables, x_np)
+    nf = orc.nf
+    rng = np.random.default_rng(0)
+    all_tr = [(a, t, c) for a in range(nf) for c in range(a + 1) for t in range(nf)]
+    order = rng.permutation(len(all_tr))
+    t0 = time.perf_counter()
+    dsig = orc.sigma_rhs(lam, xo)
+    t_sig = time.perf_counter() - t0
+    first = [all_tr[i] for i in order[:threads]]
+    t0 = time.perf_counter()
+    orc.vertex_rhs_triples(lam, xo, dsig, first)
+    spent = time.perf_counter() - t0
+    done = len(first)
+    more = int(max(0.0, target_s - spent) / (spent / done))
+    more = min(more, len(all_tr) - done)
+    if more > 0:
+        rest = [all_tr[i] for i in order[done:done + more]]
+        t0 = time.perf_counter()
+        orc.vertex_rhs_triples(lam, xo, dsig, rest)
+        spent += time.perf_counter() - t0
+        done += len(rest)
+    elems = 2 * tables.n_pairs * done
+    per_rhs = spent / done * len(all_tr) + t_sig
+    return {
+        "value": elems / spent,
+        "unit": "vertex-RHS elements/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"{done} of {len(all_tr)} frequency triples (all elements of each, "
+                   f"unreduced lattice), one FP64 RHS at Lambda={lam:.4g}, {spent:.1f} s"),
+        "rhs_seconds_extrapolated": per_rhs,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-flow", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the flow engine runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+
+    wl = W.workload("square_j1j2")
+    model = wl.model()
+    tables = build_tables(model, wl.range)
+    ctx = Context(tables, wl.mesh)
+    nf, ns = ctx.nf, ctx.ns
+    triples = nf * nf * (nf + 1) // 2
+    E = 2 * ns * triples
+    kp = torch.from_numpy(kgrid(64)).cuda()
+
+    # setup: the physical flow from the initial condition down to Lambda = 1
+    log(f"context ready: {ns} pairs, {nf} frequencies, {E} vertex elements")
+    x = ctx.init_state()
+    ctx.flow(x, schedule=W.geometric_schedule(100.0, 1.0, 40), scheme="rk4")
+    torch.cuda.synchronize()
+    x_start = x.cpu().numpy()
+    log("setup flow to Lambda=1 done")
+
+    lam = [1.0]
+
+    def step():
+        l0 = lam[0]
+        l1 = l0 * 0.95
+        ctx.step("rk4", l0, l1, x)
+        chi = ctx.chi(l1, x)
+        ctx.chi_k(chi.reshape(-1), kp)
+        lam[0] = l1
+
+    for _ in range(args.warmup):
+        step()
+    lam_timed0 = lam[0]
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    vms, vcount = ctx.profile_read("vertex")
+    sms, _ = ctx.profile_read("sigma")
+    tms, _ = ctx.profile_read("tables")
+    ctx.set_profiling(False)
+    log(f"timed {args.steps} steps: {(t1 - t0) * 1e3 / args.steps:.2f} ms/step, vertex kernel "
+        f"{vms / max(vcount, 1):.3f} ms avg over {vcount} launches")
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = 4 * E / (ms_step * 1e-3)
+
+    # algorithmic flops of every timed vertex launch (RK4 stage cutoffs)
+    flops = 0.0
+    l0 = lam_timed0
+    for _ in range(args.steps):
+        l1 = l0 * 0.95
+        h = l1 - l0
+        for ls in (l0, l0 + 0.5 * h, l0 + 0.5 * h, l1):
+            flops += vertex_flops(wl.mesh, ls, ns, tables.n_terms)
+        l0 = l1
+    vavg_ms = vms / max(vcount, 1)
+    achieved = flops / vcount / (vavg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                "kernel": "k_vertex_rhs", "avg_launch_ms": vavg_ms, "launches": vcount,
+                "flops_per_launch": flops / vcount}
+
+    out = {
+        "metric": "vertex-RHS elements/s + full-flow time vs plain FP64 GPU; adjoint/forward cost",
+        "value": value,
+        "unit": "vertex-RHS elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "square-lattice J1-J2 Heisenberg, J2/J1=0.5, range 7 (20 pairs), "
+                               "32 log freqs 1e-3..100; RK4 step + chi(k) on 64x64",
+                   "pairs": ns, "n_freq": nf, "vertex_elements": E, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernel_ms_per_step": {"vertex": vms / args.steps, "sigma": sms / args.steps,
+                               "tables": tms / args.steps},
+    }
+
+    if not args.no_full_flow:
+        xf = ctx.init_state()
+        torch.cuda.synchronize()
+        nacc = [0]
+
+        def obs(lam_, chi_, ck_):
+            nacc[0] += 1
+            if nacc[0] % 20 == 0:
+                log(f"full flow: {nacc[0]} accepted steps, Lambda={lam_:.4g}")
+            return 0
+
+        log("full adaptive flow 100 -> 0.01")
+        t0 = time.perf_counter()
+        nsteps = ctx.flow(xf, scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-6,
+                          atol=1e-10, h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=obs)
+        torch.cuda.synchronize()
+        out["full_flow"] = {"scheme": "dopri54 in ln Lambda, rtol 1e-6, atol 1e-10",
+                            "lambda": [100.0, 0.01], "seconds": time.perf_counter() - t0,
+                            "accepted_steps": nsteps, "chi_k_every_step": "64x64"}
+
+    if args.copy_probe:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = a.numel() * 8
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(model, wl, tables, x_start, 1.0)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,18 @@ pffrg_status pffrg_chi(pffrg_ctx *ctx, double lambda, const double *d_state, dou
 pffrg_status pffrg_chi_k(pffrg_ctx *ctx, const double *d_chi, int n_k, const double *d_k,
                          double *d_chi_k);
 
+/* ----------------------------------------------------------- profiling - */
+
+/* Kernel timing with HIP events recorded on the context's stream around every
+ * launch of the timed kernels (no effect on results).  pffrg_set_profiling
+ * turns recording on (1) or off (0) and clears the totals.
+ * pffrg_profile_read synchronises the stream and returns, for kernel id
+ * `kernel`, the summed duration in milliseconds and the launch count since
+ * profiling was switched on.  Up to 65536 launches per kernel are kept. */
+enum { PFFRG_K_SIGMA = 0, PFFRG_K_TABLES = 1, PFFRG_K_VERTEX = 2, PFFRG_K_COUNT = 3 };
+pffrg_status pffrg_set_profiling(pffrg_ctx *ctx, int on);
+pffrg_status pffrg_profile_read(pffrg_ctx *ctx, int kernel, double *total_ms, int *count);
+
 /* -------------------------------------------------------------- errors -- */
 
 const char *pffrg_last_error(void);

@@ -23,6 +23,7 @@ live in ``tests/test_oracle_*.py``.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 import time
@@ -192,6 +193,89 @@ class Oracle:
         k3 = self.rhs(lm, x + (0.5 * h) * k2)
         k4 = self.rhs(lam1, x + h * k3)
         return x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+    # Dormand-Prince 5(4) tableau (Dormand & Prince 1980): nodes, stage
+    # coefficients, and the difference of the 5th and 4th order weights.
+    DP_C = (0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0)
+    DP_A = ((), (1 / 5,), (3 / 40, 9 / 40), (44 / 45, -56 / 15, 32 / 9),
+            (19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729),
+            (9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656),
+            (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84))
+    DP_E = (35 / 384 - 5179 / 57600, 0.0, 500 / 1113 - 7571 / 16695, 125 / 192 - 393 / 640,
+            -2187 / 6784 + 92097 / 339200, 11 / 84 - 187 / 2100, -1 / 40)
+
+    def dopri_flow(self, lam_start, lam_stop, rtol, atol, h0, hmin, x0=None, max_steps=0,
+                   observer=None):
+        """Adaptive Dormand-Prince 5(4) in l = ln Lambda (dx/dl = Lambda dx/dLambda)
+        from lam_start down to lam_stop.  Error norm
+        max_i |e_i| / (atol + rtol max(|x_i|, |y_i|)); accept if <= 1; new step
+        |dl| * min(5, max(0.2, 0.9 err^-1/5)) (rejected: at most |dl|).
+        The right-hand side jumps where Lambda crosses w_n/2 (a step function of
+        a delta-point propagator switches), so steps end 1e-12 (in l) above each
+        such breakpoint and restart 1e-12 below it.  Returns (x, accepted cutoffs)."""
+        x = self.initial_state() if x0 is None else np.array(x0, dtype=np.float64)
+        lend = math.log(lam_stop)
+        l = math.log(lam_start)
+        h = h0
+        maxs = max_steps if max_steps > 0 else 1000000
+        brk = sorted((math.log(0.5 * w) for w in self.mesh if lend < math.log(0.5 * w) < l), reverse=True)
+        gap = 1e-12
+        ib = 0
+        k = [None] * 7
+        k[0] = self.rhs(math.exp(l), x)
+        lams = []
+        attempts = 0
+        while l > lend:
+            attempts += 1
+            if attempts > 50 * maxs:
+                raise RuntimeError("too many rejected steps")
+            while ib < len(brk) and brk[ib] + gap >= l:
+                ib += 1
+            dl = -h
+            last = at_brk = False
+            if ib < len(brk) and l + dl <= brk[ib] + gap:
+                dl = (brk[ib] + gap) - l
+                at_brk = True
+            if l + dl <= lend:
+                dl = lend - l
+                last, at_brk = True, False
+            lam = [math.exp(l + c * dl) for c in self.DP_C]
+            for i in range(1, 7):
+                y = x.copy()
+                for j in range(i):
+                    cj = dl * self.DP_A[i][j] * lam[j]
+                    if cj != 0.0:
+                        y += cj * k[j]
+                k[i] = self.rhs(lam[i], y)
+            e = np.zeros_like(x)
+            for j in range(7):
+                cj = dl * self.DP_E[j] * lam[j]
+                if cj != 0.0:
+                    e += cj * k[j]
+            fin = bool(np.all(np.isfinite(y)) and np.all(np.isfinite(x)))
+            err = float(np.max(np.abs(e) / (atol + rtol * np.maximum(np.abs(x), np.abs(y))))) if fin else 0.0
+            if fin and err <= 1.0:
+                x = y
+                k[0] = k[6]
+                l = lend if last else l + dl
+                if at_brk:
+                    l = brk[ib] - gap
+                    ib += 1
+                    k[0] = self.rhs(math.exp(l), x)
+                lams.append(math.exp(l))
+                if observer is not None:
+                    observer(math.exp(l), x)
+                if len(lams) >= maxs:
+                    break
+                fac = 0.9 * err ** -0.2 if err > 0.0 else 5.0
+                hprop = abs(dl) * min(5.0, max(0.2, fac))
+                h = max(h, hprop) if at_brk else hprop
+            else:
+                fac = 0.9 * err ** -0.2 if (fin and err > 0.0) else 0.2
+                h = abs(dl) * min(1.0, max(0.2, fac))
+            if h < hmin and l > lend:
+                raise RuntimeError(f"adaptive step fell below hmin at lambda = {math.exp(l)}")
+        return x, lams
 
     def flow(self, schedule, x0=None, scheme="rk4", observer=None):
         """Integrate along a fixed cutoff schedule; observer(lam, x) after each step."""

@@ -52,7 +52,11 @@ SIGNATURES = {
     "pffrg_flow": [P, ctypes.POINTER(FlowOpts), P, OBSERVER, P, ctypes.POINTER(I)],
     "pffrg_chi": [P, D, P, P],
     "pffrg_chi_k": [P, P, I, P, P],
+    "pffrg_set_profiling": [P, I],
+    "pffrg_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(I)],
 }
+
+K_SIGMA, K_TABLES, K_VERTEX = 0, 1, 2
 
 _lib = None
 

@@ -6,6 +6,7 @@
 // kernels_obs.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -76,6 +77,11 @@ struct pffrg_ctx {
 
     std::vector<void*> allocs;
 
+    // kernel timing: event pairs recorded around launches while profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> ev[PFFRG_K_COUNT];
+    int ev_used[PFFRG_K_COUNT] = {0, 0, 0};
+
     FlowArgs args() const {
         FlowArgs A;
         A.w = w; A.nf = nf; A.ns = ns; A.nq = nq;
@@ -108,6 +114,8 @@ pffrg_status upload(pffrg_ctx* c, T** p, const T* src, size_t n) {
 void release(pffrg_ctx* c) {
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
+    for (auto& v : c->ev)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
     if (c->host_red) (void)hipHostFree(c->host_red);
     c->host_red = nullptr;
 }
@@ -128,11 +136,30 @@ int grid_for(long n, int threads) {
     return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
+// Record an event before/after a launch of kernel `id` while profiling.
+constexpr int kMaxTimed = 65536;
+
+void prof_mark(pffrg_ctx* c, int id, bool after) {
+    if (!c->profiling) return;
+    auto& v = c->ev[id];
+    const int slot = 2 * c->ev_used[id] + (after ? 1 : 0);
+    if (c->ev_used[id] >= kMaxTimed) return;
+    while ((int)v.size() <= slot) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { c->profiling = false; return; }
+        v.push_back(e);
+    }
+    (void)hipEventRecord(v[slot], c->stream);
+    if (after) ++c->ev_used[id];
+}
+
 // ------------------------------------------------------------ one RHS ---
 
 pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
     FlowArgs A = c->args();
+    prof_mark(c, PFFRG_K_SIGMA, false);
     hipLaunchKernelGGL(k_sigma_rhs, dim3((c->nf + 63) / 64), dim3(64), 0, c->stream, A, lam, x, dsig);
+    prof_mark(c, PFFRG_K_SIGMA, true);
     return launch_check("k_sigma_rhs");
 }
 
@@ -140,11 +167,15 @@ pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
     FlowArgs A = c->args();
     TRY(sigma_rhs(c, lam, x, dx));          // the sigma part of dx is dsig
+    prof_mark(c, PFFRG_K_TABLES, false);
     hipLaunchKernelGGL(k_node_tables, dim3((3 * c->nf + 63) / 64), dim3(64), 0, c->stream, A, lam, x,
                        (const double*)dx);
+    prof_mark(c, PFFRG_K_TABLES, true);
     TRY(launch_check("k_node_tables"));
     const VertexLds L{c->nq, c->ns};
+    prof_mark(c, PFFRG_K_VERTEX, false);
     hipLaunchKernelGGL(k_vertex_rhs, dim3(c->nsu * c->nf), dim3(kThreads), L.total(), c->stream, A, x, dx);
+    prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_vertex_rhs");
 }
 
@@ -509,13 +540,31 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
     double l = std::log(o->lam_start);
     double h = o->h0;
     const int maxs = o->max_steps > 0 ? o->max_steps : 1000000;
+    // The sharp cutoff makes the right-hand side jump where Lambda crosses
+    // w_n/2 (a propagator's step function at a delta point switches for a
+    // transfer frequency w_n = 2 Lambda).  Steps end just above each such
+    // breakpoint and the next one restarts just below it.
+    std::vector<double> brk;
+    {
+        std::vector<double> wh(c->nf);
+        HIP_TRY(hipMemcpy(wh.data(), c->w, sizeof(double) * c->nf, hipMemcpyDeviceToHost));
+        for (double wv : wh) {
+            const double lb = std::log(0.5 * wv);
+            if (lb < l && lb > lend) brk.push_back(lb);
+        }
+        std::sort(brk.begin(), brk.end(), [](double a, double b) { return a > b; });
+    }
+    const double gap = 1e-12;   // in ln Lambda, on each side of a breakpoint
+    size_t ib = 0;
     TRY(rhs(c, std::exp(l), x, c->k[0]));
     int attempts = 0;
     while (l > lend) {
         if (++attempts > 50 * maxs) return fail(PFFRG_EDIVERGED, "too many rejected steps");
+        while (ib < brk.size() && brk[ib] + gap >= l) ++ib;
         double dl = -h;
-        bool last = false;
-        if (l + dl <= lend) { dl = lend - l; last = true; }
+        bool last = false, at_brk = false;
+        if (ib < brk.size() && l + dl <= brk[ib] + gap) { dl = (brk[ib] + gap) - l; at_brk = true; }
+        if (l + dl <= lend) { dl = lend - l; last = true; at_brk = false; }
         double err = 0.0;
         bool fin = true;
         double lam[7];
@@ -525,13 +574,20 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
             HIP_TRY(hipMemcpyAsync(x, c->ybuf, sizeof(double) * c->size, hipMemcpyDeviceToDevice, c->stream));
             std::swap(c->k[0], c->k[6]);
             l = last ? lend : l + dl;
+            if (at_brk) {
+                // jump over the breakpoint; the derivative must be re-evaluated
+                l = brk[ib] - gap;
+                ++ib;
+                TRY(rhs(c, std::exp(l), x, c->k[0]));
+            }
             ++steps;
             if (n_steps) *n_steps = steps;
             int stop = 0;
             TRY(observe(c, o, std::exp(l), x, cb, user, &stop));
             if (stop || steps >= maxs) break;
             const double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 5.0;
-            h = std::fabs(dl) * std::fmin(5.0, std::fmax(0.2, fac));
+            const double hprop = std::fabs(dl) * std::fmin(5.0, std::fmax(0.2, fac));
+            h = at_brk ? std::fmax(h, hprop) : hprop;   // a step cut short keeps its size
         } else {
             const double fac = (fin && err > 0.0) ? 0.9 * std::pow(err, -0.2) : 0.2;
             h = std::fabs(dl) * std::fmin(1.0, std::fmax(0.2, fac));
@@ -539,6 +595,29 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
         if (h < o->hmin && l > lend)
             return fail(PFFRG_EDIVERGED, "adaptive step fell below hmin at lambda = " + std::to_string(std::exp(l)));
     }
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_set_profiling(pffrg_ctx* c, int on) {
+    TRY(check_ctx(c));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->profiling = on != 0;
+    for (int i = 0; i < PFFRG_K_COUNT; ++i) c->ev_used[i] = 0;
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_profile_read(pffrg_ctx* c, int kernel, double* total_ms, int* count) {
+    TRY(check_ctx(c));
+    if (kernel < 0 || kernel >= PFFRG_K_COUNT || !total_ms || !count) return fail(PFFRG_EINVAL, "bad kernel id");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (int i = 0; i < c->ev_used[kernel]; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev[kernel][2 * i], c->ev[kernel][2 * i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *count = c->ev_used[kernel];
     return PFFRG_OK;
 }
 

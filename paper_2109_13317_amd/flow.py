@@ -137,6 +137,17 @@ class Context:
         del sched
         return int(nsteps.value)
 
+    # --------------------------------------------------------- profiling --
+    def set_profiling(self, on: bool):
+        _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
+
+    def profile_read(self, kernel: str):
+        """(total_ms, launches) of 'sigma', 'tables' or 'vertex' since profiling began."""
+        kid = {"sigma": _lib.K_SIGMA, "tables": _lib.K_TABLES, "vertex": _lib.K_VERTEX}[kernel]
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        _lib.check(self.lib.pffrg_profile_read(self.handle, kid, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
     # ------------------------------------------------------- observables --
     def chi(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """[2, ns]: chi^{zz} and chi^{00} per reduced pair."""

@@ -145,3 +145,32 @@ def test_full_size_rhs_sampled(which):
         tri.append((a, t, c))
     ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
     assert compare_triples(orc, tables, tri, ref, d) <= TOL
+
+
+def test_adaptive_dopri_flow_matches_oracle():
+    """Dormand-Prince 5(4) in ln Lambda with breakpoints at w_n/2: the accepted
+    cutoffs and the final state agree with the oracle's controller."""
+    torch, tables, ctx, orc = _setup("square_L2_N8")
+    x = ctx.init_state()
+    got = []
+    n = ctx.flow(x, scheme="dopri54", lam_start=50.0, lam_stop=0.5, rtol=1e-5, atol=1e-8, h0=0.05,
+                 hmin=1e-10, observer=lambda lam, chi, ck: got.append(lam) and 0)
+    xo, lams = orc.dopri_flow(50.0, 0.5, 1e-5, 1e-8, 0.05, 1e-10)
+    assert n == len(lams) == len(got)
+    assert np.abs(np.array(got) - np.array(lams)).max() <= 1e-12 * 50
+    assert compare_vertex(orc, tables, xo, x.cpu().numpy()) <= TOL
+
+
+def test_flow_reports_divergence_and_keeps_last_finite_state():
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    from paper_2109_13317_amd._lib import PffrgError, EDIVERGED
+    mesh = W.log_mesh(0.01, 10.0, 5)
+    ctx = Context(build_tables(W.model("square", j1=1e200), 1), mesh)
+    x = ctx.init_state()
+    x0 = x.clone()
+    with pytest.raises(PffrgError) as ei:
+        ctx.flow(x, schedule=[5.0, 4.0, 3.0], scheme="rk4")
+    assert ei.value.status == EDIVERGED
+    assert torch.equal(x, x0)
