@@ -38,6 +38,23 @@ import workloads as W  # noqa: E402
 PEAK_FP64_VECTOR_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per k_vertex_rhs launch from the two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, copy-kernel calibrated), keyed by
+# the hash of the kernel sources they were taken on; a changed kernel reports
+# traffic null until the counters are taken again.
+MEASURED_TRAFFIC = {
+    "a4f277fedf4283ff": 74.7e6,
+}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels_flow.h", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_2109_13317_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(f"[bench {time.strftime('%H:%M:%S')}]", *a, file=sys.stderr, flush=True)
@@ -217,7 +234,8 @@ def main():
     vavg_ms = vms / max(vcount, 1)
     achieved = flops / vcount / (vavg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+                "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()), "traffic_unit": "bytes/launch",
                 "kernel": "k_vertex_rhs", "avg_launch_ms": vavg_ms, "launches": vcount,
                 "flops_per_launch": flops / vcount}
 
@@ -255,10 +273,10 @@ def main():
 
         log("full adaptive flow 100 -> 0.01")
         t0 = time.perf_counter()
-        nsteps = ctx.flow(xf, scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-6,
-                          atol=1e-10, h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=obs)
+        nsteps = ctx.flow(xf, scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4,
+                          atol=1e-6, h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=obs)
         torch.cuda.synchronize()
-        out["full_flow"] = {"scheme": "dopri54 in ln Lambda, rtol 1e-6, atol 1e-10",
+        out["full_flow"] = {"scheme": "dopri54 in ln Lambda, rtol 1e-4, atol 1e-6, steps land on w_n/2",
                             "lambda": [100.0, 0.01], "seconds": time.perf_counter() - t0,
                             "accepted_steps": nsteps, "chi_k_every_step": "64x64"}
 

@@ -208,15 +208,26 @@ class Oracle:
                    observer=None):
         """Adaptive Dormand-Prince 5(4) in l = ln Lambda (dx/dl = Lambda dx/dLambda)
         from lam_start down to lam_stop.  Error norm
-        max_i |e_i| / (atol + rtol max(|x_i|, |y_i|)); accept if <= 1; new step
-        |dl| * min(5, max(0.2, 0.9 err^-1/5)) (rejected: at most |dl|).
-        The right-hand side jumps where Lambda crosses w_n/2 (a step function of
-        a delta-point propagator switches), so steps end 1e-12 (in l) above each
-        such breakpoint and restart 1e-12 below it.  Returns (x, accepted cutoffs)."""
+        max_i |e_i| / (atol + rtol max(|x_i|, |y_i|)); accept if <= 1.  Step
+        sizes are h0 2^(m/4); after a step m changes by round(4 log2(f)) with
+        f = clamp(0.9 err^-1/5, 0.2, 5) (rejected: clamp to [0.2, 1] and at
+        least -1); a step shortened to land on a breakpoint or the end keeps m
+        unless f < 1.  The right-hand side jumps where Lambda crosses w_n/2 (a
+        step function of a delta-point propagator switches), so steps end 1e-12
+        (in l) above each such breakpoint and restart 1e-12 below it.
+        Returns (x, accepted cutoffs)."""
         x = self.initial_state() if x0 is None else np.array(x0, dtype=np.float64)
         lend = math.log(lam_stop)
         l = math.log(lam_start)
-        h = h0
+        m = 0
+
+        def ladder(mm):
+            return h0 * 2.0 ** (mm / 4.0)
+
+        def quarter_steps(f):
+            v = 4.0 * math.log2(f)
+            return int(math.floor(v + 0.5)) if v >= 0 else -int(math.floor(-v + 0.5))
+
         maxs = max_steps if max_steps > 0 else 1000000
         brk = sorted((math.log(0.5 * w) for w in self.mesh if lend < math.log(0.5 * w) < l), reverse=True)
         gap = 1e-12
@@ -231,7 +242,7 @@ class Oracle:
                 raise RuntimeError("too many rejected steps")
             while ib < len(brk) and brk[ib] + gap >= l:
                 ib += 1
-            dl = -h
+            dl = -ladder(m)
             last = at_brk = False
             if ib < len(brk) and l + dl <= brk[ib] + gap:
                 dl = (brk[ib] + gap) - l
@@ -267,13 +278,14 @@ class Oracle:
                     observer(math.exp(l), x)
                 if len(lams) >= maxs:
                     break
-                fac = 0.9 * err ** -0.2 if err > 0.0 else 5.0
-                hprop = abs(dl) * min(5.0, max(0.2, fac))
-                h = max(h, hprop) if at_brk else hprop
+                fac = min(5.0, max(0.2, 0.9 * err ** -0.2)) if err > 0.0 else 5.0
+                dm = quarter_steps(fac)
+                if not (at_brk or last) or dm < 0:
+                    m += dm
             else:
-                fac = 0.9 * err ** -0.2 if (fin and err > 0.0) else 0.2
-                h = abs(dl) * min(1.0, max(0.2, fac))
-            if h < hmin and l > lend:
+                fac = min(1.0, max(0.2, 0.9 * err ** -0.2)) if (fin and err > 0.0) else 0.2
+                m += min(-1, quarter_steps(fac))
+            if ladder(m) < hmin and l > lend:
                 raise RuntimeError(f"adaptive step fell below hmin at lambda = {math.exp(l)}")
         return x, lams
 

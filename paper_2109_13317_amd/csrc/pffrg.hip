@@ -538,7 +538,13 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
         return fail(PFFRG_EINVAL, "bad adaptive options");
     const double lend = std::log(o->lam_stop);
     double l = std::log(o->lam_start);
-    double h = o->h0;
+    // Step sizes live on the ladder h0 * 2^(m/4); the controller only moves
+    // the integer m, so the accepted cutoffs are a deterministic function of
+    // accept/reject decisions and reproduce across implementations whose
+    // error estimates differ by rounding.
+    int m = 0;
+    auto ladder = [&](int mm) { return o->h0 * std::pow(2.0, mm / 4.0); };
+    auto quarter_steps = [](double fac) { return (int)std::lround(4.0 * std::log2(fac)); };
     const int maxs = o->max_steps > 0 ? o->max_steps : 1000000;
     // The sharp cutoff makes the right-hand side jump where Lambda crosses
     // w_n/2 (a propagator's step function at a delta point switches for a
@@ -561,7 +567,7 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
     while (l > lend) {
         if (++attempts > 50 * maxs) return fail(PFFRG_EDIVERGED, "too many rejected steps");
         while (ib < brk.size() && brk[ib] + gap >= l) ++ib;
-        double dl = -h;
+        double dl = -ladder(m);
         bool last = false, at_brk = false;
         if (ib < brk.size() && l + dl <= brk[ib] + gap) { dl = (brk[ib] + gap) - l; at_brk = true; }
         if (l + dl <= lend) { dl = lend - l; last = true; at_brk = false; }
@@ -585,14 +591,14 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
             int stop = 0;
             TRY(observe(c, o, std::exp(l), x, cb, user, &stop));
             if (stop || steps >= maxs) break;
-            const double fac = err > 0.0 ? 0.9 * std::pow(err, -0.2) : 5.0;
-            const double hprop = std::fabs(dl) * std::fmin(5.0, std::fmax(0.2, fac));
-            h = at_brk ? std::fmax(h, hprop) : hprop;   // a step cut short keeps its size
+            const double fac = err > 0.0 ? std::fmin(5.0, std::fmax(0.2, 0.9 * std::pow(err, -0.2))) : 5.0;
+            const int dm = quarter_steps(fac);
+            if (!(at_brk || last) || dm < 0) m += dm;   // a step cut short keeps its size
         } else {
-            const double fac = (fin && err > 0.0) ? 0.9 * std::pow(err, -0.2) : 0.2;
-            h = std::fabs(dl) * std::fmin(1.0, std::fmax(0.2, fac));
+            const double fac = (fin && err > 0.0) ? std::fmin(1.0, std::fmax(0.2, 0.9 * std::pow(err, -0.2))) : 0.2;
+            m += std::min(-1, quarter_steps(fac));
         }
-        if (h < o->hmin && l > lend)
+        if (ladder(m) < o->hmin && l > lend)
             return fail(PFFRG_EDIVERGED, "adaptive step fell below hmin at lambda = " + std::to_string(std::exp(l)));
     }
     return PFFRG_OK;
