@@ -189,7 +189,15 @@ pffrg_status pffrg_chi_k(pffrg_ctx *ctx, const double *d_chi, int n_k, const dou
  * pffrg_profile_read synchronises the stream and returns, for kernel id
  * `kernel`, the summed duration in milliseconds and the launch count since
  * profiling was switched on.  Up to 65536 launches per kernel are kept. */
-enum { PFFRG_K_SIGMA = 0, PFFRG_K_TABLES = 1, PFFRG_K_VERTEX = 2, PFFRG_K_COUNT = 3 };
+enum {
+    PFFRG_K_SIGMA = 0,      /* self-energy flow */
+    PFFRG_K_TABLES = 1,     /* per-channel quadrature tables */
+    PFFRG_K_VERTEX = 2,     /* the whole vertex flow (the three channel launches) */
+    PFFRG_K_VERTEX_S = 3,   /* s channel */
+    PFFRG_K_VERTEX_U = 4,   /* u channel */
+    PFFRG_K_VERTEX_T = 5,   /* t channel with the lattice sum */
+    PFFRG_K_COUNT = 6
+};
 pffrg_status pffrg_set_profiling(pffrg_ctx *ctx, int on);
 pffrg_status pffrg_profile_read(pffrg_ctx *ctx, int kernel, double *total_ms, int *count);
 

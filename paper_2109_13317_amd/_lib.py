@@ -56,7 +56,7 @@ SIGNATURES = {
     "pffrg_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(I)],
 }
 
-K_SIGMA, K_TABLES, K_VERTEX = 0, 1, 2
+K_SIGMA, K_TABLES, K_VERTEX, K_VERTEX_S, K_VERTEX_U, K_VERTEX_T = 0, 1, 2, 3, 4, 5
 
 _lib = None
 

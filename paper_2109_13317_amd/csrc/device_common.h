@@ -46,52 +46,80 @@ __device__ __forceinline__ double odd_interp(const double* __restrict__ w, int n
     return sg * (f0 * v[i0] + f1 * v[i1]);
 }
 
-// An interpolation plan: where the (at most four, see below) contributing
-// corners of one vertex evaluation sit in a strain, their weights for the
-// spin and the density strain, and whether the two sites are exchanged.
-// Every evaluation in the flow has one frequency argument exactly on the
-// mesh (or 0, which extrapolates to the first mesh point), so trilinear
-// interpolation touches at most four corners.
+// An interpolation plan: where the four contributing corners of one vertex
+// evaluation sit in a strain, their weights for the spin and the density
+// strain, and whether the two sites are exchanged.  Every evaluation in the
+// flow has one frequency argument exactly on the mesh (or 0, which
+// extrapolates to the first mesh point), whose slot and mesh index the
+// caller passes, so trilinear interpolation touches at most four corners.
+// Unused corners repeat a used one with weight 0.
 struct Plan {
-    int off[4];       // ((a(a+1)/2 + c) * nf + t) * ns : add the pair index
+    int off[4];       // element offset ((a(a+1)/2 + c) * nf + t) * ns: add the pair index
     double ws[4];     // spin-strain weights
     double wd[4];     // density-strain weights (carry the s<->u signs)
-    int n;            // corners in use
     int swp;          // 1: read the exchanged pair swap[p]
 };
 
+// Bracket of x >= 0 with a precomputed reciprocal spacing table
+// ih[i] = 1 / (w[i+1] - w[i]); weights f1 = (x - w[lo]) ih[lo], f0 = 1 - f1.
+__device__ __forceinline__ void bracket_fast(const double* __restrict__ w, const double* __restrict__ ih,
+                                             int nf, double x, int& i0, int& i1, double& f0, double& f1) {
+    if (x <= w[0]) { i0 = i1 = 0; f0 = 1.0; f1 = 0.0; return; }
+    if (x >= w[nf - 1]) { i0 = i1 = nf - 1; f0 = 1.0; f1 = 0.0; return; }
+    int lo = 0, hi = nf - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w[mid] <= x) lo = mid; else hi = mid;
+    }
+    i0 = lo; i1 = hi;
+    f1 = (x - w[lo]) * ih[lo];
+    f0 = 1.0 - f1;
+}
+
+// kslot in {0,1,2}: which of (s, t, u) holds the on-mesh value, kidx its mesh
+// index (0 for a zero argument).  ih as in bracket_fast (NULL: divide).
 __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, int ns,
-                                          double s, double t, double u, Plan& P) {
+                                          double s, double t, double u, int kslot, int kidx, Plan& P,
+                                          const double* __restrict__ ih = nullptr) {
     int swp = 0;
     double sd = 1.0;
     if (s < 0.0) { s = -s; swp ^= 1; }
     if (t < 0.0) t = -t;
     if (u < 0.0) { u = -u; swp ^= 1; }
-    if (s < u) { double q = s; s = u; u = q; sd = -1.0; }
-    int sa[2], ta[2], ua[2];
-    double fs[2], ft[2], fu[2];
-    bracket(w, nf, s, sa[0], sa[1], fs[0], fs[1]);
-    bracket(w, nf, t, ta[0], ta[1], ft[0], ft[1]);
-    bracket(w, nf, u, ua[0], ua[1], fu[0], fu[1]);
-    const int nsn = fs[1] != 0.0 ? 2 : 1;
-    const int ntn = ft[1] != 0.0 ? 2 : 1;
-    const int nun = fu[1] != 0.0 ? 2 : 1;
-    int n = 0;
-    for (int iu = 0; iu < nun; ++iu)
-        for (int it = 0; it < ntn; ++it)
-            for (int is = 0; is < nsn; ++is) {
-                double wg = fu[iu] * ft[it] * fs[is];
-                int a = sa[is], c = ua[iu];
-                double cs = 1.0;
-                if (a < c) { int q = a; a = c; c = q; cs = -1.0; }
-                if (n < 4) {
-                    P.off[n] = (int)((su_index(a, c) * nf + ta[it]) * ns);
-                    P.ws[n] = wg;
-                    P.wd[n] = sd * cs * wg;
-                }
-                ++n;
-            }
-    P.n = n < 4 ? n : 4;
+    if (s < u) {
+        const double q = s; s = u; u = q;
+        sd = -1.0;
+        kslot = kslot == 0 ? 2 : (kslot == 2 ? 0 : 1);
+    }
+    // the two free slots, in (s, t, u) order, and their brackets
+    const int f0 = kslot == 0 ? 1 : 0;
+    const int f1 = kslot == 2 ? 1 : 2;
+    const double v0 = f0 == 0 ? s : t;
+    const double v1 = f1 == 1 ? t : u;
+    int b0[2], b1[2];
+    double g0[2], g1[2];
+    if (ih) {
+        bracket_fast(w, ih, nf, v0, b0[0], b0[1], g0[0], g0[1]);
+        bracket_fast(w, ih, nf, v1, b1[0], b1[1], g1[0], g1[1]);
+    } else {
+        bracket(w, nf, v0, b0[0], b0[1], g0[0], g0[1]);
+        bracket(w, nf, v1, b1[0], b1[1], g1[0], g1[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ia = kslot == 0 ? kidx : b0[i];
+            const int it = kslot == 1 ? kidx : (kslot == 0 ? b0[i] : b1[j]);
+            const int ic = kslot == 2 ? kidx : b1[j];
+            int a = ia, c = ic;
+            double cs = sd;
+            if (a < c) { const int q = a; a = c; c = q; cs = -cs; }
+            const double wg = g0[i] * g1[j];
+            P.off[2 * i + j] = (int)((su_index(a, c) * nf + it) * ns);
+            P.ws[2 * i + j] = wg;
+            P.wd[2 * i + j] = cs * wg;
+        }
     P.swp = swp;
 }
 
@@ -102,7 +130,8 @@ __device__ __forceinline__ void eval_plan(const Plan& P, const double* __restric
                                           double& vs, double& vd) {
     const int q = P.swp ? swap[p] : p;
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < P.n; ++i) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
         a = fma(P.ws[i], gs[P.off[i] + q], a);
         b = fma(P.wd[i], gd[P.off[i] + q], b);
     }

@@ -1,17 +1,23 @@
-// kernels_flow.h -- HIP kernels of the SU(2) pf-FRG right-hand side.
+// kernels_flow.h -- HIP kernels of the SU(2) pf-FRG right-hand side (gfx950).
 //
-// One right-hand side (arXiv:2109.13317, Sec. 3) is three launches:
+// One right-hand side (arXiv:2109.13317, Sec. 3) is six launches:
 //   k_sigma_rhs     d sig/d Lambda on the mesh (Eq. 23): the single-scale
-//                   propagator pins the internal frequency to +-Lambda;
+//                   propagator pins the internal frequency to +-Lambda; one
+//                   wave per mesh frequency, lanes over pairs;
+//   k_pack          the two vertex strains interleaved as (Gs, Gd) pairs so
+//                   that one interpolation corner is one 16-byte load;
 //   k_node_tables   per channel X in {s,t,u} and transfer frequency index nu,
 //                   the evaluation points w_k of the channel's frequency
 //                   integral and their weights W_k (delta points of S and
-//                   trapezoid nodes of the Katanin term, Eq. 13), so that
-//                   channel integral = sum_k W_k F_X(w_k);
-//   k_vertex_rhs    one workgroup per output triple (s,t,u): the three channel
-//                   sums over their nodes for every pair, the particle-hole
-//                   lattice sum in GEMM form (M = sum_k W_k a_k b_k^T per
-//                   triple, then the tabulated (ka,kb) terms of each pair).
+//                   trapezoid nodes of the Katanin term, Eq. 13), so that the
+//                   channel integral is sum_k W_k F_X(w_k); one wave per list;
+//   k_vertex_su<0>  one wave per output triple (s,t,u): the s-channel sum
+//                   for every pair (writes dGamma);
+//   k_vertex_su<2>  the same for the u channel (adds);
+//   k_vertex_t<NSP> the t channel with the particle-hole lattice sum in GEMM
+//                   form (M = sum_k W_k a_k b_k^T, register-blocked 2x4 per
+//                   lane) contracted with the tabulated (ka, kb, count) terms
+//                   (adds).
 #pragma once
 
 #include "device_common.h"
@@ -27,6 +33,8 @@ struct FlowArgs {
     const int* rpa_ka;
     const int* rpa_kb;
     const int* rpa_cnt;
+    const int* rpa_term;    // packed terms (ka*ns + kb) | (count << 16), rpa_off order
+    int n_terms;
     const int* su_a;        // [nf(nf+1)/2] s-index of each (s,u) wedge entry
     const int* su_c;        //              u-index
     int* tab_n;             // [3*nf] node counts
@@ -34,36 +42,91 @@ struct FlowArgs {
     double* tab_g;          // [3*nf*nq] node weights
 };
 
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Order LDS traffic between lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Buffer resource of the packed (Gs, Gd) vertex: loads take a 32-bit byte
+// offset; reads past the end return 0 (they never happen: every plan offset
+// lies in the state).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vertex_rsrc(const double2* gv, long n) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * 16), 0x00020000);
+}
+
+__device__ __forceinline__ double2 load_corner(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+
+// Interpolation of both strains of one pair from the packed vertex; plan
+// offsets are byte offsets (element offset * 16), pp = 16 * (p, swap[p]).
+__device__ __forceinline__ void eval_packed2(const Plan& P, __amdgpu_buffer_rsrc_t r, int2 pp,
+                                             double& vs, double& vd) {
+    const unsigned q = P.swp ? pp.y : pp.x;
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 g = load_corner(r, (unsigned)P.off[i] + q);
+        a = fma(P.ws[i], g.x, a);
+        b = fma(P.wd[i], g.y, b);
+    }
+    vs = a;
+    vd = b;
+}
+
+// A plan whose offsets are turned into byte offsets of the packed vertex.
+__device__ __forceinline__ void to_bytes(Plan& P) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P.off[i] *= 16;
+}
+
 // ------------------------------------------------------------ self-energy -
 
 // d sig/d Lambda (w_n) = (1/2pi) sum_{x=+-Lambda} F(w_n, x) / (x - sig(x)),
 // F = 2 sum_r mult_r Gd_r(w+x, 0, w-x) - 3 Gs_0(w+x, x-w, 0) - Gd_0(w+x, x-w, 0).
-__global__ void k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x,
-                            double* __restrict__ dsig) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= A.nf) return;
-    const double* sig = x;
-    const double* gs = x + A.nf;
-    const double* gd = gs + (long)A.nf * (A.nf + 1) / 2 * A.nf * A.ns;
+__global__ void __launch_bounds__(kWave)
+k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, const double2* __restrict__ gv, long nv,
+            double* __restrict__ dsig) {
+    const int n = blockIdx.x, lane = threadIdx.x;
     const double wn = A.w[n];
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc(gv, nv);
     double acc = 0.0;
     for (int sx = 0; sx < 2; ++sx) {
         const double xx = sx == 0 ? lam : -lam;
-        Plan P, Q;
-        make_plan(A.w, A.nf, A.ns, wn + xx, 0.0, wn - xx, P);
+        Plan P;
+        make_plan(A.w, A.nf, A.ns, wn + xx, 0.0, wn - xx, 1, 0, P);
+        to_bytes(P);
         double f = 0.0;
-        for (int r = 0; r < A.ns; ++r) {
+        for (int r = lane; r < A.ns; r += kWave) {
             double vs, vd;
-            eval_plan(P, gs, gd, A.swap, r, vs, vd);
+            eval_packed2(P, rv, make_int2(16 * r, 16 * A.swap[r]), vs, vd);
             f = fma(2.0 * (double)A.mult[r], vd, f);
         }
-        make_plan(A.w, A.nf, A.ns, wn + xx, xx - wn, 0.0, Q);
+        f = wave_sum(f);
+        Plan Q;
+        make_plan(A.w, A.nf, A.ns, wn + xx, xx - wn, 0.0, 2, 0, Q);
+        to_bytes(Q);
         double os, od;
-        eval_plan(Q, gs, gd, A.swap, 0, os, od);
+        eval_packed2(Q, rv, make_int2(0, 0), os, od);
         f -= 3.0 * os + od;
-        acc += f / (xx - odd_interp(A.w, A.nf, sig, xx));
+        acc += f / (xx - odd_interp(A.w, A.nf, x, xx));
     }
-    dsig[n] = acc * kInvTwoPi;
+    if (lane == 0) dsig[n] = acc * kInvTwoPi;
+}
+
+__global__ void k_pack(long n, const double* __restrict__ gs, const double* __restrict__ gd,
+                       double2* __restrict__ gv) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        gv[i] = make_double2(gs[i], gd[i]);
 }
 
 // ------------------------------------------------------------ node tables -
@@ -80,11 +143,20 @@ __device__ __forceinline__ double theta_half(double y, double lam) {
     return a > lam ? 1.0 : (a == lam ? 0.5 : 0.0);
 }
 
-__global__ void k_node_tables(FlowArgs A, double lam, const double* __restrict__ x,
-                              const double* __restrict__ dsig) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= 3 * A.nf) return;
-    const int ch = id / A.nf, iv = id % A.nf;
+// The full mesh -w[nf-1] .. -w[0], w[0] .. w[nf-1], ascending.
+__device__ __forceinline__ double full_mesh(const double* __restrict__ w, int nf, int i) {
+    return i < nf ? -w[nf - 1 - i] : w[i - nf];
+}
+
+// One wave per (channel, nu).  Node list: the delta points first, then for
+// every piece of D = [-wmax, wmax] \ (-lam, lam) \ (c - lam, c + lam) (c = zero
+// of the partner) its ends and the mesh points strictly inside, with
+// trapezoid weight times the Katanin bubble.
+__global__ void __launch_bounds__(kWave)
+k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double* __restrict__ dsig) {
+    const int id = blockIdx.x, lane = threadIdx.x;
+    const int nf = A.nf;
+    const int ch = id / nf, iv = id % nf;
     const double nu = A.w[iv];
     const double* sig = x;
     double* tw = A.tab_w + (long)id * A.nq;
@@ -95,26 +167,27 @@ __global__ void k_node_tables(FlowArgs A, double lam, const double* __restrict__
     // Skat(w) puts w at x.  Weight -G(.) / (x - sig(x)) / (2 pi) in real form.
     for (int sx = 0; sx < 2; ++sx) {
         const double xx = sx == 0 ? lam : -lam;
-        const double st = 1.0 / (xx - odd_interp(A.w, A.nf, sig, xx));
         const double winv = ch == 0 ? nu - xx : (ch == 1 ? xx + nu : xx - nu);
         const double pxx = partner(ch, nu, xx);
         double g1 = theta_half(winv, lam);
         double g2 = theta_half(pxx, lam);
-        if (g1 != 0.0) {
-            g1 /= winv - odd_interp(A.w, A.nf, sig, winv);
-            tw[n] = winv; tg[n] = -st * g1 * kInvTwoPi; ++n;
-        }
-        if (g2 != 0.0) {
-            g2 /= pxx - odd_interp(A.w, A.nf, sig, pxx);
-            tw[n] = xx; tg[n] = -st * g2 * kInvTwoPi; ++n;
+        if (g1 != 0.0 || g2 != 0.0) {
+            const double st = 1.0 / (xx - odd_interp(A.w, nf, sig, xx));
+            if (g1 != 0.0) {
+                g1 /= winv - odd_interp(A.w, nf, sig, winv);
+                if (lane == 0) { tw[n] = winv; tg[n] = -st * g1 * kInvTwoPi; }
+                ++n;
+            }
+            if (g2 != 0.0) {
+                g2 /= pxx - odd_interp(A.w, nf, sig, pxx);
+                if (lane == 0) { tw[n] = xx; tg[n] = -st * g2 * kInvTwoPi; }
+                ++n;
+            }
         }
     }
 
-    // Katanin part: trapezoid over the pieces of
-    // D = [-wmax, wmax] \ (-lam, lam) \ (c - lam, c + lam), c = zero of the
-    // partner; nodes are the piece ends and the mesh points +-w_n inside.
     const double c = ch == 0 ? nu : (ch == 1 ? nu : -nu);
-    const double wmax = A.w[A.nf - 1];
+    const double wmax = A.w[nf - 1];
     const double e0 = c - lam, e1 = c + lam;
     const double a0[2] = {-wmax, lam}, b0[2] = {-lam, wmax};
     for (int ip = 0; ip < 2; ++ip) {
@@ -125,192 +198,430 @@ __global__ void k_node_tables(FlowArgs A, double lam, const double* __restrict__
         for (int q = 0; q < 2; ++q) {
             const double lo = lo2[q], hi = hi2[q];
             if (!(lo < hi)) continue;
-            // nodes: lo, mesh points +-w_n strictly inside (ascending), hi
-            const int first = n;
-            tw[n++] = lo;
-            for (int i = 0; i < 2 * A.nf; ++i) {
-                const double v = i < A.nf ? -A.w[A.nf - 1 - i] : A.w[i - A.nf];
-                if (v > lo && v < hi) tw[n++] = v;
+            // mesh points inside (lo, hi) are the contiguous run i0 .. i0+cnt-1
+            int below = 0, cnt = 0;
+            for (int i = lane; i < 2 * nf; i += kWave) {
+                const double v = full_mesh(A.w, nf, i);
+                below += v <= lo;
+                cnt += (v > lo && v < hi);
             }
-            tw[n++] = hi;
-            for (int i = first; i < n; ++i) {
-                const double cur = tw[i];
-                const double wl = i > first ? 0.5 * (cur - tw[i - 1]) : 0.0;
-                const double wr = i + 1 < n ? 0.5 * (tw[i + 1] - cur) : 0.0;
+            for (int o = kWave / 2; o > 0; o >>= 1) {
+                below += __shfl_xor(below, o, kWave);
+                cnt += __shfl_xor(cnt, o, kWave);
+            }
+            const int m = cnt + 2;
+            for (int j = lane; j < m; j += kWave) {
+                auto node = [&](int jj) {
+                    return jj == 0 ? lo : (jj == m - 1 ? hi : full_mesh(A.w, nf, below + jj - 1));
+                };
+                const double cur = node(j);
+                const double wl = j > 0 ? 0.5 * (cur - node(j - 1)) : 0.0;
+                const double wr = j + 1 < m ? 0.5 * (node(j + 1) - cur) : 0.0;
                 const double pp = partner(ch, nu, cur);
-                const double gw = 1.0 / (cur - odd_interp(A.w, A.nf, sig, cur));
-                const double gp = 1.0 / (pp - odd_interp(A.w, A.nf, sig, pp));
-                const double kat = gw * gp * gp * odd_interp(A.w, A.nf, dsig, pp)
-                                 + gp * gw * gw * odd_interp(A.w, A.nf, dsig, cur);
-                tg[i] = (wl + wr) * kat * kInvTwoPi;
+                const double gw = 1.0 / (cur - odd_interp(A.w, nf, sig, cur));
+                const double gp = 1.0 / (pp - odd_interp(A.w, nf, sig, pp));
+                const double kat = gw * gp * gp * odd_interp(A.w, nf, dsig, pp)
+                                 + gp * gw * gw * odd_interp(A.w, nf, dsig, cur);
+                tw[n + j] = cur;
+                tg[n + j] = (wl + wr) * kat * kInvTwoPi;
             }
+            n += m;
         }
     }
-    A.tab_n[id] = n;
+    if (lane == 0) A.tab_n[id] = n;
 }
 
 // ------------------------------------------------------------- vertex RHS -
+//
+// The vertex right-hand side is three launches, one per channel, each with
+// its own order of the output triples so that the workgroups resident on one
+// XCD (and its L2) share the frequency slice their channel interpolates in:
+// s channel by s, u channel by u, t channel by t.  The s launch writes dGamma,
+// the u and t launches add to it.
 
-constexpr int kThreads = 256;
-constexpr int kChunk = 8;      // nodes per chunk of the particle-hole lattice sum
+constexpr int kWavesPerBlock = 4;
+constexpr int kPlanChunk = 32;   // nodes whose plans are built at once (two vectors each)
+constexpr int kSub = 8;          // nodes per lattice-sum sub-chunk
+constexpr int kMaxPairs = 32;    // 2 register blocks of 2x4 per lane cover 32 x 32
+constexpr int kMaxFreq = 128;    // mesh copy in LDS
 
-// LDS layout of k_vertex_rhs, in bytes; see vertex_rhs_lds_bytes().
-struct VertexLds {
-    int nq, ns;
-    __host__ __device__ size_t plans() const { return (size_t)2 * nq * sizeof(Plan); }
-    __host__ __device__ size_t onsite() const { return (size_t)4 * nq * sizeof(double); }
-    __host__ __device__ size_t vchunk() const { return (size_t)4 * kChunk * ns * sizeof(double); }
-    __host__ __device__ size_t mat() const { return (size_t)2 * ns * ns * sizeof(double); }
-    __host__ __device__ size_t red() const { return (size_t)2 * kThreads * sizeof(double); }
-    __host__ __device__ size_t total() const { return plans() + onsite() + vchunk() + mat() + red(); }
+// Workgroup-shared tables in LDS: mesh, reciprocal spacings, pair exchange,
+// and (t channel) the packed tabulated lattice-sum terms with their offsets.
+struct SharedLds {
+    int nf, ns, n_terms;
+    __host__ __device__ size_t mesh() const { return 0; }
+    __host__ __device__ size_t ih() const { return (size_t)nf * sizeof(double); }
+    __host__ __device__ size_t swap() const { return (size_t)2 * nf * sizeof(double); }
+    __host__ __device__ size_t off() const { return swap() + (size_t)ns * sizeof(int); }
+    __host__ __device__ size_t terms() const { return off() + (size_t)(ns + 1) * sizeof(int); }
+    __host__ __device__ size_t bytes(bool with_terms) const {
+        const size_t b = with_terms ? terms() + (size_t)n_terms * sizeof(int) : terms();
+        return (b + 31) & ~(size_t)31;
+    }
 };
 
-__global__ void __launch_bounds__(kThreads)
-k_vertex_rhs(FlowArgs A, const double* __restrict__ x, double* __restrict__ dx) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const VertexLds L{A.nq, A.ns};
-    Plan* plan = reinterpret_cast<Plan*>(lds_raw);
-    double* onsite = reinterpret_cast<double*>(lds_raw + L.plans());
-    double* vch = reinterpret_cast<double*>(lds_raw + L.plans() + L.onsite());
-    double* mat = reinterpret_cast<double*>(lds_raw + L.plans() + L.onsite() + L.vchunk());
-    double* red = reinterpret_cast<double*>(lds_raw + L.plans() + L.onsite() + L.vchunk() + L.mat());
+struct Shared {
+    const double* w;
+    const double* ih;
+    const int* swap;
+    const int* off;
+    const int* terms;
+};
 
-    const int nf = A.nf, ns = A.ns, nq = A.nq;
-    const long vsz = (long)nf * (nf + 1) / 2 * nf * ns;
-    const double* gs = x + nf;
-    const double* gd = gs + vsz;
-    const int tid = threadIdx.x;
-    const int tau = blockIdx.x;
-    const int su = tau / nf, it = tau % nf;
-    const int ia = A.su_a[su], ic = A.su_c[su];
-    const double s = A.w[ia], t = A.w[it], u = A.w[ic];
+// Fill the shared tables (workgroup-wide; before any wave leaves).
+__device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
+    const SharedLds S{A.nf, A.ns, A.n_terms};
+    double* w = reinterpret_cast<double*>(lds + S.mesh());
+    double* ih = reinterpret_cast<double*>(lds + S.ih());
+    int* sw = reinterpret_cast<int*>(lds + S.swap());
+    int* off = reinterpret_cast<int*>(lds + S.off());
+    int* terms = reinterpret_cast<int*>(lds + S.terms());
+    for (int i = threadIdx.x; i < A.nf; i += blockDim.x) {
+        w[i] = A.w[i];
+        ih[i] = i + 1 < A.nf ? 1.0 / (A.w[i + 1] - A.w[i]) : 0.0;
+    }
+    for (int i = threadIdx.x; i < A.ns; i += blockDim.x) sw[i] = A.swap[i];
+    if (with_terms) {
+        for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
+        for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
+    }
+    __syncthreads();
+    return Shared{w, ih, sw, off, terms};
+}
+
+// Per-wave LDS of the t-channel kernel, in bytes.  The lattice-sum matrix
+// at the end reuses it.  The s/u kernel uses plans() + red().
+struct WaveLds {
+    int ns;
+    int sub = kSub;   // nodes per lattice-sum sub-chunk
+    __host__ __device__ int nsp() const { return (ns + 3) & ~3; }
+    __host__ __device__ size_t plans() const { return (size_t)2 * kPlanChunk * sizeof(Plan); }
+    __host__ __device__ size_t onsite() const { return (size_t)4 * kPlanChunk * sizeof(double); }
+    __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(double); }
+    __host__ __device__ size_t red() const { return (size_t)2 * kWave * sizeof(double); }
+    __host__ __device__ size_t mat() const { return (((size_t)ns * ns * sizeof(double)) + 31) & ~(size_t)31; }
+    __host__ __device__ size_t work() const { return plans() + onsite() + vbuf(); }
+    __host__ __device__ size_t bytes() const {
+        size_t m = mat() + red();
+        size_t b = work() > m ? work() : m;
+        return (b + 31) & ~(size_t)31;
+    }
+    __host__ __device__ size_t su_bytes() const { return plans() + red(); }
+};
+
+// Position in the channel's order of the triple handled by this wave, or -1.
+// Consecutive workgroups go round-robin over the 8 XCDs, so each XCD gets a
+// contiguous range of the order (the grid is 8 * per workgroups).
+__device__ __forceinline__ int xcd_order(int n_triples) {
+    const int per = gridDim.x / 8;
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+    const int o = (xcd * per + slot) * kWavesPerBlock + threadIdx.x / kWave;
+    return o < n_triples ? o : -1;
+}
+
+struct Triple {
+    int ia, it, ic;     // mesh indices of s, t, u
+    long out;           // (su * nf + t): element offset / ns of the output
+    double s, t, u, w1p, w2p, w1, w2;
+};
+
+__device__ __forceinline__ Triple make_triple(const double* w, int nf, int ia, int it, int ic) {
+    Triple T;
+    T.ia = ia; T.it = it; T.ic = ic;
+    T.out = (su_index(ia, ic) * nf + it);
+    T.s = w[ia]; T.t = w[it]; T.u = w[ic];
     // external frequencies from s = w1'+w2', t = w1'-w1, u = w1'-w2 (Eq. 17)
-    const double w1p = 0.5 * (s + t + u), w2p = 0.5 * (s - t - u);
-    const double w1 = 0.5 * (s - t + u), w2 = 0.5 * (s + t - u);
+    T.w1p = 0.5 * (T.s + T.t + T.u);
+    T.w2p = 0.5 * (T.s - T.t - T.u);
+    T.w1 = 0.5 * (T.s - T.t + T.u);
+    T.w2 = 0.5 * (T.s + T.t - T.u);
+    return T;
+}
 
-    // (g, p) decomposition for per-pair accumulation: G groups of ns lanes
-    const int G = kThreads / ns;
-    const int g = tid / ns, p = tid % ns;
+// Sum the per-group partials (lanes g*ns + p) and write (or add) pair p.
+__device__ __forceinline__ void finish_pairs(double* red, int lane, int ns, int G, bool act, double acc_s,
+                                             double acc_d, double extra_s, double extra_d, double* ds,
+                                             double* dd, bool add) {
+    red[lane] = act ? acc_s : 0.0;
+    red[kWave + lane] = act ? acc_d : 0.0;
+    wave_lds_sync();
+    if (lane < ns) {
+        double ts = extra_s, td = extra_d;
+        for (int gg = 0; gg < G; ++gg) {
+            ts += red[gg * ns + lane];
+            td += red[kWave + gg * ns + lane];
+        }
+        if (add) { ds[lane] += ts; dd[lane] += td; }
+        else { ds[lane] = ts; dd[lane] = td; }
+    }
+}
+
+// s channel (CH = 0): A = Gamma(s, w1'-w, w-w2'), B = Gamma(s, w-w1, w-w2),
+//   dGs += W (-2 As Bs + As Bd + Ad Bs), dGd += W (3 As Bs + Ad Bd).
+// u channel (CH = 2): A = Gamma(w1+w, w-w2', u), B = Gamma(w1'+w, w2-w, u),
+//   dGs += W (2 As Bs + As Bd + Ad Bs), dGd += W (3 As Bs + Ad Bd).
+// Order: s channel by (s, u, t) wedge order; u channel by (u, s, t) using
+// the u-major wedge tables uo_a / uo_c.
+template <int CH>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock)
+k_vertex_su(FlowArgs A, const double2* __restrict__ gv, const int* __restrict__ uo_a,
+            const int* __restrict__ uo_c, int n_triples, double* __restrict__ dx) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns, nq = A.nq;
+    const Shared sh = load_shared(A, lds_raw, false);
+    A.w = sh.w;
+    const WaveLds L{ns};
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * L.su_bytes();
+    Plan* plan = reinterpret_cast<Plan*>(base);
+    double* red = reinterpret_cast<double*>(base + L.plans());
+    const int o = xcd_order(n_triples);
+    if (o < 0) return;
+    const int q = o / nf, it = o % nf;
+    const int ia = CH == 0 ? A.su_a[q] : uo_a[q];
+    const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
+    const Triple T = make_triple(A.w, nf, ia, it, ic);
+
+    const int G = kWave / ns;
+    const int g = lane / ns, p = lane % ns;
     const bool act = g < G;
+    const int2 pp = make_int2(16 * p, 16 * sh.swap[p]);
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc(gv, (long)n_triples * ns);
     double acc_s = 0.0, acc_d = 0.0;
-
-    // ---- s channel: A = Gamma(s, w1'-w, w-w2'), B = Gamma(s, w-w1, w-w2)
-    // ---- u channel: A = Gamma(w1+w, w-w2', u),  B = Gamma(w1'+w, w2-w, u)
-    for (int pass = 0; pass < 2; ++pass) {
-        const int ch = pass == 0 ? 0 : 2;
-        const int iv = pass == 0 ? ia : ic;
-        const int cnt = A.tab_n[ch * nf + iv];
-        const double* tw = A.tab_w + (long)(ch * nf + iv) * nq;
-        const double* tg = A.tab_g + (long)(ch * nf + iv) * nq;
-        for (int k = tid; k < cnt; k += kThreads) {
-            const double om = tw[k];
-            if (pass == 0) {
-                make_plan(A.w, nf, ns, s, w1p - om, om - w2p, plan[k]);
-                make_plan(A.w, nf, ns, s, om - w1, om - w2, plan[nq + k]);
-            } else {
-                make_plan(A.w, nf, ns, w1 + om, om - w2p, u, plan[k]);
-                make_plan(A.w, nf, ns, w1p + om, w2 - om, u, plan[nq + k]);
+    const int iv = CH == 0 ? ia : ic;
+    const int cnt = A.tab_n[CH * nf + iv];
+    const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
+    const double* tg = A.tab_g + (long)(CH * nf + iv) * nq;
+    const double sgn = CH == 0 ? -2.0 : 2.0;
+    for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
+        const int kc = min(kPlanChunk, cnt - k0);
+        {
+            const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
+            if (j < kc) {
+                const double om = tw[k0 + j];
+                Plan P;
+                if (CH == 0) {
+                    if (vec == 0) make_plan(A.w, nf, ns, T.s, T.w1p - om, om - T.w2p, 0, ia, P, sh.ih);
+                    else make_plan(A.w, nf, ns, T.s, om - T.w1, om - T.w2, 0, ia, P, sh.ih);
+                } else {
+                    if (vec == 0) make_plan(A.w, nf, ns, T.w1 + om, om - T.w2p, T.u, 2, ic, P, sh.ih);
+                    else make_plan(A.w, nf, ns, T.w1p + om, T.w2 - om, T.u, 2, ic, P, sh.ih);
+                }
+                to_bytes(P);
+                plan[vec * kPlanChunk + j] = P;
             }
         }
-        __syncthreads();
+        wave_lds_sync();
         if (act) {
-            const double sgn = pass == 0 ? -2.0 : 2.0;
-            for (int k = g; k < cnt; k += G) {
+            int k = g;
+            for (; k + G < kc; k += 2 * G) {     // two nodes in flight
+                double as, ad, bs, bd, as2, ad2, bs2, bd2;
+                eval_packed2(plan[k], rv, pp, as, ad);
+                eval_packed2(plan[kPlanChunk + k], rv, pp, bs, bd);
+                eval_packed2(plan[k + G], rv, pp, as2, ad2);
+                eval_packed2(plan[kPlanChunk + k + G], rv, pp, bs2, bd2);
+                const double W = tg[k0 + k], W2 = tg[k0 + k + G];
+                acc_s = fma(W, sgn * as * bs + as * bd + ad * bs, acc_s);
+                acc_d = fma(W, 3.0 * as * bs + ad * bd, acc_d);
+                acc_s = fma(W2, sgn * as2 * bs2 + as2 * bd2 + ad2 * bs2, acc_s);
+                acc_d = fma(W2, 3.0 * as2 * bs2 + ad2 * bd2, acc_d);
+            }
+            if (k < kc) {
                 double as, ad, bs, bd;
-                eval_plan(plan[k], gs, gd, A.swap, p, as, ad);
-                eval_plan(plan[nq + k], gs, gd, A.swap, p, bs, bd);
-                const double W = tg[k];
+                eval_packed2(plan[k], rv, pp, as, ad);
+                eval_packed2(plan[kPlanChunk + k], rv, pp, bs, bd);
+                const double W = tg[k0 + k];
                 acc_s = fma(W, sgn * as * bs + as * bd + ad * bs, acc_s);
                 acc_d = fma(W, 3.0 * as * bs + ad * bd, acc_d);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
+    const long vsz = (long)n_triples * ns;
+    finish_pairs(red, lane, ns, G, act, acc_s, acc_d, 0.0, 0.0, dx + A.nf + T.out * ns,
+                 dx + A.nf + vsz + T.out * ns, CH != 0);
+}
 
-    // ---- t channel
-    //   RPA:  -sum_j Gamma_{i1 j}(w1+w, t, w1'-w) Gamma_{j i2}(w+w2', t, w-w2)
-    //   corr: Gamma_{i1i2}(w1+w, t, w1'-w) Gamma_{i2i2}(w2'+w, w2-w, -t)
-    //       + Gamma_{i1i1}(w1+w, w-w1', -t) Gamma_{i1i2}(w+w2', t, w-w2)
+// t channel, ordered by (t, s, u):
+//   RPA:  -sum_j Gamma_{i1 j}(w1+w, t, w1'-w) Gamma_{j i2}(w+w2', t, w-w2)
+//   corr: Gamma_{i1i2}(w1+w, t, w1'-w) Gamma_{i2i2}(w2'+w, w2-w, -t)
+//       + Gamma_{i1i1}(w1+w, w-w1', -t) Gamma_{i1i2}(w+w2', t, w-w2)
+// The lattice sum is the matrix M = sum_k W_k a_k b_k^T (both strains),
+// register-blocked 2x4 per lane, contracted with the tabulated (ka, kb,
+// count) terms of each output pair.  NSP = pair count padded to a multiple
+// of 4 (compile-time, so LDS offsets are immediates); NB = blocks per lane.
+template <int NSP>
+struct TShape {
+    static constexpr int NB = ((NSP / 2) * (NSP / 4) + kWave - 1) / kWave;
+    static constexpr int SUB = NB == 1 ? kSub : kSub / 2;
+};
+
+template <int NSP>
+__global__ void __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(TShape<NSP>::NB == 1 ? 4 : 3)))
+k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+    constexpr int NB = TShape<NSP>::NB;
+    constexpr int SUB = TShape<NSP>::SUB;
+    constexpr int NBK = NSP / 4;
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns, nq = A.nq;
+    const Shared sh = load_shared(A, lds_raw, true);
+    A.w = sh.w;
+    const WaveLds L{ns, SUB};
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L.bytes();
+    Plan* plan = reinterpret_cast<Plan*>(base);                                    // [2][kPlanChunk]
+    double* ons = reinterpret_cast<double*>(base + L.plans());                      // [4][kPlanChunk]
+    double* vb = reinterpret_cast<double*>(base + L.plans() + L.onsite());          // [4][SUB][NSP]
+    double* mat = reinterpret_cast<double*>(base);                                  // [ns*ns] at the end
+    double* red = reinterpret_cast<double*>(base + L.mat());                        // [2][64] at the end
+    const int o = xcd_order(n_triples);
+    if (o < 0) return;
+    const int nsu = nf * (nf + 1) / 2;
+    const int it = o / nsu, su = o % nsu;
+    const int ia = A.su_a[su], ic = A.su_c[su];
+    const Triple T = make_triple(A.w, nf, ia, it, ic);
+    const double t = T.t;
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc(gv, (long)n_triples * ns);
+
+    const int G = kWave / ns;
+    const int g = lane / ns, p = lane % ns;
+    const bool act = g < G;
+    const int2 pp = make_int2(16 * p, 16 * sh.swap[p]);
+    double acc_s = 0.0, acc_d = 0.0;
+
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
-    for (int k = tid; k < cnt; k += kThreads) {
-        const double om = tw[k];
-        make_plan(A.w, nf, ns, w1 + om, t, w1p - om, plan[k]);
-        make_plan(A.w, nf, ns, om + w2p, t, om - w2, plan[nq + k]);
-        Plan P;
-        make_plan(A.w, nf, ns, w2p + om, w2 - om, -t, P);
-        eval_plan(P, gs, gd, A.swap, 0, onsite[4 * k + 0], onsite[4 * k + 1]);
-        make_plan(A.w, nf, ns, w1 + om, om - w1p, -t, P);
-        eval_plan(P, gs, gd, A.swap, 0, onsite[4 * k + 2], onsite[4 * k + 3]);
-    }
-    __syncthreads();
 
-    // lattice-sum matrix entries owned by this thread (ns*ns <= 4*kThreads)
-    double mss[4] = {0.0, 0.0, 0.0, 0.0}, mdd[4] = {0.0, 0.0, 0.0, 0.0};
-    const int nm = ns * ns;
-    for (int k0 = 0; k0 < cnt; k0 += kChunk) {
-        const int kc = min(kChunk, cnt - k0);
-        for (int i = tid; i < kc * ns; i += kThreads) {
-            const int kk = i / ns, j = i % ns;
-            double as, ad, bs, bd;
-            eval_plan(plan[k0 + kk], gs, gd, A.swap, j, as, ad);
-            eval_plan(plan[nq + k0 + kk], gs, gd, A.swap, j, bs, bd);
-            vch[(0 * kChunk + kk) * ns + j] = as;
-            vch[(1 * kChunk + kk) * ns + j] = ad;
-            vch[(2 * kChunk + kk) * ns + j] = bs;
-            vch[(3 * kChunk + kk) * ns + j] = bd;
-        }
-        __syncthreads();
-        for (int e = tid, r = 0; e < nm; e += kThreads, ++r) {
-            const int ka = e / ns, kb = e % ns;
-            double ms = mss[r], md = mdd[r];
-            for (int kk = 0; kk < kc; ++kk) {
-                const double W = tg[k0 + kk];
-                ms = fma(W * vch[(0 * kChunk + kk) * ns + ka], vch[(2 * kChunk + kk) * ns + kb], ms);
-                md = fma(W * vch[(1 * kChunk + kk) * ns + ka], vch[(3 * kChunk + kk) * ns + kb], md);
+    // padding columns ns .. NSP-1 of the site vectors stay zero
+    for (int i = lane; i < 4 * SUB * NSP; i += kWave)
+        if (i % NSP >= ns) vb[i] = 0.0;
+
+    // register blocks: block b = lane + 64 r covers rows 2*(b / NBK) .. +1
+    // and columns 4*(b % NBK) .. +3
+    const int nblocks = ((ns + 1) / 2) * NBK;
+    double ms[NB][2][4], md[NB][2][4];
+#pragma unroll
+    for (int r = 0; r < NB; ++r)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) { ms[r][i][j] = 0.0; md[r][i][j] = 0.0; }
+
+    for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
+        const int kc = min(kPlanChunk, cnt - k0);
+        {
+            const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
+            if (j < kc) {
+                const double om = tw[k0 + j];
+                Plan P, Q;
+                if (vec == 0) {
+                    make_plan(A.w, nf, ns, T.w1 + om, t, T.w1p - om, 1, it, P, sh.ih);
+                    make_plan(A.w, nf, ns, T.w2p + om, T.w2 - om, -t, 2, it, Q, sh.ih);
+                } else {
+                    make_plan(A.w, nf, ns, om + T.w2p, t, om - T.w2, 1, it, P, sh.ih);
+                    make_plan(A.w, nf, ns, T.w1 + om, om - T.w1p, -t, 2, it, Q, sh.ih);
+                }
+                to_bytes(P);
+                to_bytes(Q);
+                plan[vec * kPlanChunk + j] = P;
+                double os, od;
+                eval_packed2(Q, rv, make_int2(0, 0), os, od);      // on-site pair 0
+                ons[(2 * vec + 0) * kPlanChunk + j] = os;
+                ons[(2 * vec + 1) * kPlanChunk + j] = od;
             }
-            mss[r] = ms; mdd[r] = md;
         }
+        wave_lds_sync();
+        for (int s0 = 0; s0 < kc; s0 += SUB) {
+            const int sc = min(SUB, kc - s0);
+            // site vectors of this sub-chunk for pair p: W*a (rows 0, 1) and b
+            // (rows 2, 3); the vertex corrections of pair p use the same ones
+            if (act) {
+                for (int kk = g; kk < sc; kk += G) {
+                    double as, ad, bs, bd;
+                    eval_packed2(plan[s0 + kk], rv, pp, as, ad);
+                    eval_packed2(plan[kPlanChunk + s0 + kk], rv, pp, bs, bd);
+                    const double W = tg[k0 + s0 + kk];
+                    const double was = W * as, wad = W * ad;
+                    vb[(0 * SUB + kk) * NSP + p] = was;
+                    vb[(1 * SUB + kk) * NSP + p] = wad;
+                    vb[(2 * SUB + kk) * NSP + p] = bs;
+                    vb[(3 * SUB + kk) * NSP + p] = bd;
+                    const double* on = ons + s0 + kk;
+                    const double o1s = on[0 * kPlanChunk], o1d = on[1 * kPlanChunk];
+                    const double o2s = on[2 * kPlanChunk], o2d = on[3 * kPlanChunk];
+                    acc_s += -was * o1s + was * o1d + W * (-o2s * bs + o2d * bs);
+                    acc_d += 3.0 * wad * o1s + wad * o1d + W * (3.0 * o2s * bd + o2d * bd);
+                }
+            }
+            wave_lds_sync();
+            // lattice-sum matrix: M[ka][kb] += (W a)[ka] b[kb], both strains
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const int bidx = lane + kWave * r;
+                if (bidx < nblocks) {
+                    const int ka0 = 2 * (bidx / NBK), kb0 = 4 * (bidx % NBK);
+                    const double* va = vb + ka0;
+                    const double* vbb = vb + kb0;
+#pragma unroll
+                    for (int kk = 0; kk < SUB; ++kk) {
+                        if (kk < sc) {
+                            const double2 xs = *reinterpret_cast<const double2*>(va + (0 * SUB + kk) * NSP);
+                            const double2 xd = *reinterpret_cast<const double2*>(va + (1 * SUB + kk) * NSP);
+                            const double4 ys = *reinterpret_cast<const double4*>(vbb + (2 * SUB + kk) * NSP);
+                            const double4 yd = *reinterpret_cast<const double4*>(vbb + (3 * SUB + kk) * NSP);
+                            const double a_s[2] = {xs.x, xs.y}, a_d[2] = {xd.x, xd.y};
+                            const double b_s[4] = {ys.x, ys.y, ys.z, ys.w}, b_d[4] = {yd.x, yd.y, yd.z, yd.w};
+#pragma unroll
+                            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    ms[r][i][j] = fma(a_s[i], b_s[j], ms[r][i][j]);
+                                    md[r][i][j] = fma(a_d[i], b_d[j], md[r][i][j]);
+                                }
+                        }
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+
+    // the matrix strain by strain (reusing the work area), contracted with
+    // the tabulated (ka, kb, count) terms of every output pair; lanes (g, p)
+    // take every G-th term of pair p
+    wave_lds_sync();
+    for (int strain = 0; strain < 2; ++strain) {
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            const int bidx = lane + kWave * r;
+            if (bidx < nblocks) {
+                const int ka0 = 2 * (bidx / NBK), kb0 = 4 * (bidx % NBK);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int ka = ka0 + i, kb = kb0 + j;
+                        if (ka < ns && kb < ns) mat[ka * ns + kb] = strain == 0 ? ms[r][i][j] : md[r][i][j];
+                    }
+            }
+        }
+        wave_lds_sync();
         if (act) {
-            for (int kk = g; kk < kc; kk += G) {
-                const double as = vch[(0 * kChunk + kk) * ns + p], ad = vch[(1 * kChunk + kk) * ns + p];
-                const double bs = vch[(2 * kChunk + kk) * ns + p], bd = vch[(3 * kChunk + kk) * ns + p];
-                const double* o = onsite + 4 * (k0 + kk);
-                const double o1s = o[0], o1d = o[1], o2s = o[2], o2d = o[3];
-                const double W = tg[k0 + kk];
-                acc_s = fma(W, -as * o1s + as * o1d - o2s * bs + o2d * bs, acc_s);
-                acc_d = fma(W, 3.0 * ad * o1s + ad * o1d + 3.0 * o2s * bd + o2d * bd, acc_d);
+            double acc = 0.0;
+            for (int q = sh.off[p] + g; q < sh.off[p + 1]; q += G) {
+                const int tq = sh.terms[q];
+                acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
             }
+            if (strain == 0) acc_s = fma(-2.0, acc, acc_s);
+            else acc_d = fma(-2.0, acc, acc_d);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
-    for (int e = tid, r = 0; e < nm; e += kThreads, ++r) {
-        mat[e] = mss[r];
-        mat[nm + e] = mdd[r];
-    }
-
-    // reduce the per-group partial sums over g
-    red[tid] = act ? acc_s : 0.0;
-    red[kThreads + tid] = act ? acc_d : 0.0;
-    __syncthreads();
-    if (tid < ns) {
-        double ts = 0.0, td = 0.0;
-        for (int gg = 0; gg < G; ++gg) {
-            ts += red[gg * ns + tid];
-            td += red[kThreads + gg * ns + tid];
-        }
-        double rs = 0.0, rd = 0.0;
-        for (int q = A.rpa_off[tid]; q < A.rpa_off[tid + 1]; ++q) {
-            const int e = A.rpa_ka[q] * ns + A.rpa_kb[q];
-            const double cw = (double)A.rpa_cnt[q];
-            rs = fma(cw, mat[e], rs);
-            rd = fma(cw, mat[nm + e], rd);
-        }
-        const long o = (long)tau * ns + tid;
-        dx[nf + o] = ts - 2.0 * rs;
-        dx[nf + vsz + o] = td - 2.0 * rd;
-    }
+    const long vsz = (long)n_triples * ns;
+    finish_pairs(red, lane, ns, G, act, acc_s, acc_d, 0.0, 0.0, dx + A.nf + T.out * ns,
+                 dx + A.nf + vsz + T.out * ns, true);
 }
 
 }  // namespace pffrg

@@ -63,12 +63,12 @@ k_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restrict_
         const double w1 = cw[i], w2 = cw[j];
         const double f = cq[i] * cq[j] * cg2[i] * cg2[j];
         Plan P;
-        make_plan(w, nf, ns, w1 + w2, 0.0, w1 - w2, P);
+        make_plan(w, nf, ns, w1 + w2, 0.0, w1 - w2, 1, 0, P);
         double vs, vd;
         eval_plan(P, gs, gd, swap, p, vs, vd);
         double tz = 4.0 * vs, td = 4.0 * vd;
         if (p == 0) {
-            make_plan(w, nf, ns, w1 + w2, w2 - w1, 0.0, P);
+            make_plan(w, nf, ns, w1 + w2, w2 - w1, 0.0, 2, 0, P);
             double es, ed;
             eval_plan(P, gs, gd, swap, 0, es, ed);
             tz += 2.0 * es - 2.0 * ed;

@@ -57,15 +57,19 @@ struct pffrg_ctx {
     // tables
     double* w = nullptr;
     int *swap = nullptr, *mult = nullptr, *rpa_off = nullptr, *rpa_ka = nullptr,
-        *rpa_kb = nullptr, *rpa_cnt = nullptr, *su_a = nullptr, *su_c = nullptr;
+        *rpa_kb = nullptr, *rpa_cnt = nullptr, *su_a = nullptr, *su_c = nullptr, *uo_a = nullptr,
+        *uo_c = nullptr;
     double* coupling = nullptr;
     int nb = 0, nterm = 0;          // chi(k) terms: (basis, site) pairs in range
     int* chi_pair = nullptr;        // [nterm]
+    int* rpa_term = nullptr;        // packed lattice-sum terms
+    int n_terms = 0;
     double* chi_dr = nullptr;       // [nterm*3]  r_b - r_j
 
     // scratch
     int* tab_n = nullptr;
     double *tab_w = nullptr, *tab_g = nullptr, *dsig = nullptr;
+    double2* gv = nullptr;          // packed (Gs, Gd) copy of the state's vertex
     double* k[kNumK] = {};
     double *ybuf = nullptr, *ebuf = nullptr;
     double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
@@ -80,13 +84,14 @@ struct pffrg_ctx {
     // kernel timing: event pairs recorded around launches while profiling
     bool profiling = false;
     std::vector<hipEvent_t> ev[PFFRG_K_COUNT];
-    int ev_used[PFFRG_K_COUNT] = {0, 0, 0};
+    int ev_used[PFFRG_K_COUNT] = {};
 
     FlowArgs args() const {
         FlowArgs A;
         A.w = w; A.nf = nf; A.ns = ns; A.nq = nq;
         A.swap = swap; A.mult = mult; A.rpa_off = rpa_off; A.rpa_ka = rpa_ka;
         A.rpa_kb = rpa_kb; A.rpa_cnt = rpa_cnt; A.su_a = su_a; A.su_c = su_c;
+        A.rpa_term = rpa_term; A.n_terms = n_terms;
         A.tab_n = tab_n; A.tab_w = tab_w; A.tab_g = tab_g;
         return A;
     }
@@ -153,30 +158,74 @@ void prof_mark(pffrg_ctx* c, int id, bool after) {
     if (after) ++c->ev_used[id];
 }
 
+// LDS of the t-channel launch (shared tables + 4 waves) for ns pairs.
+size_t t_lds_bytes(int nf, int ns, int n_terms) {
+    const int nsp = (ns + 3) & ~3;
+    const int nb = ((nsp / 2) * (nsp / 4) + kWave - 1) / kWave;
+    const WaveLds L{ns, nb == 1 ? kSub : kSub / 2};
+    return SharedLds{nf, ns, n_terms}.bytes(true) + kWavesPerBlock * L.bytes();
+}
+
 // ------------------------------------------------------------ one RHS ---
 
-pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
+pffrg_status pack(pffrg_ctx* c, const double* x) {
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf,
+                       x + c->nf + c->vsz, c->gv);
+    return launch_check("k_pack");
+}
+
+pffrg_status sigma_rhs_packed(pffrg_ctx* c, double lam, const double* x, double* dsig) {
     FlowArgs A = c->args();
     prof_mark(c, PFFRG_K_SIGMA, false);
-    hipLaunchKernelGGL(k_sigma_rhs, dim3((c->nf + 63) / 64), dim3(64), 0, c->stream, A, lam, x, dsig);
+    hipLaunchKernelGGL(k_sigma_rhs, dim3(c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double2*)c->gv,
+                       (long)c->vsz, dsig);
     prof_mark(c, PFFRG_K_SIGMA, true);
     return launch_check("k_sigma_rhs");
+}
+
+pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
+    TRY(pack(c, x));
+    return sigma_rhs_packed(c, lam, x, dsig);
 }
 
 pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
     FlowArgs A = c->args();
-    TRY(sigma_rhs(c, lam, x, dx));          // the sigma part of dx is dsig
+    TRY(pack(c, x));
+    TRY(sigma_rhs_packed(c, lam, x, dx));          // the sigma part of dx is dsig
     prof_mark(c, PFFRG_K_TABLES, false);
-    hipLaunchKernelGGL(k_node_tables, dim3((3 * c->nf + 63) / 64), dim3(64), 0, c->stream, A, lam, x,
-                       (const double*)dx);
+    hipLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)dx);
     prof_mark(c, PFFRG_K_TABLES, true);
     TRY(launch_check("k_node_tables"));
-    const VertexLds L{c->nq, c->ns};
+    const int T = c->nsu * c->nf;
+    const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per = (blocks + 7) / 8;
+    const SharedLds S{c->nf, c->ns, c->n_terms};
+    const WaveLds Lsu{c->ns};
+    const size_t lds_su = S.bytes(false) + kWavesPerBlock * Lsu.su_bytes();
+    const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
     prof_mark(c, PFFRG_K_VERTEX, false);
-    hipLaunchKernelGGL(k_vertex_rhs, dim3(c->nsu * c->nf), dim3(kThreads), L.total(), c->stream, A, x, dx);
+    prof_mark(c, PFFRG_K_VERTEX_S, false);
+    hipLaunchKernelGGL(k_vertex_su<0>, grid, block, lds_su, c->stream, A, (const double2*)c->gv,
+                       (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
+    prof_mark(c, PFFRG_K_VERTEX_S, true);
+    prof_mark(c, PFFRG_K_VERTEX_U, false);
+    hipLaunchKernelGGL(k_vertex_su<2>, grid, block, lds_su, c->stream, A, (const double2*)c->gv,
+                       (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
+    prof_mark(c, PFFRG_K_VERTEX_U, true);
+    const size_t lds_t = t_lds_bytes(c->nf, c->ns, c->n_terms);
+    prof_mark(c, PFFRG_K_VERTEX_T, false);
+    switch ((c->ns + 3) / 4) {
+#define PFFRG_T_CASE(K) \
+        case K: hipLaunchKernelGGL(k_vertex_t<4 * K>, grid, block, lds_t, c->stream, A, (const double2*)c->gv, T, dx); break;
+        PFFRG_T_CASE(1) PFFRG_T_CASE(2) PFFRG_T_CASE(3) PFFRG_T_CASE(4)
+        PFFRG_T_CASE(5) PFFRG_T_CASE(6) PFFRG_T_CASE(7) PFFRG_T_CASE(8)
+#undef PFFRG_T_CASE
+        default: return fail(PFFRG_EUNSUPPORTED, "pair count out of range");
+    }
+    prof_mark(c, PFFRG_K_VERTEX_T, true);
     prof_mark(c, PFFRG_K_VERTEX, true);
-    return launch_check("k_vertex_rhs");
+    return launch_check("k_vertex_t");
 }
 
 // max-norm error / finiteness readback (synchronises the stream)
@@ -336,7 +385,7 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
     }
     if (ns < 1 || !lat->swap || !lat->mult || !lat->rpa_off || !lat->coupling)
         return fail(PFFRG_EINVAL, "lattice tables incomplete");
-    if (ns * ns > 4 * kThreads)
+    if (ns > kMaxPairs)
         return fail(PFFRG_EUNSUPPORTED, "more than 32 reduced pairs is not supported by this kernel build");
     if (prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "only PFFRG_FP64 is available in this build");
     if (lat->swap[0] != 0) return fail(PFFRG_EINVAL, "pair 0 must be the on-site pair (swap[0] == 0)");
@@ -374,12 +423,28 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(upload(c, &c->rpa_ka, lat->rpa_ka, (size_t)nterms));
         TRY(upload(c, &c->rpa_kb, lat->rpa_kb, (size_t)nterms));
         TRY(upload(c, &c->rpa_cnt, lat->rpa_cnt, (size_t)nterms));
+        {
+            std::vector<int> packed(nterms);
+            for (int q = 0; q < nterms; ++q) {
+                if (lat->rpa_cnt[q] < 1 || lat->rpa_cnt[q] > 32767)
+                    return fail(PFFRG_EINVAL, "rpa_cnt out of range [1, 32767]");
+                packed[q] = (lat->rpa_ka[q] * ns + lat->rpa_kb[q]) | (lat->rpa_cnt[q] << 16);
+            }
+            c->n_terms = nterms;
+            TRY(upload(c, &c->rpa_term, packed.data(), packed.size()));
+        }
         TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
         std::vector<int> sa(c->nsu), sc(c->nsu);
         for (int a = 0; a < nf; ++a)
             for (int cc = 0; cc <= a; ++cc) { sa[a * (a + 1) / 2 + cc] = a; sc[a * (a + 1) / 2 + cc] = cc; }
         TRY(upload(c, &c->su_a, sa.data(), sa.size()));
         TRY(upload(c, &c->su_c, sc.data(), sc.size()));
+        // the same wedge in u-major order (u-channel launch order)
+        std::vector<int> ua, uc;
+        for (int cc = 0; cc < nf; ++cc)
+            for (int a = cc; a < nf; ++a) { ua.push_back(a); uc.push_back(cc); }
+        TRY(upload(c, &c->uo_a, ua.data(), ua.size()));
+        TRY(upload(c, &c->uo_c, uc.data(), uc.size()));
         std::vector<int> cp;
         std::vector<double> dr;
         for (int b = 0; b < lat->n_basis; ++b)
@@ -398,6 +463,7 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->tab_w, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->tab_g, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->dsig, (size_t)nf));
+        TRY(dev_alloc(c, &c->gv, (size_t)c->vsz));
         for (int j = 0; j < kNumK; ++j) TRY(dev_alloc(c, &c->k[j], (size_t)c->size));
         TRY(dev_alloc(c, &c->ybuf, (size_t)c->size));
         TRY(dev_alloc(c, &c->ebuf, (size_t)c->size));
@@ -409,8 +475,9 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->part, (size_t)2 * kRedBlocks));
         TRY(dev_alloc(c, &c->red, 2));
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
-        const VertexLds L{c->nq, c->ns};
-        if (L.total() > 64 * 1024) return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
+        if (nf > kMaxFreq) return fail(PFFRG_EUNSUPPORTED, "more than 128 frequencies is not supported");
+        if (t_lds_bytes(nf, ns, nterms) > 64 * 1024)
+            return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
         return PFFRG_OK;
     };
     pffrg_status st = body();

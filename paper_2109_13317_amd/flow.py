@@ -142,8 +142,10 @@ class Context:
         _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
 
     def profile_read(self, kernel: str):
-        """(total_ms, launches) of 'sigma', 'tables' or 'vertex' since profiling began."""
-        kid = {"sigma": _lib.K_SIGMA, "tables": _lib.K_TABLES, "vertex": _lib.K_VERTEX}[kernel]
+        """(total_ms, launches) of 'sigma', 'tables', 'vertex' (all three channel
+        launches), 'vertex_s', 'vertex_u' or 'vertex_t' since profiling began."""
+        kid = {"sigma": _lib.K_SIGMA, "tables": _lib.K_TABLES, "vertex": _lib.K_VERTEX,
+               "vertex_s": _lib.K_VERTEX_S, "vertex_u": _lib.K_VERTEX_U, "vertex_t": _lib.K_VERTEX_T}[kernel]
         ms, n = ctypes.c_double(), ctypes.c_int()
         _lib.check(self.lib.pffrg_profile_read(self.handle, kid, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
