@@ -53,12 +53,16 @@ __device__ __forceinline__ double odd_interp(const double* __restrict__ w, int n
 // extrapolates to the first mesh point), whose slot and mesh index the
 // caller passes, so trilinear interpolation touches at most four corners.
 // Unused corners repeat a used one with weight 0.
-struct Plan {
+// R is the type the weights are applied in (double, or float in the FP32
+// mode); the brackets themselves are always found in FP64.
+template <class R>
+struct PlanT {
     int off[4];       // element offset ((a(a+1)/2 + c) * nf + t) * ns: add the pair index
-    double ws[4];     // spin-strain weights
-    double wd[4];     // density-strain weights (carry the s<->u signs)
+    R ws[4];          // spin-strain weights
+    R wd[4];          // density-strain weights (carry the s<->u signs)
     int swp;          // 1: read the exchanged pair swap[p]
 };
+using Plan = PlanT<double>;
 
 // Bracket of x >= 0 with a precomputed reciprocal spacing table
 // ih[i] = 1 / (w[i+1] - w[i]); weights f1 = (x - w[lo]) ih[lo], f0 = 1 - f1.
@@ -78,8 +82,9 @@ __device__ __forceinline__ void bracket_fast(const double* __restrict__ w, const
 
 // kslot in {0,1,2}: which of (s, t, u) holds the on-mesh value, kidx its mesh
 // index (0 for a zero argument).  ih as in bracket_fast (NULL: divide).
+template <class R>
 __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, int ns,
-                                          double s, double t, double u, int kslot, int kidx, Plan& P,
+                                          double s, double t, double u, int kslot, int kidx, PlanT<R>& P,
                                           const double* __restrict__ ih = nullptr) {
     int swp = 0;
     double sd = 1.0;
@@ -117,8 +122,8 @@ __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, 
             if (a < c) { const int q = a; a = c; c = q; cs = -cs; }
             const double wg = g0[i] * g1[j];
             P.off[2 * i + j] = (int)((su_index(a, c) * nf + it) * ns);
-            P.ws[2 * i + j] = wg;
-            P.wd[2 * i + j] = cs * wg;
+            P.ws[2 * i + j] = (R)wg;
+            P.wd[2 * i + j] = (R)(cs * wg);
         }
     P.swp = swp;
 }

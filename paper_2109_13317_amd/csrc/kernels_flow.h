@@ -56,77 +56,117 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Buffer resource of the packed (Gs, Gd) vertex: loads take a 32-bit byte
-// offset; reads past the end return 0 (they never happen: every plan offset
-// lies in the state).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t vertex_rsrc(const double2* gv, long n) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * 16), 0x00020000);
+// The packed vertex: the two strains of one element side by side, in the
+// precision R the vertex kernels work in (double2, or float2 in FP32 mode).
+template <class R> struct Packed;
+template <> struct Packed<double> { using V2 = double2; using V4 = double4; };
+template <> struct Packed<float> { using V2 = float2; using V4 = float4; };
+template <class R> using V2 = typename Packed<R>::V2;
+template <class R> using V4 = typename Packed<R>::V4;
+template <class R> constexpr int kElemBytes = 2 * (int)sizeof(R);
+
+__device__ __forceinline__ double fmr(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmr(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Buffer resource of the packed vertex: loads take a 32-bit byte offset;
+// reads past the end return 0 (they never happen: every plan offset lies in
+// the state).
+template <class R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vertex_rsrc(const V2<R>* gv, long n) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * kElemBytes<R>), 0x00020000);
 }
 
-__device__ __forceinline__ double2 load_corner(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+__device__ __forceinline__ double2 load_corner(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+__device__ __forceinline__ float2 load_corner(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
 }
 
 // Interpolation of both strains of one pair from the packed vertex; plan
-// offsets are byte offsets (element offset * 16), pp = 16 * (p, swap[p]).
-__device__ __forceinline__ void eval_packed2(const Plan& P, __amdgpu_buffer_rsrc_t r, int2 pp,
-                                             double& vs, double& vd) {
+// offsets are byte offsets, pp = element bytes * (p, swap[p]).
+template <class R>
+__device__ __forceinline__ void eval_packed2(const PlanT<R>& P, __amdgpu_buffer_rsrc_t r, int2 pp,
+                                             R& vs, R& vd) {
     const unsigned q = P.swp ? pp.y : pp.x;
-    double a = 0.0, b = 0.0;
+    R a = 0, b = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const double2 g = load_corner(r, (unsigned)P.off[i] + q);
-        a = fma(P.ws[i], g.x, a);
-        b = fma(P.wd[i], g.y, b);
+        const V2<R> g = load_corner(r, (unsigned)P.off[i] + q, R());
+        a = fmr(P.ws[i], g.x, a);
+        b = fmr(P.wd[i], g.y, b);
     }
     vs = a;
     vd = b;
 }
 
 // A plan whose offsets are turned into byte offsets of the packed vertex.
-__device__ __forceinline__ void to_bytes(Plan& P) {
+template <class R>
+__device__ __forceinline__ void to_bytes(PlanT<R>& P) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) P.off[i] *= 16;
+    for (int i = 0; i < 4; ++i) P.off[i] *= kElemBytes<R>;
 }
+
+// Running sum of per-chunk partial sums.  In FP32 the rounding error of each
+// addition is carried along (Kahan's compensated summation) and the value is
+// s - c evaluated in FP64; in FP64 it is a plain sum.
+template <class R>
+struct CompSum {
+    R s = 0, c = 0;
+    __device__ __forceinline__ void add(R x) {
+        if constexpr (sizeof(R) == 4) {
+            const R y = x - c;
+            const R t = s + y;
+            c = (t - s) - y;
+            s = t;
+        } else {
+            s += x;
+        }
+    }
+    __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
 
 // ------------------------------------------------------------ self-energy -
 
 // d sig/d Lambda (w_n) = (1/2pi) sum_{x=+-Lambda} F(w_n, x) / (x - sig(x)),
 // F = 2 sum_r mult_r Gd_r(w+x, 0, w-x) - 3 Gs_0(w+x, x-w, 0) - Gd_0(w+x, x-w, 0).
 __global__ void __launch_bounds__(kWave)
-k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, const double2* __restrict__ gv, long nv,
-            double* __restrict__ dsig) {
+k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, long nv, double* __restrict__ dsig) {
     const int n = blockIdx.x, lane = threadIdx.x;
     const double wn = A.w[n];
-    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc(gv, nv);
+    const double* gs = x + A.nf;
+    const double* gd = gs + nv;
     double acc = 0.0;
     for (int sx = 0; sx < 2; ++sx) {
         const double xx = sx == 0 ? lam : -lam;
         Plan P;
         make_plan(A.w, A.nf, A.ns, wn + xx, 0.0, wn - xx, 1, 0, P);
-        to_bytes(P);
         double f = 0.0;
         for (int r = lane; r < A.ns; r += kWave) {
             double vs, vd;
-            eval_packed2(P, rv, make_int2(16 * r, 16 * A.swap[r]), vs, vd);
+            eval_plan(P, gs, gd, A.swap, r, vs, vd);
             f = fma(2.0 * (double)A.mult[r], vd, f);
         }
         f = wave_sum(f);
         Plan Q;
         make_plan(A.w, A.nf, A.ns, wn + xx, xx - wn, 0.0, 2, 0, Q);
-        to_bytes(Q);
         double os, od;
-        eval_packed2(Q, rv, make_int2(0, 0), os, od);
+        eval_plan(Q, gs, gd, A.swap, 0, os, od);
         f -= 3.0 * os + od;
         acc += f / (xx - odd_interp(A.w, A.nf, x, xx));
     }
     if (lane == 0) dsig[n] = acc * kInvTwoPi;
 }
 
+template <class R>
 __global__ void k_pack(long n, const double* __restrict__ gs, const double* __restrict__ gd,
-                       double2* __restrict__ gv) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        gv[i] = make_double2(gs[i], gd[i]);
+                       V2<R>* __restrict__ gv) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        V2<R> v;
+        v.x = (R)gs[i];
+        v.y = (R)gd[i];
+        gv[i] = v;
+    }
 }
 
 // ------------------------------------------------------------ node tables -
@@ -289,15 +329,17 @@ __device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* 
     return Shared{w, ih, sw, off, terms};
 }
 
-// Per-wave LDS of the t-channel kernel, in bytes.  The lattice-sum matrix
-// at the end reuses it.  The s/u kernel uses plans() + red().
+// Per-wave LDS of the t-channel kernel, in bytes (R: the vertex precision).
+// The lattice-sum matrix at the end reuses it.  The s/u kernel uses
+// plans() + red().
+template <class R>
 struct WaveLds {
     int ns;
     int sub = kSub;   // nodes per lattice-sum sub-chunk
     __host__ __device__ int nsp() const { return (ns + 3) & ~3; }
-    __host__ __device__ size_t plans() const { return (size_t)2 * kPlanChunk * sizeof(Plan); }
-    __host__ __device__ size_t onsite() const { return (size_t)4 * kPlanChunk * sizeof(double); }
-    __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(double); }
+    __host__ __device__ size_t plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
+    __host__ __device__ size_t onsite() const { return (size_t)4 * kPlanChunk * sizeof(R); }
+    __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(R); }
     __host__ __device__ size_t red() const { return (size_t)2 * kWave * sizeof(double); }
     __host__ __device__ size_t mat() const { return (((size_t)ns * ns * sizeof(double)) + 31) & ~(size_t)31; }
     __host__ __device__ size_t work() const { return plans() + onsite() + vbuf(); }
@@ -306,7 +348,7 @@ struct WaveLds {
         size_t b = work() > m ? work() : m;
         return (b + 31) & ~(size_t)31;
     }
-    __host__ __device__ size_t su_bytes() const { return plans() + red(); }
+    __host__ __device__ size_t su_bytes() const { return ((plans() + 31) & ~(size_t)31) + red(); }
 };
 
 // Position in the channel's order of the triple handled by this wave, or -1.
@@ -361,20 +403,21 @@ __device__ __forceinline__ void finish_pairs(double* red, int lane, int ns, int 
 // u channel (CH = 2): A = Gamma(w1+w, w-w2', u), B = Gamma(w1'+w, w2-w, u),
 //   dGs += W (2 As Bs + As Bd + Ad Bs), dGd += W (3 As Bs + Ad Bd).
 // Order: s channel by (s, u, t) wedge order; u channel by (u, s, t) using
-// the u-major wedge tables uo_a / uo_c.
-template <int CH>
+// the u-major wedge tables uo_a / uo_c.  R: precision of the interpolation,
+// products and per-chunk sums (the chunk sums are folded by CompSum).
+template <int CH, class R>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-k_vertex_su(FlowArgs A, const double2* __restrict__ gv, const int* __restrict__ uo_a,
+k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo_a,
             const int* __restrict__ uo_c, int n_triples, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, false);
     A.w = sh.w;
-    const WaveLds L{ns};
+    const WaveLds<R> L{ns};
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * L.su_bytes();
-    Plan* plan = reinterpret_cast<Plan*>(base);
-    double* red = reinterpret_cast<double*>(base + L.plans());
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);
+    double* red = reinterpret_cast<double*>(base + L.su_bytes() - L.red());
     const int o = xcd_order(n_triples);
     if (o < 0) return;
     const int q = o / nf, it = o % nf;
@@ -385,21 +428,23 @@ k_vertex_su(FlowArgs A, const double2* __restrict__ gv, const int* __restrict__ 
     const int G = kWave / ns;
     const int g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(16 * p, 16 * sh.swap[p]);
-    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc(gv, (long)n_triples * ns);
-    double acc_s = 0.0, acc_d = 0.0;
+    const int2 pp = make_int2(kElemBytes<R> * p, kElemBytes<R> * sh.swap[p]);
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
+    CompSum<R> sum_s, sum_d;
     const int iv = CH == 0 ? ia : ic;
     const int cnt = A.tab_n[CH * nf + iv];
     const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
     const double* tg = A.tab_g + (long)(CH * nf + iv) * nq;
-    const double sgn = CH == 0 ? -2.0 : 2.0;
+    const R sgn = CH == 0 ? R(-2) : R(2);
+    const R three = R(3);
+    R acc_s = 0, acc_d = 0;
     for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
         const int kc = min(kPlanChunk, cnt - k0);
         {
             const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
             if (j < kc) {
                 const double om = tw[k0 + j];
-                Plan P;
+                PlanT<R> P;
                 if (CH == 0) {
                     if (vec == 0) make_plan(A.w, nf, ns, T.s, T.w1p - om, om - T.w2p, 0, ia, P, sh.ih);
                     else make_plan(A.w, nf, ns, T.s, om - T.w1, om - T.w2, 0, ia, P, sh.ih);
@@ -415,30 +460,39 @@ k_vertex_su(FlowArgs A, const double2* __restrict__ gv, const int* __restrict__ 
         if (act) {
             int k = g;
             for (; k + G < kc; k += 2 * G) {     // two nodes in flight
-                double as, ad, bs, bd, as2, ad2, bs2, bd2;
+                R as, ad, bs, bd, as2, ad2, bs2, bd2;
                 eval_packed2(plan[k], rv, pp, as, ad);
                 eval_packed2(plan[kPlanChunk + k], rv, pp, bs, bd);
                 eval_packed2(plan[k + G], rv, pp, as2, ad2);
                 eval_packed2(plan[kPlanChunk + k + G], rv, pp, bs2, bd2);
-                const double W = tg[k0 + k], W2 = tg[k0 + k + G];
-                acc_s = fma(W, sgn * as * bs + as * bd + ad * bs, acc_s);
-                acc_d = fma(W, 3.0 * as * bs + ad * bd, acc_d);
-                acc_s = fma(W2, sgn * as2 * bs2 + as2 * bd2 + ad2 * bs2, acc_s);
-                acc_d = fma(W2, 3.0 * as2 * bs2 + ad2 * bd2, acc_d);
+                const R W = (R)tg[k0 + k], W2 = (R)tg[k0 + k + G];
+                acc_s = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s);
+                acc_d = fmr(W, three * as * bs + ad * bd, acc_d);
+                acc_s = fmr(W2, sgn * as2 * bs2 + as2 * bd2 + ad2 * bs2, acc_s);
+                acc_d = fmr(W2, three * as2 * bs2 + ad2 * bd2, acc_d);
             }
             if (k < kc) {
-                double as, ad, bs, bd;
+                R as, ad, bs, bd;
                 eval_packed2(plan[k], rv, pp, as, ad);
                 eval_packed2(plan[kPlanChunk + k], rv, pp, bs, bd);
-                const double W = tg[k0 + k];
-                acc_s = fma(W, sgn * as * bs + as * bd + ad * bs, acc_s);
-                acc_d = fma(W, 3.0 * as * bs + ad * bd, acc_d);
+                const R W = (R)tg[k0 + k];
+                acc_s = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s);
+                acc_d = fmr(W, three * as * bs + ad * bd, acc_d);
             }
+        }
+        if constexpr (sizeof(R) == 4) {
+            sum_s.add(acc_s);
+            sum_d.add(acc_d);
+            acc_s = acc_d = R(0);
         }
         wave_lds_sync();
     }
+    if constexpr (sizeof(R) == 8) {
+        sum_s.s = acc_s;
+        sum_d.s = acc_d;
+    }
     const long vsz = (long)n_triples * ns;
-    finish_pairs(red, lane, ns, G, act, acc_s, acc_d, 0.0, 0.0, dx + A.nf + T.out * ns,
+    finish_pairs(red, lane, ns, G, act, sum_s.value(), sum_d.value(), 0.0, 0.0, dx + A.nf + T.out * ns,
                  dx + A.nf + vsz + T.out * ns, CH != 0);
 }
 
@@ -450,29 +504,32 @@ k_vertex_su(FlowArgs A, const double2* __restrict__ gv, const int* __restrict__ 
 // register-blocked 2x4 per lane, contracted with the tabulated (ka, kb,
 // count) terms of each output pair.  NSP = pair count padded to a multiple
 // of 4 (compile-time, so LDS offsets are immediates); NB = blocks per lane.
+// In FP32 the matrix of each plan chunk is folded into a compensated sum;
+// the contraction with the terms runs in FP64.
 template <int NSP>
 struct TShape {
     static constexpr int NB = ((NSP / 2) * (NSP / 4) + kWave - 1) / kWave;
     static constexpr int SUB = NB == 1 ? kSub : kSub / 2;
 };
 
-template <int NSP>
+template <int NSP, class R>
 __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(TShape<NSP>::NB == 1 ? 4 : 3)))
-k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+__attribute__((amdgpu_waves_per_eu(TShape<NSP>::NB == 1 && sizeof(R) == 8 ? 4 : 3)))
+k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
     constexpr int NB = TShape<NSP>::NB;
     constexpr int SUB = TShape<NSP>::SUB;
     constexpr int NBK = NSP / 4;
+    constexpr bool kComp = sizeof(R) == 4;
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, true);
     A.w = sh.w;
-    const WaveLds L{ns, SUB};
+    const WaveLds<R> L{ns, SUB};
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L.bytes();
-    Plan* plan = reinterpret_cast<Plan*>(base);                                    // [2][kPlanChunk]
-    double* ons = reinterpret_cast<double*>(base + L.plans());                      // [4][kPlanChunk]
-    double* vb = reinterpret_cast<double*>(base + L.plans() + L.onsite());          // [4][SUB][NSP]
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                           // [2][kPlanChunk]
+    R* ons = reinterpret_cast<R*>(base + L.plans());                                // [4][kPlanChunk]
+    R* vb = reinterpret_cast<R*>(base + L.plans() + L.onsite());                    // [4][SUB][NSP]
     double* mat = reinterpret_cast<double*>(base);                                  // [ns*ns] at the end
     double* red = reinterpret_cast<double*>(base + L.mat());                        // [2][64] at the end
     const int o = xcd_order(n_triples);
@@ -482,13 +539,15 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
     const int ia = A.su_a[su], ic = A.su_c[su];
     const Triple T = make_triple(A.w, nf, ia, it, ic);
     const double t = T.t;
-    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc(gv, (long)n_triples * ns);
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
 
     const int G = kWave / ns;
     const int g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(16 * p, 16 * sh.swap[p]);
-    double acc_s = 0.0, acc_d = 0.0;
+    const int2 pp = make_int2(kElemBytes<R> * p, kElemBytes<R> * sh.swap[p]);
+    CompSum<R> sum_s, sum_d;
+    const R three = R(3);
+    R acc_s = 0, acc_d = 0;
 
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
@@ -496,18 +555,19 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
 
     // padding columns ns .. NSP-1 of the site vectors stay zero
     for (int i = lane; i < 4 * SUB * NSP; i += kWave)
-        if (i % NSP >= ns) vb[i] = 0.0;
+        if (i % NSP >= ns) vb[i] = R(0);
 
     // register blocks: block b = lane + 64 r covers rows 2*(b / NBK) .. +1
     // and columns 4*(b % NBK) .. +3
     const int nblocks = ((ns + 1) / 2) * NBK;
-    double ms[NB][2][4], md[NB][2][4];
+    R ms[NB][2][4], md[NB][2][4];
+    CompSum<R> cms[kComp ? NB : 1][2][4], cmd[kComp ? NB : 1][2][4];
 #pragma unroll
     for (int r = 0; r < NB; ++r)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) { ms[r][i][j] = 0.0; md[r][i][j] = 0.0; }
+            for (int j = 0; j < 4; ++j) { ms[r][i][j] = R(0); md[r][i][j] = R(0); }
 
     for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
         const int kc = min(kPlanChunk, cnt - k0);
@@ -515,7 +575,7 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
             const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
             if (j < kc) {
                 const double om = tw[k0 + j];
-                Plan P, Q;
+                PlanT<R> P, Q;
                 if (vec == 0) {
                     make_plan(A.w, nf, ns, T.w1 + om, t, T.w1p - om, 1, it, P, sh.ih);
                     make_plan(A.w, nf, ns, T.w2p + om, T.w2 - om, -t, 2, it, Q, sh.ih);
@@ -526,7 +586,7 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
                 to_bytes(P);
                 to_bytes(Q);
                 plan[vec * kPlanChunk + j] = P;
-                double os, od;
+                R os, od;
                 eval_packed2(Q, rv, make_int2(0, 0), os, od);      // on-site pair 0
                 ons[(2 * vec + 0) * kPlanChunk + j] = os;
                 ons[(2 * vec + 1) * kPlanChunk + j] = od;
@@ -539,20 +599,20 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
             // (rows 2, 3); the vertex corrections of pair p use the same ones
             if (act) {
                 for (int kk = g; kk < sc; kk += G) {
-                    double as, ad, bs, bd;
+                    R as, ad, bs, bd;
                     eval_packed2(plan[s0 + kk], rv, pp, as, ad);
                     eval_packed2(plan[kPlanChunk + s0 + kk], rv, pp, bs, bd);
-                    const double W = tg[k0 + s0 + kk];
-                    const double was = W * as, wad = W * ad;
+                    const R W = (R)tg[k0 + s0 + kk];
+                    const R was = W * as, wad = W * ad;
                     vb[(0 * SUB + kk) * NSP + p] = was;
                     vb[(1 * SUB + kk) * NSP + p] = wad;
                     vb[(2 * SUB + kk) * NSP + p] = bs;
                     vb[(3 * SUB + kk) * NSP + p] = bd;
-                    const double* on = ons + s0 + kk;
-                    const double o1s = on[0 * kPlanChunk], o1d = on[1 * kPlanChunk];
-                    const double o2s = on[2 * kPlanChunk], o2d = on[3 * kPlanChunk];
+                    const R* on = ons + s0 + kk;
+                    const R o1s = on[0 * kPlanChunk], o1d = on[1 * kPlanChunk];
+                    const R o2s = on[2 * kPlanChunk], o2d = on[3 * kPlanChunk];
                     acc_s += -was * o1s + was * o1d + W * (-o2s * bs + o2d * bs);
-                    acc_d += 3.0 * wad * o1s + wad * o1d + W * (3.0 * o2s * bd + o2d * bd);
+                    acc_d += three * wad * o1s + wad * o1d + W * (three * o2s * bd + o2d * bd);
                 }
             }
             wave_lds_sync();
@@ -562,23 +622,23 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
                 const int bidx = lane + kWave * r;
                 if (bidx < nblocks) {
                     const int ka0 = 2 * (bidx / NBK), kb0 = 4 * (bidx % NBK);
-                    const double* va = vb + ka0;
-                    const double* vbb = vb + kb0;
+                    const R* va = vb + ka0;
+                    const R* vbb = vb + kb0;
 #pragma unroll
                     for (int kk = 0; kk < SUB; ++kk) {
                         if (kk < sc) {
-                            const double2 xs = *reinterpret_cast<const double2*>(va + (0 * SUB + kk) * NSP);
-                            const double2 xd = *reinterpret_cast<const double2*>(va + (1 * SUB + kk) * NSP);
-                            const double4 ys = *reinterpret_cast<const double4*>(vbb + (2 * SUB + kk) * NSP);
-                            const double4 yd = *reinterpret_cast<const double4*>(vbb + (3 * SUB + kk) * NSP);
-                            const double a_s[2] = {xs.x, xs.y}, a_d[2] = {xd.x, xd.y};
-                            const double b_s[4] = {ys.x, ys.y, ys.z, ys.w}, b_d[4] = {yd.x, yd.y, yd.z, yd.w};
+                            const V2<R> xs = *reinterpret_cast<const V2<R>*>(va + (0 * SUB + kk) * NSP);
+                            const V2<R> xd = *reinterpret_cast<const V2<R>*>(va + (1 * SUB + kk) * NSP);
+                            const V4<R> ys = *reinterpret_cast<const V4<R>*>(vbb + (2 * SUB + kk) * NSP);
+                            const V4<R> yd = *reinterpret_cast<const V4<R>*>(vbb + (3 * SUB + kk) * NSP);
+                            const R a_s[2] = {xs.x, xs.y}, a_d[2] = {xd.x, xd.y};
+                            const R b_s[4] = {ys.x, ys.y, ys.z, ys.w}, b_d[4] = {yd.x, yd.y, yd.z, yd.w};
 #pragma unroll
                             for (int i = 0; i < 2; ++i)
 #pragma unroll
                                 for (int j = 0; j < 4; ++j) {
-                                    ms[r][i][j] = fma(a_s[i], b_s[j], ms[r][i][j]);
-                                    md[r][i][j] = fma(a_d[i], b_d[j], md[r][i][j]);
+                                    ms[r][i][j] = fmr(a_s[i], b_s[j], ms[r][i][j]);
+                                    md[r][i][j] = fmr(a_d[i], b_d[j], md[r][i][j]);
                                 }
                         }
                     }
@@ -586,12 +646,33 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
             }
             wave_lds_sync();
         }
+        if constexpr (kComp) {
+            sum_s.add(acc_s);
+            sum_d.add(acc_d);
+            acc_s = acc_d = R(0);
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        cms[r][i][j].add(ms[r][i][j]);
+                        cmd[r][i][j].add(md[r][i][j]);
+                        ms[r][i][j] = R(0);
+                        md[r][i][j] = R(0);
+                    }
+        }
     }
 
     // the matrix strain by strain (reusing the work area), contracted with
     // the tabulated (ka, kb, count) terms of every output pair; lanes (g, p)
     // take every G-th term of pair p
     wave_lds_sync();
+    if constexpr (!kComp) {
+        sum_s.s = acc_s;
+        sum_d.s = acc_d;
+    }
+    double tot_s = sum_s.value(), tot_d = sum_d.value();
     for (int strain = 0; strain < 2; ++strain) {
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
@@ -603,7 +684,10 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int ka = ka0 + i, kb = kb0 + j;
-                        if (ka < ns && kb < ns) mat[ka * ns + kb] = strain == 0 ? ms[r][i][j] : md[r][i][j];
+                        double v;
+                        if constexpr (kComp) v = strain == 0 ? cms[r][i][j].value() : cmd[r][i][j].value();
+                        else v = strain == 0 ? (double)ms[r][i][j] : (double)md[r][i][j];
+                        if (ka < ns && kb < ns) mat[ka * ns + kb] = v;
                     }
             }
         }
@@ -614,13 +698,13 @@ k_vertex_t(FlowArgs A, const double2* __restrict__ gv, int n_triples, double* __
                 const int tq = sh.terms[q];
                 acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
             }
-            if (strain == 0) acc_s = fma(-2.0, acc, acc_s);
-            else acc_d = fma(-2.0, acc, acc_d);
+            if (strain == 0) tot_s = fma(-2.0, acc, tot_s);
+            else tot_d = fma(-2.0, acc, tot_d);
         }
         wave_lds_sync();
     }
     const long vsz = (long)n_triples * ns;
-    finish_pairs(red, lane, ns, G, act, acc_s, acc_d, 0.0, 0.0, dx + A.nf + T.out * ns,
+    finish_pairs(red, lane, ns, G, act, tot_s, tot_d, 0.0, 0.0, dx + A.nf + T.out * ns,
                  dx + A.nf + vsz + T.out * ns, true);
 }
 

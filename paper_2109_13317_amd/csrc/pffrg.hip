@@ -69,7 +69,8 @@ struct pffrg_ctx {
     // scratch
     int* tab_n = nullptr;
     double *tab_w = nullptr, *tab_g = nullptr, *dsig = nullptr;
-    double2* gv = nullptr;          // packed (Gs, Gd) copy of the state's vertex
+    void* gv = nullptr;             // packed (Gs, Gd) copy of the state's vertex:
+                                    // double2, or float2 in FP32 mode
     double* k[kNumK] = {};
     double *ybuf = nullptr, *ebuf = nullptr;
     double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
@@ -159,65 +160,58 @@ void prof_mark(pffrg_ctx* c, int id, bool after) {
 }
 
 // LDS of the t-channel launch (shared tables + 4 waves) for ns pairs.
+template <class R>
 size_t t_lds_bytes(int nf, int ns, int n_terms) {
     const int nsp = (ns + 3) & ~3;
     const int nb = ((nsp / 2) * (nsp / 4) + kWave - 1) / kWave;
-    const WaveLds L{ns, nb == 1 ? kSub : kSub / 2};
+    const WaveLds<R> L{ns, nb == 1 ? kSub : kSub / 2};
     return SharedLds{nf, ns, n_terms}.bytes(true) + kWavesPerBlock * L.bytes();
+}
+
+size_t t_lds_bytes(int nf, int ns, int n_terms, pffrg_precision prec) {
+    return prec == PFFRG_FP32 ? t_lds_bytes<float>(nf, ns, n_terms) : t_lds_bytes<double>(nf, ns, n_terms);
 }
 
 // ------------------------------------------------------------ one RHS ---
 
-pffrg_status pack(pffrg_ctx* c, const double* x) {
-    hipLaunchKernelGGL(k_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf,
-                       x + c->nf + c->vsz, c->gv);
-    return launch_check("k_pack");
-}
-
-pffrg_status sigma_rhs_packed(pffrg_ctx* c, double lam, const double* x, double* dsig) {
+pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
     FlowArgs A = c->args();
     prof_mark(c, PFFRG_K_SIGMA, false);
-    hipLaunchKernelGGL(k_sigma_rhs, dim3(c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double2*)c->gv,
-                       (long)c->vsz, dsig);
+    hipLaunchKernelGGL(k_sigma_rhs, dim3(c->nf), dim3(kWave), 0, c->stream, A, lam, x, (long)c->vsz, dsig);
     prof_mark(c, PFFRG_K_SIGMA, true);
     return launch_check("k_sigma_rhs");
 }
 
-pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
-    TRY(pack(c, x));
-    return sigma_rhs_packed(c, lam, x, dsig);
-}
-
-pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
-    if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+// The vertex right-hand side in precision R: pack the state's vertex into
+// c->gv, then the three channel launches (s writes dGamma, u and t add).
+template <class R>
+pffrg_status vertex_rhs(pffrg_ctx* c, const double* x, double* dx) {
     FlowArgs A = c->args();
-    TRY(pack(c, x));
-    TRY(sigma_rhs_packed(c, lam, x, dx));          // the sigma part of dx is dsig
-    prof_mark(c, PFFRG_K_TABLES, false);
-    hipLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)dx);
-    prof_mark(c, PFFRG_K_TABLES, true);
-    TRY(launch_check("k_node_tables"));
+    V2<R>* gv = static_cast<V2<R>*>(c->gv);
+    hipLaunchKernelGGL(k_pack<R>, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf,
+                       x + c->nf + c->vsz, gv);
+    TRY(launch_check("k_pack"));
     const int T = c->nsu * c->nf;
     const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per = (blocks + 7) / 8;
     const SharedLds S{c->nf, c->ns, c->n_terms};
-    const WaveLds Lsu{c->ns};
+    const WaveLds<R> Lsu{c->ns};
     const size_t lds_su = S.bytes(false) + kWavesPerBlock * Lsu.su_bytes();
     const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
     prof_mark(c, PFFRG_K_VERTEX, false);
     prof_mark(c, PFFRG_K_VERTEX_S, false);
-    hipLaunchKernelGGL(k_vertex_su<0>, grid, block, lds_su, c->stream, A, (const double2*)c->gv,
+    hipLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, c->stream, A, (const V2<R>*)gv,
                        (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
     prof_mark(c, PFFRG_K_VERTEX_S, true);
     prof_mark(c, PFFRG_K_VERTEX_U, false);
-    hipLaunchKernelGGL(k_vertex_su<2>, grid, block, lds_su, c->stream, A, (const double2*)c->gv,
+    hipLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, c->stream, A, (const V2<R>*)gv,
                        (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
     prof_mark(c, PFFRG_K_VERTEX_U, true);
-    const size_t lds_t = t_lds_bytes(c->nf, c->ns, c->n_terms);
+    const size_t lds_t = t_lds_bytes<R>(c->nf, c->ns, c->n_terms);
     prof_mark(c, PFFRG_K_VERTEX_T, false);
     switch ((c->ns + 3) / 4) {
 #define PFFRG_T_CASE(K) \
-        case K: hipLaunchKernelGGL(k_vertex_t<4 * K>, grid, block, lds_t, c->stream, A, (const double2*)c->gv, T, dx); break;
+        case K: hipLaunchKernelGGL((k_vertex_t<4 * K, R>), grid, block, lds_t, c->stream, A, (const V2<R>*)gv, T, dx); break;
         PFFRG_T_CASE(1) PFFRG_T_CASE(2) PFFRG_T_CASE(3) PFFRG_T_CASE(4)
         PFFRG_T_CASE(5) PFFRG_T_CASE(6) PFFRG_T_CASE(7) PFFRG_T_CASE(8)
 #undef PFFRG_T_CASE
@@ -226,6 +220,17 @@ pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     prof_mark(c, PFFRG_K_VERTEX_T, true);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_vertex_t");
+}
+
+pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
+    if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    FlowArgs A = c->args();
+    TRY(sigma_rhs(c, lam, x, dx));                  // the sigma part of dx is dsig
+    prof_mark(c, PFFRG_K_TABLES, false);
+    hipLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)dx);
+    prof_mark(c, PFFRG_K_TABLES, true);
+    TRY(launch_check("k_node_tables"));
+    return c->prec == PFFRG_FP32 ? vertex_rhs<float>(c, x, dx) : vertex_rhs<double>(c, x, dx);
 }
 
 // max-norm error / finiteness readback (synchronises the stream)
@@ -387,7 +392,7 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         return fail(PFFRG_EINVAL, "lattice tables incomplete");
     if (ns > kMaxPairs)
         return fail(PFFRG_EUNSUPPORTED, "more than 32 reduced pairs is not supported by this kernel build");
-    if (prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "only PFFRG_FP64 is available in this build");
+    if (prec != PFFRG_FP64 && prec != PFFRG_FP32) return fail(PFFRG_EINVAL, "unknown precision");
     if (lat->swap[0] != 0) return fail(PFFRG_EINVAL, "pair 0 must be the on-site pair (swap[0] == 0)");
     const int nterms = lat->rpa_off[ns];
     if (lat->rpa_off[0] != 0 || nterms < 0) return fail(PFFRG_EINVAL, "bad rpa_off");
@@ -463,7 +468,11 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->tab_w, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->tab_g, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->dsig, (size_t)nf));
-        TRY(dev_alloc(c, &c->gv, (size_t)c->vsz));
+        {
+            double2* g2 = nullptr;      // large enough for either precision
+            TRY(dev_alloc(c, &g2, (size_t)c->vsz));
+            c->gv = g2;
+        }
         for (int j = 0; j < kNumK; ++j) TRY(dev_alloc(c, &c->k[j], (size_t)c->size));
         TRY(dev_alloc(c, &c->ybuf, (size_t)c->size));
         TRY(dev_alloc(c, &c->ebuf, (size_t)c->size));
@@ -476,7 +485,7 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->red, 2));
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
         if (nf > kMaxFreq) return fail(PFFRG_EUNSUPPORTED, "more than 128 frequencies is not supported");
-        if (t_lds_bytes(nf, ns, nterms) > 64 * 1024)
+        if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
         return PFFRG_OK;
     };

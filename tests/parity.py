@@ -88,3 +88,19 @@ def compare_chi(orc, tables, zz, dd, chi_red: np.ndarray) -> float:
                   np.abs(dd[b, :n] - chi_red[1, pmap[b, :n]]).max())
         scale = max(scale, np.abs(zz[b, :n]).max(), np.abs(dd[b, :n]).max())
     return float(err / scale)
+
+
+def compare_parts(orc, tables, ref: np.ndarray, red: np.ndarray) -> tuple[float, float]:
+    """(sigma error / max |sigma|, vertex error / max |vertex|): the two parts
+    of a state or derivative measured on their own scales."""
+    pmap = pair_map(orc, tables)
+    nf, ns = orc.nf, tables.n_pairs
+    sig, gs, gd = _reduced_views(np.asarray(red), nf, ns)
+    rsig, rgs, rgd = orc.split(ref)
+    es = np.abs(rsig - sig).max() / max(np.abs(rsig).max(), 1e-300)
+    ev, scale = 0.0, max(np.abs(rgs).max(), np.abs(rgd).max(), 1e-300)
+    for b in range(orc.lat.nb):
+        n = orc.lat.nsites[b]
+        ev = max(ev, np.abs(rgs[b, :, :, :n] - gs[:, :, pmap[b, :n]]).max(),
+                 np.abs(rgd[b, :, :, :n] - gd[:, :, pmap[b, :n]]).max())
+    return float(es), float(ev / scale)
