@@ -201,6 +201,79 @@ enum {
 pffrg_status pffrg_set_profiling(pffrg_ctx *ctx, int on);
 pffrg_status pffrg_profile_read(pffrg_ctx *ctx, int kernel, double *total_ms, int *count);
 
+/* ------------------------------------------------------------ batches -- */
+
+/*
+ * A batch advances n_points independent flows on one frequency mesh in
+ * lockstep: the scans over couplings and lattice ranges with which phase
+ * diagrams are mapped (Sec. 6.1, which also suggests reduced precision for
+ * such scans).  Each point has its own lattice (at most 20 reduced pairs in
+ * this kernel build) and flow state; mesh, precision and the RK4 cutoff
+ * schedule are shared.  Per point the arithmetic is that of pffrg_rhs /
+ * pffrg_step; the batch runs the self-energy flow, the quadrature tables and
+ * the vertex flow of all points as single launches (the vertex one a
+ * persistent kernel over a list of tiles of output triples) and can replay
+ * one RK4 step as a hipGraph.
+ *
+ * Batch state: the points' states (single-flow layout) back to back; point
+ * p starts at offsets[p] (in doubles) and offsets[n_points] is the total
+ * size.  chi of a batch: the points' [2][Ns_p] arrays back to back.
+ */
+typedef struct pffrg_batch pffrg_batch;
+
+/* lats[p] as for pffrg_create (host arrays, copied).  Errors as for
+ * pffrg_create; a point with more than 20 pairs gives PFFRG_EUNSUPPORTED. */
+pffrg_status pffrg_batch_create(int n_points, const pffrg_lattice *const *lats, const pffrg_mesh *mesh,
+                                pffrg_precision prec, void *stream, pffrg_batch **out);
+pffrg_status pffrg_batch_destroy(pffrg_batch *batch);
+
+/* offsets[n_points + 1] (host) as described above. */
+pffrg_status pffrg_batch_state_offsets(const pffrg_batch *batch, size_t *offsets);
+
+/* Initial condition of every point (as pffrg_init_state). */
+pffrg_status pffrg_batch_init_state(pffrg_batch *batch, double *d_state);
+
+/* d_dstate = d state / d Lambda of every point at cutoff lambda > 0 (as
+ * pffrg_rhs, Eq. 23 and Eq. 24).  d_state and d_dstate must not overlap. */
+pffrg_status pffrg_batch_rhs(pffrg_batch *batch, double lambda, const double *d_state, double *d_dstate);
+
+/* Classical RK4 (as pffrg_step with PFFRG_RK4) from lambdas[0] through
+ * lambdas[n_lambda-1] (host array, 2 <= n_lambda <= 65536, all finite and
+ * > 0) for every point, in place.  use_graph != 0 captures one step into a
+ * hipGraph (once per state pointer and launch shape) and replays it; the
+ * results are identical to use_graph == 0.  No observer runs; if
+ * point_finite (host, [n_points]) is not NULL the call synchronises and
+ * writes 1 for every point whose final state is finite, else 0 (points are
+ * independent: a diverging point does not affect the others). */
+pffrg_status pffrg_batch_flow(pffrg_batch *batch, int n_lambda, const double *lambdas, double *d_state,
+                              int use_graph, int *point_finite);
+
+/* chi per pair of every point (as pffrg_chi, Eq. 30), concatenated. */
+pffrg_status pffrg_batch_chi(pffrg_batch *batch, double lambda, const double *d_state, double *d_chi);
+
+/* chi(k) of point `point` (as pffrg_chi_k, Eq. 31) from its chi block. */
+pffrg_status pffrg_batch_chi_k(pffrg_batch *batch, int point, const double *d_chi_point, int n_k,
+                               const double *d_k, double *d_chi_k);
+
+/* Launch shape of the persistent vertex kernel: `per` workgroups per XCD,
+ * the tile order (0: each point's tiles on one XCD, chosen so the XCDs
+ * carry equal estimated cost; 1: tiles dealt round-robin over the XCDs) and
+ * split (0: one launch computes all three channels; 1: one launch for the s
+ * and u channels, a second for the t channel, each with fewer registers).
+ * pffrg_batch_tune times every candidate (per in 32, 64, 96, 128; both
+ * orders; both splits) on three right-hand sides at (lambda, d_state),
+ * keeps the fastest and caches it for the process under (n_freq, pair
+ * counts, precision); a later batch with the same key starts with it.
+ * Outputs may be NULL.  The shape never changes results. */
+pffrg_status pffrg_batch_tune(pffrg_batch *batch, double lambda, const double *d_state, int *per, int *order,
+                              int *split);
+pffrg_status pffrg_batch_set_launch(pffrg_batch *batch, int per, int order, int split);
+
+/* HIP-event timing of the vertex launch of direct (non-graph) batch right-
+ * hand sides, as pffrg_set_profiling / pffrg_profile_read. */
+pffrg_status pffrg_batch_set_profiling(pffrg_batch *batch, int on);
+pffrg_status pffrg_batch_profile_read(pffrg_batch *batch, double *total_ms, int *count);
+
 /* -------------------------------------------------------------- errors -- */
 
 const char *pffrg_last_error(void);

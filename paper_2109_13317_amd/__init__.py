@@ -2,18 +2,19 @@
 
 The flow right-hand side, Runge-Kutta steps and correlations run in HIP
 kernels behind the C ABI of include/pffrg.h (libpffrg.so, built in this
-directory).  This package holds the Python binding (``flow.Context``), the
+directory).  This package holds the Python binding (``flow.Context`` for one flow,
+``flow.Batch`` for many flows in lockstep), the
 lattice front end that produces the ABI's symmetry-reduced tables
 (``lattice.build_tables``) and the build script.
 """
 
 from .lattice import LatticeTables, build_tables
 
-__all__ = ["LatticeTables", "build_tables", "Context"]
+__all__ = ["LatticeTables", "build_tables", "Context", "Batch"]
 
 
 def __getattr__(name):
-    if name == "Context":
-        from .flow import Context
-        return Context
+    if name in ("Context", "Batch"):
+        from . import flow
+        return getattr(flow, name)
     raise AttributeError(name)

@@ -54,6 +54,19 @@ SIGNATURES = {
     "pffrg_chi_k": [P, P, I, P, P],
     "pffrg_set_profiling": [P, I],
     "pffrg_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(I)],
+    "pffrg_batch_create": [I, ctypes.POINTER(ctypes.POINTER(Lattice)), ctypes.POINTER(Mesh), I, P,
+                           ctypes.POINTER(P)],
+    "pffrg_batch_destroy": [P],
+    "pffrg_batch_state_offsets": [P, ctypes.POINTER(ctypes.c_size_t)],
+    "pffrg_batch_init_state": [P, P],
+    "pffrg_batch_rhs": [P, D, P, P],
+    "pffrg_batch_flow": [P, I, P, P, I, ctypes.POINTER(I)],
+    "pffrg_batch_chi": [P, D, P, P],
+    "pffrg_batch_chi_k": [P, I, P, I, P, P],
+    "pffrg_batch_tune": [P, D, P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
+    "pffrg_batch_set_launch": [P, I, I, I],
+    "pffrg_batch_set_profiling": [P, I],
+    "pffrg_batch_profile_read": [P, ctypes.POINTER(D), ctypes.POINTER(I)],
 }
 
 K_SIGMA, K_TABLES, K_VERTEX, K_VERTEX_S, K_VERTEX_U, K_VERTEX_T = 0, 1, 2, 3, 4, 5

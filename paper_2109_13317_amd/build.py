@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "pffrg.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("pffrg.hip", "pffrg_batch.hip")]
 LIB = os.path.join(HERE, "libpffrg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -23,7 +23,7 @@ FLAGS = [
 def build(verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           "-o", tmp, SRC]
+           "-o", tmp, *SRCS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

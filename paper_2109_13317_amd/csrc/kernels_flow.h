@@ -130,9 +130,8 @@ struct CompSum {
 
 // d sig/d Lambda (w_n) = (1/2pi) sum_{x=+-Lambda} F(w_n, x) / (x - sig(x)),
 // F = 2 sum_r mult_r Gd_r(w+x, 0, w-x) - 3 Gs_0(w+x, x-w, 0) - Gd_0(w+x, x-w, 0).
-__global__ void __launch_bounds__(kWave)
-k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, long nv, double* __restrict__ dsig) {
-    const int n = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void sigma_body(const FlowArgs& A, double lam, const double* __restrict__ x, long nv,
+                                           double* __restrict__ dsig, int n, int lane) {
     const double wn = A.w[n];
     const double* gs = x + A.nf;
     const double* gd = gs + nv;
@@ -158,8 +157,13 @@ k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, long nv, doubl
     if (lane == 0) dsig[n] = acc * kInvTwoPi;
 }
 
+static __global__ void __launch_bounds__(kWave)
+k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, long nv, double* __restrict__ dsig) {
+    sigma_body(A, lam, x, nv, dsig, blockIdx.x, threadIdx.x);
+}
+
 template <class R>
-__global__ void k_pack(long n, const double* __restrict__ gs, const double* __restrict__ gd,
+static __global__ void k_pack(long n, const double* __restrict__ gs, const double* __restrict__ gd,
                        V2<R>* __restrict__ gv) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         V2<R> v;
@@ -192,9 +196,8 @@ __device__ __forceinline__ double full_mesh(const double* __restrict__ w, int nf
 // every piece of D = [-wmax, wmax] \ (-lam, lam) \ (c - lam, c + lam) (c = zero
 // of the partner) its ends and the mesh points strictly inside, with
 // trapezoid weight times the Katanin bubble.
-__global__ void __launch_bounds__(kWave)
-k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double* __restrict__ dsig) {
-    const int id = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void tables_body(const FlowArgs& A, double lam, const double* __restrict__ x,
+                                            const double* __restrict__ dsig, int id, int lane) {
     const int nf = A.nf;
     const int ch = id / nf, iv = id % nf;
     const double nu = A.w[iv];
@@ -271,6 +274,11 @@ k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double
     if (lane == 0) A.tab_n[id] = n;
 }
 
+static __global__ void __launch_bounds__(kWave)
+k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double* __restrict__ dsig) {
+    tables_body(A, lam, x, dsig, blockIdx.x, threadIdx.x);
+}
+
 // ------------------------------------------------------------- vertex RHS -
 //
 // The vertex right-hand side is three launches, one per channel, each with
@@ -308,14 +316,22 @@ struct Shared {
     const int* terms;
 };
 
-// Fill the shared tables (workgroup-wide; before any wave leaves).
-__device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
+// Pointers to the shared tables in LDS (no memory traffic).
+__device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* lds) {
     const SharedLds S{A.nf, A.ns, A.n_terms};
-    double* w = reinterpret_cast<double*>(lds + S.mesh());
-    double* ih = reinterpret_cast<double*>(lds + S.ih());
-    int* sw = reinterpret_cast<int*>(lds + S.swap());
-    int* off = reinterpret_cast<int*>(lds + S.off());
-    int* terms = reinterpret_cast<int*>(lds + S.terms());
+    return Shared{reinterpret_cast<double*>(lds + S.mesh()), reinterpret_cast<double*>(lds + S.ih()),
+                  reinterpret_cast<int*>(lds + S.swap()), reinterpret_cast<int*>(lds + S.off()),
+                  reinterpret_cast<int*>(lds + S.terms())};
+}
+
+// Fill the shared tables (workgroup-wide; before any wave leaves).
+__device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
+    const Shared sh = shared_ptrs(A, lds);
+    double* w = const_cast<double*>(sh.w);
+    double* ih = const_cast<double*>(sh.ih);
+    int* sw = const_cast<int*>(sh.swap);
+    int* off = const_cast<int*>(sh.off);
+    int* terms = const_cast<int*>(sh.terms);
     for (int i = threadIdx.x; i < A.nf; i += blockDim.x) {
         w[i] = A.w[i];
         ih[i] = i + 1 < A.nf ? 1.0 / (A.w[i + 1] - A.w[i]) : 0.0;
@@ -326,7 +342,11 @@ __device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* 
         for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
     }
     __syncthreads();
-    return Shared{w, ih, sw, off, terms};
+}
+
+__device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
+    fill_shared(A, lds, with_terms);
+    return shared_ptrs(A, lds);
 }
 
 // Per-wave LDS of the t-channel kernel, in bytes (R: the vertex precision).
@@ -357,7 +377,9 @@ struct WaveLds {
 __device__ __forceinline__ int xcd_order(int n_triples) {
     const int per = gridDim.x / 8;
     const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
-    const int o = (xcd * per + slot) * kWavesPerBlock + threadIdx.x / kWave;
+    // the same for every lane of the wave: keep it (and all that derives
+    // from it) in scalar registers
+    const int o = __builtin_amdgcn_readfirstlane((xcd * per + slot) * kWavesPerBlock + (int)threadIdx.x / kWave);
     return o < n_triples ? o : -1;
 }
 
@@ -398,38 +420,28 @@ __device__ __forceinline__ void finish_pairs(double* red, int lane, int ns, int 
     }
 }
 
+// The per-lane result of one channel body: lanes (g, p) hold partial sums
+// for pair p that finish_pairs adds up over the groups g.
+struct LanePart {
+    double s, d;
+};
+
 // s channel (CH = 0): A = Gamma(s, w1'-w, w-w2'), B = Gamma(s, w-w1, w-w2),
 //   dGs += W (-2 As Bs + As Bd + Ad Bs), dGd += W (3 As Bs + Ad Bd).
 // u channel (CH = 2): A = Gamma(w1+w, w-w2', u), B = Gamma(w1'+w, w2-w, u),
 //   dGs += W (2 As Bs + As Bd + Ad Bs), dGd += W (3 As Bs + Ad Bd).
-// Order: s channel by (s, u, t) wedge order; u channel by (u, s, t) using
-// the u-major wedge tables uo_a / uo_c.  R: precision of the interpolation,
-// products and per-chunk sums (the chunk sums are folded by CompSum).
+// R: precision of the interpolation, products and per-chunk sums (the chunk
+// sums are folded by CompSum).  A.w must point at the LDS mesh copy; plan is
+// the wave's LDS plan area.
 template <int CH, class R>
-__global__ void __launch_bounds__(kWave * kWavesPerBlock)
-k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo_a,
-            const int* __restrict__ uo_c, int n_triples, double* __restrict__ dx) {
-    extern __shared__ __align__(32) unsigned char lds_raw[];
+__device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh, PlanT<R>* plan,
+                                            const Triple& T, __amdgpu_buffer_rsrc_t rv, int lane) {
     const int nf = A.nf, ns = A.ns, nq = A.nq;
-    const Shared sh = load_shared(A, lds_raw, false);
-    A.w = sh.w;
-    const WaveLds<R> L{ns};
-    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * L.su_bytes();
-    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);
-    double* red = reinterpret_cast<double*>(base + L.su_bytes() - L.red());
-    const int o = xcd_order(n_triples);
-    if (o < 0) return;
-    const int q = o / nf, it = o % nf;
-    const int ia = CH == 0 ? A.su_a[q] : uo_a[q];
-    const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
-    const Triple T = make_triple(A.w, nf, ia, it, ic);
-
+    const int ia = T.ia, ic = T.ic;
     const int G = kWave / ns;
     const int g = lane / ns, p = lane % ns;
     const bool act = g < G;
     const int2 pp = make_int2(kElemBytes<R> * p, kElemBytes<R> * sh.swap[p]);
-    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
     CompSum<R> sum_s, sum_d;
     const int iv = CH == 0 ? ia : ic;
     const int cnt = A.tab_n[CH * nf + iv];
@@ -491,12 +503,38 @@ k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo
         sum_s.s = acc_s;
         sum_d.s = acc_d;
     }
-    const long vsz = (long)n_triples * ns;
-    finish_pairs(red, lane, ns, G, act, sum_s.value(), sum_d.value(), 0.0, 0.0, dx + A.nf + T.out * ns,
-                 dx + A.nf + vsz + T.out * ns, CH != 0);
+    return LanePart{act ? sum_s.value() : 0.0, act ? sum_d.value() : 0.0};
 }
 
-// t channel, ordered by (t, s, u):
+// One context: the s channel by (s, u, t) wedge order, the u channel by
+// (u, s, t) using the u-major wedge tables uo_a / uo_c; s writes, u adds.
+template <int CH, class R>
+static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
+k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo_a,
+            const int* __restrict__ uo_c, int n_triples, double* __restrict__ dx) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns;
+    const Shared sh = load_shared(A, lds_raw, false);
+    A.w = sh.w;
+    const WaveLds<R> L{ns};
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * L.su_bytes();
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);
+    double* red = reinterpret_cast<double*>(base + L.su_bytes() - L.red());
+    const int o = xcd_order(n_triples);
+    if (o < 0) return;
+    const int q = o / nf, it = o % nf;
+    const int ia = CH == 0 ? A.su_a[q] : uo_a[q];
+    const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
+    const Triple T = make_triple(A.w, nf, ia, it, ic);
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
+    const LanePart r = su_body<CH, R>(A, sh, plan, T, rv, lane);
+    const long vsz = (long)n_triples * ns;
+    finish_pairs(red, lane, ns, kWave / ns, lane / ns < kWave / ns, r.s, r.d, 0.0, 0.0,
+                 dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, CH != 0);
+}
+
+// t channel:
 //   RPA:  -sum_j Gamma_{i1 j}(w1+w, t, w1'-w) Gamma_{j i2}(w+w2', t, w-w2)
 //   corr: Gamma_{i1i2}(w1+w, t, w1'-w) Gamma_{i2i2}(w2'+w, w2-w, -t)
 //       + Gamma_{i1i1}(w1+w, w-w1', -t) Gamma_{i1i2}(w+w2', t, w-w2)
@@ -512,34 +550,23 @@ struct TShape {
     static constexpr int SUB = NB == 1 ? kSub : kSub / 2;
 };
 
+// base: the wave's LDS area (layout WaveLds<R>{ns, SUB}); sh.off / sh.terms
+// must hold the lattice-sum tables.
 template <int NSP, class R>
-__global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(TShape<NSP>::NB == 1 && sizeof(R) == 8 ? 4 : 3)))
-k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+__device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, unsigned char* base,
+                                           const Triple& T, __amdgpu_buffer_rsrc_t rv, int lane) {
     constexpr int NB = TShape<NSP>::NB;
     constexpr int SUB = TShape<NSP>::SUB;
     constexpr int NBK = NSP / 4;
     constexpr bool kComp = sizeof(R) == 4;
-    extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
-    const Shared sh = load_shared(A, lds_raw, true);
-    A.w = sh.w;
     const WaveLds<R> L{ns, SUB};
-    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L.bytes();
     PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                           // [2][kPlanChunk]
     R* ons = reinterpret_cast<R*>(base + L.plans());                                // [4][kPlanChunk]
     R* vb = reinterpret_cast<R*>(base + L.plans() + L.onsite());                    // [4][SUB][NSP]
     double* mat = reinterpret_cast<double*>(base);                                  // [ns*ns] at the end
-    double* red = reinterpret_cast<double*>(base + L.mat());                        // [2][64] at the end
-    const int o = xcd_order(n_triples);
-    if (o < 0) return;
-    const int nsu = nf * (nf + 1) / 2;
-    const int it = o / nsu, su = o % nsu;
-    const int ia = A.su_a[su], ic = A.su_c[su];
-    const Triple T = make_triple(A.w, nf, ia, it, ic);
+    const int it = T.it;
     const double t = T.t;
-    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
 
     const int G = kWave / ns;
     const int g = lane / ns, p = lane % ns;
@@ -703,9 +730,32 @@ k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __re
         }
         wave_lds_sync();
     }
+    return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
+}
+
+// One context, ordered by (t, s, u); adds to dGamma.
+template <int NSP, class R>
+static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(3)))
+k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns;
+    const Shared sh = load_shared(A, lds_raw, true);
+    A.w = sh.w;
+    const WaveLds<R> L{ns, TShape<NSP>::SUB};
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L.bytes();
+    double* red = reinterpret_cast<double*>(base + L.mat());                        // [2][64] at the end
+    const int o = xcd_order(n_triples);
+    if (o < 0) return;
+    const int nsu = nf * (nf + 1) / 2;
+    const int it = o / nsu, su = o % nsu;
+    const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
+    const LanePart r = t_body<NSP, R>(A, sh, base, T, rv, lane);
     const long vsz = (long)n_triples * ns;
-    finish_pairs(red, lane, ns, G, act, tot_s, tot_d, 0.0, 0.0, dx + A.nf + T.out * ns,
-                 dx + A.nf + vsz + T.out * ns, true);
+    finish_pairs(red, lane, ns, kWave / ns, lane / ns < kWave / ns, r.s, r.d, 0.0, 0.0,
+                 dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, true);
 }
 
 }  // namespace pffrg

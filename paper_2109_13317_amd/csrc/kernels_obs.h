@@ -15,7 +15,7 @@
 namespace pffrg {
 
 // One thread: nodes, trapezoid weights and g^2 of the correlation integrals.
-__global__ void k_chi_nodes(const double* __restrict__ w, int nf, double lam,
+static __global__ void k_chi_nodes(const double* __restrict__ w, int nf, double lam,
                             const double* __restrict__ x, double* __restrict__ cw,
                             double* __restrict__ cq, double* __restrict__ cg2, int* __restrict__ cn) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
@@ -46,7 +46,7 @@ __global__ void k_chi_nodes(const double* __restrict__ w, int nf, double lam,
 constexpr int kChiThreads = 256;
 
 // One workgroup per pair p: chi^{zz}_p, chi^{00}_p into chi[p], chi[ns + p].
-__global__ void __launch_bounds__(kChiThreads)
+static __global__ void __launch_bounds__(kChiThreads)
 k_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restrict__ swap,
             const double* __restrict__ x, const double* __restrict__ cw,
             const double* __restrict__ cq, const double* __restrict__ cg2,
@@ -100,7 +100,7 @@ k_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restrict_
 }
 
 // chi(k_q) = (1/nb) sum_{b, j} cos(k_q . dr_bj) 3 chi^{zz}_{pair(b,j)}
-__global__ void k_chi_k(int nterm, const int* __restrict__ pair, const double* __restrict__ dr,
+static __global__ void k_chi_k(int nterm, const int* __restrict__ pair, const double* __restrict__ dr,
                         double inv_nb, const double* __restrict__ chi, int nk,
                         const double* __restrict__ kp, double* __restrict__ out) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,7 +117,7 @@ __global__ void k_chi_k(int nterm, const int* __restrict__ pair, const double* _
 // ------------------------------------------------------- Runge-Kutta ----
 
 // y = x + a*k  and  acc = (init ? x : acc) + b*k, one pass over the state.
-__global__ void k_rk_stage(long n, const double* __restrict__ x, const double* __restrict__ k,
+static __global__ void k_rk_stage(long n, const double* __restrict__ x, const double* __restrict__ k,
                            double a, double* __restrict__ y, double b, double* __restrict__ acc,
                            int init) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -134,7 +134,7 @@ struct Combo {
     int m;
 };
 
-__global__ void k_combine(long n, const double* __restrict__ x, Combo C, double* __restrict__ y) {
+static __global__ void k_combine(long n, const double* __restrict__ x, Combo C, double* __restrict__ y) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         double v = x ? x[i] : 0.0;
         for (int j = 0; j < C.m; ++j)
@@ -147,7 +147,7 @@ __global__ void k_combine(long n, const double* __restrict__ x, Combo C, double*
 //   part[2b]   = max_i |e_i| / (atol + rtol * max(|x_i|, |y_i|))  (e may be NULL -> 0)
 //   part[2b+1] = 1 if any x_i or y_i is not finite
 constexpr int kRedThreads = 256;
-__global__ void __launch_bounds__(kRedThreads)
+static __global__ void __launch_bounds__(kRedThreads)
 k_err_norm(long n, const double* __restrict__ x, const double* __restrict__ y,
            const double* __restrict__ e, double atol, double rtol, double* __restrict__ part) {
     __shared__ double sm[kRedThreads], sf[kRedThreads];
@@ -174,7 +174,7 @@ k_err_norm(long n, const double* __restrict__ x, const double* __restrict__ y,
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = sm[0]; part[2 * blockIdx.x + 1] = sf[0]; }
 }
 
-__global__ void k_err_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+static __global__ void k_err_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double m = 0.0, bad = 0.0;
     for (int b = 0; b < nb; ++b) { m = fmax(m, part[2 * b]); bad = fmax(bad, part[2 * b + 1]); }
@@ -182,7 +182,7 @@ __global__ void k_err_final(int nb, const double* __restrict__ part, double* __r
     out[1] = bad;
 }
 
-__global__ void k_init_state(long n, int nf, int ns, const double* __restrict__ coupling,
+static __global__ void k_init_state(long n, int nf, int ns, const double* __restrict__ coupling,
                              double* __restrict__ x) {
     const long vsz = (long)nf * (nf + 1) / 2 * nf * ns;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {

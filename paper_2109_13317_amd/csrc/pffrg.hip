@@ -15,32 +15,14 @@
 #include <vector>
 
 #include "pffrg.h"
+#include "host_common.h"
 #include "kernels_flow.h"
 #include "kernels_obs.h"
 
 using namespace pffrg;
+using namespace pffrg_host;
 
 namespace {
-
-thread_local std::string g_err;
-
-pffrg_status fail(pffrg_status s, const std::string& msg) {
-    g_err = msg;
-    return s;
-}
-
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(PFFRG_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
-    } while (0)
-
-#define TRY(expr)                              \
-    do {                                       \
-        pffrg_status s_ = (expr);              \
-        if (s_ != PFFRG_OK) return s_;         \
-    } while (0)
 
 constexpr int kNumK = 7;     // Dormand-Prince stages (RK4 uses the first three)
 constexpr int kRedBlocks = 512;
@@ -129,17 +111,6 @@ void release(pffrg_ctx* c) {
 pffrg_status check_ctx(const pffrg_ctx* c) {
     if (!c) return fail(PFFRG_EINVAL, "null context");
     return PFFRG_OK;
-}
-
-pffrg_status launch_check(const char* what) {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(PFFRG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-    return PFFRG_OK;
-}
-
-int grid_for(long n, int threads) {
-    long b = (n + threads - 1) / threads;
-    return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
 }
 
 // Record an event before/after a launch of kernel `id` while profiling.
@@ -357,6 +328,55 @@ pffrg_status observe(pffrg_ctx* c, const pffrg_flow_opts* o, double lam, const d
 
 }  // namespace
 
+namespace pffrg_host {
+
+pffrg_status check_mesh(const pffrg_mesh* mesh, int max_freq) {
+    if (!mesh) return fail(PFFRG_EINVAL, "mesh is null");
+    const int nf = mesh->n_freq;
+    if (nf < 2 || !mesh->omega) return fail(PFFRG_EINVAL, "mesh needs n_freq >= 2 frequencies");
+    for (int i = 0; i < nf; ++i) {
+        if (!(mesh->omega[i] > 0.0) || !std::isfinite(mesh->omega[i]))
+            return fail(PFFRG_EINVAL, "mesh frequencies must be finite and > 0");
+        if (i > 0 && !(mesh->omega[i] > mesh->omega[i - 1]))
+            return fail(PFFRG_EINVAL, "mesh must be strictly ascending");
+    }
+    if (nf > max_freq) return fail(PFFRG_EUNSUPPORTED, "more than 128 frequencies is not supported");
+    return PFFRG_OK;
+}
+
+pffrg_status check_lattice(const pffrg_lattice* lat, int max_pairs) {
+    if (!lat) return fail(PFFRG_EINVAL, "lattice is null");
+    const int ns = lat->n_pairs;
+    if (ns < 1 || !lat->swap || !lat->mult || !lat->rpa_off || !lat->coupling)
+        return fail(PFFRG_EINVAL, "lattice tables incomplete");
+    if (ns > max_pairs)
+        return fail(PFFRG_EUNSUPPORTED, "more reduced pairs than this kernel build supports (" +
+                                            std::to_string(max_pairs) + ")");
+    if (lat->swap[0] != 0) return fail(PFFRG_EINVAL, "pair 0 must be the on-site pair (swap[0] == 0)");
+    const int nterms = lat->rpa_off[ns];
+    if (lat->rpa_off[0] != 0 || nterms < 0) return fail(PFFRG_EINVAL, "bad rpa_off");
+    for (int p = 0; p < ns; ++p) {
+        if (lat->swap[p] < 0 || lat->swap[p] >= ns) return fail(PFFRG_EINVAL, "swap out of range");
+        if (lat->mult[p] < 1) return fail(PFFRG_EINVAL, "mult must be >= 1");
+        if (lat->rpa_off[p + 1] < lat->rpa_off[p]) return fail(PFFRG_EINVAL, "rpa_off not ascending");
+    }
+    if (nterms > 0 && (!lat->rpa_ka || !lat->rpa_kb || !lat->rpa_cnt))
+        return fail(PFFRG_EINVAL, "lattice-sum terms missing");
+    for (int q = 0; q < nterms; ++q) {
+        if (lat->rpa_ka[q] < 0 || lat->rpa_ka[q] >= ns || lat->rpa_kb[q] < 0 || lat->rpa_kb[q] >= ns)
+            return fail(PFFRG_EINVAL, "rpa term pair out of range");
+        if (lat->rpa_cnt[q] < 1 || lat->rpa_cnt[q] > 32767)
+            return fail(PFFRG_EINVAL, "rpa_cnt out of range [1, 32767]");
+    }
+    if (lat->n_basis < 1 || lat->n_sites_total < 1 || !lat->site_pair || !lat->site_pos || !lat->basis_pos)
+        return fail(PFFRG_EINVAL, "site map incomplete");
+    for (long k = 0; k < (long)lat->n_basis * lat->n_sites_total; ++k)
+        if (lat->site_pair[k] >= ns) return fail(PFFRG_EINVAL, "site_pair out of range");
+    return PFFRG_OK;
+}
+
+}  // namespace pffrg_host
+
 // ====================================================================== ABI
 
 extern "C" {
@@ -379,33 +399,11 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
                           pffrg_ctx** out) {
     if (!out) return fail(PFFRG_EINVAL, "out is null");
     *out = nullptr;
-    if (!lat || !mesh) return fail(PFFRG_EINVAL, "lattice or mesh is null");
-    const int nf = mesh->n_freq, ns = lat->n_pairs;
-    if (nf < 2 || !mesh->omega) return fail(PFFRG_EINVAL, "mesh needs n_freq >= 2 frequencies");
-    for (int i = 0; i < nf; ++i) {
-        if (!(mesh->omega[i] > 0.0) || !std::isfinite(mesh->omega[i]))
-            return fail(PFFRG_EINVAL, "mesh frequencies must be finite and > 0");
-        if (i > 0 && !(mesh->omega[i] > mesh->omega[i - 1]))
-            return fail(PFFRG_EINVAL, "mesh must be strictly ascending");
-    }
-    if (ns < 1 || !lat->swap || !lat->mult || !lat->rpa_off || !lat->coupling)
-        return fail(PFFRG_EINVAL, "lattice tables incomplete");
-    if (ns > kMaxPairs)
-        return fail(PFFRG_EUNSUPPORTED, "more than 32 reduced pairs is not supported by this kernel build");
+    TRY(check_mesh(mesh, kMaxFreq));
+    TRY(check_lattice(lat, kMaxPairs));
     if (prec != PFFRG_FP64 && prec != PFFRG_FP32) return fail(PFFRG_EINVAL, "unknown precision");
-    if (lat->swap[0] != 0) return fail(PFFRG_EINVAL, "pair 0 must be the on-site pair (swap[0] == 0)");
+    const int nf = mesh->n_freq, ns = lat->n_pairs;
     const int nterms = lat->rpa_off[ns];
-    if (lat->rpa_off[0] != 0 || nterms < 0) return fail(PFFRG_EINVAL, "bad rpa_off");
-    for (int p = 0; p < ns; ++p) {
-        if (lat->swap[p] < 0 || lat->swap[p] >= ns) return fail(PFFRG_EINVAL, "swap out of range");
-        if (lat->mult[p] < 1) return fail(PFFRG_EINVAL, "mult must be >= 1");
-        if (lat->rpa_off[p + 1] < lat->rpa_off[p]) return fail(PFFRG_EINVAL, "rpa_off not ascending");
-    }
-    for (int q = 0; q < nterms; ++q)
-        if (lat->rpa_ka[q] < 0 || lat->rpa_ka[q] >= ns || lat->rpa_kb[q] < 0 || lat->rpa_kb[q] >= ns)
-            return fail(PFFRG_EINVAL, "rpa term pair out of range");
-    if (lat->n_basis < 1 || lat->n_sites_total < 1 || !lat->site_pair || !lat->site_pos || !lat->basis_pos)
-        return fail(PFFRG_EINVAL, "site map incomplete");
 
     pffrg_ctx* c = new (std::nothrow) pffrg_ctx;
     if (!c) return fail(PFFRG_ENOMEM, "host allocation failed");
@@ -484,7 +482,6 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->part, (size_t)2 * kRedBlocks));
         TRY(dev_alloc(c, &c->red, 2));
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
-        if (nf > kMaxFreq) return fail(PFFRG_EUNSUPPORTED, "more than 128 frequencies is not supported");
         if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
         return PFFRG_OK;

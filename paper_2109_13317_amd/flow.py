@@ -21,6 +21,20 @@ def _dptr(t: torch.Tensor) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _lattice_struct(t: LatticeTables):
+    """(pffrg_lattice, arrays it points into: keep them alive for the call)."""
+    keep = [np.ascontiguousarray(a, dtype=np.int32) for a in (t.swap, t.mult, t.rpa_off, t.rpa_ka,
+                                                              t.rpa_kb, t.rpa_cnt)]
+    keep += [np.ascontiguousarray(t.coupling, dtype=np.float64),
+             np.ascontiguousarray(t.site_pair, dtype=np.int32),
+             np.ascontiguousarray(t.site_pos, dtype=np.float64),
+             np.ascontiguousarray(t.basis_pos, dtype=np.float64)]
+    ptr = [ctypes.c_void_p(a.ctypes.data) for a in keep]
+    lat = _lib.Lattice(t.n_pairs, ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6],
+                       t.n_basis, t.n_sites_total, ptr[7], ptr[8], ptr[9])
+    return lat, keep
+
+
 class Context:
     """A ``pffrg_ctx``: one lattice model on one frequency mesh."""
 
@@ -30,16 +44,7 @@ class Context:
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.ns = tables.n_pairs
-        t = tables
-        keep = [np.ascontiguousarray(a) for a in (t.swap, t.mult, t.rpa_off, t.rpa_ka, t.rpa_kb,
-                                                  t.rpa_cnt)]
-        keep += [np.ascontiguousarray(t.coupling, dtype=np.float64),
-                 np.ascontiguousarray(t.site_pair, dtype=np.int32),
-                 np.ascontiguousarray(t.site_pos, dtype=np.float64),
-                 np.ascontiguousarray(t.basis_pos, dtype=np.float64)]
-        ptr = [ctypes.c_void_p(a.ctypes.data) for a in keep]
-        lat = _lib.Lattice(t.n_pairs, ptr[0], ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6],
-                           t.n_basis, t.n_sites_total, ptr[7], ptr[8], ptr[9])
+        lat, keep = _lattice_struct(tables)
         msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
         prec = {"fp64": _lib.FP64, "fp32": _lib.FP32}[precision]
         if stream is None:
@@ -163,6 +168,109 @@ class Context:
         _lib.check(self.lib.pffrg_chi_k(self.handle, _dptr(chi.contiguous()), int(kp.shape[0]),
                                         _dptr(kp), _dptr(out)))
         return out
+
+
+class Batch:
+    """A ``pffrg_batch``: many lattice models on one mesh, advanced in lockstep.
+
+    The batch state is one float64 tensor; ``offsets[p]`` is where point p's
+    state (single-flow layout) begins."""
+
+    def __init__(self, tables: list[LatticeTables], mesh, precision: str = "fp32", stream=None):
+        self.lib = _lib.load()
+        self.tables = list(tables)
+        self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
+        self.nf = len(self.mesh)
+        self.n_points = len(self.tables)
+        self.ns = [t.n_pairs for t in self.tables]
+        structs, keep = [], []
+        for t in self.tables:
+            lat, k = _lattice_struct(t)
+            structs.append(lat)
+            keep.append(k)
+        arr = (ctypes.POINTER(_lib.Lattice) * self.n_points)(*[ctypes.pointer(s) for s in structs])
+        msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
+        prec = {"fp64": _lib.FP64, "fp32": _lib.FP32}[precision]
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.pffrg_batch_create(self.n_points, arr, ctypes.byref(msh), prec,
+                                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        off = (ctypes.c_size_t * (self.n_points + 1))()
+        _lib.check(self.lib.pffrg_batch_state_offsets(self.handle, off))
+        self.offsets = [int(v) for v in off]
+        self.size = self.offsets[-1]
+        self.chi_offsets = list(np.concatenate([[0], np.cumsum([2 * n for n in self.ns])]))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _lib.check(self.lib.pffrg_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_state(self) -> torch.Tensor:
+        return torch.empty(self.size, dtype=torch.float64, device="cuda")
+
+    def point(self, x: torch.Tensor, p: int) -> torch.Tensor:
+        """View of point p's state inside a batch state."""
+        return x[self.offsets[p]:self.offsets[p + 1]]
+
+    def init_state(self, x: torch.Tensor | None = None) -> torch.Tensor:
+        x = self.new_state() if x is None else x
+        _lib.check(self.lib.pffrg_batch_init_state(self.handle, _dptr(x)))
+        return x
+
+    def rhs(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.new_state() if out is None else out
+        _lib.check(self.lib.pffrg_batch_rhs(self.handle, float(lam), _dptr(x), _dptr(out)))
+        return out
+
+    def flow(self, x: torch.Tensor, schedule, use_graph: bool = True) -> list[bool]:
+        """Lockstep RK4 along schedule, in place; per-point finiteness."""
+        sched = np.ascontiguousarray(schedule, dtype=np.float64)
+        ok = (ctypes.c_int * self.n_points)()
+        _lib.check(self.lib.pffrg_batch_flow(self.handle, len(sched), ctypes.c_void_p(sched.ctypes.data),
+                                             _dptr(x), int(bool(use_graph)), ok))
+        return [bool(v) for v in ok]
+
+    def chi(self, lam: float, x: torch.Tensor) -> list[torch.Tensor]:
+        """[2, ns_p] per point."""
+        out = torch.empty(int(self.chi_offsets[-1]), dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.pffrg_batch_chi(self.handle, float(lam), _dptr(x), _dptr(out)))
+        return [out[self.chi_offsets[p]:self.chi_offsets[p + 1]].view(2, self.ns[p])
+                for p in range(self.n_points)]
+
+    def chi_k(self, p: int, chi: torch.Tensor, kpoints: torch.Tensor) -> torch.Tensor:
+        kp = kpoints.contiguous()
+        out = torch.empty(kp.shape[0], dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.pffrg_batch_chi_k(self.handle, int(p), _dptr(chi.contiguous().view(-1)),
+                                              int(kp.shape[0]), _dptr(kp), _dptr(out)))
+        return out
+
+    def tune(self, lam: float, x: torch.Tensor) -> tuple[int, int, int]:
+        """Autotune the vertex launch; (workgroups per XCD, tile order, split)."""
+        per, order, split = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _lib.check(self.lib.pffrg_batch_tune(self.handle, float(lam), _dptr(x), ctypes.byref(per),
+                                             ctypes.byref(order), ctypes.byref(split)))
+        return int(per.value), int(order.value), int(split.value)
+
+    def set_launch(self, per: int, order: int, split: int = 0):
+        _lib.check(self.lib.pffrg_batch_set_launch(self.handle, int(per), int(order), int(split)))
+
+    def set_profiling(self, on: bool):
+        _lib.check(self.lib.pffrg_batch_set_profiling(self.handle, int(bool(on))))
+
+    def profile_read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int()
+        _lib.check(self.lib.pffrg_batch_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
 
 
 def _wrap(ptr: int, n: int) -> torch.Tensor:

@@ -147,3 +147,25 @@ def test_lattice_sum_tables_against_brute_force(lattice, params, L):
         # term count: sites within range of both ends
         n_terms = int(t.rpa_cnt[t.rpa_off[p]:t.rpa_off[p + 1]].sum())
         assert n_terms == sum(1 for j in d0 if j in dp), p
+
+
+def test_batch_create_rejects_bad_inputs_before_touching_the_gpu():
+    from paper_2109_13317_amd import _lib
+    from paper_2109_13317_amd.flow import _lattice_struct
+    lib = _lib.load()
+    small = build_tables(W.model("square", j1=1.0), 1)
+    big = build_tables(W.model("pyrochlore", j1=1.0), 5)          # 31 pairs
+    m = np.array([0.1, 1.0, 10.0])
+    msh = _lib.Mesh(3, ctypes.c_void_p(m.ctypes.data))
+    h = ctypes.c_void_p()
+    lat_s, keep_s = _lattice_struct(small)
+    lat_b, keep_b = _lattice_struct(big)
+    arr = (ctypes.POINTER(_lib.Lattice) * 2)(ctypes.pointer(lat_s), ctypes.pointer(lat_b))
+    assert lib.pffrg_batch_create(2, arr, ctypes.byref(msh), _lib.FP32, None, ctypes.byref(h)) == _lib.EUNSUPPORTED
+    assert b"point 1" in lib.pffrg_last_error() and not h.value
+    assert lib.pffrg_batch_create(0, arr, ctypes.byref(msh), _lib.FP32, None, ctypes.byref(h)) == _lib.EINVAL
+    bad = np.array([1.0, 0.5])
+    msh2 = _lib.Mesh(2, ctypes.c_void_p(bad.ctypes.data))
+    assert lib.pffrg_batch_create(1, arr, ctypes.byref(msh2), _lib.FP64, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.pffrg_batch_create(1, arr, ctypes.byref(msh), 7, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.pffrg_batch_rhs(None, 1.0, None, None) == _lib.EINVAL
