@@ -181,6 +181,51 @@ pffrg_status pffrg_chi(pffrg_ctx *ctx, double lambda, const double *d_state, dou
 pffrg_status pffrg_chi_k(pffrg_ctx *ctx, const double *d_chi, int n_k, const double *d_k,
                          double *d_chi_k);
 
+/* -------------------------------------------------------- reverse mode - */
+
+/*
+ * Gradients of observables with respect to the couplings through the whole
+ * flow (reverse mode; FP64 whatever the context's precision).  The flow
+ * equations (Eq. 23, Eq. 24) are differentiated as discretised: the same
+ * mesh, interpolation, quadrature nodes and RK4 stages, so the results are
+ * the exact derivatives of the computed chi up to rounding.
+ */
+
+/* Initial condition (as pffrg_init_state) for the couplings d_coupling[Ns]
+ * (device) instead of the ones given at create. */
+pffrg_status pffrg_init_state_from(pffrg_ctx *ctx, const double *d_coupling, double *d_state);
+
+/* d_cot_state = J^T d_cot_dstate, J = d(pffrg_rhs output)/d(state) at
+ * (lambda, d_state); all three arrays in the state layout, d_cot_state
+ * overwritten and not overlapping the inputs. */
+pffrg_status pffrg_rhs_vjp(pffrg_ctx *ctx, double lambda, const double *d_state, const double *d_cot_dstate,
+                           double *d_cot_state);
+
+/* d_cot_state = (d chi / d state)^T d_cot_chi for chi per pair (Eq. 30) at
+ * (lambda, d_state); d_cot_chi as pffrg_chi's output ([2][Ns]). */
+pffrg_status pffrg_chi_vjp(pffrg_ctx *ctx, double lambda, const double *d_state, const double *d_cot_chi,
+                           double *d_cot_state);
+
+/* d_cot_chi[2*Ns] = (d chi(k) / d chi)^T d_cot_chi_k for the structure
+ * factor of pffrg_chi_k (Eq. 31) at the n_k points d_k. */
+pffrg_status pffrg_chi_k_vjp(pffrg_ctx *ctx, const double *d_cot_chi_k, int n_k, const double *d_k,
+                             double *d_cot_chi);
+
+/* RK4 along lambdas (as pffrg_step per interval), storing the state at the
+ * start of every step: d_checkpoints[(n_lambda-1) * state size] (device,
+ * caller-owned; 120 steps of the honeycomb range-6 workload take 454 MB).
+ * PFFRG_EDIVERGED if the final state is not finite. */
+pffrg_status pffrg_flow_checkpoints(pffrg_ctx *ctx, int n_lambda, const double *lambdas, double *d_state,
+                                    double *d_checkpoints);
+
+/* Discrete adjoint of that flow: on entry d_cot holds the cotangent of the
+ * final state, on return that of the initial state (each step's stages are
+ * recomputed from its checkpoint and transposed).  If d_dcoupling[Ns] is not
+ * NULL it receives the gradient with respect to the couplings of the
+ * initial condition (Gs = coupling / 4, Eq. 21). */
+pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas, const double *d_checkpoints,
+                            double *d_cot, double *d_dcoupling);
+
 /* ----------------------------------------------------------- profiling - */
 
 /* Kernel timing with HIP events recorded on the context's stream around every

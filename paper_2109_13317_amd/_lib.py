@@ -54,6 +54,12 @@ SIGNATURES = {
     "pffrg_chi_k": [P, P, I, P, P],
     "pffrg_set_profiling": [P, I],
     "pffrg_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(I)],
+    "pffrg_init_state_from": [P, P, P],
+    "pffrg_rhs_vjp": [P, D, P, P, P],
+    "pffrg_chi_vjp": [P, D, P, P, P],
+    "pffrg_chi_k_vjp": [P, P, I, P, P],
+    "pffrg_flow_checkpoints": [P, I, P, P, P],
+    "pffrg_flow_vjp": [P, I, P, P, P, P],
     "pffrg_batch_create": [I, ctypes.POINTER(ctypes.POINTER(Lattice)), ctypes.POINTER(Mesh), I, P,
                            ctypes.POINTER(P)],
     "pffrg_batch_destroy": [P],

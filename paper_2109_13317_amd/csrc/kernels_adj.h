@@ -1,0 +1,514 @@
+// kernels_adj.h -- vector-Jacobian products (reverse mode) of the flow
+// right-hand side and of the correlations, in FP64.
+//
+// For a cotangent v of d state / d Lambda (layout of the state) these
+// kernels compute J^T v, where J is the Jacobian of the right-hand side
+// f(Lambda, state) of kernels_flow.h with respect to the state (self-energy
+// and both vertex strains).  The forward pieces are recomputed from the
+// state (self-energy derivative, node tables); then, in reverse order:
+//   1. vertex channels: every evaluation W_k F(A_k, B_k) of an output element
+//      sends v * dF/dA to the four corners of A's interpolation plan and
+//      v * dF/dB to B's (the transpose of the gather: scattered with FP64
+//      atomics), and v * F to the cotangent of the node weight W_k, summed
+//      over the triples and pairs sharing the node list (ctg);
+//      the t-channel lattice sum sum_q cnt_q a[ka_q] b[kb_q] is transposed
+//      through the matrix N = sum_p v(p) C_p of the term counts C_p:
+//      cot a = N b, cot b = N^T a;
+//   2. node tables: ctg through the weights' dependence on the self-energy
+//      (propagators at the nodes) and on its derivative (Katanin term);
+//   3. self-energy flow (Eq. 23): its cotangent (v's own sigma part plus
+//      step 2) through the vertex values and propagators it reads.
+// Every linear interpolation sig(w) = odd_interp(sig, w) is transposed the
+// same way (odd_interp_vjp).
+#pragma once
+
+#include "kernels_flow.h"
+#include "kernels_obs.h"
+
+namespace pffrg {
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Transpose of odd_interp: cot[v_i] += (d value / d v_i) c.
+__device__ __forceinline__ void odd_interp_vjp(const double* __restrict__ w, int nf, double x, double c,
+                                               double* __restrict__ cot) {
+    double sg = 1.0;
+    if (x < 0.0) { x = -x; sg = -1.0; }
+    int i0, i1;
+    double f0, f1;
+    bracket(w, nf, x, i0, i1, f0, f1);
+    if (f0 != 0.0) atomic_add(cot + i0, sg * f0 * c);
+    if (f1 != 0.0) atomic_add(cot + i1, sg * f1 * c);
+}
+
+// Transpose of eval_plan for pair index q (already exchanged): the cotangents
+// (cs, cd) of the spin and density values go to the plan's corners.
+__device__ __forceinline__ void scatter_plan(const Plan& P, double* __restrict__ cgs, double* __restrict__ cgd,
+                                             int q, double cs, double cd) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (P.ws[i] != 0.0) {
+            atomic_add(cgs + P.off[i] + q, P.ws[i] * cs);
+            atomic_add(cgd + P.off[i] + q, P.wd[i] * cd);
+        }
+    }
+}
+
+static __global__ void k_fill(long n, double v, double* __restrict__ p) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Sum of the ns values red[g*ns .. g*ns+ns) of group g (one lane per group
+// calls it).
+__device__ __forceinline__ double group_sum(const double* red, int g, int ns) {
+    double s = 0.0;
+    for (int i = 0; i < ns; ++i) s += red[g * ns + i];
+    return s;
+}
+
+// ----------------------------------------------------------- s, u ------
+
+// One wave per triple (as k_vertex_su).  v: cotangent of the state
+// derivative; cgs/cgd: cotangent of the vertex strains (accumulated);
+// ctg: cotangent of the node weights [3][nf][nq] (accumulated).
+constexpr int kAdjWaves = 4;
+
+struct AdjWaveLds {
+    __host__ __device__ static constexpr size_t plans() { return (size_t)2 * kPlanChunk * sizeof(Plan); }
+    __host__ __device__ static constexpr size_t red() { return (size_t)kWave * sizeof(double); }
+    __host__ __device__ static constexpr size_t bytes() { return ((plans() + red()) + 31) & ~(size_t)31; }
+};
+
+template <int CH>
+static __global__ void __launch_bounds__(kWave * kAdjWaves)
+k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict__ uo_a,
+                const int* __restrict__ uo_c, int n_triples, const double* __restrict__ v,
+                double* __restrict__ cgs, double* __restrict__ cgd, double* __restrict__ ctg) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns, nq = A.nq;
+    const Shared sh = load_shared(A, lds_raw, false);
+    A.w = sh.w;
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * AdjWaveLds::bytes();
+    Plan* plan = reinterpret_cast<Plan*>(base);
+    double* red = reinterpret_cast<double*>(base + AdjWaveLds::plans());
+    const int blocks = gridDim.x;
+    const int per = blocks / 8;
+    const int o = __builtin_amdgcn_readfirstlane(((blockIdx.x % 8) * per + blockIdx.x / 8) * kAdjWaves + wid);
+    if (o >= n_triples) return;
+    const int q = o / nf, it = o % nf;
+    const int ia = CH == 0 ? A.su_a[q] : uo_a[q];
+    const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
+    const Triple T = make_triple(A.w, nf, ia, it, ic);
+    const long vsz = (long)n_triples * ns;
+    const double* gs = x + nf;
+    const double* gd = gs + vsz;
+
+    const int G = kWave / ns;
+    const int g = lane / ns, p = lane % ns;
+    const bool act = g < G;
+    const double vs = act ? v[nf + T.out * ns + p] : 0.0;
+    const double vd = act ? v[nf + vsz + T.out * ns + p] : 0.0;
+    const int iv = CH == 0 ? ia : ic;
+    const int cnt = A.tab_n[CH * nf + iv];
+    const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
+    const double* tg = A.tab_g + (long)(CH * nf + iv) * nq;
+    double* ct = ctg + (long)(CH * nf + iv) * nq;
+    const double sgn = CH == 0 ? -2.0 : 2.0;
+    for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
+        const int kc = min(kPlanChunk, cnt - k0);
+        {
+            const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
+            if (j < kc) {
+                const double om = tw[k0 + j];
+                Plan P;
+                if (CH == 0) {
+                    if (vec == 0) make_plan(A.w, nf, ns, T.s, T.w1p - om, om - T.w2p, 0, ia, P, sh.ih);
+                    else make_plan(A.w, nf, ns, T.s, om - T.w1, om - T.w2, 0, ia, P, sh.ih);
+                } else {
+                    if (vec == 0) make_plan(A.w, nf, ns, T.w1 + om, om - T.w2p, T.u, 2, ic, P, sh.ih);
+                    else make_plan(A.w, nf, ns, T.w1p + om, T.w2 - om, T.u, 2, ic, P, sh.ih);
+                }
+                plan[vec * kPlanChunk + j] = P;
+            }
+        }
+        wave_lds_sync();
+        for (int kb = 0; kb < kc; kb += G) {
+            const int k = kb + g;
+            const bool on = act && k < kc;
+            double cval = 0.0;
+            if (on) {
+                const Plan& Pa = plan[k];
+                const Plan& Pb = plan[kPlanChunk + k];
+                double as, ad, bs, bd;
+                eval_plan(Pa, gs, gd, sh.swap, p, as, ad);
+                eval_plan(Pb, gs, gd, sh.swap, p, bs, bd);
+                const double W = tg[k0 + k];
+                cval = vs * (sgn * as * bs + as * bd + ad * bs) + vd * (3.0 * as * bs + ad * bd);
+                const double cas = W * (vs * (sgn * bs + bd) + vd * 3.0 * bs);
+                const double cad = W * (vs * bs + vd * bd);
+                const double cbs = W * (vs * (sgn * as + ad) + vd * 3.0 * as);
+                const double cbd = W * (vs * as + vd * ad);
+                scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
+                scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
+            }
+            red[lane] = cval;
+            wave_lds_sync();
+            if (on && p == 0) atomic_add(ct + k0 + k, group_sum(red, g, ns));
+            wave_lds_sync();
+        }
+        wave_lds_sync();
+    }
+}
+
+// ---------------------------------------------------------------- t ----
+
+// Per-wave LDS of the t-channel product, one wave per workgroup.
+struct AdjTLds {
+    int ns;
+    __host__ __device__ size_t plans() const { return (size_t)4 * kPlanChunk * sizeof(Plan); }   // Pa Pb Q1 Q2
+    __host__ __device__ size_t ons() const { return (size_t)4 * kPlanChunk * sizeof(double); }
+    __host__ __device__ size_t vb() const { return (size_t)4 * kSub * ns * sizeof(double); }
+    __host__ __device__ size_t nmat() const { return (size_t)2 * ns * ns * sizeof(double); }
+    __host__ __device__ size_t vin() const { return (size_t)2 * ns * sizeof(double); }
+    __host__ __device__ size_t red() const { return (size_t)5 * kWave * sizeof(double); }
+    __host__ __device__ size_t bytes() const {
+        return ((plans() + ons() + vb() + nmat() + vin() + red()) + 31) & ~(size_t)31;
+    }
+};
+
+// rpat_off[ns*ns + 1], rpat_ent[n_terms]: the lattice-sum terms grouped by
+// (ka, kb), entry = p | (count << 16) (the transpose of the per-output table).
+static __global__ void __launch_bounds__(kWave)
+k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const int* __restrict__ rpat_off,
+               const int* __restrict__ rpat_ent, const double* __restrict__ v, double* __restrict__ cgs,
+               double* __restrict__ cgd, double* __restrict__ ctg) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns, nq = A.nq;
+    const Shared sh = load_shared(A, lds_raw, false);
+    A.w = sh.w;
+    const int lane = threadIdx.x;
+    const AdjTLds L{ns};
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false);
+    Plan* plan = reinterpret_cast<Plan*>(base);                                          // [4][kPlanChunk]
+    double* ons = reinterpret_cast<double*>(base + L.plans());                           // [4][kPlanChunk]
+    double* vb = reinterpret_cast<double*>(base + L.plans() + L.ons());                  // [4][kSub][ns]
+    double* nm = reinterpret_cast<double*>(base + L.plans() + L.ons() + L.vb());         // [2][ns*ns]
+    double* vin = nm + 2 * ns * ns;                                                      // [2][ns]
+    double* red = vin + 2 * ns;                                                          // [5][64]
+    const int per = gridDim.x / 8;
+    const int o = __builtin_amdgcn_readfirstlane((int)((blockIdx.x % 8) * per + blockIdx.x / 8));
+    if (o >= n_triples) return;
+    const int nsu = nf * (nf + 1) / 2;
+    const int it = o / nsu, su = o % nsu;
+    const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
+    const double t = T.t;
+    const long vsz = (long)n_triples * ns;
+    const double* gs = x + nf;
+    const double* gd = gs + vsz;
+
+    for (int i = lane; i < ns; i += kWave) {
+        vin[i] = v[nf + T.out * ns + i];
+        vin[ns + i] = v[nf + vsz + T.out * ns + i];
+    }
+    wave_lds_sync();
+    // N[ka][kb] = sum over outputs p of v(p) * count of (ka, kb) in p's terms
+    for (int e = lane; e < ns * ns; e += kWave) {
+        double a = 0.0, b = 0.0;
+        for (int qq = rpat_off[e]; qq < rpat_off[e + 1]; ++qq) {
+            const int en = rpat_ent[qq];
+            const double c = (double)(en >> 16);
+            a = fma(c, vin[en & 0xffff], a);
+            b = fma(c, vin[ns + (en & 0xffff)], b);
+        }
+        nm[e] = a;
+        nm[ns * ns + e] = b;
+    }
+    const double* nsm = nm;
+    const double* ndm = nm + ns * ns;
+
+    const int G = kWave / ns;
+    const int g = lane / ns, p = lane % ns;
+    const bool act = g < G;
+    const double vs = act ? vin[p] : 0.0;
+    const double vd = act ? vin[ns + p] : 0.0;
+    const int cnt = A.tab_n[1 * nf + it];
+    const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
+    const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
+    double* ct = ctg + (long)(1 * nf + it) * nq;
+
+    for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
+        const int kc = min(kPlanChunk, cnt - k0);
+        wave_lds_sync();
+        {
+            const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
+            if (j < kc) {
+                const double om = tw[k0 + j];
+                Plan P, Q;
+                if (vec == 0) {
+                    make_plan(A.w, nf, ns, T.w1 + om, t, T.w1p - om, 1, it, P, sh.ih);
+                    make_plan(A.w, nf, ns, T.w2p + om, T.w2 - om, -t, 2, it, Q, sh.ih);
+                } else {
+                    make_plan(A.w, nf, ns, om + T.w2p, t, om - T.w2, 1, it, P, sh.ih);
+                    make_plan(A.w, nf, ns, T.w1 + om, om - T.w1p, -t, 2, it, Q, sh.ih);
+                }
+                plan[vec * kPlanChunk + j] = P;
+                plan[(2 + vec) * kPlanChunk + j] = Q;
+                double os, od;
+                eval_plan(Q, gs, gd, sh.swap, 0, os, od);
+                ons[(2 * vec + 0) * kPlanChunk + j] = os;
+                ons[(2 * vec + 1) * kPlanChunk + j] = od;
+            }
+        }
+        wave_lds_sync();
+        for (int s0 = 0; s0 < kc; s0 += kSub) {
+            const int sc = min(kSub, kc - s0);
+            if (act) {
+                for (int kk = g; kk < sc; kk += G) {
+                    double as, ad, bs, bd;
+                    eval_plan(plan[s0 + kk], gs, gd, sh.swap, p, as, ad);
+                    eval_plan(plan[kPlanChunk + s0 + kk], gs, gd, sh.swap, p, bs, bd);
+                    vb[(0 * kSub + kk) * ns + p] = as;
+                    vb[(1 * kSub + kk) * ns + p] = ad;
+                    vb[(2 * kSub + kk) * ns + p] = bs;
+                    vb[(3 * kSub + kk) * ns + p] = bd;
+                }
+            }
+            wave_lds_sync();
+            for (int kb = 0; kb < sc; kb += G) {
+                const int kk = kb + g;
+                const bool on = act && kk < sc;
+                double cval = 0.0, c1s = 0.0, c1d = 0.0, c2s = 0.0, c2d = 0.0;
+                if (on) {
+                    const int k = s0 + kk;
+                    const double W = tg[k0 + k];
+                    const double o1s = ons[0 * kPlanChunk + k], o1d = ons[1 * kPlanChunk + k];
+                    const double o2s = ons[2 * kPlanChunk + k], o2d = ons[3 * kPlanChunk + k];
+                    const double* ra = vb + (0 * kSub + kk) * ns;
+                    const double* rad = vb + (1 * kSub + kk) * ns;
+                    const double* rb = vb + (2 * kSub + kk) * ns;
+                    const double* rbd = vb + (3 * kSub + kk) * ns;
+                    const double as = ra[p], ad = rad[p], bs = rb[p], bd = rbd[p];
+                    // (N b)[p] and (N^T a)[p] for both strains
+                    double nbs = 0.0, nbd = 0.0, nas = 0.0, nad = 0.0;
+                    for (int j = 0; j < ns; ++j) {
+                        nbs = fma(nsm[p * ns + j], rb[j], nbs);
+                        nbd = fma(ndm[p * ns + j], rbd[j], nbd);
+                        nas = fma(nsm[j * ns + p], ra[j], nas);
+                        nad = fma(ndm[j * ns + p], rad[j], nad);
+                    }
+                    const double cs = -as * o1s + as * o1d - o2s * bs + o2d * bs;
+                    const double cd = 3.0 * ad * o1s + ad * o1d + 3.0 * o2s * bd + o2d * bd;
+                    cval = vs * cs + vd * cd - 2.0 * (as * nbs + ad * nbd);
+                    const double cas = W * (vs * (o1d - o1s) - 2.0 * nbs);
+                    const double cad = W * (vd * (3.0 * o1s + o1d) - 2.0 * nbd);
+                    const double cbs = W * (vs * (o2d - o2s) - 2.0 * nas);
+                    const double cbd = W * (vd * (3.0 * o2s + o2d) - 2.0 * nad);
+                    const Plan& Pa = plan[k];
+                    const Plan& Pb = plan[kPlanChunk + k];
+                    scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
+                    scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
+                    c1s = W * (-vs * as + 3.0 * vd * ad);
+                    c1d = W * (vs * as + vd * ad);
+                    c2s = W * (-vs * bs + 3.0 * vd * bd);
+                    c2d = W * (vs * bs + vd * bd);
+                }
+                red[lane] = cval;
+                red[kWave + lane] = c1s;
+                red[2 * kWave + lane] = c1d;
+                red[3 * kWave + lane] = c2s;
+                red[4 * kWave + lane] = c2d;
+                wave_lds_sync();
+                if (on && p == 0) {
+                    const int k = s0 + kk;
+                    atomic_add(ct + k0 + k, group_sum(red, g, ns));
+                    scatter_plan(plan[2 * kPlanChunk + k], cgs, cgd, 0, group_sum(red + kWave, g, ns),
+                                 group_sum(red + 2 * kWave, g, ns));
+                    scatter_plan(plan[3 * kPlanChunk + k], cgs, cgd, 0, group_sum(red + 3 * kWave, g, ns),
+                                 group_sum(red + 4 * kWave, g, ns));
+                }
+                wave_lds_sync();
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------ node tables ----
+
+// Reverse of TableWriter for one node list: ctg -> cot_sig, cot_dsig.
+struct TableVjp {
+    const double* w;
+    int nf;
+    const double* sig;
+    const double* dsig;
+    const double* ctg;
+    double* cot_sig;
+    double* cot_dsig;
+    __device__ __forceinline__ void delta(int n, double node, double xx, double y, double th, int lane) {
+        if (lane != 0) return;
+        const double c = ctg[n];
+        if (c == 0.0) return;
+        const double st = 1.0 / (xx - odd_interp(w, nf, sig, xx));
+        const double gy = 1.0 / (y - odd_interp(w, nf, sig, y));
+        const double tgv = -st * th * gy * kInvTwoPi;
+        odd_interp_vjp(w, nf, xx, c * tgv * st, cot_sig);
+        odd_interp_vjp(w, nf, y, c * tgv * gy, cot_sig);
+    }
+    __device__ __forceinline__ void kat(int n, double cur, double pp, double wt) {
+        const double c = ctg[n] * wt * kInvTwoPi;
+        if (c == 0.0) return;
+        const double gw = 1.0 / (cur - odd_interp(w, nf, sig, cur));
+        const double gp = 1.0 / (pp - odd_interp(w, nf, sig, pp));
+        const double dp = odd_interp(w, nf, dsig, pp), dc = odd_interp(w, nf, dsig, cur);
+        odd_interp_vjp(w, nf, pp, c * gw * gp * gp, cot_dsig);
+        odd_interp_vjp(w, nf, cur, c * gp * gw * gw, cot_dsig);
+        odd_interp_vjp(w, nf, cur, c * (gw * gw * gp * gp * dp + 2.0 * gp * gw * gw * gw * dc), cot_sig);
+        odd_interp_vjp(w, nf, pp, c * (2.0 * gw * gp * gp * gp * dp + gp * gp * gw * gw * dc), cot_sig);
+    }
+    __device__ __forceinline__ void done(int, int) {}
+};
+
+// one wave per (channel, nu)
+static __global__ void __launch_bounds__(kWave)
+k_tables_vjp(FlowArgs A, double lam, const double* __restrict__ x, const double* __restrict__ dsig,
+             const double* __restrict__ ctg, double* __restrict__ cot_sig, double* __restrict__ cot_dsig) {
+    const int id = blockIdx.x;
+    TableVjp vj{A.w, A.nf, x, dsig, ctg + (long)id * A.nq, cot_sig, cot_dsig};
+    walk_nodes(A, lam, id, threadIdx.x, vj);
+}
+
+// ------------------------------------------------------- self-energy ----
+
+// Reverse of sigma_body: cdsig[n] is the cotangent of d sig(w_n)/d Lambda.
+static __global__ void __launch_bounds__(kWave)
+k_sigma_vjp(FlowArgs A, double lam, const double* __restrict__ x, long nv, const double* __restrict__ cdsig,
+            double* __restrict__ cgs, double* __restrict__ cgd, double* __restrict__ cot_sig) {
+    const int n = blockIdx.x, lane = threadIdx.x;
+    const double cn = cdsig[n];
+    if (cn == 0.0) return;
+    const double wn = A.w[n];
+    const double* gs = x + A.nf;
+    const double* gd = gs + nv;
+    for (int sx = 0; sx < 2; ++sx) {
+        const double xx = sx == 0 ? lam : -lam;
+        Plan P;
+        make_plan(A.w, A.nf, A.ns, wn + xx, 0.0, wn - xx, 1, 0, P);
+        double f = 0.0;
+        for (int r = lane; r < A.ns; r += kWave) {
+            double vs, vd;
+            eval_plan(P, gs, gd, A.swap, r, vs, vd);
+            f = fma(2.0 * (double)A.mult[r], vd, f);
+        }
+        f = wave_sum(f);
+        Plan Q;
+        make_plan(A.w, A.nf, A.ns, wn + xx, xx - wn, 0.0, 2, 0, Q);
+        double os, od;
+        eval_plan(Q, gs, gd, A.swap, 0, os, od);
+        f -= 3.0 * os + od;
+        const double sv = 1.0 / (xx - odd_interp(A.w, A.nf, x, xx));
+        const double c = cn * sv * kInvTwoPi;
+        for (int r = lane; r < A.ns; r += kWave)
+            scatter_plan(P, cgs, cgd, P.swp ? A.swap[r] : r, 0.0, 2.0 * (double)A.mult[r] * c);
+        if (lane == 0) {
+            scatter_plan(Q, cgs, cgd, 0, -3.0 * c, -c);
+            odd_interp_vjp(A.w, A.nf, xx, cn * f * sv * sv * kInvTwoPi, cot_sig);
+        }
+    }
+}
+
+// ------------------------------------------------------ correlations ----
+
+// Reverse of k_chi_pairs: cchi[p], cchi[ns + p] are the cotangents of
+// chi^{zz}_p, chi^{00}_p; one workgroup per pair.  cg2[i] accumulates the
+// cotangent of g^2 at correlation node i.
+static __global__ void __launch_bounds__(kChiThreads)
+k_chi_pairs_vjp(const double* __restrict__ w, int nf, int ns, const int* __restrict__ swap,
+                const double* __restrict__ x, const double* __restrict__ cw, const double* __restrict__ cq,
+                const double* __restrict__ cg2, const int* __restrict__ cn, const double* __restrict__ cchi,
+                double* __restrict__ cgs, double* __restrict__ cgd, double* __restrict__ cot_g2) {
+    const int p = blockIdx.x, tid = threadIdx.x;
+    const int n = *cn;
+    const long vsz = (long)nf * (nf + 1) / 2 * nf * ns;
+    const double* gs = x + nf;
+    const double* gd = gs + vsz;
+    const double pref = 1.0 / (16.0 * M_PI * M_PI);
+    const double cz = cchi[p], cd = cchi[ns + p];
+    if (cz == 0.0 && cd == 0.0) return;
+    for (int e = tid; e < n * n; e += kChiThreads) {
+        const int i = e / n, j = e % n;
+        const double w1 = cw[i], w2 = cw[j];
+        const double qq = cq[i] * cq[j];
+        const double f = qq * cg2[i] * cg2[j];
+        Plan P;
+        make_plan(w, nf, ns, w1 + w2, 0.0, w1 - w2, 1, 0, P);
+        double vs, vd;
+        eval_plan(P, gs, gd, swap, p, vs, vd);
+        double tz = 4.0 * vs, td = 4.0 * vd;
+        scatter_plan(P, cgs, cgd, P.swp ? swap[p] : p, -pref * f * 4.0 * cz, -pref * f * 4.0 * cd);
+        if (p == 0) {
+            Plan Q;
+            make_plan(w, nf, ns, w1 + w2, w2 - w1, 0.0, 2, 0, Q);
+            double es, ed;
+            eval_plan(Q, gs, gd, swap, 0, es, ed);
+            tz += 2.0 * es - 2.0 * ed;
+            td -= 6.0 * es + 2.0 * ed;
+            scatter_plan(Q, cgs, cgd, 0, -pref * f * (2.0 * cz - 6.0 * cd), -pref * f * (-2.0 * cz - 2.0 * cd));
+        }
+        const double val = -pref * qq * (cz * tz + cd * td);
+        atomic_add(cot_g2 + i, val * cg2[j]);
+        atomic_add(cot_g2 + j, val * cg2[i]);
+    }
+    if (p == 0)
+        for (int i = tid; i < n; i += kChiThreads) atomic_add(cot_g2 + i, (cz + cd) * cq[i] * 0.5 * kInvTwoPi);
+}
+
+// cot_g2 -> cot_sig (g^2 = 1/(w - sig(w))^2, d g^2 / d sig(w) = 2 g^3); one thread.
+static __global__ void k_chi_nodes_vjp(const double* __restrict__ w, int nf, const double* __restrict__ x,
+                                       const double* __restrict__ cw, const int* __restrict__ cn,
+                                       const double* __restrict__ cot_g2, double* __restrict__ cot_sig) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int i = 0; i < *cn; ++i) {
+        const double g = 1.0 / (cw[i] - odd_interp(w, nf, x, cw[i]));
+        odd_interp_vjp(w, nf, cw[i], cot_g2[i] * 2.0 * g * g * g, cot_sig);
+    }
+}
+
+// Reverse of k_chi_k: cchi[pair] += (3 / nb) sum_q ck[q] cos(k_q . dr) for
+// every (basis, site) term; one thread per term.
+static __global__ void k_chi_k_vjp(int nterm, const int* __restrict__ pair, const double* __restrict__ dr,
+                                   double inv_nb, int nk, const double* __restrict__ kp,
+                                   const double* __restrict__ ck, double* __restrict__ cchi) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nterm) return;
+    double acc = 0.0;
+    for (int q = 0; q < nk; ++q) {
+        const double ph = kp[3 * q] * dr[3 * i] + kp[3 * q + 1] * dr[3 * i + 1] + kp[3 * q + 2] * dr[3 * i + 2];
+        acc = fma(cos(ph), ck[q], acc);
+    }
+    atomic_add(cchi + pair[i], 3.0 * inv_nb * acc);
+}
+
+// d/d coupling_p of a function of the initial state (Gs = coupling / 4 at
+// every frequency): 0.25 * sum over the frequencies of the cotangent of Gs_p.
+static __global__ void __launch_bounds__(256)
+k_coupling_grad(long n_el, int ns, const double* __restrict__ cgs, double* __restrict__ out) {
+    __shared__ double red[256];
+    const int p = blockIdx.x;
+    double a = 0.0;
+    for (long e = threadIdx.x; e < n_el; e += blockDim.x) a += cgs[e * ns + p];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[p] = 0.25 * red[0];
+}
+
+// y += alpha * a (elementwise).
+static __global__ void k_axpy(long n, double alpha, const double* __restrict__ a, double* __restrict__ y) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = fma(alpha, a[i], y[i]);
+}
+
+}  // namespace pffrg

@@ -195,38 +195,30 @@ __device__ __forceinline__ double full_mesh(const double* __restrict__ w, int nf
 // One wave per (channel, nu).  Node list: the delta points first, then for
 // every piece of D = [-wmax, wmax] \ (-lam, lam) \ (c - lam, c + lam) (c = zero
 // of the partner) its ends and the mesh points strictly inside, with
-// trapezoid weight times the Katanin bubble.
-__device__ __forceinline__ void tables_body(const FlowArgs& A, double lam, const double* __restrict__ x,
-                                            const double* __restrict__ dsig, int id, int lane) {
+// trapezoid weight times the Katanin bubble.  The walk is shared by the
+// table builder and its vector-Jacobian product: V receives
+//   delta(n, node, x, y, theta, lane)  node n = w at a delta point x = +-Lambda,
+//       weight -theta / ((x - sig(x)) (y - sig(y))) / (2 pi) with y the
+//       frequency of the other propagator (uniform over the wave);
+//   kat(n, w, partner(w), trapezoid weight)  one Katanin node (per lane);
+//   done(n, lane)  the list length.
+template <class V>
+__device__ __forceinline__ void walk_nodes(const FlowArgs& A, double lam, int id, int lane, V& vis) {
     const int nf = A.nf;
     const int ch = id / nf, iv = id % nf;
     const double nu = A.w[iv];
-    const double* sig = x;
-    double* tw = A.tab_w + (long)id * A.nq;
-    double* tg = A.tab_g + (long)id * A.nq;
     int n = 0;
 
     // delta parts: the S in Skat(partner(w)) puts w at partner^-1(x); the S in
-    // Skat(w) puts w at x.  Weight -G(.) / (x - sig(x)) / (2 pi) in real form.
+    // Skat(w) puts w at x.
     for (int sx = 0; sx < 2; ++sx) {
         const double xx = sx == 0 ? lam : -lam;
         const double winv = ch == 0 ? nu - xx : (ch == 1 ? xx + nu : xx - nu);
         const double pxx = partner(ch, nu, xx);
-        double g1 = theta_half(winv, lam);
-        double g2 = theta_half(pxx, lam);
-        if (g1 != 0.0 || g2 != 0.0) {
-            const double st = 1.0 / (xx - odd_interp(A.w, nf, sig, xx));
-            if (g1 != 0.0) {
-                g1 /= winv - odd_interp(A.w, nf, sig, winv);
-                if (lane == 0) { tw[n] = winv; tg[n] = -st * g1 * kInvTwoPi; }
-                ++n;
-            }
-            if (g2 != 0.0) {
-                g2 /= pxx - odd_interp(A.w, nf, sig, pxx);
-                if (lane == 0) { tw[n] = xx; tg[n] = -st * g2 * kInvTwoPi; }
-                ++n;
-            }
-        }
+        const double g1 = theta_half(winv, lam);
+        const double g2 = theta_half(pxx, lam);
+        if (g1 != 0.0) vis.delta(n++, winv, xx, winv, g1, lane);
+        if (g2 != 0.0) vis.delta(n++, xx, xx, pxx, g2, lane);
     }
 
     const double c = ch == 0 ? nu : (ch == 1 ? nu : -nu);
@@ -260,18 +252,44 @@ __device__ __forceinline__ void tables_body(const FlowArgs& A, double lam, const
                 const double cur = node(j);
                 const double wl = j > 0 ? 0.5 * (cur - node(j - 1)) : 0.0;
                 const double wr = j + 1 < m ? 0.5 * (node(j + 1) - cur) : 0.0;
-                const double pp = partner(ch, nu, cur);
-                const double gw = 1.0 / (cur - odd_interp(A.w, nf, sig, cur));
-                const double gp = 1.0 / (pp - odd_interp(A.w, nf, sig, pp));
-                const double kat = gw * gp * gp * odd_interp(A.w, nf, dsig, pp)
-                                 + gp * gw * gw * odd_interp(A.w, nf, dsig, cur);
-                tw[n + j] = cur;
-                tg[n + j] = (wl + wr) * kat * kInvTwoPi;
+                vis.kat(n + j, cur, partner(ch, nu, cur), wl + wr);
             }
             n += m;
         }
     }
-    if (lane == 0) A.tab_n[id] = n;
+    vis.done(n, lane);
+}
+
+// Writes the node list (frequencies tw, weights tg, length tn).
+struct TableWriter {
+    const double* w;
+    int nf;
+    const double* sig;
+    const double* dsig;
+    double* tw;
+    double* tg;
+    int* tn;
+    __device__ __forceinline__ void delta(int n, double node, double xx, double y, double th, int lane) {
+        const double st = 1.0 / (xx - odd_interp(w, nf, sig, xx));
+        const double g = th / (y - odd_interp(w, nf, sig, y));
+        if (lane == 0) { tw[n] = node; tg[n] = -st * g * kInvTwoPi; }
+    }
+    __device__ __forceinline__ void kat(int n, double cur, double pp, double wt) {
+        const double gw = 1.0 / (cur - odd_interp(w, nf, sig, cur));
+        const double gp = 1.0 / (pp - odd_interp(w, nf, sig, pp));
+        const double k = gw * gp * gp * odd_interp(w, nf, dsig, pp) + gp * gw * gw * odd_interp(w, nf, dsig, cur);
+        tw[n] = cur;
+        tg[n] = wt * k * kInvTwoPi;
+    }
+    __device__ __forceinline__ void done(int n, int lane) {
+        if (lane == 0) *tn = n;
+    }
+};
+
+__device__ __forceinline__ void tables_body(const FlowArgs& A, double lam, const double* __restrict__ x,
+                                            const double* __restrict__ dsig, int id, int lane) {
+    TableWriter wr{A.w, A.nf, x, dsig, A.tab_w + (long)id * A.nq, A.tab_g + (long)id * A.nq, A.tab_n + id};
+    walk_nodes(A, lam, id, lane, wr);
 }
 
 static __global__ void __launch_bounds__(kWave)

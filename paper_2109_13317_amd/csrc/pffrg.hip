@@ -18,6 +18,7 @@
 #include "host_common.h"
 #include "kernels_flow.h"
 #include "kernels_obs.h"
+#include "kernels_adj.h"
 
 using namespace pffrg;
 using namespace pffrg_host;
@@ -61,6 +62,13 @@ struct pffrg_ctx {
     double* part = nullptr;         // [2*kRedBlocks]
     double* red = nullptr;          // [2]
     double* host_red = nullptr;     // pinned [2]
+
+    // reverse mode
+    int *rpat_off = nullptr, *rpat_ent = nullptr;   // lattice-sum terms grouped by (ka, kb)
+    double* ctg = nullptr;          // [3*nf*nq] cotangent of the node weights
+    double* cdsig = nullptr;        // [nf] cotangent of d sig / d Lambda
+    double* cot_g2 = nullptr;       // [nq] cotangent of g^2 at the correlation nodes
+    double* cchi = nullptr;         // [2*ns]
 
     std::vector<void*> allocs;
 
@@ -326,6 +334,76 @@ pffrg_status observe(pffrg_ctx* c, const pffrg_flow_opts* o, double lam, const d
     return PFFRG_OK;
 }
 
+// ------------------------------------------------------- reverse mode ---
+
+pffrg_status fill(pffrg_ctx* c, double* p, long n, double v) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, v, p);
+    return launch_check("k_fill");
+}
+
+pffrg_status axpy(pffrg_ctx* c, long n, double alpha, const double* a, double* y) {
+    hipLaunchKernelGGL(k_axpy, dim3(grid_for(n, 256)), dim3(256), 0, c->stream, n, alpha, a, y);
+    return launch_check("k_axpy");
+}
+
+// out = J^T v for the right-hand side at (lam, x); out and v must not alias x.
+pffrg_status rhs_vjp(pffrg_ctx* c, double lam, const double* x, const double* v, double* out) {
+    if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    FlowArgs A = c->args();
+    // forward pieces at (lam, x)
+    TRY(sigma_rhs(c, lam, x, c->dsig));
+    hipLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)c->dsig);
+    TRY(launch_check("k_node_tables"));
+    TRY(fill(c, out, c->size, 0.0));
+    TRY(fill(c, c->ctg, 3L * c->nf * c->nq, 0.0));
+    TRY(fill(c, c->cdsig, c->nf, 0.0));
+    TRY(axpy(c, c->nf, 1.0, v, c->cdsig));
+    double* cgs = out + c->nf;
+    double* cgd = cgs + c->vsz;
+    const int T = c->nsu * c->nf;
+    {
+        const int blocks = (T + kAdjWaves - 1) / kAdjWaves;
+        const int per = (blocks + 7) / 8;
+        const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + kAdjWaves * AdjWaveLds::bytes();
+        hipLaunchKernelGGL(k_vertex_vjp_su<0>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
+                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, cgs, cgd, c->ctg);
+        TRY(launch_check("k_vertex_vjp_su"));
+        hipLaunchKernelGGL(k_vertex_vjp_su<2>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
+                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, cgs, cgd, c->ctg);
+        TRY(launch_check("k_vertex_vjp_su"));
+    }
+    {
+        const int per = (T + 7) / 8;
+        const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + AdjTLds{c->ns}.bytes();
+        hipLaunchKernelGGL(k_vertex_vjp_t, dim3(8 * per), dim3(kWave), lds, c->stream, A, x, T,
+                           (const int*)c->rpat_off, (const int*)c->rpat_ent, v, cgs, cgd, c->ctg);
+        TRY(launch_check("k_vertex_vjp_t"));
+    }
+    hipLaunchKernelGGL(k_tables_vjp, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)c->dsig,
+                       (const double*)c->ctg, out, c->cdsig);
+    TRY(launch_check("k_tables_vjp"));
+    hipLaunchKernelGGL(k_sigma_vjp, dim3(c->nf), dim3(kWave), 0, c->stream, A, lam, x, (long)c->vsz,
+                       (const double*)c->cdsig, cgs, cgd, out);
+    return launch_check("k_sigma_vjp");
+}
+
+// out = (d chi / d x)^T cchi at (lam, x).
+pffrg_status chi_vjp(pffrg_ctx* c, double lam, const double* x, const double* cchi, double* out) {
+    hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(1), 0, c->stream, (const double*)c->w, c->nf, lam, x, c->cw, c->cq,
+                       c->cg2, c->cn);
+    TRY(launch_check("k_chi_nodes"));
+    TRY(fill(c, out, c->size, 0.0));
+    TRY(fill(c, c->cot_g2, c->nq, 0.0));
+    hipLaunchKernelGGL(k_chi_pairs_vjp, dim3(c->ns), dim3(kChiThreads), 0, c->stream, (const double*)c->w, c->nf,
+                       c->ns, (const int*)c->swap, x, (const double*)c->cw, (const double*)c->cq,
+                       (const double*)c->cg2, (const int*)c->cn, cchi, out + c->nf, out + c->nf + c->vsz,
+                       c->cot_g2);
+    TRY(launch_check("k_chi_pairs_vjp"));
+    hipLaunchKernelGGL(k_chi_nodes_vjp, dim3(1), dim3(1), 0, c->stream, (const double*)c->w, c->nf, x,
+                       (const double*)c->cw, (const int*)c->cn, (const double*)c->cot_g2, out);
+    return launch_check("k_chi_nodes_vjp");
+}
+
 }  // namespace
 
 namespace pffrg_host {
@@ -437,6 +515,20 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
             TRY(upload(c, &c->rpa_term, packed.data(), packed.size()));
         }
         TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
+        {
+            // the same terms grouped by (ka, kb): entry = output pair | count << 16
+            std::vector<std::vector<int>> by(ns * ns);
+            for (int p = 0; p < ns; ++p)
+                for (int q = lat->rpa_off[p]; q < lat->rpa_off[p + 1]; ++q)
+                    by[lat->rpa_ka[q] * ns + lat->rpa_kb[q]].push_back(p | (lat->rpa_cnt[q] << 16));
+            std::vector<int> off(ns * ns + 1, 0), ent;
+            for (int e = 0; e < ns * ns; ++e) {
+                ent.insert(ent.end(), by[e].begin(), by[e].end());
+                off[e + 1] = (int)ent.size();
+            }
+            TRY(upload(c, &c->rpat_off, off.data(), off.size()));
+            TRY(upload(c, &c->rpat_ent, ent.data(), ent.size()));
+        }
         std::vector<int> sa(c->nsu), sc(c->nsu);
         for (int a = 0; a < nf; ++a)
             for (int cc = 0; cc <= a; ++cc) { sa[a * (a + 1) / 2 + cc] = a; sc[a * (a + 1) / 2 + cc] = cc; }
@@ -481,6 +573,10 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->chi, (size_t)2 * ns));
         TRY(dev_alloc(c, &c->part, (size_t)2 * kRedBlocks));
         TRY(dev_alloc(c, &c->red, 2));
+        TRY(dev_alloc(c, &c->ctg, (size_t)3 * nf * c->nq));
+        TRY(dev_alloc(c, &c->cdsig, (size_t)nf));
+        TRY(dev_alloc(c, &c->cot_g2, (size_t)c->nq));
+        TRY(dev_alloc(c, &c->cchi, (size_t)2 * ns));
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
         if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
@@ -673,6 +769,115 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
         }
         if (ladder(m) < o->hmin && l > lend)
             return fail(PFFRG_EDIVERGED, "adaptive step fell below hmin at lambda = " + std::to_string(std::exp(l)));
+    }
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_init_state_from(pffrg_ctx* c, const double* coupling, double* x) {
+    TRY(check_ctx(c));
+    if (!x || !coupling) return fail(PFFRG_EINVAL, "null pointer");
+    hipLaunchKernelGGL(k_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size, c->nf,
+                       c->ns, coupling, x);
+    return launch_check("k_init_state");
+}
+
+pffrg_status pffrg_rhs_vjp(pffrg_ctx* c, double lambda, const double* x, const double* v, double* out) {
+    TRY(check_ctx(c));
+    if (!x || !v || !out) return fail(PFFRG_EINVAL, "null pointer");
+    if (out == x || out == v) return fail(PFFRG_EINVAL, "output must not overlap the inputs");
+    return rhs_vjp(c, lambda, x, v, out);
+}
+
+pffrg_status pffrg_chi_vjp(pffrg_ctx* c, double lambda, const double* x, const double* cchi, double* out) {
+    TRY(check_ctx(c));
+    if (!x || !cchi || !out) return fail(PFFRG_EINVAL, "null pointer");
+    if (out == x) return fail(PFFRG_EINVAL, "output must not overlap the state");
+    if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    return chi_vjp(c, lambda, x, cchi, out);
+}
+
+pffrg_status pffrg_chi_k_vjp(pffrg_ctx* c, const double* ck, int nk, const double* kp, double* cchi) {
+    TRY(check_ctx(c));
+    if (nk < 0 || !cchi || (nk > 0 && (!ck || !kp))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
+    TRY(fill(c, cchi, 2L * c->ns, 0.0));
+    if (nk == 0) return PFFRG_OK;
+    hipLaunchKernelGGL(k_chi_k_vjp, dim3((c->nterm + 127) / 128), dim3(128), 0, c->stream, c->nterm,
+                       (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, nk, kp, ck, cchi);
+    return launch_check("k_chi_k_vjp");
+}
+
+static pffrg_status check_schedule(int n, const double* l) {
+    if (n < 2 || !l) return fail(PFFRG_EINVAL, "schedule needs >= 2 cutoffs");
+    for (int i = 0; i < n; ++i)
+        if (!(l[i] > 0.0) || !std::isfinite(l[i])) return fail(PFFRG_EINVAL, "cutoffs must be finite and > 0");
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_flow_checkpoints(pffrg_ctx* c, int n_lambda, const double* lambdas, double* x, double* ckpt) {
+    TRY(check_ctx(c));
+    TRY(check_schedule(n_lambda, lambdas));
+    if (!x || !ckpt) return fail(PFFRG_EINVAL, "null pointer");
+    for (int i = 0; i + 1 < n_lambda; ++i) {
+        HIP_TRY(hipMemcpyAsync(ckpt + (size_t)i * c->size, x, sizeof(double) * c->size, hipMemcpyDeviceToDevice,
+                               c->stream));
+        TRY(step_rk4(c, lambdas[i], lambdas[i + 1], x));
+    }
+    bool fin = true;
+    TRY(reduce_err(c, nullptr, x, nullptr, 0.0, 0.0, nullptr, &fin));
+    if (!fin) return fail(PFFRG_EDIVERGED, "state not finite at the end of the checkpointed flow");
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_flow_vjp(pffrg_ctx* c, int n_lambda, const double* lambdas, const double* ckpt, double* ybar,
+                            double* dcoupling) {
+    TRY(check_ctx(c));
+    TRY(check_schedule(n_lambda, lambdas));
+    if (!ckpt || !ybar) return fail(PFFRG_EINVAL, "null pointer");
+    const long n = c->size;
+    const int gb = grid_for(n, 256);
+    double* K = c->k[0];
+    double* Y2 = c->k[1];
+    double* Y3 = c->k[2];
+    double* Y4 = c->k[3];
+    double* Abar = c->k[4];
+    double* kbar = c->k[5];
+    double* Ybar = c->k[6];
+    for (int i = n_lambda - 2; i >= 0; --i) {
+        const double* y = ckpt + (size_t)i * n;
+        const double l0 = lambdas[i], l1 = lambdas[i + 1];
+        const double h = l1 - l0;
+        const double lm = l0 + 0.5 * h;
+        // the step's stage states, as in step_rk4
+        TRY(rhs(c, l0, y, K));
+        hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, y, (const double*)K, 0.5 * h, Y2, 0.0,
+                           (double*)nullptr, 0);
+        TRY(launch_check("k_rk_stage"));
+        TRY(rhs(c, lm, Y2, K));
+        hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, y, (const double*)K, 0.5 * h, Y3, 0.0,
+                           (double*)nullptr, 0);
+        TRY(launch_check("k_rk_stage"));
+        TRY(rhs(c, lm, Y3, K));
+        hipLaunchKernelGGL(k_rk_stage, dim3(gb), dim3(256), 0, c->stream, n, y, (const double*)K, h, Y4, 0.0,
+                           (double*)nullptr, 0);
+        TRY(launch_check("k_rk_stage"));
+        // reverse: y1 = Acc + (h/6) k4 with Acc = y + (h/6) k1 + (h/3) k2 + (h/3) k3
+        HIP_TRY(hipMemcpyAsync(Abar, ybar, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        const double* ys[4] = {Y4, Y3, Y2, y};
+        const double ls[4] = {l1, lm, lm, l0};
+        const double cacc[4] = {h / 6.0, h / 3.0, h / 3.0, h / 6.0};   // d y1 / d k_j through Acc (k4: direct)
+        const double cy[3] = {h, 0.5 * h, 0.5 * h};                     // d Y_{j+1} / d k_j
+        for (int s = 0; s < 4; ++s) {
+            TRY(fill(c, kbar, n, 0.0));
+            if (s > 0) TRY(axpy(c, n, cy[s - 1], Ybar, kbar));
+            TRY(axpy(c, n, cacc[s], Abar, kbar));
+            TRY(rhs_vjp(c, ls[s], ys[s], kbar, Ybar));
+            TRY(axpy(c, n, 1.0, Ybar, ybar));
+        }
+    }
+    if (dcoupling) {
+        hipLaunchKernelGGL(k_coupling_grad, dim3(c->ns), dim3(256), 0, c->stream, (long)c->nsu * c->nf, c->ns,
+                           (const double*)(ybar + c->nf), dcoupling);
+        TRY(launch_check("k_coupling_grad"));
     }
     return PFFRG_OK;
 }

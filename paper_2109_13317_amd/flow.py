@@ -142,6 +142,50 @@ class Context:
         del sched
         return int(nsteps.value)
 
+    # ------------------------------------------------------ reverse mode --
+    def init_state_from(self, coupling, x: torch.Tensor | None = None) -> torch.Tensor:
+        """Initial condition for per-pair couplings (device or host array)."""
+        x = self.new_state() if x is None else x
+        cp = torch.as_tensor(np.asarray(coupling, dtype=np.float64) if not torch.is_tensor(coupling)
+                             else coupling, dtype=torch.float64).cuda().contiguous()
+        _lib.check(self.lib.pffrg_init_state_from(self.handle, _dptr(cp), _dptr(x)))
+        return x
+
+    def rhs_vjp(self, lam: float, x: torch.Tensor, cot: torch.Tensor, out: torch.Tensor | None = None):
+        out = self.new_state() if out is None else out
+        _lib.check(self.lib.pffrg_rhs_vjp(self.handle, float(lam), _dptr(x), _dptr(cot), _dptr(out)))
+        return out
+
+    def chi_vjp(self, lam: float, x: torch.Tensor, cot_chi: torch.Tensor, out: torch.Tensor | None = None):
+        out = self.new_state() if out is None else out
+        _lib.check(self.lib.pffrg_chi_vjp(self.handle, float(lam), _dptr(x), _dptr(cot_chi.contiguous().view(-1)),
+                                          _dptr(out)))
+        return out
+
+    def chi_k_vjp(self, cot_chi_k: torch.Tensor, kpoints: torch.Tensor) -> torch.Tensor:
+        kp = kpoints.contiguous()
+        out = torch.empty(2 * self.ns, dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.pffrg_chi_k_vjp(self.handle, _dptr(cot_chi_k.contiguous()), int(kp.shape[0]),
+                                            _dptr(kp), _dptr(out)))
+        return out.view(2, self.ns)
+
+    def flow_checkpoints(self, x: torch.Tensor, schedule) -> torch.Tensor:
+        """RK4 along schedule in place; returns the checkpoints [steps, size]."""
+        sched = np.ascontiguousarray(schedule, dtype=np.float64)
+        ck = torch.empty((len(sched) - 1, self.size), dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.pffrg_flow_checkpoints(self.handle, len(sched), ctypes.c_void_p(sched.ctypes.data),
+                                                   _dptr(x), _dptr(ck)))
+        return ck
+
+    def flow_vjp(self, schedule, checkpoints: torch.Tensor, cot: torch.Tensor) -> torch.Tensor:
+        """cot: final-state cotangent, replaced by the initial-state one;
+        returns d/d coupling per pair."""
+        sched = np.ascontiguousarray(schedule, dtype=np.float64)
+        dcp = torch.empty(self.ns, dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.pffrg_flow_vjp(self.handle, len(sched), ctypes.c_void_p(sched.ctypes.data),
+                                           _dptr(checkpoints), _dptr(cot), _dptr(dcp)))
+        return dcp
+
     # --------------------------------------------------------- profiling --
     def set_profiling(self, on: bool):
         _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
@@ -168,6 +212,41 @@ class Context:
         _lib.check(self.lib.pffrg_chi_k(self.handle, _dptr(chi.contiguous()), int(kp.shape[0]),
                                         _dptr(kp), _dptr(out)))
         return out
+
+
+class ChiAdjoint(torch.autograd.Function):
+    """chi(k) at the end of an RK4 flow as a differentiable function of the
+    couplings J (one per coupling shell): the initial condition takes the
+    per-pair couplings design @ J; the backward pass is the library's
+    discrete adjoint (checkpointed steps).
+
+    forward(J, ctx, design [ns, nJ], schedule, kpoints [nk, 3]) -> chi(k) [nk]
+    """
+
+    @staticmethod
+    def forward(fctx, J, ctx, design, schedule, kpoints):
+        Jn = J.detach().cpu().numpy().astype(np.float64)
+        coupling = np.asarray(design, dtype=np.float64) @ Jn
+        x = ctx.init_state_from(coupling)
+        ck = ctx.flow_checkpoints(x, schedule)
+        lam = float(schedule[-1])
+        chi = ctx.chi(lam, x)
+        kp = kpoints.to(device="cuda", dtype=torch.float64).contiguous()
+        out = ctx.chi_k(chi, kp)
+        fctx.save_for_backward(J)
+        fctx.stash = (ctx, np.asarray(design, dtype=np.float64), np.asarray(schedule, dtype=np.float64), x, ck, kp)
+        return out.to(J.device)
+
+    @staticmethod
+    def backward(fctx, grad):
+        (J,) = fctx.saved_tensors
+        ctx, design, schedule, x, ck, kp = fctx.stash
+        g = grad.detach().to(device="cuda", dtype=torch.float64).contiguous()
+        cchi = ctx.chi_k_vjp(g, kp)
+        cot = ctx.chi_vjp(float(schedule[-1]), x, cchi)
+        dcp = ctx.flow_vjp(schedule, ck, cot)
+        dJ = design.T @ dcp.cpu().numpy()
+        return torch.as_tensor(dJ, dtype=J.dtype, device=J.device), None, None, None, None
 
 
 class Batch:

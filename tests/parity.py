@@ -104,3 +104,25 @@ def compare_parts(orc, tables, ref: np.ndarray, red: np.ndarray) -> tuple[float,
         ev = max(ev, np.abs(rgs[b, :, :, :n] - gs[:, :, pmap[b, :n]]).max(),
                  np.abs(rgd[b, :, :, :n] - gd[:, :, pmap[b, :n]]).max())
     return float(es), float(ev / scale)
+
+
+def restrict_state(orc, tables, x_unred: np.ndarray) -> np.ndarray:
+    """Reduced-layout state holding, for every reduced pair, the values of
+    one of its unreduced copies (the first (basis, site) mapped to it).  For
+    a symmetric state this inverts expand_state."""
+    pmap = pair_map(orc, tables)
+    nf, ns = orc.nf, tables.n_pairs
+    rep = {}
+    for b in range(orc.lat.nb):
+        for k in range(orc.lat.nsites[b]):
+            rep.setdefault(int(pmap[b, k]), (b, k))
+    assert len(rep) == ns
+    sig, gs, gd = orc.split(np.asarray(x_unred))
+    n_su = nf * (nf + 1) // 2
+    out = np.zeros(nf + 2 * n_su * nf * ns)
+    osig, ogs, ogd = _reduced_views(out, nf, ns)
+    osig[:] = sig
+    for p, (b, k) in rep.items():
+        ogs[:, :, p] = gs[b, :, :, k]
+        ogd[:, :, p] = gd[b, :, :, k]
+    return out
