@@ -15,8 +15,12 @@ E = 2 * pairs * triples = 675,840 vertex elements per right-hand side.
 
 Also reported: the dominant kernel's roofline position (algorithmic FP64
 flops per launch over its HIP-event duration), the whole adaptive flow
-(Dormand-Prince 5(4), Lambda 100 -> 0.01, chi(k) every accepted step), and
-the CPU oracle timed on a bounded sample of the same workload.
+(Dormand-Prince 5(4), Lambda 100 -> 0.01, chi(k) every accepted step), the
+CPU oracle timed on a bounded sample of the same workload, and three more
+measurements: the same right-hand side in FP32 mode (fp32_mode), a 64-point
+phase scan advanced as one batch against 64 sequential FP64 flows
+(batch_scan), and d chi(k_peak)/dJ through a 120-step flow by the discrete
+adjoint against the forward cost (adjoint).
 """
 
 from __future__ import annotations
@@ -126,6 +130,157 @@ def kgrid(n: int) -> np.ndarray:
     return np.stack([kx.ravel(), ky.ravel(), np.zeros(n * n)], axis=1)
 
 
+def fp32_leg(tables, wl, x_np, lam, reps=10):
+    """The same right-hand side in FP32 mode (vertex gathers, products and
+    lattice-sum matrix in FP32 with compensated sums) next to FP64."""
+    import torch
+    from paper_2109_13317_amd.flow import Context
+    x = torch.from_numpy(x_np).cuda()
+    res = {}
+    for prec in ("fp64", "fp32"):
+        c = Context(tables, wl.mesh, precision=prec)
+        out = c.new_state()
+        c.rhs(lam, x, out)
+        torch.cuda.synchronize()
+        c.set_profiling(True)
+        for _ in range(reps):
+            c.rhs(lam, x, out)
+        ms, n = c.profile_read("vertex")
+        c.set_profiling(False)
+        res[prec] = (ms / n, out.cpu().numpy())
+    nf = len(wl.mesh)
+    a, b = res["fp64"][1], res["fp32"][1]
+    E = a.size - nf
+    return {"vertex_rhs_ms": res["fp32"][0], "vertex_rhs_ms_fp64": res["fp64"][0],
+            "vertex_rhs_elements_per_s": E / (res["fp32"][0] * 1e-3),
+            "speedup_vs_fp64": res["fp64"][0] / res["fp32"][0],
+            "max_rel_err_vs_fp64": float(np.abs(a[nf:] - b[nf:]).max() / np.abs(a[nf:]).max()),
+            "sigma_part": "FP64 in both (bitwise equal)" if np.array_equal(a[:nf], b[:nf]) else "differs",
+            "lambda": lam}
+
+
+def batch_leg():
+    """64-point square J1-J2 scan (J2/J1 = k/63, ranges 4..7, 24 frequencies),
+    RK4 100 -> 0.01 in 120 steps: one FP32 batch (persistent vertex launch,
+    hipGraph step, tuned launch shape) against 64 sequential plain FP64 flows."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Batch, Context
+    from paper_2109_13317_amd._lib import PffrgError
+    wl = W.workload("square_scan")
+    pts = W.batch_scan_points(64)
+    tables = [build_tables(W.model("square", j1=q["j1"], j2=q["j2"]), q["range"]) for q in pts]
+    sched = wl.schedule
+    cut = [l for l in sched if l >= 1.0]
+    b = Batch(tables, wl.mesh, precision="fp32")
+    x = b.init_state()
+    tuned = b.tune(0.5, x)
+    x = b.init_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok = b.flow(x, sched, use_graph=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    log(f"batch scan flow {t_batch:.3f} s ({sum(ok)} of 64 points finite)")
+    chi_f = [c.cpu().numpy() for c in b.chi(sched[-1], x)]
+    x1 = b.init_state()
+    b.flow(x1, cut)
+    chi_1 = [c.cpu().numpy() for c in b.chi(cut[-1], x1)]
+    b.close()
+    seq_ok, seq_chi_f, seq_chi_1 = [], [], []
+    t_seq = 0.0
+    for t in tables:
+        c = Context(t, wl.mesh)
+        xs = c.init_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            c.flow(xs, schedule=sched, scheme="rk4")
+            fin = True
+        except PffrgError:
+            fin = False
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        seq_ok.append(fin)
+        seq_chi_f.append(c.chi(sched[-1], xs).cpu().numpy() if fin else None)
+        xs = c.init_state()
+        c.flow(xs, schedule=cut, scheme="rk4")
+        seq_chi_1.append(c.chi(cut[-1], xs).cpu().numpy())
+        c.close()
+    log(f"64 sequential FP64 flows {t_seq:.3f} s")
+    e1 = [float(np.abs(chi_1[p] - seq_chi_1[p]).max() / np.abs(seq_chi_1[p]).max()) for p in range(64)]
+    ef = [float(np.abs(chi_f[p] - seq_chi_f[p]).max() / np.abs(seq_chi_f[p]).max())
+          for p in range(64) if ok[p] and seq_ok[p]]
+    return {"workload": "64 square J1-J2 points, J2/J1 = k/63, ranges 4..7 (9/12/16/20 pairs), 24 log freqs "
+                        "1e-3..100, RK4 100 -> 0.01 in 120 steps",
+            "batch_fp32_seconds": t_batch, "sequential_fp64_seconds": t_seq,
+            "speedup": t_seq / t_batch, "tuned_launch": {"per_xcd": tuned[0], "order": tuned[1], "split": tuned[2]},
+            "finite_points_batch": int(sum(ok)), "finite_points_fp64": int(sum(seq_ok)),
+            "sequential_note": "a diverging FP64 flow stops at its first non-finite step",
+            "chi_rel_err_vs_fp64_at_lambda_1": {"max": max(e1), "median": float(np.median(e1))},
+            "chi_rel_err_vs_fp64_at_lambda_f": {"points": len(ef), "max": max(ef), "median": float(np.median(ef))}}
+
+
+def adjoint_leg():
+    """d chi(k_peak, Lambda=0.1) / d(J1, J2, J3) on the honeycomb lattice
+    (range 6, 32 frequencies, RK4 100 -> 0.1 in 120 steps) through the
+    discrete adjoint, timed against the forward flow, and checked against
+    central differences of the forward flow."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import ChiAdjoint, Context
+    wl = W.workload("honeycomb_j123")
+    shells = ("j1", "j2", "j3")
+    J0 = np.array([wl.params[s] for s in shells])
+    D = np.stack([build_tables(W.model("honeycomb", **{s: 1.0}), wl.range).coupling for s in shells], axis=1)
+    ctx = Context(build_tables(wl.model(), wl.range), wl.mesh)
+    sched = wl.schedule
+    grid = torch.from_numpy(kgrid(64)).cuda()
+    x = ctx.init_state()
+    ctx.flow(x, schedule=sched, scheme="rk4")
+    ck = ctx.chi_k(ctx.chi(sched[-1], x), grid)
+    kpk = grid[int(torch.argmax(ck))].reshape(1, 3).cpu()
+    x = ctx.init_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.flow(x, schedule=sched, scheme="rk4")
+    ctx.chi_k(ctx.chi(sched[-1], x), kpk.cuda())
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    J = torch.tensor(J0, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = ChiAdjoint.apply(J, ctx, D, sched, kpk)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out.sum().backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grad = J.grad.numpy()
+    log(f"adjoint: forward {t_fwd:.3f} s, checkpointed forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s")
+
+    def f(jv):
+        xx = ctx.init_state_from(D @ jv)
+        ctx.flow(xx, schedule=sched, scheme="rk4")
+        return float(ctx.chi_k(ctx.chi(sched[-1], xx), kpk.cuda()).cpu()[0])
+
+    fd = np.zeros(3)
+    for i in range(3):
+        def cd(h):
+            e = np.zeros(3); e[i] = h
+            return (f(J0 + e) - f(J0 - e)) / (2 * h)
+        h = 1e-3 * abs(J0[i])
+        fd[i] = (4.0 * cd(h / 2) - cd(h)) / 3.0
+    return {"workload": "honeycomb J1-J2-J3 (J from default_rng(210913317)), range 6 (14 pairs), 32 log freqs, "
+                        "RK4 100 -> 0.1 in 120 steps, k_peak = argmax chi(k) on 64x64",
+            "J": J0.tolist(), "k_peak": kpk.numpy().ravel().tolist(), "chi_k_peak": float(out.detach()[0]),
+            "dchi_dJ": grad.tolist(), "forward_seconds": t_fwd, "checkpointed_forward_seconds": t1 - t0,
+            "adjoint_seconds": t2 - t1, "adjoint_over_forward": (t1 - t0 + t2 - t1) / t_fwd,
+            "checkpoint_bytes": int((len(sched) - 1) * ctx.size * 8),
+            "fd_check": {"method": "central differences of the forward flow, h = 1e-3 J_i, Richardson",
+                         "max_rel_err": float(np.abs(grad - fd).max() / np.abs(fd).max())}}
+
+
 def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
     """The oracle on a bounded sample: every vertex element of a set of
     frequency triples (plus the self-energy flow), timed on the host cores;
@@ -175,6 +330,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full-flow", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32, batched-scan and adjoint measurements")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -300,6 +457,14 @@ def main():
         out["full_flow"] = {"scheme": "dopri54 in ln Lambda, rtol 1e-4, atol 1e-6, steps land on w_n/2",
                             "lambda": [100.0, 0.01], "seconds": time.perf_counter() - t0,
                             "accepted_steps": nsteps, "chi_k_every_step": "64x64"}
+
+    if not args.no_extras:
+        log("FP32 mode")
+        out["fp32_mode"] = fp32_leg(tables, wl, x_start, 0.5)
+        log("batched scan")
+        out["batch_scan"] = batch_leg()
+        log("adjoint")
+        out["adjoint"] = adjoint_leg()
 
     if args.copy_probe:
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")

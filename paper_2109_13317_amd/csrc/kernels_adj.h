@@ -75,7 +75,7 @@ constexpr int kAdjWaves = 4;
 
 struct AdjWaveLds {
     __host__ __device__ static constexpr size_t plans() { return (size_t)2 * kPlanChunk * sizeof(Plan); }
-    __host__ __device__ static constexpr size_t red() { return (size_t)kWave * sizeof(double); }
+    __host__ __device__ static constexpr size_t red() { return (size_t)kPlanChunk * sizeof(double); }
     __host__ __device__ static constexpr size_t bytes() { return ((plans() + red()) + 31) & ~(size_t)31; }
 };
 
@@ -96,9 +96,12 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict_
     const int per = blocks / 8;
     const int o = __builtin_amdgcn_readfirstlane(((blockIdx.x % 8) * per + blockIdx.x / 8) * kAdjWaves + wid);
     if (o >= n_triples) return;
+    // the opposite order of the forward launch: waves running together
+    // work on different slices of the channel, so their scatters rarely hit
+    // the same addresses
     const int q = o / nf, it = o % nf;
-    const int ia = CH == 0 ? A.su_a[q] : uo_a[q];
-    const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
+    const int ia = CH == 2 ? A.su_a[q] : uo_a[q];
+    const int ic = CH == 2 ? A.su_c[q] : uo_c[q];
     const Triple T = make_triple(A.w, nf, ia, it, ic);
     const long vsz = (long)n_triples * ns;
     const double* gs = x + nf;
@@ -131,20 +134,18 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict_
                 }
                 plan[vec * kPlanChunk + j] = P;
             }
+            if (lane < kPlanChunk) red[lane] = 0.0;
         }
         wave_lds_sync();
-        for (int kb = 0; kb < kc; kb += G) {
-            const int k = kb + g;
-            const bool on = act && k < kc;
-            double cval = 0.0;
-            if (on) {
+        for (int k = g; k < kc; k += G) {
+            if (act) {
                 const Plan& Pa = plan[k];
                 const Plan& Pb = plan[kPlanChunk + k];
                 double as, ad, bs, bd;
                 eval_plan(Pa, gs, gd, sh.swap, p, as, ad);
                 eval_plan(Pb, gs, gd, sh.swap, p, bs, bd);
                 const double W = tg[k0 + k];
-                cval = vs * (sgn * as * bs + as * bd + ad * bs) + vd * (3.0 * as * bs + ad * bd);
+                atomicAdd(red + k, vs * (sgn * as * bs + as * bd + ad * bs) + vd * (3.0 * as * bs + ad * bd));
                 const double cas = W * (vs * (sgn * bs + bd) + vd * 3.0 * bs);
                 const double cad = W * (vs * bs + vd * bd);
                 const double cbs = W * (vs * (sgn * as + ad) + vd * 3.0 * as);
@@ -152,11 +153,9 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict_
                 scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
                 scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
             }
-            red[lane] = cval;
-            wave_lds_sync();
-            if (on && p == 0) atomic_add(ct + k0 + k, group_sum(red, g, ns));
-            wave_lds_sync();
         }
+        wave_lds_sync();
+        if (lane < kc) atomic_add(ct + k0 + lane, red[lane]);     // node weights' cotangent (LDS ds_add_f64 above)
         wave_lds_sync();
     }
 }
@@ -171,7 +170,7 @@ struct AdjTLds {
     __host__ __device__ size_t vb() const { return (size_t)4 * kSub * ns * sizeof(double); }
     __host__ __device__ size_t nmat() const { return (size_t)2 * ns * ns * sizeof(double); }
     __host__ __device__ size_t vin() const { return (size_t)2 * ns * sizeof(double); }
-    __host__ __device__ size_t red() const { return (size_t)5 * kWave * sizeof(double); }
+    __host__ __device__ size_t red() const { return (size_t)5 * kPlanChunk * sizeof(double); }
     __host__ __device__ size_t bytes() const {
         return ((plans() + ons() + vb() + nmat() + vin() + red()) + 31) & ~(size_t)31;
     }
@@ -195,12 +194,12 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
     double* vb = reinterpret_cast<double*>(base + L.plans() + L.ons());                  // [4][kSub][ns]
     double* nm = reinterpret_cast<double*>(base + L.plans() + L.ons() + L.vb());         // [2][ns*ns]
     double* vin = nm + 2 * ns * ns;                                                      // [2][ns]
-    double* red = vin + 2 * ns;                                                          // [5][64]
+    double* red = vin + 2 * ns;                                                          // [5][kPlanChunk]
     const int per = gridDim.x / 8;
     const int o = __builtin_amdgcn_readfirstlane((int)((blockIdx.x % 8) * per + blockIdx.x / 8));
     if (o >= n_triples) return;
-    const int nsu = nf * (nf + 1) / 2;
-    const int it = o / nsu, su = o % nsu;
+    // (s, u, t) order, the opposite of the forward t launch (see k_vertex_vjp_su)
+    const int su = o / nf, it = o % nf;
     const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
     const double t = T.t;
     const long vsz = (long)n_triples * ns;
@@ -259,6 +258,7 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                 ons[(2 * vec + 0) * kPlanChunk + j] = os;
                 ons[(2 * vec + 1) * kPlanChunk + j] = od;
             }
+            for (int i = lane; i < 5 * kPlanChunk; i += kWave) red[i] = 0.0;
         }
         wave_lds_sync();
         for (int s0 = 0; s0 < kc; s0 += kSub) {
@@ -275,11 +275,8 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                 }
             }
             wave_lds_sync();
-            for (int kb = 0; kb < sc; kb += G) {
-                const int kk = kb + g;
-                const bool on = act && kk < sc;
-                double cval = 0.0, c1s = 0.0, c1d = 0.0, c2s = 0.0, c2d = 0.0;
-                if (on) {
+            if (act) {
+                for (int kk = g; kk < sc; kk += G) {
                     const int k = s0 + kk;
                     const double W = tg[k0 + k];
                     const double o1s = ons[0 * kPlanChunk + k], o1d = ons[1 * kPlanChunk + k];
@@ -299,7 +296,6 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                     }
                     const double cs = -as * o1s + as * o1d - o2s * bs + o2d * bs;
                     const double cd = 3.0 * ad * o1s + ad * o1d + 3.0 * o2s * bd + o2d * bd;
-                    cval = vs * cs + vd * cd - 2.0 * (as * nbs + ad * nbd);
                     const double cas = W * (vs * (o1d - o1s) - 2.0 * nbs);
                     const double cad = W * (vd * (3.0 * o1s + o1d) - 2.0 * nbd);
                     const double cbs = W * (vs * (o2d - o2s) - 2.0 * nas);
@@ -308,27 +304,22 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                     const Plan& Pb = plan[kPlanChunk + k];
                     scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
                     scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
-                    c1s = W * (-vs * as + 3.0 * vd * ad);
-                    c1d = W * (vs * as + vd * ad);
-                    c2s = W * (-vs * bs + 3.0 * vd * bd);
-                    c2d = W * (vs * bs + vd * bd);
+                    // per-node sums over the pairs (LDS ds_add_f64)
+                    atomicAdd(red + k, vs * cs + vd * cd - 2.0 * (as * nbs + ad * nbd));
+                    atomicAdd(red + kPlanChunk + k, W * (-vs * as + 3.0 * vd * ad));
+                    atomicAdd(red + 2 * kPlanChunk + k, W * (vs * as + vd * ad));
+                    atomicAdd(red + 3 * kPlanChunk + k, W * (-vs * bs + 3.0 * vd * bd));
+                    atomicAdd(red + 4 * kPlanChunk + k, W * (vs * bs + vd * bd));
                 }
-                red[lane] = cval;
-                red[kWave + lane] = c1s;
-                red[2 * kWave + lane] = c1d;
-                red[3 * kWave + lane] = c2s;
-                red[4 * kWave + lane] = c2d;
-                wave_lds_sync();
-                if (on && p == 0) {
-                    const int k = s0 + kk;
-                    atomic_add(ct + k0 + k, group_sum(red, g, ns));
-                    scatter_plan(plan[2 * kPlanChunk + k], cgs, cgd, 0, group_sum(red + kWave, g, ns),
-                                 group_sum(red + 2 * kWave, g, ns));
-                    scatter_plan(plan[3 * kPlanChunk + k], cgs, cgd, 0, group_sum(red + 3 * kWave, g, ns),
-                                 group_sum(red + 4 * kWave, g, ns));
-                }
-                wave_lds_sync();
             }
+            wave_lds_sync();
+        }
+        // flush the chunk: node weights and the two on-site vertices (pair 0)
+        if (lane < kc) {
+            atomic_add(ct + k0 + lane, red[lane]);
+            scatter_plan(plan[2 * kPlanChunk + lane], cgs, cgd, 0, red[kPlanChunk + lane], red[2 * kPlanChunk + lane]);
+            scatter_plan(plan[3 * kPlanChunk + lane], cgs, cgd, 0, red[3 * kPlanChunk + lane],
+                         red[4 * kPlanChunk + lane]);
         }
     }
 }
