@@ -306,7 +306,8 @@ k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double
 // the u and t launches add to it.
 
 constexpr int kWavesPerBlock = 4;
-constexpr int kPlanChunk = 32;   // nodes whose plans are built at once (two vectors each)
+constexpr int kPlanChunk = 32;   // s/u channels: nodes whose plans are built at once (two vectors each)
+constexpr int kTChunk = 16;      // t channel: nodes whose four plans (two vectors, two on-site) are built at once
 constexpr int kSub = 8;          // nodes per lattice-sum sub-chunk
 constexpr int kMaxPairs = 32;    // 2 register blocks of 2x4 per lane cover 32 x 32
 constexpr int kMaxFreq = 128;    // mesh copy in LDS
@@ -375,8 +376,9 @@ struct WaveLds {
     int ns;
     int sub = kSub;   // nodes per lattice-sum sub-chunk
     __host__ __device__ int nsp() const { return (ns + 3) & ~3; }
-    __host__ __device__ size_t plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
-    __host__ __device__ size_t onsite() const { return (size_t)4 * kPlanChunk * sizeof(R); }
+    __host__ __device__ size_t plans() const { return (size_t)2 * kTChunk * sizeof(PlanT<R>); }
+    __host__ __device__ size_t onsite() const { return (size_t)4 * kTChunk * sizeof(R); }
+    __host__ __device__ size_t su_plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
     __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(R); }
     __host__ __device__ size_t red() const { return (size_t)2 * kWave * sizeof(double); }
     __host__ __device__ size_t mat() const { return (((size_t)ns * ns * sizeof(double)) + 31) & ~(size_t)31; }
@@ -386,7 +388,9 @@ struct WaveLds {
         size_t b = work() > m ? work() : m;
         return (b + 31) & ~(size_t)31;
     }
-    __host__ __device__ size_t su_bytes() const { return ((plans() + 31) & ~(size_t)31) + red(); }
+    __host__ __device__ size_t su_bytes() const { return ((su_plans() + 31) & ~(size_t)31) + red(); }
+    // an area that serves both bodies (one wave doing s, u and t in turn)
+    __host__ __device__ size_t all_bytes() const { return bytes() > su_bytes() ? bytes() : su_bytes(); }
 };
 
 // Position in the channel's order of the triple handled by this wave, or -1.
@@ -474,14 +478,14 @@ __device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh,
             const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
             if (j < kc) {
                 const double om = tw[k0 + j];
+                // arguments chosen per lane, one plan construction for all
                 PlanT<R> P;
-                if (CH == 0) {
-                    if (vec == 0) make_plan(A.w, nf, ns, T.s, T.w1p - om, om - T.w2p, 0, ia, P, sh.ih);
-                    else make_plan(A.w, nf, ns, T.s, om - T.w1, om - T.w2, 0, ia, P, sh.ih);
-                } else {
-                    if (vec == 0) make_plan(A.w, nf, ns, T.w1 + om, om - T.w2p, T.u, 2, ic, P, sh.ih);
-                    else make_plan(A.w, nf, ns, T.w1p + om, T.w2 - om, T.u, 2, ic, P, sh.ih);
-                }
+                if (CH == 0)
+                    make_plan(A.w, nf, ns, T.s, vec == 0 ? T.w1p - om : om - T.w1, vec == 0 ? om - T.w2p : om - T.w2,
+                              0, ia, P, sh.ih);
+                else
+                    make_plan(A.w, nf, ns, vec == 0 ? T.w1 + om : T.w1p + om, vec == 0 ? om - T.w2p : T.w2 - om, T.u,
+                              2, ic, P, sh.ih);
                 to_bytes(P);
                 plan[vec * kPlanChunk + j] = P;
             }
@@ -579,8 +583,8 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     constexpr bool kComp = sizeof(R) == 4;
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const WaveLds<R> L{ns, SUB};
-    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                           // [2][kPlanChunk]
-    R* ons = reinterpret_cast<R*>(base + L.plans());                                // [4][kPlanChunk]
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                           // [2][kTChunk]
+    R* ons = reinterpret_cast<R*>(base + L.plans());                                // [4][kTChunk]
     R* vb = reinterpret_cast<R*>(base + L.plans() + L.onsite());                    // [4][SUB][NSP]
     double* mat = reinterpret_cast<double*>(base);                                  // [ns*ns] at the end
     const int it = T.it;
@@ -614,27 +618,29 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
 #pragma unroll
             for (int j = 0; j < 4; ++j) { ms[r][i][j] = R(0); md[r][i][j] = R(0); }
 
-    for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
-        const int kc = min(kPlanChunk, cnt - k0);
+    for (int k0 = 0; k0 < cnt; k0 += kTChunk) {
+        const int kc = min(kTChunk, cnt - k0);
         {
-            const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
+            // lane (role, j): role 0/1 the site-vector plans a/b of node j,
+            // role 2/3 the on-site vertices of the two corrections
+            const int j = lane % kTChunk, role = lane / kTChunk;
             if (j < kc) {
                 const double om = tw[k0 + j];
-                PlanT<R> P, Q;
-                if (vec == 0) {
-                    make_plan(A.w, nf, ns, T.w1 + om, t, T.w1p - om, 1, it, P, sh.ih);
-                    make_plan(A.w, nf, ns, T.w2p + om, T.w2 - om, -t, 2, it, Q, sh.ih);
-                } else {
-                    make_plan(A.w, nf, ns, om + T.w2p, t, om - T.w2, 1, it, P, sh.ih);
-                    make_plan(A.w, nf, ns, T.w1 + om, om - T.w1p, -t, 2, it, Q, sh.ih);
-                }
+                // arguments chosen per lane, one plan construction for all
+                const double a0 = role == 0 ? T.w1 + om : (role == 1 ? om + T.w2p : (role == 2 ? T.w2p + om : T.w1 + om));
+                const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
+                const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
+                PlanT<R> P;
+                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, sh.ih);
                 to_bytes(P);
-                to_bytes(Q);
-                plan[vec * kPlanChunk + j] = P;
-                R os, od;
-                eval_packed2(Q, rv, make_int2(0, 0), os, od);      // on-site pair 0
-                ons[(2 * vec + 0) * kPlanChunk + j] = os;
-                ons[(2 * vec + 1) * kPlanChunk + j] = od;
+                if (role < 2) {
+                    plan[role * kTChunk + j] = P;
+                } else {
+                    R os, od;
+                    eval_packed2(P, rv, make_int2(0, 0), os, od);      // on-site pair 0
+                    ons[(2 * (role - 2) + 0) * kTChunk + j] = os;
+                    ons[(2 * (role - 2) + 1) * kTChunk + j] = od;
+                }
             }
         }
         wave_lds_sync();
@@ -646,7 +652,7 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
                 for (int kk = g; kk < sc; kk += G) {
                     R as, ad, bs, bd;
                     eval_packed2(plan[s0 + kk], rv, pp, as, ad);
-                    eval_packed2(plan[kPlanChunk + s0 + kk], rv, pp, bs, bd);
+                    eval_packed2(plan[kTChunk + s0 + kk], rv, pp, bs, bd);
                     const R W = (R)tg[k0 + s0 + kk];
                     const R was = W * as, wad = W * ad;
                     vb[(0 * SUB + kk) * NSP + p] = was;
@@ -654,8 +660,8 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
                     vb[(2 * SUB + kk) * NSP + p] = bs;
                     vb[(3 * SUB + kk) * NSP + p] = bd;
                     const R* on = ons + s0 + kk;
-                    const R o1s = on[0 * kPlanChunk], o1d = on[1 * kPlanChunk];
-                    const R o2s = on[2 * kPlanChunk], o2d = on[3 * kPlanChunk];
+                    const R o1s = on[0 * kTChunk], o1d = on[1 * kTChunk];
+                    const R o2s = on[2 * kTChunk], o2d = on[3 * kTChunk];
                     acc_s += -was * o1s + was * o1d + W * (-o2s * bs + o2d * bs);
                     acc_d += three * wad * o1s + wad * o1d + W * (three * o2s * bd + o2d * bd);
                 }

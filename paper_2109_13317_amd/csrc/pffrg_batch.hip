@@ -366,8 +366,8 @@ pffrg_status pffrg_batch_create(int n_points, const pffrg_lattice* const* lats, 
             b->chi_cnt.push_back((int)cp.size() - b->chi_off.back());
             b->nb_chi.push_back(L->n_basis);
             max_shared = std::max(max_shared, (int)SharedLds{nf, ns, nt}.bytes(true));
-            const int wb = prec == PFFRG_FP32 ? (int)WaveLds<float>{ns, kSub}.bytes()
-                                              : (int)WaveLds<double>{ns, kSub}.bytes();
+            const int wb = prec == PFFRG_FP32 ? (int)WaveLds<float>{ns, kSub}.all_bytes()
+                                              : (int)WaveLds<double>{ns, kSub}.all_bytes();
             max_wave = std::max(max_wave, wb);
         }
         b->size = x_off;
