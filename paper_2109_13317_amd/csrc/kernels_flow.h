@@ -100,6 +100,28 @@ __device__ __forceinline__ void eval_packed2(const PlanT<R>& P, __amdgpu_buffer_
     vd = b;
 }
 
+// Two interpolations (plans Pa and Pb, pair offsets pp) with all eight corner
+// loads issued before any arithmetic, so they are in flight together.
+template <class R>
+__device__ __forceinline__ void eval_packed_ab(const PlanT<R>& Pa, const PlanT<R>& Pb, __amdgpu_buffer_rsrc_t r,
+                                               int2 pp, R& as, R& ad, R& bs, R& bd) {
+    const unsigned qa = Pa.swp ? pp.y : pp.x, qb = Pb.swp ? pp.y : pp.x;
+    V2<R> ga[4], gb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ga[i] = load_corner(r, (unsigned)Pa.off[i] + qa, R());
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gb[i] = load_corner(r, (unsigned)Pb.off[i] + qb, R());
+    R a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a0 = fmr(Pa.ws[i], ga[i].x, a0);
+        a1 = fmr(Pa.wd[i], ga[i].y, a1);
+        b0 = fmr(Pb.ws[i], gb[i].x, b0);
+        b1 = fmr(Pb.wd[i], gb[i].y, b1);
+    }
+    as = a0; ad = a1; bs = b0; bd = b1;
+}
+
 // A plan whose offsets are turned into byte offsets of the packed vertex.
 template <class R>
 __device__ __forceinline__ void to_bytes(PlanT<R>& P) {
@@ -377,7 +399,7 @@ struct WaveLds {
     int sub = kSub;   // nodes per lattice-sum sub-chunk
     __host__ __device__ int nsp() const { return (ns + 3) & ~3; }
     __host__ __device__ size_t plans() const { return (size_t)2 * kTChunk * sizeof(PlanT<R>); }
-    __host__ __device__ size_t onsite() const { return (size_t)4 * kTChunk * sizeof(R); }
+    __host__ __device__ size_t onsite() const { return (((size_t)5 * kTChunk * sizeof(R)) + 15) & ~(size_t)15; }
     __host__ __device__ size_t su_plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
     __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(R); }
     __host__ __device__ size_t red() const { return (size_t)2 * kWave * sizeof(double); }
@@ -495,11 +517,9 @@ __device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh,
             int k = g;
             for (; k + G < kc; k += 2 * G) {     // two nodes in flight
                 R as, ad, bs, bd, as2, ad2, bs2, bd2;
-                eval_packed2(plan[k], rv, pp, as, ad);
-                eval_packed2(plan[kPlanChunk + k], rv, pp, bs, bd);
-                eval_packed2(plan[k + G], rv, pp, as2, ad2);
-                eval_packed2(plan[kPlanChunk + k + G], rv, pp, bs2, bd2);
                 const R W = (R)tg[k0 + k], W2 = (R)tg[k0 + k + G];
+                eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
+                eval_packed_ab(plan[k + G], plan[kPlanChunk + k + G], rv, pp, as2, ad2, bs2, bd2);
                 acc_s = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s);
                 acc_d = fmr(W, three * as * bs + ad * bd, acc_d);
                 acc_s = fmr(W2, sgn * as2 * bs2 + as2 * bd2 + ad2 * bs2, acc_s);
@@ -507,9 +527,8 @@ __device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh,
             }
             if (k < kc) {
                 R as, ad, bs, bd;
-                eval_packed2(plan[k], rv, pp, as, ad);
-                eval_packed2(plan[kPlanChunk + k], rv, pp, bs, bd);
                 const R W = (R)tg[k0 + k];
+                eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
                 acc_s = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s);
                 acc_d = fmr(W, three * as * bs + ad * bd, acc_d);
             }
@@ -584,7 +603,8 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const WaveLds<R> L{ns, SUB};
     PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                           // [2][kTChunk]
-    R* ons = reinterpret_cast<R*>(base + L.plans());                                // [4][kTChunk]
+    R* ons = reinterpret_cast<R*>(base + L.plans());                                // [5][kTChunk]: on-site, weights
+    R* wts = ons + 4 * kTChunk;
     R* vb = reinterpret_cast<R*>(base + L.plans() + L.onsite());                    // [4][SUB][NSP]
     double* mat = reinterpret_cast<double*>(base);                                  // [ns*ns] at the end
     const int it = T.it;
@@ -635,6 +655,7 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
                 to_bytes(P);
                 if (role < 2) {
                     plan[role * kTChunk + j] = P;
+                    if (role == 0) wts[j] = (R)tg[k0 + j];
                 } else {
                     R os, od;
                     eval_packed2(P, rv, make_int2(0, 0), os, od);      // on-site pair 0
@@ -651,9 +672,8 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             if (act) {
                 for (int kk = g; kk < sc; kk += G) {
                     R as, ad, bs, bd;
-                    eval_packed2(plan[s0 + kk], rv, pp, as, ad);
-                    eval_packed2(plan[kTChunk + s0 + kk], rv, pp, bs, bd);
-                    const R W = (R)tg[k0 + s0 + kk];
+                    eval_packed_ab(plan[s0 + kk], plan[kTChunk + s0 + kk], rv, pp, as, ad, bs, bd);
+                    const R W = wts[s0 + kk];
                     const R was = W * as, wad = W * ad;
                     vb[(0 * SUB + kk) * NSP + p] = was;
                     vb[(1 * SUB + kk) * NSP + p] = wad;
