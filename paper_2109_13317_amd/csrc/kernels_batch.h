@@ -94,9 +94,12 @@ static __global__ void __launch_bounds__(kWave)
 k_batch_sigma(BatchArgs B, const double* __restrict__ lamp, const double* __restrict__ x,
               double* __restrict__ dx) {
     const int b = blockIdx.y;
-    const FlowArgs A = point_args(B, b);
+    FlowArgs A = point_args(B, b);
     const long off = B.pts[b].x_off;
-    sigma_body(A, *lamp, x + off, point_vsz(A), dx + off, blockIdx.x, threadIdx.x);
+    __shared__ MeshLds M;
+    M.load(A, x + off, nullptr, threadIdx.x);
+    A.w = M.w;
+    sigma_body(A, *lamp, M.sig, x + off, point_vsz(A), dx + off, blockIdx.x, threadIdx.x);
 }
 
 // grid (3 nf, points); dx holds d sig of each point
@@ -104,9 +107,12 @@ static __global__ void __launch_bounds__(kWave)
 k_batch_tables(BatchArgs B, const double* __restrict__ lamp, const double* __restrict__ x,
                const double* __restrict__ dx) {
     const int b = blockIdx.y;
-    const FlowArgs A = point_args(B, b);
+    FlowArgs A = point_args(B, b);
     const long off = B.pts[b].x_off;
-    tables_body(A, *lamp, x + off, dx + off, blockIdx.x, threadIdx.x);
+    __shared__ MeshLds M;
+    M.load(A, x + off, dx + off, threadIdx.x);
+    A.w = M.w;
+    tables_body(A, *lamp, M.sig, M.dsig, blockIdx.x, threadIdx.x);
 }
 
 // grid (blocks, points): the packed vertex of every point

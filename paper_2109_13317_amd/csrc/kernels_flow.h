@@ -152,8 +152,10 @@ struct CompSum {
 
 // d sig/d Lambda (w_n) = (1/2pi) sum_{x=+-Lambda} F(w_n, x) / (x - sig(x)),
 // F = 2 sum_r mult_r Gd_r(w+x, 0, w-x) - 3 Gs_0(w+x, x-w, 0) - Gd_0(w+x, x-w, 0).
-__device__ __forceinline__ void sigma_body(const FlowArgs& A, double lam, const double* __restrict__ x, long nv,
-                                           double* __restrict__ dsig, int n, int lane) {
+// sig: the self-energy values (may be an LDS copy of x[0 .. nf)).
+__device__ __forceinline__ void sigma_body(const FlowArgs& A, double lam, const double* __restrict__ sig,
+                                           const double* __restrict__ x, long nv, double* __restrict__ dsig,
+                                           int n, int lane) {
     const double wn = A.w[n];
     const double* gs = x + A.nf;
     const double* gd = gs + nv;
@@ -174,14 +176,31 @@ __device__ __forceinline__ void sigma_body(const FlowArgs& A, double lam, const 
         double os, od;
         eval_plan(Q, gs, gd, A.swap, 0, os, od);
         f -= 3.0 * os + od;
-        acc += f / (xx - odd_interp(A.w, A.nf, x, xx));
+        acc += f / (xx - odd_interp(A.w, A.nf, sig, xx));
     }
     if (lane == 0) dsig[n] = acc * kInvTwoPi;
 }
 
+// Mesh, self-energy and (optionally) its derivative copied to LDS by one
+// wave: the binary searches of the look-ups then never touch memory.
+struct MeshLds {
+    double w[128], sig[128], dsig[128];
+    __device__ __forceinline__ void load(const FlowArgs& A, const double* sig_g, const double* dsig_g, int lane) {
+        for (int i = lane; i < A.nf; i += kWave) {
+            w[i] = A.w[i];
+            sig[i] = sig_g[i];
+            if (dsig_g) dsig[i] = dsig_g[i];
+        }
+        __syncthreads();
+    }
+};
+
 static __global__ void __launch_bounds__(kWave)
 k_sigma_rhs(FlowArgs A, double lam, const double* __restrict__ x, long nv, double* __restrict__ dsig) {
-    sigma_body(A, lam, x, nv, dsig, blockIdx.x, threadIdx.x);
+    __shared__ MeshLds M;
+    M.load(A, x, nullptr, threadIdx.x);
+    A.w = M.w;
+    sigma_body(A, lam, M.sig, x, nv, dsig, blockIdx.x, threadIdx.x);
 }
 
 template <class R>
@@ -316,7 +335,10 @@ __device__ __forceinline__ void tables_body(const FlowArgs& A, double lam, const
 
 static __global__ void __launch_bounds__(kWave)
 k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double* __restrict__ dsig) {
-    tables_body(A, lam, x, dsig, blockIdx.x, threadIdx.x);
+    __shared__ MeshLds M;
+    M.load(A, x, dsig, threadIdx.x);
+    A.w = M.w;
+    tables_body(A, lam, M.sig, M.dsig, blockIdx.x, threadIdx.x);
 }
 
 // ------------------------------------------------------------- vertex RHS -

@@ -14,51 +14,76 @@
 
 namespace pffrg {
 
-// One thread: nodes, trapezoid weights and g^2 of the correlation integrals.
-static __global__ void k_chi_nodes(const double* __restrict__ w, int nf, double lam,
-                            const double* __restrict__ x, double* __restrict__ cw,
-                            double* __restrict__ cq, double* __restrict__ cg2, int* __restrict__ cn) {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const double wmax = w[nf - 1];
+constexpr int kMaxMesh = 128;     // largest mesh (LDS copies)
+
+// One wave: nodes, trapezoid weights and g^2 of the correlation integrals
+// (mesh and self-energy staged in LDS; lanes fill the node list).
+static __global__ void __launch_bounds__(64)
+k_chi_nodes(const double* __restrict__ w, int nf, double lam, const double* __restrict__ x,
+            double* __restrict__ cw, double* __restrict__ cq, double* __restrict__ cg2, int* __restrict__ cn) {
+    __shared__ double sw[kMaxMesh], ss[kMaxMesh];
+    const int lane = threadIdx.x;
+    for (int i = lane; i < nf; i += 64) { sw[i] = w[i]; ss[i] = x[i]; }
+    __syncthreads();
+    const double wmax = sw[nf - 1];
     const double lo2[2] = {-wmax, lam}, hi2[2] = {-lam, wmax};
     int n = 0;
     for (int q = 0; q < 2; ++q) {
         const double lo = lo2[q], hi = hi2[q];
         if (!(lo < hi)) continue;
-        const int first = n;
-        cw[n++] = lo;
-        for (int i = 0; i < 2 * nf; ++i) {
-            const double v = i < nf ? -w[nf - 1 - i] : w[i - nf];
-            if (v > lo && v < hi) cw[n++] = v;
+        // mesh points inside (lo, hi): a contiguous run of the full mesh
+        int below = 0, cnt = 0;
+        for (int i = lane; i < 2 * nf; i += 64) {
+            const double v = i < nf ? -sw[nf - 1 - i] : sw[i - nf];
+            below += v <= lo;
+            cnt += (v > lo && v < hi);
         }
-        cw[n++] = hi;
-        for (int i = first; i < n; ++i) {
-            const double wl = i > first ? 0.5 * (cw[i] - cw[i - 1]) : 0.0;
-            const double wr = i + 1 < n ? 0.5 * (cw[i + 1] - cw[i]) : 0.0;
-            cq[i] = wl + wr;
-            const double g = 1.0 / (cw[i] - odd_interp(w, nf, x, cw[i]));
-            cg2[i] = g * g;
+        for (int o = 32; o > 0; o >>= 1) {
+            below += __shfl_xor(below, o, 64);
+            cnt += __shfl_xor(cnt, o, 64);
         }
+        const int m = cnt + 2;
+        for (int j = lane; j < m; j += 64) {
+            auto node = [&](int jj) {
+                if (jj == 0) return lo;
+                if (jj == m - 1) return hi;
+                const int i = below + jj - 1;
+                return i < nf ? -sw[nf - 1 - i] : sw[i - nf];
+            };
+            const double cur = node(j);
+            const double wl = j > 0 ? 0.5 * (cur - node(j - 1)) : 0.0;
+            const double wr = j + 1 < m ? 0.5 * (node(j + 1) - cur) : 0.0;
+            cw[n + j] = cur;
+            cq[n + j] = wl + wr;
+            const double g = 1.0 / (cur - odd_interp(sw, nf, ss, cur));
+            cg2[n + j] = g * g;
+        }
+        n += m;
     }
-    *cn = n;
+    if (lane == 0) *cn = n;
 }
 
 constexpr int kChiThreads = 256;
 
-// One workgroup per pair p: chi^{zz}_p, chi^{00}_p into chi[p], chi[ns + p].
+// Workgroup (p, slice): the part of the double integral of pair p over the
+// node pairs e = (i, j) of its slice; part[(p * slices + slice) * 2 + {0,1}].
+constexpr int kChiSlices = 16;
+
 static __global__ void __launch_bounds__(kChiThreads)
 k_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restrict__ swap,
             const double* __restrict__ x, const double* __restrict__ cw,
             const double* __restrict__ cq, const double* __restrict__ cg2,
-            const int* __restrict__ cn, double* __restrict__ chi) {
+            const int* __restrict__ cn, double* __restrict__ part) {
     __shared__ double rz[kChiThreads], rd[kChiThreads];
-    const int p = blockIdx.x, tid = threadIdx.x;
+    const int p = blockIdx.x, sl = blockIdx.y, tid = threadIdx.x;
     const int n = *cn;
     const long vsz = (long)nf * (nf + 1) / 2 * nf * ns;
     const double* gs = x + nf;
     const double* gd = gs + vsz;
+    const int nn = n * n;
+    const int e0 = (int)((long)nn * sl / kChiSlices), e1 = (int)((long)nn * (sl + 1) / kChiSlices);
     double az = 0.0, ad = 0.0;
-    for (int e = tid; e < n * n; e += kChiThreads) {
+    for (int e = e0 + tid; e < e1; e += kChiThreads) {
         const int i = e / n, j = e % n;
         const double w1 = cw[i], w2 = cw[j];
         const double f = cq[i] * cq[j] * cg2[i] * cg2[j];
@@ -85,33 +110,51 @@ k_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restrict_
         __syncthreads();
     }
     if (tid == 0) {
-        const double pref = 1.0 / (16.0 * M_PI * M_PI);
-        double z = -pref * rz[0], d = -pref * rd[0];
-        if (p == 0) {
-            double b = 0.0;
-            for (int i = 0; i < n; ++i) b = fma(cq[i], cg2[i], b);
-            b *= 0.5 * kInvTwoPi;        // 1/(4 pi)
-            z += b;
-            d += b;
-        }
-        chi[p] = z;
-        chi[ns + p] = d;
+        part[(p * kChiSlices + sl) * 2 + 0] = rz[0];
+        part[(p * kChiSlices + sl) * 2 + 1] = rd[0];
     }
 }
 
-// chi(k_q) = (1/nb) sum_{b, j} cos(k_q . dr_bj) 3 chi^{zz}_{pair(b,j)}
-static __global__ void k_chi_k(int nterm, const int* __restrict__ pair, const double* __restrict__ dr,
-                        double inv_nb, const double* __restrict__ chi, int nk,
-                        const double* __restrict__ kp, double* __restrict__ out) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+// chi[p], chi[ns + p] from the slices, with the on-site one-loop term.
+static __global__ void k_chi_final(int ns, const double* __restrict__ cq, const double* __restrict__ cg2,
+                                   const int* __restrict__ cn, const double* __restrict__ part,
+                                   double* __restrict__ chi) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ns) return;
+    double sz = 0.0, sd = 0.0;
+    for (int sl = 0; sl < kChiSlices; ++sl) {
+        sz += part[(p * kChiSlices + sl) * 2 + 0];
+        sd += part[(p * kChiSlices + sl) * 2 + 1];
+    }
+    const double pref = 1.0 / (16.0 * M_PI * M_PI);
+    double z = -pref * sz, d = -pref * sd;
+    if (p == 0) {
+        double b = 0.0;
+        for (int i = 0; i < *cn; ++i) b = fma(cq[i], cg2[i], b);
+        b *= 0.5 * kInvTwoPi;        // 1/(4 pi)
+        z += b;
+        d += b;
+    }
+    chi[p] = z;
+    chi[ns + p] = d;
+}
+
+// chi(k_q) = (1/nb) sum_{b, j} cos(k_q . dr_bj) 3 chi^{zz}_{pair(b,j)};
+// one wave per k point, lanes over the (basis, site) terms.
+constexpr int kChiKWaves = 4;
+static __global__ void __launch_bounds__(64 * kChiKWaves)
+k_chi_k(int nterm, const int* __restrict__ pair, const double* __restrict__ dr, double inv_nb,
+        const double* __restrict__ chi, int nk, const double* __restrict__ kp, double* __restrict__ out) {
+    const int q = blockIdx.x * kChiKWaves + threadIdx.x / 64, lane = threadIdx.x % 64;
     if (q >= nk) return;
     const double kx = kp[3 * q], ky = kp[3 * q + 1], kz = kp[3 * q + 2];
     double acc = 0.0;
-    for (int i = 0; i < nterm; ++i) {
+    for (int i = lane; i < nterm; i += 64) {
         const double ph = kx * dr[3 * i] + ky * dr[3 * i + 1] + kz * dr[3 * i + 2];
         acc = fma(cos(ph), chi[pair[i]], acc);
     }
-    out[q] = 3.0 * inv_nb * acc;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[q] = 3.0 * inv_nb * acc;
 }
 
 // ------------------------------------------------------- Runge-Kutta ----

@@ -59,6 +59,7 @@ struct pffrg_ctx {
     double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
     int* cn = nullptr;
     double* chi = nullptr;          // [2*ns]
+    double* chi_part = nullptr;     // [ns * kChiSlices * 2] partial double integrals
     double* part = nullptr;         // [2*kRedBlocks]
     double* red = nullptr;          // [2]
     double* host_red = nullptr;     // pinned [2]
@@ -389,7 +390,7 @@ pffrg_status rhs_vjp(pffrg_ctx* c, double lam, const double* x, const double* v,
 
 // out = (d chi / d x)^T cchi at (lam, x).
 pffrg_status chi_vjp(pffrg_ctx* c, double lam, const double* x, const double* cchi, double* out) {
-    hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(1), 0, c->stream, (const double*)c->w, c->nf, lam, x, c->cw, c->cq,
+    hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(64), 0, c->stream, (const double*)c->w, c->nf, lam, x, c->cw, c->cq,
                        c->cg2, c->cn);
     TRY(launch_check("k_chi_nodes"));
     TRY(fill(c, out, c->size, 0.0));
@@ -571,6 +572,7 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->cg2, (size_t)c->nq));
         TRY(dev_alloc(c, &c->cn, 1));
         TRY(dev_alloc(c, &c->chi, (size_t)2 * ns));
+        TRY(dev_alloc(c, &c->chi_part, (size_t)2 * ns * kChiSlices));
         TRY(dev_alloc(c, &c->part, (size_t)2 * kRedBlocks));
         TRY(dev_alloc(c, &c->red, 2));
         TRY(dev_alloc(c, &c->ctg, (size_t)3 * nf * c->nq));
@@ -651,20 +653,23 @@ pffrg_status pffrg_chi(pffrg_ctx* c, double lambda, const double* x, double* chi
     TRY(check_ctx(c));
     if (!x || !chi) return fail(PFFRG_EINVAL, "null pointer");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
-    hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(1), 0, c->stream, (const double*)c->w, c->nf, lambda, x, c->cw,
+    hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(64), 0, c->stream, (const double*)c->w, c->nf, lambda, x, c->cw,
                        c->cq, c->cg2, c->cn);
     TRY(launch_check("k_chi_nodes"));
-    hipLaunchKernelGGL(k_chi_pairs, dim3(c->ns), dim3(kChiThreads), 0, c->stream, (const double*)c->w, c->nf, c->ns,
-                       (const int*)c->swap, x, (const double*)c->cw, (const double*)c->cq,
-                       (const double*)c->cg2, (const int*)c->cn, chi);
-    return launch_check("k_chi_pairs");
+    hipLaunchKernelGGL(k_chi_pairs, dim3(c->ns, kChiSlices), dim3(kChiThreads), 0, c->stream, (const double*)c->w,
+                       c->nf, c->ns, (const int*)c->swap, x, (const double*)c->cw, (const double*)c->cq,
+                       (const double*)c->cg2, (const int*)c->cn, c->chi_part);
+    TRY(launch_check("k_chi_pairs"));
+    hipLaunchKernelGGL(k_chi_final, dim3(1), dim3(64), 0, c->stream, c->ns, (const double*)c->cq,
+                       (const double*)c->cg2, (const int*)c->cn, (const double*)c->chi_part, chi);
+    return launch_check("k_chi_final");
 }
 
 pffrg_status pffrg_chi_k(pffrg_ctx* c, const double* chi, int nk, const double* kp, double* out) {
     TRY(check_ctx(c));
     if (nk < 0 || (nk > 0 && (!chi || !kp || !out))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
     if (nk == 0) return PFFRG_OK;
-    hipLaunchKernelGGL(k_chi_k, dim3((nk + 127) / 128), dim3(128), 0, c->stream, c->nterm,
+    hipLaunchKernelGGL(k_chi_k, dim3((nk + kChiKWaves - 1) / kChiKWaves), dim3(64 * kChiKWaves), 0, c->stream, c->nterm,
                        (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, chi, nk, kp, out);
     return launch_check("k_chi_k");
 }

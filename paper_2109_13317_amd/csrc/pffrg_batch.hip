@@ -72,6 +72,7 @@ struct pffrg_batch {
     double* chi_dr = nullptr;
     double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
     int* cn = nullptr;
+    double* chi_part = nullptr;        // [max ns * kChiSlices * 2]
     int* tab_n = nullptr;
     double *tab_w = nullptr, *tab_g = nullptr;
     void* gv = nullptr;
@@ -396,6 +397,7 @@ pffrg_status pffrg_batch_create(int n_points, const pffrg_lattice* const* lats, 
         TRY(b->mem.alloc(&b->cq, (size_t)b->nq));
         TRY(b->mem.alloc(&b->cg2, (size_t)b->nq));
         TRY(b->mem.alloc(&b->cn, 1));
+        TRY(b->mem.alloc(&b->chi_part, (size_t)2 * kChiSlices * *std::max_element(b->ns.begin(), b->ns.end())));
         TRY(b->mem.alloc(&b->tab_n, (size_t)n_points * 3 * nf));
         TRY(b->mem.alloc(&b->tab_w, (size_t)n_points * 3 * nf * b->nq));
         TRY(b->mem.alloc(&b->tab_g, (size_t)n_points * 3 * nf * b->nq));
@@ -502,13 +504,17 @@ pffrg_status pffrg_batch_chi(pffrg_batch* b, double lambda, const double* x, dou
     long co = 0;
     for (int p = 0; p < b->np; ++p) {
         const double* xp = x + b->pts[p].x_off;
-        hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(1), 0, b->stream, (const double*)b->w, b->nf, lambda, xp, b->cw,
+        hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(64), 0, b->stream, (const double*)b->w, b->nf, lambda, xp, b->cw,
                            b->cq, b->cg2, b->cn);
         TRY(launch_check("k_chi_nodes"));
-        hipLaunchKernelGGL(k_chi_pairs, dim3(b->ns[p]), dim3(kChiThreads), 0, b->stream, (const double*)b->w, b->nf,
-                           b->ns[p], (const int*)(b->swap + b->pts[p].pair_off), xp, (const double*)b->cw,
-                           (const double*)b->cq, (const double*)b->cg2, (const int*)b->cn, chi + co);
+        hipLaunchKernelGGL(k_chi_pairs, dim3(b->ns[p], kChiSlices), dim3(kChiThreads), 0, b->stream,
+                           (const double*)b->w, b->nf, b->ns[p], (const int*)(b->swap + b->pts[p].pair_off), xp,
+                           (const double*)b->cw, (const double*)b->cq, (const double*)b->cg2, (const int*)b->cn,
+                           b->chi_part);
         TRY(launch_check("k_chi_pairs"));
+        hipLaunchKernelGGL(k_chi_final, dim3(1), dim3(64), 0, b->stream, b->ns[p], (const double*)b->cq,
+                           (const double*)b->cg2, (const int*)b->cn, (const double*)b->chi_part, chi + co);
+        TRY(launch_check("k_chi_final"));
         co += 2 * b->ns[p];
     }
     return PFFRG_OK;
@@ -519,7 +525,8 @@ pffrg_status pffrg_batch_chi_k(pffrg_batch* b, int point, const double* chi, int
     if (point < 0 || point >= b->np) return fail(PFFRG_EINVAL, "point out of range");
     if (nk < 0 || (nk > 0 && (!chi || !kp || !out))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
     if (nk == 0) return PFFRG_OK;
-    hipLaunchKernelGGL(k_chi_k, dim3((nk + 127) / 128), dim3(128), 0, b->stream, b->chi_cnt[point],
+    hipLaunchKernelGGL(k_chi_k, dim3((nk + kChiKWaves - 1) / kChiKWaves), dim3(64 * kChiKWaves), 0, b->stream,
+                       b->chi_cnt[point],
                        (const int*)(b->chi_pair + b->chi_off[point]), (const double*)(b->chi_dr + 3L * b->chi_off[point]),
                        1.0 / b->nb_chi[point], chi, nk, kp, out);
     return launch_check("k_chi_k");
