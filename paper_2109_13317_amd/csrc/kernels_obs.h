@@ -217,12 +217,21 @@ k_err_norm(long n, const double* __restrict__ x, const double* __restrict__ y,
     if (threadIdx.x == 0) { part[2 * blockIdx.x] = sm[0]; part[2 * blockIdx.x + 1] = sf[0]; }
 }
 
-static __global__ void k_err_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one wave
+static __global__ void __launch_bounds__(64)
+k_err_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
+    if (blockIdx.x != 0) return;
+    const int lane = threadIdx.x;
     double m = 0.0, bad = 0.0;
-    for (int b = 0; b < nb; ++b) { m = fmax(m, part[2 * b]); bad = fmax(bad, part[2 * b + 1]); }
-    out[0] = m;
-    out[1] = bad;
+    for (int b = lane; b < nb; b += 64) { m = fmax(m, part[2 * b]); bad = fmax(bad, part[2 * b + 1]); }
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, 64));
+        bad = fmax(bad, __shfl_xor(bad, o, 64));
+    }
+    if (lane == 0) {
+        out[0] = m;
+        out[1] = bad;
+    }
 }
 
 static __global__ void k_init_state(long n, int nf, int ns, const double* __restrict__ coupling,

@@ -219,7 +219,7 @@ pffrg_status reduce_err(pffrg_ctx* c, const double* x, const double* y, const do
     hipLaunchKernelGGL(k_err_norm, dim3(kRedBlocks), dim3(kRedThreads), 0, c->stream, (long)c->size, x, y, e,
                        atol, rtol, c->part);
     TRY(launch_check("k_err_norm"));
-    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(1), 0, c->stream, kRedBlocks, (const double*)c->part, c->red);
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, c->stream, kRedBlocks, (const double*)c->part, c->red);
     TRY(launch_check("k_err_final"));
     HIP_TRY(hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -283,7 +283,7 @@ pffrg_status finite_points(pffrg_batch* b, const double* x, int* ok) {
         hipLaunchKernelGGL(k_err_norm, dim3(64), dim3(kRedThreads), 0, b->stream, n, (const double*)nullptr,
                            x + off, (const double*)nullptr, 0.0, 0.0, b->part);
         TRY(launch_check("k_err_norm"));
-        hipLaunchKernelGGL(k_err_final, dim3(1), dim3(1), 0, b->stream, 64, (const double*)b->part, b->red + 2 * p);
+        hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, b->stream, 64, (const double*)b->part, b->red + 2 * p);
         TRY(launch_check("k_err_final"));
     }
     HIP_TRY(hipMemcpyAsync(b->host_red, b->red, sizeof(double) * 2 * b->np, hipMemcpyDeviceToHost, b->stream));
