@@ -537,17 +537,7 @@ __device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh,
         wave_lds_sync();
         if (act) {
             int k = g;
-            for (; k + G < kc; k += 2 * G) {     // two nodes in flight
-                R as, ad, bs, bd, as2, ad2, bs2, bd2;
-                const R W = (R)tg[k0 + k], W2 = (R)tg[k0 + k + G];
-                eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
-                eval_packed_ab(plan[k + G], plan[kPlanChunk + k + G], rv, pp, as2, ad2, bs2, bd2);
-                acc_s = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s);
-                acc_d = fmr(W, three * as * bs + ad * bd, acc_d);
-                acc_s = fmr(W2, sgn * as2 * bs2 + as2 * bd2 + ad2 * bs2, acc_s);
-                acc_d = fmr(W2, three * as2 * bs2 + ad2 * bd2, acc_d);
-            }
-            if (k < kc) {
+            for (; k < kc; k += G) {
                 R as, ad, bs, bd;
                 const R W = (R)tg[k0 + k];
                 eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
