@@ -79,11 +79,24 @@ struct AdjWaveLds {
     __host__ __device__ static constexpr size_t bytes() { return ((plans() + red()) + 31) & ~(size_t)31; }
 };
 
+// The vertex-channel products scatter into one of kCotCopies copies of the
+// vertex cotangent (copies copy_stride doubles apart), which spreads the
+// atomic adds that land on one element over several addresses.  The copy is
+// the workgroup's slot within its XCD (workgroup index / 8) modulo
+// kCotCopies, so neighbouring workgroups of one XCD, which work on nearby
+// triples and hit the same elements, use different copies.  k_sum_copies
+// adds the copies up.
+constexpr int kCotCopies = 16;
+
+__device__ __forceinline__ long cot_copy(long stride) { return (long)((blockIdx.x / 8) % kCotCopies) * stride; }
+
 template <int CH>
 static __global__ void __launch_bounds__(kWave * kAdjWaves)
 k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict__ uo_a,
                 const int* __restrict__ uo_c, int n_triples, const double* __restrict__ v,
-                double* __restrict__ cgs, double* __restrict__ cgd, double* __restrict__ ctg) {
+                double* __restrict__ cgs, double* __restrict__ cgd, long copy_stride, double* __restrict__ ctg) {
+    cgs += cot_copy(copy_stride);
+    cgd += cot_copy(copy_stride);
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, false);
@@ -181,7 +194,9 @@ struct AdjTLds {
 static __global__ void __launch_bounds__(kWave)
 k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const int* __restrict__ rpat_off,
                const int* __restrict__ rpat_ent, const double* __restrict__ v, double* __restrict__ cgs,
-               double* __restrict__ cgd, double* __restrict__ ctg) {
+               double* __restrict__ cgd, long copy_stride, double* __restrict__ ctg) {
+    cgs += cot_copy(copy_stride);
+    cgd += cot_copy(copy_stride);
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, false);
@@ -494,6 +509,16 @@ k_coupling_grad(long n_el, int ns, const double* __restrict__ cgs, double* __res
         __syncthreads();
     }
     if (threadIdx.x == 0) out[p] = 0.25 * red[0];
+}
+
+// y[i] += sum over the copies of c[copy * stride + i], i < n.
+static __global__ void k_sum_copies(long n, long stride, const double* __restrict__ c, double* __restrict__ y) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double acc = y[i];
+#pragma unroll
+        for (int k = 0; k < kCotCopies; ++k) acc += c[k * stride + i];
+        y[i] = acc;
+    }
 }
 
 // y += alpha * a (elementwise).

@@ -70,6 +70,7 @@ struct pffrg_ctx {
     double* cdsig = nullptr;        // [nf] cotangent of d sig / d Lambda
     double* cot_g2 = nullptr;       // [nq] cotangent of g^2 at the correlation nodes
     double* cchi = nullptr;         // [2*ns]
+    double* cot_copies = nullptr;   // [kCotCopies * 2 * vsz] spread vertex cotangents
 
     std::vector<void*> allocs;
 
@@ -361,25 +362,32 @@ pffrg_status rhs_vjp(pffrg_ctx* c, double lam, const double* x, const double* v,
     TRY(axpy(c, c->nf, 1.0, v, c->cdsig));
     double* cgs = out + c->nf;
     double* cgd = cgs + c->vsz;
+    const long cstride = 2 * c->vsz;
+    TRY(fill(c, c->cot_copies, kCotCopies * cstride, 0.0));
+    double* kgs = c->cot_copies;
+    double* kgd = kgs + c->vsz;
     const int T = c->nsu * c->nf;
     {
         const int blocks = (T + kAdjWaves - 1) / kAdjWaves;
         const int per = (blocks + 7) / 8;
         const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + kAdjWaves * AdjWaveLds::bytes();
         hipLaunchKernelGGL(k_vertex_vjp_su<0>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
-                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, cgs, cgd, c->ctg);
+                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_su"));
         hipLaunchKernelGGL(k_vertex_vjp_su<2>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
-                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, cgs, cgd, c->ctg);
+                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_su"));
     }
     {
         const int per = (T + 7) / 8;
         const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + AdjTLds{c->ns}.bytes();
         hipLaunchKernelGGL(k_vertex_vjp_t, dim3(8 * per), dim3(kWave), lds, c->stream, A, x, T,
-                           (const int*)c->rpat_off, (const int*)c->rpat_ent, v, cgs, cgd, c->ctg);
+                           (const int*)c->rpat_off, (const int*)c->rpat_ent, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_t"));
     }
+    hipLaunchKernelGGL(k_sum_copies, dim3(grid_for(cstride, 256)), dim3(256), 0, c->stream, cstride, cstride,
+                       (const double*)c->cot_copies, cgs);
+    TRY(launch_check("k_sum_copies"));
     hipLaunchKernelGGL(k_tables_vjp, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)c->dsig,
                        (const double*)c->ctg, out, c->cdsig);
     TRY(launch_check("k_tables_vjp"));
@@ -579,6 +587,7 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->cdsig, (size_t)nf));
         TRY(dev_alloc(c, &c->cot_g2, (size_t)c->nq));
         TRY(dev_alloc(c, &c->cchi, (size_t)2 * ns));
+        TRY(dev_alloc(c, &c->cot_copies, (size_t)kCotCopies * 2 * c->vsz));
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
         if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
