@@ -175,15 +175,17 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict_
 
 // ---------------------------------------------------------------- t ----
 
-// Per-wave LDS of the t-channel product, one wave per workgroup.
+// Per-wave LDS of the t-channel product, one wave per workgroup; plans are
+// built kAdjTChunk nodes at a time, one plan per lane (4 per node).
+constexpr int kAdjTChunk = kWave / 4;
 struct AdjTLds {
     int ns;
-    __host__ __device__ size_t plans() const { return (size_t)4 * kPlanChunk * sizeof(Plan); }   // Pa Pb Q1 Q2
-    __host__ __device__ size_t ons() const { return (size_t)4 * kPlanChunk * sizeof(double); }
+    __host__ __device__ size_t plans() const { return (size_t)4 * kAdjTChunk * sizeof(Plan); }   // Pa Pb Q1 Q2
+    __host__ __device__ size_t ons() const { return (size_t)4 * kAdjTChunk * sizeof(double); }
     __host__ __device__ size_t vb() const { return (size_t)4 * kSub * ns * sizeof(double); }
     __host__ __device__ size_t nmat() const { return (size_t)2 * ns * ns * sizeof(double); }
     __host__ __device__ size_t vin() const { return (size_t)2 * ns * sizeof(double); }
-    __host__ __device__ size_t red() const { return (size_t)5 * kPlanChunk * sizeof(double); }
+    __host__ __device__ size_t red() const { return (size_t)5 * kAdjTChunk * sizeof(double); }
     __host__ __device__ size_t bytes() const {
         return ((plans() + ons() + vb() + nmat() + vin() + red()) + 31) & ~(size_t)31;
     }
@@ -204,12 +206,12 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
     const int lane = threadIdx.x;
     const AdjTLds L{ns};
     unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false);
-    Plan* plan = reinterpret_cast<Plan*>(base);                                          // [4][kPlanChunk]
-    double* ons = reinterpret_cast<double*>(base + L.plans());                           // [4][kPlanChunk]
+    Plan* plan = reinterpret_cast<Plan*>(base);                                          // [4][kAdjTChunk]
+    double* ons = reinterpret_cast<double*>(base + L.plans());                           // [4][kAdjTChunk]
     double* vb = reinterpret_cast<double*>(base + L.plans() + L.ons());                  // [4][kSub][ns]
     double* nm = reinterpret_cast<double*>(base + L.plans() + L.ons() + L.vb());         // [2][ns*ns]
     double* vin = nm + 2 * ns * ns;                                                      // [2][ns]
-    double* red = vin + 2 * ns;                                                          // [5][kPlanChunk]
+    double* red = vin + 2 * ns;                                                          // [5][kAdjTChunk]
     const int per = gridDim.x / 8;
     const int o = __builtin_amdgcn_readfirstlane((int)((blockIdx.x % 8) * per + blockIdx.x / 8));
     if (o >= n_triples) return;
@@ -251,29 +253,29 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
     double* ct = ctg + (long)(1 * nf + it) * nq;
 
-    for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
-        const int kc = min(kPlanChunk, cnt - k0);
+    for (int k0 = 0; k0 < cnt; k0 += kAdjTChunk) {
+        const int kc = min(kAdjTChunk, cnt - k0);
         wave_lds_sync();
         {
-            const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
+            // lane (role, j): role 0/1 the site-vector plans a/b of node j,
+            // role 2/3 the on-site plans of the two corrections (kAdjTChunk = 16)
+            const int j = lane % kAdjTChunk, role = lane / kAdjTChunk;
             if (j < kc) {
                 const double om = tw[k0 + j];
-                Plan P, Q;
-                if (vec == 0) {
-                    make_plan(A.w, nf, ns, T.w1 + om, t, T.w1p - om, 1, it, P, sh.ih);
-                    make_plan(A.w, nf, ns, T.w2p + om, T.w2 - om, -t, 2, it, Q, sh.ih);
-                } else {
-                    make_plan(A.w, nf, ns, om + T.w2p, t, om - T.w2, 1, it, P, sh.ih);
-                    make_plan(A.w, nf, ns, T.w1 + om, om - T.w1p, -t, 2, it, Q, sh.ih);
+                const double a0 = role == 0 ? T.w1 + om : (role == 1 ? om + T.w2p : (role == 2 ? T.w2p + om : T.w1 + om));
+                const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
+                const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
+                Plan P;
+                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, sh.ih);
+                plan[role * kAdjTChunk + j] = P;
+                if (role >= 2) {
+                    double os, od;
+                    eval_plan(P, gs, gd, sh.swap, 0, os, od);
+                    ons[(2 * (role - 2) + 0) * kAdjTChunk + j] = os;
+                    ons[(2 * (role - 2) + 1) * kAdjTChunk + j] = od;
                 }
-                plan[vec * kPlanChunk + j] = P;
-                plan[(2 + vec) * kPlanChunk + j] = Q;
-                double os, od;
-                eval_plan(Q, gs, gd, sh.swap, 0, os, od);
-                ons[(2 * vec + 0) * kPlanChunk + j] = os;
-                ons[(2 * vec + 1) * kPlanChunk + j] = od;
             }
-            for (int i = lane; i < 5 * kPlanChunk; i += kWave) red[i] = 0.0;
+            for (int i = lane; i < 5 * kAdjTChunk; i += kWave) red[i] = 0.0;
         }
         wave_lds_sync();
         for (int s0 = 0; s0 < kc; s0 += kSub) {
@@ -282,7 +284,7 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                 for (int kk = g; kk < sc; kk += G) {
                     double as, ad, bs, bd;
                     eval_plan(plan[s0 + kk], gs, gd, sh.swap, p, as, ad);
-                    eval_plan(plan[kPlanChunk + s0 + kk], gs, gd, sh.swap, p, bs, bd);
+                    eval_plan(plan[kAdjTChunk + s0 + kk], gs, gd, sh.swap, p, bs, bd);
                     vb[(0 * kSub + kk) * ns + p] = as;
                     vb[(1 * kSub + kk) * ns + p] = ad;
                     vb[(2 * kSub + kk) * ns + p] = bs;
@@ -294,8 +296,8 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                 for (int kk = g; kk < sc; kk += G) {
                     const int k = s0 + kk;
                     const double W = tg[k0 + k];
-                    const double o1s = ons[0 * kPlanChunk + k], o1d = ons[1 * kPlanChunk + k];
-                    const double o2s = ons[2 * kPlanChunk + k], o2d = ons[3 * kPlanChunk + k];
+                    const double o1s = ons[0 * kAdjTChunk + k], o1d = ons[1 * kAdjTChunk + k];
+                    const double o2s = ons[2 * kAdjTChunk + k], o2d = ons[3 * kAdjTChunk + k];
                     const double* ra = vb + (0 * kSub + kk) * ns;
                     const double* rad = vb + (1 * kSub + kk) * ns;
                     const double* rb = vb + (2 * kSub + kk) * ns;
@@ -316,15 +318,15 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                     const double cbs = W * (vs * (o2d - o2s) - 2.0 * nas);
                     const double cbd = W * (vd * (3.0 * o2s + o2d) - 2.0 * nad);
                     const Plan& Pa = plan[k];
-                    const Plan& Pb = plan[kPlanChunk + k];
+                    const Plan& Pb = plan[kAdjTChunk + k];
                     scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
                     scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
                     // per-node sums over the pairs (LDS ds_add_f64)
                     atomicAdd(red + k, vs * cs + vd * cd - 2.0 * (as * nbs + ad * nbd));
-                    atomicAdd(red + kPlanChunk + k, W * (-vs * as + 3.0 * vd * ad));
-                    atomicAdd(red + 2 * kPlanChunk + k, W * (vs * as + vd * ad));
-                    atomicAdd(red + 3 * kPlanChunk + k, W * (-vs * bs + 3.0 * vd * bd));
-                    atomicAdd(red + 4 * kPlanChunk + k, W * (vs * bs + vd * bd));
+                    atomicAdd(red + kAdjTChunk + k, W * (-vs * as + 3.0 * vd * ad));
+                    atomicAdd(red + 2 * kAdjTChunk + k, W * (vs * as + vd * ad));
+                    atomicAdd(red + 3 * kAdjTChunk + k, W * (-vs * bs + 3.0 * vd * bd));
+                    atomicAdd(red + 4 * kAdjTChunk + k, W * (vs * bs + vd * bd));
                 }
             }
             wave_lds_sync();
@@ -332,9 +334,9 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
         // flush the chunk: node weights and the two on-site vertices (pair 0)
         if (lane < kc) {
             atomic_add(ct + k0 + lane, red[lane]);
-            scatter_plan(plan[2 * kPlanChunk + lane], cgs, cgd, 0, red[kPlanChunk + lane], red[2 * kPlanChunk + lane]);
-            scatter_plan(plan[3 * kPlanChunk + lane], cgs, cgd, 0, red[3 * kPlanChunk + lane],
-                         red[4 * kPlanChunk + lane]);
+            scatter_plan(plan[2 * kAdjTChunk + lane], cgs, cgd, 0, red[kAdjTChunk + lane], red[2 * kAdjTChunk + lane]);
+            scatter_plan(plan[3 * kAdjTChunk + lane], cgs, cgd, 0, red[3 * kAdjTChunk + lane],
+                         red[4 * kAdjTChunk + lane]);
         }
     }
 }
