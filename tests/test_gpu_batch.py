@@ -149,3 +149,16 @@ def test_batch_scan_full_size_sampled():
         err = compare_triples(orc, tables[p], tri, ref, dp)
         _say(f"scan point {p} (range {pts[p]['range']}, ns={b.ns[p]}): vertex {err:.2e}")
         assert err <= 1e-5
+
+
+def test_batch_with_single_pair_point():
+    """A batch holding a range-0 point (the on-site pair only) beside larger
+    ones: every point against its own oracle."""
+    pts = [("square", dict(j1=1.0), 0)] + POINTS[:2]
+    torch, tables, b, orcs = _batch(pts, MESH, "fp64")
+    parts, x = _random_batch_state(b, torch, seed=17)
+    d = b.rhs(0.3, x).cpu().numpy()
+    for p in range(b.n_points):
+        ref = orcs[p].rhs(0.3, expand_state(orcs[p], tables[p], parts[p]))
+        es, ev = compare_parts(orcs[p], tables[p], ref, d[b.offsets[p]:b.offsets[p + 1]])
+        assert es <= 1e-10 and ev <= 1e-10, (p, es, ev)

@@ -45,12 +45,15 @@ def _say(*a):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("lam_kind", ["low", "mid", "mesh", "high"])
+@pytest.mark.parametrize("lam_kind", ["low", "mid", "mesh", "half", "high"])
 def test_rhs_random_state(name, lam_kind):
+    """'half' puts Lambda at half a mesh frequency, so transfer frequencies
+    2 Lambda sit on the mesh and delta-point propagators meet |w| = Lambda
+    exactly (the theta = 1/2 ties)."""
     torch, tables, ctx, orc = _setup(name)
     mesh = ctx.mesh
     lam = {"low": 0.5 * mesh[0], "mid": 0.37, "mesh": float(mesh[len(mesh) // 2]),
-           "high": 1.7 * mesh[-1]}[lam_kind]
+           "half": 0.5 * float(mesh[len(mesh) // 2]), "high": 1.7 * mesh[-1]}[lam_kind]
     x = W.random_state(ctx.nf, ctx.ns, seed=hash((name, lam_kind)) % 1000)
     _say(f"rhs {name} lam={lam}")
     d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
@@ -174,3 +177,30 @@ def test_flow_reports_divergence_and_keeps_last_finite_state():
         ctx.flow(x, schedule=[5.0, 4.0, 3.0], scheme="rk4")
     assert ei.value.status == EDIVERGED
     assert torch.equal(x, x0)
+
+
+@pytest.mark.parametrize("L,nf", [(0, 2), (0, 3), (1, 2)])
+def test_degenerate_lattices_and_meshes(L, nf):
+    """Range 0 (the on-site pair only, one lattice-sum term) and the smallest
+    meshes (2 and 3 frequencies): right-hand side, chi and an RK4 step."""
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    model = W.model("square", j1=0.8, j2=0.3)
+    mesh = W.log_mesh(0.05, 20.0, nf)
+    tables = build_tables(model, L)
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, L, mesh, threads=0)
+    x = W.random_state(nf, ctx.ns, seed=31 + L + nf)
+    xo = expand_state(orc, tables, x)
+    for lam in (0.01, 0.5 * mesh[-1], 1.3, 40.0):
+        _say(f"degenerate L={L} nf={nf} lam={lam}")
+        d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert compare_vertex(orc, tables, orc.rhs(lam, xo), d) <= TOL
+        chi = ctx.chi(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+        zz, dd = orc.chi(lam, xo)
+        assert compare_chi(orc, tables, zz, dd, chi) <= TOL
+    xd = torch.from_numpy(x).cuda()
+    ctx.step("rk4", 2.0, 1.5, xd)
+    assert compare_vertex(orc, tables, orc.rk4_step(2.0, 1.5, xo), xd.cpu().numpy()) <= TOL
