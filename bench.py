@@ -19,8 +19,11 @@ flops per launch over its HIP-event duration), the whole adaptive flow
 CPU oracle timed on a bounded sample of the same workload, and three more
 measurements: the same right-hand side in FP32 mode (fp32_mode), a 64-point
 phase scan advanced as one batch against 64 sequential FP64 flows
-(batch_scan), and d chi(k_peak)/dJ through a 120-step flow by the discrete
-adjoint against the forward cost (adjoint).
+(batch_scan), d chi(k_peak)/dJ through a 120-step flow by the discrete
+adjoint against the forward cost (adjoint), and the vertex right-hand side's
+growth with the frequency and pair counts (scaling_shape).  paper_context
+quotes the only throughput the paper allows to derive (a CPU node, another
+workload): context, not a baseline.
 """
 
 from __future__ import annotations
@@ -281,15 +284,45 @@ def adjoint_leg():
                          "max_rel_err": float(np.abs(grad - fd).max() / np.abs(fd).max())}}
 
 
-def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
-    """The oracle on a bounded sample: every vertex element of a set of
-    frequency triples (plus the self-energy flow), timed on the host cores;
-    scaled to vertex-RHS elements per second of the reduced workload."""
-    import oracle
-    from tests.parity import expand_state
-    threads = os.cpu_count() or 1
-    orc = oracle.Oracle(model, wl.range, wl.mesh, threads=threads)
-    xo = expand_state(orc, tables, x_np)
+def scaling_leg(lam=0.7, reps=5):
+    """Vertex right-hand-side time against the frequency count (square J1-J2,
+    range 7) and against the pair count (square J1-J2, ranges 4..7, 32
+    frequencies), with the fitted exponents."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+
+    def t_vertex(tables, nf):
+        mesh = W.log_mesh(1e-3, 100.0, nf)
+        c = Context(tables, mesh)
+        x = torch.from_numpy(W.random_state(nf, c.ns, seed=1, scale=0.2)).cuda()
+        out = c.new_state()
+        c.rhs(lam, x, out)
+        torch.cuda.synchronize()
+        c.set_profiling(True)
+        for _ in range(reps):
+            c.rhs(lam, x, out)
+        ms, n = c.profile_read("vertex")
+        c.close()
+        return ms / n
+
+    model = W.model("square", j1=1.0, j2=0.5)
+    t7 = build_tables(model, 7)
+    nfs = [16, 24, 32, 48]
+    tn = [t_vertex(t7, nf) for nf in nfs]
+    ranges = [4, 5, 6, 7]
+    tabs = [build_tables(model, L) for L in ranges]
+    tl = [t_vertex(t, 32) for t in tabs]
+    nss = [t.n_pairs for t in tabs]
+    slope_nf = float(np.polyfit(np.log(nfs), np.log(tn), 1)[0])
+    slope_ns = float(np.polyfit(np.log(nss), np.log(tl), 1)[0])
+    return {"lambda": lam, "vs_n_freq": {"n_freq": nfs, "vertex_ms": tn, "exponent": slope_nf},
+            "vs_pairs": {"pairs": nss, "ranges": ranges, "vertex_ms": tl, "exponent": slope_ns},
+            "note": "work grows like n_freq^3 * (evaluation points ~ n_freq) and like pairs (channel "
+                    "products) to pairs^2 (lattice-sum matrix)"}
+
+
+def _oracle_sample(orc, tables, xo, lam, target_s, threads):
     nf = orc.nf
     rng = np.random.default_rng(0)
     all_tr = [(a, t, c) for a in range(nf) for c in range(a + 1) for t in range(nf)]
@@ -311,15 +344,33 @@ def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
         spent += time.perf_counter() - t0
         done += len(rest)
     elems = 2 * tables.n_pairs * done
-    per_rhs = spent / done * len(all_tr) + t_sig
+    return elems / spent, done, len(all_tr), spent, spent / done * len(all_tr) + t_sig
+
+
+def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
+    """The oracle on a bounded sample: every vertex element of a set of
+    frequency triples (plus the self-energy flow), timed on the host cores
+    (all of them, and one thread); scaled to vertex-RHS elements per second
+    of the reduced workload."""
+    import oracle
+    from tests.parity import expand_state
+    threads = os.cpu_count() or 1
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    orc = oracle.Oracle(model, wl.range, wl.mesh, threads=threads)
+    xo = expand_state(orc, tables, x_np)
+    value, done, total, spent, per_rhs = _oracle_sample(orc, tables, xo, lam, target_s, threads)
+    orc1 = oracle.Oracle(model, wl.range, wl.mesh, threads=1)
+    v1, d1, _, s1, _ = _oracle_sample(orc1, tables, xo, lam, target_s / 3, 1)
     return {
-        "value": elems / spent,
+        "value": value,
         "unit": "vertex-RHS elements/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"{done} of {len(all_tr)} frequency triples (all elements of each, "
+        "sample": (f"{done} of {total} frequency triples (all elements of each, "
                    f"unreduced lattice), one FP64 RHS at Lambda={lam:.4g}, {spent:.1f} s"),
         "rhs_seconds_extrapolated": per_rhs,
+        "single_thread": {"value": v1, "sample": f"{d1} triples, {s1:.1f} s"},
     }
 
 
@@ -465,6 +516,13 @@ def main():
         out["batch_scan"] = batch_leg()
         log("adjoint")
         out["adjoint"] = adjoint_leg()
+        log("scaling shape")
+        out["scaling_shape"] = scaling_leg()
+    out["paper_context"] = {
+        "value": 2.6e6, "unit": "vertex elements per second per node",
+        "hardware": "Intel Xeon Phi 7250-F node (68 cores, 1.4 GHz)",
+        "workload": "cubic J1-J2, range 7 (31 pairs), 64 frequencies, Euler steps with correlations",
+        "derivation": "about 25 core-hours for 422 steps of 8.25 M vertex elements, perfect scaling assumed"}
 
     if args.copy_probe:
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
