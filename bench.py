@@ -280,6 +280,10 @@ def adjoint_leg():
             "dchi_dJ": grad.tolist(), "forward_seconds": t_fwd, "checkpointed_forward_seconds": t1 - t0,
             "adjoint_seconds": t2 - t1, "adjoint_over_forward": (t1 - t0 + t2 - t1) / t_fwd,
             "checkpoint_bytes": int((len(sched) - 1) * ctx.size * 8),
+            "central_differences_equivalent": {
+                "flows_for_3_shell_couplings": 6, "flows_for_per_pair_couplings": 2 * (ctx.ns - 1),
+                "note": "the adjoint returns d chi/d J for every pair coupling at once (ratio above, in forward "
+                        "flows); central differences need two flows per parameter (off-site pairs only: the on-site pair has no coupling)"},
             "fd_check": {"method": "central differences of the forward flow, h = 1e-3 J_i, Richardson",
                          "max_rel_err": float(np.abs(grad - fd).max() / np.abs(fd).max())}}
 

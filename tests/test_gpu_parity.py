@@ -204,3 +204,32 @@ def test_degenerate_lattices_and_meshes(L, nf):
     xd = torch.from_numpy(x).cuda()
     ctx.step("rk4", 2.0, 1.5, xd)
     assert compare_vertex(orc, tables, orc.rk4_step(2.0, 1.5, xo), xd.cpu().numpy()) <= TOL
+
+
+def test_largest_mesh_sampled():
+    """The largest supported mesh (128 frequencies, 1.06 M frequency triples)
+    on a range-1 square lattice: the self-energy derivative in full and the
+    vertex derivative on sampled triples (mesh ends, diagonal, random)."""
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    model = W.model("square", j1=1.0)
+    mesh = W.log_mesh(1e-3, 100.0, 128)
+    tables = build_tables(model, 1)
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, 1, mesh, threads=0)
+    nf = ctx.nf
+    x = W.random_state(nf, ctx.ns, seed=8, scale=0.2)
+    lam = float(mesh[64]) * 0.5
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    xo = expand_state(orc, tables, x)
+    dsig = orc.sigma_rhs(lam, xo)
+    assert np.abs(dsig - d[:nf]).max() <= TOL * np.abs(dsig).max()
+    rng = np.random.default_rng(4)
+    tri = [(0, 0, 0), (nf - 1, nf - 1, nf - 1), (nf - 1, 0, 0), (64, 64, 64), (127, 3, 126)]
+    for _ in range(6):
+        a = int(rng.integers(nf)); c = int(rng.integers(a + 1)); t = int(rng.integers(nf))
+        tri.append((a, t, c))
+    ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
+    assert compare_triples(orc, tables, tri, ref, d) <= TOL
