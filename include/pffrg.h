@@ -229,10 +229,13 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
 /* ----------------------------------------------------------- profiling - */
 
 /* Kernel timing with HIP events recorded on the context's stream around every
- * launch of the timed kernels (no effect on results).  pffrg_set_profiling
- * turns recording on (1) or off (0) and clears the totals.
- * pffrg_profile_read synchronises the stream and returns, for kernel id
- * `kernel`, the summed duration in milliseconds and the launch count since
+ * launch of the timed kernels (no effect on results; each event pair adds a
+ * few microseconds between launches).  pffrg_set_profiling turns recording on
+ * for all of them (1) or off (0); pffrg_set_profiling_mask records only the
+ * kernels whose bit (1 << id) is set in `mask` (0: off; a bit at or above
+ * PFFRG_K_COUNT: PFFRG_EINVAL).  Both synchronise the stream and clear the
+ * totals.  pffrg_profile_read synchronises the stream and returns, for kernel
+ * id `kernel`, the summed duration in milliseconds and the launch count since
  * profiling was switched on.  Up to 65536 launches per kernel are kept. */
 enum {
     PFFRG_K_SIGMA = 0,      /* self-energy flow */
@@ -244,6 +247,7 @@ enum {
     PFFRG_K_COUNT = 6
 };
 pffrg_status pffrg_set_profiling(pffrg_ctx *ctx, int on);
+pffrg_status pffrg_set_profiling_mask(pffrg_ctx *ctx, unsigned mask);
 pffrg_status pffrg_profile_read(pffrg_ctx *ctx, int kernel, double *total_ms, int *count);
 
 /* ------------------------------------------------------------ batches -- */

@@ -53,6 +53,7 @@ SIGNATURES = {
     "pffrg_chi": [P, D, P, P],
     "pffrg_chi_k": [P, P, I, P, P],
     "pffrg_set_profiling": [P, I],
+    "pffrg_set_profiling_mask": [P, ctypes.c_uint],
     "pffrg_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(I)],
     "pffrg_init_state_from": [P, P, P],
     "pffrg_rhs_vjp": [P, D, P, P, P],

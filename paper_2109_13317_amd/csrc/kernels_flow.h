@@ -365,8 +365,10 @@ struct SharedLds {
     __host__ __device__ size_t swap() const { return (size_t)2 * nf * sizeof(double); }
     __host__ __device__ size_t off() const { return swap() + (size_t)ns * sizeof(int); }
     __host__ __device__ size_t terms() const { return off() + (size_t)(ns + 1) * sizeof(int); }
+    __host__ __device__ size_t runs() const { return (terms() + (size_t)n_terms * sizeof(int) + 7) & ~(size_t)7; }
+    __host__ __device__ size_t run0() const { return runs() + (size_t)64 * 2 * sizeof(int); }
     __host__ __device__ size_t bytes(bool with_terms) const {
-        const size_t b = with_terms ? terms() + (size_t)n_terms * sizeof(int) : terms();
+        const size_t b = with_terms ? run0() + (size_t)(ns + 1) * sizeof(int) : terms();
         return (b + 31) & ~(size_t)31;
     }
 };
@@ -377,6 +379,8 @@ struct Shared {
     const int* swap;
     const int* off;
     const int* terms;
+    const int2* runs;       // [kWave] term range [x, y) summed by each lane
+    const int* run0;        // [ns+1] lanes run0[p] .. run0[p+1]-1 hold pair p's runs
 };
 
 // Pointers to the shared tables in LDS (no memory traffic).
@@ -384,7 +388,41 @@ __device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* 
     const SharedLds S{A.nf, A.ns, A.n_terms};
     return Shared{reinterpret_cast<double*>(lds + S.mesh()), reinterpret_cast<double*>(lds + S.ih()),
                   reinterpret_cast<int*>(lds + S.swap()), reinterpret_cast<int*>(lds + S.off()),
-                  reinterpret_cast<int*>(lds + S.terms())};
+                  reinterpret_cast<int*>(lds + S.terms()), reinterpret_cast<int2*>(lds + S.runs()),
+                  reinterpret_cast<int*>(lds + S.run0())};
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Runs of the lattice-sum contraction (one wave, lane = thread): the terms of
+// each pair are cut into runs of at most len terms, len the shortest odd
+// length for which the runs of all pairs fit the lanes of a wave (it exists:
+// at the largest term count every pair has one run, and there are fewer
+// pairs than lanes).  Lanes past the last run get empty runs.
+__device__ __forceinline__ void fill_runs(int ns, int n_terms, const int* off, int2* runs, int* run0) {
+    const int lane = threadIdx.x;
+    const int n = lane < ns ? off[lane + 1] - off[lane] : 0;
+    int len = max(1, (n_terms + kWave - 1) / kWave);
+    while (wave_sum_int((n + len - 1) / len) > kWave) ++len;
+    len |= 1;       // odd: lanes reading term i of their runs hit distinct LDS banks
+    const int k = (n + len - 1) / len;
+    int incl = k;                                         // inclusive prefix sum over the lanes
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int v = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += v;
+    }
+    const int first = incl - k;
+    if (lane < ns) run0[lane] = first;
+    if (lane == ns - 1) run0[ns] = incl;
+    runs[lane] = make_int2(0, 0);
+    wave_lds_sync();
+    for (int j = 0; j < k; ++j) {
+        const int q = off[lane] + j * len;
+        runs[first + j] = make_int2(q, min(q + len, off[lane] + n));
+    }
 }
 
 // Fill the shared tables (workgroup-wide; before any wave leaves).
@@ -403,6 +441,9 @@ __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* ld
     if (with_terms) {
         for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
         for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
+        __syncthreads();
+        if (threadIdx.x < kWave)
+            fill_runs(A.ns, A.n_terms, off, const_cast<int2*>(sh.runs), const_cast<int*>(sh.run0));
     }
     __syncthreads();
 }
@@ -592,15 +633,41 @@ k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo
 //   corr: Gamma_{i1i2}(w1+w, t, w1'-w) Gamma_{i2i2}(w2'+w, w2-w, -t)
 //       + Gamma_{i1i1}(w1+w, w-w1', -t) Gamma_{i1i2}(w+w2', t, w-w2)
 // The lattice sum is the matrix M = sum_k W_k a_k b_k^T (both strains),
-// register-blocked 2x4 per lane, contracted with the tabulated (ka, kb,
-// count) terms of each output pair.  NSP = pair count padded to a multiple
-// of 4 (compile-time, so LDS offsets are immediates); NB = blocks per lane.
-// In FP32 the matrix of each plan chunk is folded into a compensated sum;
-// the contraction with the terms runs in FP64.
+// contracted with the tabulated (ka, kb, count) terms of each output pair.
+// In FP64 M is accumulated on the matrix cores: 16x16 tiles, four nodes per
+// step (v_mfma_f64_16x16x4f64, operands read from the site vectors in LDS).
+// In FP32 it is register-blocked 2x4 per lane on the vector ALU, and the
+// matrix of each plan chunk is folded into a compensated sum; the
+// contraction with the terms runs in FP64.  NSP = pair count padded to a
+// multiple of 4 (compile-time, so LDS offsets are immediates); NB = vector
+// ALU blocks per lane; NT = 16x16 tiles per matrix side.
 template <int NSP>
 struct TShape {
     static constexpr int NB = ((NSP / 2) * (NSP / 4) + kWave - 1) / kWave;
     static constexpr int SUB = NB == 1 ? kSub : kSub / 2;
+    static constexpr int NT = (NSP + 15) / 16;
+};
+
+// Lanes of v_mfma_f64_16x16x4f64 and v_mfma_f32_16x16x4f32 (64 lanes):
+// operand A(16x4) element (i, k) and B(4x16) element (k, j) sit in lane
+// i + 16k resp. j + 16k; result register r of lane l holds D(l / 16 + 4r,
+// l % 16) in FP64 and D(4 (l / 16) + r, l % 16) in FP32.
+template <class R> using Vec4 = R __attribute__((ext_vector_type(4)));
+template <class R>
+__device__ __forceinline__ Vec4<R> mfma16x16x4(R a, R b, Vec4<R> c) {
+    if constexpr (sizeof(R) == 8) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class R>
+__device__ __forceinline__ int mfma_row(int lane, int r) {
+    return sizeof(R) == 8 ? lane / 16 + 4 * r : 4 * (lane / 16) + r;
+}
+// Matrix cores for the lattice sum: while one tile covers the pairs, and in
+// FP64 also beyond 20 pairs, where the vector-ALU blocks need as many
+// registers as the four tiles (from 17 to 20 pairs the tiles would cost a
+// wave per SIMD; in FP32 every matrix entry carries a compensated sum).
+template <class R, int NSP> struct TMatrixCores {
+    static constexpr bool on = NSP <= 16 || (sizeof(R) == 8 && NSP > 20);
 };
 
 // base: the wave's LDS area (layout WaveLds<R>{ns, SUB}); sh.off / sh.terms
@@ -634,9 +701,20 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
 
+    constexpr bool kMat = TMatrixCores<R, NSP>::on;
+    constexpr int NT = kMat ? TShape<NSP>::NT : 1;
     // padding columns ns .. NSP-1 of the site vectors stay zero
-    for (int i = lane; i < 4 * SUB * NSP; i += kWave)
-        if (i % NSP >= ns) vb[i] = R(0);
+    if constexpr (!kMat)
+        for (int i = lane; i < 4 * SUB * NSP; i += kWave)
+            if (i % NSP >= ns) vb[i] = R(0);
+    Vec4<R> cs[NT][NT], cd[NT][NT];
+    CompSum<R> ccs[kMat && kComp ? NT : 1][kMat && kComp ? NT : 1][4],
+        ccd[kMat && kComp ? NT : 1][kMat && kComp ? NT : 1][4];
+    if constexpr (kMat)
+#pragma unroll
+        for (int I = 0; I < NT; ++I)
+#pragma unroll
+            for (int J = 0; J < NT; ++J) { cs[I][J] = Vec4<R>{0, 0, 0, 0}; cd[I][J] = Vec4<R>{0, 0, 0, 0}; }
 
     // register blocks: block b = lane + 64 r covers rows 2*(b / NBK) .. +1
     // and columns 4*(b % NBK) .. +3
@@ -700,6 +778,34 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             }
             wave_lds_sync();
             // lattice-sum matrix: M[ka][kb] += (W a)[ka] b[kb], both strains
+            if constexpr (kMat) {
+                const int i16 = lane % 16, k4 = lane / 16;
+#pragma unroll
+                for (int kq = 0; kq < SUB; kq += 4) {
+                    if (kq < sc) {
+                        const int kk = kq + k4;
+                        R xa[2][NT], xb[2][NT];
+#pragma unroll
+                        for (int I = 0; I < NT; ++I) {
+                            const int pr = 16 * I + i16;
+                            const bool in = kk < sc && pr < ns;
+                            const int o = in ? kk * NSP + pr : 0;
+                            xa[0][I] = vb[0 * SUB * NSP + o];
+                            xa[1][I] = vb[1 * SUB * NSP + o];
+                            xb[0][I] = vb[2 * SUB * NSP + o];
+                            xb[1][I] = vb[3 * SUB * NSP + o];
+                            if (!in) xa[0][I] = xa[1][I] = xb[0][I] = xb[1][I] = R(0);
+                        }
+#pragma unroll
+                        for (int I = 0; I < NT; ++I)
+#pragma unroll
+                            for (int J = 0; J < NT; ++J) {
+                                cs[I][J] = mfma16x16x4<R>(xa[0][I], xb[0][J], cs[I][J]);
+                                cd[I][J] = mfma16x16x4<R>(xa[1][I], xb[1][J], cd[I][J]);
+                            }
+                    }
+                }
+            } else
 #pragma unroll
             for (int r = 0; r < NB; ++r) {
                 const int bidx = lane + kWave * r;
@@ -733,6 +839,20 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             sum_s.add(acc_s);
             sum_d.add(acc_d);
             acc_s = acc_d = R(0);
+            if constexpr (kMat) {
+#pragma unroll
+                for (int I = 0; I < NT; ++I)
+#pragma unroll
+                    for (int J = 0; J < NT; ++J) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            ccs[I][J][r].add(cs[I][J][r]);
+                            ccd[I][J][r].add(cd[I][J][r]);
+                        }
+                        cs[I][J] = Vec4<R>{0, 0, 0, 0};
+                        cd[I][J] = Vec4<R>{0, 0, 0, 0};
+                    }
+            } else
 #pragma unroll
             for (int r = 0; r < NB; ++r)
 #pragma unroll
@@ -748,15 +868,32 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     }
 
     // the matrix strain by strain (reusing the work area), contracted with
-    // the tabulated (ka, kb, count) terms of every output pair; lanes (g, p)
-    // take every G-th term of pair p
+    // the tabulated (ka, kb, count) terms: lane l sums the terms of its run
+    // (a piece of one pair's terms of nearly equal length for all lanes),
+    // and lane p adds up the runs of pair p
     wave_lds_sync();
     if constexpr (!kComp) {
         sum_s.s = acc_s;
         sum_d.s = acc_d;
     }
     double tot_s = sum_s.value(), tot_d = sum_d.value();
+    double* cpart = reinterpret_cast<double*>(base + L.mat());                      // [2][kWave]
+    const int2 run = sh.runs[lane];
     for (int strain = 0; strain < 2; ++strain) {
+        if constexpr (kMat) {
+#pragma unroll
+            for (int I = 0; I < NT; ++I)
+#pragma unroll
+                for (int J = 0; J < NT; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ka = 16 * I + mfma_row<R>(lane, r), kb = 16 * J + lane % 16;
+                        double v;
+                        if constexpr (kComp) v = strain == 0 ? ccs[I][J][r].value() : ccd[I][J][r].value();
+                        else v = strain == 0 ? (double)cs[I][J][r] : (double)cd[I][J][r];
+                        if (ka < ns && kb < ns) mat[ka * ns + kb] = v;
+                    }
+        } else
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
             const int bidx = lane + kWave * r;
@@ -775,17 +912,24 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             }
         }
         wave_lds_sync();
-        if (act) {
-            double acc = 0.0;
-            for (int q = sh.off[p] + g; q < sh.off[p + 1]; q += G) {
-                const int tq = sh.terms[q];
-                acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
-            }
-            if (strain == 0) tot_s = fma(-2.0, acc, tot_s);
-            else tot_d = fma(-2.0, acc, tot_d);
+        double acc = 0.0;
+        for (int q = run.x; q < run.y; ++q) {
+            const int tq = sh.terms[q];
+            acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
         }
+        cpart[strain * kWave + lane] = acc;
         wave_lds_sync();
     }
+    if (act && g == 0) {
+        double cs_ = 0.0, cd_ = 0.0;
+        for (int l = sh.run0[p]; l < sh.run0[p + 1]; ++l) {
+            cs_ += cpart[l];
+            cd_ += cpart[kWave + l];
+        }
+        tot_s = fma(-2.0, cs_, tot_s);
+        tot_d = fma(-2.0, cd_, tot_d);
+    }
+    wave_lds_sync();      // the reduction area is reused by the caller
     return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
 }
 

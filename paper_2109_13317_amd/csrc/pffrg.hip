@@ -74,8 +74,9 @@ struct pffrg_ctx {
 
     std::vector<void*> allocs;
 
-    // kernel timing: event pairs recorded around launches while profiling
-    bool profiling = false;
+    // kernel timing: event pairs recorded around the launches of the kernels
+    // whose bit (1 << kernel id) is set
+    unsigned prof_mask = 0;
     std::vector<hipEvent_t> ev[PFFRG_K_COUNT];
     int ev_used[PFFRG_K_COUNT] = {};
 
@@ -127,13 +128,13 @@ pffrg_status check_ctx(const pffrg_ctx* c) {
 constexpr int kMaxTimed = 65536;
 
 void prof_mark(pffrg_ctx* c, int id, bool after) {
-    if (!c->profiling) return;
+    if (!((c->prof_mask >> id) & 1u)) return;
     auto& v = c->ev[id];
     const int slot = 2 * c->ev_used[id] + (after ? 1 : 0);
     if (c->ev_used[id] >= kMaxTimed) return;
     while ((int)v.size() <= slot) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { c->profiling = false; return; }
+        if (hipEventCreate(&e) != hipSuccess) { c->prof_mask = 0; return; }
         v.push_back(e);
     }
     (void)hipEventRecord(v[slot], c->stream);
@@ -896,12 +897,17 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx* c, int n_lambda, const double* lambdas, c
     return PFFRG_OK;
 }
 
-pffrg_status pffrg_set_profiling(pffrg_ctx* c, int on) {
+pffrg_status pffrg_set_profiling_mask(pffrg_ctx* c, unsigned mask) {
     TRY(check_ctx(c));
+    if (mask >> PFFRG_K_COUNT) return fail(PFFRG_EINVAL, "profiling mask names an unknown kernel");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    c->profiling = on != 0;
+    c->prof_mask = mask;
     for (int i = 0; i < PFFRG_K_COUNT; ++i) c->ev_used[i] = 0;
     return PFFRG_OK;
+}
+
+pffrg_status pffrg_set_profiling(pffrg_ctx* c, int on) {
+    return pffrg_set_profiling_mask(c, on ? (1u << PFFRG_K_COUNT) - 1u : 0u);
 }
 
 pffrg_status pffrg_profile_read(pffrg_ctx* c, int kernel, double* total_ms, int* count) {

@@ -187,14 +187,24 @@ class Context:
         return dcp
 
     # --------------------------------------------------------- profiling --
-    def set_profiling(self, on: bool):
-        _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
+    _KERNELS = {"sigma": _lib.K_SIGMA, "tables": _lib.K_TABLES, "vertex": _lib.K_VERTEX,
+                "vertex_s": _lib.K_VERTEX_S, "vertex_u": _lib.K_VERTEX_U, "vertex_t": _lib.K_VERTEX_T}
+
+    def set_profiling(self, on: bool, kernels=None):
+        """Record kernel durations with HIP events: all timed kernels, or only
+        the named ones (names as in profile_read); False turns it off."""
+        if kernels is None or not on:
+            _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << self._KERNELS[k]
+            _lib.check(self.lib.pffrg_set_profiling_mask(self.handle, mask))
 
     def profile_read(self, kernel: str):
         """(total_ms, launches) of 'sigma', 'tables', 'vertex' (all three channel
         launches), 'vertex_s', 'vertex_u' or 'vertex_t' since profiling began."""
-        kid = {"sigma": _lib.K_SIGMA, "tables": _lib.K_TABLES, "vertex": _lib.K_VERTEX,
-               "vertex_s": _lib.K_VERTEX_S, "vertex_u": _lib.K_VERTEX_U, "vertex_t": _lib.K_VERTEX_T}[kernel]
+        kid = self._KERNELS[kernel]
         ms, n = ctypes.c_double(), ctypes.c_int()
         _lib.check(self.lib.pffrg_profile_read(self.handle, kid, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)

@@ -233,3 +233,22 @@ def test_largest_mesh_sampled():
         tri.append((a, t, c))
     ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
     assert compare_triples(orc, tables, tri, ref, d) <= TOL
+
+
+def test_profiling_mask_times_only_the_named_kernels():
+    """Events recorded around the t-channel launches only; results unchanged."""
+    from paper_2109_13317_amd import _lib
+    torch, tables, ctx, orc = _setup("square_L2_N8")
+    x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=3, scale=0.2)).cuda()
+    ref = ctx.rhs(0.7, x).clone()
+    ctx.set_profiling(True, kernels=("vertex_t",))
+    out = ctx.rhs(0.7, x)
+    out = ctx.rhs(0.7, x, out)
+    ms_t, n_t = ctx.profile_read("vertex_t")
+    assert n_t == 2 and ms_t > 0.0
+    for k in ("sigma", "tables", "vertex", "vertex_s", "vertex_u"):
+        assert ctx.profile_read(k) == (0.0, 0)
+    ctx.set_profiling(False)
+    assert torch.equal(out, ref)
+    with pytest.raises(_lib.PffrgError):           # a bit past the last kernel id
+        _lib.check(ctx.lib.pffrg_set_profiling_mask(ctx.handle, 1 << 6))
