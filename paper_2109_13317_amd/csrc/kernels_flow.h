@@ -641,10 +641,16 @@ k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo
 // contraction with the terms runs in FP64.  NSP = pair count padded to a
 // multiple of 4 (compile-time, so LDS offsets are immediates); NB = vector
 // ALU blocks per lane; NT = 16x16 tiles per matrix side.
+// Nodes per lattice-sum sub-chunk: 8 where one 2x4 register block per lane
+// covers the matrix (17 to 20 pairs), else 4 (one matrix-core step, or two
+// register blocks per lane), which also keeps the LDS of a workgroup small
+// enough for five per CU at up to 16 pairs.
+__host__ __device__ constexpr int t_sub(int nsp) { return nsp > 16 && nsp <= 20 ? kSub : kSub / 2; }
+
 template <int NSP>
 struct TShape {
     static constexpr int NB = ((NSP / 2) * (NSP / 4) + kWave - 1) / kWave;
-    static constexpr int SUB = NB == 1 ? kSub : kSub / 2;
+    static constexpr int SUB = t_sub(NSP);
     static constexpr int NT = (NSP + 15) / 16;
 };
 
@@ -936,7 +942,7 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
 // One context, ordered by (t, s, u); adds to dGamma.
 template <int NSP, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(3)))
+__attribute__((amdgpu_waves_per_eu(NSP > 16 ? 3 : (sizeof(R) == 4 ? 5 : 4))))
 k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns;

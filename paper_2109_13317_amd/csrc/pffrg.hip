@@ -144,9 +144,7 @@ void prof_mark(pffrg_ctx* c, int id, bool after) {
 // LDS of the t-channel launch (shared tables + 4 waves) for ns pairs.
 template <class R>
 size_t t_lds_bytes(int nf, int ns, int n_terms) {
-    const int nsp = (ns + 3) & ~3;
-    const int nb = ((nsp / 2) * (nsp / 4) + kWave - 1) / kWave;
-    const WaveLds<R> L{ns, nb == 1 ? kSub : kSub / 2};
+    const WaveLds<R> L{ns, t_sub((ns + 3) & ~3)};
     return SharedLds{nf, ns, n_terms}.bytes(true) + kWavesPerBlock * L.bytes();
 }
 
