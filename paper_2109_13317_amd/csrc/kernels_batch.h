@@ -196,12 +196,13 @@ k_batch_vertex(BatchArgs B, const V2<R>* __restrict__ gv, const int2* __restrict
             // s + u are finished (written) before t is added, in every
             // launch shape, so all shapes give the same bits
             if (PART != kT) {
-                LanePart ps = su_body<0, R>(A, sh, reinterpret_cast<PlanT<R>*>(base), T, rv, lane);
-                const LanePart pu = su_body<2, R>(A, sh, reinterpret_cast<PlanT<R>*>(base), T, rv, lane);
-                ps.s += pu.s;
-                ps.d += pu.d;
-                finish_pairs(red, lane, ns, G, act, ps.s, ps.d, 0.0, 0.0, out + T.out * ns,
-                             out + vsz + T.out * ns, false);
+                SuPart ps = su_body<0, R>(A, sh, reinterpret_cast<PlanT<R>*>(base), T, rv, lane);
+                const SuPart pu = su_body<2, R>(A, sh, reinterpret_cast<PlanT<R>*>(base), T, rv, lane);
+                for (int h = 0; h < 2; ++h) {
+                    ps.s[h] += pu.s[h];
+                    ps.d[h] += pu.d[h];
+                }
+                finish_su<R>(red, lane, ns, ps, out + T.out * ns, out + vsz + T.out * ns, false);
                 wave_lds_sync();
             }
             if (PART != kSU) {

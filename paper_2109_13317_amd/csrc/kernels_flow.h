@@ -365,10 +365,8 @@ struct SharedLds {
     __host__ __device__ size_t swap() const { return (size_t)2 * nf * sizeof(double); }
     __host__ __device__ size_t off() const { return swap() + (size_t)ns * sizeof(int); }
     __host__ __device__ size_t terms() const { return off() + (size_t)(ns + 1) * sizeof(int); }
-    __host__ __device__ size_t runs() const { return (terms() + (size_t)n_terms * sizeof(int) + 7) & ~(size_t)7; }
-    __host__ __device__ size_t run0() const { return runs() + (size_t)64 * 2 * sizeof(int); }
     __host__ __device__ size_t bytes(bool with_terms) const {
-        const size_t b = with_terms ? run0() + (size_t)(ns + 1) * sizeof(int) : terms();
+        const size_t b = with_terms ? terms() + (size_t)n_terms * sizeof(int) : terms();
         return (b + 31) & ~(size_t)31;
     }
 };
@@ -379,8 +377,6 @@ struct Shared {
     const int* swap;
     const int* off;
     const int* terms;
-    const int2* runs;       // [kWave] term range [x, y) summed by each lane
-    const int* run0;        // [ns+1] lanes run0[p] .. run0[p+1]-1 hold pair p's runs
 };
 
 // Pointers to the shared tables in LDS (no memory traffic).
@@ -388,41 +384,7 @@ __device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* 
     const SharedLds S{A.nf, A.ns, A.n_terms};
     return Shared{reinterpret_cast<double*>(lds + S.mesh()), reinterpret_cast<double*>(lds + S.ih()),
                   reinterpret_cast<int*>(lds + S.swap()), reinterpret_cast<int*>(lds + S.off()),
-                  reinterpret_cast<int*>(lds + S.terms()), reinterpret_cast<int2*>(lds + S.runs()),
-                  reinterpret_cast<int*>(lds + S.run0())};
-}
-
-__device__ __forceinline__ int wave_sum_int(int v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// Runs of the lattice-sum contraction (one wave, lane = thread): the terms of
-// each pair are cut into runs of at most len terms, len the shortest odd
-// length for which the runs of all pairs fit the lanes of a wave (it exists:
-// at the largest term count every pair has one run, and there are fewer
-// pairs than lanes).  Lanes past the last run get empty runs.
-__device__ __forceinline__ void fill_runs(int ns, int n_terms, const int* off, int2* runs, int* run0) {
-    const int lane = threadIdx.x;
-    const int n = lane < ns ? off[lane + 1] - off[lane] : 0;
-    int len = max(1, (n_terms + kWave - 1) / kWave);
-    while (wave_sum_int((n + len - 1) / len) > kWave) ++len;
-    len |= 1;       // odd: lanes reading term i of their runs hit distinct LDS banks
-    const int k = (n + len - 1) / len;
-    int incl = k;                                         // inclusive prefix sum over the lanes
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int v = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += v;
-    }
-    const int first = incl - k;
-    if (lane < ns) run0[lane] = first;
-    if (lane == ns - 1) run0[ns] = incl;
-    runs[lane] = make_int2(0, 0);
-    wave_lds_sync();
-    for (int j = 0; j < k; ++j) {
-        const int q = off[lane] + j * len;
-        runs[first + j] = make_int2(q, min(q + len, off[lane] + n));
-    }
+                  reinterpret_cast<int*>(lds + S.terms())};
 }
 
 // Fill the shared tables (workgroup-wide; before any wave leaves).
@@ -441,9 +403,6 @@ __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* ld
     if (with_terms) {
         for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
         for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
-        __syncthreads();
-        if (threadIdx.x < kWave)
-            fill_runs(A.ns, A.n_terms, off, const_cast<int2*>(sh.runs), const_cast<int*>(sh.run0));
     }
     __syncthreads();
 }
@@ -452,6 +411,11 @@ __device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* 
     fill_shared(A, lds, with_terms);
     return shared_ptrs(A, lds);
 }
+
+// Pairs per lane in the s/u channels: FP64 one (a 16-byte corner load per
+// pair); FP32 two adjacent pairs, whose packed elements one 16-byte load
+// fetches together, so a node takes half the load instructions.
+template <class R> constexpr int kSuPairs = sizeof(R) == 4 ? 2 : 1;
 
 // Per-wave LDS of the t-channel kernel, in bytes (R: the vertex precision).
 // The lattice-sum matrix at the end reuses it.  The s/u kernel uses
@@ -465,7 +429,7 @@ struct WaveLds {
     __host__ __device__ size_t onsite() const { return (((size_t)5 * kTChunk * sizeof(R)) + 15) & ~(size_t)15; }
     __host__ __device__ size_t su_plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
     __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(R); }
-    __host__ __device__ size_t red() const { return (size_t)2 * kWave * sizeof(double); }
+    __host__ __device__ size_t red() const { return (size_t)2 * kSuPairs<R> * kWave * sizeof(double); }
     __host__ __device__ size_t mat() const { return (((size_t)ns * ns * sizeof(double)) + 31) & ~(size_t)31; }
     __host__ __device__ size_t work() const { return plans() + onsite() + vbuf(); }
     __host__ __device__ size_t bytes() const {
@@ -533,6 +497,93 @@ struct LanePart {
     double s, d;
 };
 
+// s/u channels: lanes (g, q) hold partial sums for the pairs q * kSuPairs + h.
+struct SuPart {
+    double s[2] = {0.0, 0.0}, d[2] = {0.0, 0.0};
+};
+
+// Sum the s/u partials over the groups and write (or add) every pair.
+template <class R>
+__device__ __forceinline__ void finish_su(double* red, int lane, int ns, const SuPart& v, double* ds, double* dd,
+                                          bool add) {
+    constexpr int PL = kSuPairs<R>;
+    const int np = (ns + PL - 1) / PL, G = kWave / np;
+    const bool act = lane / np < G;
+#pragma unroll
+    for (int h = 0; h < PL; ++h) {
+        red[h * kWave + lane] = act ? v.s[h] : 0.0;
+        red[(PL + h) * kWave + lane] = act ? v.d[h] : 0.0;
+    }
+    wave_lds_sync();
+    if (lane < ns) {
+        const int q = lane / PL, h = lane % PL;
+        double ts = 0.0, td = 0.0;
+        for (int gg = 0; gg < G; ++gg) {
+            ts += red[h * kWave + gg * np + q];
+            td += red[(PL + h) * kWave + gg * np + q];
+        }
+        if (add) { ds[lane] += ts; dd[lane] += td; }
+        else { ds[lane] = ts; dd[lane] = td; }
+    }
+}
+
+// Byte offsets of a lane's two adjacent pairs p0 = 2q, p0 + 1 (FP32): un for
+// the unexchanged element p0, sw0 / sw1 for the exchange partners of the two
+// pairs; two_loads when the partners are not adjacent (the second pair's
+// corners are then read on their own).
+struct PairOff2 {
+    unsigned un, sw0, sw1;
+    bool two_loads;
+};
+
+// Interpolation of both vectors (plans Pa, Pb) for the two pairs of a lane:
+// a[h] / b[h] = (spin, density) of pair 2q + h.  All eight 16-byte corner
+// loads are issued before any arithmetic.
+__device__ __forceinline__ void eval_packed_ab2(const PlanT<float>& Pa, const PlanT<float>& Pb,
+                                                __amdgpu_buffer_rsrc_t r, const PairOff2& po, float2 (&a)[2],
+                                                float2 (&b)[2]) {
+    const unsigned qa = Pa.swp ? po.sw0 : po.un, qb = Pb.swp ? po.sw0 : po.un;
+    float4 ga[4], gb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        ga[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)((unsigned)Pa.off[i] + qa), 0, 0));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        gb[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)((unsigned)Pb.off[i] + qb), 0, 0));
+    if (po.two_loads) {
+        if (Pa.swp)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 v = load_corner(r, (unsigned)Pa.off[i] + po.sw1, float());
+                ga[i].z = v.x;
+                ga[i].w = v.y;
+            }
+        if (Pb.swp)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 v = load_corner(r, (unsigned)Pb.off[i] + po.sw1, float());
+                gb[i].z = v.x;
+                gb[i].w = v.y;
+            }
+    }
+    float a0 = 0, a1 = 0, a2 = 0, a3 = 0, b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a0 = fmaf(Pa.ws[i], ga[i].x, a0);
+        a1 = fmaf(Pa.wd[i], ga[i].y, a1);
+        a2 = fmaf(Pa.ws[i], ga[i].z, a2);
+        a3 = fmaf(Pa.wd[i], ga[i].w, a3);
+        b0 = fmaf(Pb.ws[i], gb[i].x, b0);
+        b1 = fmaf(Pb.wd[i], gb[i].y, b1);
+        b2 = fmaf(Pb.ws[i], gb[i].z, b2);
+        b3 = fmaf(Pb.wd[i], gb[i].w, b3);
+    }
+    a[0] = make_float2(a0, a1);
+    a[1] = make_float2(a2, a3);
+    b[0] = make_float2(b0, b1);
+    b[1] = make_float2(b2, b3);
+}
+
 // s channel (CH = 0): A = Gamma(s, w1'-w, w-w2'), B = Gamma(s, w-w1, w-w2),
 //   dGs += W (-2 As Bs + As Bd + Ad Bs), dGd += W (3 As Bs + Ad Bd).
 // u channel (CH = 2): A = Gamma(w1+w, w-w2', u), B = Gamma(w1'+w, w2-w, u),
@@ -541,22 +592,37 @@ struct LanePart {
 // sums are folded by CompSum).  A.w must point at the LDS mesh copy; plan is
 // the wave's LDS plan area.
 template <int CH, class R>
-__device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh, PlanT<R>* plan,
-                                            const Triple& T, __amdgpu_buffer_rsrc_t rv, int lane) {
+__device__ __forceinline__ SuPart su_body(const FlowArgs& A, const Shared& sh, PlanT<R>* plan, const Triple& T,
+                                          __amdgpu_buffer_rsrc_t rv, int lane) {
+    constexpr int PL = kSuPairs<R>;
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const int ia = T.ia, ic = T.ic;
-    const int G = kWave / ns;
-    const int g = lane / ns, p = lane % ns;
+    const int np = (ns + PL - 1) / PL;
+    const int G = kWave / np;
+    const int g = lane / np, q = lane % np;
     const bool act = g < G;
-    const int2 pp = make_int2(kElemBytes<R> * p, kElemBytes<R> * sh.swap[p]);
-    CompSum<R> sum_s, sum_d;
+    const int p0 = PL * q;
+    int2 pp{0, 0};
+    PairOff2 po{0u, 0u, 0u, false};
+    if constexpr (PL == 1) {
+        pp = make_int2(kElemBytes<R> * p0, kElemBytes<R> * sh.swap[p0]);
+    } else {
+        const int s0 = sh.swap[p0];
+        const bool second = p0 + 1 < ns;
+        const int s1 = second ? sh.swap[p0 + 1] : s0 + 1;
+        po = PairOff2{(unsigned)(kElemBytes<R> * p0), (unsigned)(kElemBytes<R> * s0), (unsigned)(kElemBytes<R> * s1),
+                      s1 != s0 + 1};
+    }
+    CompSum<R> sum_s[PL], sum_d[PL];
     const int iv = CH == 0 ? ia : ic;
     const int cnt = A.tab_n[CH * nf + iv];
     const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
     const double* tg = A.tab_g + (long)(CH * nf + iv) * nq;
     const R sgn = CH == 0 ? R(-2) : R(2);
     const R three = R(3);
-    R acc_s = 0, acc_d = 0;
+    R acc_s[PL], acc_d[PL];
+#pragma unroll
+    for (int h = 0; h < PL; ++h) acc_s[h] = acc_d[h] = R(0);
     for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
         const int kc = min(kPlanChunk, cnt - k0);
         {
@@ -577,31 +643,46 @@ __device__ __forceinline__ LanePart su_body(const FlowArgs& A, const Shared& sh,
         }
         wave_lds_sync();
         if (act) {
-            int k = g;
-            for (; k < kc; k += G) {
-                R as, ad, bs, bd;
+            for (int k = g; k < kc; k += G) {
                 const R W = (R)tg[k0 + k];
-                eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
-                acc_s = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s);
-                acc_d = fmr(W, three * as * bs + ad * bd, acc_d);
+                if constexpr (PL == 1) {
+                    R as, ad, bs, bd;
+                    eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
+                    acc_s[0] = fmr(W, sgn * as * bs + as * bd + ad * bs, acc_s[0]);
+                    acc_d[0] = fmr(W, three * as * bs + ad * bd, acc_d[0]);
+                } else {
+                    float2 a[2], b[2];
+                    eval_packed_ab2(plan[k], plan[kPlanChunk + k], rv, po, a, b);
+#pragma unroll
+                    for (int h = 0; h < PL; ++h) {
+                        acc_s[h] = fmr(W, sgn * a[h].x * b[h].x + a[h].x * b[h].y + a[h].y * b[h].x, acc_s[h]);
+                        acc_d[h] = fmr(W, three * a[h].x * b[h].x + a[h].y * b[h].y, acc_d[h]);
+                    }
+                }
             }
         }
         if constexpr (sizeof(R) == 4) {
-            sum_s.add(acc_s);
-            sum_d.add(acc_d);
-            acc_s = acc_d = R(0);
+#pragma unroll
+            for (int h = 0; h < PL; ++h) {
+                sum_s[h].add(acc_s[h]);
+                sum_d[h].add(acc_d[h]);
+                acc_s[h] = acc_d[h] = R(0);
+            }
         }
         wave_lds_sync();
     }
-    if constexpr (sizeof(R) == 8) {
-        sum_s.s = acc_s;
-        sum_d.s = acc_d;
+    SuPart out;
+#pragma unroll
+    for (int h = 0; h < PL; ++h) {
+        if constexpr (sizeof(R) == 8) {
+            sum_s[h].s = acc_s[h];
+            sum_d[h].s = acc_d[h];
+        }
+        out.s[h] = act ? sum_s[h].value() : 0.0;
+        out.d[h] = act ? sum_d[h].value() : 0.0;
     }
-    return LanePart{act ? sum_s.value() : 0.0, act ? sum_d.value() : 0.0};
+    return out;
 }
-
-// One context: the s channel by (s, u, t) wedge order, the u channel by
-// (u, s, t) using the u-major wedge tables uo_a / uo_c; s writes, u adds.
 template <int CH, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo_a,
@@ -622,10 +703,9 @@ k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo
     const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
     const Triple T = make_triple(A.w, nf, ia, it, ic);
     const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, (long)n_triples * ns);
-    const LanePart r = su_body<CH, R>(A, sh, plan, T, rv, lane);
+    const SuPart r = su_body<CH, R>(A, sh, plan, T, rv, lane);
     const long vsz = (long)n_triples * ns;
-    finish_pairs(red, lane, ns, kWave / ns, lane / ns < kWave / ns, r.s, r.d, 0.0, 0.0,
-                 dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, CH != 0);
+    finish_su<R>(red, lane, ns, r, dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, CH != 0);
 }
 
 // t channel:
@@ -874,17 +954,14 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     }
 
     // the matrix strain by strain (reusing the work area), contracted with
-    // the tabulated (ka, kb, count) terms: lane l sums the terms of its run
-    // (a piece of one pair's terms of nearly equal length for all lanes),
-    // and lane p adds up the runs of pair p
+    // the tabulated (ka, kb, count) terms of every output pair; lanes (g, p)
+    // take every G-th term of pair p
     wave_lds_sync();
     if constexpr (!kComp) {
         sum_s.s = acc_s;
         sum_d.s = acc_d;
     }
     double tot_s = sum_s.value(), tot_d = sum_d.value();
-    double* cpart = reinterpret_cast<double*>(base + L.mat());                      // [2][kWave]
-    const int2 run = sh.runs[lane];
     for (int strain = 0; strain < 2; ++strain) {
         if constexpr (kMat) {
 #pragma unroll
@@ -918,31 +995,24 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             }
         }
         wave_lds_sync();
-        double acc = 0.0;
-        for (int q = run.x; q < run.y; ++q) {
-            const int tq = sh.terms[q];
-            acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
+        if (act) {
+            double acc = 0.0;
+            for (int q = sh.off[p] + g; q < sh.off[p + 1]; q += G) {
+                const int tq = sh.terms[q];
+                acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
+            }
+            if (strain == 0) tot_s = fma(-2.0, acc, tot_s);
+            else tot_d = fma(-2.0, acc, tot_d);
         }
-        cpart[strain * kWave + lane] = acc;
         wave_lds_sync();
     }
-    if (act && g == 0) {
-        double cs_ = 0.0, cd_ = 0.0;
-        for (int l = sh.run0[p]; l < sh.run0[p + 1]; ++l) {
-            cs_ += cpart[l];
-            cd_ += cpart[kWave + l];
-        }
-        tot_s = fma(-2.0, cs_, tot_s);
-        tot_d = fma(-2.0, cd_, tot_d);
-    }
-    wave_lds_sync();      // the reduction area is reused by the caller
     return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
 }
 
 // One context, ordered by (t, s, u); adds to dGamma.
 template <int NSP, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(NSP > 16 ? 3 : (sizeof(R) == 4 ? 5 : 4))))
+__attribute__((amdgpu_waves_per_eu(NSP > 16 ? 3 : 5)))
 k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns;
