@@ -67,14 +67,18 @@ def test_fp32_rhs_random_state(name, lam_kind):
     assert ev <= TOL_RHS, ev
 
 
-def test_fp32_full_size_rhs_sampled():
-    """FP32 at the square J1-J2 workload size (range 7, 32 frequencies):
-    every element of a sample of triples against the oracle."""
+@pytest.mark.parametrize("which", ["square_j1j2", "honeycomb_j123", "pyrochlore"])
+def test_fp32_full_size_rhs_sampled(which):
+    """FP32 at the full workload sizes: every element of a sample of triples
+    against the oracle, and every element against the FP64 kernels (which
+    the FP64 tests pin to the oracle).  Honeycomb (14 pairs) and pyrochlore
+    (31 pairs, an odd count) have pairs whose exchange partners are not
+    adjacent, the case where a lane's two pairs need two loads per corner."""
     import torch
     import oracle
     from paper_2109_13317_amd import build_tables
     from paper_2109_13317_amd.flow import Context
-    wl = W.workload("square_j1j2")
+    wl = W.workload(which)
     model = wl.model()
     tables = build_tables(model, wl.range)
     ctx = Context(tables, wl.mesh, precision="fp32")
@@ -83,6 +87,10 @@ def test_fp32_full_size_rhs_sampled():
     x = W.random_state(nf, ctx.ns, seed=5, scale=0.2)
     lam = 0.21
     d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    d64 = Context(tables, wl.mesh).rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    e64 = np.abs(d[nf:] - d64[nf:]).max() / np.abs(d64[nf:]).max()
+    _say(f"fp32 {which} whole vertex vs fp64 kernels: {e64:.2e}")
+    assert e64 <= TOL_RHS, e64
     xo = expand_state(orc, tables, x)
     dsig = orc.sigma_rhs(lam, xo)
     assert np.abs(dsig - d[:nf]).max() <= TOL_SIGMA * np.abs(dsig).max()
@@ -93,7 +101,7 @@ def test_fp32_full_size_rhs_sampled():
         tri.append((a, t, c))
     ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
     err = compare_triples(orc, tables, tri, ref, d)
-    _say(f"fp32 full-size sampled vertex error {err:.2e}")
+    _say(f"fp32 {which} full-size sampled vertex error {err:.2e}")
     assert err <= TOL_RHS, err
 
 
