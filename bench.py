@@ -392,7 +392,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the flow engine runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -52,7 +52,7 @@ typedef enum {
     PFFRG_EHIP = -2,          /* HIP runtime failure */
     PFFRG_ENOMEM = -3,        /* device allocation failed in pffrg_create */
     PFFRG_EDIVERGED = -4,     /* NaN/Inf in the state, or step size below hmin */
-    PFFRG_EUNSUPPORTED = -5   /* option not available in this build */
+    PFFRG_EUNSUPPORTED = -5   /* option or size beyond what the library supports */
 } pffrg_status;
 
 typedef enum {
