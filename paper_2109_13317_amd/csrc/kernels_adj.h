@@ -41,6 +41,41 @@ __device__ __forceinline__ void odd_interp_vjp(const double* __restrict__ w, int
     if (f1 != 0.0) atomic_add(cot + i1, sg * f1 * c);
 }
 
+// Both strains at a plan's corners for pair element q (already exchanged),
+// from the packed (Gs, Gd) copy of the vertex: one 16-byte load per corner.
+__device__ __forceinline__ void eval_packed_el(const Plan& P, __amdgpu_buffer_rsrc_t r, int q, double& vs,
+                                               double& vd) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 g = load_corner(r, (unsigned)(P.off[i] + q) * 16u, double());
+        a = fma(P.ws[i], g.x, a);
+        b = fma(P.wd[i], g.y, b);
+    }
+    vs = a;
+    vd = b;
+}
+
+// Two plans at once, all eight loads issued before any arithmetic.
+__device__ __forceinline__ void eval_packed_el2(const Plan& Pa, int qa, const Plan& Pb, int qb,
+                                                __amdgpu_buffer_rsrc_t r, double& as, double& ad, double& bs,
+                                                double& bd) {
+    double2 ga[4], gb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ga[i] = load_corner(r, (unsigned)(Pa.off[i] + qa) * 16u, double());
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gb[i] = load_corner(r, (unsigned)(Pb.off[i] + qb) * 16u, double());
+    double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a0 = fma(Pa.ws[i], ga[i].x, a0);
+        a1 = fma(Pa.wd[i], ga[i].y, a1);
+        b0 = fma(Pb.ws[i], gb[i].x, b0);
+        b1 = fma(Pb.wd[i], gb[i].y, b1);
+    }
+    as = a0; ad = a1; bs = b0; bd = b1;
+}
+
 // Transpose of eval_plan for pair index q (already exchanged): the cotangents
 // (cs, cd) of the spin and density values go to the plan's corners.
 __device__ __forceinline__ void scatter_plan(const Plan& P, double* __restrict__ cgs, double* __restrict__ cgd,
@@ -92,9 +127,10 @@ __device__ __forceinline__ long cot_copy(long stride) { return (long)((blockIdx.
 
 template <int CH>
 static __global__ void __launch_bounds__(kWave * kAdjWaves)
-k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict__ uo_a,
-                const int* __restrict__ uo_c, int n_triples, const double* __restrict__ v,
-                double* __restrict__ cgs, double* __restrict__ cgd, long copy_stride, double* __restrict__ ctg) {
+k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const V2<double>* __restrict__ gv,
+                const int* __restrict__ uo_a, const int* __restrict__ uo_c, int n_triples,
+                const double* __restrict__ v, double* __restrict__ cgs, double* __restrict__ cgd, long copy_stride,
+                double* __restrict__ ctg) {
     cgs += cot_copy(copy_stride);
     cgd += cot_copy(copy_stride);
     extern __shared__ __align__(32) unsigned char lds_raw[];
@@ -117,8 +153,7 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict_
     const int ic = CH == 2 ? A.su_c[q] : uo_c[q];
     const Triple T = make_triple(A.w, nf, ia, it, ic);
     const long vsz = (long)n_triples * ns;
-    const double* gs = x + nf;
-    const double* gd = gs + vsz;
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<double>(gv, vsz);
 
     const int G = kWave / ns;
     const int g = lane / ns, p = lane % ns;
@@ -154,17 +189,17 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const int* __restrict_
             if (act) {
                 const Plan& Pa = plan[k];
                 const Plan& Pb = plan[kPlanChunk + k];
+                const int qa = Pa.swp ? sh.swap[p] : p, qb = Pb.swp ? sh.swap[p] : p;
                 double as, ad, bs, bd;
-                eval_plan(Pa, gs, gd, sh.swap, p, as, ad);
-                eval_plan(Pb, gs, gd, sh.swap, p, bs, bd);
+                eval_packed_el2(Pa, qa, Pb, qb, rv, as, ad, bs, bd);
                 const double W = tg[k0 + k];
                 atomicAdd(red + k, vs * (sgn * as * bs + as * bd + ad * bs) + vd * (3.0 * as * bs + ad * bd));
                 const double cas = W * (vs * (sgn * bs + bd) + vd * 3.0 * bs);
                 const double cad = W * (vs * bs + vd * bd);
                 const double cbs = W * (vs * (sgn * as + ad) + vd * 3.0 * as);
                 const double cbd = W * (vs * as + vd * ad);
-                scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
-                scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
+                scatter_plan(Pa, cgs, cgd, qa, cas, cad);
+                scatter_plan(Pb, cgs, cgd, qb, cbs, cbd);
             }
         }
         wave_lds_sync();
@@ -194,7 +229,7 @@ struct AdjTLds {
 // rpat_off[ns*ns + 1], rpat_ent[n_terms]: the lattice-sum terms grouped by
 // (ka, kb), entry = p | (count << 16) (the transpose of the per-output table).
 static __global__ void __launch_bounds__(kWave)
-k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const int* __restrict__ rpat_off,
+k_vertex_vjp_t(FlowArgs A, const V2<double>* __restrict__ gv, int n_triples, const int* __restrict__ rpat_off,
                const int* __restrict__ rpat_ent, const double* __restrict__ v, double* __restrict__ cgs,
                double* __restrict__ cgd, long copy_stride, double* __restrict__ ctg) {
     cgs += cot_copy(copy_stride);
@@ -220,8 +255,7 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
     const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
     const double t = T.t;
     const long vsz = (long)n_triples * ns;
-    const double* gs = x + nf;
-    const double* gd = gs + vsz;
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<double>(gv, vsz);
 
     for (int i = lane; i < ns; i += kWave) {
         vin[i] = v[nf + T.out * ns + i];
@@ -270,7 +304,7 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
                 plan[role * kAdjTChunk + j] = P;
                 if (role >= 2) {
                     double os, od;
-                    eval_plan(P, gs, gd, sh.swap, 0, os, od);
+                    eval_packed_el(P, rv, P.swp ? sh.swap[0] : 0, os, od);
                     ons[(2 * (role - 2) + 0) * kAdjTChunk + j] = os;
                     ons[(2 * (role - 2) + 1) * kAdjTChunk + j] = od;
                 }
@@ -283,8 +317,9 @@ k_vertex_vjp_t(FlowArgs A, const double* __restrict__ x, int n_triples, const in
             if (act) {
                 for (int kk = g; kk < sc; kk += G) {
                     double as, ad, bs, bd;
-                    eval_plan(plan[s0 + kk], gs, gd, sh.swap, p, as, ad);
-                    eval_plan(plan[kAdjTChunk + s0 + kk], gs, gd, sh.swap, p, bs, bd);
+                    const Plan& Pa = plan[s0 + kk];
+                    const Plan& Pb = plan[kAdjTChunk + s0 + kk];
+                    eval_packed_el2(Pa, Pa.swp ? sh.swap[p] : p, Pb, Pb.swp ? sh.swap[p] : p, rv, as, ad, bs, bd);
                     vb[(0 * kSub + kk) * ns + p] = as;
                     vb[(1 * kSub + kk) * ns + p] = ad;
                     vb[(2 * kSub + kk) * ns + p] = bs;

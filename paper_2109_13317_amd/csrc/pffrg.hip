@@ -366,21 +366,26 @@ pffrg_status rhs_vjp(pffrg_ctx* c, double lam, const double* x, const double* v,
     double* kgs = c->cot_copies;
     double* kgd = kgs + c->vsz;
     const int T = c->nsu * c->nf;
+    // the packed (Gs, Gd) copy of the vertex the gathers read
+    V2<double>* gv = static_cast<V2<double>*>(c->gv);
+    hipLaunchKernelGGL(k_pack<double>, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz,
+                       x + c->nf, x + c->nf + c->vsz, gv);
+    TRY(launch_check("k_pack"));
     {
         const int blocks = (T + kAdjWaves - 1) / kAdjWaves;
         const int per = (blocks + 7) / 8;
         const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + kAdjWaves * AdjWaveLds::bytes();
         hipLaunchKernelGGL(k_vertex_vjp_su<0>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
-                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
+                           (const V2<double>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_su"));
         hipLaunchKernelGGL(k_vertex_vjp_su<2>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
-                           (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
+                           (const V2<double>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_su"));
     }
     {
         const int per = (T + 7) / 8;
         const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + AdjTLds{c->ns}.bytes();
-        hipLaunchKernelGGL(k_vertex_vjp_t, dim3(8 * per), dim3(kWave), lds, c->stream, A, x, T,
+        hipLaunchKernelGGL(k_vertex_vjp_t, dim3(8 * per), dim3(kWave), lds, c->stream, A, (const V2<double>*)gv, T,
                            (const int*)c->rpat_off, (const int*)c->rpat_ent, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_t"));
     }
