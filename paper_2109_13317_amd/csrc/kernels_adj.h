@@ -76,6 +76,61 @@ __device__ __forceinline__ void eval_packed_el2(const Plan& Pa, int qa, const Pl
     as = a0; ad = a1; bs = b0; bd = b1;
 }
 
+// Corner contributions of one vector pending along a lane's run of nodes.
+// Consecutive nodes often interpolate from some of the same corners; their
+// contributions are added in registers and each corner is sent (two FP64
+// atomics, spin and density) once when the run leaves it.  Unused corners
+// (zero weight) take no slot.
+struct PendingCorners {
+    int e[4];
+    double s[4], d[4];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { e[i] = -1; s[i] = 0.0; d[i] = 0.0; }
+    }
+    __device__ __forceinline__ void flush(double* __restrict__ cgs, double* __restrict__ cgd) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (e[i] >= 0) {
+                atomic_add(cgs + e[i], s[i]);
+                atomic_add(cgd + e[i], d[i]);
+            }
+        clear();
+    }
+    // The corners of plan P (pair element q, cotangents cs / cd of its spin
+    // and density values) replace the pending ones: a pending corner that P
+    // also touches is carried into P's slot, the others are sent.
+    __device__ __forceinline__ void push(const Plan& P, int q, double cs, double cd, double* __restrict__ cgs,
+                                         double* __restrict__ cgd) {
+        int n[4];
+        double ns[4], nd[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            n[i] = P.ws[i] != 0.0 ? P.off[i] + q : -1;
+            ns[i] = P.ws[i] * cs;
+            nd[i] = P.wd[i] * cd;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (e[j] < 0) continue;
+            bool carried = false;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (!carried && n[i] == e[j]) {
+                    ns[i] += s[j];
+                    nd[i] += d[j];
+                    carried = true;
+                }
+            if (!carried) {
+                atomic_add(cgs + e[j], s[j]);
+                atomic_add(cgd + e[j], d[j]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { e[i] = n[i]; s[i] = ns[i]; d[i] = nd[i]; }
+    }
+};
+
 // Transpose of eval_plan for pair index q (already exchanged): the cotangents
 // (cs, cd) of the spin and density values go to the plan's corners.
 __device__ __forceinline__ void scatter_plan(const Plan& P, double* __restrict__ cgs, double* __restrict__ cgd,
@@ -185,7 +240,12 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const V2<double>* __re
             if (lane < kPlanChunk) red[lane] = 0.0;
         }
         wave_lds_sync();
-        for (int k = g; k < kc; k += G) {
+        // lanes of group g walk a contiguous run of the chunk's nodes
+        PendingCorners pa, pb;
+        pa.clear();
+        pb.clear();
+        const int kb = (g * kc) / G, ke = ((g + 1) * kc) / G;
+        for (int k = kb; k < ke; ++k) {
             if (act) {
                 const Plan& Pa = plan[k];
                 const Plan& Pb = plan[kPlanChunk + k];
@@ -198,9 +258,13 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const V2<double>* __re
                 const double cad = W * (vs * bs + vd * bd);
                 const double cbs = W * (vs * (sgn * as + ad) + vd * 3.0 * as);
                 const double cbd = W * (vs * as + vd * ad);
-                scatter_plan(Pa, cgs, cgd, qa, cas, cad);
-                scatter_plan(Pb, cgs, cgd, qb, cbs, cbd);
+                pa.push(Pa, qa, cas, cad, cgs, cgd);
+                pb.push(Pb, qb, cbs, cbd, cgs, cgd);
             }
+        }
+        if (act) {
+            pa.flush(cgs, cgd);
+            pb.flush(cgs, cgd);
         }
         wave_lds_sync();
         if (lane < kc) atomic_add(ct + k0 + lane, red[lane]);     // node weights' cotangent (LDS ds_add_f64 above)
