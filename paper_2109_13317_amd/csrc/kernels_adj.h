@@ -277,11 +277,12 @@ k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const V2<double>* __re
 // Per-wave LDS of the t-channel product, one wave per workgroup; plans are
 // built kAdjTChunk nodes at a time, one plan per lane (4 per node).
 constexpr int kAdjTChunk = kWave / 4;
+constexpr int kAdjTSub = kAdjTChunk;     // nodes whose site vectors are gathered at once
 struct AdjTLds {
     int ns;
     __host__ __device__ size_t plans() const { return (size_t)4 * kAdjTChunk * sizeof(Plan); }   // Pa Pb Q1 Q2
     __host__ __device__ size_t ons() const { return (size_t)4 * kAdjTChunk * sizeof(double); }
-    __host__ __device__ size_t vb() const { return (size_t)4 * kSub * ns * sizeof(double); }
+    __host__ __device__ size_t vb() const { return (size_t)4 * kAdjTSub * ns * sizeof(double); }
     __host__ __device__ size_t nmat() const { return (size_t)2 * ns * ns * sizeof(double); }
     __host__ __device__ size_t vin() const { return (size_t)2 * ns * sizeof(double); }
     __host__ __device__ size_t red() const { return (size_t)5 * kAdjTChunk * sizeof(double); }
@@ -307,7 +308,7 @@ k_vertex_vjp_t(FlowArgs A, const V2<double>* __restrict__ gv, int n_triples, con
     unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false);
     Plan* plan = reinterpret_cast<Plan*>(base);                                          // [4][kAdjTChunk]
     double* ons = reinterpret_cast<double*>(base + L.plans());                           // [4][kAdjTChunk]
-    double* vb = reinterpret_cast<double*>(base + L.plans() + L.ons());                  // [4][kSub][ns]
+    double* vb = reinterpret_cast<double*>(base + L.plans() + L.ons());                  // [4][kAdjTSub][ns]
     double* nm = reinterpret_cast<double*>(base + L.plans() + L.ons() + L.vb());         // [2][ns*ns]
     double* vin = nm + 2 * ns * ns;                                                      // [2][ns]
     double* red = vin + 2 * ns;                                                          // [5][kAdjTChunk]
@@ -376,31 +377,36 @@ k_vertex_vjp_t(FlowArgs A, const V2<double>* __restrict__ gv, int n_triples, con
             for (int i = lane; i < 5 * kAdjTChunk; i += kWave) red[i] = 0.0;
         }
         wave_lds_sync();
-        for (int s0 = 0; s0 < kc; s0 += kSub) {
-            const int sc = min(kSub, kc - s0);
+        for (int s0 = 0; s0 < kc; s0 += kAdjTSub) {
+            const int sc = min(kAdjTSub, kc - s0);
             if (act) {
                 for (int kk = g; kk < sc; kk += G) {
                     double as, ad, bs, bd;
                     const Plan& Pa = plan[s0 + kk];
                     const Plan& Pb = plan[kAdjTChunk + s0 + kk];
                     eval_packed_el2(Pa, Pa.swp ? sh.swap[p] : p, Pb, Pb.swp ? sh.swap[p] : p, rv, as, ad, bs, bd);
-                    vb[(0 * kSub + kk) * ns + p] = as;
-                    vb[(1 * kSub + kk) * ns + p] = ad;
-                    vb[(2 * kSub + kk) * ns + p] = bs;
-                    vb[(3 * kSub + kk) * ns + p] = bd;
+                    vb[(0 * kAdjTSub + kk) * ns + p] = as;
+                    vb[(1 * kAdjTSub + kk) * ns + p] = ad;
+                    vb[(2 * kAdjTSub + kk) * ns + p] = bs;
+                    vb[(3 * kAdjTSub + kk) * ns + p] = bd;
                 }
             }
             wave_lds_sync();
             if (act) {
-                for (int kk = g; kk < sc; kk += G) {
+                // lanes of group g walk a contiguous run of the sub-chunk's
+                // nodes, merging the corners consecutive nodes share
+                PendingCorners pa, pb;
+                pa.clear();
+                pb.clear();
+                for (int kk = (g * sc) / G; kk < ((g + 1) * sc) / G; ++kk) {
                     const int k = s0 + kk;
                     const double W = tg[k0 + k];
                     const double o1s = ons[0 * kAdjTChunk + k], o1d = ons[1 * kAdjTChunk + k];
                     const double o2s = ons[2 * kAdjTChunk + k], o2d = ons[3 * kAdjTChunk + k];
-                    const double* ra = vb + (0 * kSub + kk) * ns;
-                    const double* rad = vb + (1 * kSub + kk) * ns;
-                    const double* rb = vb + (2 * kSub + kk) * ns;
-                    const double* rbd = vb + (3 * kSub + kk) * ns;
+                    const double* ra = vb + (0 * kAdjTSub + kk) * ns;
+                    const double* rad = vb + (1 * kAdjTSub + kk) * ns;
+                    const double* rb = vb + (2 * kAdjTSub + kk) * ns;
+                    const double* rbd = vb + (3 * kAdjTSub + kk) * ns;
                     const double as = ra[p], ad = rad[p], bs = rb[p], bd = rbd[p];
                     // (N b)[p] and (N^T a)[p] for both strains
                     double nbs = 0.0, nbd = 0.0, nas = 0.0, nad = 0.0;
@@ -418,8 +424,8 @@ k_vertex_vjp_t(FlowArgs A, const V2<double>* __restrict__ gv, int n_triples, con
                     const double cbd = W * (vd * (3.0 * o2s + o2d) - 2.0 * nad);
                     const Plan& Pa = plan[k];
                     const Plan& Pb = plan[kAdjTChunk + k];
-                    scatter_plan(Pa, cgs, cgd, Pa.swp ? sh.swap[p] : p, cas, cad);
-                    scatter_plan(Pb, cgs, cgd, Pb.swp ? sh.swap[p] : p, cbs, cbd);
+                    pa.push(Pa, Pa.swp ? sh.swap[p] : p, cas, cad, cgs, cgd);
+                    pb.push(Pb, Pb.swp ? sh.swap[p] : p, cbs, cbd, cgs, cgd);
                     // per-node sums over the pairs (LDS ds_add_f64)
                     atomicAdd(red + k, vs * cs + vd * cd - 2.0 * (as * nbs + ad * nbd));
                     atomicAdd(red + kAdjTChunk + k, W * (-vs * as + 3.0 * vd * ad));
@@ -427,6 +433,8 @@ k_vertex_vjp_t(FlowArgs A, const V2<double>* __restrict__ gv, int n_triples, con
                     atomicAdd(red + 3 * kAdjTChunk + k, W * (-vs * bs + 3.0 * vd * bd));
                     atomicAdd(red + 4 * kAdjTChunk + k, W * (vs * bs + vd * bd));
                 }
+                pa.flush(cgs, cgd);
+                pb.flush(cgs, cgd);
             }
             wave_lds_sync();
         }
