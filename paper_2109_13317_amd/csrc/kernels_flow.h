@@ -714,13 +714,13 @@ k_vertex_su(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo
 //       + Gamma_{i1i1}(w1+w, w-w1', -t) Gamma_{i1i2}(w+w2', t, w-w2)
 // The lattice sum is the matrix M = sum_k W_k a_k b_k^T (both strains),
 // contracted with the tabulated (ka, kb, count) terms of each output pair.
-// In FP64 M is accumulated on the matrix cores: 16x16 tiles, four nodes per
-// step (v_mfma_f64_16x16x4f64, operands read from the site vectors in LDS).
-// In FP32 it is register-blocked 2x4 per lane on the vector ALU, and the
-// matrix of each plan chunk is folded into a compensated sum; the
-// contraction with the terms runs in FP64.  NSP = pair count padded to a
-// multiple of 4 (compile-time, so LDS offsets are immediates); NB = vector
-// ALU blocks per lane; NT = 16x16 tiles per matrix side.
+// M is accumulated either on the matrix cores, in 16x16 tiles taking four
+// nodes per step with their operands read from the site vectors in LDS
+// (TMatrixCores below says when), or register-blocked 2x4 per lane on the
+// vector ALU.  In FP32 the matrix of each plan chunk is folded into a
+// compensated sum; the contraction with the terms runs in FP64.  NSP = pair
+// count padded to a multiple of 4 (compile-time, so LDS offsets are
+// immediates); NB = vector-ALU blocks per lane; NT = tiles per matrix side.
 // Nodes per lattice-sum sub-chunk: 8 where one 2x4 register block per lane
 // covers the matrix (17 to 20 pairs), else 4 (one matrix-core step, or two
 // register blocks per lane), which also keeps the LDS of a workgroup small
