@@ -155,9 +155,15 @@ static __global__ void k_batch_rk_stage(long n, const double* __restrict__ x, co
 // right-hand side is one launch or two with smaller register needs.
 constexpr int kAll = 0, kSU = 1, kT = 2;
 
-template <class R, int PART>
+// MAXNSP: the largest padded pair count the launch's points may have.  The
+// split t launch runs the points of up to 16 pairs in an instance compiled
+// for them alone (matrix-core lattice sum, fewer registers, more waves per
+// SIMD) and the larger ones in another.
+constexpr int kSmallNsp = 16;
+
+template <class R, int PART, int MAXNSP = 20>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(PART == kSU ? 4 : 3)))
+__attribute__((amdgpu_waves_per_eu(PART == kSU ? 4 : (MAXNSP <= kSmallNsp && sizeof(R) == 4 ? 4 : 3))))
 k_batch_vertex(BatchArgs B, const V2<R>* __restrict__ gv, const int2* __restrict__ items,
                const int* __restrict__ begin, int shared_bytes, int wave_bytes, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
@@ -212,7 +218,9 @@ k_batch_vertex(BatchArgs B, const V2<R>* __restrict__ gv, const int2* __restrict
                     case 2: pt = t_body<8, R>(A, sh, base, T, rv, lane); break;
                     case 3: pt = t_body<12, R>(A, sh, base, T, rv, lane); break;
                     case 4: pt = t_body<16, R>(A, sh, base, T, rv, lane); break;
-                    default: pt = t_body<20, R>(A, sh, base, T, rv, lane); break;
+                    default:
+                        if constexpr (MAXNSP > kSmallNsp) pt = t_body<20, R>(A, sh, base, T, rv, lane);
+                        break;
                 }
                 finish_pairs(red, lane, ns, G, act, pt.s, pt.d, 0.0, 0.0, out + T.out * ns,
                              out + vsz + T.out * ns, true);

@@ -86,6 +86,10 @@ struct pffrg_batch {
 
     int2* items[kOrders] = {};
     int* begin[kOrders] = {};
+    // the split t launch's lists, per pair class (0: up to 16 pairs, 1: more)
+    int2* items_t[2][kOrders] = {};
+    int* begin_t[2][kOrders] = {};
+    bool has_class[2] = {false, false};
     int shared_bytes = 0, wave_bytes = 0;
     LaunchCfg cfg;
     bool tuned = false;
@@ -157,11 +161,11 @@ double triple_cost(int ns) { return ns * (142.0 + 4.0 * ns); }
 // Tile lists of both orders.  Order 0 assigns whole points to XCDs, largest
 // cost first to the least loaded XCD, so each point's vertex is read through
 // one L2; order 1 deals all tiles round-robin over the XCDs.
-void build_items(const pffrg_batch* b, std::vector<int2> out[kOrders], std::vector<int> beg[kOrders]) {
+void build_items(const pffrg_batch* b, const std::vector<int>& points, std::vector<int2> out[kOrders],
+                 std::vector<int> beg[kOrders]) {
     const int T = b->nsu * b->nf;
     const int tiles = (T + kWavesPerBlock - 1) / kWavesPerBlock;
-    std::vector<int> idx(b->np);
-    std::iota(idx.begin(), idx.end(), 0);
+    std::vector<int> idx(points);
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return triple_cost(b->ns[x]) > triple_cost(b->ns[y]); });
     std::vector<double> load(8, 0.0);
     std::vector<std::vector<int>> on(8);
@@ -180,7 +184,7 @@ void build_items(const pffrg_batch* b, std::vector<int2> out[kOrders], std::vect
     beg[0][8] = (int)out[0].size();
     std::vector<std::vector<int2>> part(8);
     long k = 0;
-    for (int p = 0; p < b->np; ++p)
+    for (int p : points)
         for (int t = 0; t < tiles; ++t, ++k) part[k % 8].push_back(make_int2(p, t * kWavesPerBlock));
     out[1].clear();
     beg[1].assign(9, 0);
@@ -214,8 +218,18 @@ pffrg_status batch_rhs_t(pffrg_batch* b, hipStream_t s, const double* lamp, cons
         hipLaunchKernelGGL((k_batch_vertex<R, kSU>), grid, block, lds_bytes(b), s, B, (const V2<R>*)gv, items, beg,
                            b->shared_bytes, b->wave_bytes, dx);
         TRY(launch_check("k_batch_vertex"));
-        hipLaunchKernelGGL((k_batch_vertex<R, kT>), grid, block, lds_bytes(b), s, B, (const V2<R>*)gv, items, beg,
-                           b->shared_bytes, b->wave_bytes, dx);
+        if (b->has_class[0]) {
+            TRY(launch_check("k_batch_vertex"));
+            hipLaunchKernelGGL((k_batch_vertex<R, kT, kSmallNsp>), grid, block, lds_bytes(b), s, B, (const V2<R>*)gv,
+                               (const int2*)b->items_t[0][c.order], (const int*)b->begin_t[0][c.order],
+                               b->shared_bytes, b->wave_bytes, dx);
+        }
+        if (b->has_class[1]) {
+            TRY(launch_check("k_batch_vertex"));
+            hipLaunchKernelGGL((k_batch_vertex<R, kT>), grid, block, lds_bytes(b), s, B, (const V2<R>*)gv,
+                               (const int2*)b->items_t[1][c.order], (const int*)b->begin_t[1][c.order],
+                               b->shared_bytes, b->wave_bytes, dx);
+        }
     } else {
         hipLaunchKernelGGL((k_batch_vertex<R, kAll>), grid, block, lds_bytes(b), s, B, (const V2<R>*)gv, items, beg,
                            b->shared_bytes, b->wave_bytes, dx);
@@ -415,10 +429,22 @@ pffrg_status pffrg_batch_create(int n_points, const pffrg_lattice* const* lats, 
         HIP_TRY(hipHostMalloc((void**)&b->host_red, sizeof(double) * 2 * n_points, hipHostMallocDefault));
         std::vector<int2> items[kOrders];
         std::vector<int> beg[kOrders];
-        build_items(b, items, beg);
+        std::vector<int> all(n_points), cls[2];
+        std::iota(all.begin(), all.end(), 0);
+        for (int p = 0; p < n_points; ++p) cls[((b->ns[p] + 3) & ~3) > kSmallNsp ? 1 : 0].push_back(p);
+        build_items(b, all, items, beg);
         for (int o = 0; o < kOrders; ++o) {
             TRY(b->mem.upload(&b->items[o], items[o].data(), items[o].size()));
             TRY(b->mem.upload(&b->begin[o], beg[o].data(), beg[o].size()));
+        }
+        for (int k = 0; k < 2; ++k) {
+            b->has_class[k] = !cls[k].empty();
+            if (!b->has_class[k]) continue;
+            build_items(b, cls[k], items, beg);
+            for (int o = 0; o < kOrders; ++o) {
+                TRY(b->mem.upload(&b->items_t[k][o], items[o].data(), items[o].size()));
+                TRY(b->mem.upload(&b->begin_t[k][o], beg[o].data(), beg[o].size()));
+            }
         }
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
