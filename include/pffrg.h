@@ -309,7 +309,7 @@ pffrg_status pffrg_batch_chi_k(pffrg_batch *batch, int point, const double *d_ch
  * carry equal estimated cost; 1: tiles dealt round-robin over the XCDs) and
  * split (0: one launch computes all three channels; 1: one launch for the s
  * and u channels, a second for the t channel, each with fewer registers).
- * pffrg_batch_tune times every candidate (per in 32, 64, 96, 128; both
+ * pffrg_batch_tune times every candidate (per in 32, 64, 96, 128, 192, 256, 384, 512; both
  * orders; both splits) on three right-hand sides at (lambda, d_state),
  * keeps the fastest and caches it for the process under (n_freq, pair
  * counts, precision); a later batch with the same key starts with it.

@@ -580,7 +580,7 @@ pffrg_status pffrg_batch_tune(pffrg_batch* b, double lambda, const double* x, in
         auto run = [&]() -> pffrg_status {
             for (int split = 0; split < 2; ++split)
             for (int order = 0; order < kOrders; ++order)
-                for (int perv : {32, 64, 96, 128}) {
+                for (int perv : {32, 64, 96, 128, 192, 256, 384, 512}) {
                     b->cfg = LaunchCfg{perv, order, split};
                     TRY(pffrg_batch_rhs(b, lambda, x, b->K));        // warm-up
                     HIP_TRY(hipEventRecord(e0, b->stream));

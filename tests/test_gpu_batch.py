@@ -63,14 +63,14 @@ def test_batch_launch_shapes_give_identical_bits():
     torch, tables, b, orcs = _batch(POINTS, MESH, "fp32")
     _, x = _random_batch_state(b, torch, seed=3)
     ref = b.rhs(0.5, x).clone()
-    for per in (1, 7, 32, 96):
+    for per in (1, 7, 32, 96, 512):
         for order in (0, 1):
             for split in (0, 1):
                 b.set_launch(per, order, split)
                 assert torch.equal(b.rhs(0.5, x), ref), (per, order, split)
     per, order, split = b.tune(0.5, x)
     _say(f"tuned launch: {per} workgroups per XCD, order {order}, split {split}")
-    assert per in (32, 64, 96, 128) and order in (0, 1) and split in (0, 1)
+    assert per in (32, 64, 96, 128, 192, 256, 384, 512) and order in (0, 1) and split in (0, 1)
     assert torch.equal(b.rhs(0.5, x), ref)
 
 
