@@ -323,6 +323,23 @@ pffrg_status pffrg_batch_set_launch(pffrg_batch *batch, int per, int order, int 
 pffrg_status pffrg_batch_set_profiling(pffrg_batch *batch, int on);
 pffrg_status pffrg_batch_profile_read(pffrg_batch *batch, double *total_ms, int *count);
 
+/* --------------------------------------------------------- diagnostics - */
+
+/* Measured peaks of the device the stream (a hipStream_t or NULL) runs on,
+ * for roofline fractions:
+ * FP64 and FP32 vector FMA throughput (2 flops per FMA, every CU, 8
+ * independent FMA chains per lane, FP32 without packed instructions as in
+ * every kernel of the library) and the bandwidth of a 512 MiB device-to-
+ * device copy (bytes read + written per second).  Allocates 1 GiB of device
+ * memory for the duration of the call and frees it; synchronises the stream.
+ * Errors: PFFRG_EINVAL (NULL out), PFFRG_ENOMEM, PFFRG_EHIP. */
+typedef struct pffrg_peaks {
+    double fp64_fma_tflops;
+    double fp32_fma_tflops;
+    double hbm_copy_gbs;
+} pffrg_peaks;
+pffrg_status pffrg_measure_peaks(void *stream, pffrg_peaks *out);
+
 /* -------------------------------------------------------------- errors -- */
 
 const char *pffrg_last_error(void);

@@ -52,6 +52,7 @@ SIGNATURES = {
     "pffrg_flow": [P, ctypes.POINTER(FlowOpts), P, OBSERVER, P, ctypes.POINTER(I)],
     "pffrg_chi": [P, D, P, P],
     "pffrg_chi_k": [P, P, I, P, P],
+    "pffrg_measure_peaks": [P, P],
     "pffrg_set_profiling": [P, I],
     "pffrg_set_profiling_mask": [P, ctypes.c_uint],
     "pffrg_profile_read": [P, I, ctypes.POINTER(D), ctypes.POINTER(I)],

@@ -362,6 +362,22 @@ class Batch:
         return float(ms.value), int(n.value)
 
 
+class _Peaks(ctypes.Structure):
+    _fields_ = [("fp64_fma_tflops", ctypes.c_double), ("fp32_fma_tflops", ctypes.c_double),
+                ("hbm_copy_gbs", ctypes.c_double)]
+
+
+def measure_peaks(stream=None) -> dict:
+    """Measured FP64 / FP32 vector FMA throughput (TFLOP/s) and device-copy
+    bandwidth (GB/s) of the current device (pffrg_measure_peaks)."""
+    lib = _lib.load()
+    stream = torch.cuda.current_stream() if stream is None else stream
+    out = _Peaks()
+    _lib.check(lib.pffrg_measure_peaks(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out)))
+    return {"fp64_fma_tflops": out.fp64_fma_tflops, "fp32_fma_tflops": out.fp32_fma_tflops,
+            "hbm_copy_gbs": out.hbm_copy_gbs}
+
+
 def _wrap(ptr: int, n: int) -> torch.Tensor:
     """A float64 torch view of n doubles of library-owned device memory."""
     # torch has no public from-pointer constructor for device memory; go via

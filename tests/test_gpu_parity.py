@@ -252,3 +252,14 @@ def test_profiling_mask_times_only_the_named_kernels():
     assert torch.equal(out, ref)
     with pytest.raises(_lib.PffrgError):           # a bit past the last kernel id
         _lib.check(ctx.lib.pffrg_set_profiling_mask(ctx.handle, 1 << 6))
+
+
+def test_measure_peaks_is_plausible():
+    """The on-device peak measurement returns finite rates in a plausible
+    range (it feeds the roofline fractions of the benchmark)."""
+    from paper_2109_13317_amd.flow import measure_peaks
+    pk = measure_peaks()
+    _say(f"measured peaks {pk}")
+    assert 1.0 < pk["fp64_fma_tflops"] < 200.0
+    assert 1.0 < pk["fp32_fma_tflops"] < 400.0
+    assert 100.0 < pk["hbm_copy_gbs"] < 20000.0
