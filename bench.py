@@ -288,6 +288,55 @@ def adjoint_leg():
                          "max_rel_err": float(np.abs(grad - fd).max() / np.abs(fd).max())}}
 
 
+def pyrochlore_leg(reps=10):
+    """Pyrochlore nearest-neighbour Heisenberg, range 5 (31 pairs), 48 log
+    frequencies 1e-3..100: one FP64 right-hand side at Lambda = 1 on the flowed
+    state (HIP events around the vertex launches), and the whole fixed RK4
+    flow 100 -> 0.01 on the exponential schedule b = 0.95 with chi at the end."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    wl = W.workload("pyrochlore")
+    ctx = Context(build_tables(wl.model(), wl.range), wl.mesh)
+    nf, ns = ctx.nf, ctx.ns
+    E = 2 * ns * nf * nf * (nf + 1) // 2
+    sched = list(wl.schedule)
+    x = ctx.init_state()
+    ctx.flow(x, schedule=[l for l in sched if l >= 1.0], scheme="rk4")
+    lam = [l for l in sched if l >= 1.0][-1]
+    out = ctx.new_state()
+    ctx.rhs(lam, x, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.rhs(lam, x, out)
+    torch.cuda.synchronize()
+    t_rhs = (time.perf_counter() - t0) / reps
+    ctx.set_profiling(True)
+    for _ in range(reps):
+        ctx.rhs(lam, x, out)
+    vms, vn = ctx.profile_read("vertex")
+    tms, tn = ctx.profile_read("vertex_t")
+    ctx.set_profiling(False)
+    from paper_2109_13317_amd._lib import PffrgError
+    xf = ctx.init_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        ctx.flow(xf, schedule=sched, scheme="rk4")
+        chi0 = float(ctx.chi(sched[-1], xf).reshape(-1)[0].cpu())
+    except PffrgError as e:              # a flow that leaves the finite range stops there
+        chi0 = f"flow stopped: {e}"
+    torch.cuda.synchronize()
+    t_flow = time.perf_counter() - t0
+    return {"workload": "pyrochlore NN J=1, range 5 (31 pairs), 48 log freqs 1e-3..100; RK4 100 -> 0.01, "
+                        "b = 0.95 (180 steps)",
+            "vertex_elements": E, "rhs_ms": t_rhs * 1e3, "rhs_elements_per_s": E / t_rhs,
+            "vertex_rhs_ms_events": vms / max(vn, 1), "vertex_t_ms_events": tms / max(tn, 1),
+            "rhs_lambda": lam, "flow_seconds": t_flow, "flow_steps": len(sched) - 1,
+            "chi_zz_onsite_final": chi0}
+
+
 def scaling_leg(lam=0.7, reps=5):
     """Vertex right-hand-side time against the frequency count (square J1-J2,
     range 7) and against the pair count (square J1-J2, ranges 4..7, 32
@@ -548,6 +597,8 @@ def main():
         out["batch_scan"] = batch_leg()
         log("adjoint")
         out["adjoint"] = adjoint_leg()
+        log("pyrochlore")
+        out["pyrochlore"] = pyrochlore_leg()
         log("scaling shape")
         out["scaling_shape"] = scaling_leg()
     out["paper_context"] = {
