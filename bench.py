@@ -415,6 +415,7 @@ def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
     value, done, total, spent, per_rhs = _oracle_sample(orc, tables, xo, lam, target_s, threads)
     orc1 = oracle.Oracle(model, wl.range, wl.mesh, threads=1)
     v1, d1, _, s1, _ = _oracle_sample(orc1, tables, xo, lam, target_s / 3, 1)
+    tiny = _tiny_flows(threads)
     return {
         "value": value,
         "unit": "vertex-RHS elements/s",
@@ -424,7 +425,41 @@ def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
                    f"unreduced lattice), one FP64 RHS at Lambda={lam:.4g}, {spent:.1f} s"),
         "rhs_seconds_extrapolated": per_rhs,
         "single_thread": {"value": v1, "sample": f"{d1} triples, {s1:.1f} s"},
+        "square_tiny_flow": tiny,
     }
+
+
+def _tiny_flows(threads):
+    """The whole small flow (square, range 2, 8 frequencies 0.005..50, RK4
+    50 -> 0.5 in 40 steps, 160 right-hand sides) on the oracle (all cores and
+    one thread) and on the GPU, with the largest relative state difference."""
+    import torch
+    import oracle
+    from tests.parity import restrict_state
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    wl = W.workload("square_tiny")
+    model = wl.model()
+    tables = build_tables(model, wl.range)
+    ctx = Context(tables, wl.mesh)
+    x = ctx.init_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.flow(x, schedule=wl.schedule, scheme="rk4")
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    res = {}
+    for n in (threads, 1):
+        orc = oracle.Oracle(model, wl.range, wl.mesh, threads=n)
+        t0 = time.perf_counter()
+        xo = orc.flow(wl.schedule, scheme="rk4")
+        res[n] = (time.perf_counter() - t0, xo)
+    ref = restrict_state(orc, tables, res[1][1])
+    got = x.cpu().numpy()
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    return {"workload": "square range 2, 8 log freqs 0.005..50, RK4 50 -> 0.5 in 40 steps (160 RHS)",
+            "oracle_seconds_all_cores": res[threads][0], "oracle_seconds_1_thread": res[1][0],
+            "cores": threads, "gpu_seconds": t_gpu, "max_rel_state_diff": err}
 
 
 def main():
