@@ -182,7 +182,7 @@ __device__ __forceinline__ long cot_copy(long stride) { return (long)((blockIdx.
 
 template <int CH>
 static __global__ void __launch_bounds__(kWave * kAdjWaves)
-k_vertex_vjp_su(FlowArgs A, const double* __restrict__ x, const V2<double>* __restrict__ gv,
+k_vertex_vjp_su(FlowArgs A, const V2<double>* __restrict__ gv,
                 const int* __restrict__ uo_a, const int* __restrict__ uo_c, int n_triples,
                 const double* __restrict__ v, double* __restrict__ cgs, double* __restrict__ cgd, long copy_stride,
                 double* __restrict__ ctg) {

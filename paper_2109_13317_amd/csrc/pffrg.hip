@@ -375,10 +375,10 @@ pffrg_status rhs_vjp(pffrg_ctx* c, double lam, const double* x, const double* v,
         const int blocks = (T + kAdjWaves - 1) / kAdjWaves;
         const int per = (blocks + 7) / 8;
         const size_t lds = SharedLds{c->nf, c->ns, c->n_terms}.bytes(false) + kAdjWaves * AdjWaveLds::bytes();
-        hipLaunchKernelGGL(k_vertex_vjp_su<0>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
+        hipLaunchKernelGGL(k_vertex_vjp_su<0>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A,
                            (const V2<double>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_su"));
-        hipLaunchKernelGGL(k_vertex_vjp_su<2>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A, x,
+        hipLaunchKernelGGL(k_vertex_vjp_su<2>, dim3(8 * per), dim3(kWave * kAdjWaves), lds, c->stream, A,
                            (const V2<double>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, v, kgs, kgd, cstride, c->ctg);
         TRY(launch_check("k_vertex_vjp_su"));
     }
