@@ -162,3 +162,29 @@ def test_batch_with_single_pair_point():
         ref = orcs[p].rhs(0.3, expand_state(orcs[p], tables[p], parts[p]))
         es, ev = compare_parts(orcs[p], tables[p], ref, d[b.offsets[p]:b.offsets[p + 1]])
         assert es <= 1e-10 and ev <= 1e-10, (p, es, ev)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_batch_with_non_adjacent_exchange_partners(precision, tol):
+    """Honeycomb range 6 (14 pairs) beside square points in one batch: its
+    pairs include exchange partners that are not adjacent (in FP32 the case
+    where a lane's two pairs need two loads per corner).  Every element of
+    each point against a single context of the same precision (pinned to the
+    oracle at full size by the FP32 and FP64 parity tests)."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Batch, Context
+    mesh = W.log_mesh(1e-3, 100.0, 8)
+    models = [W.model("honeycomb", j1=0.6, j2=0.3, j3=0.45), W.model("square", j1=1.0, j2=0.5)]
+    tables = [build_tables(models[0], 6), build_tables(models[1], 3)]
+    b = Batch(tables, mesh, precision=precision)
+    parts, x = _random_batch_state(b, torch, seed=21, scale=0.3)
+    lam = 0.29
+    d = b.rhs(lam, x).cpu().numpy()
+    for p, t in enumerate(tables):
+        c = Context(t, mesh, precision=precision)
+        ref = c.rhs(lam, torch.from_numpy(parts[p]).cuda()).cpu().numpy()
+        got = d[b.offsets[p]:b.offsets[p + 1]]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        _say(f"batch {precision} point {p} (ns={b.ns[p]}) vs single context: {err:.2e}")
+        assert err <= tol, err
