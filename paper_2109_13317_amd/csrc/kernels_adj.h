@@ -459,8 +459,7 @@ struct TableVjp {
     const double* ctg;
     double* cot_sig;
     double* cot_dsig;
-    __device__ __forceinline__ void delta(int n, double node, double xx, double y, double th, int lane) {
-        if (lane != 0) return;
+    __device__ __forceinline__ void delta(int n, double, double xx, double y, double th) {
         const double c = ctg[n];
         if (c == 0.0) return;
         const double st = 1.0 / (xx - odd_interp(w, nf, sig, xx));

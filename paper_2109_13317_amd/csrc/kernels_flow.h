@@ -233,14 +233,28 @@ __device__ __forceinline__ double full_mesh(const double* __restrict__ w, int nf
     return i < nf ? -w[nf - 1 - i] : w[i - nf];
 }
 
+// Number of full-mesh points that are <= x (le) or < x (!le).
+__device__ __forceinline__ int full_mesh_count(const double* __restrict__ w, int nf, double x, bool le) {
+    int lo = 0, hi = 2 * nf;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const double v = full_mesh(w, nf, mid);
+        if (le ? v <= x : v < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // One wave per (channel, nu).  Node list: the delta points first, then for
 // every piece of D = [-wmax, wmax] \ (-lam, lam) \ (c - lam, c + lam) (c = zero
 // of the partner) its ends and the mesh points strictly inside, with
-// trapezoid weight times the Katanin bubble.  The walk is shared by the
-// table builder and its vector-Jacobian product: V receives
-//   delta(n, node, x, y, theta, lane)  node n = w at a delta point x = +-Lambda,
+// trapezoid weight times the Katanin bubble.  The four delta candidates and
+// the four pieces are worked out on lanes 0..3 at once; the nodes of all
+// pieces are then spread over the wave.  The walk is shared by the table
+// builder and its vector-Jacobian product: V receives
+//   delta(n, node, x, y, theta)  node n = w at a delta point x = +-Lambda,
 //       weight -theta / ((x - sig(x)) (y - sig(y))) / (2 pi) with y the
-//       frequency of the other propagator (uniform over the wave);
+//       frequency of the other propagator (called by one lane per node);
 //   kat(n, w, partner(w), trapezoid weight)  one Katanin node (per lane);
 //   done(n, lane)  the list length.
 template <class V>
@@ -248,57 +262,77 @@ __device__ __forceinline__ void walk_nodes(const FlowArgs& A, double lam, int id
     const int nf = A.nf;
     const int ch = id / nf, iv = id % nf;
     const double nu = A.w[iv];
-    int n = 0;
 
-    // delta parts: the S in Skat(partner(w)) puts w at partner^-1(x); the S in
-    // Skat(w) puts w at x.
-    for (int sx = 0; sx < 2; ++sx) {
-        const double xx = sx == 0 ? lam : -lam;
-        const double winv = ch == 0 ? nu - xx : (ch == 1 ? xx + nu : xx - nu);
-        const double pxx = partner(ch, nu, xx);
-        const double g1 = theta_half(winv, lam);
-        const double g2 = theta_half(pxx, lam);
-        if (g1 != 0.0) vis.delta(n++, winv, xx, winv, g1, lane);
-        if (g2 != 0.0) vis.delta(n++, xx, xx, pxx, g2, lane);
+    // delta parts (lane 2 sx + k, x = +Lambda then -Lambda): the S in
+    // Skat(partner(w)) puts w at partner^-1(x) (k = 0); the S in Skat(w) puts
+    // w at x (k = 1)
+    int nd;
+    {
+        double node = 0.0, xx = 0.0, y = 0.0, th = 0.0;
+        if (lane < 4) {
+            xx = (lane >> 1) == 0 ? lam : -lam;
+            if ((lane & 1) == 0) {
+                node = ch == 0 ? nu - xx : (ch == 1 ? xx + nu : xx - nu);
+                y = node;
+            } else {
+                node = xx;
+                y = partner(ch, nu, xx);
+            }
+            th = theta_half(y, lam);
+        }
+        const bool on = lane < 4 && th != 0.0;
+        const unsigned long long mask = __ballot(on);
+        if (on) vis.delta(__popcll(mask & ((1ull << lane) - 1ull)), node, xx, y, th);
+        nd = __popcll(mask);
     }
 
+    // pieces (lane 2 ip + q): [lo, hi], the full-mesh points up to lo and
+    // the node count m (the two ends and the mesh points strictly inside)
     const double c = ch == 0 ? nu : (ch == 1 ? nu : -nu);
     const double wmax = A.w[nf - 1];
     const double e0 = c - lam, e1 = c + lam;
-    const double a0[2] = {-wmax, lam}, b0[2] = {-lam, wmax};
-    for (int ip = 0; ip < 2; ++ip) {
-        const double a = a0[ip], b = b0[ip];
-        if (!(a < b)) continue;
-        const double lo2[2] = {a, a > e1 ? a : e1};
-        const double hi2[2] = {b < e0 ? b : e0, b};
-        for (int q = 0; q < 2; ++q) {
-            const double lo = lo2[q], hi = hi2[q];
-            if (!(lo < hi)) continue;
-            // mesh points inside (lo, hi) are the contiguous run i0 .. i0+cnt-1
-            int below = 0, cnt = 0;
-            for (int i = lane; i < 2 * nf; i += kWave) {
-                const double v = full_mesh(A.w, nf, i);
-                below += v <= lo;
-                cnt += (v > lo && v < hi);
+    double lo = 0.0, hi = 0.0;
+    int below = 0, m = 0;
+    if (lane < 4) {
+        const int ip = lane >> 1, q = lane & 1;
+        const double a = ip == 0 ? -wmax : lam, b = ip == 0 ? -lam : wmax;
+        if (a < b) {
+            lo = q == 0 ? a : (a > e1 ? a : e1);
+            hi = q == 0 ? (b < e0 ? b : e0) : b;
+            if (lo < hi) {
+                below = full_mesh_count(A.w, nf, lo, true);
+                m = full_mesh_count(A.w, nf, hi, false) - below + 2;
             }
-            for (int o = kWave / 2; o > 0; o >>= 1) {
-                below += __shfl_xor(below, o, kWave);
-                cnt += __shfl_xor(cnt, o, kWave);
-            }
-            const int m = cnt + 2;
-            for (int j = lane; j < m; j += kWave) {
-                auto node = [&](int jj) {
-                    return jj == 0 ? lo : (jj == m - 1 ? hi : full_mesh(A.w, nf, below + jj - 1));
-                };
-                const double cur = node(j);
-                const double wl = j > 0 ? 0.5 * (cur - node(j - 1)) : 0.0;
-                const double wr = j + 1 < m ? 0.5 * (node(j + 1) - cur) : 0.0;
-                vis.kat(n + j, cur, partner(ch, nu, cur), wl + wr);
-            }
-            n += m;
         }
     }
-    vis.done(n, lane);
+    double plo[4], phi[4];
+    int pbelow[4], pm[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        plo[k] = __shfl(lo, k, kWave);
+        phi[k] = __shfl(hi, k, kWave);
+        pbelow[k] = __shfl(below, k, kWave);
+        pm[k] = __shfl(m, k, kWave);
+    }
+    const int total = pm[0] + pm[1] + pm[2] + pm[3];
+    for (int j = lane; j < total; j += kWave) {
+        int k = 0, base = 0;
+#pragma unroll
+        for (int kk = 1; kk < 4; ++kk)
+            if (j >= base + pm[k]) { base += pm[k]; k = kk; }
+        double l = plo[0], h = phi[0];
+        int bl = pbelow[0], mm = pm[0];
+#pragma unroll
+        for (int kk = 1; kk < 4; ++kk)
+            if (k == kk) { l = plo[kk]; h = phi[kk]; bl = pbelow[kk]; mm = pm[kk]; }
+        const int jj = j - base;
+        auto node = [&](int q) { return q == 0 ? l : (q == mm - 1 ? h : full_mesh(A.w, nf, bl + q - 1)); };
+        const double cur = node(jj);
+        const double wl = jj > 0 ? 0.5 * (cur - node(jj - 1)) : 0.0;
+        const double wr = jj + 1 < mm ? 0.5 * (node(jj + 1) - cur) : 0.0;
+        vis.kat(nd + j, cur, partner(ch, nu, cur), wl + wr);
+    }
+    vis.done(nd + total, lane);
 }
 
 // Writes the node list (frequencies tw, weights tg, length tn).
@@ -310,10 +344,11 @@ struct TableWriter {
     double* tw;
     double* tg;
     int* tn;
-    __device__ __forceinline__ void delta(int n, double node, double xx, double y, double th, int lane) {
+    __device__ __forceinline__ void delta(int n, double node, double xx, double y, double th) {
         const double st = 1.0 / (xx - odd_interp(w, nf, sig, xx));
         const double g = th / (y - odd_interp(w, nf, sig, y));
-        if (lane == 0) { tw[n] = node; tg[n] = -st * g * kInvTwoPi; }
+        tw[n] = node;
+        tg[n] = -st * g * kInvTwoPi;
     }
     __device__ __forceinline__ void kat(int n, double cur, double pp, double wt) {
         const double gw = 1.0 / (cur - odd_interp(w, nf, sig, cur));
