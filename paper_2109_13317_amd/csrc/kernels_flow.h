@@ -159,26 +159,29 @@ __device__ __forceinline__ void sigma_body(const FlowArgs& A, double lam, const 
     const double wn = A.w[n];
     const double* gs = x + A.nf;
     const double* gd = gs + nv;
-    double acc = 0.0;
-    for (int sx = 0; sx < 2; ++sx) {
-        const double xx = sx == 0 ? lam : -lam;
-        Plan P;
-        make_plan(A.w, A.nf, A.ns, wn + xx, 0.0, wn - xx, 1, 0, P);
-        double f = 0.0;
-        for (int r = lane; r < A.ns; r += kWave) {
-            double vs, vd;
-            eval_plan(P, gs, gd, A.swap, r, vs, vd);
-            f = fma(2.0 * (double)A.mult[r], vd, f);
-        }
-        f = wave_sum(f);
+    // lanes 0..31 take x = +Lambda, lanes 32..63 x = -Lambda; lane r of a
+    // half reads pair r (at most 32 pairs), its lane 0 also the on-site terms
+    const int half = lane >> 5, r = lane & 31;
+    const double xx = half == 0 ? lam : -lam;
+    Plan P;
+    make_plan(A.w, A.nf, A.ns, wn + xx, 0.0, wn - xx, 1, 0, P);
+    double f = 0.0;
+    if (r < A.ns) {
+        double vs, vd;
+        eval_plan(P, gs, gd, A.swap, r, vs, vd);
+        f = 2.0 * (double)A.mult[r] * vd;
+    }
+    if (r == 0) {
         Plan Q;
         make_plan(A.w, A.nf, A.ns, wn + xx, xx - wn, 0.0, 2, 0, Q);
         double os, od;
         eval_plan(Q, gs, gd, A.swap, 0, os, od);
         f -= 3.0 * os + od;
-        acc += f / (xx - odd_interp(A.w, A.nf, sig, xx));
     }
-    if (lane == 0) dsig[n] = acc * kInvTwoPi;
+    for (int o = 16; o > 0; o >>= 1) f += __shfl_xor(f, o, kWave);
+    const double term = f / (xx - odd_interp(A.w, A.nf, sig, xx));
+    const double other = __shfl(term, 32, kWave);
+    if (lane == 0) dsig[n] = (term + other) * kInvTwoPi;
 }
 
 // Mesh, self-energy and (optionally) its derivative copied to LDS by one
