@@ -64,6 +64,41 @@ struct PlanT {
 };
 using Plan = PlanT<double>;
 
+// The same plan with the weights left as the two bracket fractions t0, t1 of
+// the free slots: corner 2i + j weighs ((1 - t0, t0)[i]) ((1 - t1, t1)[j]),
+// formed where the plan is applied.  It is less than half the size of a
+// PlanT<double> in LDS and in registers.  flags: bit k set = the density weight
+// of corner k is negated (an s <-> u corner), bit 4 = exchanged pair.
+struct FracPlan {
+    int off[4];
+    double t0, t1;
+    int flags;
+};
+
+// The weights stored into a plan: products of the two bracket weights (and
+// the density sign), or the fractions alone.
+template <class R>
+__device__ __forceinline__ void plan_start(PlanT<R>&) {}
+__device__ __forceinline__ void plan_start(FracPlan& P) { P.flags = 0; }
+template <class R>
+__device__ __forceinline__ void plan_corner(PlanT<R>& P, int k, double g0, double g1, bool neg) {
+    const double wg = g0 * g1;
+    P.ws[k] = (R)wg;
+    P.wd[k] = (R)(neg ? -wg : wg);
+}
+__device__ __forceinline__ void plan_corner(FracPlan& P, int k, double, double, bool neg) {
+    P.flags |= (int)neg << k;
+}
+template <class R>
+__device__ __forceinline__ void plan_finish(PlanT<R>& P, int swp, double, double) {
+    P.swp = swp;
+}
+__device__ __forceinline__ void plan_finish(FracPlan& P, int swp, double t0, double t1) {
+    P.flags |= swp << 4;
+    P.t0 = t0;
+    P.t1 = t1;
+}
+
 // Bracket of x >= 0 with a precomputed reciprocal spacing table
 // ih[i] = 1 / (w[i+1] - w[i]); weights f1 = (x - w[lo]) ih[lo], f0 = 1 - f1.
 __device__ __forceinline__ void bracket_fast(const double* __restrict__ w, const double* __restrict__ ih,
@@ -82,9 +117,10 @@ __device__ __forceinline__ void bracket_fast(const double* __restrict__ w, const
 
 // kslot in {0,1,2}: which of (s, t, u) holds the on-mesh value, kidx its mesh
 // index (0 for a zero argument).  ih as in bracket_fast (NULL: divide).
-template <class R>
+// PL: PlanT<R> or FracPlan.
+template <class PL>
 __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, int ns,
-                                          double s, double t, double u, int kslot, int kidx, PlanT<R>& P,
+                                          double s, double t, double u, int kslot, int kidx, PL& P,
                                           const double* __restrict__ ih = nullptr) {
     int swp = 0;
     double sd = 1.0;
@@ -103,6 +139,7 @@ __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, 
     const double v1 = f1 == 1 ? t : u;
     int b0[2], b1[2];
     double g0[2], g1[2];
+    plan_start(P);
     if (ih) {
         bracket_fast(w, ih, nf, v0, b0[0], b0[1], g0[0], g0[1]);
         bracket_fast(w, ih, nf, v1, b1[0], b1[1], g1[0], g1[1]);
@@ -120,12 +157,10 @@ __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, 
             int a = ia, c = ic;
             double cs = sd;
             if (a < c) { const int q = a; a = c; c = q; cs = -cs; }
-            const double wg = g0[i] * g1[j];
             P.off[2 * i + j] = (int)((su_index(a, c) * nf + it) * ns);
-            P.ws[2 * i + j] = (R)wg;
-            P.wd[2 * i + j] = (R)(cs * wg);
+            plan_corner(P, 2 * i + j, g0[i], g1[j], cs < 0.0);
         }
-    P.swp = swp;
+    plan_finish(P, swp, g0[1], g1[1]);
 }
 
 // Value of both strains of pair p through a plan.

@@ -157,13 +157,13 @@ constexpr int kAll = 0, kSU = 1, kT = 2;
 
 // MAXNSP: the largest padded pair count the launch's points may have.  The
 // split t launch runs the points of up to 16 pairs in an instance compiled
-// for them alone (matrix-core lattice sum, fewer registers, more waves per
-// SIMD) and the larger ones in another.
+// for them alone (matrix-core lattice sum) and the larger ones in another;
+// each fits four waves per SIMD, the one-launch kAll form three.
 constexpr int kSmallNsp = 16;
 
 template <class R, int PART, int MAXNSP = 20>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(PART == kSU ? 4 : (MAXNSP <= kSmallNsp && sizeof(R) == 4 ? 4 : 3))))
+__attribute__((amdgpu_waves_per_eu(PART == kAll ? 3 : 4)))
 k_batch_vertex(BatchArgs B, const V2<R>* __restrict__ gv, const int2* __restrict__ items,
                const int* __restrict__ begin, int shared_bytes, int wave_bytes, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
@@ -213,7 +213,10 @@ k_batch_vertex(BatchArgs B, const V2<R>* __restrict__ gv, const int2* __restrict
             }
             if (PART != kSU) {
                 LanePart pt{0.0, 0.0};
-                switch ((ns + 3) / 4) {
+                // the large-pair t launch holds the 20-pair body alone, which
+                // keeps it within the registers of four waves per SIMD
+                if constexpr (PART == kT && MAXNSP > kSmallNsp) pt = t_body<20, R>(A, sh, base, T, rv, lane);
+                else switch ((ns + 3) / 4) {
                     case 1: pt = t_body<4, R>(A, sh, base, T, rv, lane); break;
                     case 2: pt = t_body<8, R>(A, sh, base, T, rv, lane); break;
                     case 3: pt = t_body<12, R>(A, sh, base, T, rv, lane); break;

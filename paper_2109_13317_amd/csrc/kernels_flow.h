@@ -122,12 +122,58 @@ __device__ __forceinline__ void eval_packed_ab(const PlanT<R>& Pa, const PlanT<R
     as = a0; ad = a1; bs = b0; bd = b1;
 }
 
+// The same two evaluations through fraction plans (FP64): the corner weights
+// are formed here, after the loads are issued.
+__device__ __forceinline__ void frac_apply(const FracPlan& P, const double2 (&g)[4], double& vs, double& vd) {
+    const double u0 = 1.0 - P.t0, u1 = 1.0 - P.t1;
+    const double wg[4] = {u0 * u1, u0 * P.t1, P.t0 * u1, P.t0 * P.t1};
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        a = fmr(wg[i], g[i].x, a);
+        b = fmr((P.flags >> i) & 1 ? -wg[i] : wg[i], g[i].y, b);
+    }
+    vs = a;
+    vd = b;
+}
+__device__ __forceinline__ void eval_packed2(const FracPlan& P, __amdgpu_buffer_rsrc_t r, int2 pp, double& vs,
+                                             double& vd) {
+    const unsigned q = P.flags & 16 ? pp.y : pp.x;
+    double2 g[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = load_corner(r, (unsigned)P.off[i] + q, double());
+    frac_apply(P, g, vs, vd);
+}
+__device__ __forceinline__ void eval_packed_ab(const FracPlan& Pa, const FracPlan& Pb, __amdgpu_buffer_rsrc_t r,
+                                               int2 pp, double& as, double& ad, double& bs, double& bd) {
+    const unsigned qa = Pa.flags & 16 ? pp.y : pp.x, qb = Pb.flags & 16 ? pp.y : pp.x;
+    double2 ga[4], gb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ga[i] = load_corner(r, (unsigned)Pa.off[i] + qa, double());
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gb[i] = load_corner(r, (unsigned)Pb.off[i] + qb, double());
+    frac_apply(Pa, ga, as, ad);
+    frac_apply(Pb, gb, bs, bd);
+}
+
 // A plan whose offsets are turned into byte offsets of the packed vertex.
 template <class R>
 __device__ __forceinline__ void to_bytes(PlanT<R>& P) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) P.off[i] *= kElemBytes<R>;
 }
+__device__ __forceinline__ void to_bytes(FracPlan& P) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P.off[i] *= kElemBytes<double>;
+}
+
+// The t channel's plans: in FP64 fraction plans (under half the LDS bytes
+// read per evaluation, and fewer live registers: the kernels up to 16 pairs
+// hold five waves per SIMD without spilling); in FP32 the float weights of
+// PlanT<float> are already compact.
+template <class R> struct TPlanOf { using type = PlanT<R>; };
+template <> struct TPlanOf<double> { using type = FracPlan; };
+template <class R> using TPlan = typename TPlanOf<R>::type;
 
 // Running sum of per-chunk partial sums.  In FP32 the rounding error of each
 // addition is carried along (Kahan's compensated summation) and the value is
@@ -463,7 +509,7 @@ struct WaveLds {
     int ns;
     int sub = kSub;   // nodes per lattice-sum sub-chunk
     __host__ __device__ int nsp() const { return (ns + 3) & ~3; }
-    __host__ __device__ size_t plans() const { return (size_t)2 * kTChunk * sizeof(PlanT<R>); }
+    __host__ __device__ size_t plans() const { return (size_t)2 * kTChunk * sizeof(TPlan<R>); }
     __host__ __device__ size_t onsite() const { return (((size_t)5 * kTChunk * sizeof(R)) + 15) & ~(size_t)15; }
     __host__ __device__ size_t su_plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
     __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(R); }
@@ -805,7 +851,7 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     constexpr bool kComp = sizeof(R) == 4;
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const WaveLds<R> L{ns, SUB};
-    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                           // [2][kTChunk]
+    TPlan<R>* plan = reinterpret_cast<TPlan<R>*>(base);                           // [2][kTChunk]
     R* ons = reinterpret_cast<R*>(base + L.plans());                                // [5][kTChunk]: on-site, weights
     R* wts = ons + 4 * kTChunk;
     R* vb = reinterpret_cast<R*>(base + L.plans() + L.onsite());                    // [4][SUB][NSP]
@@ -864,7 +910,7 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
                 const double a0 = role == 0 ? T.w1 + om : (role == 1 ? om + T.w2p : (role == 2 ? T.w2p + om : T.w1 + om));
                 const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
                 const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
-                PlanT<R> P;
+                TPlan<R> P;
                 make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, sh.ih);
                 to_bytes(P);
                 if (role < 2) {
@@ -1047,10 +1093,12 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
 }
 
-// One context, ordered by (t, s, u); adds to dGamma.
+// One context, ordered by (t, s, u); adds to dGamma.  Occupancy targets: the
+// widest that hold the register blocks without spilling (five waves per SIMD
+// up to 16 pairs, four up to 20, three beyond).
 template <int NSP, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(NSP > 16 ? 3 : 5)))
+__attribute__((amdgpu_waves_per_eu(NSP > 20 ? 3 : (NSP > 16 ? 4 : 5))))
 k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns;
