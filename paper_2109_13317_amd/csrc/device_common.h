@@ -99,29 +99,70 @@ __device__ __forceinline__ void plan_finish(FracPlan& P, int swp, double t0, dou
     P.t1 = t1;
 }
 
-// Bracket of x >= 0 with a precomputed reciprocal spacing table
-// ih[i] = 1 / (w[i+1] - w[i]); weights f1 = (x - w[lo]) ih[lo], f0 = 1 - f1.
-__device__ __forceinline__ void bracket_fast(const double* __restrict__ w, const double* __restrict__ ih,
-                                             int nf, double x, int& i0, int& i1, double& f0, double& f1) {
+// Mesh look-up table.  The bits of a positive double, read as an unsigned
+// integer, grow with its value, so key(x) = bits(x) >> shift (the exponent
+// and the leading mantissa bits) cuts the mesh range into buckets, each a
+// fixed fraction of an octave.  lut[key(x) - kmin] is the bracket of the
+// smallest value of x's bucket; from there a forward search finds x's own
+// bracket in a step or two wherever the mesh holds at most a point or two
+// per bucket (the logarithmic meshes of the flow: under one).
+constexpr int kLutMax = 512;   // buckets (bytes of LDS)
+
+__host__ __device__ inline unsigned lut_key(double x, int shift) {
+    return (unsigned)(__builtin_bit_cast(unsigned long long, x) >> shift);
+}
+
+struct MeshLut {
+    const double* ih;            // ih[i] = 1 / (w[i+1] - w[i])
+    const unsigned char* lut;    // [kLutMax] first bracket of each bucket
+    int shift, kmin;
+};
+
+// Host: the table of mesh w[0..nf) (positive, ascending, 2 <= nf <= 256):
+// the finest key (shift >= 32, so that it fits 32 bits) whose range fits
+// kLutMax buckets; per bucket the largest i <= nf - 2 with w[i] <= its
+// smallest value (0 below w[0]); buckets past the range hold nf - 2.
+inline void build_mesh_lut(const double* w, int nf, unsigned char* lut, int& shift, int& kmin) {
+    shift = 32;
+    while (shift < 62 && lut_key(w[nf - 1], shift) - lut_key(w[0], shift) >= (unsigned)kLutMax) ++shift;
+    kmin = (int)lut_key(w[0], shift);
+    const int n = (int)lut_key(w[nf - 1], shift) - kmin + 1;
+    int lo = 0;
+    for (int b = 0; b < kLutMax; ++b) {
+        if (b < n) {
+            const double x0 = __builtin_bit_cast(double, (unsigned long long)(kmin + b) << shift);
+            while (lo + 1 <= nf - 2 && w[lo + 1] <= x0) ++lo;
+            lut[b] = (unsigned char)lo;
+        } else {
+            lut[b] = (unsigned char)(nf - 2);
+        }
+    }
+}
+
+// Bracket of x >= 0 through the look-up table: the largest lo with
+// w[lo] <= x (what a binary search over the mesh finds), weights
+// f1 = (x - w[lo]) ih[lo], f0 = 1 - f1; constant outside the mesh.
+__host__ __device__ __forceinline__ void bracket_lut(const double* __restrict__ w, const MeshLut& m, int nf,
+                                                     double x, int& i0, int& i1, double& f0, double& f1) {
     if (x <= w[0]) { i0 = i1 = 0; f0 = 1.0; f1 = 0.0; return; }
     if (x >= w[nf - 1]) { i0 = i1 = nf - 1; f0 = 1.0; f1 = 0.0; return; }
-    int lo = 0, hi = nf - 1;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (w[mid] <= x) lo = mid; else hi = mid;
-    }
-    i0 = lo; i1 = hi;
-    f1 = (x - w[lo]) * ih[lo];
+    // w[0] < x < w[nf-1]: the key lies in the table's range (clamped all
+    // the same, so that a NaN stays in bounds; it then leaves lo as found)
+    const unsigned k = lut_key(x, m.shift) - (unsigned)m.kmin;
+    int lo = m.lut[k < (unsigned)kLutMax ? k : (unsigned)(kLutMax - 1)];
+    while (w[lo + 1] <= x) ++lo;   // stops at nf - 2 at the latest: w[nf-1] > x
+    i0 = lo; i1 = lo + 1;
+    f1 = (x - w[lo]) * m.ih[lo];
     f0 = 1.0 - f1;
 }
 
 // kslot in {0,1,2}: which of (s, t, u) holds the on-mesh value, kidx its mesh
-// index (0 for a zero argument).  ih as in bracket_fast (NULL: divide).
-// PL: PlanT<R> or FracPlan.
+// index (0 for a zero argument).  lut: the mesh look-up table (NULL: binary
+// search and division).  PL: PlanT<R> or FracPlan.
 template <class PL>
 __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, int ns,
                                           double s, double t, double u, int kslot, int kidx, PL& P,
-                                          const double* __restrict__ ih = nullptr) {
+                                          const MeshLut* lut = nullptr) {
     int swp = 0;
     double sd = 1.0;
     if (s < 0.0) { s = -s; swp ^= 1; }
@@ -140,9 +181,9 @@ __device__ __forceinline__ void make_plan(const double* __restrict__ w, int nf, 
     int b0[2], b1[2];
     double g0[2], g1[2];
     plan_start(P);
-    if (ih) {
-        bracket_fast(w, ih, nf, v0, b0[0], b0[1], g0[0], g0[1]);
-        bracket_fast(w, ih, nf, v1, b1[0], b1[1], g1[0], g1[1]);
+    if (lut) {
+        bracket_lut(w, *lut, nf, v0, b0[0], b0[1], g0[0], g0[1]);
+        bracket_lut(w, *lut, nf, v1, b1[0], b1[1], g1[0], g1[1]);
     } else {
         bracket(w, nf, v0, b0[0], b0[1], g0[0], g0[1]);
         bracket(w, nf, v1, b1[0], b1[1], g1[0], g1[1]);

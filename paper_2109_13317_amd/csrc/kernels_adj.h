@@ -229,11 +229,11 @@ k_vertex_vjp_su(FlowArgs A, const V2<double>* __restrict__ gv,
                 const double om = tw[k0 + j];
                 Plan P;
                 if (CH == 0) {
-                    if (vec == 0) make_plan(A.w, nf, ns, T.s, T.w1p - om, om - T.w2p, 0, ia, P, sh.ih);
-                    else make_plan(A.w, nf, ns, T.s, om - T.w1, om - T.w2, 0, ia, P, sh.ih);
+                    if (vec == 0) make_plan(A.w, nf, ns, T.s, T.w1p - om, om - T.w2p, 0, ia, P, &sh.lut);
+                    else make_plan(A.w, nf, ns, T.s, om - T.w1, om - T.w2, 0, ia, P, &sh.lut);
                 } else {
-                    if (vec == 0) make_plan(A.w, nf, ns, T.w1 + om, om - T.w2p, T.u, 2, ic, P, sh.ih);
-                    else make_plan(A.w, nf, ns, T.w1p + om, T.w2 - om, T.u, 2, ic, P, sh.ih);
+                    if (vec == 0) make_plan(A.w, nf, ns, T.w1 + om, om - T.w2p, T.u, 2, ic, P, &sh.lut);
+                    else make_plan(A.w, nf, ns, T.w1p + om, T.w2 - om, T.u, 2, ic, P, &sh.lut);
                 }
                 plan[vec * kPlanChunk + j] = P;
             }
@@ -365,7 +365,7 @@ k_vertex_vjp_t(FlowArgs A, const V2<double>* __restrict__ gv, int n_triples, con
                 const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
                 const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
                 Plan P;
-                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, sh.ih);
+                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, &sh.lut);
                 plan[role * kAdjTChunk + j] = P;
                 if (role >= 2) {
                     double os, od;

@@ -40,6 +40,8 @@ struct FlowArgs {
     int* tab_n;             // [3*nf] node counts
     double* tab_w;          // [3*nf*nq] node frequencies
     double* tab_g;          // [3*nf*nq] node weights
+    const unsigned char* lut;   // [kLutMax] mesh look-up table (build_mesh_lut)
+    int lut_shift, lut_kmin;
 };
 
 constexpr int kWave = 64;
@@ -440,13 +442,15 @@ constexpr int kSub = 8;          // nodes per lattice-sum sub-chunk
 constexpr int kMaxPairs = 32;    // 2 register blocks of 2x4 per lane cover 32 x 32
 constexpr int kMaxFreq = 128;    // mesh copy in LDS
 
-// Workgroup-shared tables in LDS: mesh, reciprocal spacings, pair exchange,
-// and (t channel) the packed tabulated lattice-sum terms with their offsets.
+// Workgroup-shared tables in LDS: mesh, reciprocal spacings, the mesh look-up
+// table, pair exchange, and (t channel) the packed tabulated lattice-sum
+// terms with their offsets.
 struct SharedLds {
     int nf, ns, n_terms;
     __host__ __device__ size_t mesh() const { return 0; }
     __host__ __device__ size_t ih() const { return (size_t)nf * sizeof(double); }
-    __host__ __device__ size_t swap() const { return (size_t)2 * nf * sizeof(double); }
+    __host__ __device__ size_t lut() const { return (size_t)2 * nf * sizeof(double); }
+    __host__ __device__ size_t swap() const { return lut() + kLutMax; }
     __host__ __device__ size_t off() const { return swap() + (size_t)ns * sizeof(int); }
     __host__ __device__ size_t terms() const { return off() + (size_t)(ns + 1) * sizeof(int); }
     __host__ __device__ size_t bytes(bool with_terms) const {
@@ -457,7 +461,7 @@ struct SharedLds {
 
 struct Shared {
     const double* w;
-    const double* ih;
+    MeshLut lut;    // reciprocal spacings and look-up table in LDS
     const int* swap;
     const int* off;
     const int* terms;
@@ -466,7 +470,8 @@ struct Shared {
 // Pointers to the shared tables in LDS (no memory traffic).
 __device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* lds) {
     const SharedLds S{A.nf, A.ns, A.n_terms};
-    return Shared{reinterpret_cast<double*>(lds + S.mesh()), reinterpret_cast<double*>(lds + S.ih()),
+    return Shared{reinterpret_cast<double*>(lds + S.mesh()),
+                  MeshLut{reinterpret_cast<double*>(lds + S.ih()), lds + S.lut(), A.lut_shift, A.lut_kmin},
                   reinterpret_cast<int*>(lds + S.swap()), reinterpret_cast<int*>(lds + S.off()),
                   reinterpret_cast<int*>(lds + S.terms())};
 }
@@ -475,7 +480,8 @@ __device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* 
 __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
     const Shared sh = shared_ptrs(A, lds);
     double* w = const_cast<double*>(sh.w);
-    double* ih = const_cast<double*>(sh.ih);
+    double* ih = const_cast<double*>(sh.lut.ih);
+    unsigned* lut = reinterpret_cast<unsigned*>(const_cast<unsigned char*>(sh.lut.lut));
     int* sw = const_cast<int*>(sh.swap);
     int* off = const_cast<int*>(sh.off);
     int* terms = const_cast<int*>(sh.terms);
@@ -483,6 +489,7 @@ __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* ld
         w[i] = A.w[i];
         ih[i] = i + 1 < A.nf ? 1.0 / (A.w[i + 1] - A.w[i]) : 0.0;
     }
+    for (int i = threadIdx.x; i < kLutMax / 4; i += blockDim.x) lut[i] = reinterpret_cast<const unsigned*>(A.lut)[i];
     for (int i = threadIdx.x; i < A.ns; i += blockDim.x) sw[i] = A.swap[i];
     if (with_terms) {
         for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
@@ -717,10 +724,10 @@ __device__ __forceinline__ SuPart su_body(const FlowArgs& A, const Shared& sh, P
                 PlanT<R> P;
                 if (CH == 0)
                     make_plan(A.w, nf, ns, T.s, vec == 0 ? T.w1p - om : om - T.w1, vec == 0 ? om - T.w2p : om - T.w2,
-                              0, ia, P, sh.ih);
+                              0, ia, P, &sh.lut);
                 else
                     make_plan(A.w, nf, ns, vec == 0 ? T.w1 + om : T.w1p + om, vec == 0 ? om - T.w2p : T.w2 - om, T.u,
-                              2, ic, P, sh.ih);
+                              2, ic, P, &sh.lut);
                 to_bytes(P);
                 plan[vec * kPlanChunk + j] = P;
             }
@@ -911,7 +918,7 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
                 const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
                 const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
                 TPlan<R> P;
-                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, sh.ih);
+                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, &sh.lut);
                 to_bytes(P);
                 if (role < 2) {
                     plan[role * kTChunk + j] = P;

@@ -39,6 +39,8 @@ struct pffrg_ctx {
 
     // tables
     double* w = nullptr;
+    unsigned char* lut = nullptr;   // [kLutMax] mesh look-up table
+    int lut_shift = 0, lut_kmin = 0;
     int *swap = nullptr, *mult = nullptr, *rpa_off = nullptr, *rpa_ka = nullptr,
         *rpa_kb = nullptr, *rpa_cnt = nullptr, *su_a = nullptr, *su_c = nullptr, *uo_a = nullptr,
         *uo_c = nullptr;
@@ -87,6 +89,7 @@ struct pffrg_ctx {
         A.rpa_kb = rpa_kb; A.rpa_cnt = rpa_cnt; A.su_a = su_a; A.su_c = su_c;
         A.rpa_term = rpa_term; A.n_terms = n_terms;
         A.tab_n = tab_n; A.tab_w = tab_w; A.tab_g = tab_g;
+        A.lut = lut; A.lut_shift = lut_shift; A.lut_kmin = lut_kmin;
         return A;
     }
 };
@@ -511,6 +514,11 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
 
     auto body = [&]() -> pffrg_status {
         TRY(upload(c, &c->w, mesh->omega, (size_t)nf));
+        {
+            unsigned char lut[kLutMax];
+            build_mesh_lut(mesh->omega, nf, lut, c->lut_shift, c->lut_kmin);
+            TRY(upload(c, &c->lut, lut, (size_t)kLutMax));
+        }
         TRY(upload(c, &c->swap, lat->swap, (size_t)ns));
         TRY(upload(c, &c->mult, lat->mult, (size_t)ns));
         TRY(upload(c, &c->rpa_off, lat->rpa_off, (size_t)ns + 1));

@@ -64,6 +64,8 @@ struct pffrg_batch {
     DevAllocs mem;
 
     double* w = nullptr;
+    unsigned char* lut = nullptr;   // [kLutMax] mesh look-up table
+    int lut_shift = 0, lut_kmin = 0;
     int *swap = nullptr, *mult = nullptr, *rpa_off = nullptr, *rpa_term = nullptr;
     int *su_a = nullptr, *su_c = nullptr;
     double* coupling = nullptr;
@@ -110,6 +112,7 @@ struct pffrg_batch {
         A.rpa_cnt = nullptr; A.rpa_term = rpa_term; A.n_terms = n_terms[0];
         A.su_a = su_a; A.su_c = su_c;
         A.tab_n = tab_n; A.tab_w = tab_w; A.tab_g = tab_g;
+        A.lut = lut; A.lut_shift = lut_shift; A.lut_kmin = lut_kmin;
         B.pts = d_pts;
         B.n_points = np;
         return B;
@@ -394,6 +397,11 @@ pffrg_status pffrg_batch_create(int n_points, const pffrg_lattice* const* lats, 
             if ((long)b->nsu * nf * P.ns * 16 > 0x7fffffffL) return fail(PFFRG_EUNSUPPORTED, "point too large");
 
         TRY(b->mem.upload(&b->w, mesh->omega, (size_t)nf));
+        {
+            unsigned char lut[kLutMax];
+            build_mesh_lut(mesh->omega, nf, lut, b->lut_shift, b->lut_kmin);
+            TRY(b->mem.upload(&b->lut, lut, (size_t)kLutMax));
+        }
         TRY(b->mem.upload(&b->swap, swap.data(), swap.size()));
         TRY(b->mem.upload(&b->mult, mult.data(), mult.size()));
         TRY(b->mem.upload(&b->rpa_off, roff.data(), roff.size()));
