@@ -515,8 +515,9 @@ def main():
     lam_timed0 = lam[0]
     x_timed0 = x.clone()
     torch.cuda.synchronize()
-    # timed region: HIP events around the t-channel launches only (an event
-    # pair around every launch would add ~12 % to the step)
+    # timed region: HIP events on the t-channel launches only (the library
+    # hands them to the launch, which stamps its own start and end, so they
+    # add nothing to the stream)
     ctx.set_profiling(True, kernels=("vertex_t",))
     t0 = time.perf_counter()
     for _ in range(args.steps):

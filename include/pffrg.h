@@ -228,9 +228,12 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
 
 /* ----------------------------------------------------------- profiling - */
 
-/* Kernel timing with HIP events recorded on the context's stream around every
- * launch of the timed kernels (no effect on results; each event pair adds a
- * few microseconds between launches).  pffrg_set_profiling turns recording on
+/* Kernel timing with HIP events on the context's stream for every launch of
+ * the timed kernels (no effect on results).  The single-kernel ids get the
+ * start and end of the launch itself (events handed to the launch, adding
+ * nothing to the stream); PFFRG_K_VERTEX is timed by events recorded before
+ * the s and after the t launch (a few microseconds of stream time each).
+ * pffrg_set_profiling turns recording on
  * for all of them (1) or off (0); pffrg_set_profiling_mask records only the
  * kernels whose bit (1 << id) is set in `mask` (0: off; a bit at or above
  * PFFRG_K_COUNT: PFFRG_EINVAL).  Both synchronise the stream and clear the

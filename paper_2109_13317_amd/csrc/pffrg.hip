@@ -4,6 +4,7 @@
 // scratch buffer, all allocated in pffrg_create.  The flow kernels live in
 // kernels_flow.h, correlations and Runge-Kutta vector kernels in
 // kernels_obs.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -127,21 +128,48 @@ pffrg_status check_ctx(const pffrg_ctx* c) {
     return PFFRG_OK;
 }
 
-// Record an event before/after a launch of kernel `id` while profiling.
+// Kernel timing.  Event pairs per kernel id, created on first use; timing
+// only (read after a stream synchronisation), so without the system-scope
+// fence, whose cache writeback would stall the stream.
 constexpr int kMaxTimed = 65536;
 
-void prof_mark(pffrg_ctx* c, int id, bool after) {
-    if (!((c->prof_mask >> id) & 1u)) return;
+bool prof_events(pffrg_ctx* c, int id, int slot) {
     auto& v = c->ev[id];
-    const int slot = 2 * c->ev_used[id] + (after ? 1 : 0);
-    if (c->ev_used[id] >= kMaxTimed) return;
     while ((int)v.size() <= slot) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { c->prof_mask = 0; return; }
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) { c->prof_mask = 0; return false; }
         v.push_back(e);
     }
-    (void)hipEventRecord(v[slot], c->stream);
+    return true;
+}
+
+// Events recorded on the stream before/after the launches of kernel `id`
+// (the whole vertex right-hand side, which spans several launches).
+void prof_mark(pffrg_ctx* c, int id, bool after) {
+    if (!((c->prof_mask >> id) & 1u) || c->ev_used[id] >= kMaxTimed) return;
+    const int slot = 2 * c->ev_used[id] + (after ? 1 : 0);
+    if (!prof_events(c, id, slot)) return;
+    (void)hipEventRecord(c->ev[id][slot], c->stream);
     if (after) ++c->ev_used[id];
+}
+
+// The start/stop pair for the next launch of kernel `id` (nulls when it is
+// not timed).  The pair is handed to hipExtLaunchKernelGGL, which stamps it
+// with the launch's own start and end, so timing adds no packets (and no
+// gaps) to the stream.
+struct ProfPair {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
+ProfPair prof_pair(pffrg_ctx* c, int id) {
+    ProfPair e;
+    if (!((c->prof_mask >> id) & 1u) || c->ev_used[id] >= kMaxTimed) return e;
+    const int slot = 2 * c->ev_used[id];
+    if (!prof_events(c, id, slot + 1)) return e;
+    e.start = c->ev[id][slot];
+    e.stop = c->ev[id][slot + 1];
+    ++c->ev_used[id];
+    return e;
 }
 
 // LDS of the t-channel launch (shared tables + 4 waves) for ns pairs.
@@ -159,9 +187,9 @@ size_t t_lds_bytes(int nf, int ns, int n_terms, pffrg_precision prec) {
 
 pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
     FlowArgs A = c->args();
-    prof_mark(c, PFFRG_K_SIGMA, false);
-    hipLaunchKernelGGL(k_sigma_rhs, dim3(c->nf), dim3(kWave), 0, c->stream, A, lam, x, (long)c->vsz, dsig);
-    prof_mark(c, PFFRG_K_SIGMA, true);
+    const ProfPair e = prof_pair(c, PFFRG_K_SIGMA);
+    hipExtLaunchKernelGGL(k_sigma_rhs, dim3(c->nf), dim3(kWave), 0, c->stream, e.start, e.stop, 0, A, lam, x,
+                          (long)c->vsz, dsig);
     return launch_check("k_sigma_rhs");
 }
 
@@ -182,25 +210,23 @@ pffrg_status vertex_rhs(pffrg_ctx* c, const double* x, double* dx) {
     const size_t lds_su = S.bytes(false) + kWavesPerBlock * Lsu.su_bytes();
     const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
     prof_mark(c, PFFRG_K_VERTEX, false);
-    prof_mark(c, PFFRG_K_VERTEX_S, false);
-    hipLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, c->stream, A, (const V2<R>*)gv,
-                       (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
-    prof_mark(c, PFFRG_K_VERTEX_S, true);
-    prof_mark(c, PFFRG_K_VERTEX_U, false);
-    hipLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, c->stream, A, (const V2<R>*)gv,
-                       (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
-    prof_mark(c, PFFRG_K_VERTEX_U, true);
+    const ProfPair es = prof_pair(c, PFFRG_K_VERTEX_S);
+    hipExtLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, c->stream, es.start, es.stop, 0, A,
+                          (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
+    const ProfPair eu = prof_pair(c, PFFRG_K_VERTEX_U);
+    hipExtLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, c->stream, eu.start, eu.stop, 0, A,
+                          (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
     const size_t lds_t = t_lds_bytes<R>(c->nf, c->ns, c->n_terms);
-    prof_mark(c, PFFRG_K_VERTEX_T, false);
+    const ProfPair et = prof_pair(c, PFFRG_K_VERTEX_T);
     switch ((c->ns + 3) / 4) {
 #define PFFRG_T_CASE(K) \
-        case K: hipLaunchKernelGGL((k_vertex_t<4 * K, R>), grid, block, lds_t, c->stream, A, (const V2<R>*)gv, T, dx); break;
+        case K: hipExtLaunchKernelGGL((k_vertex_t<4 * K, R>), grid, block, lds_t, c->stream, et.start, et.stop, 0, \
+                                      A, (const V2<R>*)gv, T, dx); break;
         PFFRG_T_CASE(1) PFFRG_T_CASE(2) PFFRG_T_CASE(3) PFFRG_T_CASE(4)
         PFFRG_T_CASE(5) PFFRG_T_CASE(6) PFFRG_T_CASE(7) PFFRG_T_CASE(8)
 #undef PFFRG_T_CASE
         default: return fail(PFFRG_EUNSUPPORTED, "pair count out of range");
     }
-    prof_mark(c, PFFRG_K_VERTEX_T, true);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_vertex_t");
 }
@@ -209,9 +235,9 @@ pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
     FlowArgs A = c->args();
     TRY(sigma_rhs(c, lam, x, dx));                  // the sigma part of dx is dsig
-    prof_mark(c, PFFRG_K_TABLES, false);
-    hipLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, A, lam, x, (const double*)dx);
-    prof_mark(c, PFFRG_K_TABLES, true);
+    const ProfPair e = prof_pair(c, PFFRG_K_TABLES);
+    hipExtLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, e.start, e.stop, 0, A, lam, x,
+                          (const double*)dx);
     TRY(launch_check("k_node_tables"));
     return c->prec == PFFRG_FP32 ? vertex_rhs<float>(c, x, dx) : vertex_rhs<double>(c, x, dx);
 }

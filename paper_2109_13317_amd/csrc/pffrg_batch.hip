@@ -150,7 +150,8 @@ void prof_mark(pffrg_batch* b, hipStream_t s, bool after) {
     if (b->ev_used >= 65536) return;
     while ((int)b->ev.size() <= slot) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) { b->profiling = false; return; }
+        // timing only (read after a stream synchronisation): no system-scope fence
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) { b->profiling = false; return; }
         b->ev.push_back(e);
     }
     (void)hipEventRecord(b->ev[slot], s);
