@@ -100,6 +100,31 @@ def node_counts(mesh: np.ndarray, lam: float) -> np.ndarray:
     return out
 
 
+def checkpoint_cost(x) -> dict:
+    """Time to write and read back one flow snapshot of state x (median of 3,
+    a temporary directory on the host's disk)."""
+    import tempfile
+    import torch
+    from paper_2109_13317_amd import checkpoint as ck
+    state = x.cpu().numpy()
+    wr, rd = [], []
+    with tempfile.TemporaryDirectory() as d:
+        p = os.path.join(d, "flow.checkpoint")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            torch.cuda.synchronize()
+            ck.write(p, x.cpu().numpy(), {"format": ck.FORMAT})
+            wr.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            x.copy_(torch.from_numpy(ck.read(p).state))
+            torch.cuda.synchronize()
+            rd.append(time.perf_counter() - t0)
+        size = os.path.getsize(p)
+    assert (x.cpu().numpy() == state).all()
+    return {"bytes": size, "write_ms": 1e3 * float(np.median(wr)), "read_ms": 1e3 * float(np.median(rd)),
+            "includes": "device-host copy, npz write with fsync and rename / read and host-device copy"}
+
+
 def vertex_flops(mesh: np.ndarray, lam: float, ns: int, n_terms: int) -> dict:
     """Algorithmic FP64 flops of one vertex right-hand side at cutoff lam,
     per channel launch.
@@ -622,9 +647,25 @@ def main():
         nsteps = ctx.flow(xf, scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4,
                           atol=1e-6, h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=obs)
         torch.cuda.synchronize()
+        flow_s = time.perf_counter() - t0
+        # the same flow again, untimed, recording chi_max(Lambda) for the
+        # breakdown detector
+        from paper_2109_13317_amd.breakdown import ChiMaxRecorder
+        rec = ChiMaxRecorder()
+        ctx.flow(ctx.init_state(), scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4, atol=1e-6,
+                 h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=rec)
+        chimax = np.asarray(rec.chi_max)
+        bd = rec.breakdown(lam_max=wl.mesh[-1] / 4)
+        log(f"breakdown detector: {bd.kind} (Lambda = {bd.lam})")
         out["full_flow"] = {"scheme": "dopri54 in ln Lambda, rtol 1e-4, atol 1e-6, steps land on w_n/2",
-                            "lambda": [100.0, 0.01], "seconds": time.perf_counter() - t0,
-                            "accepted_steps": nsteps, "chi_k_every_step": "64x64"}
+                            "lambda": [100.0, 0.01], "seconds": flow_s,
+                            "accepted_steps": nsteps, "chi_k_every_step": "64x64",
+                            "breakdown": {"kind": bd.kind, "lambda": bd.lam, "step": bd.index,
+                                          "chi_max_first": float(chimax[0]), "chi_max_last": float(chimax[-1]),
+                                          "detector": "first step below a quarter of the top mesh frequency "
+                                                      "with ln chi_max slope in ln Lambda below -8 or a "
+                                                      "slope change above 1 (heuristic)"},
+                            "checkpoint": checkpoint_cost(xf)}
 
     if not args.no_extras:
         log("FP32 mode")

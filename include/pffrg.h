@@ -160,6 +160,16 @@ typedef struct {
     int n_k;
     const double *d_k;
     double *d_chi_k;            /* device output [n_k], passed to the observer */
+    /* adaptive: resume != 0 continues an earlier flow from the position
+     * (ln Lambda, step-ladder index) that pffrg_flow_position reported at one
+     * of its accepted steps, with d_state the state accepted there; lam_start
+     * is then ignored.  With the same mesh, lattice, precision, tolerances,
+     * h0 and lam_stop the continued flow takes exactly the steps the earlier
+     * one took after that point (bitwise the same states); with a lower
+     * lam_stop it extends a finished flow. */
+    int resume;
+    int resume_ladder;
+    double resume_log_lambda;
 } pffrg_flow_opts;
 
 /* Integrate d_state along the options' schedule.  Returns PFFRG_EDIVERGED
@@ -168,6 +178,15 @@ typedef struct {
  * steps is written to *n_steps if it is not NULL. */
 pffrg_status pffrg_flow(pffrg_ctx *ctx, const pffrg_flow_opts *opts, double *d_state,
                         pffrg_observer cb, void *user, int *n_steps);
+
+/* Position of the last accepted step of the running (when called from the
+ * observer) or last flow on this context: its cutoff, ln of it as the
+ * integrator holds it, and the step-ladder index the adaptive controller
+ * would start the next step from (fixed schedules: the index of the accepted
+ * cutoff in the schedule).  These, with the state, are what a checkpoint
+ * needs to resume the flow exactly (the paper's checkpoint files, Sec. 5.1).
+ * Before any accepted step: PFFRG_EINVAL. */
+pffrg_status pffrg_flow_position(pffrg_ctx *ctx, double *lambda, double *log_lambda, int *ladder);
 
 /* --------------------------------------------------------- observables - */
 

@@ -5,7 +5,8 @@ kernels behind the C ABI of include/pffrg.h (libpffrg.so, built in this
 directory).  This package holds the Python binding (``flow.Context`` for one flow,
 ``flow.Batch`` for many flows in lockstep), the
 lattice front end that produces the ABI's symmetry-reduced tables
-(``lattice.build_tables``) and the build script.
+(``lattice.build_tables``), flow checkpoints (``checkpoint``), the breakdown
+detector for chi_max(Lambda) (``breakdown``) and the build script.
 """
 
 from .lattice import LatticeTables, build_tables

@@ -34,7 +34,8 @@ class Mesh(ctypes.Structure):
 class FlowOpts(ctypes.Structure):
     _fields_ = [("scheme", I), ("n_lambda", I), ("lambdas", P), ("lam_start", D),
                 ("lam_stop", D), ("rtol", D), ("atol", D), ("h0", D), ("hmin", D),
-                ("max_steps", I), ("n_k", I), ("d_k", P), ("d_chi_k", P)]
+                ("max_steps", I), ("n_k", I), ("d_k", P), ("d_chi_k", P),
+                ("resume", I), ("resume_ladder", I), ("resume_log_lambda", D)]
 
 
 OBSERVER = ctypes.CFUNCTYPE(ctypes.c_int, D, P, P, P)
@@ -50,6 +51,7 @@ SIGNATURES = {
     "pffrg_sigma_rhs": [P, D, P, P],
     "pffrg_step": [P, I, D, D, P],
     "pffrg_flow": [P, ctypes.POINTER(FlowOpts), P, OBSERVER, P, ctypes.POINTER(I)],
+    "pffrg_flow_position": [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I)],
     "pffrg_chi": [P, D, P, P],
     "pffrg_chi_k": [P, P, I, P, P],
     "pffrg_measure_peaks": [P, P],

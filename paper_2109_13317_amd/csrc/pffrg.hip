@@ -79,6 +79,11 @@ struct pffrg_ctx {
 
     // kernel timing: event pairs recorded around the launches of the kernels
     // whose bit (1 << kernel id) is set
+    // position of the last accepted flow step (pffrg_flow_position)
+    bool flow_pos = false;
+    double flow_lambda = 0.0, flow_log_lambda = 0.0;
+    int flow_ladder = 0;
+
     unsigned prof_mask = 0;
     std::vector<hipEvent_t> ev[PFFRG_K_COUNT];
     int ev_used[PFFRG_K_COUNT] = {};
@@ -728,6 +733,7 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
     if (o->n_k < 0 || (o->n_k > 0 && (!o->d_k || !o->d_chi_k))) return fail(PFFRG_EINVAL, "bad k-point arguments");
     int steps = 0;
     if (n_steps) *n_steps = 0;
+    c->flow_pos = false;
     if (o->scheme == PFFRG_EULER || o->scheme == PFFRG_RK4) {
         if (o->n_lambda < 2 || !o->lambdas) return fail(PFFRG_EINVAL, "fixed schedule needs >= 2 cutoffs");
         for (int i = 0; i < o->n_lambda; ++i)
@@ -747,6 +753,10 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
             }
             ++steps;
             if (n_steps) *n_steps = steps;
+            c->flow_pos = true;
+            c->flow_lambda = o->lambdas[i + 1];
+            c->flow_log_lambda = std::log(o->lambdas[i + 1]);
+            c->flow_ladder = i + 1;
             int stop = 0;
             TRY(observe(c, o, o->lambdas[i + 1], x, cb, user, &stop));
             if (stop) break;
@@ -754,16 +764,18 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
         return PFFRG_OK;
     }
     if (o->scheme != PFFRG_DOPRI54) return fail(PFFRG_EINVAL, "unknown scheme");
-    if (!(o->lam_start > o->lam_stop) || !(o->lam_stop > 0.0) || !(o->h0 > 0.0) || !(o->hmin > 0.0) ||
-        !(o->rtol >= 0.0) || !(o->atol >= 0.0) || !(o->rtol + o->atol > 0.0))
-        return fail(PFFRG_EINVAL, "bad adaptive options");
     const double lend = std::log(o->lam_stop);
-    double l = std::log(o->lam_start);
+    const double lstart = o->resume ? o->resume_log_lambda : std::log(o->lam_start);
+    const bool down = o->resume ? lstart > lend : o->lam_start > o->lam_stop;
+    if (!down || !(o->lam_stop > 0.0) || !(o->h0 > 0.0) || !(o->hmin > 0.0) || !(o->rtol >= 0.0) ||
+        !(o->atol >= 0.0) || !(o->rtol + o->atol > 0.0) || !std::isfinite(lstart))
+        return fail(PFFRG_EINVAL, "bad adaptive options");
+    double l = lstart;
     // Step sizes live on the ladder h0 * 2^(m/4); the controller only moves
     // the integer m, so the accepted cutoffs are a deterministic function of
     // accept/reject decisions and reproduce across implementations whose
     // error estimates differ by rounding.
-    int m = 0;
+    int m = o->resume ? o->resume_ladder : 0;
     auto ladder = [&](int mm) { return o->h0 * std::pow(2.0, mm / 4.0); };
     auto quarter_steps = [](double fac) { return (int)std::lround(4.0 * std::log2(fac)); };
     const int maxs = o->max_steps > 0 ? o->max_steps : 1000000;
@@ -809,12 +821,16 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
             }
             ++steps;
             if (n_steps) *n_steps = steps;
-            int stop = 0;
-            TRY(observe(c, o, std::exp(l), x, cb, user, &stop));
-            if (stop || steps >= maxs) break;
             const double fac = err > 0.0 ? std::fmin(5.0, std::fmax(0.2, 0.9 * std::pow(err, -0.2))) : 5.0;
             const int dm = quarter_steps(fac);
             if (!(at_brk || last) || dm < 0) m += dm;   // a step cut short keeps its size
+            c->flow_pos = true;
+            c->flow_lambda = std::exp(l);
+            c->flow_log_lambda = l;
+            c->flow_ladder = m;
+            int stop = 0;
+            TRY(observe(c, o, std::exp(l), x, cb, user, &stop));
+            if (stop || steps >= maxs) break;
         } else {
             const double fac = (fin && err > 0.0) ? std::fmin(1.0, std::fmax(0.2, 0.9 * std::pow(err, -0.2))) : 0.2;
             m += std::min(-1, quarter_steps(fac));
@@ -822,6 +838,15 @@ pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg
         if (ladder(m) < o->hmin && l > lend)
             return fail(PFFRG_EDIVERGED, "adaptive step fell below hmin at lambda = " + std::to_string(std::exp(l)));
     }
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_flow_position(pffrg_ctx* c, double* lambda, double* log_lambda, int* ladder) {
+    TRY(check_ctx(c));
+    if (!c->flow_pos) return fail(PFFRG_EINVAL, "no accepted flow step on this context");
+    if (lambda) *lambda = c->flow_lambda;
+    if (log_lambda) *log_lambda = c->flow_log_lambda;
+    if (ladder) *ladder = c->flow_ladder;
     return PFFRG_OK;
 }
 

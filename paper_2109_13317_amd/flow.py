@@ -41,6 +41,7 @@ class Context:
     def __init__(self, tables: LatticeTables, mesh, precision: str = "fp64", stream=None):
         self.lib = _lib.load()
         self.tables = tables
+        self.precision = precision
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.ns = tables.n_pairs
@@ -108,9 +109,11 @@ class Context:
 
     def flow(self, x: torch.Tensor, *, schedule=None, scheme: str = "rk4", lam_start=None,
              lam_stop=None, rtol=1e-6, atol=1e-10, h0=0.05, hmin=1e-8, max_steps=0,
-             kpoints: torch.Tensor | None = None, observer=None) -> int:
+             kpoints: torch.Tensor | None = None, observer=None, resume=None) -> int:
         """Integrate x in place; observer(lam, chi_pairs[2, ns], chi_k or None)
-        receives torch views of the library's device buffers (copy to keep)."""
+        receives torch views of the library's device buffers (copy to keep).
+        resume=(log_lambda, ladder) continues an adaptive flow from a position
+        that position() reported (lam_start is then ignored)."""
         o = _lib.FlowOpts()
         o.scheme = {"euler": _lib.EULER, "rk4": _lib.RK4, "dopri54": _lib.DOPRI54}[scheme]
         sched = None
@@ -119,7 +122,10 @@ class Context:
             o.n_lambda = len(sched)
             o.lambdas = ctypes.c_void_p(sched.ctypes.data)
         else:
-            o.lam_start, o.lam_stop = float(lam_start), float(lam_stop)
+            o.lam_start = float(lam_start) if lam_start is not None else 0.0
+            o.lam_stop = float(lam_stop)
+            if resume is not None:
+                o.resume, o.resume_log_lambda, o.resume_ladder = 1, float(resume[0]), int(resume[1])
         o.rtol, o.atol, o.h0, o.hmin, o.max_steps = rtol, atol, h0, hmin, int(max_steps)
         chik = None
         if kpoints is not None:
@@ -141,6 +147,15 @@ class Context:
                                        ctypes.byref(nsteps)))
         del sched
         return int(nsteps.value)
+
+    def position(self) -> tuple[float, float, int]:
+        """(lambda, ln lambda, ladder index) of the last accepted flow step:
+        the adaptive controller's step index, or for fixed schedules the index
+        of the accepted cutoff in the schedule."""
+        lam, ll, lad = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+        _lib.check(self.lib.pffrg_flow_position(self.handle, ctypes.byref(lam), ctypes.byref(ll),
+                                                ctypes.byref(lad)))
+        return lam.value, ll.value, lad.value
 
     # ------------------------------------------------------ reverse mode --
     def init_state_from(self, coupling, x: torch.Tensor | None = None) -> torch.Tensor:
