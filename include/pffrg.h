@@ -261,7 +261,7 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
  * profiling was switched on.  Up to 65536 launches per kernel are kept. */
 enum {
     PFFRG_K_SIGMA = 0,      /* self-energy flow */
-    PFFRG_K_TABLES = 1,     /* per-channel quadrature tables */
+    PFFRG_K_TABLES = 1,     /* per-channel quadrature tables (with the packed vertex copy, same launch) */
     PFFRG_K_VERTEX = 2,     /* the whole vertex flow (the three channel launches) */
     PFFRG_K_VERTEX_S = 3,   /* s channel */
     PFFRG_K_VERTEX_U = 4,   /* u channel */

@@ -427,6 +427,39 @@ k_node_tables(FlowArgs A, double lam, const double* __restrict__ x, const double
     tables_body(A, lam, M.sig, M.dsig, blockIdx.x, threadIdx.x);
 }
 
+// The node tables and the packed vertex in one launch (both only read the
+// state): the first 3 nf workgroups build one node list each, the others
+// pack kPackPerLane elements per lane, so the bandwidth-bound packing runs
+// beside the latency-bound tables instead of after them.
+constexpr int kPackPerLane = 4;
+
+template <class R>
+static __global__ void __launch_bounds__(kWave)
+k_tables_pack(FlowArgs A, double lam, const double* __restrict__ x, const double* __restrict__ dsig, long nv,
+              V2<R>* __restrict__ gv) {
+    const int n_lists = 3 * A.nf;
+    if ((int)blockIdx.x < n_lists) {
+        __shared__ MeshLds M;
+        M.load(A, x, dsig, threadIdx.x);
+        A.w = M.w;
+        tables_body(A, lam, M.sig, M.dsig, blockIdx.x, threadIdx.x);
+        return;
+    }
+    const double* gs = x + A.nf;
+    const double* gd = gs + nv;
+    const long base = (long)(blockIdx.x - n_lists) * (kWave * kPackPerLane) + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kPackPerLane; ++j) {
+        const long i = base + (long)j * kWave;
+        if (i < nv) {
+            V2<R> v;
+            v.x = (R)gs[i];
+            v.y = (R)gd[i];
+            gv[i] = v;
+        }
+    }
+}
+
 // ------------------------------------------------------------- vertex RHS -
 //
 // The vertex right-hand side is three launches, one per channel, each with

@@ -198,15 +198,22 @@ pffrg_status sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) 
     return launch_check("k_sigma_rhs");
 }
 
-// The vertex right-hand side in precision R: pack the state's vertex into
-// c->gv, then the three channel launches (s writes dGamma, u and t add).
+// Node tables and the packed vertex (c->gv) in precision R, one launch.
 template <class R>
-pffrg_status vertex_rhs(pffrg_ctx* c, const double* x, double* dx) {
+pffrg_status tables_pack(pffrg_ctx* c, double lam, const double* x, const double* dsig) {
+    const ProfPair e = prof_pair(c, PFFRG_K_TABLES);
+    const long packs = (c->vsz + kWave * kPackPerLane - 1) / (kWave * kPackPerLane);
+    hipExtLaunchKernelGGL((k_tables_pack<R>), dim3((unsigned)(3 * c->nf + packs)), dim3(kWave), 0, c->stream, e.start,
+                          e.stop, 0, c->args(), lam, x, dsig, (long)c->vsz, static_cast<V2<R>*>(c->gv));
+    return launch_check("k_tables_pack");
+}
+
+// The vertex right-hand side in precision R from the packed vertex in c->gv:
+// the three channel launches (s writes dGamma, u and t add).
+template <class R>
+pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
     FlowArgs A = c->args();
     V2<R>* gv = static_cast<V2<R>*>(c->gv);
-    hipLaunchKernelGGL(k_pack<R>, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf,
-                       x + c->nf + c->vsz, gv);
-    TRY(launch_check("k_pack"));
     const int T = c->nsu * c->nf;
     const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
     const int per = (blocks + 7) / 8;
@@ -238,13 +245,13 @@ pffrg_status vertex_rhs(pffrg_ctx* c, const double* x, double* dx) {
 
 pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
-    FlowArgs A = c->args();
     TRY(sigma_rhs(c, lam, x, dx));                  // the sigma part of dx is dsig
-    const ProfPair e = prof_pair(c, PFFRG_K_TABLES);
-    hipExtLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, e.start, e.stop, 0, A, lam, x,
-                          (const double*)dx);
-    TRY(launch_check("k_node_tables"));
-    return c->prec == PFFRG_FP32 ? vertex_rhs<float>(c, x, dx) : vertex_rhs<double>(c, x, dx);
+    if (c->prec == PFFRG_FP32) {
+        TRY(tables_pack<float>(c, lam, x, dx));
+        return vertex_rhs<float>(c, dx);
+    }
+    TRY(tables_pack<double>(c, lam, x, dx));
+    return vertex_rhs<double>(c, dx);
 }
 
 // max-norm error / finiteness readback (synchronises the stream)
