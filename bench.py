@@ -50,7 +50,7 @@ PEAK_HBM_GBS = 8000.0
 # the hash of the kernel sources they were taken on; a changed kernel reports
 # traffic null until the counters are taken again.
 MEASURED_TRAFFIC = {
-    "f50da8ac14a383cb": 15.27e6,
+    "a06ade22bba998a4": 15.26e6,
 }
 
 
