@@ -451,7 +451,27 @@ def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
         "rhs_seconds_extrapolated": per_rhs,
         "single_thread": {"value": v1, "sample": f"{d1} triples, {s1:.1f} s"},
         "square_tiny_flow": tiny,
+        "host": host_cpu(),
     }
+
+
+def host_cpu() -> dict:
+    """The host the oracle ran on: logical CPUs, model and current clock
+    (from /proc/cpuinfo, where present), and how the oracle was compiled."""
+    model, mhz = None, []
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                if k.strip() == "model name" and model is None:
+                    model = v.strip()
+                elif k.strip() == "cpu MHz":
+                    mhz.append(float(v))
+    except OSError:
+        pass
+    return {"logical_cpus": os.cpu_count(), "model": model,
+            "mhz_mean": float(np.mean(mhz)) if mhz else None,
+            "oracle_build": "gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math"}
 
 
 def _tiny_flows(threads):
