@@ -179,3 +179,65 @@ def flow(ctx, x, path: str, *, scheme: str = "rk4", schedule=None, lam_start=Non
         done = (lad + offset >= len(sched) - 1) if sched is not None else not (ll > float(np.log(lam_stop)))
         save("finished" if done else "running")
     return n
+
+
+def batch_identity(batch, schedule) -> dict:
+    """What must match for a snapshot to continue a batch flow (the schedule
+    may be extended)."""
+    return {"format": FORMAT, "kind": "batch", "mesh": [_hex(w) for w in batch.mesh],
+            "lattices": [lattice_digest(t) for t in batch.tables], "precision": batch.precision,
+            "size": int(batch.size), "scheme": "rk4", "schedule": [_hex(v) for v in schedule]}
+
+
+def batch_flow(batch, x, path: str, schedule, *, every: float = 3600.0, segment: int = 8,
+               force_restart: bool = False, use_graph: bool = True) -> list[bool]:
+    """``Batch.flow`` with checkpoints in ``path``.  The schedule runs in
+    segments of ``segment`` RK4 steps (one batch launch sequence each; the
+    steps are those of one call over the whole schedule, so the states are
+    bitwise the same); after a segment ending at least ``every`` seconds after
+    the previous snapshot, and at the end, the batch state is written with
+    the schedule index reached and each point's finiteness.  A snapshot of
+    the same batch (points, mesh, precision, a schedule that the given one
+    continues) is resumed from unless ``force_restart``.  Returns each
+    point's finiteness at the end."""
+    import torch
+
+    sched = [float(v) for v in schedule]
+    if len(sched) < 2 or segment < 1:
+        raise ValueError("a batch flow needs >= 2 cutoffs and segment >= 1")
+    ident = batch_identity(batch, sched)
+    meta = dict(ident, status="running", start_time=_now(), steps=0)
+    start, ok = 0, [True] * batch.n_points
+    if not force_restart and os.path.exists(path):
+        snap = read(path)
+        _check_identity(snap.meta, ident, path)
+        if snap.state.size != batch.size:
+            raise ValueError(f"{path}: state size differs")
+        x.copy_(torch.from_numpy(snap.state))
+        start, ok = int(snap.meta["index"]), [bool(v) for v in snap.meta["finite"]]
+        meta.update(start_time=snap.meta["start_time"], steps=snap.meta["steps"])
+        if start >= len(sched) - 1:
+            return ok
+    last = time.monotonic()
+
+    def save(status: str, i: int) -> None:
+        meta.update(status=status, checkpoint_time=_now(), index=i, finite=ok,
+                    schedule=[_hex(v) for v in sched[:i + 1]], **{"lambda": _hex(sched[i])})
+        if status != "running":
+            meta["end_time"] = meta["checkpoint_time"]
+        torch.cuda.current_stream().synchronize()
+        write(path, x.detach().cpu().numpy(), meta)
+
+    i = start
+    while i < len(sched) - 1:
+        j = min(i + segment, len(sched) - 1)
+        seg_ok = batch.flow(x, sched[i:j + 1], use_graph=use_graph)
+        ok = [a and b for a, b in zip(ok, seg_ok)]
+        meta["steps"] += j - i
+        i = j
+        if i < len(sched) - 1 and time.monotonic() - last >= every:
+            save("running", i)
+            last = time.monotonic()
+    save("finished", i)
+    return ok
+

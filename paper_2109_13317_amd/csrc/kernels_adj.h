@@ -612,7 +612,7 @@ k_coupling_grad(long n_el, int ns, const double* __restrict__ cgs, double* __res
     for (long e = threadIdx.x; e < n_el; e += blockDim.x) a += cgs[e * ns + p];
     red[threadIdx.x] = a;
     __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
+    for (unsigned st = 128; st > 0; st >>= 1) {
         if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }

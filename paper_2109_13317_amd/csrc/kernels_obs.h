@@ -207,7 +207,7 @@ k_err_norm(long n, const double* __restrict__ x, const double* __restrict__ y,
     sm[threadIdx.x] = m;
     sf[threadIdx.x] = bad;
     __syncthreads();
-    for (int st = kRedThreads / 2; st > 0; st >>= 1) {
+    for (unsigned st = kRedThreads / 2; st > 0; st >>= 1) {
         if (threadIdx.x < st) {
             sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + st]);
             sf[threadIdx.x] = fmax(sf[threadIdx.x], sf[threadIdx.x + st]);

@@ -283,6 +283,7 @@ class Batch:
     def __init__(self, tables: list[LatticeTables], mesh, precision: str = "fp32", stream=None):
         self.lib = _lib.load()
         self.tables = list(tables)
+        self.precision = precision
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.n_points = len(self.tables)

@@ -7,7 +7,9 @@ after the same number of steps: adaptive (DOPRI54, FP64 and FP32) and fixed
 RK4 schedules.  A finished fixed-schedule flow extended to a longer schedule
 equals the direct flow bitwise; a finished adaptive flow extended to a lower
 cutoff continues to it.  A snapshot of another calculation is refused and
-force_restart ignores a snapshot.
+force_restart ignores a snapshot.  A batch flow run in segments and
+checkpointed, then extended from its snapshot to a longer schedule, equals
+the one-call batch flow bitwise, diverging point included.
 
 Breakdown detector on full flows (square J1-J2, range 7, 32 frequencies,
 adaptive 100 -> 0.01, chi(k) on 64 x 64 points): the ordered phases at
@@ -155,3 +157,30 @@ def test_breakdown_marks_the_ordered_phases(j2, kind, lo, hi):
     assert b.kind == kind
     if kind is not None:
         assert lo < b.lam < hi
+
+
+def test_batch_flow_checkpoints_and_extends_bitwise(tmp_path):
+    import torch
+    from paper_2109_13317_amd import build_tables, checkpoint as C
+    from paper_2109_13317_amd.flow import Batch
+    pts = [("square", dict(j1=1.0, j2=0.5), 2), ("square", dict(j1=1e200), 2),
+           ("honeycomb", dict(j1=0.6, j2=0.3, j3=0.45), 2)]
+    tables = [build_tables(W.model(lat, **par), L) for lat, par, L in pts]
+    b = Batch(tables, W.log_mesh(1e-3, 100.0, 6), precision="fp64")
+    sched = list(50.0 * 0.8 ** np.arange(13))
+    x_ref = b.init_state()
+    ok_ref = b.flow(x_ref, sched)
+    assert ok_ref == [True, False, True]
+    p = str(tmp_path / "b.checkpoint")
+    x = b.init_state()
+    assert C.batch_flow(b, x, p, sched[:7], every=0.0, segment=4) == ok_ref
+    meta = C.read(p).meta
+    assert meta["status"] == "finished" and meta["index"] == 6 and meta["steps"] == 6
+    x2 = b.init_state()
+    assert C.batch_flow(b, x2, p, sched, every=0.0, segment=5) == ok_ref
+    meta = C.read(p).meta
+    assert meta["index"] == len(sched) - 1 and meta["steps"] == len(sched) - 1
+    assert torch.equal(torch.nan_to_num(x2, nan=7.0), torch.nan_to_num(x_ref, nan=7.0))
+    with pytest.raises(ValueError, match="another calculation"):
+        C.batch_flow(Batch(tables[:2], W.log_mesh(1e-3, 100.0, 6), precision="fp64"),
+                     b.init_state()[:0], p, sched)
