@@ -214,6 +214,19 @@ def batch_leg():
     x1 = b.init_state()
     b.flow(x1, cut)
     chi_1 = [c.cpu().numpy() for c in b.chi(cut[-1], x1)]
+    # the scan's phase diagram: the same flow again, untimed, step by step
+    # with chi(k) of every point on a 32 x 32 grid after every step, and each
+    # point's breakdown (a kink or divergence of chi_max(Lambda))
+    from paper_2109_13317_amd.breakdown import batch_breakdowns
+    g = 2 * np.pi * (np.arange(32) / 32 - 0.5)
+    kx, ky = np.meshgrid(g, g, indexing="ij")
+    kp32 = torch.from_numpy(np.stack([kx.ravel(), ky.ravel(), np.zeros(kx.size)], 1).copy()).cuda()
+    bds, _, _ = batch_breakdowns(b, b.init_state(), sched, kp32, lam_max=wl.mesh[-1] / 4)
+    phase = [{"j2_over_j1": q["j2"] / q["j1"], "range": q["range"], "breakdown": bd.kind,
+              "lambda_c": bd.lam} for q, bd in zip(pts, bds)]
+    log("batch scan breakdowns: " + ", ".join(f"{d['j2_over_j1']:.2f}/{d['range']}:"
+                                              f"{d['lambda_c'] if d['lambda_c'] is None else round(d['lambda_c'], 3)}"
+                                              for d in phase[::8]))
     b.close()
     seq_ok, seq_chi_f, seq_chi_1 = [], [], []
     t_seq = 0.0
@@ -246,7 +259,11 @@ def batch_leg():
             "finite_points_batch": int(sum(ok)), "finite_points_fp64": int(sum(seq_ok)),
             "sequential_note": "a diverging FP64 flow stops at its first non-finite step",
             "chi_rel_err_vs_fp64_at_lambda_1": {"max": max(e1), "median": float(np.median(e1))},
-            "chi_rel_err_vs_fp64_at_lambda_f": {"points": len(ef), "max": max(ef), "median": float(np.median(ef))}}
+            "chi_rel_err_vs_fp64_at_lambda_f": {"points": len(ef), "max": max(ef), "median": float(np.median(ef))},
+            "phase_diagram": {"points": phase,
+                              "method": "breakdown.batch_breakdowns on the FP32 batch (untimed): chi(k) on "
+                                        "32 x 32 points after every RK4 step, first kink or divergence of "
+                                        "chi_max(Lambda) below a quarter of the top mesh frequency"}}
 
 
 def adjoint_leg():

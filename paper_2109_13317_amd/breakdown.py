@@ -88,3 +88,23 @@ class ChiMaxRecorder:
 
     def breakdown(self, **kw) -> Breakdown:
         return find_breakdown(self.lams, self.chi_max, **kw)
+
+
+def batch_breakdowns(batch, x, schedule, kpoints, *, use_graph: bool = True, **kw):
+    """Advance a batch (``flow.Batch``) along an RK4 schedule one step at a
+    time, in place, recording chi_max = max over kpoints of chi(k) for every
+    point after every step, and locate each point's breakdown (keyword
+    arguments as find_breakdown).  The steps are those of one
+    ``Batch.flow`` call over the schedule.  Returns (breakdowns, lams,
+    chi_max[point][step])."""
+    import torch
+    sched = [float(v) for v in schedule]
+    lams, maxima = [], []
+    for i in range(len(sched) - 1):
+        batch.flow(x, sched[i:i + 2], use_graph=use_graph)
+        chis = batch.chi(sched[i + 1], x)
+        maxima.append(torch.stack([batch.chi_k(p, c, kpoints).max() for p, c in enumerate(chis)]))
+        lams.append(sched[i + 1])
+    chi_max = torch.stack(maxima, 1).cpu().numpy()
+    return [find_breakdown(lams, chi_max[p], **kw) for p in range(batch.n_points)], lams, chi_max
+
