@@ -9,7 +9,8 @@ equals the direct flow bitwise; a finished adaptive flow extended to a lower
 cutoff continues to it.  A snapshot of another calculation is refused and
 force_restart ignores a snapshot.  A batch flow run in segments and
 checkpointed, then extended from its snapshot to a longer schedule, equals
-the one-call batch flow bitwise, diverging point included.
+the one-call batch flow bitwise, diverging point included; so does the
+batch breakdown scan, which steps one RK4 step at a time.
 
 Breakdown detector on full flows (square J1-J2, range 7, 32 frequencies,
 adaptive 100 -> 0.01, chi(k) on 64 x 64 points): the ordered phases at
@@ -184,3 +185,26 @@ def test_batch_flow_checkpoints_and_extends_bitwise(tmp_path):
     with pytest.raises(ValueError, match="another calculation"):
         C.batch_flow(Batch(tables[:2], W.log_mesh(1e-3, 100.0, 6), precision="fp64"),
                      b.init_state()[:0], p, sched)
+
+
+def test_batch_breakdowns_steps_like_one_flow_call():
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.breakdown import batch_breakdowns
+    from paper_2109_13317_amd.flow import Batch
+    pts = [("square", dict(j1=1.0, j2=0.5), 3), ("square", dict(j1=1e200), 2)]
+    tables = [build_tables(W.model(lat, **par), L) for lat, par, L in pts]
+    b = Batch(tables, W.log_mesh(1e-3, 100.0, 8), precision="fp64")
+    sched = list(50.0 * 0.8 ** np.arange(15))
+    x_ref = b.init_state()
+    b.flow(x_ref, sched)
+    g = 2 * np.pi * (np.arange(8) / 8 - 0.5)
+    kx, ky = np.meshgrid(g, g, indexing="ij")
+    kp = torch.from_numpy(np.stack([kx.ravel(), ky.ravel(), np.zeros(kx.size)], 1).copy()).cuda()
+    x = b.init_state()
+    bds, lams, chi_max = batch_breakdowns(b, x, sched, kp)
+    assert torch.equal(torch.nan_to_num(x, nan=7.0), torch.nan_to_num(x_ref, nan=7.0))
+    assert lams == sched[1:] and chi_max.shape == (2, len(sched) - 1)
+    assert np.isfinite(chi_max[0]).all() and (chi_max[0] > 0).all()
+    assert bds[1].kind == "nonfinite"
+    _say(f"batch breakdowns: {[(d.kind, d.lam) for d in bds]}")
