@@ -6,7 +6,8 @@ directory).  This package holds the Python binding (``flow.Context`` for one flo
 ``flow.Batch`` for many flows in lockstep), the
 lattice front end that produces the ABI's symmetry-reduced tables
 (``lattice.build_tables``), flow checkpoints (``checkpoint``), the breakdown
-detector for chi_max(Lambda) (``breakdown``) and the build script.
+detector for chi_max(Lambda) (``breakdown``), task and resource files in the
+paper's XML layout (``taskfile``) and the build script.
 """
 
 from .lattice import LatticeTables, build_tables

@@ -1,0 +1,351 @@
+"""Task files and resource files in the XML layout of Sec. 5 of
+arXiv:2109.13317, for the SU(2) engine of this package.
+
+A task file names the frequency mesh and the cutoff values (Sec. 5.1,
+"exponential" or "manual"), a lattice (the name of a unit cell and the
+truncation range), a spin model (the name of a model definition, its
+numerical backend in the ``symmetry`` attribute and the values of its
+coupling parameters) and the measurements.  Unit cells (Sec. 5.2:
+primitive vectors, basis sites, bonds) and models (Sec. 5.3: interactions
+between two sites given as four integers a0,a1,a2,b, with a coupling
+parameter and a type) live in resource files: every ``*.xml`` file of a
+search path is scanned for the named definitions.
+
+What this engine accepts: the ``SU2`` backend, Heisenberg interactions
+(``type="heisenberg"``), and the ``correlation`` measurement, written as a
+NumPy ``.npz`` file (chi^zz and chi^00 per reduced pair and cutoff) where
+the paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
+integrates the cutoff list (the paper's Euler steps, Eq. 42, or RK4 through
+the same cutoffs) with checkpoints next to the task file and records the
+calculation status (start, checkpoint and end times; running or finished)
+in the task file's ``calculation`` node, as the paper's program does.
+"""
+
+from __future__ import annotations
+
+import ast
+import datetime
+import glob
+import math
+import operator
+import os
+import xml.etree.ElementTree as ET
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+class TaskError(ValueError):
+    """A task or resource file this engine cannot run."""
+
+
+# ------------------------------------------------------------ expressions --
+
+_OPS = {ast.Add: operator.add, ast.Sub: operator.sub, ast.Mult: operator.mul, ast.Div: operator.truediv,
+        ast.Pow: operator.pow, ast.USub: operator.neg, ast.UAdd: operator.pos}
+_FUNCS = {"sqrt": math.sqrt, "sin": math.sin, "cos": math.cos, "tan": math.tan}
+_CONSTS = {"pi": math.pi}
+
+
+def evaluate(expr: str) -> float:
+    """Value of an arithmetic coordinate expression such as ``3/2`` or
+    ``-sqrt(3)/2``: numbers, + - * / **, parentheses, sqrt/sin/cos/tan and
+    pi; nothing else is evaluated."""
+    def ev(node):
+        if isinstance(node, ast.Expression):
+            return ev(node.body)
+        if isinstance(node, ast.Constant) and isinstance(node.value, (int, float)):
+            return float(node.value)
+        if isinstance(node, ast.BinOp) and type(node.op) in _OPS:
+            return _OPS[type(node.op)](ev(node.left), ev(node.right))
+        if isinstance(node, ast.UnaryOp) and type(node.op) in _OPS:
+            return _OPS[type(node.op)](ev(node.operand))
+        if isinstance(node, ast.Name) and node.id in _CONSTS:
+            return _CONSTS[node.id]
+        if (isinstance(node, ast.Call) and isinstance(node.func, ast.Name) and node.func.id in _FUNCS
+                and len(node.args) == 1 and not node.keywords):
+            return _FUNCS[node.func.id](ev(node.args[0]))
+        raise TaskError(f"unsupported expression {expr!r}")
+    try:
+        tree = ast.parse(expr.strip(), mode="eval")
+    except SyntaxError as e:
+        raise TaskError(f"unsupported expression {expr!r}") from e
+    return float(ev(tree))
+
+
+# ------------------------------------------------------------ definitions --
+
+@dataclass(frozen=True)
+class UnitCellDef:
+    """A unit cell (Sec. 5.2): rows of ``primitives`` are a0, a1, a2; bonds
+    are (from, to, da0, da1, da2)."""
+    name: str
+    primitives: np.ndarray
+    basis: np.ndarray
+    bonds: tuple
+
+    @property
+    def n_basis(self) -> int:
+        return int(self.basis.shape[0])
+
+
+@dataclass(frozen=True)
+class ModelDef:
+    """Heisenberg couplings (Sec. 5.3) as the lattice front end takes them:
+    interactions (parameter, b_from, b_to, da0, da1, da2) with the first site
+    in cell 0, and the parameter values."""
+    name: str
+    cell: UnitCellDef
+    interactions: tuple
+    params: dict = field(default_factory=dict)
+
+
+@dataclass
+class Measurement:
+    name: str
+    output: str | None = None
+    min_cutoff: float = 0.0
+    max_cutoff: float = math.inf
+    method: str | None = None
+
+
+@dataclass
+class Task:
+    path: str
+    mesh: np.ndarray            # positive frequencies, ascending
+    cutoffs: np.ndarray         # cutoff values in the order of the flow
+    lattice_range: int
+    model: ModelDef
+    symmetry: str
+    measurements: list
+    calculation: dict           # attributes of the calculation node ({} if none)
+
+
+def _child_text(node, tag, path):
+    c = node.find(tag)
+    if c is None or c.text is None:
+        raise TaskError(f"{path}: <{node.tag}> needs <{tag}>")
+    return c.text
+
+
+def _discretization(node, path, kind):
+    how = node.get("discretization")
+    if how == "manual":
+        vals = [evaluate(v.text) for v in node.findall("value")]
+        if len(vals) < 2:
+            raise TaskError(f"{path}: manual <{kind}> needs at least two values")
+        return np.asarray(vals, dtype=np.float64)
+    if how != "exponential":
+        raise TaskError(f"{path}: <{kind}> discretization must be exponential or manual")
+    lo = evaluate(_child_text(node, "min", path))
+    hi = evaluate(_child_text(node, "max", path))
+    if not (0.0 < lo < hi):
+        raise TaskError(f"{path}: <{kind}> needs 0 < min < max")
+    if kind == "frequency":
+        n = int(_child_text(node, "count", path))
+        if n < 2:
+            raise TaskError(f"{path}: <frequency> needs count >= 2")
+        k = np.arange(n, dtype=np.float64)
+        return lo * (hi / lo) ** (k / (n - 1))
+    b = evaluate(_child_text(node, "step", path))
+    if not (0.0 < b < 1.0):
+        raise TaskError(f"{path}: <cutoff> step must lie in (0, 1)")
+    nmax = int(math.floor(math.log(lo / hi) / math.log(b) + 1e-12))
+    return hi * b ** np.arange(nmax + 1, dtype=np.float64)
+
+
+def _resource_nodes(search_path, tag, name):
+    found = []
+    for d in search_path:
+        for f in sorted(glob.glob(os.path.join(d, "*.xml"))):
+            try:
+                text = open(f).read()
+            except OSError:
+                continue
+            try:
+                root = ET.fromstring(f"<resources>{text}</resources>")
+            except ET.ParseError as e:
+                raise TaskError(f"{f}: not well-formed XML ({e})") from e
+            # definitions are top-level elements (a task file's nested
+            # <model> node is a reference, not a definition)
+            found += [(f, n) for n in root.findall(tag) if n.get("name") == name]
+    if not found:
+        raise TaskError(f"no <{tag} name=\"{name}\"> in the resource files of {list(search_path)}")
+    if len(found) > 1:
+        raise TaskError(f"<{tag} name=\"{name}\"> is defined more than once: {[f for f, _ in found]}")
+    return found[0]
+
+
+def _unit_cell(search_path, name):
+    f, node = _resource_nodes(search_path, "unitcell", name)
+    prims = [[evaluate(p.get(c, "0")) for c in "xyz"] for p in node.findall("primitive")]
+    if len(prims) != 3:
+        raise TaskError(f"{f}: unit cell {name!r} needs three primitive vectors")
+    basis = [[evaluate(s.get(c, "0")) for c in "xyz"] for s in node.findall("site")]
+    if not basis:
+        raise TaskError(f"{f}: unit cell {name!r} has no sites")
+    bonds = []
+    for bnd in node.findall("bond"):
+        b = tuple(int(bnd.get(k, "0")) for k in ("from", "to", "da0", "da1", "da2"))
+        if not (0 <= b[0] < len(basis) and 0 <= b[1] < len(basis)):
+            raise TaskError(f"{f}: bond of unit cell {name!r} names a missing site")
+        bonds.append(b)
+    return UnitCellDef(name, np.asarray(prims, dtype=np.float64), np.asarray(basis, dtype=np.float64),
+                       tuple(bonds))
+
+
+def _model(search_path, name, cell, params):
+    f, node = _resource_nodes(search_path, "model", name)
+    inter = []
+    for it in node.findall("interaction"):
+        kind = it.get("type", "")
+        if kind != "heisenberg":
+            raise TaskError(f"{f}: interaction type {kind!r} needs a backend other than SU2")
+        src = [int(v) for v in it.get("from", "").split(",")]
+        dst = [int(v) for v in it.get("to", "").split(",")]
+        if len(src) != 4 or len(dst) != 4:
+            raise TaskError(f"{f}: interaction sites are a0,a1,a2,b")
+        if not (0 <= src[3] < cell.n_basis and 0 <= dst[3] < cell.n_basis):
+            raise TaskError(f"{f}: interaction names a missing basis site")
+        p = it.get("parameter")
+        if p not in params:
+            raise TaskError(f"the task gives no value for the model parameter {p!r}")
+        inter.append((p, src[3], dst[3], dst[0] - src[0], dst[1] - src[1], dst[2] - src[2]))
+    return ModelDef(name, cell, tuple(inter), dict(params))
+
+
+def load(path: str, search_path=None) -> Task:
+    """Read a task file and the resource files it references (default
+    search path: the task file's directory and its ``res`` subdirectory)."""
+    try:
+        root = ET.parse(path).getroot()
+    except (OSError, ET.ParseError) as e:
+        raise TaskError(f"{path}: {e}") from e
+    if root.tag != "task":
+        raise TaskError(f"{path}: the top-level node must be <task>")
+    if search_path is None:
+        here = os.path.dirname(os.path.abspath(path))
+        search_path = [here, os.path.join(here, "res")]
+    par = root.find("parameters")
+    if par is None:
+        raise TaskError(f"{path}: <task> needs <parameters>")
+    nodes = {t: par.find(t) for t in ("frequency", "cutoff", "lattice", "model")}
+    for t, n in nodes.items():
+        if n is None:
+            raise TaskError(f"{path}: <parameters> needs <{t}>")
+    mesh = _discretization(nodes["frequency"], path, "frequency")
+    if not (mesh > 0).all() or not (np.diff(mesh) > 0).all():
+        raise TaskError(f"{path}: frequencies must be positive and ascending")
+    cut = _discretization(nodes["cutoff"], path, "cutoff")
+    if not (cut > 0).all() or not (np.diff(cut) < 0).all():
+        raise TaskError(f"{path}: cutoff values must be positive and descending")
+    lat, mod = nodes["lattice"], nodes["model"]
+    symmetry = mod.get("symmetry", "")
+    if symmetry != "SU2":
+        raise TaskError(f"{path}: backend {symmetry!r} is not available (this engine is SU2)")
+    params = {c.tag: evaluate(c.text) for c in mod if c.text is not None}
+    cell = _unit_cell(search_path, lat.get("name"))
+    model = _model(search_path, mod.get("name"), cell, params)
+    meas = []
+    mnode = root.find("measurements")
+    for m in (mnode.findall("measurement") if mnode is not None else []):
+        if m.get("name") != "correlation":
+            raise TaskError(f"{path}: unknown measurement {m.get('name')!r}")
+        if m.get("method") not in (None, "direct"):
+            raise TaskError(f"{path}: measurement method {m.get('method')!r} is not available")
+        meas.append(Measurement("correlation", m.get("output"),
+                                evaluate(m.get("minCutoff", "0")),
+                                evaluate(m.get("maxCutoff", "inf")) if m.get("maxCutoff") else math.inf))
+    calc = root.find("calculation")
+    return Task(os.path.abspath(path), mesh, cut, int(lat.get("range", "-1")), model, symmetry, meas,
+                dict(calc.attrib) if calc is not None else {})
+
+
+def _stamp() -> str:
+    return datetime.datetime.now().strftime("%Y-%b-%d %H:%M:%S")
+
+
+def _set_calculation(path: str, **attrs) -> None:
+    tree = ET.parse(path)
+    root = tree.getroot()
+    calc = root.find("calculation")
+    if calc is None:
+        calc = ET.SubElement(root, "calculation")
+    for k, v in attrs.items():
+        calc.set(k, v)
+    tmp = path + ".tmp"
+    tree.write(tmp)
+    os.replace(tmp, path)
+
+
+def _write_obs(dest, rec) -> None:
+    tmp = dest + ".tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, **{"lambda": np.asarray(rec[0], dtype=np.float64), "chi_zz": np.asarray(rec[1]),
+                       "chi_00": np.asarray(rec[2])})
+    os.replace(tmp, dest)
+
+
+def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: float = 3600.0,
+        force_restart: bool = False) -> dict:
+    """Integrate a loaded task along its cutoff values (``euler`` as in the
+    paper, or ``rk4`` through the same cutoffs) on the GPU, with checkpoints
+    in the task path with extension ``.checkpoint`` (a snapshot at least
+    ``every`` seconds apart, and at the end), and write each correlation
+    measurement (default output: the task path with extension ``.obs``; a
+    NumPy archive with ``lambda`` and ``chi_zz``, ``chi_00`` per reduced
+    pair), updated after every accepted step.  A task with a snapshot of the
+    same calculation resumes from it (measurements up to the snapshot are kept
+    and the rest recomputed; the resumed steps are bitwise the uninterrupted
+    ones) unless ``force_restart``.  Returns {output path: cutoffs recorded}."""
+    from . import checkpoint
+    from .flow import Context
+    from .lattice import build_tables
+
+    if task.lattice_range < 0:
+        raise TaskError(f"{task.path}: <lattice> needs a range")
+    if scheme not in ("euler", "rk4"):
+        raise TaskError("scheme must be euler or rk4")
+    base = os.path.splitext(task.path)[0]
+    ck = base + ".checkpoint"
+    dests = []
+    for m in task.measurements:
+        d = m.output or base + ".obs"
+        dests.append(d if os.path.isabs(d) else os.path.join(os.path.dirname(task.path), d))
+    records = [([], [], []) for _ in task.measurements]
+    resuming = os.path.exists(ck) and not force_restart
+    if resuming:
+        lam_snap = float.fromhex(checkpoint.read(ck).meta["lambda"])
+        for rec, d in zip(records, dests):
+            if os.path.exists(d):
+                with np.load(d, allow_pickle=False) as z:
+                    keep = z["lambda"] >= lam_snap
+                    rec[0].extend(z["lambda"][keep].tolist())
+                    rec[1].extend(list(z["chi_zz"][keep]))
+                    rec[2].extend(list(z["chi_00"][keep]))
+    ctx = Context(build_tables(task.model, task.lattice_range), task.mesh, precision=precision)
+    x = ctx.init_state()
+
+    def observe(lam, chi, chik):
+        c = chi.detach().cpu().numpy()
+        for m, rec, d in zip(task.measurements, records, dests):
+            if m.min_cutoff <= lam <= m.max_cutoff:
+                rec[0].append(lam)
+                rec[1].append(c[0].copy())
+                rec[2].append(c[1].copy())
+                _write_obs(d, rec)
+        return False
+
+    started = task.calculation.get("startTime") if resuming else None
+    _set_calculation(task.path, startTime=started or _stamp(), status="running")
+    checkpoint.flow(ctx, x, ck, scheme=scheme, schedule=list(task.cutoffs), every=every, observer=observe,
+                    force_restart=force_restart)
+    snap = checkpoint.read(ck).meta
+    now = _stamp()
+    _set_calculation(task.path, checkpointTime=now, endTime=now,
+                     status="finished" if snap["status"] == "finished" else "running")
+    out = {}
+    for rec, d in zip(records, dests):
+        _write_obs(d, rec)
+        out[d] = len(rec[0])
+    return out

@@ -1,0 +1,157 @@
+"""Task and resource files (the XML layout of Sec. 5) on the host: the
+loader's meshes follow the paper's formulas, its unit cells and models give
+the lattice front end exactly the tables the built-in models give, and
+everything this SU(2) engine cannot run is refused with a clear error.  The
+fixture files are written here (own model names and values)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_2109_13317_amd import build_tables
+from paper_2109_13317_amd import taskfile as T
+
+RESOURCES = """
+<unitcell name="sq">
+  <primitive x="1" y="0" z="0"/>
+  <primitive x="0" y="1" z="0"/>
+  <primitive x="0" y="0" z="1"/>
+  <site x="0" y="0" z="0"/>
+  <bond from="0" to="0" da0="1" da1="0" da2="0"/>
+  <bond from="0" to="0" da0="0" da1="1" da2="0"/>
+</unitcell>
+<unitcell name="hc">
+  <primitive x="1.5" y="sqrt(3)/2" z="0"/>
+  <primitive x="3/2" y="-sqrt(3) / 2" z="0"/>
+  <primitive x="0" y="0" z="1"/>
+  <site x="0" y="0" z="0"/>
+  <site x="1" y="0" z="0"/>
+  <bond from="0" to="1" da0="0" da1="0" da2="0"/>
+  <bond from="1" to="0" da0="1" da1="0" da2="0"/>
+  <bond from="1" to="0" da0="0" da1="1" da2="0"/>
+</unitcell>
+<model name="sq-first-second">
+  <interaction parameter="ja" from="0,0,0,0" to="1,0,0,0" type="heisenberg"/>
+  <interaction parameter="ja" from="0,-1,0,0" to="0,0,0,0" type="heisenberg"/>
+  <interaction parameter="jb" from="0,0,0,0" to="1,1,0,0" type="heisenberg"/>
+  <interaction parameter="jb" from="0,0,0,0" to="1,-1,0,0" type="heisenberg"/>
+</model>
+<model name="hc-first">
+  <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,1" to="1,0,0,0" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,1" to="0,1,0,0" type="heisenberg"/>
+</model>
+<model name="hc-anisotropic">
+  <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="xx"/>
+</model>
+"""
+
+
+def _task(tmp_path, body, name="t.xml"):
+    (tmp_path / "res.xml").write_text(RESOURCES)
+    p = tmp_path / name
+    p.write_text(body)
+    return str(p)
+
+
+def _sq_task(tmp_path, ja="1.0", jb="0.4", symmetry="SU2", extra=""):
+    return _task(tmp_path, f"""<task>
+  <parameters>
+    <frequency discretization="exponential"><min>0.01</min><max>40</max><count>9</count></frequency>
+    <cutoff discretization="exponential"><min>0.5</min><max>20</max><step>0.85</step></cutoff>
+    <lattice name="sq" range="3"/>
+    <model name="sq-first-second" symmetry="{symmetry}"><ja>{ja}</ja><jb>{jb}</jb></model>
+  </parameters>
+  <measurements><measurement name="correlation" minCutoff="1.0"/></measurements>{extra}
+</task>""")
+
+
+def _same_tables(a, b):
+    assert a.n_pairs == b.n_pairs
+    for k in ("swap", "mult", "rpa_off", "rpa_ka", "rpa_kb", "rpa_cnt", "coupling", "site_pair", "site_pos",
+              "basis_pos"):
+        assert np.array_equal(np.asarray(getattr(a, k)), np.asarray(getattr(b, k))), k
+
+
+def test_meshes_follow_the_paper_formulas(tmp_path):
+    t = T.load(_sq_task(tmp_path))
+    assert np.array_equal(t.mesh, W.log_mesh(0.01, 40.0, 9))
+    assert np.array_equal(t.cutoffs, W.exponential_schedule(20.0, 0.5, 0.85))
+    n = int(math.floor(math.log(0.5 / 20.0) / math.log(0.85)))
+    assert len(t.cutoffs) == n + 1 and t.cutoffs[-1] >= 0.5
+    assert t.measurements[0].min_cutoff == 1.0 and t.measurements[0].max_cutoff == math.inf
+    p = _task(tmp_path, """<task><parameters>
+      <frequency discretization="manual"><value>0.1</value><value>1/2</value><value>3</value></frequency>
+      <cutoff discretization="manual"><value>9</value><value>4</value><value>2.5</value></cutoff>
+      <lattice name="hc" range="2"/><model name="hc-first" symmetry="SU2"><j>1</j></model>
+    </parameters></task>""", "m.xml")
+    t = T.load(p)
+    assert np.array_equal(t.mesh, [0.1, 0.5, 3.0]) and np.array_equal(t.cutoffs, [9.0, 4.0, 2.5])
+
+
+def test_square_model_gives_the_builtin_tables(tmp_path):
+    t = T.load(_sq_task(tmp_path, ja="1.0", jb="0.4"))
+    assert t.model.cell.bonds == W.unit_cell("square").bonds
+    for L in (2, 3, 4):
+        _same_tables(build_tables(t.model, L), build_tables(W.model("square", j1=1.0, j2=0.4), L))
+
+
+def test_honeycomb_cell_with_expressions_gives_the_builtin_tables(tmp_path):
+    p = _task(tmp_path, """<task><parameters>
+      <frequency discretization="exponential"><min>0.01</min><max>40</max><count>4</count></frequency>
+      <cutoff discretization="exponential"><min>1</min><max>10</max><step>0.5</step></cutoff>
+      <lattice name="hc" range="3"/><model name="hc-first" symmetry="SU2"><j>0.7</j></model>
+    </parameters></task>""")
+    t = T.load(p)
+    assert np.allclose(t.model.cell.primitives, W.unit_cell("honeycomb").primitives, atol=0, rtol=1e-15)
+    for L in (2, 3):
+        _same_tables(build_tables(t.model, L), build_tables(W.model("honeycomb", j1=0.7), L))
+
+
+def test_expressions_are_arithmetic_only():
+    assert T.evaluate("-sqrt(3)/2") == -math.sqrt(3.0) / 2
+    assert T.evaluate("(1 + 2) * 2 ** 2") == 12.0
+    assert T.evaluate("pi/4") == math.pi / 4
+    for bad in ("__import__('os')", "x", "open('f')", "sqrt(1, 2)", "1 if 1 else 2", "[1]", ""):
+        with pytest.raises(T.TaskError):
+            T.evaluate(bad)
+
+
+def test_what_the_su2_engine_cannot_run_is_refused(tmp_path):
+    good = _read(_sq_task(tmp_path))
+    cases = [
+        (good.replace('symmetry="SU2"', 'symmetry="XYZ"'), "backend"),
+        (good.replace("<jb>0.4</jb>", ""), "no value"),
+        (good.replace('<lattice name="sq"', '<lattice name="nowhere"'), "unitcell"),
+        (good.replace("<step>0.85</step>", "<step>1.5</step>"), "step"),
+        (good.replace('minCutoff="1.0"', 'method="defer"'), "method"),
+        (good.replace('name="correlation"', 'name="structure"'), "measurement"),
+        (good.replace("<count>9</count>", "<count>1</count>"), "count"),
+        (good.replace('discretization="exponential"><min>0.5', 'discretization="linear"><min>0.5'), "discretization"),
+    ]
+    for i, (text, msg) in enumerate(cases):
+        with pytest.raises(T.TaskError, match=msg):
+            T.load(_task(tmp_path, text, f"bad{i}.xml"))
+    p = _task(tmp_path, """<task><parameters>
+      <frequency discretization="exponential"><min>0.1</min><max>10</max><count>4</count></frequency>
+      <cutoff discretization="exponential"><min>1</min><max>10</max><step>0.5</step></cutoff>
+      <lattice name="hc" range="2"/><model name="hc-anisotropic" symmetry="SU2"><j>1</j></model>
+    </parameters></task>""", "aniso.xml")
+    with pytest.raises(T.TaskError, match="type 'xx'"):
+        T.load(p)
+    (tmp_path / "dup.xml").write_text('<unitcell name="sq"><primitive x="1"/></unitcell>')
+    with pytest.raises(T.TaskError, match="more than once"):
+        T.load(str(tmp_path / "t.xml"))
+
+
+def _read(p):
+    with open(p) as f:
+        return f.read()
+
+
+def test_calculation_node_is_read(tmp_path):
+    p = _sq_task(tmp_path, extra='\n  <calculation startTime="2026-Jan-02 03:04:05" status="running"/>')
+    t = T.load(p)
+    assert t.calculation == {"startTime": "2026-Jan-02 03:04:05", "status": "running"}

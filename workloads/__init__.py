@@ -6,9 +6,9 @@ random flow states.  It contains none of the pf-FRG arithmetic (no
 propagators, no flow equations, no symmetry reduction), so that the oracle and
 the GPU library can both consume it without sharing any method code.
 
-Unit cells follow the resource-file format of the paper (Sec. 5.3, "Definition
+Unit cells follow the resource-file format of the paper (Sec. 5.2, "Definition
 of lattice graphs": three primitive vectors, basis sites, and bonds given as
-(from, to, da0, da1, da2)).  Couplings follow Sec. 5.4 ("Definition of spin
+(from, to, da0, da1, da2)).  Couplings follow Sec. 5.3 ("Definition of spin
 interactions"): each interaction joins a site of the home cell to a site given
 by (da0, da1, da2, basis) and carries a named Heisenberg parameter.  Each
 unordered bond of the infinite lattice appears exactly once per unit cell.
@@ -31,7 +31,7 @@ __all__ = [
 
 @dataclass(frozen=True)
 class UnitCell:
-    """A lattice unit cell embedded in three dimensions (Sec. 5.3)."""
+    """A lattice unit cell embedded in three dimensions (Sec. 5.2)."""
     name: str
     primitives: np.ndarray          # (3, 3): rows are a0, a1, a2
     basis: np.ndarray               # (nb, 3) Cartesian basis-site positions
@@ -69,14 +69,14 @@ def _bonds_by_distance(prims, basis, dist, tol=1e-6, reach=2):
 _S3 = math.sqrt(3.0)
 
 UNIT_CELLS = {
-    # Sec. 5.3, listing of unit cells: square lattice.
+    # Sec. 5.2, listing of unit cells: square lattice.
     "square": UnitCell(
         "square",
         np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]),
         np.array([[0.0, 0.0, 0.0]]),
         ((0, 0, 1, 0, 0), (0, 0, 0, 1, 0)),
     ),
-    # Sec. 5.3, listing of unit cells: honeycomb lattice.
+    # Sec. 5.2, listing of unit cells: honeycomb lattice.
     "honeycomb": UnitCell(
         "honeycomb",
         np.array([[1.5, _S3 / 2, 0.0], [1.5, -_S3 / 2, 0.0], [0.0, 0.0, 1.0]]),
@@ -108,7 +108,7 @@ def unit_cell(name: str) -> UnitCell:
 
 @dataclass(frozen=True)
 class Model:
-    """Heisenberg couplings on a unit cell (Sec. 5.4).
+    """Heisenberg couplings on a unit cell (Sec. 5.3).
 
     ``interactions`` lists (param, b_from, b_to, da0, da1, da2); the value of
     each named parameter is in ``params``.  The Hamiltonian is the sum of
@@ -153,7 +153,7 @@ def model(lattice: str, **params) -> Model:
 # ---------------------------------------------------------------- meshes ---
 
 def log_mesh(wmin: float, wmax: float, n: int) -> np.ndarray:
-    """Positive frequency mesh, logarithmically spaced (Sec. 5.2, exponential
+    """Positive frequency mesh, logarithmically spaced (Sec. 5.1, exponential
     frequency discretization): w_n = wmin (wmax/wmin)^(n/(n-1))."""
     if n < 2:
         raise ValueError("need at least two frequencies")
@@ -163,7 +163,7 @@ def log_mesh(wmin: float, wmax: float, n: int) -> np.ndarray:
 
 def exponential_schedule(lmax: float, lmin: float, b: float) -> np.ndarray:
     """Cutoff values Lambda_n = lmax b^n for n = 0 .. floor(log_b(lmin/lmax))
-    (Sec. 5.2, exponential cutoff discretization)."""
+    (Sec. 5.1, exponential cutoff discretization)."""
     nmax = int(math.floor(math.log(lmin / lmax) / math.log(b) + 1e-12))
     return lmax * b ** np.arange(nmax + 1, dtype=np.float64)
 
