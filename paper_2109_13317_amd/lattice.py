@@ -284,3 +284,45 @@ def build_tables(model, L: int) -> LatticeTables:
         site_pos=site_pos, basis_pos=lat.basis.copy(),
         pair_rep=np.array([[r[0][0], r[0][1], r[0][2], r[1]] for r in reps], dtype=np.int32),
         stabiliser_order=len(stab))
+
+
+@dataclass
+class LatticeDescription:
+    """The lattice spin model as built, for checking it by eye or by script
+    (the lattice description output of Sec. 5, "Output data")."""
+    positions: np.ndarray       # float64 [n_sites, 3], site id = row
+    parametrized: np.ndarray    # bool [n_sites]: the site represents a reduced pair
+    bonds: list                 # [(from id, to id)], once per unit-cell bond
+    interactions: list          # [(from id, to id, J)], Heisenberg: J times the 3x3 identity
+
+
+def describe(model, L: int) -> LatticeDescription:
+    """Sites within bond distance L of the reference site (breadth-first
+    order, id 0 the reference site), the lattice bonds and the nonzero
+    couplings between them, each listed once in the orientation of the unit
+    cell or model that defines it, and which sites are parametrized: the
+    representatives of the reduced pairs that ``build_tables`` keeps."""
+    lat = _Lattice(model.cell, model.interactions, model.params)
+    sites, _ = lat.ball(0, int(L))
+    ids = {s: i for i, s in enumerate(sites)}
+    reps = {((int(r[0]), int(r[1]), int(r[2])), int(r[3])) for r in build_tables(model, L).pair_rep}
+
+    def links(defs):
+        out = {}
+        for (c, b) in sites:
+            for (val, f, t, d0, d1, d2) in defs:
+                if f != b:
+                    continue
+                j = ids.get(((c[0] + d0, c[1] + d1, c[2] + d2), t))
+                if j is not None:
+                    out[(ids[(c, b)], j)] = out.get((ids[(c, b)], j), 0.0) + val
+        return out
+
+    bonds = sorted(links([(1.0,) + tuple(bd) for bd in model.cell.bonds]))
+    coup = links([(float(model.params.get(p, 0.0)), f, t, d0, d1, d2)
+                  for (p, f, t, d0, d1, d2) in model.interactions])
+    return LatticeDescription(
+        positions=np.array([lat.pos(*s) for s in sites]),
+        parametrized=np.array([s in reps for s in sites]),
+        bonds=bonds,
+        interactions=[(i, j, v) for (i, j), v in sorted(coup.items()) if v != 0.0])

@@ -18,7 +18,10 @@ the paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
 integrates the cutoff list (the paper's Euler steps, Eq. 42, or RK4 through
 the same cutoffs) with checkpoints next to the task file and records the
 calculation status (start, checkpoint and end times; running or finished)
-in the task file's ``calculation`` node, as the paper's program does.
+in the task file's ``calculation`` node, as the paper's program does.  It
+also writes the lattice description file (task path with extension
+``.ldf``): the sites within range of the reference site, which of them are
+parametrized, the bonds and the interactions (``write_ldf``).
 """
 
 from __future__ import annotations
@@ -278,6 +281,52 @@ def _set_calculation(path: str, **attrs) -> None:
     os.replace(tmp, path)
 
 
+def write_ldf(path: str, desc) -> None:
+    """Write a ``lattice.LatticeDescription`` as a lattice description file
+    (the XML layout of Sec. 5, "Output data": a ``lattice`` root with
+    ``site`` nodes (id, Cartesian x, y, z, parametrized), ``bond`` nodes
+    (from, to) and ``interaction`` nodes (from, to, the 3x3 coupling matrix
+    row by row); numbers are written exactly, as Python's shortest round-trip
+    decimal)."""
+    root = ET.Element("lattice")
+    for i, (p, par) in enumerate(zip(desc.positions, desc.parametrized)):
+        ET.SubElement(root, "site", id=str(i), x=repr(float(p[0])), y=repr(float(p[1])), z=repr(float(p[2])),
+                      parametrized="true" if par else "false")
+    for i, j in desc.bonds:
+        ET.SubElement(root, "bond", **{"from": str(i), "to": str(j)})
+    for i, j, v in desc.interactions:
+        m = np.eye(3) * v
+        val = "[" + ", ".join("[" + ",".join(repr(float(e)) for e in row) + "]" for row in m) + "]"
+        ET.SubElement(root, "interaction", value=val, **{"from": str(i), "to": str(j)})
+    ET.indent(root)
+    tmp = path + ".tmp"
+    ET.ElementTree(root).write(tmp)
+    os.replace(tmp, path)
+
+
+def read_ldf(path: str):
+    """Read a lattice description file back: (positions [n, 3], parametrized
+    [n], bonds [(from, to)], interactions [(from, to, 3x3 matrix)])."""
+    try:
+        root = ET.parse(path).getroot()
+    except (ET.ParseError, OSError) as e:
+        raise TaskError(f"{path}: {e}") from None
+    sites = sorted(root.findall("site"), key=lambda e: int(e.get("id")))
+    if [int(e.get("id")) for e in sites] != list(range(len(sites))):
+        raise TaskError(f"{path}: site ids are not 0..n-1")
+    pos = np.array([[float(e.get(k)) for k in "xyz"] for e in sites]).reshape(-1, 3)
+    par = np.array([e.get("parametrized") == "true" for e in sites], dtype=bool)
+    bonds = [(int(e.get("from")), int(e.get("to"))) for e in root.findall("bond")]
+    inter = []
+    for e in root.findall("interaction"):
+        rows = e.get("value").strip()[1:-1].replace(" ", "").split("],[")
+        m = np.array([[float(v) for v in r.strip("[]").split(",")] for r in rows])
+        if m.shape != (3, 3):
+            raise TaskError(f"{path}: interaction value is not a 3x3 matrix")
+        inter.append((int(e.get("from")), int(e.get("to")), m))
+    return pos, par, bonds, inter
+
+
 def _write_obs(dest, rec) -> None:
     tmp = dest + ".tmp"
     with open(tmp, "wb") as f:
@@ -294,13 +343,14 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
     ``every`` seconds apart, and at the end), and write each correlation
     measurement (default output: the task path with extension ``.obs``; a
     NumPy archive with ``lambda`` and ``chi_zz``, ``chi_00`` per reduced
-    pair), updated after every accepted step.  A task with a snapshot of the
+    pair), updated after every accepted step, and the lattice description
+    in the task path with extension ``.ldf`` (``write_ldf``).  A task with a snapshot of the
     same calculation resumes from it (measurements up to the snapshot are kept
     and the rest recomputed; the resumed steps are bitwise the uninterrupted
     ones) unless ``force_restart``.  Returns {output path: cutoffs recorded}."""
     from . import checkpoint
     from .flow import Context
-    from .lattice import build_tables
+    from .lattice import build_tables, describe
 
     if task.lattice_range < 0:
         raise TaskError(f"{task.path}: <lattice> needs a range")
@@ -323,6 +373,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                     rec[0].extend(z["lambda"][keep].tolist())
                     rec[1].extend(list(z["chi_zz"][keep]))
                     rec[2].extend(list(z["chi_00"][keep]))
+    write_ldf(base + ".ldf", describe(task.model, task.lattice_range))
     ctx = Context(build_tables(task.model, task.lattice_range), task.mesh, precision=precision)
     x = ctx.init_state()
 

@@ -1,7 +1,7 @@
 """A task file (the XML layout of Sec. 5) run end to end on the GPU: the
 measured correlations equal those of a direct flow with the same mesh,
 cutoffs and Euler steps bitwise, the task's calculation node records a
-finished run, and lowering the task's minimum cutoff afterwards extends the
+finished run, the lattice description file lists the lattice, and lowering the task's minimum cutoff afterwards extends the
 calculation from its checkpoint (the extension of Sec. 5.1), again bitwise
 equal to the direct flow, with the earlier measurements kept."""
 
@@ -38,6 +38,10 @@ def test_task_file_runs_and_extends(tmp_path):
     first = np.load(obs)
     calc = ET.parse(str(task_path)).getroot().find("calculation").attrib
     assert calc["status"] == "finished" and "startTime" in calc and "endTime" in calc
+    pos, par, bonds, inter = T.read_ldf(str(tmp_path / "run.ldf"))
+    tables = build_tables(W.model("square", j1=1.0, j2=0.3), 2)
+    assert len(pos) == tables.n_sites_total and int(par.sum()) == tables.n_pairs
+    assert len(bonds) == 16 and len(inter) == 16 + 16    # J1 and J2 pairs within two bonds of the reference
 
     def direct(lmin):
         mesh = W.log_mesh(0.01, 40.0, 8)

@@ -155,3 +155,86 @@ def test_calculation_node_is_read(tmp_path):
     p = _sq_task(tmp_path, extra='\n  <calculation startTime="2026-Jan-02 03:04:05" status="running"/>')
     t = T.load(p)
     assert t.calculation == {"startTime": "2026-Jan-02 03:04:05", "status": "running"}
+
+
+@pytest.mark.parametrize("lat,L,params", [
+    ("square", 3, dict(j1=1.0, j2=0.4)),
+    ("honeycomb", 3, dict(j1=1.0, j2=0.3, j3=-0.2)),
+    ("cubic", 2, dict(j1=1.0, j2=0.5)),
+    ("pyrochlore", 2, dict(j1=1.0)),
+])
+def test_lattice_description_by_brute_force(tmp_path, lat, L, params):
+    """The lattice description (Sec. 5, "Output data") against what the
+    positions alone fix: the sites are those within bond distance L of the
+    reference site (bond-graph distances recomputed here from the listed
+    bonds), every unordered nearest-neighbour pair of listed sites is one bond,
+    every pair at a coupling shell's distance is one interaction with that
+    shell's value, the parametrized sites are one per reduced pair and their
+    orbits (pairs of equal distance to the reference) account for every site;
+    the file reads back exactly."""
+    from paper_2109_13317_amd.lattice import describe
+    m = W.model(lat, **params)
+    d = describe(m, L)
+    t = build_tables(m, L)
+    pos = d.positions
+    n = len(pos)
+    assert n == t.n_sites_total and np.array_equal(pos[0], t.basis_pos[0])
+    dist = np.linalg.norm(pos[:, None, :] - pos[None, :, :], axis=-1)
+    shells = dict(W._SHELLS[lat])
+    nn = shells["j1"]
+    want_bonds = {(i, j) for i in range(n) for j in range(i + 1, n) if abs(dist[i, j] - nn) < 1e-9}
+    got_bonds = {tuple(sorted(b)) for b in d.bonds}
+    assert len(got_bonds) == len(d.bonds) and got_bonds == want_bonds
+    want_int = {}
+    for name, r in W._SHELLS[lat]:
+        if params.get(name, 0.0) != 0.0:
+            for i in range(n):
+                for j in range(i + 1, n):
+                    if abs(dist[i, j] - r) < 1e-9:
+                        want_int[(i, j)] = params[name]
+    got_int = {tuple(sorted((i, j))): v for i, j, v in d.interactions}
+    assert len(got_int) == len(d.interactions) and got_int == want_int
+    # bond-graph distance from the reference site <= L for every listed site
+    adj = [[] for _ in range(n)]
+    for i, j in d.bonds:
+        adj[i].append(j); adj[j].append(i)
+    hop = {0: 0}
+    frontier = [0]
+    while frontier:
+        nxt = []
+        for i in frontier:
+            for j in adj[i]:
+                if j not in hop:
+                    hop[j] = hop[i] + 1
+                    nxt.append(j)
+        frontier = nxt
+    assert len(hop) == n and max(hop.values()) == L
+    assert int(d.parametrized.sum()) == t.n_pairs and d.parametrized[0]
+    assert int(np.sum(t.mult)) == n
+    par_d = dist[0, d.parametrized]
+    for r in np.unique(np.round(dist[0], 9)):          # every distance shell holds a parametrized site
+        assert np.any(np.abs(par_d - r) < 1e-8)
+    p = str(tmp_path / "lat.ldf")
+    T.write_ldf(p, d)
+    pos2, par2, bonds2, int2 = T.read_ldf(p)
+    assert np.array_equal(pos2, pos) and np.array_equal(par2, d.parametrized) and bonds2 == d.bonds
+    assert [(i, j) for i, j, _ in int2] == [(i, j) for i, j, _ in d.interactions]
+    for (_, _, mtx), (_, _, v) in zip(int2, d.interactions):
+        assert np.array_equal(mtx, np.eye(3) * v)
+
+
+def test_lattice_description_layout(tmp_path):
+    """Node and attribute names of the paper's lattice description layout."""
+    import xml.etree.ElementTree as ET
+    from paper_2109_13317_amd.lattice import describe
+    p = str(tmp_path / "sq.ldf")
+    T.write_ldf(p, describe(W.model("square", j1=1.0, j2=0.0), 1))
+    root = ET.parse(p).getroot()
+    assert root.tag == "lattice"
+    assert {e.tag for e in root} == {"site", "bond", "interaction"}
+    s = root.find("site")
+    assert set(s.attrib) == {"id", "x", "y", "z", "parametrized"} and s.get("parametrized") == "true"
+    assert len(root.findall("site")) == 5 and len(root.findall("bond")) == 4
+    inter = root.findall("interaction")
+    assert len(inter) == 4 and set(inter[0].attrib) == {"from", "to", "value"}
+    assert inter[0].get("value") == "[[1.0,0.0,0.0], [0.0,1.0,0.0], [0.0,0.0,1.0]]"
