@@ -76,10 +76,11 @@ typedef struct pffrg_ctx pffrg_ctx;
  *                rpa_cnt[q] * Gamma_{rpa_ka[q]} * Gamma_{rpa_kb[q]} to
  *                sum_j Gamma_{i_ref j} Gamma_{j j_p}
  *   coupling[p]  Heisenberg coupling J of the bond (i_ref, j_p), 0 if none;
- *                each unordered bond counted once (Eq. 21: Gs = J/4)
+ *                each unordered bond counted once (Eq. 21: Gs = J/4); finite
  *   n_basis, n_sites_total, site_pair[b*n_sites_total + k], site_pos[..*3]
  *                for every basis site b the sites within range of b, their
- *                reduced pair (-1 pads short lists) and Cartesian position;
+ *                reduced pair (-1 pads short lists; values below -1 are
+ *                rejected) and Cartesian position;
  *   basis_pos    [n_basis*3] Cartesian basis-site positions (chi(k))
  */
 typedef struct {
@@ -108,7 +109,13 @@ typedef struct {
 /* ---------------------------------------------------------- lifecycle -- */
 
 /* Copy the tables to the device and allocate every buffer the context will
- * use.  `stream` is a hipStream_t or NULL. */
+ * use.  `stream` is a hipStream_t or NULL.  The mesh and every table are
+ * checked on the host before the first HIP call: a null or malformed one
+ * (an index out of range, rpa_off descending, a count outside [1, 32767], a
+ * non-positive, non-finite or unsorted frequency, a non-finite coupling, an
+ * unknown precision) gives PFFRG_EINVAL, more than 128 frequencies or pairs
+ * beyond the kernel build PFFRG_EUNSUPPORTED, with *out left NULL and
+ * nothing allocated; a failed device allocation gives PFFRG_ENOMEM. */
 pffrg_status pffrg_create(const pffrg_lattice *lat, const pffrg_mesh *mesh,
                           pffrg_precision prec, void *stream, pffrg_ctx **out);
 pffrg_status pffrg_destroy(pffrg_ctx *ctx);

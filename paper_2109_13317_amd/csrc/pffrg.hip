@@ -491,6 +491,7 @@ pffrg_status check_lattice(const pffrg_lattice* lat, int max_pairs) {
         if (lat->swap[p] < 0 || lat->swap[p] >= ns) return fail(PFFRG_EINVAL, "swap out of range");
         if (lat->mult[p] < 1) return fail(PFFRG_EINVAL, "mult must be >= 1");
         if (lat->rpa_off[p + 1] < lat->rpa_off[p]) return fail(PFFRG_EINVAL, "rpa_off not ascending");
+        if (!std::isfinite(lat->coupling[p])) return fail(PFFRG_EINVAL, "couplings must be finite");
     }
     if (nterms > 0 && (!lat->rpa_ka || !lat->rpa_kb || !lat->rpa_cnt))
         return fail(PFFRG_EINVAL, "lattice-sum terms missing");
@@ -503,7 +504,7 @@ pffrg_status check_lattice(const pffrg_lattice* lat, int max_pairs) {
     if (lat->n_basis < 1 || lat->n_sites_total < 1 || !lat->site_pair || !lat->site_pos || !lat->basis_pos)
         return fail(PFFRG_EINVAL, "site map incomplete");
     for (long k = 0; k < (long)lat->n_basis * lat->n_sites_total; ++k)
-        if (lat->site_pair[k] >= ns) return fail(PFFRG_EINVAL, "site_pair out of range");
+        if (lat->site_pair[k] < -1 || lat->site_pair[k] >= ns) return fail(PFFRG_EINVAL, "site_pair out of range");
     return PFFRG_OK;
 }
 

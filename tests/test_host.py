@@ -2,6 +2,7 @@
 validation, and the symmetry-reduced lattice tables of the front end."""
 
 import ctypes
+import dataclasses
 import math
 import os
 import re
@@ -53,6 +54,54 @@ def test_create_rejects_bad_inputs_before_touching_the_gpu():
     assert lib.pffrg_create(None, ctypes.byref(msh), _lib.FP64, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.pffrg_rhs(None, 1.0, None, None) == _lib.EINVAL
     assert lib.pffrg_status_string(_lib.EDIVERGED) == b"PFFRG_EDIVERGED"
+
+
+def test_create_rejects_each_malformed_table():
+    """One field of valid tables corrupted at a time: pffrg_create returns
+    the documented status with a message naming the field, leaves the handle
+    NULL, and does so before any HIP call (this runs without a GPU)."""
+    from paper_2109_13317_amd import _lib
+    from paper_2109_13317_amd.flow import _lattice_struct
+    lib = _lib.load()
+    t = build_tables(W.model("square", j1=1.0, j2=0.5), 2)
+    ns = t.n_pairs
+    mesh = np.array([0.1, 1.0, 10.0])
+    cases = [
+        ("swap", 1, ns, "swap out of range"), ("swap", 1, -1, "swap out of range"),
+        ("mult", 1, 0, "mult"), ("rpa_off", 0, 1, "bad rpa_off"),
+        ("rpa_off", 1, int(t.rpa_off[2]) + 1, "rpa_off not ascending"),
+        ("rpa_ka", 0, ns, "rpa term pair"), ("rpa_kb", 0, -1, "rpa term pair"),
+        ("rpa_cnt", 0, 0, "rpa_cnt"), ("rpa_cnt", 0, 32768, "rpa_cnt"),
+        ("coupling", 1, float("nan"), "couplings must be finite"),
+        ("coupling", 1, float("inf"), "couplings must be finite"),
+        ("site_pair", (0, 0), ns, "site_pair"), ("site_pair", (0, 1), -2, "site_pair"),
+    ]
+    h = ctypes.c_void_p()
+    msh = _lib.Mesh(3, ctypes.c_void_p(mesh.ctypes.data))
+
+    def create(tab, m=msh, prec=_lib.FP64):
+        lat, keep = _lattice_struct(tab)
+        st = lib.pffrg_create(ctypes.byref(lat), ctypes.byref(m), prec, None, ctypes.byref(h))
+        assert not h.value
+        return st, lib.pffrg_last_error().decode()
+
+    for field, idx, val, msg in cases:
+        a = np.array(getattr(t, field), copy=True)
+        a[idx] = val
+        st, err = create(dataclasses.replace(t, **{field: a}))
+        assert st == _lib.EINVAL and msg in err, (field, val, err)
+    assert create(t, prec=7) == (_lib.EINVAL, "unknown precision")
+    st, err = create(dataclasses.replace(t, n_pairs=33))
+    assert st == _lib.EUNSUPPORTED and "32" in err
+    st, err = create(dataclasses.replace(t, n_pairs=0))
+    assert st == _lib.EINVAL and "incomplete" in err
+    st, err = create(dataclasses.replace(t, n_basis=0))
+    assert st == _lib.EINVAL and "site map" in err
+    big = np.geomspace(0.01, 50.0, 129)
+    st, err = create(t, m=_lib.Mesh(129, ctypes.c_void_p(big.ctypes.data)))
+    assert st == _lib.EUNSUPPORTED and "128" in err
+    lat, keep = _lattice_struct(t)
+    assert lib.pffrg_create(ctypes.byref(lat), ctypes.byref(msh), _lib.FP64, None, None) == _lib.EINVAL
 
 
 # ---------------------------------------------------------- lattice tables -
