@@ -12,7 +12,8 @@ parameter and a type) live in resource files: every ``*.xml`` file of a
 search path is scanned for the named definitions.
 
 What this engine accepts: the ``SU2`` backend, Heisenberg interactions
-(``type="heisenberg"``), and the ``correlation`` measurement, written as a
+(``type="heisenberg"``), and the ``correlation`` measurement (direct, or
+deferred to a re-run from stored vertex states), written as a
 NumPy ``.npz`` file (chi^zz and chi^00 per reduced pair and cutoff) where
 the paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
 integrates the cutoff list (the paper's Euler steps, Eq. 42, or RK4 through
@@ -254,11 +255,12 @@ def load(path: str, search_path=None) -> Task:
     for m in (mnode.findall("measurement") if mnode is not None else []):
         if m.get("name") != "correlation":
             raise TaskError(f"{path}: unknown measurement {m.get('name')!r}")
-        if m.get("method") not in (None, "direct"):
+        if m.get("method") not in (None, "direct", "defer"):
             raise TaskError(f"{path}: measurement method {m.get('method')!r} is not available")
         meas.append(Measurement("correlation", m.get("output"),
                                 evaluate(m.get("minCutoff", "0")),
-                                evaluate(m.get("maxCutoff", "inf")) if m.get("maxCutoff") else math.inf))
+                                evaluate(m.get("maxCutoff", "inf")) if m.get("maxCutoff") else math.inf,
+                                m.get("method")))
     calc = root.find("calculation")
     return Task(os.path.abspath(path), mesh, cut, int(lat.get("range", "-1")), model, symmetry, meas,
                 dict(calc.attrib) if calc is not None else {})
@@ -327,6 +329,24 @@ def read_ldf(path: str):
     return pos, par, bonds, inter
 
 
+def _write_state(dest, lam, index, state) -> None:
+    tmp = dest + ".tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, **{"lambda": np.float64(lam), "index": np.int64(index), "state": state})
+    os.replace(tmp, dest)
+
+
+def read_data(path: str):
+    """The vertex states a deferred measurement left in ``path`` (the task
+    path with extension ``.data``): [(cutoff, schedule index, state)] in the
+    order of the flow."""
+    out = []
+    for f in sorted(glob.glob(os.path.join(path, "*.npz"))):
+        with np.load(f, allow_pickle=False) as z:
+            out.append((float(z["lambda"]), int(z["index"]), np.array(z["state"], dtype=np.float64)))
+    return out
+
+
 def _write_obs(dest, rec) -> None:
     tmp = dest + ".tmp"
     with open(tmp, "wb") as f:
@@ -344,10 +364,17 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
     measurement (default output: the task path with extension ``.obs``; a
     NumPy archive with ``lambda`` and ``chi_zz``, ``chi_00`` per reduced
     pair), updated after every accepted step, and the lattice description
-    in the task path with extension ``.ldf`` (``write_ldf``).  A task with a snapshot of the
+    in the task path with extension ``.ldf`` (``write_ldf``).  A measurement
+    with ``method="defer"`` (Sec. 5.1) records nothing during the flow: the
+    vertex state of each of its cutoffs goes to the directory with the task
+    path and extension ``.data`` (one ``.npz`` per cutoff, ``read_data``),
+    and running the finished task again computes the measurement from them.
+    A task with a snapshot of the
     same calculation resumes from it (measurements up to the snapshot are kept
     and the rest recomputed; the resumed steps are bitwise the uninterrupted
-    ones) unless ``force_restart``.  Returns {output path: cutoffs recorded}."""
+    ones) unless ``force_restart``.  Returns {output path: cutoffs recorded},
+    with {data path: states stored in this call} for deferred measurements
+    not yet computed."""
     from . import checkpoint
     from .flow import Context
     from .lattice import build_tables, describe
@@ -376,27 +403,60 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
     write_ldf(base + ".ldf", describe(task.model, task.lattice_range))
     ctx = Context(build_tables(task.model, task.lattice_range), task.mesh, precision=precision)
     x = ctx.init_state()
+    defer = [m.method == "defer" for m in task.measurements]
+    data_dir = base + ".data"
+    index_of = {float(v): i for i, v in enumerate(task.cutoffs)}
+    stored = [0]
 
     def observe(lam, chi, chik):
         c = chi.detach().cpu().numpy()
-        for m, rec, d in zip(task.measurements, records, dests):
+        keep_state = False
+        for m, rec, d, dfr in zip(task.measurements, records, dests, defer):
             if m.min_cutoff <= lam <= m.max_cutoff:
+                if dfr:
+                    keep_state = True
+                    continue
                 rec[0].append(lam)
                 rec[1].append(c[0].copy())
                 rec[2].append(c[1].copy())
                 _write_obs(d, rec)
+        if keep_state:
+            os.makedirs(data_dir, exist_ok=True)
+            i = index_of.get(float(lam))
+            if i is None:
+                i = int(np.argmin(np.abs(np.asarray(task.cutoffs) - lam)))
+            _write_state(os.path.join(data_dir, f"{i:06d}.npz"), lam, i, x.detach().cpu().numpy())
+            stored[0] += 1
         return False
 
     started = task.calculation.get("startTime") if resuming else None
     _set_calculation(task.path, startTime=started or _stamp(), status="running")
-    checkpoint.flow(ctx, x, ck, scheme=scheme, schedule=list(task.cutoffs), every=every, observer=observe,
-                    force_restart=force_restart)
+    n = checkpoint.flow(ctx, x, ck, scheme=scheme, schedule=list(task.cutoffs), every=every, observer=observe,
+                        force_restart=force_restart)
     snap = checkpoint.read(ck).meta
     now = _stamp()
-    _set_calculation(task.path, checkpointTime=now, endTime=now,
-                     status="finished" if snap["status"] == "finished" else "running")
+    finished = snap["status"] == "finished"
+    _set_calculation(task.path, checkpointTime=now, endTime=now, status="finished" if finished else "running")
     out = {}
-    for rec, d in zip(records, dests):
-        _write_obs(d, rec)
-        out[d] = len(rec[0])
+    if any(defer) and finished and n == 0:
+        # a re-run of a finished calculation: the deferred measurements, from
+        # the stored vertex states
+        import torch
+        for lam, _, state in read_data(data_dir):
+            c = ctx.chi(lam, torch.from_numpy(state).cuda()).cpu().numpy()
+            for m, rec, dfr in zip(task.measurements, records, defer):
+                if dfr and m.min_cutoff <= lam <= m.max_cutoff:
+                    rec[0].append(lam)
+                    rec[1].append(c[0].copy())
+                    rec[2].append(c[1].copy())
+        for rec, d, dfr in zip(records, dests, defer):
+            if dfr:
+                _write_obs(d, rec)
+                out[d] = len(rec[0])
+    elif stored[0]:
+        out[data_dir] = stored[0]
+    for rec, d, dfr in zip(records, dests, defer):
+        if not dfr:
+            _write_obs(d, rec)
+            out[d] = len(rec[0])
     return out

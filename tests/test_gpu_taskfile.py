@@ -64,3 +64,40 @@ def test_task_file_runs_and_extends(tmp_path):
     assert np.array_equal(second["chi_zz"][:len(sched) - 1], first["chi_zz"])
     assert np.array_equal(second["chi_zz"][-1], chi2[0]) and np.array_equal(second["chi_00"][-1], chi2[1])
     assert ET.parse(str(task_path)).getroot().find("calculation").get("status") == "finished"
+
+
+def test_deferred_measurement_is_computed_on_the_rerun(tmp_path):
+    """method="defer" (Sec. 5.1): the flow writes the vertex state of every
+    cutoff in the measurement's window instead of the measurement; running
+    the finished task again computes it from them, bitwise equal to the
+    same task measured directly."""
+    import os
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd import taskfile as T
+    from paper_2109_13317_amd.flow import Context
+    (tmp_path / "res.xml").write_text(RESOURCES)
+    direct = tmp_path / "direct.xml"
+    direct.write_text(TASK.format(lmin=2.0).replace('<measurement name="correlation"/>',
+                                                   '<measurement name="correlation" minCutoff="4"/>'))
+    T.run(T.load(str(direct)), scheme="rk4")
+    ref = np.load(str(tmp_path / "direct.obs"))
+    deferred = tmp_path / "later.xml"
+    deferred.write_text(direct.read_text().replace('minCutoff="4"', 'minCutoff="4" method="defer"'))
+    out = T.run(T.load(str(deferred)), scheme="rk4")
+    data = str(tmp_path / "later.data")
+    assert not os.path.exists(str(tmp_path / "later.obs"))
+    states = T.read_data(data)
+    assert out == {data: len(ref["lambda"])} and [s[0] for s in states] == ref["lambda"].tolist()
+    # the stored state of the window's last cutoff is the direct flow's there
+    sched = W.exponential_schedule(20.0, 2.0, 0.85)
+    k = states[-1][1]
+    assert sched[k] == states[-1][0] and sched[k] >= 4.0 > sched[k + 1]
+    ctx = Context(build_tables(W.model("square", j1=1.0, j2=0.3), 2), W.log_mesh(0.01, 40.0, 8))
+    x = ctx.init_state()
+    ctx.flow(x, scheme="rk4", schedule=sched[:k + 1])
+    assert np.array_equal(states[-1][2], x.cpu().numpy())
+    out = T.run(T.load(str(deferred)), scheme="rk4")
+    got = np.load(str(tmp_path / "later.obs"))
+    assert out[str(tmp_path / "later.obs")] == len(ref["lambda"])
+    for k in ("lambda", "chi_zz", "chi_00"):
+        assert np.array_equal(got[k], ref[k]), k

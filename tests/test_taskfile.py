@@ -82,6 +82,7 @@ def test_meshes_follow_the_paper_formulas(tmp_path):
     n = int(math.floor(math.log(0.5 / 20.0) / math.log(0.85)))
     assert len(t.cutoffs) == n + 1 and t.cutoffs[-1] >= 0.5
     assert t.measurements[0].min_cutoff == 1.0 and t.measurements[0].max_cutoff == math.inf
+    assert t.measurements[0].method is None
     p = _task(tmp_path, """<task><parameters>
       <frequency discretization="manual"><value>0.1</value><value>1/2</value><value>3</value></frequency>
       <cutoff discretization="manual"><value>9</value><value>4</value><value>2.5</value></cutoff>
@@ -126,7 +127,7 @@ def test_what_the_su2_engine_cannot_run_is_refused(tmp_path):
         (good.replace("<jb>0.4</jb>", ""), "no value"),
         (good.replace('<lattice name="sq"', '<lattice name="nowhere"'), "unitcell"),
         (good.replace("<step>0.85</step>", "<step>1.5</step>"), "step"),
-        (good.replace('minCutoff="1.0"', 'method="defer"'), "method"),
+        (good.replace('minCutoff="1.0"', 'method="later"'), "method"),
         (good.replace('name="correlation"', 'name="structure"'), "measurement"),
         (good.replace("<count>9</count>", "<count>1</count>"), "count"),
         (good.replace('discretization="exponential"><min>0.5', 'discretization="linear"><min>0.5'), "discretization"),
