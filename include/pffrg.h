@@ -258,7 +258,11 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
  * the timed kernels (no effect on results).  The single-kernel ids get the
  * start and end of the launch itself (events handed to the launch, adding
  * nothing to the stream); PFFRG_K_VERTEX is timed by events recorded before
- * the s and after the t launch (a few microseconds of stream time each).
+ * the first and after the last vertex launch (a few microseconds of stream
+ * time each).  The vertex channels normally run as one launch
+ * (PFFRG_K_VERTEX_STU) followed by the sum of the channel parts; while any of
+ * PFFRG_K_VERTEX_S, _U, _T is timed they run as three launches instead (the
+ * s launch writes, the u and t launches add: the same sums, bitwise).
  * pffrg_set_profiling turns recording on
  * for all of them (1) or off (0); pffrg_set_profiling_mask records only the
  * kernels whose bit (1 << id) is set in `mask` (0: off; a bit at or above
@@ -269,11 +273,12 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
 enum {
     PFFRG_K_SIGMA = 0,      /* self-energy flow */
     PFFRG_K_TABLES = 1,     /* per-channel quadrature tables (with the packed vertex copy, same launch) */
-    PFFRG_K_VERTEX = 2,     /* the whole vertex flow (the three channel launches) */
-    PFFRG_K_VERTEX_S = 3,   /* s channel */
-    PFFRG_K_VERTEX_U = 4,   /* u channel */
-    PFFRG_K_VERTEX_T = 5,   /* t channel with the lattice sum */
-    PFFRG_K_COUNT = 6
+    PFFRG_K_VERTEX = 2,     /* the whole vertex flow (all its launches) */
+    PFFRG_K_VERTEX_S = 3,   /* s channel, own launch */
+    PFFRG_K_VERTEX_U = 4,   /* u channel, own launch */
+    PFFRG_K_VERTEX_T = 5,   /* t channel with the lattice sum, own launch */
+    PFFRG_K_VERTEX_STU = 6, /* s, u and t channels in one launch (the default) */
+    PFFRG_K_COUNT = 7
 };
 pffrg_status pffrg_set_profiling(pffrg_ctx *ctx, int on);
 pffrg_status pffrg_set_profiling_mask(pffrg_ctx *ctx, unsigned mask);

@@ -79,7 +79,7 @@ SIGNATURES = {
     "pffrg_batch_profile_read": [P, ctypes.POINTER(D), ctypes.POINTER(I)],
 }
 
-K_SIGMA, K_TABLES, K_VERTEX, K_VERTEX_S, K_VERTEX_U, K_VERTEX_T = 0, 1, 2, 3, 4, 5
+K_SIGMA, K_TABLES, K_VERTEX, K_VERTEX_S, K_VERTEX_U, K_VERTEX_T, K_VERTEX_STU = 0, 1, 2, 3, 4, 5, 6
 
 _lib = None
 

@@ -1,23 +1,30 @@
 // kernels_flow.h -- HIP kernels of the SU(2) pf-FRG right-hand side (gfx950).
 //
-// One right-hand side (arXiv:2109.13317, Sec. 3) is six launches:
+// One right-hand side (arXiv:2109.13317, Sec. 3) is four launches:
 //   k_sigma_rhs     d sig/d Lambda on the mesh (Eq. 23): the single-scale
 //                   propagator pins the internal frequency to +-Lambda; one
 //                   wave per mesh frequency, lanes over pairs;
-//   k_pack          the two vertex strains interleaved as (Gs, Gd) pairs so
-//                   that one interpolation corner is one 16-byte load;
-//   k_node_tables   per channel X in {s,t,u} and transfer frequency index nu,
+//   k_tables_pack   per channel X in {s,t,u} and transfer frequency index nu,
 //                   the evaluation points w_k of the channel's frequency
 //                   integral and their weights W_k (delta points of S and
 //                   trapezoid nodes of the Katanin term, Eq. 13), so that the
-//                   channel integral is sum_k W_k F_X(w_k); one wave per list;
-//   k_vertex_su<0>  one wave per output triple (s,t,u): the s-channel sum
-//                   for every pair (writes dGamma);
-//   k_vertex_su<2>  the same for the u channel (adds);
-//   k_vertex_t<NSP> the t channel with the particle-hole lattice sum in GEMM
-//                   form (M = sum_k W_k a_k b_k^T, register-blocked 2x4 per
-//                   lane) contracted with the tabulated (ka, kb, count) terms
-//                   (adds).
+//                   channel integral is sum_k W_k F_X(w_k), one wave per list;
+//                   the remaining workgroups interleave the two vertex
+//                   strains as (Gs, Gd) pairs, so that one interpolation
+//                   corner is one 16-byte load;
+//   k_vertex_stu    the three channel sums of every output triple (s,t,u) for
+//                   every pair, one wave per triple; its workgroups take the
+//                   s, u and t roles in turn, so every CU runs all three: the
+//                   t role (the particle-hole lattice sum in GEMM form,
+//                   M = sum_k W_k a_k b_k^T, register-blocked 2x4 per lane,
+//                   contracted with the tabulated (ka, kb, count) terms) is
+//                   bound by the vector ALU and load latency, the s and u
+//                   roles by the rate of gather instructions, and mixed on
+//                   one CU they overlap;
+//   k_sum_channels  dGamma = (s part + u part) + t part.
+// The same channel bodies run as three launches (k_vertex_su<0> writes,
+// k_vertex_su<2> and k_vertex_t<NSP> add, in that order: the same sums
+// bitwise) where each channel is timed on its own.
 #pragma once
 
 #include "device_common.h"
@@ -1158,6 +1165,65 @@ k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __re
     const long vsz = (long)n_triples * ns;
     finish_pairs(red, lane, ns, kWave / ns, lane / ns < kWave / ns, r.s, r.d, 0.0, 0.0,
                  dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, true);
+}
+
+// The s, u and t channels in one launch (grid 24 * per workgroups).  The
+// hardware deals consecutive workgroups round-robin to the 8 XCDs; within an
+// XCD the j-th workgroup takes role j mod 3 (s, u, t) and slot j / 3, and a
+// role's slots walk its XCD's contiguous range of triples as in the separate
+// launches.  The s role writes dx, the u and t roles write du and dt; the
+// LDS area is the larger of the two layouts.
+template <int NSP, class R>
+static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(NSP > 20 ? 3 : (NSP > 16 ? 4 : 5))))
+k_vertex_stu(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ uo_a, const int* __restrict__ uo_c,
+             int n_triples, double* __restrict__ dx, double* __restrict__ du, double* __restrict__ dt) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns;
+    const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int role = __builtin_amdgcn_readfirstlane(j % 3), slot = j / 3;
+    const int per = gridDim.x / 24;
+    const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const Shared sh = load_shared(A, lds_raw, role == 2);
+    A.w = sh.w;
+    const int o = __builtin_amdgcn_readfirstlane((xcd * per + slot) * kWavesPerBlock + wid);
+    if (o >= n_triples) return;
+    const long vsz = (long)n_triples * ns;
+    const __amdgpu_buffer_rsrc_t rv = vertex_rsrc<R>(gv, vsz);
+    if (role < 2) {
+        const WaveLds<R> L{ns};
+        unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * L.su_bytes();
+        PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);
+        double* red = reinterpret_cast<double*>(base + L.su_bytes() - L.red());
+        const int q = o / nf, it = o % nf;
+        if (role == 0) {
+            const Triple T = make_triple(A.w, nf, A.su_a[q], it, A.su_c[q]);
+            const SuPart r = su_body<0, R>(A, sh, plan, T, rv, lane);
+            finish_su<R>(red, lane, ns, r, dx + nf + T.out * ns, dx + nf + vsz + T.out * ns, false);
+        } else {
+            const Triple T = make_triple(A.w, nf, uo_a[q], it, uo_c[q]);
+            const SuPart r = su_body<2, R>(A, sh, plan, T, rv, lane);
+            finish_su<R>(red, lane, ns, r, du + nf + T.out * ns, du + nf + vsz + T.out * ns, false);
+        }
+    } else {
+        const WaveLds<R> L{ns, TShape<NSP>::SUB};
+        unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L.bytes();
+        double* red = reinterpret_cast<double*>(base + L.mat());
+        const int nsu = nf * (nf + 1) / 2;
+        const int it = o / nsu, su = o % nsu;
+        const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
+        const LanePart r = t_body<NSP, R>(A, sh, base, T, rv, lane);
+        finish_pairs(red, lane, ns, kWave / ns, lane / ns < kWave / ns, r.s, r.d, 0.0, 0.0,
+                     dt + nf + T.out * ns, dt + nf + vsz + T.out * ns, false);
+    }
+}
+
+// x[i] = (x[i] + u[i]) + t[i]: the channel parts in the order of the
+// separate launches (grid-stride, any grid size).
+static __global__ void __launch_bounds__(256)
+k_sum_channels(long n, double* __restrict__ x, const double* __restrict__ u, const double* __restrict__ t) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = (x[i] + u[i]) + t[i];
 }
 
 }  // namespace pffrg

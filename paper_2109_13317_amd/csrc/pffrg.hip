@@ -59,6 +59,7 @@ struct pffrg_ctx {
                                     // double2, or float2 in FP32 mode
     double* k[kNumK] = {};
     double *ybuf = nullptr, *ebuf = nullptr;
+    double *part_u = nullptr, *part_t = nullptr;   // u- and t-channel parts of one vertex RHS (state layout)
     double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
     int* cn = nullptr;
     double* chi = nullptr;          // [2*ns]
@@ -221,14 +222,36 @@ pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
     const WaveLds<R> Lsu{c->ns};
     const size_t lds_su = S.bytes(false) + kWavesPerBlock * Lsu.su_bytes();
     const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
+    const size_t lds_t = t_lds_bytes<R>(c->nf, c->ns, c->n_terms);
     prof_mark(c, PFFRG_K_VERTEX, false);
+    constexpr unsigned kPerChannel = (1u << PFFRG_K_VERTEX_S) | (1u << PFFRG_K_VERTEX_U) | (1u << PFFRG_K_VERTEX_T);
+    if (!(c->prof_mask & kPerChannel)) {
+        // the three channels in one launch, then (s + u) + t
+        const size_t lds = lds_t > lds_su ? lds_t : lds_su;
+        const ProfPair e = prof_pair(c, PFFRG_K_VERTEX_STU);
+        switch ((c->ns + 3) / 4) {
+#define PFFRG_STU_CASE(K) \
+            case K: hipExtLaunchKernelGGL((k_vertex_stu<4 * K, R>), dim3(24 * per), block, lds, c->stream, e.start, \
+                                          e.stop, 0, A, (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, \
+                                          T, dx, c->part_u, c->part_t); break;
+            PFFRG_STU_CASE(1) PFFRG_STU_CASE(2) PFFRG_STU_CASE(3) PFFRG_STU_CASE(4)
+            PFFRG_STU_CASE(5) PFFRG_STU_CASE(6) PFFRG_STU_CASE(7) PFFRG_STU_CASE(8)
+#undef PFFRG_STU_CASE
+            default: return fail(PFFRG_EUNSUPPORTED, "pair count out of range");
+        }
+        TRY(launch_check("k_vertex_stu"));
+        const long nv = 2L * T * c->ns;
+        hipLaunchKernelGGL(k_sum_channels, dim3(grid_for(nv, 256)), dim3(256), 0, c->stream, nv, dx + c->nf,
+                           (const double*)c->part_u + c->nf, (const double*)c->part_t + c->nf);
+        prof_mark(c, PFFRG_K_VERTEX, true);
+        return launch_check("k_sum_channels");
+    }
     const ProfPair es = prof_pair(c, PFFRG_K_VERTEX_S);
     hipExtLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, c->stream, es.start, es.stop, 0, A,
                           (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
     const ProfPair eu = prof_pair(c, PFFRG_K_VERTEX_U);
     hipExtLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, c->stream, eu.start, eu.stop, 0, A,
                           (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
-    const size_t lds_t = t_lds_bytes<R>(c->nf, c->ns, c->n_terms);
     const ProfPair et = prof_pair(c, PFFRG_K_VERTEX_T);
     switch ((c->ns + 3) / 4) {
 #define PFFRG_T_CASE(K) \
@@ -625,6 +648,8 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         }
         for (int j = 0; j < kNumK; ++j) TRY(dev_alloc(c, &c->k[j], (size_t)c->size));
         TRY(dev_alloc(c, &c->ybuf, (size_t)c->size));
+        TRY(dev_alloc(c, &c->part_u, (size_t)c->size));
+        TRY(dev_alloc(c, &c->part_t, (size_t)c->size));
         TRY(dev_alloc(c, &c->ebuf, (size_t)c->size));
         TRY(dev_alloc(c, &c->cw, (size_t)c->nq));
         TRY(dev_alloc(c, &c->cq, (size_t)c->nq));

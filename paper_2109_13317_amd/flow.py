@@ -203,11 +203,15 @@ class Context:
 
     # --------------------------------------------------------- profiling --
     _KERNELS = {"sigma": _lib.K_SIGMA, "tables": _lib.K_TABLES, "vertex": _lib.K_VERTEX,
-                "vertex_s": _lib.K_VERTEX_S, "vertex_u": _lib.K_VERTEX_U, "vertex_t": _lib.K_VERTEX_T}
+                "vertex_s": _lib.K_VERTEX_S, "vertex_u": _lib.K_VERTEX_U, "vertex_t": _lib.K_VERTEX_T,
+                "vertex_stu": _lib.K_VERTEX_STU}
 
     def set_profiling(self, on: bool, kernels=None):
         """Record kernel durations with HIP events: all timed kernels, or only
-        the named ones (names as in profile_read); False turns it off."""
+        the named ones (names as in profile_read); False turns it off.
+        Timing 'vertex_s', 'vertex_u' or 'vertex_t' (also implied by all)
+        runs the three channels as separate launches (same results bitwise);
+        otherwise they run as the one 'vertex_stu' launch."""
         if kernels is None or not on:
             _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
         else:
@@ -217,8 +221,9 @@ class Context:
             _lib.check(self.lib.pffrg_set_profiling_mask(self.handle, mask))
 
     def profile_read(self, kernel: str):
-        """(total_ms, launches) of 'sigma', 'tables', 'vertex' (all three channel
-        launches), 'vertex_s', 'vertex_u' or 'vertex_t' since profiling began."""
+        """(total_ms, launches) of 'sigma', 'tables', 'vertex' (all vertex
+        launches), 'vertex_stu', 'vertex_s', 'vertex_u' or 'vertex_t' since
+        profiling began."""
         kid = self._KERNELS[kernel]
         ms, n = ctypes.c_double(), ctypes.c_int()
         _lib.check(self.lib.pffrg_profile_read(self.handle, kid, ctypes.byref(ms), ctypes.byref(n)))

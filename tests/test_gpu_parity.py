@@ -235,10 +235,22 @@ def test_largest_mesh_sampled():
     assert compare_triples(orc, tables, tri, ref, d) <= TOL
 
 
-def test_profiling_mask_times_only_the_named_kernels():
-    """Events recorded around the t-channel launches only; results unchanged."""
-    from paper_2109_13317_amd import _lib
-    torch, tables, ctx, orc = _setup("square_L2_N8")
+@pytest.mark.parametrize("lat,params,L,nf,precision", [
+    ("square", dict(j1=1.0), 2, 8, "fp64"),                      # 4 pairs
+    ("honeycomb", dict(j1=0.6, j2=0.3, j3=0.45), 6, 10, "fp64"),  # 14 pairs
+    ("square", dict(j1=1.0, j2=0.5), 7, 32, "fp64"),             # 20 pairs, the bench workload
+    ("square", dict(j1=1.0, j2=0.5), 7, 32, "fp32"),
+    ("pyrochlore", dict(j1=1.0), 5, 48, "fp64"),                 # 31 pairs, 3.5 M elements (past one grid)
+])
+def test_profiling_mask_times_only_the_named_kernels(lat, params, L, nf, precision):
+    """Events recorded around the named launches only.  The default runs the
+    three channels as one launch; timing a single channel runs them as three
+    launches: the derivatives agree bitwise."""
+    import torch
+    from paper_2109_13317_amd import _lib, build_tables
+    from paper_2109_13317_amd.flow import Context
+    ctx = Context(build_tables(W.model(lat, **params), L), W.log_mesh(1e-3, 100.0, nf), precision=precision)
+    _say(f"{lat} L={L} nf={nf} {precision}: {ctx.ns} pairs")
     x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=3, scale=0.2)).cuda()
     ref = ctx.rhs(0.7, x).clone()
     ctx.set_profiling(True, kernels=("vertex_t",))
@@ -246,12 +258,17 @@ def test_profiling_mask_times_only_the_named_kernels():
     out = ctx.rhs(0.7, x, out)
     ms_t, n_t = ctx.profile_read("vertex_t")
     assert n_t == 2 and ms_t > 0.0
-    for k in ("sigma", "tables", "vertex", "vertex_s", "vertex_u"):
+    for k in ("sigma", "tables", "vertex", "vertex_s", "vertex_u", "vertex_stu"):
         assert ctx.profile_read(k) == (0.0, 0)
+    assert torch.equal(out, ref)
+    ctx.set_profiling(True, kernels=("vertex_stu",))
+    out = ctx.rhs(0.7, x, out)
+    ms, n = ctx.profile_read("vertex_stu")
+    assert n == 1 and ms > 0.0 and ctx.profile_read("vertex_t") == (0.0, 0)
     ctx.set_profiling(False)
     assert torch.equal(out, ref)
     with pytest.raises(_lib.PffrgError):           # a bit past the last kernel id
-        _lib.check(ctx.lib.pffrg_set_profiling_mask(ctx.handle, 1 << 6))
+        _lib.check(ctx.lib.pffrg_set_profiling_mask(ctx.handle, 1 << 7))
 
 
 def test_measure_peaks_is_plausible():
