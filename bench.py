@@ -478,6 +478,7 @@ def cpu_baseline(model, wl, tables, x_np, lam, target_s=12.0):
 def host_cpu() -> dict:
     """The host the oracle ran on: logical CPUs, model and current clock
     (from /proc/cpuinfo, where present), and how the oracle was compiled."""
+    import oracle
     model, mhz = None, []
     try:
         with open("/proc/cpuinfo") as f:
@@ -491,7 +492,7 @@ def host_cpu() -> dict:
         pass
     return {"logical_cpus": os.cpu_count(), "model": model,
             "mhz_mean": float(np.mean(mhz)) if mhz else None,
-            "oracle_build": "gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math"}
+            "oracle_build": "gcc " + " ".join(oracle.CFLAGS)}
 
 
 def _tiny_flows(threads):

@@ -37,14 +37,21 @@ _SRC = os.path.join(_HERE, "pffrg_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the C oracle with gcc (FP64, no contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
-                               "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+# gcc flags of the oracle: FP64 throughout, no contraction into fused
+# multiply-adds and no reassociation, so the optimisation level changes no
+# result bit (tests/test_oracle_sanitized.py compares an -O1 build with this one).
+CFLAGS = ["-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared"]
+
+
+def build(force: bool = True, out: str | None = None, extra=()) -> str:
+    """Compile the C oracle with gcc (FP64, no contraction, no fast-math).
+    out/extra: another output path and flags (the sanitizer build of the tests)."""
+    lib = out or _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Lat(ctypes.Structure):
@@ -59,9 +66,10 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("PFFRG_ORACLE_LIB", _LIB)
+        if path == _LIB and not os.path.exists(_LIB):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         D = ctypes.c_double
         I = ctypes.c_int
@@ -194,100 +202,17 @@ class Oracle:
         k4 = self.rhs(lam1, x + h * k3)
         return x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
-    # Dormand-Prince 5(4) tableau (Dormand & Prince 1980): nodes, stage
-    # coefficients, and the difference of the 5th and 4th order weights.
-    DP_C = (0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0)
-    DP_A = ((), (1 / 5,), (3 / 40, 9 / 40), (44 / 45, -56 / 15, 32 / 9),
-            (19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729),
-            (9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656),
-            (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84))
-    DP_E = (35 / 384 - 5179 / 57600, 0.0, 500 / 1113 - 7571 / 16695, 125 / 192 - 393 / 640,
-            -2187 / 6784 + 92097 / 339200, 11 / 84 - 187 / 2100, -1 / 40)
-
     def dopri_flow(self, lam_start, lam_stop, rtol, atol, h0, hmin, x0=None, max_steps=0,
                    observer=None):
-        """Adaptive Dormand-Prince 5(4) in l = ln Lambda (dx/dl = Lambda dx/dLambda)
-        from lam_start down to lam_stop.  Error norm
-        max_i |e_i| / (atol + rtol max(|x_i|, |y_i|)); accept if <= 1.  Step
-        sizes are h0 2^(m/4); after a step m changes by round(4 log2(f)) with
-        f = clamp(0.9 err^-1/5, 0.2, 5) (rejected: clamp to [0.2, 1] and at
-        least -1); a step shortened to land on a breakpoint or the end keeps m
-        unless f < 1.  The right-hand side jumps where Lambda crosses w_n/2 (a
-        step function of a delta-point propagator switches), so steps end 1e-12
-        (in l) above each such breakpoint and restart 1e-12 below it.
+        """Adaptive Dormand-Prince 5(4) flow of this model from lam_start down
+        to lam_stop (see ``dopri_integrate``).  The right-hand side jumps where
+        Lambda crosses w_n/2 (a step function of a delta-point propagator
+        switches, Eq. 12), so those cutoffs are the breakpoints.
         Returns (x, accepted cutoffs)."""
         x = self.initial_state() if x0 is None else np.array(x0, dtype=np.float64)
-        lend = math.log(lam_stop)
-        l = math.log(lam_start)
-        m = 0
-
-        def ladder(mm):
-            return h0 * 2.0 ** (mm / 4.0)
-
-        def quarter_steps(f):
-            v = 4.0 * math.log2(f)
-            return int(math.floor(v + 0.5)) if v >= 0 else -int(math.floor(-v + 0.5))
-
-        maxs = max_steps if max_steps > 0 else 1000000
-        brk = sorted((math.log(0.5 * w) for w in self.mesh if lend < math.log(0.5 * w) < l), reverse=True)
-        gap = 1e-12
-        ib = 0
-        k = [None] * 7
-        k[0] = self.rhs(math.exp(l), x)
-        lams = []
-        attempts = 0
-        while l > lend:
-            attempts += 1
-            if attempts > 50 * maxs:
-                raise RuntimeError("too many rejected steps")
-            while ib < len(brk) and brk[ib] + gap >= l:
-                ib += 1
-            dl = -ladder(m)
-            last = at_brk = False
-            if ib < len(brk) and l + dl <= brk[ib] + gap:
-                dl = (brk[ib] + gap) - l
-                at_brk = True
-            if l + dl <= lend:
-                dl = lend - l
-                last, at_brk = True, False
-            lam = [math.exp(l + c * dl) for c in self.DP_C]
-            for i in range(1, 7):
-                y = x.copy()
-                for j in range(i):
-                    cj = dl * self.DP_A[i][j] * lam[j]
-                    if cj != 0.0:
-                        y += cj * k[j]
-                k[i] = self.rhs(lam[i], y)
-            e = np.zeros_like(x)
-            for j in range(7):
-                cj = dl * self.DP_E[j] * lam[j]
-                if cj != 0.0:
-                    e += cj * k[j]
-            fin = bool(np.all(np.isfinite(y)) and np.all(np.isfinite(x)))
-            err = float(np.max(np.abs(e) / (atol + rtol * np.maximum(np.abs(x), np.abs(y))))) if fin else 0.0
-            if fin and err <= 1.0:
-                x = y
-                k[0] = k[6]
-                l = lend if last else l + dl
-                if at_brk:
-                    l = brk[ib] - gap
-                    ib += 1
-                    k[0] = self.rhs(math.exp(l), x)
-                lams.append(math.exp(l))
-                if observer is not None:
-                    observer(math.exp(l), x)
-                if len(lams) >= maxs:
-                    break
-                fac = min(5.0, max(0.2, 0.9 * err ** -0.2)) if err > 0.0 else 5.0
-                dm = quarter_steps(fac)
-                if not (at_brk or last) or dm < 0:
-                    m += dm
-            else:
-                fac = min(1.0, max(0.2, 0.9 * err ** -0.2)) if (fin and err > 0.0) else 0.2
-                m += min(-1, quarter_steps(fac))
-            if ladder(m) < hmin and l > lend:
-                raise RuntimeError(f"adaptive step fell below hmin at lambda = {math.exp(l)}")
-        return x, lams
+        return dopri_integrate(self.rhs, x, lam_start, lam_stop, rtol, atol, h0, hmin,
+                               breakpoints=[0.5 * w for w in self.mesh], max_steps=max_steps,
+                               observer=observer)
 
     def flow(self, schedule, x0=None, scheme="rk4", observer=None):
         """Integrate along a fixed cutoff schedule; observer(lam, x) after each step."""
@@ -299,6 +224,117 @@ class Oracle:
                 observer(float(schedule[i + 1]), x)
         return x
 
+
+
+# ---------------------------------------------------------------------------
+# Dormand-Prince 5(4) (J. R. Dormand and P. J. Prince, "A family of embedded
+# Runge-Kutta formulae", J. Comput. Appl. Math. 6 (1980) 19-26): nodes, stage
+# coefficients, and the difference of the 5th and 4th order weights.  The
+# seventh stage is evaluated at the accepted 5th-order point, so it serves as
+# the first stage of the next step.
+DP_C = (0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0)
+DP_A = ((), (1 / 5,), (3 / 40, 9 / 40), (44 / 45, -56 / 15, 32 / 9),
+        (19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729),
+        (9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656),
+        (35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84))
+DP_E = (35 / 384 - 5179 / 57600, 0.0, 500 / 1113 - 7571 / 16695, 125 / 192 - 393 / 640,
+        -2187 / 6784 + 92097 / 339200, 11 / 84 - 187 / 2100, -1 / 40)
+
+
+def dopri_step(rhs, l, dl, x, k0):
+    """One Dormand-Prince 5(4) step in l = ln Lambda of dx/dl = Lambda dx/dLambda
+    (rhs(Lambda, x) = dx/dLambda) from l to l + dl, with k0 = rhs(exp(l), x).
+    Returns (y, e, k): the 5th-order point, the difference of the 5th- and
+    4th-order points, and the seven stage derivatives dx/dLambda."""
+    lam = [math.exp(l + c * dl) for c in DP_C]
+    k = [k0] + [None] * 6
+    y = x
+    for i in range(1, 7):
+        y = x.copy()
+        for j in range(i):
+            cj = dl * DP_A[i][j] * lam[j]
+            if cj != 0.0:
+                y += cj * k[j]
+        k[i] = rhs(lam[i], y)
+    e = np.zeros_like(x)
+    for j in range(7):
+        cj = dl * DP_E[j] * lam[j]
+        if cj != 0.0:
+            e += cj * k[j]
+    return y, e, k
+
+
+def dopri_integrate(rhs, x0, lam_start, lam_stop, rtol, atol, h0, hmin, breakpoints=(),
+                    max_steps=0, observer=None):
+    """Adaptive Dormand-Prince 5(4) in l = ln Lambda from lam_start down to
+    lam_stop.  Error norm max_i |e_i| / (atol + rtol max(|x_i|, |y_i|));
+    accept if <= 1.  Step sizes are h0 2^(m/4); after a step m changes by
+    round(4 log2(f)) with f = clamp(0.9 err^-1/5, 0.2, 5) (rejected: clamp to
+    [0.2, 1] and at least -1); a step shortened to land on a breakpoint or the
+    end keeps m unless f < 1.  Across a breakpoint of the right-hand side (a
+    cutoff where it jumps) a step ends 1e-12 (in l) above it and the next one
+    starts 1e-12 below it, with the derivative evaluated afresh.
+    observer(Lambda, x) after each accepted step.  Returns (x, accepted
+    cutoffs)."""
+    x = np.array(x0, dtype=np.float64)
+    lend = math.log(lam_stop)
+    l = math.log(lam_start)
+    m = 0
+
+    def ladder(mm):
+        return h0 * 2.0 ** (mm / 4.0)
+
+    def quarter_steps(f):
+        v = 4.0 * math.log2(f)
+        return int(math.floor(v + 0.5)) if v >= 0 else -int(math.floor(-v + 0.5))
+
+    maxs = max_steps if max_steps > 0 else 1000000
+    brk = sorted((math.log(b) for b in breakpoints if lend < math.log(b) < l), reverse=True)
+    gap = 1e-12
+    ib = 0
+    k0 = rhs(math.exp(l), x)
+    lams = []
+    attempts = 0
+    while l > lend:
+        attempts += 1
+        if attempts > 50 * maxs:
+            raise RuntimeError("too many rejected steps")
+        while ib < len(brk) and brk[ib] + gap >= l:
+            ib += 1
+        dl = -ladder(m)
+        last = at_brk = False
+        if ib < len(brk) and l + dl <= brk[ib] + gap:
+            dl = (brk[ib] + gap) - l
+            at_brk = True
+        if l + dl <= lend:
+            dl = lend - l
+            last, at_brk = True, False
+        y, e, k = dopri_step(rhs, l, dl, x, k0)
+        fin = bool(np.all(np.isfinite(y)) and np.all(np.isfinite(x)))
+        err = float(np.max(np.abs(e) / (atol + rtol * np.maximum(np.abs(x), np.abs(y))))) if fin else 0.0
+        if fin and err <= 1.0:
+            x = y
+            k0 = k[6]
+            l = lend if last else l + dl
+            if at_brk:
+                l = brk[ib] - gap
+                ib += 1
+                k0 = rhs(math.exp(l), x)
+            lams.append(math.exp(l))
+            if observer is not None:
+                observer(math.exp(l), x)
+            if len(lams) >= maxs:
+                break
+            fac = min(5.0, max(0.2, 0.9 * err ** -0.2)) if err > 0.0 else 5.0
+            dm = quarter_steps(fac)
+            if not (at_brk or last) or dm < 0:
+                m += dm
+        else:
+            fac = min(1.0, max(0.2, 0.9 * err ** -0.2)) if (fin and err > 0.0) else 0.2
+            m += min(-1, quarter_steps(fac))
+        if ladder(m) < hmin and l > lend:
+            raise RuntimeError(f"adaptive step fell below hmin at lambda = {math.exp(l)}")
+    return x, lams
 
 def timed(fn, *a, **kw):
     t0 = time.perf_counter()
