@@ -57,7 +57,8 @@ def build(force: bool = True, out: str | None = None, extra=()) -> str:
 class _Lat(ctypes.Structure):
     _fields_ = [("nf", ctypes.c_int), ("w", ctypes.c_void_p), ("nb", ctypes.c_int),
                 ("ns", ctypes.c_int), ("nsites", ctypes.c_void_p), ("cell", ctypes.c_void_p),
-                ("bas", ctypes.c_void_p), ("rm", ctypes.c_int), ("lookup", ctypes.c_void_p)]
+                ("bas", ctypes.c_void_p), ("rm", ctypes.c_int), ("lookup", ctypes.c_void_p),
+                ("nc", ctypes.c_int)]
 
 
 _lib = None
@@ -85,6 +86,8 @@ def _load():
         lib.orc_vertex_rhs_triples.restype = None
         lib.orc_chi.argtypes = [P, D, P, P, P]
         lib.orc_chi.restype = None
+        lib.orc_chi_comps.argtypes = [P, D, P, P]
+        lib.orc_chi_comps.restype = None
         _lib = lib
     return _lib
 
@@ -96,9 +99,12 @@ def _ptr(a: np.ndarray):
 class Oracle:
     """The oracle on one lattice model and one frequency mesh.
 
-    State layout (oracle-private): sig[nf] | Gs[nb][n_su][nf][ns] | Gd[...]
-    where n_su enumerates mesh index pairs a >= c of (s, u) as a(a+1)/2 + c
-    and ns pads every basis site's site list to the same length.
+    State layout (oracle-private): sig[nf] | strain 0 | strain 1 [| 2 | 3],
+    each strain [nb][n_su][nf][ns], where n_su enumerates mesh index pairs
+    a >= c of (s, u) as a(a+1)/2 + c and ns pads every basis site's site
+    list to the same length.  Heisenberg models (SU(2)) have two strains,
+    spin and density; XYZ models (couplings (Jx, Jy, Jz), Sec. 2) four: x, y,
+    z and density.
     """
 
     def __init__(self, model, lattice_range: int, mesh: np.ndarray, threads: int = 0):
@@ -106,10 +112,12 @@ class Oracle:
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.threads = int(threads)
+        self.symmetry = "xyz" if self.lat.coupling.ndim == 3 else "su2"
+        self.nc = 4 if self.symmetry == "xyz" else 2
         lat = self.lat
         self._keep = [self.mesh, lat.nsites, lat.cell, lat.bas, lat.lookup]
         self._s = _Lat(self.nf, self.mesh.ctypes.data, lat.nb, lat.ns, lat.nsites.ctypes.data,
-                       lat.cell.ctypes.data, lat.bas.ctypes.data, lat.rm, lat.lookup.ctypes.data)
+                       lat.cell.ctypes.data, lat.bas.ctypes.data, lat.rm, lat.lookup.ctypes.data, self.nc)
         self._p = ctypes.byref(self._s)
         self.lib = _load()
         self.n_su = self.nf * (self.nf + 1) // 2
@@ -118,18 +126,24 @@ class Oracle:
 
     # ---------------------------------------------------------- layout --
     def split(self, x: np.ndarray):
-        """Views (sig, Gs, Gd) with Gs/Gd shaped [nb, n_su, nf, ns]."""
+        """Views (sig, strain 0, strain 1, ...), each strain [nb, n_su, nf, ns]:
+        SU(2) (sig, Gs, Gd), XYZ (sig, Gx, Gy, Gz, Gd)."""
         lat = self.lat
         sig = x[: self.nf]
-        gs = x[self.nf: self.nf + self.vsize].reshape(lat.nb, self.n_su, self.nf, lat.ns)
-        gd = x[self.nf + self.vsize:].reshape(lat.nb, self.n_su, self.nf, lat.ns)
-        return sig, gs, gd
+        return (sig,) + tuple(x[self.nf + c * self.vsize: self.nf + (c + 1) * self.vsize]
+                              .reshape(lat.nb, self.n_su, self.nf, lat.ns) for c in range(self.nc))
 
     def initial_state(self) -> np.ndarray:
-        """Sigma = 0, spin vertex = J_ij/4, density vertex = 0 (Eq. 14, Eq. 21)."""
+        """Sigma = 0, spin vertices = J_ij/4 (SU(2): the spin strain; XYZ: each
+        of Gx, Gy, Gz from its own coupling), density vertex = 0 (Eq. 14,
+        Eq. 21)."""
         x = np.zeros(self.size)
-        _, gs, _ = self.split(x)
-        gs[...] = (self.lat.coupling / 4.0)[:, None, None, :]
+        parts = self.split(x)
+        if self.nc == 2:
+            parts[1][...] = (self.lat.coupling / 4.0)[:, None, None, :]
+        else:
+            for c in range(3):
+                parts[1 + c][...] = (self.lat.coupling[:, :, c] / 4.0)[:, None, None, :]
         return x
 
     # ------------------------------------------------------------- RHS --
@@ -148,26 +162,45 @@ class Oracle:
     def vertex_rhs_element(self, lam, x, dsig, b, k, a, t, c):
         x = np.ascontiguousarray(x, dtype=np.float64)
         dsig = np.ascontiguousarray(dsig, dtype=np.float64)
-        out = np.zeros(2)
+        out = np.zeros(self.nc)
         self.lib.orc_vertex_rhs_element(self._p, float(lam), _ptr(x), _ptr(dsig),
                                         int(b), int(k), int(a), int(t), int(c), _ptr(out))
         return out
 
     def vertex_rhs_triples(self, lam, x, dsig, triples) -> np.ndarray:
         """Flow of every (basis, site) element at each (a, t, c) triple:
-        returns [nq, nb, ns, 2]."""
+        returns [nq, nb, ns, strains]."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         dsig = np.ascontiguousarray(dsig, dtype=np.float64)
         tr = np.asarray(triples, dtype=np.int32).reshape(-1, 3)
         a = np.ascontiguousarray(tr[:, 0]); t = np.ascontiguousarray(tr[:, 1])
         c = np.ascontiguousarray(tr[:, 2])
-        out = np.zeros((len(tr), self.lat.nb, self.lat.ns, 2))
+        out = np.zeros((len(tr), self.lat.nb, self.lat.ns, self.nc))
         self.lib.orc_vertex_rhs_triples(self._p, float(lam), _ptr(x), _ptr(dsig), len(tr),
                                         _ptr(a), _ptr(t), _ptr(c), _ptr(out), self.threads)
         return out
 
+    def chi_comps(self, lam: float, x: np.ndarray) -> np.ndarray:
+        """chi per strain, [strains, nb, ns] (SU(2): zz, 00; XYZ: xx, yy, zz, 00)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros((self.nc, self.lat.nb, self.lat.ns))
+        self.lib.orc_chi_comps(self._p, float(lam), _ptr(x), _ptr(out))
+        return out
+
+    def chi_k_xyz(self, chi: np.ndarray, kpts: np.ndarray) -> np.ndarray:
+        """XYZ structure factor (Eq. 31) per unit cell:
+        (1/nb) sum_b sum_{j in range of b} cos(k.(r_b - r_j)) (chi^xx + chi^yy + chi^zz)_bj."""
+        kpts = np.asarray(kpts, dtype=np.float64).reshape(-1, 3)
+        out = np.zeros(len(kpts))
+        lat = self.lat
+        for b in range(lat.nb):
+            n = lat.nsites[b]
+            dr = lat.basis_pos[b][None, :] - lat.site_pos[b, :n]
+            out += np.cos(kpts @ dr.T) @ (chi[0, b, :n] + chi[1, b, :n] + chi[2, b, :n])
+        return out / lat.nb
+
     def chi(self, lam: float, x: np.ndarray):
-        """(chi_zz, chi_dd), each [nb, ns] over the unreduced site lists."""
+        """SU(2): (chi_zz, chi_dd), each [nb, ns] over the unreduced site lists."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         zz = np.zeros((self.lat.nb, self.lat.ns))
         dd = np.zeros((self.lat.nb, self.lat.ns))

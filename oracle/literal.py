@@ -4,7 +4,9 @@ TEST INFRASTRUCTURE ONLY.  An independent second evaluation of what the C
 oracle computes, written straight from the paper's explicit equations:
 
   * the vertex is built as 16 basis functions Gamma^{mu nu} (Eq. 16) with the
-    SU(2) constraint (Gamma^{11}=Gamma^{22}=Gamma^{33}, off-diagonals zero);
+    SU(2) constraint (Gamma^{11}=Gamma^{22}=Gamma^{33}, off-diagonals zero),
+    or for XYZ states the XYZ constraint (the four diagonal components
+    Gamma^{00}, Gamma^{11}, Gamma^{22}, Gamma^{33} free, off-diagonals zero);
     values outside the stored octant come from the general symmetry relations
     (Eq. 18, with xi of Eq. 19 and mu<->nu transposition applied literally);
   * the spin tensor Gamma^{a'b';ab} = Gamma^{mu nu} sigma^mu_{a'a} sigma^nu_{b'b}
@@ -59,10 +61,16 @@ class LiteralFlow:
             m = self._stored(b, k, c, t, a)
             return m * (-XI)[None, :]
         su = a * (a + 1) // 2 + c
-        _, gs, gd = self.o.split(self.x)
+        parts = self.o.split(self.x)
         m = np.zeros((4, 4))
-        m[0, 0] = gd[b, su, t, k]
-        m[1, 1] = m[2, 2] = m[3, 3] = gs[b, su, t, k]
+        if self.o.nc == 2:
+            _, gs, gd = parts
+            m[0, 0] = gd[b, su, t, k]
+            m[1, 1] = m[2, 2] = m[3, 3] = gs[b, su, t, k]
+        else:
+            _, gx, gy, gz, gd = parts
+            m[0, 0] = gd[b, su, t, k]
+            m[1, 1], m[2, 2], m[3, 3] = gx[b, su, t, k], gy[b, su, t, k], gz[b, su, t, k]
         return m
 
     def gamma(self, b1, d, b2, s, t, u):

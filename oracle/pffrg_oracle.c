@@ -12,11 +12,15 @@
  *     the two points |w| = Lambda.
  *   - Vertex flow, Sec. 3 explicit two-particle flow (Eq. 24): s, t (RPA plus
  *     two vertex corrections) and u channels, Katanin propagator (Eq. 13).
- *   - SU(2) vertex: Gamma^{11}=Gamma^{22}=Gamma^{33} ("spin" strain) and
- *     Gamma^{00} ("density" strain), other components zero (Sec. 3, SU(2)
- *     constraint).  The spin contractions of Eq. 24 with Eq. 25 are done by
- *     hand; the coefficients are the Pauli-algebra results
- *     sum_k s^k s^l s^k = -s^l, (s.s)x(s.s) = 3 1x1 -+ 2 s.s, etc.
+ *   - SU(2) vertex (nc = 2 strains): Gamma^{11}=Gamma^{22}=Gamma^{33}
+ *     ("spin" strain) and Gamma^{00} ("density" strain), other components
+ *     zero (Sec. 3, SU(2) constraint).  XYZ vertex (nc = 4 strains, Sec. 3:
+ *     only the diagonal components mu = nu are non-zero): Gamma^{11},
+ *     Gamma^{22}, Gamma^{33} (x, y, z) and Gamma^{00} (density).  The density
+ *     strain is the last one in both.  The spin contractions of Eq. 24 with
+ *     Eq. 25 are done by hand; the coefficients are Pauli-algebra results
+ *     (sigma^a sigma^b = delta_ab + i eps_abc sigma^c), and the SU(2) ones are
+ *     the XYZ ones with the three spin strains equal.
  *   - Vertex symmetries (Eq. 18 with xi of Eq. 19), octant storage s>=u,
  *     t>=0 (Sec. 4.2) and trilinear interpolation with constant
  *     extrapolation (Eq. 37); Sigma odd with linear interpolation (Eq. 36).
@@ -68,6 +72,7 @@ typedef struct {
     const int *bas;      /* [nb][ns]   basis index of each listed site */
     int rm;              /* half-width of the offset lookup box */
     const int *lookup;   /* [nb][2rm+1][2rm+1][2rm+1][nb] -> list index or -1 */
+    int nc;              /* vertex strains: 2 (SU(2): spin, density) or 4 (XYZ: x, y, z, density) */
 } orc_lattice;
 
 /* ------------------------------------------------------------ layout --- */
@@ -76,7 +81,8 @@ static long su_index(int a, int c) { return (long)a * (a + 1) / 2 + c; }
 
 static long n_su(const orc_lattice *L) { return su_index(L->nf, 0); }
 
-/* Offset of strain `comp` (0 spin, 1 density) in the state vector. */
+/* Offset of strain `comp` in the state vector (SU(2): 0 spin, 1 density;
+ * XYZ: 0 x, 1 y, 2 z, 3 density). */
 static long strain_offset(const orc_lattice *L, int comp)
 {
     return L->nf + (long)comp * L->nb * n_su(L) * L->nf * L->ns;
@@ -84,8 +90,11 @@ static long strain_offset(const orc_lattice *L, int comp)
 
 long orc_state_size(const orc_lattice *L)
 {
-    return L->nf + 2L * L->nb * n_su(L) * L->nf * L->ns;
+    return L->nf + (long)L->nc * L->nb * n_su(L) * L->nf * L->ns;
 }
+
+/* The density strain Gamma^{00} is the last one; it alone changes sign under s <-> u. */
+static int is_density(const orc_lattice *L, int comp) { return comp == L->nc - 1; }
 
 /* Index of vertex value (comp, basis b, s-index a, t-index t, u-index c, site k), a>=c. */
 static long vidx(const orc_lattice *L, int comp, int b, int a, int t, int c, int k)
@@ -135,7 +144,7 @@ static double odd_interp(const orc_lattice *L, const double *v, double x)
  * Vertex strain `comp` between site (b1, cell 0) and site (b2, cell d) at
  * transfer frequencies (s,t,u).  Eq. 18 with xi(0)=+1, xi(3)=-1:
  *   s -> -s swaps the two sites; t -> -t is free; u -> -u swaps the sites;
- *   s <-> u is free for the spin strain and flips the density strain.
+ *   s <-> u is free for the spin strains and flips the density strain.
  * Outside the truncation range the vertex is zero (Eq. 34).
  */
 static double vertex(const orc_lattice *L, const double *x, int comp,
@@ -146,7 +155,7 @@ static double vertex(const orc_lattice *L, const double *x, int comp,
     if (s < 0.0) { s = -s; int tb = b1; b1 = b2; b2 = tb; d[0] = -d[0]; d[1] = -d[1]; d[2] = -d[2]; }
     if (t < 0.0) t = -t;
     if (u < 0.0) { u = -u; int tb = b1; b1 = b2; b2 = tb; d[0] = -d[0]; d[1] = -d[1]; d[2] = -d[2]; }
-    if (s < u) { double q = s; s = u; u = q; if (comp == 1) sign = -sign; }
+    if (s < u) { double q = s; s = u; u = q; if (is_density(L, comp)) sign = -sign; }
     int k = site_of(L, b1, d, b2);
     if (k < 0) return 0.0;
 
@@ -164,7 +173,7 @@ static double vertex(const orc_lattice *L, const double *x, int comp,
                 int a = sa[is], c = ua[iu];
                 double v;
                 if (a >= c) v = x[vidx(L, comp, b1, a, ta[it], c, k)];
-                else v = (comp == 1 ? -1.0 : 1.0) * x[vidx(L, comp, b1, c, ta[it], a, k)];
+                else v = (is_density(L, comp) ? -1.0 : 1.0) * x[vidx(L, comp, b1, c, ta[it], a, k)];
                 acc += wgt * v;
             }
     return sign * acc;
@@ -239,24 +248,31 @@ static int piece_nodes(const orc_lattice *L, double lo, double hi, double *nodes
 
 /*
  * d sig/dLambda(w) = (1/2pi) sum_{x=+-Lambda} F(w,x) / (x - sig(x)) with
- * F = 2 sum_j Gd_{0j}(w+x, 0, w-x) - (3 Gs_{00} + Gd_{00})(w+x, x-w, 0)
- * (Eq. 23 contracted with Eq. 25; the sum over j covers every site in range
- * of the reference site, which is basis site 0).
+ *   SU(2): F = 2 sum_j Gd_{0j}(w+x, 0, w-x) - (3 Gs_{00} + Gd_{00})(w+x, x-w, 0)
+ *   XYZ:   F = 2 sum_j Gd_{0j}(w+x, 0, w-x) - (Gx + Gy + Gz + Gd)_{00}(w+x, x-w, 0)
+ * (Eq. 23 contracted with Eq. 25: the direct term traces the density
+ * strain, the exchange term sums every diagonal component; the sum over j
+ * covers every site in range of the reference site, basis site 0).
  */
 double orc_sigma_rhs_at(const orc_lattice *L, double lam, const double *x, double w)
 {
     orc_eval E = {L, x, NULL, lam};
     const int zero[3] = {0, 0, 0};
+    const int dens = L->nc - 1;
     double acc = 0.0;
     for (int sx = 0; sx < 2; ++sx) {
         double xx = sx == 0 ? lam : -lam;
         double f = 0.0;
         for (int k = 0; k < L->nsites[0]; ++k) {
             const int *cr = &L->cell[(long)k * 3];
-            f += 2.0 * vertex(L, x, 1, 0, cr, L->bas[k], w + xx, 0.0, w - xx);
+            f += 2.0 * vertex(L, x, dens, 0, cr, L->bas[k], w + xx, 0.0, w - xx);
         }
-        f -= 3.0 * vertex(L, x, 0, 0, zero, 0, w + xx, xx - w, 0.0);
-        f -= vertex(L, x, 1, 0, zero, 0, w + xx, xx - w, 0.0);
+        if (L->nc == 2) {
+            f -= 3.0 * vertex(L, x, 0, 0, zero, 0, w + xx, xx - w, 0.0);
+        } else {
+            for (int c = 0; c < 3; ++c) f -= vertex(L, x, c, 0, zero, 0, w + xx, xx - w, 0.0);
+        }
+        f -= vertex(L, x, dens, 0, zero, 0, w + xx, xx - w, 0.0);
         acc += f / (xx - sig_at(&E, xx));
     }
     return acc / TWO_PI;
@@ -277,75 +293,116 @@ typedef struct {
     double w1p, w2p, w1, w2;   /* external frequencies (Eq. 17 inverted) */
 } orc_out;
 
-/* The channel integrands: out[0] += spin part, out[1] += density part,
- * for one frequency w of the loop, already multiplied by `wt`. */
-static void integrand_s(const orc_eval *E, const orc_out *o, double w, double wt, double acc[2])
+/* The channel integrands for one frequency w of the loop, already
+ * multiplied by `wt`, added to acc[comp] for every strain.
+ *
+ * SU(2) (acc[0] spin, acc[1] density; A, B the two vertices of each
+ * product in the order of Eq. 24):
+ *   s: dGs = -2 As Bs + As Bd + Ad Bs,  dGd = 3 As Bs + Ad Bd
+ *   u: dGs = +2 As Bs + As Bd + Ad Bs,  dGd = 3 As Bs + Ad Bd
+ *   t: dGs = -2 sum_j a_js b_js - As O1s + As O1d - O2s Bs + O2d Bs
+ *      dGd = -2 sum_j a_jd b_jd + 3 Ad O1s + Ad O1d + 3 O2s Bd + O2d Bd
+ * XYZ (acc[0..2] = x, y, z, acc[3] = density; (a, b, c) any cyclic
+ * permutation of (x, y, z), d the density strain):
+ *   s: dGd = Ad Bd + Ax Bx + Ay By + Az Bz,  dGa = Ad Ba + Aa Bd - Ab Bc - Ac Bb
+ *   u: dGd = Ad Bd + Ax Bx + Ay By + Az Bz,  dGa = Ad Ba + Aa Bd + Ab Bc + Ac Bb
+ *   t: dGm = -2 sum_j a_jm b_jm + Am sum_n e(m,n) O1n + Bm sum_n e(m,n) O2n
+ *      with e(m,n) = +1 if m or n is the density strain or m = n, else -1.
+ */
+static void integrand_s(const orc_eval *E, const orc_out *o, double w, double wt, double acc[4])
 {
     const orc_lattice *L = E->L;
-    double As = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->s, o->w1p - w, w - o->w2p);
-    double Ad = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->s, o->w1p - w, w - o->w2p);
-    double Bs = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->s, w - o->w1, w - o->w2);
-    double Bd = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->s, w - o->w1, w - o->w2);
-    acc[0] += wt * (-2.0 * As * Bs + As * Bd + Ad * Bs);
-    acc[1] += wt * (3.0 * As * Bs + Ad * Bd);
+    double A[4], B[4];
+    for (int c = 0; c < L->nc; ++c) {
+        A[c] = vertex(L, E->x, c, o->b, o->dk, o->bk, o->s, o->w1p - w, w - o->w2p);
+        B[c] = vertex(L, E->x, c, o->b, o->dk, o->bk, o->s, w - o->w1, w - o->w2);
+    }
+    if (L->nc == 2) {
+        acc[0] += wt * (-2.0 * A[0] * B[0] + A[0] * B[1] + A[1] * B[0]);
+        acc[1] += wt * (3.0 * A[0] * B[0] + A[1] * B[1]);
+    } else {
+        acc[3] += wt * (A[3] * B[3] + A[0] * B[0] + A[1] * B[1] + A[2] * B[2]);
+        acc[0] += wt * (A[3] * B[0] + A[0] * B[3] - A[1] * B[2] - A[2] * B[1]);
+        acc[1] += wt * (A[3] * B[1] + A[1] * B[3] - A[2] * B[0] - A[0] * B[2]);
+        acc[2] += wt * (A[3] * B[2] + A[2] * B[3] - A[0] * B[1] - A[1] * B[0]);
+    }
 }
 
-static void integrand_t(const orc_eval *E, const orc_out *o, double w, double wt, double acc[2])
+/* e(m,n) of the XYZ t-channel vertex corrections and correlations. */
+static double xyz_sign(int m, int n) { return (m == 3 || n == 3 || m == n) ? 1.0 : -1.0; }
+
+static void integrand_t(const orc_eval *E, const orc_out *o, double w, double wt, double acc[4])
 {
     const orc_lattice *L = E->L;
     const int zero[3] = {0, 0, 0};
+    const int nc = L->nc;
     /* particle-hole RPA term: -sum_j Gamma_{i1 j} Gamma_{j i2}, j in range of both */
-    double rs = 0.0, rd = 0.0;
+    double r[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = 0; j < L->nsites[o->b]; ++j) {
         const int *cj = &L->cell[((long)o->b * L->ns + j) * 3];
         int bj = L->bas[(long)o->b * L->ns + j];
         int d2[3] = {o->dk[0] - cj[0], o->dk[1] - cj[1], o->dk[2] - cj[2]};
         if (site_of(L, bj, d2, o->bk) < 0) continue;
-        double as = vertex(L, E->x, 0, o->b, cj, bj, o->w1 + w, o->t, o->w1p - w);
-        double ad = vertex(L, E->x, 1, o->b, cj, bj, o->w1 + w, o->t, o->w1p - w);
-        double bs = vertex(L, E->x, 0, bj, d2, o->bk, w + o->w2p, o->t, w - o->w2);
-        double bd = vertex(L, E->x, 1, bj, d2, o->bk, w + o->w2p, o->t, w - o->w2);
-        rs += as * bs;
-        rd += ad * bd;
+        for (int c = 0; c < nc; ++c)
+            r[c] += vertex(L, E->x, c, o->b, cj, bj, o->w1 + w, o->t, o->w1p - w)
+                  * vertex(L, E->x, c, bj, d2, o->bk, w + o->w2p, o->t, w - o->w2);
     }
     /* vertex corrections with the on-site vertex at i2 and at i1 */
-    double As = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->w1 + w, o->t, o->w1p - w);
-    double Ad = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->w1 + w, o->t, o->w1p - w);
-    double O1s = vertex(L, E->x, 0, o->bk, zero, o->bk, o->w2p + w, o->w2 - w, -o->t);
-    double O1d = vertex(L, E->x, 1, o->bk, zero, o->bk, o->w2p + w, o->w2 - w, -o->t);
-    double O2s = vertex(L, E->x, 0, o->b, zero, o->b, o->w1 + w, w - o->w1p, -o->t);
-    double O2d = vertex(L, E->x, 1, o->b, zero, o->b, o->w1 + w, w - o->w1p, -o->t);
-    double Bs = vertex(L, E->x, 0, o->b, o->dk, o->bk, w + o->w2p, o->t, w - o->w2);
-    double Bd = vertex(L, E->x, 1, o->b, o->dk, o->bk, w + o->w2p, o->t, w - o->w2);
-    double gs = -2.0 * rs - As * O1s + As * O1d - O2s * Bs + O2d * Bs;
-    double gd = -2.0 * rd + 3.0 * Ad * O1s + Ad * O1d + 3.0 * O2s * Bd + O2d * Bd;
-    acc[0] += wt * gs;
-    acc[1] += wt * gd;
+    double A[4], O1[4], O2[4], B[4];
+    for (int c = 0; c < nc; ++c) {
+        A[c] = vertex(L, E->x, c, o->b, o->dk, o->bk, o->w1 + w, o->t, o->w1p - w);
+        O1[c] = vertex(L, E->x, c, o->bk, zero, o->bk, o->w2p + w, o->w2 - w, -o->t);
+        O2[c] = vertex(L, E->x, c, o->b, zero, o->b, o->w1 + w, w - o->w1p, -o->t);
+        B[c] = vertex(L, E->x, c, o->b, o->dk, o->bk, w + o->w2p, o->t, w - o->w2);
+    }
+    if (nc == 2) {
+        double gs = -2.0 * r[0] - A[0] * O1[0] + A[0] * O1[1] - O2[0] * B[0] + O2[1] * B[0];
+        double gd = -2.0 * r[1] + 3.0 * A[1] * O1[0] + A[1] * O1[1] + 3.0 * O2[0] * B[1] + O2[1] * B[1];
+        acc[0] += wt * gs;
+        acc[1] += wt * gd;
+    } else {
+        for (int m = 0; m < 4; ++m) {
+            double c1 = 0.0, c2 = 0.0;
+            for (int n = 0; n < 4; ++n) {
+                c1 += xyz_sign(m, n) * O1[n];
+                c2 += xyz_sign(m, n) * O2[n];
+            }
+            acc[m] += wt * (-2.0 * r[m] + A[m] * c1 + B[m] * c2);
+        }
+    }
 }
 
-static void integrand_u(const orc_eval *E, const orc_out *o, double w, double wt, double acc[2])
+static void integrand_u(const orc_eval *E, const orc_out *o, double w, double wt, double acc[4])
 {
     const orc_lattice *L = E->L;
-    double As = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->w1 + w, w - o->w2p, o->u);
-    double Ad = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->w1 + w, w - o->w2p, o->u);
-    double Bs = vertex(L, E->x, 0, o->b, o->dk, o->bk, o->w1p + w, o->w2 - w, o->u);
-    double Bd = vertex(L, E->x, 1, o->b, o->dk, o->bk, o->w1p + w, o->w2 - w, o->u);
-    acc[0] += wt * (2.0 * As * Bs + As * Bd + Ad * Bs);
-    acc[1] += wt * (3.0 * As * Bs + Ad * Bd);
+    double A[4], B[4];
+    for (int c = 0; c < L->nc; ++c) {
+        A[c] = vertex(L, E->x, c, o->b, o->dk, o->bk, o->w1 + w, w - o->w2p, o->u);
+        B[c] = vertex(L, E->x, c, o->b, o->dk, o->bk, o->w1p + w, o->w2 - w, o->u);
+    }
+    if (L->nc == 2) {
+        acc[0] += wt * (2.0 * A[0] * B[0] + A[0] * B[1] + A[1] * B[0]);
+        acc[1] += wt * (3.0 * A[0] * B[0] + A[1] * B[1]);
+    } else {
+        acc[3] += wt * (A[3] * B[3] + A[0] * B[0] + A[1] * B[1] + A[2] * B[2]);
+        acc[0] += wt * (A[3] * B[0] + A[0] * B[3] + A[1] * B[2] + A[2] * B[1]);
+        acc[1] += wt * (A[3] * B[1] + A[1] * B[3] + A[2] * B[0] + A[0] * B[2]);
+        acc[2] += wt * (A[3] * B[2] + A[2] * B[3] + A[0] * B[1] + A[1] * B[0]);
+    }
 }
 
-typedef void (*integrand_fn)(const orc_eval *, const orc_out *, double, double, double[2]);
+typedef void (*integrand_fn)(const orc_eval *, const orc_out *, double, double, double[4]);
 
 /*
  * One channel: (1/2pi) * integral of the bubble times the channel integrand.
  * partner(w) = ps * w + pc  (s: pc - w; t: w - t; u: u + w) and its zero c.
  */
 static void channel(const orc_eval *E, const orc_out *o, integrand_fn fn,
-                    double ps, double pc, double acc[2])
+                    double ps, double pc, double acc[4])
 {
     const orc_lattice *L = E->L;
     double lam = E->lam;
-    double loc[2] = {0.0, 0.0};
+    double loc[4] = {0.0, 0.0, 0.0, 0.0};
 
     /* delta parts (R1): the S in Skat(partner) and the S in Skat(w) */
     for (int sx = 0; sx < 2; ++sx) {
@@ -379,8 +436,7 @@ static void channel(const orc_eval *E, const orc_out *o, integrand_fn fn,
         }
     }
     free(nodes);
-    acc[0] += loc[0] / TWO_PI;
-    acc[1] += loc[1] / TWO_PI;
+    for (int c = 0; c < L->nc; ++c) acc[c] += loc[c] / TWO_PI;
 }
 
 /*
@@ -389,7 +445,7 @@ static void channel(const orc_eval *E, const orc_out *o, integrand_fn fn,
  * self-energy flow of the same state at the same Lambda (Katanin term).
  */
 void orc_vertex_rhs_element(const orc_lattice *L, double lam, const double *x, const double *dsig,
-                            int b, int k, int a, int it, int c, double out[2])
+                            int b, int k, int a, int it, int c, double *out)
 {
     orc_eval E = {L, x, dsig, lam};
     orc_out o;
@@ -402,12 +458,11 @@ void orc_vertex_rhs_element(const orc_lattice *L, double lam, const double *x, c
     o.w2p = 0.5 * (o.s - o.t - o.u);
     o.w1 = 0.5 * (o.s - o.t + o.u);
     o.w2 = 0.5 * (o.s + o.t - o.u);
-    double acc[2] = {0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     channel(&E, &o, integrand_s, -1.0, o.s, acc);   /* partner s - w */
     channel(&E, &o, integrand_t, 1.0, -o.t, acc);   /* partner w - t */
     channel(&E, &o, integrand_u, 1.0, o.u, acc);    /* partner u + w */
-    out[0] = acc[0];
-    out[1] = acc[1];
+    for (int comp = 0; comp < L->nc; ++comp) out[comp] = acc[comp];
 }
 
 /* Full right-hand side: sigma flow, then every vertex element. */
@@ -430,17 +485,16 @@ void orc_rhs(const orc_lattice *L, double lam, const double *x, double *dx, int 
         while (su_index(a + 1, 0) <= su) ++a;
         int c = su - (int)su_index(a, 0);
         for (int k = 0; k < L->nsites[b]; ++k) {
-            double out[2];
+            double out[4];
             orc_vertex_rhs_element(L, lam, x, dsig, b, k, a, it, c, out);
-            dx[vidx(L, 0, b, a, it, c, k)] = out[0];
-            dx[vidx(L, 1, b, a, it, c, k)] = out[1];
+            for (int comp = 0; comp < L->nc; ++comp) dx[vidx(L, comp, b, a, it, c, k)] = out[comp];
         }
     }
 }
 
 /*
  * Every vertex element of a list of frequency triples (all basis sites and
- * listed sites), written to out[q][b][k][2].  Used for sampled comparisons
+ * listed sites), written to out[q][b][k][nc].  Used for sampled comparisons
  * and for the CPU baseline timing.
  */
 void orc_vertex_rhs_triples(const orc_lattice *L, double lam, const double *x, const double *dsig,
@@ -455,20 +509,22 @@ void orc_vertex_rhs_triples(const orc_lattice *L, double lam, const double *x, c
         for (int b = 0; b < L->nb; ++b)
             for (int k = 0; k < L->nsites[b]; ++k)
                 orc_vertex_rhs_element(L, lam, x, dsig, b, k, a_list[q], t_list[q], c_list[q],
-                                       &out[(((long)q * L->nb + b) * L->ns + k) * 2]);
+                                       &out[(((long)q * L->nb + b) * L->ns + k) * L->nc]);
 }
 
 /* ------------------------------------------------------- correlations -- */
 
 /*
- * chi^{zz}_{bk} and chi^{00}_{bk} (Eq. 30 contracted with Eq. 25, R5):
- *   chi^zz = d_ij (1/4pi) I g^2 - (1/16pi^2) II g1^2 g2^2
- *            [4 Gs_ij(w1+w2, 0, w1-w2) + d_ij (2Gs_ii - 2Gd_ii)(w1+w2, w2-w1, 0)]
- *   chi^00 = d_ij (1/4pi) I g^2 - (1/16pi^2) II g1^2 g2^2
- *            [4 Gd_ij(w1+w2, 0, w1-w2) - d_ij (6Gs_ii + 2Gd_ii)(w1+w2, w2-w1, 0)]
- * with g = 1/(w - sig(w)) on |w| >= Lambda (G^2 = -g^2).
+ * Two-spin correlations (Eq. 30 contracted with Eq. 25, R5), one per strain:
+ *   chi^m_ij = d_ij (1/4pi) I g^2 - (1/16pi^2) II g1^2 g2^2
+ *              [4 G^m_ij(w1+w2, 0, w1-w2) + d_ij X^m(w1+w2, w2-w1, 0)]
+ * with g = 1/(w - sig(w)) on |w| >= Lambda (G^2 = -g^2) and the on-site
+ * exchange term
+ *   SU(2): X^zz = 2 Gs_ii - 2 Gd_ii,  X^00 = -(6 Gs_ii + 2 Gd_ii);
+ *   XYZ:   X^m = -2 sum_n e(m,n) G^n_ii (e as in the t channel).
+ * out[m][b][k] for every strain m (SU(2): zz, 00; XYZ: xx, yy, zz, 00).
  */
-void orc_chi(const orc_lattice *L, double lam, const double *x, double *chi_zz, double *chi_dd)
+void orc_chi_comps(const orc_lattice *L, double lam, const double *x, double *out)
 {
     orc_eval E = {L, x, NULL, lam};
     double wmax = L->w[L->nf - 1];
@@ -497,33 +553,51 @@ void orc_chi(const orc_lattice *L, double lam, const double *x, double *chi_zz, 
     bubble /= 2.0 * TWO_PI;
     const double pref = 1.0 / (4.0 * TWO_PI * TWO_PI);   /* 1/(16 pi^2) */
     const int zero[3] = {0, 0, 0};
+    const int nc = L->nc;
+    const long plane = (long)L->nb * L->ns;
     for (int b = 0; b < L->nb; ++b)
         for (int k = 0; k < L->nsites[b]; ++k) {
             const int *ck = &L->cell[((long)b * L->ns + k) * 3];
             int bk = L->bas[(long)b * L->ns + k];
             int onsite = (k == 0);
-            double zz = 0.0, dd = 0.0;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < n; ++j) {
                     double w1 = nw[i], w2 = nw[j];
                     double f = ww[i] * ww[j] * g2[i] * g2[j];
-                    double ds = vertex(L, x, 0, b, ck, bk, w1 + w2, 0.0, w1 - w2);
-                    double dd_ = vertex(L, x, 1, b, ck, bk, w1 + w2, 0.0, w1 - w2);
-                    double tz = 4.0 * ds, td = 4.0 * dd_;
+                    double t[4] = {0.0, 0.0, 0.0, 0.0}, e[4] = {0.0, 0.0, 0.0, 0.0};
+                    for (int m = 0; m < nc; ++m) t[m] = 4.0 * vertex(L, x, m, b, ck, bk, w1 + w2, 0.0, w1 - w2);
                     if (onsite) {
-                        double es = vertex(L, x, 0, b, zero, b, w1 + w2, w2 - w1, 0.0);
-                        double ed = vertex(L, x, 1, b, zero, b, w1 + w2, w2 - w1, 0.0);
-                        tz += 2.0 * es - 2.0 * ed;
-                        td -= 6.0 * es + 2.0 * ed;
+                        for (int m = 0; m < nc; ++m) e[m] = vertex(L, x, m, b, zero, b, w1 + w2, w2 - w1, 0.0);
+                        if (nc == 2) {
+                            t[0] += 2.0 * e[0] - 2.0 * e[1];
+                            t[1] -= 6.0 * e[0] + 2.0 * e[1];
+                        } else {
+                            for (int m = 0; m < 4; ++m) {
+                                double xm = 0.0;
+                                for (int q = 0; q < 4; ++q) xm += xyz_sign(m, q) * e[q];
+                                t[m] += -2.0 * xm;
+                            }
+                        }
                     }
-                    zz += f * tz;
-                    dd += f * td;
+                    for (int m = 0; m < nc; ++m) acc[m] += f * t[m];
                 }
-            zz *= -pref;
-            dd *= -pref;
-            if (onsite) { zz += bubble; dd += bubble; }
-            chi_zz[(long)b * L->ns + k] = zz;
-            chi_dd[(long)b * L->ns + k] = dd;
+            for (int m = 0; m < nc; ++m) {
+                double v = -pref * acc[m];
+                if (onsite) v += bubble;
+                out[m * plane + (long)b * L->ns + k] = v;
+            }
         }
     free(nw); free(ww); free(g2); free(tmp);
+}
+
+/* SU(2): chi^{zz} and chi^{00} of every (basis, site) element (orc_chi_comps). */
+void orc_chi(const orc_lattice *L, double lam, const double *x, double *chi_zz, double *chi_dd)
+{
+    const long plane = (long)L->nb * L->ns;
+    double *both = (double *)malloc(sizeof(double) * 2 * plane);
+    orc_chi_comps(L, lam, x, both);
+    memcpy(chi_zz, both, sizeof(double) * plane);
+    memcpy(chi_dd, both + plane, sizeof(double) * plane);
+    free(both);
 }

@@ -77,10 +77,13 @@ class UnreducedLattice:
             for k in range(self.nsites[b]):
                 self.site_pos[b, k] = cell.position(self.cell[b, k], self.bas[b, k])
 
-        # couplings J_{(0,b),(c,b')}: each listed interaction and its reverse
-        self.coupling = np.zeros((nb, ns))
+        # couplings J_{(0,b),(c,b')}: each listed interaction and its reverse;
+        # a Heisenberg model gives one number per site, an XYZ model (params
+        # (Jx, Jy, Jz)) three: coupling[nb, ns, 3]
+        vec = any(np.ndim(v) == 1 for v in model.params.values())
+        self.coupling = np.zeros((nb, ns, 3) if vec else (nb, ns))
         for (pname, f, t, d0, d1, d2) in model.interactions:
-            J = float(model.params.get(pname, 0.0))
+            J = np.asarray(model.params.get(pname, (0.0, 0.0, 0.0) if vec else 0.0), dtype=np.float64)
             for (b1, d, b2) in ((f, (d0, d1, d2), t), (t, (-d0, -d1, -d2), f)):
                 k = self.index(b1, d, b2)
                 if k >= 0:

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "UnitCell", "Model", "UNIT_CELLS", "unit_cell", "model",
+    "UnitCell", "Model", "UNIT_CELLS", "unit_cell", "model", "model_xyz",
     "log_mesh", "exponential_schedule", "geometric_schedule",
     "Workload", "workload", "WORKLOAD_NAMES", "batch_scan_points",
     "random_state", "state_layout",
@@ -108,12 +108,14 @@ def unit_cell(name: str) -> UnitCell:
 
 @dataclass(frozen=True)
 class Model:
-    """Heisenberg couplings on a unit cell (Sec. 5.3).
+    """Spin couplings on a unit cell (Sec. 5.3).
 
     ``interactions`` lists (param, b_from, b_to, da0, da1, da2); the value of
-    each named parameter is in ``params``.  The Hamiltonian is the sum of
-    J * S_from . S_to over every listed bond and all lattice translations, each
-    unordered bond counted once.
+    each named parameter is in ``params``.  A number J is a Heisenberg
+    coupling, J S_from . S_to; a triple (Jx, Jy, Jz) an XYZ coupling,
+    Jx S^x S^x + Jy S^y S^y + Jz S^z S^z (Sec. 2).  The Hamiltonian is the sum
+    over every listed bond and all lattice translations, each unordered bond
+    counted once.
     """
     name: str
     cell: UnitCell
@@ -124,6 +126,11 @@ class Model:
         p = dict(self.params)
         p.update(kw)
         return Model(self.name, self.cell, self.interactions, p)
+
+    @property
+    def symmetry(self) -> str:
+        """'xyz' when the couplings are (Jx, Jy, Jz) triples, else 'su2'."""
+        return "xyz" if any(np.ndim(v) == 1 for v in self.params.values()) else "su2"
 
 
 # Coupling shells by Euclidean distance: (parameter name, distance).
@@ -148,6 +155,21 @@ def model(lattice: str, **params) -> Model:
     if unknown:
         raise ValueError(f"unknown couplings {sorted(unknown)} for {lattice}")
     return Model(f"{lattice}-heisenberg", cell, tuple(inter), full)
+
+
+def model_xyz(lattice: str, **params) -> Model:
+    """XYZ model on ``lattice`` with shell couplings j1=(Jx, Jy, Jz), ...
+    (the same bonds as ``model``; unnamed shells are (0, 0, 0))."""
+    base = model(lattice)
+    full = {name: (0.0, 0.0, 0.0) for name in base.params}
+    for k, v in params.items():
+        if k not in full:
+            raise ValueError(f"unknown coupling {k} for {lattice}")
+        v = tuple(float(x) for x in v)
+        if len(v) != 3:
+            raise ValueError(f"{k}: an XYZ coupling is a triple (Jx, Jy, Jz)")
+        full[k] = v
+    return Model(f"{lattice}-xyz", base.cell, base.interactions, full)
 
 
 # ---------------------------------------------------------------- meshes ---
