@@ -207,6 +207,29 @@ pffrg_status pffrg_chi(pffrg_ctx *ctx, double lambda, const double *d_state, dou
 pffrg_status pffrg_chi_k(pffrg_ctx *ctx, const double *d_chi, int n_k, const double *d_k,
                          double *d_chi_k);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * correlations as pffrg_chi, d_chi[0*Ns + p] = chi^{zz}, d_chi[1*Ns + p] =
+ * chi^{00}, with no context and no allocation.  The caller passes the mesh
+ * d_omega[n_freq] (device, positive, strictly ascending, as for
+ * pffrg_create), the pair exchange table d_swap[n_pairs] (device, entries in
+ * [0, n_pairs), as pffrg_lattice.swap), the state (layout above) and the
+ * output; work is enqueued on `stream` (a hipStream_t of the current device,
+ * or NULL).  Device inputs are not read on the host, so their contents are
+ * not checked.  The kernels' scratch (node lists and partial integrals,
+ * PFFRG_NOALLOC_SCRATCH_BYTES) is a fixed device array that each device holds
+ * until the process ends; its address is looked up on the first call with a
+ * device current.  All calls on one device share it: calls that overlap on
+ * one device race and must be ordered by the caller.  More than
+ * PFFRG_NOALLOC_MAX_FREQ frequencies or PFFRG_NOALLOC_MAX_PAIRS pairs give
+ * PFFRG_EUNSUPPORTED; a null pointer, n_freq < 2, n_pairs < 1 or a lambda
+ * that is not finite and > 0 give PFFRG_EINVAL.  Asynchronous. */
+#define PFFRG_NOALLOC_MAX_FREQ 128
+#define PFFRG_NOALLOC_MAX_PAIRS 32
+#define PFFRG_NOALLOC_SCRATCH_BYTES 14448
+pffrg_status pffrg_chi_noalloc(int n_freq, const double *d_omega, int n_pairs, const int *d_swap, double lambda,
+                               const double *d_state, double *d_chi, void *stream);
+
 /* -------------------------------------------------------- reverse mode - */
 
 /*

@@ -54,6 +54,7 @@ SIGNATURES = {
     "pffrg_flow_position": [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I)],
     "pffrg_chi": [P, D, P, P],
     "pffrg_chi_k": [P, P, I, P, P],
+    "pffrg_chi_noalloc": [I, P, I, P, D, P, P, P],
     "pffrg_measure_peaks": [P, P],
     "pffrg_set_profiling": [P, I],
     "pffrg_set_profiling_mask": [P, ctypes.c_uint],

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("pffrg.hip", "pffrg_batch.hip", "pffrg_peaks.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("pffrg.hip", "pffrg_batch.hip", "pffrg_peaks.hip", "pffrg_noalloc.hip")]
 LIB = os.path.join(HERE, "libpffrg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

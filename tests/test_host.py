@@ -218,3 +218,22 @@ def test_batch_create_rejects_bad_inputs_before_touching_the_gpu():
     assert lib.pffrg_batch_create(1, arr, ctypes.byref(msh2), _lib.FP64, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.pffrg_batch_create(1, arr, ctypes.byref(msh), 7, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.pffrg_batch_rhs(None, 1.0, None, None) == _lib.EINVAL
+
+
+def test_chi_noalloc_rejects_bad_arguments_before_any_hip_call():
+    """Argument checks of the no-allocation entry point run on the host before
+    the device is touched (the fake device pointers are never dereferenced)."""
+    from paper_2109_13317_amd import _lib
+    lib = _lib.load()
+    fake = ctypes.c_void_p(256)
+    cases = [((2, None, 1, fake, 0.5, fake, fake, None), _lib.EINVAL),
+             ((2, fake, 1, fake, 0.5, fake, None, None), _lib.EINVAL),
+             ((1, fake, 1, fake, 0.5, fake, fake, None), _lib.EINVAL),
+             ((4, fake, 0, fake, 0.5, fake, fake, None), _lib.EINVAL),
+             ((4, fake, 2, fake, 0.0, fake, fake, None), _lib.EINVAL),
+             ((4, fake, 2, fake, float("inf"), fake, fake, None), _lib.EINVAL),
+             ((129, fake, 2, fake, 0.5, fake, fake, None), _lib.EUNSUPPORTED),
+             ((8, fake, 33, fake, 0.5, fake, fake, None), _lib.EUNSUPPORTED)]
+    for args, want in cases:
+        assert lib.pffrg_chi_noalloc(*args) == want, args
+        assert lib.pffrg_last_error()
