@@ -24,24 +24,25 @@ def pair_map(orc, tables) -> np.ndarray:
     return pmap
 
 
-def _reduced_views(x, nf, ns):
+def _reduced_views(x, nf, ns, nc=2):
+    """(sig, strain 0, ..., strain nc-1) of a reduced state, strains [n_su, nf, ns]."""
     n_su = nf * (nf + 1) // 2
     v = n_su * nf * ns
-    return x[:nf], x[nf:nf + v].reshape(n_su, nf, ns), x[nf + v:nf + 2 * v].reshape(n_su, nf, ns)
+    return (x[:nf],) + tuple(x[nf + c * v:nf + (c + 1) * v].reshape(n_su, nf, ns) for c in range(nc))
 
 
 def expand_state(orc, tables, x_red: np.ndarray) -> np.ndarray:
     """Oracle-layout state holding the same values as a reduced state."""
     pmap = pair_map(orc, tables)
     nf, ns = orc.nf, tables.n_pairs
-    sig, gs, gd = _reduced_views(np.asarray(x_red), nf, ns)
+    red = _reduced_views(np.asarray(x_red), nf, ns, orc.nc)
     out = orc.initial_state() * 0.0
-    osig, ogs, ogd = orc.split(out)
-    osig[:] = sig
+    parts = orc.split(out)
+    parts[0][:] = red[0]
     for b in range(orc.lat.nb):
         n = orc.lat.nsites[b]
-        ogs[b, :, :, :n] = gs[:, :, pmap[b, :n]]
-        ogd[b, :, :, :n] = gd[:, :, pmap[b, :n]]
+        for c in range(1, orc.nc + 1):
+            parts[c][b, :, :, :n] = red[c][:, :, pmap[b, :n]]
     return out
 
 
@@ -50,44 +51,51 @@ def compare_vertex(orc, tables, ref: np.ndarray, red: np.ndarray) -> float:
     element of every (basis, site) of the oracle."""
     pmap = pair_map(orc, tables)
     nf, ns = orc.nf, tables.n_pairs
-    sig, gs, gd = _reduced_views(np.asarray(red), nf, ns)
-    rsig, rgs, rgd = orc.split(ref)
-    err = np.abs(rsig - sig).max()
-    scale = max(np.abs(rsig).max(), np.abs(rgs).max(), np.abs(rgd).max(), 1e-300)
+    got = _reduced_views(np.asarray(red), nf, ns, orc.nc)
+    exp = orc.split(ref)
+    err = np.abs(exp[0] - got[0]).max()
+    scale = max(max(np.abs(e).max() for e in exp), 1e-300)
     for b in range(orc.lat.nb):
         n = orc.lat.nsites[b]
-        err = max(err, np.abs(rgs[b, :, :, :n] - gs[:, :, pmap[b, :n]]).max(),
-                  np.abs(rgd[b, :, :, :n] - gd[:, :, pmap[b, :n]]).max())
+        for c in range(1, orc.nc + 1):
+            err = max(err, np.abs(exp[c][b, :, :, :n] - got[c][:, :, pmap[b, :n]]).max())
     return float(err / scale)
 
 
 def compare_triples(orc, tables, triples, ref_tr: np.ndarray, red: np.ndarray) -> float:
-    """Like compare_vertex for the oracle's per-triple output [nq, nb, ns, 2]."""
+    """Like compare_vertex for the oracle's per-triple output [nq, nb, ns, strains]."""
     pmap = pair_map(orc, tables)
     nf, ns = orc.nf, tables.n_pairs
-    _, gs, gd = _reduced_views(np.asarray(red), nf, ns)
+    got = _reduced_views(np.asarray(red), nf, ns, orc.nc)
     err, scale = 0.0, 1e-300
     for q, (a, t, c) in enumerate(triples):
         su = a * (a + 1) // 2 + c
         for b in range(orc.lat.nb):
             n = orc.lat.nsites[b]
             r = ref_tr[q, b, :n]
-            err = max(err, np.abs(r[:, 0] - gs[su, t, pmap[b, :n]]).max(),
-                      np.abs(r[:, 1] - gd[su, t, pmap[b, :n]]).max())
+            for m in range(orc.nc):
+                err = max(err, np.abs(r[:, m] - got[1 + m][su, t, pmap[b, :n]]).max())
             scale = max(scale, np.abs(r).max())
     return float(err / scale)
 
 
-def compare_chi(orc, tables, zz, dd, chi_red: np.ndarray) -> float:
+def compare_chi_comps(orc, tables, chi_unred: np.ndarray, chi_red: np.ndarray) -> float:
+    """chi per strain: the oracle's [strains, nb, ns] against the library's
+    [strains, n_pairs], relative to max |oracle|."""
     pmap = pair_map(orc, tables)
-    chi_red = np.asarray(chi_red).reshape(2, -1)
+    chi_red = np.asarray(chi_red).reshape(orc.nc, -1)
     err, scale = 0.0, 1e-300
     for b in range(orc.lat.nb):
         n = orc.lat.nsites[b]
-        err = max(err, np.abs(zz[b, :n] - chi_red[0, pmap[b, :n]]).max(),
-                  np.abs(dd[b, :n] - chi_red[1, pmap[b, :n]]).max())
-        scale = max(scale, np.abs(zz[b, :n]).max(), np.abs(dd[b, :n]).max())
+        for m in range(orc.nc):
+            err = max(err, np.abs(chi_unred[m, b, :n] - chi_red[m, pmap[b, :n]]).max())
+            scale = max(scale, np.abs(chi_unred[m, b, :n]).max())
     return float(err / scale)
+
+
+def compare_chi(orc, tables, zz, dd, chi_red: np.ndarray) -> float:
+    """SU(2): chi^zz and chi^00 (compare_chi_comps with the two strains)."""
+    return compare_chi_comps(orc, tables, np.stack([zz, dd]), chi_red)
 
 
 def compare_parts(orc, tables, ref: np.ndarray, red: np.ndarray) -> tuple[float, float]:
@@ -95,14 +103,14 @@ def compare_parts(orc, tables, ref: np.ndarray, red: np.ndarray) -> tuple[float,
     of a state or derivative measured on their own scales."""
     pmap = pair_map(orc, tables)
     nf, ns = orc.nf, tables.n_pairs
-    sig, gs, gd = _reduced_views(np.asarray(red), nf, ns)
-    rsig, rgs, rgd = orc.split(ref)
-    es = np.abs(rsig - sig).max() / max(np.abs(rsig).max(), 1e-300)
-    ev, scale = 0.0, max(np.abs(rgs).max(), np.abs(rgd).max(), 1e-300)
+    got = _reduced_views(np.asarray(red), nf, ns, orc.nc)
+    exp = orc.split(ref)
+    es = np.abs(exp[0] - got[0]).max() / max(np.abs(exp[0]).max(), 1e-300)
+    ev, scale = 0.0, max(max(np.abs(e).max() for e in exp[1:]), 1e-300)
     for b in range(orc.lat.nb):
         n = orc.lat.nsites[b]
-        ev = max(ev, np.abs(rgs[b, :, :, :n] - gs[:, :, pmap[b, :n]]).max(),
-                 np.abs(rgd[b, :, :, :n] - gd[:, :, pmap[b, :n]]).max())
+        for c in range(1, orc.nc + 1):
+            ev = max(ev, np.abs(exp[c][b, :, :, :n] - got[c][:, :, pmap[b, :n]]).max())
     return float(es), float(ev / scale)
 
 
@@ -117,12 +125,12 @@ def restrict_state(orc, tables, x_unred: np.ndarray) -> np.ndarray:
         for k in range(orc.lat.nsites[b]):
             rep.setdefault(int(pmap[b, k]), (b, k))
     assert len(rep) == ns
-    sig, gs, gd = orc.split(np.asarray(x_unred))
+    src = orc.split(np.asarray(x_unred))
     n_su = nf * (nf + 1) // 2
-    out = np.zeros(nf + 2 * n_su * nf * ns)
-    osig, ogs, ogd = _reduced_views(out, nf, ns)
-    osig[:] = sig
+    out = np.zeros(nf + orc.nc * n_su * nf * ns)
+    dst = _reduced_views(out, nf, ns, orc.nc)
+    dst[0][:] = src[0]
     for p, (b, k) in rep.items():
-        ogs[:, :, p] = gs[b, :, :, k]
-        ogd[:, :, p] = gd[b, :, :, k]
+        for c in range(1, orc.nc + 1):
+            dst[c][:, :, p] = src[c][b, :, :, k]
     return out
