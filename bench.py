@@ -1,27 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the SU(2) pf-FRG flow hot path on one MI355X.
 
-Workload: square-lattice J1-J2 Heisenberg model, J2/J1 = 0.5, vertex range 7
-bonds (20 symmetry-reduced pairs, 113 sites in range), 32 positive Matsubara
-frequencies log-spaced 1e-3..100, FP64.  Synthetic input: the flow state is
-the physical flow from the initial condition (Lambda 100 -> 1 in 40 RK4
-steps, untimed setup); no datasets or trained weights are involved.
+Headline workload: pyrochlore nearest-neighbour Heisenberg model (fcc lattice
+with the four-site tetrahedral basis), vertex range 5 bonds (31
+symmetry-reduced pairs, 277 sites in range), 48 positive Matsubara
+frequencies log-spaced 1e-3..100, FP64: the largest FP64 configuration of the
+benchmark set on one GPU (3.5 M vertex elements, 28 MB state).  Synthetic
+input: the flow state is the physical flow from the initial condition
+(Lambda 100 -> 1 in 40 RK4 steps, untimed setup); no datasets or trained
+weights are involved.
 
 One timed step = one pass of the whole hot path: a classical RK4 step
 (4 self-energy + 4 vertex right-hand sides and the stage combinations) from
-Lambda to 0.95 Lambda, then chi per pair and chi(k) on a 64x64 k-grid.
+Lambda to 0.95 Lambda, then chi per pair and chi(k) on 16^3 k-points.
 `value` = vertex-RHS elements per second = 4 * E / step time, with
-E = 2 * pairs * triples = 675,840 vertex elements per right-hand side.
+E = 2 * pairs * triples vertex elements per right-hand side.
 
 Also reported: the dominant kernel's roofline position (algorithmic FP64
-flops per launch over its HIP-event duration), the whole adaptive flow
-(Dormand-Prince 5(4), Lambda 100 -> 0.01, chi(k) every accepted step), the
-CPU oracle timed on a bounded sample of the same workload, and three more
-measurements: the same right-hand side in FP32 mode (fp32_mode), a 64-point
-phase scan advanced as one batch against 64 sequential FP64 flows
-(batch_scan), d chi(k_peak)/dJ through a 120-step flow by the discrete
-adjoint against the forward cost (adjoint), and the vertex right-hand side's
-growth with the frequency and pair counts (scaling_shape).  paper_context
+flops per launch over its HIP-event duration), the whole flows of the
+headline workload (fixed RK4 on the exponential schedule b = 0.95, and the
+adaptive Dormand-Prince 5(4) flow with chi(k) every accepted step), the CPU
+oracle timed on a bounded sample of the same workload, and, as extras, the
+square J1-J2 workload's hot path and adaptive flow (range 7, 32
+frequencies), the FP32 mode, a 64-point phase scan advanced as one batch
+against 64 sequential FP64 flows, d chi(k_peak)/dJ through a 120-step flow
+by the discrete adjoint against the forward cost, and the growth of the
+vertex right-hand side with the frequency and pair counts.  paper_context
 quotes the only throughput the paper allows to derive (a CPU node, another
 workload): context, not a baseline.
 """
@@ -47,10 +51,10 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per k_vertex_stu launch from the two rocprofv3 --pmc runs
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, copy-kernel calibrated), keyed by
-# the hash of the kernel sources they were taken on; a changed kernel reports
-# traffic null until the counters are taken again.
+# the hash of the kernel sources they were taken on and the workload; a
+# changed kernel reports traffic null until the counters are taken again.
 MEASURED_TRAFFIC = {
-    "a8535505e0deef2b": 27.70e6,
+    ("a8535505e0deef2b", "square_j1j2"): 27.70e6,
 }
 
 
@@ -150,6 +154,49 @@ def vertex_flops(mesh: np.ndarray, lam: float, ns: int, n_terms: int) -> dict:
                 out["t"] += 52.0 * ns * nt + 4.0 * ns * ns * nt + 32.0 * nt + 4.0 * n_terms
     out["all"] = out["s"] + out["u"] + out["t"]
     return out
+
+
+def xyz_vertex_flops(mesh: np.ndarray, lam: float, ns: int, n_terms: int) -> float:
+    """Algorithmic FP64 flops of one XYZ vertex right-hand side at cutoff lam
+    (four strains).  Per triple and evaluation point:
+      s and u: 100 flops per pair (two interpolated vectors, 4 strains x 4
+      corners FMA = 32 flops each, and 36 flops of channel products);
+      t: 148 flops per pair (the two vectors, the two vertex corrections of
+      every strain with their 4-term sign sums, the weighted site vector),
+      64 flops for the two on-site vertices, 8 ns^2 for the four lattice-sum
+      matrices (GEMM form), and 8 flops per tabulated term."""
+    nc = node_counts(mesh, lam)
+    nf = len(mesh)
+    tot = 0.0
+    for a in range(nf):
+        for c in range(a + 1):
+            for t in range(nf):
+                tot += 100.0 * ns * (nc[0, a] + nc[2, c])
+                nt = nc[1, t]
+                tot += 148.0 * ns * nt + 8.0 * ns * ns * nt + 64.0 * nt + 8.0 * n_terms
+    return tot
+
+
+def gather_instructions(mesh: np.ndarray, lam: float, ns: int) -> float:
+    """Wave-level 16-byte vertex gathers of one FP64 vertex right-hand side
+    (counting only): lanes cover G = 64 // ns evaluation points of one triple
+    at once, each point reads the four corners of two interpolated vectors;
+    the t channel takes its points in sub-chunks of 4 (8 at 17-20 pairs) and
+    reads the two on-site vertices (four corners each) once per 16 points."""
+    nc = node_counts(mesh, lam)
+    nf = len(mesh)
+    G = max(1, 64 // ns)
+    sub = 8 if 16 < ns <= 20 else 4
+    tot = 0.0
+    for a in range(nf):
+        for c in range(a + 1):
+            for t in range(nf):
+                tot += 8 * math.ceil(nc[0, a] / G) + 8 * math.ceil(nc[2, c] / G)
+                nt = int(nc[1, t])
+                full, rest = divmod(nt, sub)
+                tot += 8 * (full * math.ceil(sub / G) + (math.ceil(rest / G) if rest else 0))
+                tot += 4 * math.ceil(nt / 16)
+    return tot
 
 
 def kgrid(n: int) -> np.ndarray:
@@ -330,56 +377,52 @@ def adjoint_leg():
                          "max_rel_err": float(np.abs(grad - fd).max() / np.abs(fd).max())}}
 
 
-def pyrochlore_leg(reps=10):
-    """Pyrochlore nearest-neighbour Heisenberg, range 5 (31 pairs), 48 log
-    frequencies 1e-3..100: one FP64 right-hand side at Lambda = 1 on the flowed
-    state (HIP events around the vertex launches), and the whole fixed RK4
-    flow 100 -> 0.01 on the exponential schedule b = 0.95 with chi at the end."""
+def xyz_leg(reps=10):
+    """XYZ flow (Sec. 2, diagonal vertex components): honeycomb J1-J2-J3 with
+    (Jx, Jy, Jz) couplings per shell, range 6 (14 pairs), 32 log frequencies
+    1e-3..100: one right-hand side at Lambda = 0.5 on the flowed state (HIP
+    events around the vertex launches) and the RK4 flow 100 -> 0.1 in 120
+    steps, beside the SU(2) flow of the same lattice and mesh."""
     import torch
     from paper_2109_13317_amd import build_tables
     from paper_2109_13317_amd.flow import Context
-    wl = W.workload("pyrochlore")
-    ctx = Context(build_tables(wl.model(), wl.range), wl.mesh)
-    nf, ns = ctx.nf, ctx.ns
-    E = 2 * ns * nf * nf * (nf + 1) // 2
-    sched = list(wl.schedule)
-    x = ctx.init_state()
-    ctx.flow(x, schedule=[l for l in sched if l >= 1.0], scheme="rk4")
-    lam = [l for l in sched if l >= 1.0][-1]
-    out = ctx.new_state()
-    ctx.rhs(lam, x, out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ctx.rhs(lam, x, out)
-    torch.cuda.synchronize()
-    t_rhs = (time.perf_counter() - t0) / reps
-    ctx.set_profiling(True, kernels=("vertex",))
-    for _ in range(reps):
-        ctx.rhs(lam, x, out)
-    vms, vn = ctx.profile_read("vertex")
-    ctx.set_profiling(True, kernels=("vertex_t",))      # the t channel as its own launch
-    for _ in range(reps):
-        ctx.rhs(lam, x, out)
-    tms, tn = ctx.profile_read("vertex_t")
-    ctx.set_profiling(False)
-    from paper_2109_13317_amd._lib import PffrgError
-    xf = ctx.init_state()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    try:
+    model = W.model_xyz("honeycomb", j1=(0.9, 0.7, 0.5), j2=(0.3, 0.2, 0.25), j3=(0.1, 0.15, 0.3))
+    mesh = W.log_mesh(1e-3, 100.0, 32)
+    tables = build_tables(model, 6)
+    sched = W.geometric_schedule(100.0, 0.1, 120)
+    res = {"workload": "XYZ honeycomb J1-J2-J3, J1 = (0.9, 0.7, 0.5), J2 = (0.3, 0.2, 0.25), J3 = (0.1, 0.15, "
+                       "0.3), range 6 (14 pairs), 32 log freqs 1e-3..100; RK4 100 -> 0.1 in 120 steps"}
+    for sym, tab in (("xyz", tables), ("su2", build_tables(W.model("honeycomb", j1=0.9, j2=0.3, j3=0.1), 6))):
+        ctx = Context(tab, mesh)
+        x = ctx.init_state()
+        ctx.flow(x, schedule=[l for l in sched if l >= 0.5], scheme="rk4")
+        out = ctx.new_state()
+        ctx.rhs(0.5, x, out)
+        ctx.set_profiling(True, kernels=("vertex",))
+        for _ in range(reps):
+            ctx.rhs(0.5, x, out)
+        ms, n = ctx.profile_read("vertex")
+        ctx.set_profiling(False)
+        xf = ctx.init_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         ctx.flow(xf, schedule=sched, scheme="rk4")
-        chi0 = float(ctx.chi(sched[-1], xf).reshape(-1)[0].cpu())
-    except PffrgError as e:              # a flow that leaves the finite range stops there
-        chi0 = f"flow stopped: {e}"
-    torch.cuda.synchronize()
-    t_flow = time.perf_counter() - t0
-    return {"workload": "pyrochlore NN J=1, range 5 (31 pairs), 48 log freqs 1e-3..100; RK4 100 -> 0.01, "
-                        "b = 0.95 (180 steps)",
-            "vertex_elements": E, "rhs_ms": t_rhs * 1e3, "rhs_elements_per_s": E / t_rhs,
-            "vertex_rhs_ms_events": vms / max(vn, 1), "vertex_t_ms_events": tms / max(tn, 1),
-            "rhs_lambda": lam, "flow_seconds": t_flow, "flow_steps": len(sched) - 1,
-            "chi_zz_onsite_final": chi0}
+        torch.cuda.synchronize()
+        t_flow = time.perf_counter() - t0
+        E = ctx.nc * ctx.ns * ctx.nf * ctx.nf * (ctx.nf + 1) // 2
+        r = {"vertex_rhs_ms": ms / n, "vertex_elements": E, "elements_per_s": E / (ms / n * 1e-3),
+             "flow_seconds": t_flow}
+        if sym == "xyz":
+            fl = xyz_vertex_flops(mesh, 0.5, ctx.ns, tab.n_terms)
+            r.update({"flops": fl, "tflops": fl / (ms / n * 1e-3) / 1e12,
+                      "frac_of_fp64_peak": fl / (ms / n * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS})
+        res[sym] = r
+        ctx.close()
+    res["xyz_over_su2_rhs_time"] = res["xyz"]["vertex_rhs_ms"] / res["su2"]["vertex_rhs_ms"]
+    log(f"XYZ: vertex RHS {res['xyz']['vertex_rhs_ms']:.3f} ms ({res['xyz']['tflops']:.2f} TFLOP/s), SU(2) "
+        f"{res['su2']['vertex_rhs_ms']:.3f} ms; flows {res['xyz']['flow_seconds']:.3f} / "
+        f"{res['su2']['flow_seconds']:.3f} s")
+    return res
 
 
 def scaling_leg(lam=0.7, reps=5):
@@ -528,44 +571,48 @@ def _tiny_flows(threads):
             "cores": threads, "gpu_seconds": t_gpu, "max_rel_state_diff": err}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-full-flow", action="store_true")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32, batched-scan and adjoint measurements")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a 256 MiB device copy (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the flow engine runs on a single MI355X "
-              "(sharding across GPUs is not implemented)", file=sys.stderr)
-        sys.exit(2)
+def kgrid3(n: int, extent: float = 4.0 * math.pi) -> np.ndarray:
+    """n^3 Cartesian k-points on [-extent/2, extent/2)^3 (pyrochlore: the
+    cubic cell has side 1, so this covers the extended Brillouin zone)."""
+    m = (np.arange(n) / n - 0.5) * extent
+    kx, ky, kz = np.meshgrid(m, m, m, indexing="ij")
+    return np.stack([kx.ravel(), ky.ravel(), kz.ravel()], axis=1)
 
+
+HOT_PATH = {
+    # workload, k-grid of chi(k) per step, description
+    "pyrochlore": ("pyrochlore NN Heisenberg J=1, range 5 (31 pairs), 48 log freqs 1e-3..100; "
+                   "RK4 step + chi + chi(k) on 16^3 k-points", lambda: kgrid3(16)),
+    "square_j1j2": ("square-lattice J1-J2 Heisenberg, J2/J1=0.5, range 7 (20 pairs), 32 log freqs "
+                    "1e-3..100; RK4 step + chi + chi(k) on 64x64", lambda: kgrid(64)),
+}
+
+
+def hot_path_leg(name: str, steps: int, warmup: int, breakdown: bool = True) -> dict:
+    """One workload's hot path on the GPU: the physical flow from the initial
+    condition down to Lambda = 1 (untimed setup), then `steps` timed passes of
+    [RK4 step Lambda -> 0.95 Lambda (4 self-energy + 4 vertex right-hand sides
+    and the stage combinations), chi per pair, chi(k)] with HIP events on the
+    vertex launches (s, u and t channels in one launch) for the roofline;
+    optionally a second pass over the same steps with the channels as three
+    launches and events around every kernel, for the per-kernel breakdown."""
     import torch
     from paper_2109_13317_amd import build_tables
     from paper_2109_13317_amd.flow import Context
-
-    wl = W.workload("square_j1j2")
+    desc, kfun = HOT_PATH[name]
+    wl = W.workload(name)
     model = wl.model()
     tables = build_tables(model, wl.range)
     ctx = Context(tables, wl.mesh)
     nf, ns = ctx.nf, ctx.ns
-    triples = nf * nf * (nf + 1) // 2
-    E = 2 * ns * triples
-    kp = torch.from_numpy(kgrid(64)).cuda()
-
-    # setup: the physical flow from the initial condition down to Lambda = 1
-    log(f"context ready: {ns} pairs, {nf} frequencies, {E} vertex elements")
+    E = 2 * ns * nf * nf * (nf + 1) // 2
+    kp = torch.from_numpy(kfun()).cuda()
+    log(f"{name}: context ready, {ns} pairs, {nf} frequencies, {E} vertex elements")
     x = ctx.init_state()
     ctx.flow(x, schedule=W.geometric_schedule(100.0, 1.0, 40), scheme="rk4")
     torch.cuda.synchronize()
     x_start = x.cpu().numpy()
-    log("setup flow to Lambda=1 done")
-
+    log(f"{name}: setup flow to Lambda=1 done")
     lam = [1.0]
 
     def step():
@@ -576,49 +623,30 @@ def main():
         ctx.chi_k(chi.reshape(-1), kp)
         lam[0] = l1
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     lam_timed0 = lam[0]
     x_timed0 = x.clone()
     torch.cuda.synchronize()
-    # timed region: HIP events on the vertex launches (s, u and t channels in
-    # one launch) only; the library hands them to the launch, which stamps its
-    # own start and end, so they add nothing to the stream
-    ctx.set_profiling(True, kernels=("vertex_stu",))
+    # timed region.  The library runs the s, u and t channels as one launch up
+    # to 20 pairs (the events are handed to that launch, which stamps its own
+    # start and end on the library's stream) and beyond as s+u beside a
+    # concurrent t launch (events before the fork and after the join: the
+    # span of the whole vertex right-hand side)
+    concurrent = ns > 20
+    timed = "vertex" if concurrent else "vertex_stu"
+    ctx.set_profiling(True, kernels=(timed,))
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tms_t, tcount = ctx.profile_read("vertex_stu")
+    tms_t, tcount = ctx.profile_read(timed)
     ctx.set_profiling(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    # the same steps again from the same state, with events around every
-    # timed kernel, for the per-kernel breakdown (the channels then run as
-    # three launches, with the same results bitwise)
-    lam[0] = lam_timed0
-    x.copy_(x_timed0)
-    ctx.set_profiling(True)
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    vms, vcount = ctx.profile_read("vertex")
-    sms_s, _ = ctx.profile_read("vertex_s")
-    ums_u, _ = ctx.profile_read("vertex_u")
-    tms_t2, _ = ctx.profile_read("vertex_t")
-    sms, _ = ctx.profile_read("sigma")
-    tms, _ = ctx.profile_read("tables")
-    ctx.set_profiling(False)
-    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, s+u+t launch {tms_t / max(tcount, 1):.3f} ms avg; "
-        f"breakdown pass {(t3 - t2) * 1e3 / args.steps:.2f} ms/step, vertex RHS {vms / max(vcount, 1):.3f} ms avg")
-    value = 4 * E / (ms_step * 1e-3)
-
-    # algorithmic flops of every timed vertex launch (RK4 stage cutoffs)
+    ms_step = (t1 - t0) * 1e3 / steps
     fl = {"s": 0.0, "u": 0.0, "t": 0.0, "all": 0.0}
     l0 = lam_timed0
-    for _ in range(args.steps):
+    for _ in range(steps):
         l1 = l0 * 0.95
         h = l1 - l0
         for ls in (l0, l0 + 0.5 * h, l0 + 0.5 * h, l1):
@@ -630,95 +658,227 @@ def main():
     achieved = fl["all"] / tcount / (tavg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-                "traffic": MEASURED_TRAFFIC.get(kernel_source_hash()), "traffic_unit": "bytes/launch",
-                "kernel": "k_vertex_stu (s, u and t channels in one launch)",
+                "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(), name)), "traffic_unit": "bytes/launch",
+                "kernel": (f"vertex right-hand side: k_vertex_su<0>, k_vertex_su<2> on the library stream beside "
+                           f"k_vertex_t<{4 * ((ns + 3) // 4)}, double> on its second stream, then the t-part sum "
+                           "(timed from before the fork to after the join)") if concurrent else
+                          f"k_vertex_stu<{4 * ((ns + 3) // 4)}, double> (s, u and t channels in one launch)",
+                "launch_form": "concurrent" if concurrent else "one_launch",
                 "avg_launch_ms": tavg_ms, "launches": tcount,
                 "flops_per_launch": fl["all"] / tcount,
-                "whole_vertex_rhs": {"avg_ms": vms / max(vcount, 1),
-                                     "achieved_tflops": fl["all"] / vcount / (vms / vcount * 1e-3) / 1e12,
-                                     "s_ms": sms_s / max(vcount, 1), "u_ms": ums_u / max(vcount, 1),
-                                     "t_ms": tms_t2 / max(vcount, 1),
-                                     "source": "a second pass over the same steps with the channels as three "
-                                               "separate launches (same results bitwise) and HIP events "
-                                               "around every kernel"}}
+                "flops_per_launch_by_channel": {k: fl[k] / tcount for k in ("s", "u", "t")},
+                "hbm_bytes_algorithmic_per_launch": 16.0 * E / 2 + 8.0 * E}
+    # each launch form of the whole vertex right-hand side on the same state
+    # and cutoff (the same bits), timed from before its first to after its
+    # last launch
+    forms = {}
+    out = ctx.new_state()
+    xs = torch.from_numpy(x_start).cuda()
+    for form in ("one_launch", "separate", "concurrent"):
+        ctx.set_vertex_mode(form)
+        ctx.rhs(0.5, xs, out)
+        ctx.set_profiling(True, kernels=("vertex",))
+        for _ in range(5):
+            ctx.rhs(0.5, xs, out)
+        ms, n = ctx.profile_read("vertex")
+        ctx.set_profiling(False)
+        forms[form] = ms / n
+    ctx.set_vertex_mode("auto")
+    roofline["launch_forms_ms_at_lambda_0.5"] = forms
+    log(f"{name}: vertex right-hand side at Lambda=0.5 by launch form: " +
+        ", ".join(f"{k} {v:.4f} ms" for k, v in forms.items()))
+    stage_lams = []
+    l0 = lam_timed0
+    for _ in range(steps):
+        l1 = l0 * 0.95
+        stage_lams += [l0, l0 + 0.5 * (l1 - l0), l1]
+        l0 = l1
+    res = {"workload": desc, "pairs": ns, "n_freq": nf, "vertex_elements": E, "ms_per_step": ms_step,
+           "stage_lambdas": stage_lams[::max(1, len(stage_lams) // 6)],
+           "value": 4 * E / (ms_step * 1e-3), "roofline": roofline, "lambda_timed": [lam_timed0, lam[0]],
+           "tables": tables, "model": model, "wl": wl, "x_start": x_start, "ctx": ctx}
+    log(f"{name}: {steps} steps {ms_step:.3f} ms/step, vertex launch {tavg_ms:.4f} ms, "
+        f"{achieved:.2f} TFLOP/s ({roofline['frac']:.3f} of FP64 peak)")
+    if breakdown:
+        lam[0] = lam_timed0
+        x.copy_(x_timed0)
+        ctx.set_profiling(True)
+        t2 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        vms, vcount = ctx.profile_read("vertex")
+        parts = {k: ctx.profile_read(k)[0] for k in ("vertex_s", "vertex_u", "vertex_t", "sigma", "tables")}
+        ctx.set_profiling(False)
+        roofline["whole_vertex_rhs"] = {
+            "avg_ms": vms / max(vcount, 1),
+            "achieved_tflops": fl["all"] / vcount / (vms / vcount * 1e-3) / 1e12,
+            "s_ms": parts["vertex_s"] / max(vcount, 1), "u_ms": parts["vertex_u"] / max(vcount, 1),
+            "t_ms": parts["vertex_t"] / max(vcount, 1),
+            "source": "a second pass over the same steps with the channels as three separate launches "
+                      "(same results bitwise) and HIP events around every kernel"}
+        res["kernel_ms_per_step"] = {"vertex": vms / steps, "sigma": parts["sigma"] / steps,
+                                     "tables": parts["tables"] / steps,
+                                     "breakdown_pass_ms_per_step": (t3 - t2) * 1e3 / steps}
+    return res
 
+
+def _public(d: dict) -> dict:
+    return {k: v for k, v in d.items() if k not in ("tables", "model", "wl", "x_start", "ctx", "stage_lambdas")}
+
+
+def adaptive_flow(ctx, kp, lam_max_breakdown, label):
+    """The adaptive Dormand-Prince flow 100 -> 0.01 with chi(k) every accepted
+    step (timed), then the same flow untimed recording chi_max(Lambda) for the
+    breakdown detector."""
+    import torch
+    xf = ctx.init_state()
+    torch.cuda.synchronize()
+    nacc = [0]
+
+    def obs(lam_, chi_, ck_):
+        nacc[0] += 1
+        if nacc[0] % 20 == 0:
+            log(f"{label} adaptive flow: {nacc[0]} accepted steps, Lambda={lam_:.4g}")
+        return 0
+
+    t0 = time.perf_counter()
+    nsteps = ctx.flow(xf, scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4,
+                      atol=1e-6, h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=obs)
+    torch.cuda.synchronize()
+    flow_s = time.perf_counter() - t0
+    from paper_2109_13317_amd.breakdown import ChiMaxRecorder
+    rec = ChiMaxRecorder()
+    ctx.flow(ctx.init_state(), scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4, atol=1e-6,
+             h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=rec)
+    chimax = np.asarray(rec.chi_max)
+    bd = rec.breakdown(lam_max=lam_max_breakdown)
+    log(f"{label}: adaptive flow {flow_s:.3f} s, {nsteps} steps; breakdown detector: {bd.kind} (Lambda = {bd.lam})")
+    return xf, {"scheme": "dopri54 in ln Lambda, rtol 1e-4, atol 1e-6, steps land on w_n/2",
+                "lambda": [100.0, 0.01], "seconds": flow_s, "accepted_steps": nsteps,
+                "breakdown": {"kind": bd.kind, "lambda": bd.lam, "step": bd.index,
+                              "chi_max_first": float(chimax[0]), "chi_max_last": float(chimax[-1]),
+                              "detector": "first step below a quarter of the top mesh frequency with ln chi_max "
+                                          "slope in ln Lambda below -8 or a slope change above 1 (heuristic, "
+                                          "parity unpinned)"}}
+
+
+def fixed_flow(ctx, sched):
+    """The fixed RK4 flow along sched with chi at the end (timed)."""
+    import torch
+    from paper_2109_13317_amd._lib import PffrgError
+    xf = ctx.init_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        ctx.flow(xf, schedule=sched, scheme="rk4")
+        chi0 = float(ctx.chi(sched[-1], xf).reshape(-1)[0].cpu())
+    except PffrgError as e:              # a flow that leaves the finite range stops there
+        chi0 = f"flow stopped: {e}"
+    torch.cuda.synchronize()
+    return {"seconds": time.perf_counter() - t0, "steps": len(sched) - 1, "chi_zz_onsite_final": chi0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=sorted(HOT_PATH), default="pyrochlore",
+                    help="the headline workload (default: pyrochlore, the largest FP64 configuration)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full-flow", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the second hot-path workload and the FP32, batched-scan, adjoint and scaling "
+                         "measurements")
+    ap.add_argument("--no-breakdown", action="store_true", help="skip the per-kernel breakdown pass")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the flow engine runs on a single MI355X "
+              "(sharding across GPUs is not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    head = hot_path_leg(args.workload, args.steps, args.warmup, breakdown=not args.no_breakdown)
+    roofline = head["roofline"]
     # the device's own peaks (FMA throughput, copy bandwidth) beside the vendor figures
     from paper_2109_13317_amd.flow import measure_peaks
     peaks = measure_peaks()
     roofline["measured_peak"] = peaks["fp64_fma_tflops"]
-    roofline["frac_of_measured_peak"] = achieved / peaks["fp64_fma_tflops"]
+    roofline["frac_of_measured_peak"] = roofline["achieved"] / peaks["fp64_fma_tflops"]
+    # the on-chip ceiling: every interpolation corner is one 1 KB wave gather
+    # served by L1 at the measured rate
+    wl_h = head["wl"]
+    gi = np.mean([gather_instructions(wl_h.mesh, l, head["pairs"]) for l in head["stage_lambdas"]])
+    bound_ms = gi * 1024.0 / (peaks["l1_load_tbs"] * 1e12) * 1e3
+    roofline["l1_gather_bound"] = {
+        "gather_instructions_per_launch": gi, "bytes_per_instruction": 1024,
+        "measured_l1_tbs": peaks["l1_load_tbs"], "bound_ms": bound_ms,
+        "fraction_of_bound_achieved": bound_ms / roofline["avg_launch_ms"],
+        "fp64_fraction_at_bound": roofline["frac"] * roofline["avg_launch_ms"] / bound_ms}
+    log(f"L1 gather bound: {gi:.3e} wave gathers per launch, {bound_ms:.4f} ms at {peaks['l1_load_tbs']:.1f} TB/s "
+        f"({bound_ms / roofline['avg_launch_ms']:.2f} of the launch time)")
     log(f"measured peaks: FP64 FMA {peaks['fp64_fma_tflops']:.1f} TFLOP/s, FP32 FMA "
-        f"{peaks['fp32_fma_tflops']:.1f} TFLOP/s, copy {peaks['hbm_copy_gbs']:.0f} GB/s")
+        f"{peaks['fp32_fma_tflops']:.1f} TFLOP/s, copy {peaks['hbm_copy_gbs']:.0f} GB/s, 16-byte lane loads: "
+        f"L1 {peaks['l1_load_tbs']:.1f} TB/s (two rows {peaks['l1_load_2row_tbs']:.1f}), "
+        f"LDS {peaks['lds_read_tbs']:.1f} TB/s")
 
     out = {
         "metric": "vertex-RHS elements/s + full-flow time vs plain FP64 GPU; adjoint/forward cost",
-        "value": value,
+        "value": head["value"],
         "unit": "vertex-RHS elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "square-lattice J1-J2 Heisenberg, J2/J1=0.5, range 7 (20 pairs), "
-                               "32 log freqs 1e-3..100; RK4 step + chi(k) on 64x64",
-                   "pairs": ns, "n_freq": nf, "vertex_elements": E, "parallelism": "single GPU"},
+        "config": {"workload": HOT_PATH[args.workload][0], "pairs": head["pairs"], "n_freq": head["n_freq"],
+                   "vertex_elements": head["vertex_elements"], "parallelism": "single GPU",
+                   "lambda_timed": head["lambda_timed"]},
         "roofline": roofline,
         "measured_peaks": {**peaks, "method": "pffrg_measure_peaks: 8 FMA chains per lane on every CU "
-                                              "(FP32 without packed instructions); 512 MiB device copy"},
-        "kernel_ms_per_step": {"vertex": vms / args.steps, "sigma": sms / args.steps,
-                               "tables": tms / args.steps,
-                               "breakdown_pass_ms_per_step": (t3 - t2) * 1e3 / args.steps},
+                                              "(FP32 without packed instructions); 512 MiB device copy; "
+                                              "128-bit lane loads from a 16 KB L1-resident buffer and from LDS"},
     }
+    if "kernel_ms_per_step" in head:
+        out["kernel_ms_per_step"] = head["kernel_ms_per_step"]
 
     if not args.no_full_flow:
-        xf = ctx.init_state()
-        torch.cuda.synchronize()
-        nacc = [0]
-
-        def obs(lam_, chi_, ck_):
-            nacc[0] += 1
-            if nacc[0] % 20 == 0:
-                log(f"full flow: {nacc[0]} accepted steps, Lambda={lam_:.4g}")
-            return 0
-
-        log("full adaptive flow 100 -> 0.01")
-        t0 = time.perf_counter()
-        nsteps = ctx.flow(xf, scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4,
-                          atol=1e-6, h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=obs)
-        torch.cuda.synchronize()
-        flow_s = time.perf_counter() - t0
-        # the same flow again, untimed, recording chi_max(Lambda) for the
-        # breakdown detector
-        from paper_2109_13317_amd.breakdown import ChiMaxRecorder
-        rec = ChiMaxRecorder()
-        ctx.flow(ctx.init_state(), scheme="dopri54", lam_start=100.0, lam_stop=0.01, rtol=1e-4, atol=1e-6,
-                 h0=0.05, hmin=1e-9, max_steps=20000, kpoints=kp, observer=rec)
-        chimax = np.asarray(rec.chi_max)
-        bd = rec.breakdown(lam_max=wl.mesh[-1] / 4)
-        log(f"breakdown detector: {bd.kind} (Lambda = {bd.lam})")
-        out["full_flow"] = {"scheme": "dopri54 in ln Lambda, rtol 1e-4, atol 1e-6, steps land on w_n/2",
-                            "lambda": [100.0, 0.01], "seconds": flow_s,
-                            "accepted_steps": nsteps, "chi_k_every_step": "64x64",
-                            "breakdown": {"kind": bd.kind, "lambda": bd.lam, "step": bd.index,
-                                          "chi_max_first": float(chimax[0]), "chi_max_last": float(chimax[-1]),
-                                          "detector": "first step below a quarter of the top mesh frequency "
-                                                      "with ln chi_max slope in ln Lambda below -8 or a "
-                                                      "slope change above 1 (heuristic)"},
-                            "checkpoint": checkpoint_cost(xf)}
+        ctx, wl = head["ctx"], head["wl"]
+        kp = torch.from_numpy(HOT_PATH[args.workload][1]()).cuda()
+        flows = {}
+        if wl.schedule is not None:
+            log(f"{args.workload}: fixed RK4 flow")
+            flows["fixed_rk4"] = {"schedule": "exponential Lambda_n = 100 * 0.95^n down to 0.01",
+                                  **fixed_flow(ctx, list(wl.schedule))}
+        xf, flows["adaptive"] = adaptive_flow(ctx, kp, wl.mesh[-1] / 4, args.workload)
+        flows["adaptive"]["chi_k_every_step"] = f"{len(kp)} k-points"
+        flows["checkpoint"] = checkpoint_cost(xf)
+        out["full_flow"] = flows
 
     if not args.no_extras:
+        other = "square_j1j2" if args.workload == "pyrochlore" else "pyrochlore"
+        sec = hot_path_leg(other, args.steps, args.warmup, breakdown=False)
+        out[other] = _public(sec)
+        if not args.no_full_flow and other == "square_j1j2":
+            kp2 = torch.from_numpy(HOT_PATH[other][1]()).cuda()
+            _, out[other]["full_flow"] = adaptive_flow(sec["ctx"], kp2, sec["wl"].mesh[-1] / 4, other)
+        sq = head if args.workload == "square_j1j2" else sec
         log("FP32 mode")
-        out["fp32_mode"] = fp32_leg(tables, wl, x_start, 0.5)
+        out["fp32_mode"] = fp32_leg(sq["tables"], sq["wl"], sq["x_start"], 0.5)
         log("batched scan")
         out["batch_scan"] = batch_leg()
         log("adjoint")
         out["adjoint"] = adjoint_leg()
-        log("pyrochlore")
-        out["pyrochlore"] = pyrochlore_leg()
+        log("XYZ")
+        out["xyz"] = xyz_leg()
         log("scaling shape")
         out["scaling_shape"] = scaling_leg()
     out["paper_context"] = {
@@ -738,7 +898,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(model, wl, tables, x_start, 1.0)
+        out["cpu_baseline"] = cpu_baseline(head["model"], head["wl"], head["tables"], head["x_start"], 1.0)
 
     print(json.dumps(out), flush=True)
 

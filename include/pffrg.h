@@ -118,6 +118,23 @@ typedef struct {
  * nothing allocated; a failed device allocation gives PFFRG_ENOMEM. */
 pffrg_status pffrg_create(const pffrg_lattice *lat, const pffrg_mesh *mesh,
                           pffrg_precision prec, void *stream, pffrg_ctx **out);
+
+/* An XYZ context (Sec. 2: H = sum over bonds of Jx S^x S^x + Jy S^y S^y +
+ * Jz S^z S^z; Sec. 3: only the diagonal vertex components flow).
+ * coupling3[m * n_pairs + p] (host, copied) is J^m of the bond (i_ref, j_p)
+ * for m = x, y, z; lat->coupling is not read (it may be NULL).  The pair
+ * tables must reduce by symmetries that map every bond to one with equal
+ * (Jx, Jy, Jz).  The state then holds four strains,
+ *   sig | Gx | Gy | Gz | Gd   (V = T*Ns elements each, the layout above),
+ * Gx, Gy, Gz even under s <-> u like the SU(2) spin strain, Gd odd; the
+ * initial condition is G^m = J^m/4, Gd = 0; pffrg_chi returns [4][Ns]
+ * (chi^xx, chi^yy, chi^zz, chi^00) and pffrg_chi_k sums chi^xx + chi^yy +
+ * chi^zz (Eq. 31).  Everything runs in FP64: PFFRG_FP32 gives
+ * PFFRG_EUNSUPPORTED, as do more than 16 pairs; the reverse-mode calls
+ * (pffrg_init_state_from, pffrg_*_vjp) give PFFRG_EUNSUPPORTED on an XYZ
+ * context.  NULL coupling3 or a non-finite coupling: PFFRG_EINVAL. */
+pffrg_status pffrg_create_xyz(const pffrg_lattice *lat, const double *coupling3, const pffrg_mesh *mesh,
+                              pffrg_precision prec, void *stream, pffrg_ctx **out);
 pffrg_status pffrg_destroy(pffrg_ctx *ctx);
 pffrg_status pffrg_set_stream(pffrg_ctx *ctx, void *stream);
 
@@ -275,6 +292,27 @@ pffrg_status pffrg_flow_checkpoints(pffrg_ctx *ctx, int n_lambda, const double *
 pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas, const double *d_checkpoints,
                             double *d_cot, double *d_dcoupling);
 
+/* How the three channels of the vertex flow (Eq. 24) are launched; every
+ * form computes dGamma = (s part + u part) + t part in that order, so the
+ * results are bitwise the same:
+ *   PFFRG_VERTEX_ONE_LAUNCH   one launch whose workgroups take the s, u and t
+ *                             roles in turn, then the sum of the parts;
+ *   PFFRG_VERTEX_SEPARATE     three launches in turn (s writes, u and t add);
+ *   PFFRG_VERTEX_CONCURRENT   s and u on the context's stream while the t
+ *                             channel runs on a second stream of the context
+ *                             (default priority), joined before the sum;
+ *   PFFRG_VERTEX_AUTO         (the default) concurrent beyond 20 pairs, one
+ *                             launch otherwise.
+ * Profiling a single channel (PFFRG_K_VERTEX_S, _U, _T) uses the separate
+ * form.  An unknown mode gives PFFRG_EINVAL. */
+enum {
+    PFFRG_VERTEX_AUTO = -1,
+    PFFRG_VERTEX_ONE_LAUNCH = 0,
+    PFFRG_VERTEX_SEPARATE = 1,
+    PFFRG_VERTEX_CONCURRENT = 2
+};
+pffrg_status pffrg_set_vertex_mode(pffrg_ctx *ctx, int mode);
+
 /* ----------------------------------------------------------- profiling - */
 
 /* Kernel timing with HIP events on the context's stream for every launch of
@@ -283,9 +321,11 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
  * nothing to the stream); PFFRG_K_VERTEX is timed by events recorded before
  * the first and after the last vertex launch (a few microseconds of stream
  * time each).  The vertex channels normally run as one launch
- * (PFFRG_K_VERTEX_STU) followed by the sum of the channel parts; while any of
- * PFFRG_K_VERTEX_S, _U, _T is timed they run as three launches instead (the
- * s launch writes, the u and t launches add: the same sums, bitwise).
+ * (PFFRG_K_VERTEX_STU) followed by the sum of the channel parts, or as
+ * concurrent launches (pffrg_set_vertex_mode; PFFRG_K_VERTEX then spans the
+ * fork to the join); while any of PFFRG_K_VERTEX_S, _U, _T is timed they run
+ * as three launches in turn instead (the s launch writes, the u and t
+ * launches add: the same sums, bitwise).
  * pffrg_set_profiling turns recording on
  * for all of them (1) or off (0); pffrg_set_profiling_mask records only the
  * kernels whose bit (1 << id) is set in `mask` (0: off; a bit at or above
@@ -387,13 +427,21 @@ pffrg_status pffrg_batch_profile_read(pffrg_batch *batch, double *total_ms, int 
  * FP64 and FP32 vector FMA throughput (2 flops per FMA, every CU, 8
  * independent FMA chains per lane, FP32 without packed instructions as in
  * every kernel of the library) and the bandwidth of a 512 MiB device-to-
- * device copy (bytes read + written per second).  Allocates 1 GiB of device
- * memory for the duration of the call and frees it; synchronises the stream.
- * Errors: PFFRG_EINVAL (NULL out), PFFRG_ENOMEM, PFFRG_EHIP. */
+ * device copy (bytes read + written per second), and the rates at which 16
+ * bytes per lane reach the registers, the width of one interpolation corner
+ * of the vertex kernels (TB/s over every CU): 128-bit buffer loads from a
+ * 16 KB L1-resident buffer, each wave instruction one contiguous 1 KB row
+ * (l1_load_tbs) or two 512-byte rows (l1_load_2row_tbs, two pair vectors per
+ * instruction), and 128-bit LDS reads (lds_read_tbs).  Allocates 1 GiB of
+ * device memory for the duration of the call and frees it; synchronises the
+ * stream.  Errors: PFFRG_EINVAL (NULL out), PFFRG_ENOMEM, PFFRG_EHIP. */
 typedef struct pffrg_peaks {
     double fp64_fma_tflops;
     double fp32_fma_tflops;
     double hbm_copy_gbs;
+    double l1_load_tbs;
+    double l1_load_2row_tbs;
+    double lds_read_tbs;
 } pffrg_peaks;
 pffrg_status pffrg_measure_peaks(void *stream, pffrg_peaks *out);
 

@@ -19,6 +19,7 @@ D = ctypes.c_double
 OK, EINVAL, EHIP, ENOMEM, EDIVERGED, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 EULER, RK4, DOPRI54 = 0, 1, 2
+VERTEX_MODES = {"auto": -1, "one_launch": 0, "separate": 1, "concurrent": 2}
 
 
 class Lattice(ctypes.Structure):
@@ -43,8 +44,10 @@ OBSERVER = ctypes.CFUNCTYPE(ctypes.c_int, D, P, P, P)
 # name -> (argtypes); every entry point returns pffrg_status (int)
 SIGNATURES = {
     "pffrg_create": [ctypes.POINTER(Lattice), ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
+    "pffrg_create_xyz": [ctypes.POINTER(Lattice), P, ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
     "pffrg_destroy": [P],
     "pffrg_set_stream": [P, P],
+    "pffrg_set_vertex_mode": [P, I],
     "pffrg_state_size": [P, ctypes.POINTER(ctypes.c_size_t)],
     "pffrg_init_state": [P, P],
     "pffrg_rhs": [P, D, P, P],

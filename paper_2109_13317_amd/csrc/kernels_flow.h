@@ -559,6 +559,7 @@ struct WaveLds {
     __host__ __device__ size_t plans() const { return (size_t)2 * kTChunk * sizeof(TPlan<R>); }
     __host__ __device__ size_t onsite() const { return (((size_t)5 * kTChunk * sizeof(R)) + 15) & ~(size_t)15; }
     __host__ __device__ size_t su_plans() const { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
+    __host__ __device__ size_t su_w() const { return (size_t)kPlanChunk * sizeof(double); }
     __host__ __device__ size_t vbuf() const { return (size_t)4 * sub * nsp() * sizeof(R); }
     __host__ __device__ size_t red() const { return (size_t)2 * kSuPairs<R> * kWave * sizeof(double); }
     __host__ __device__ size_t mat() const { return (((size_t)ns * ns * sizeof(double)) + 31) & ~(size_t)31; }
@@ -568,7 +569,7 @@ struct WaveLds {
         size_t b = work() > m ? work() : m;
         return (b + 31) & ~(size_t)31;
     }
-    __host__ __device__ size_t su_bytes() const { return ((su_plans() + 31) & ~(size_t)31) + red(); }
+    __host__ __device__ size_t su_bytes() const { return ((su_plans() + su_w() + 31) & ~(size_t)31) + red(); }
     // an area that serves both bodies (one wave doing s, u and t in turn)
     __host__ __device__ size_t all_bytes() const { return bytes() > su_bytes() ? bytes() : su_bytes(); }
 };
@@ -725,6 +726,8 @@ __device__ __forceinline__ void eval_packed_ab2(const PlanT<float>& Pa, const Pl
 template <int CH, class R>
 __device__ __forceinline__ SuPart su_body(const FlowArgs& A, const Shared& sh, PlanT<R>* plan, const Triple& T,
                                           __amdgpu_buffer_rsrc_t rv, int lane) {
+    // the chunk's node weights sit in LDS after the plans
+    double* wts = reinterpret_cast<double*>(plan + 2 * kPlanChunk);
     constexpr int PL = kSuPairs<R>;
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const int ia = T.ia, ic = T.ic;
@@ -770,12 +773,13 @@ __device__ __forceinline__ SuPart su_body(const FlowArgs& A, const Shared& sh, P
                               2, ic, P, &sh.lut);
                 to_bytes(P);
                 plan[vec * kPlanChunk + j] = P;
+                if (vec == 0) wts[j] = tg[k0 + j];
             }
         }
         wave_lds_sync();
         if (act) {
             for (int k = g; k < kc; k += G) {
-                const R W = (R)tg[k0 + k];
+                const R W = (R)wts[k];
                 if constexpr (PL == 1) {
                     R as, ad, bs, bd;
                     eval_packed_ab(plan[k], plan[kPlanChunk + k], rv, pp, as, ad, bs, bd);
@@ -1140,13 +1144,14 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
 }
 
-// One context, ordered by (t, s, u); adds to dGamma.  Occupancy targets: the
+// One context, ordered by (t, s, u); adds to dGamma (add != 0) or writes its
+// part (add == 0).  Occupancy targets: the
 // widest that hold the register blocks without spilling (five waves per SIMD
 // up to 16 pairs, four up to 20, three beyond).
 template <int NSP, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu(NSP > 20 ? 3 : (NSP > 16 ? 4 : 5))))
-k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx, int add) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns;
     const Shared sh = load_shared(A, lds_raw, true);
@@ -1164,7 +1169,7 @@ k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __re
     const LanePart r = t_body<NSP, R>(A, sh, base, T, rv, lane);
     const long vsz = (long)n_triples * ns;
     finish_pairs(red, lane, ns, kWave / ns, lane / ns < kWave / ns, r.s, r.d, 0.0, 0.0,
-                 dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, true);
+                 dx + A.nf + T.out * ns, dx + A.nf + vsz + T.out * ns, add != 0);
 }
 
 // The s, u and t channels in one launch (grid 24 * per workgroups).  The

@@ -139,22 +139,27 @@ static __global__ void k_chi_final(int ns, const double* __restrict__ cq, const 
     chi[ns + p] = d;
 }
 
-// chi(k_q) = (1/nb) sum_{b, j} cos(k_q . dr_bj) 3 chi^{zz}_{pair(b,j)};
-// one wave per k point, lanes over the (basis, site) terms.
+// chi(k_q) = (1/nb) sum_{b, j} cos(k_q . dr_bj) scale (sum_m chi^m_{pair(b,j)}),
+// the sum over the nsum strains chi[m * stride + pair], m < nsum (SU(2): 3
+// chi^{zz}; XYZ: chi^xx + chi^yy + chi^zz); one wave per k point, lanes over
+// the (basis, site) terms.
 constexpr int kChiKWaves = 4;
 static __global__ void __launch_bounds__(64 * kChiKWaves)
 k_chi_k(int nterm, const int* __restrict__ pair, const double* __restrict__ dr, double inv_nb,
-        const double* __restrict__ chi, int nk, const double* __restrict__ kp, double* __restrict__ out) {
+        const double* __restrict__ chi, int nsum, int stride, double scale, int nk, const double* __restrict__ kp,
+        double* __restrict__ out) {
     const int q = blockIdx.x * kChiKWaves + threadIdx.x / 64, lane = threadIdx.x % 64;
     if (q >= nk) return;
     const double kx = kp[3 * q], ky = kp[3 * q + 1], kz = kp[3 * q + 2];
     double acc = 0.0;
     for (int i = lane; i < nterm; i += 64) {
         const double ph = kx * dr[3 * i] + ky * dr[3 * i + 1] + kz * dr[3 * i + 2];
-        acc = fma(cos(ph), chi[pair[i]], acc);
+        double v = chi[pair[i]];
+        for (int m = 1; m < nsum; ++m) v += chi[m * stride + pair[i]];
+        acc = fma(cos(ph), v, acc);
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) out[q] = 3.0 * inv_nb * acc;
+    if (lane == 0) out[q] = scale * inv_nb * acc;
 }
 
 // ------------------------------------------------------- Runge-Kutta ----

@@ -20,6 +20,7 @@
 #include "kernels_flow.h"
 #include "kernels_obs.h"
 #include "kernels_adj.h"
+#include "kernels_xyz.h"
 
 using namespace pffrg;
 using namespace pffrg_host;
@@ -33,6 +34,8 @@ constexpr int kRedBlocks = 512;
 
 struct pffrg_ctx {
     int nf = 0, ns = 0, nq = 0, nsu = 0;
+    int nc = 2;                     // vertex strains: 2 (SU(2)) or 4 (XYZ)
+    double* coupling3 = nullptr;    // XYZ: [3][ns] couplings Jx, Jy, Jz
     long vsz = 0, size = 0;
     pffrg_precision prec = PFFRG_FP64;
     hipStream_t stream = nullptr;
@@ -60,6 +63,12 @@ struct pffrg_ctx {
     double* k[kNumK] = {};
     double *ybuf = nullptr, *ebuf = nullptr;
     double *part_u = nullptr, *part_t = nullptr;   // u- and t-channel parts of one vertex RHS (state layout)
+    // how the three channels are launched (pffrg_set_vertex_mode); the
+    // concurrent mode runs the t channel on `side`, forked from and joined to
+    // the context's stream through the two events
+    int vertex_mode = PFFRG_VERTEX_AUTO;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     double *cw = nullptr, *cq = nullptr, *cg2 = nullptr;
     int* cn = nullptr;
     double* chi = nullptr;          // [2*ns]
@@ -123,6 +132,11 @@ pffrg_status upload(pffrg_ctx* c, T** p, const T* src, size_t n) {
 void release(pffrg_ctx* c) {
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    if (c->join) (void)hipEventDestroy(c->join);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    c->fork = c->join = nullptr;
+    c->side = nullptr;
     for (auto& v : c->ev)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     if (c->host_red) (void)hipHostFree(c->host_red);
@@ -209,8 +223,48 @@ pffrg_status tables_pack(pffrg_ctx* c, double lam, const double* x, const double
     return launch_check("k_tables_pack");
 }
 
-// The vertex right-hand side in precision R from the packed vertex in c->gv:
-// the three channel launches (s writes dGamma, u and t add).
+// How the channels of one vertex right-hand side run (mode = the context's
+// setting; PFFRG_VERTEX_AUTO resolved by the pair count): while a single
+// channel is timed they always run as three launches.
+int vertex_mode_for(const pffrg_ctx* c) {
+    constexpr unsigned kPerChannel = (1u << PFFRG_K_VERTEX_S) | (1u << PFFRG_K_VERTEX_U) | (1u << PFFRG_K_VERTEX_T);
+    if (c->prof_mask & kPerChannel) return PFFRG_VERTEX_SEPARATE;
+    if (c->vertex_mode != PFFRG_VERTEX_AUTO) return c->vertex_mode;
+    // up to 20 pairs one launch, whose s/u and t workgroups share every CU;
+    // beyond, the t role's lattice-sum tiles would hold that kernel at 3 waves
+    // per SIMD for all three roles, and s+u beside a concurrent t launch,
+    // each at its own occupancy, is faster
+    return c->ns > 20 ? PFFRG_VERTEX_CONCURRENT : PFFRG_VERTEX_ONE_LAUNCH;
+}
+
+template <class R>
+pffrg_status launch_vertex_t(pffrg_ctx* c, hipStream_t st, ProfPair e, const FlowArgs& A, int T, double* out,
+                             int add) {
+    const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per = (blocks + 7) / 8;
+    const size_t lds_t = t_lds_bytes<R>(c->nf, c->ns, c->n_terms);
+    const V2<R>* gv = static_cast<const V2<R>*>(c->gv);
+    switch ((c->ns + 3) / 4) {
+#define PFFRG_T_CASE(K) \
+        case K: hipExtLaunchKernelGGL((k_vertex_t<4 * K, R>), dim3(8 * per), dim3(kWave * kWavesPerBlock), lds_t, st, \
+                                      e.start, e.stop, 0, A, gv, T, out, add); break;
+        PFFRG_T_CASE(1) PFFRG_T_CASE(2) PFFRG_T_CASE(3) PFFRG_T_CASE(4)
+        PFFRG_T_CASE(5) PFFRG_T_CASE(6) PFFRG_T_CASE(7) PFFRG_T_CASE(8)
+#undef PFFRG_T_CASE
+        default: return fail(PFFRG_EUNSUPPORTED, "pair count out of range");
+    }
+    return launch_check("k_vertex_t");
+}
+
+// The vertex right-hand side in precision R from the packed vertex in c->gv,
+// in one of three launch forms with the same sums in the same order,
+// dGamma = (s part + u part) + t part, bitwise equal:
+//   one launch     k_vertex_stu writes the three parts (s into dx), then
+//                  k_sum_channels adds them;
+//   separate       s writes dx, u adds, t adds (three launches in turn);
+//   concurrent     s writes dx and u adds on the context's stream while t
+//                  writes its part on the side stream; after the join the t
+//                  part is added.
 template <class R>
 pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
     FlowArgs A = c->args();
@@ -223,10 +277,10 @@ pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
     const size_t lds_su = S.bytes(false) + kWavesPerBlock * Lsu.su_bytes();
     const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
     const size_t lds_t = t_lds_bytes<R>(c->nf, c->ns, c->n_terms);
+    const long nv = 2L * T * c->ns;
     prof_mark(c, PFFRG_K_VERTEX, false);
-    constexpr unsigned kPerChannel = (1u << PFFRG_K_VERTEX_S) | (1u << PFFRG_K_VERTEX_U) | (1u << PFFRG_K_VERTEX_T);
-    if (!(c->prof_mask & kPerChannel)) {
-        // the three channels in one launch, then (s + u) + t
+    const int mode = vertex_mode_for(c);
+    if (mode == PFFRG_VERTEX_ONE_LAUNCH) {
         const size_t lds = lds_t > lds_su ? lds_t : lds_su;
         const ProfPair e = prof_pair(c, PFFRG_K_VERTEX_STU);
         switch ((c->ns + 3) / 4) {
@@ -240,11 +294,16 @@ pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
             default: return fail(PFFRG_EUNSUPPORTED, "pair count out of range");
         }
         TRY(launch_check("k_vertex_stu"));
-        const long nv = 2L * T * c->ns;
         hipLaunchKernelGGL(k_sum_channels, dim3(grid_for(nv, 256)), dim3(256), 0, c->stream, nv, dx + c->nf,
                            (const double*)c->part_u + c->nf, (const double*)c->part_t + c->nf);
         prof_mark(c, PFFRG_K_VERTEX, true);
         return launch_check("k_sum_channels");
+    }
+    if (mode == PFFRG_VERTEX_CONCURRENT) {
+        HIP_TRY(hipEventRecord(c->fork, c->stream));
+        HIP_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
+        TRY(launch_vertex_t<R>(c, c->side, ProfPair{}, A, T, c->part_t, 0));
+        HIP_TRY(hipEventRecord(c->join, c->side));
     }
     const ProfPair es = prof_pair(c, PFFRG_K_VERTEX_S);
     hipExtLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, c->stream, es.start, es.stop, 0, A,
@@ -252,22 +311,60 @@ pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
     const ProfPair eu = prof_pair(c, PFFRG_K_VERTEX_U);
     hipExtLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, c->stream, eu.start, eu.stop, 0, A,
                           (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
-    const ProfPair et = prof_pair(c, PFFRG_K_VERTEX_T);
-    switch ((c->ns + 3) / 4) {
-#define PFFRG_T_CASE(K) \
-        case K: hipExtLaunchKernelGGL((k_vertex_t<4 * K, R>), grid, block, lds_t, c->stream, et.start, et.stop, 0, \
-                                      A, (const V2<R>*)gv, T, dx); break;
-        PFFRG_T_CASE(1) PFFRG_T_CASE(2) PFFRG_T_CASE(3) PFFRG_T_CASE(4)
-        PFFRG_T_CASE(5) PFFRG_T_CASE(6) PFFRG_T_CASE(7) PFFRG_T_CASE(8)
-#undef PFFRG_T_CASE
-        default: return fail(PFFRG_EUNSUPPORTED, "pair count out of range");
+    TRY(launch_check("k_vertex_su"));
+    if (mode == PFFRG_VERTEX_CONCURRENT) {
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
+        hipLaunchKernelGGL(k_axpy, dim3(grid_for(nv, 256)), dim3(256), 0, c->stream, nv, 1.0,
+                           (const double*)c->part_t + c->nf, dx + c->nf);
+        prof_mark(c, PFFRG_K_VERTEX, true);
+        return launch_check("k_axpy");
     }
+    TRY(launch_vertex_t<R>(c, c->stream, prof_pair(c, PFFRG_K_VERTEX_T), A, T, dx, 1));
     prof_mark(c, PFFRG_K_VERTEX, true);
-    return launch_check("k_vertex_t");
+    return PFFRG_OK;
+}
+
+// XYZ right-hand side (kernels_xyz.h): self-energy flow, node tables, the
+// packed (x, y, z, d) vertex, then the s (writes), u and t (add) launches.
+pffrg_status xyz_sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
+    const ProfPair e = prof_pair(c, PFFRG_K_SIGMA);
+    hipExtLaunchKernelGGL(k_xyz_sigma, dim3(c->nf), dim3(kWave), 0, c->stream, e.start, e.stop, 0, c->args(), lam, x,
+                          (long)c->vsz, dsig);
+    return launch_check("k_xyz_sigma");
+}
+
+pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
+    FlowArgs A = c->args();
+    TRY(xyz_sigma_rhs(c, lam, x, dx));             // the sigma part of dx is dsig
+    const ProfPair et = prof_pair(c, PFFRG_K_TABLES);
+    hipExtLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, et.start, et.stop, 0, A, lam, x,
+                          (const double*)dx);
+    TRY(launch_check("k_node_tables"));
+    double4* gv = static_cast<double4*>(c->gv);
+    hipLaunchKernelGGL(k_xyz_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz,
+                       x + c->nf, gv);
+    TRY(launch_check("k_xyz_pack"));
+    const int T = c->nsu * c->nf;
+    const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per = (blocks + 7) / 8;
+    const SharedLds S{c->nf, c->ns, c->n_terms};
+    const size_t lds_su = S.bytes(false) + kWavesPerBlock * XyzWaveLds::bytes();
+    const size_t lds_t = S.bytes(true) + kWavesPerBlock * XyzWaveLds::bytes();
+    const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
+    prof_mark(c, PFFRG_K_VERTEX, false);
+    hipLaunchKernelGGL(k_xyz_su<0>, grid, block, lds_su, c->stream, A, (const double4*)gv, (const int*)c->uo_a,
+                       (const int*)c->uo_c, T, dx);
+    hipLaunchKernelGGL(k_xyz_su<2>, grid, block, lds_su, c->stream, A, (const double4*)gv, (const int*)c->uo_a,
+                       (const int*)c->uo_c, T, dx);
+    TRY(launch_check("k_xyz_su"));
+    hipLaunchKernelGGL(k_xyz_t, grid, block, lds_t, c->stream, A, (const double4*)gv, T, dx);
+    prof_mark(c, PFFRG_K_VERTEX, true);
+    return launch_check("k_xyz_t");
 }
 
 pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    if (c->nc == 4) return xyz_rhs(c, lam, x, dx);
     TRY(sigma_rhs(c, lam, x, dx));                  // the sigma part of dx is dsig
     if (c->prec == PFFRG_FP32) {
         TRY(tables_pack<float>(c, lam, x, dx));
@@ -551,13 +648,31 @@ const char* pffrg_status_string(pffrg_status s) {
     return "unknown status";
 }
 
-pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffrg_precision prec, void* stream,
-                          pffrg_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+// The context of pffrg_create (coupling3 NULL, SU(2)) and pffrg_create_xyz
+// (coupling3 = [3][ns] couplings Jx, Jy, Jz; lat->coupling is not read).
+pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, const pffrg_mesh* mesh,
+                        pffrg_precision prec, void* stream, pffrg_ctx** out) {
     if (!out) return fail(PFFRG_EINVAL, "out is null");
     *out = nullptr;
+    if (!lat_in) return fail(PFFRG_EINVAL, "null lattice");
+    const bool xyz = coupling3 != nullptr;
+    pffrg_lattice lat_copy = *lat_in;
+    if (xyz) lat_copy.coupling = coupling3;        // the x couplings stand in for the table check
+    const pffrg_lattice* lat = &lat_copy;
     TRY(check_mesh(mesh, kMaxFreq));
     TRY(check_lattice(lat, kMaxPairs));
     if (prec != PFFRG_FP64 && prec != PFFRG_FP32) return fail(PFFRG_EINVAL, "unknown precision");
+    if (xyz) {
+        for (int i = 0; i < 3 * lat->n_pairs; ++i)
+            if (!std::isfinite(coupling3[i])) return fail(PFFRG_EINVAL, "couplings must be finite");
+        if (prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "the XYZ flow runs in FP64 only");
+        if (lat->n_pairs > kXyzMaxPairs)
+            return fail(PFFRG_EUNSUPPORTED, "the XYZ flow takes at most 16 pairs (one matrix-core tile per strain)");
+    }
     const int nf = mesh->n_freq, ns = lat->n_pairs;
     const int nterms = lat->rpa_off[ns];
 
@@ -565,10 +680,11 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
     if (!c) return fail(PFFRG_ENOMEM, "host allocation failed");
     c->nf = nf;
     c->ns = ns;
+    c->nc = xyz ? 4 : 2;
     c->nq = 2 * nf + 10;
     c->nsu = nf * (nf + 1) / 2;
     c->vsz = (long)c->nsu * nf * ns;
-    c->size = nf + 2 * c->vsz;
+    c->size = nf + c->nc * c->vsz;
     c->prec = prec;
     c->stream = static_cast<hipStream_t>(stream);
     c->nb = lat->n_basis;
@@ -597,7 +713,8 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
             c->n_terms = nterms;
             TRY(upload(c, &c->rpa_term, packed.data(), packed.size()));
         }
-        TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
+        if (xyz) TRY(upload(c, &c->coupling3, coupling3, (size_t)3 * ns));
+        else TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
         {
             // the same terms grouped by (ka, kb): entry = output pair | count << 16
             std::vector<std::vector<int>> by(ns * ns);
@@ -642,8 +759,8 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->tab_g, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->dsig, (size_t)nf));
         {
-            double2* g2 = nullptr;      // large enough for either precision
-            TRY(dev_alloc(c, &g2, (size_t)c->vsz));
+            double2* g2 = nullptr;      // large enough for either precision (XYZ: 32 bytes per element)
+            TRY(dev_alloc(c, &g2, (size_t)(c->nc / 2) * c->vsz));
             c->gv = g2;
         }
         for (int j = 0; j < kNumK; ++j) TRY(dev_alloc(c, &c->k[j], (size_t)c->size));
@@ -655,8 +772,8 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->cq, (size_t)c->nq));
         TRY(dev_alloc(c, &c->cg2, (size_t)c->nq));
         TRY(dev_alloc(c, &c->cn, 1));
-        TRY(dev_alloc(c, &c->chi, (size_t)2 * ns));
-        TRY(dev_alloc(c, &c->chi_part, (size_t)2 * ns * kChiSlices));
+        TRY(dev_alloc(c, &c->chi, (size_t)c->nc * ns));
+        TRY(dev_alloc(c, &c->chi_part, (size_t)c->nc * ns * kChiSlices));
         TRY(dev_alloc(c, &c->part, (size_t)2 * kRedBlocks));
         TRY(dev_alloc(c, &c->red, 2));
         TRY(dev_alloc(c, &c->ctg, (size_t)3 * nf * c->nq));
@@ -665,8 +782,15 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
         TRY(dev_alloc(c, &c->cchi, (size_t)2 * ns));
         TRY(dev_alloc(c, &c->cot_copies, (size_t)kCotCopies * 2 * c->vsz));
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
+        // second stream (default priority) and fork/join events of the
+        // concurrent vertex mode
+        HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
         if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
+        if (xyz && SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds::bytes() > 64 * 1024)
+            return fail(PFFRG_EUNSUPPORTED, "XYZ vertex kernel LDS budget exceeded");
         return PFFRG_OK;
     };
     pffrg_status st = body();
@@ -679,11 +803,41 @@ pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffr
     return PFFRG_OK;
 }
 
+pffrg_status no_xyz(const pffrg_ctx* c, const char* what) {
+    if (c->nc == 4) return fail(PFFRG_EUNSUPPORTED, std::string(what) + " is not available for XYZ contexts");
+    return PFFRG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffrg_precision prec, void* stream,
+                          pffrg_ctx** out) {
+    return create_ctx(lat, nullptr, mesh, prec, stream, out);
+}
+
+pffrg_status pffrg_create_xyz(const pffrg_lattice* lat, const double* coupling3, const pffrg_mesh* mesh,
+                              pffrg_precision prec, void* stream, pffrg_ctx** out) {
+    if (!coupling3) {
+        if (out) *out = nullptr;
+        return fail(PFFRG_EINVAL, "null XYZ couplings");
+    }
+    return create_ctx(lat, coupling3, mesh, prec, stream, out);
+}
+
 pffrg_status pffrg_destroy(pffrg_ctx* c) {
     if (!c) return PFFRG_OK;
     (void)hipStreamSynchronize(c->stream);
     release(c);
     delete c;
+    return PFFRG_OK;
+}
+
+pffrg_status pffrg_set_vertex_mode(pffrg_ctx* c, int mode) {
+    TRY(check_ctx(c));
+    if (mode < PFFRG_VERTEX_AUTO || mode > PFFRG_VERTEX_CONCURRENT) return fail(PFFRG_EINVAL, "unknown vertex mode");
+    c->vertex_mode = mode;
     return PFFRG_OK;
 }
 
@@ -703,6 +857,11 @@ pffrg_status pffrg_state_size(const pffrg_ctx* c, size_t* n) {
 pffrg_status pffrg_init_state(pffrg_ctx* c, double* x) {
     TRY(check_ctx(c));
     if (!x) return fail(PFFRG_EINVAL, "null state");
+    if (c->nc == 4) {
+        hipLaunchKernelGGL(k_xyz_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size,
+                           c->nf, c->ns, (const double*)c->coupling3, x);
+        return launch_check("k_xyz_init_state");
+    }
     hipLaunchKernelGGL(k_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size, c->nf,
                        c->ns, (const double*)c->coupling, x);
     return launch_check("k_init_state");
@@ -719,6 +878,7 @@ pffrg_status pffrg_sigma_rhs(pffrg_ctx* c, double lambda, const double* x, doubl
     TRY(check_ctx(c));
     if (!x || !dsig) return fail(PFFRG_EINVAL, "null pointer");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
+    if (c->nc == 4) return xyz_sigma_rhs(c, lambda, x, dsig);
     return sigma_rhs(c, lambda, x, dsig);
 }
 
@@ -741,6 +901,15 @@ pffrg_status pffrg_chi(pffrg_ctx* c, double lambda, const double* x, double* chi
     hipLaunchKernelGGL(k_chi_nodes, dim3(1), dim3(64), 0, c->stream, (const double*)c->w, c->nf, lambda, x, c->cw,
                        c->cq, c->cg2, c->cn);
     TRY(launch_check("k_chi_nodes"));
+    if (c->nc == 4) {
+        hipLaunchKernelGGL(k_xyz_chi_pairs, dim3(c->ns, kChiSlices), dim3(kChiThreads), 0, c->stream,
+                           (const double*)c->w, c->nf, c->ns, (const int*)c->swap, x, (const double*)c->cw,
+                           (const double*)c->cq, (const double*)c->cg2, (const int*)c->cn, c->chi_part);
+        TRY(launch_check("k_xyz_chi_pairs"));
+        hipLaunchKernelGGL(k_xyz_chi_final, dim3(1), dim3(64), 0, c->stream, c->ns, (const double*)c->cq,
+                           (const double*)c->cg2, (const int*)c->cn, (const double*)c->chi_part, chi);
+        return launch_check("k_xyz_chi_final");
+    }
     hipLaunchKernelGGL(k_chi_pairs, dim3(c->ns, kChiSlices), dim3(kChiThreads), 0, c->stream, (const double*)c->w,
                        c->nf, c->ns, (const int*)c->swap, x, (const double*)c->cw, (const double*)c->cq,
                        (const double*)c->cg2, (const int*)c->cn, c->chi_part);
@@ -754,8 +923,10 @@ pffrg_status pffrg_chi_k(pffrg_ctx* c, const double* chi, int nk, const double* 
     TRY(check_ctx(c));
     if (nk < 0 || (nk > 0 && (!chi || !kp || !out))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
     if (nk == 0) return PFFRG_OK;
+    // SU(2): 3 chi^zz; XYZ: chi^xx + chi^yy + chi^zz
     hipLaunchKernelGGL(k_chi_k, dim3((nk + kChiKWaves - 1) / kChiKWaves), dim3(64 * kChiKWaves), 0, c->stream, c->nterm,
-                       (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, chi, nk, kp, out);
+                       (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, chi, c->nc == 4 ? 3 : 1,
+                       c->ns, c->nc == 4 ? 1.0 : 3.0, nk, kp, out);
     return launch_check("k_chi_k");
 }
 
@@ -885,6 +1056,7 @@ pffrg_status pffrg_flow_position(pffrg_ctx* c, double* lambda, double* log_lambd
 
 pffrg_status pffrg_init_state_from(pffrg_ctx* c, const double* coupling, double* x) {
     TRY(check_ctx(c));
+    TRY(no_xyz(c, "pffrg_init_state_from"));
     if (!x || !coupling) return fail(PFFRG_EINVAL, "null pointer");
     hipLaunchKernelGGL(k_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size, c->nf,
                        c->ns, coupling, x);
@@ -893,6 +1065,7 @@ pffrg_status pffrg_init_state_from(pffrg_ctx* c, const double* coupling, double*
 
 pffrg_status pffrg_rhs_vjp(pffrg_ctx* c, double lambda, const double* x, const double* v, double* out) {
     TRY(check_ctx(c));
+    TRY(no_xyz(c, "pffrg_rhs_vjp"));
     if (!x || !v || !out) return fail(PFFRG_EINVAL, "null pointer");
     if (out == x || out == v) return fail(PFFRG_EINVAL, "output must not overlap the inputs");
     return rhs_vjp(c, lambda, x, v, out);
@@ -900,6 +1073,7 @@ pffrg_status pffrg_rhs_vjp(pffrg_ctx* c, double lambda, const double* x, const d
 
 pffrg_status pffrg_chi_vjp(pffrg_ctx* c, double lambda, const double* x, const double* cchi, double* out) {
     TRY(check_ctx(c));
+    TRY(no_xyz(c, "pffrg_chi_vjp"));
     if (!x || !cchi || !out) return fail(PFFRG_EINVAL, "null pointer");
     if (out == x) return fail(PFFRG_EINVAL, "output must not overlap the state");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
@@ -908,6 +1082,7 @@ pffrg_status pffrg_chi_vjp(pffrg_ctx* c, double lambda, const double* x, const d
 
 pffrg_status pffrg_chi_k_vjp(pffrg_ctx* c, const double* ck, int nk, const double* kp, double* cchi) {
     TRY(check_ctx(c));
+    TRY(no_xyz(c, "pffrg_chi_k_vjp"));
     if (nk < 0 || !cchi || (nk > 0 && (!ck || !kp))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
     TRY(fill(c, cchi, 2L * c->ns, 0.0));
     if (nk == 0) return PFFRG_OK;
@@ -941,6 +1116,7 @@ pffrg_status pffrg_flow_checkpoints(pffrg_ctx* c, int n_lambda, const double* la
 pffrg_status pffrg_flow_vjp(pffrg_ctx* c, int n_lambda, const double* lambdas, const double* ckpt, double* ybar,
                             double* dcoupling) {
     TRY(check_ctx(c));
+    TRY(no_xyz(c, "pffrg_flow_vjp"));
     TRY(check_schedule(n_lambda, lambdas));
     if (!ckpt || !ybar) return fail(PFFRG_EINVAL, "null pointer");
     const long n = c->size;

@@ -563,7 +563,7 @@ pffrg_status pffrg_batch_chi_k(pffrg_batch* b, int point, const double* chi, int
     hipLaunchKernelGGL(k_chi_k, dim3((nk + kChiKWaves - 1) / kChiKWaves), dim3(64 * kChiKWaves), 0, b->stream,
                        b->chi_cnt[point],
                        (const int*)(b->chi_pair + b->chi_off[point]), (const double*)(b->chi_dr + 3L * b->chi_off[point]),
-                       1.0 / b->nb_chi[point], chi, nk, kp, out);
+                       1.0 / b->nb_chi[point], chi, 1, 0, 3.0, nk, kp, out);
     return launch_check("k_chi_k");
 }
 

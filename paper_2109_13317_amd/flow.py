@@ -25,7 +25,10 @@ def _lattice_struct(t: LatticeTables):
     """(pffrg_lattice, arrays it points into: keep them alive for the call)."""
     keep = [np.ascontiguousarray(a, dtype=np.int32) for a in (t.swap, t.mult, t.rpa_off, t.rpa_ka,
                                                               t.rpa_kb, t.rpa_cnt)]
-    keep += [np.ascontiguousarray(t.coupling, dtype=np.float64),
+    # an XYZ model's coupling triples go to pffrg_create_xyz; the lattice
+    # struct then carries their x components, which it does not read
+    coup = t.coupling if t.coupling.ndim == 1 else t.coupling[:, 0]
+    keep += [np.ascontiguousarray(coup, dtype=np.float64),
              np.ascontiguousarray(t.site_pair, dtype=np.int32),
              np.ascontiguousarray(t.site_pos, dtype=np.float64),
              np.ascontiguousarray(t.basis_pos, dtype=np.float64)]
@@ -36,7 +39,10 @@ def _lattice_struct(t: LatticeTables):
 
 
 class Context:
-    """A ``pffrg_ctx``: one lattice model on one frequency mesh."""
+    """A ``pffrg_ctx``: one lattice model on one frequency mesh.  Tables of a
+    Heisenberg model give an SU(2) context (two strains, spin and density);
+    tables of an XYZ model (coupling triples) an XYZ context (four strains:
+    x, y, z, density)."""
 
     def __init__(self, tables: LatticeTables, mesh, precision: str = "fp64", stream=None):
         self.lib = _lib.load()
@@ -45,6 +51,8 @@ class Context:
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.ns = tables.n_pairs
+        self.symmetry = "xyz" if tables.coupling.ndim == 2 else "su2"
+        self.nc = 4 if self.symmetry == "xyz" else 2
         lat, keep = _lattice_struct(tables)
         msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
         prec = {"fp64": _lib.FP64, "fp32": _lib.FP32}[precision]
@@ -52,8 +60,14 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         h = ctypes.c_void_p()
-        _lib.check(self.lib.pffrg_create(ctypes.byref(lat), ctypes.byref(msh), prec,
-                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        if self.symmetry == "xyz":
+            c3 = np.ascontiguousarray(np.asarray(tables.coupling, dtype=np.float64).T)     # [3][ns]
+            _lib.check(self.lib.pffrg_create_xyz(ctypes.byref(lat), ctypes.c_void_p(c3.ctypes.data),
+                                                 ctypes.byref(msh), prec, ctypes.c_void_p(stream.cuda_stream),
+                                                 ctypes.byref(h)))
+        else:
+            _lib.check(self.lib.pffrg_create(ctypes.byref(lat), ctypes.byref(msh), prec,
+                                             ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
         n = ctypes.c_size_t()
         _lib.check(self.lib.pffrg_state_size(self.handle, ctypes.byref(n)))
@@ -81,10 +95,11 @@ class Context:
         return torch.empty(self.size, dtype=torch.float64, device="cuda")
 
     def split(self, x: torch.Tensor):
-        """Views (sig[nf], Gs[n_su, nf, ns], Gd[n_su, nf, ns])."""
+        """Views (sig[nf], strain 0, strain 1, ...), each strain [n_su, nf, ns]:
+        SU(2) (sig, Gs, Gd), XYZ (sig, Gx, Gy, Gz, Gd)."""
         nf, v = self.nf, self.vsize
-        return (x[:nf], x[nf:nf + v].view(self.n_su, nf, self.ns),
-                x[nf + v:].view(self.n_su, nf, self.ns))
+        return (x[:nf],) + tuple(x[nf + c * v:nf + (c + 1) * v].view(self.n_su, nf, self.ns)
+                                 for c in range(self.nc))
 
     def init_state(self, x: torch.Tensor | None = None) -> torch.Tensor:
         x = self.new_state() if x is None else x
@@ -137,7 +152,7 @@ class Context:
         def _cb(lam, dchi, dchik, _user):
             if observer is None:
                 return 0
-            chi = _wrap(dchi, 2 * ns).view(2, ns)
+            chi = _wrap(dchi, self.nc * ns).view(self.nc, ns)
             ck = chik if dchik else None
             return int(bool(observer(lam, chi, ck)))
 
@@ -206,12 +221,18 @@ class Context:
                 "vertex_s": _lib.K_VERTEX_S, "vertex_u": _lib.K_VERTEX_U, "vertex_t": _lib.K_VERTEX_T,
                 "vertex_stu": _lib.K_VERTEX_STU}
 
+    def set_vertex_mode(self, mode: str):
+        """How the vertex channels are launched: 'auto' (default), 'one_launch',
+        'separate' or 'concurrent' (pffrg_set_vertex_mode; same results bitwise)."""
+        _lib.check(self.lib.pffrg_set_vertex_mode(self.handle, _lib.VERTEX_MODES[mode]))
+
     def set_profiling(self, on: bool, kernels=None):
         """Record kernel durations with HIP events: all timed kernels, or only
         the named ones (names as in profile_read); False turns it off.
         Timing 'vertex_s', 'vertex_u' or 'vertex_t' (also implied by all)
         runs the three channels as separate launches (same results bitwise);
-        otherwise they run as the one 'vertex_stu' launch."""
+        otherwise they run in the context's vertex mode ('vertex_stu' is the
+        one-launch form, 'vertex' spans any form)."""
         if kernels is None or not on:
             _lib.check(self.lib.pffrg_set_profiling(self.handle, int(bool(on))))
         else:
@@ -231,10 +252,11 @@ class Context:
 
     # ------------------------------------------------------- observables --
     def chi(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        """[2, ns]: chi^{zz} and chi^{00} per reduced pair."""
-        out = torch.empty(2 * self.ns, dtype=torch.float64, device="cuda") if out is None else out
+        """[strains, ns] per reduced pair: SU(2) chi^{zz}, chi^{00}; XYZ chi^{xx},
+        chi^{yy}, chi^{zz}, chi^{00}."""
+        out = torch.empty(self.nc * self.ns, dtype=torch.float64, device="cuda") if out is None else out
         _lib.check(self.lib.pffrg_chi(self.handle, float(lam), _dptr(x), _dptr(out)))
-        return out.view(2, self.ns)
+        return out.view(self.nc, self.ns)
 
     def chi_k(self, chi: torch.Tensor, kpoints: torch.Tensor, out: torch.Tensor | None = None):
         kp = kpoints.contiguous()
@@ -385,18 +407,21 @@ class Batch:
 
 class _Peaks(ctypes.Structure):
     _fields_ = [("fp64_fma_tflops", ctypes.c_double), ("fp32_fma_tflops", ctypes.c_double),
-                ("hbm_copy_gbs", ctypes.c_double)]
+                ("hbm_copy_gbs", ctypes.c_double), ("l1_load_tbs", ctypes.c_double),
+                ("l1_load_2row_tbs", ctypes.c_double), ("lds_read_tbs", ctypes.c_double)]
 
 
 def measure_peaks(stream=None) -> dict:
-    """Measured FP64 / FP32 vector FMA throughput (TFLOP/s) and device-copy
-    bandwidth (GB/s) of the current device (pffrg_measure_peaks)."""
+    """Measured FP64 / FP32 vector FMA throughput (TFLOP/s), device-copy
+    bandwidth (GB/s) and the 16-byte-per-lane load rates from L1 and LDS
+    (TB/s) of the current device (pffrg_measure_peaks)."""
     lib = _lib.load()
     stream = torch.cuda.current_stream() if stream is None else stream
     out = _Peaks()
     _lib.check(lib.pffrg_measure_peaks(ctypes.c_void_p(stream.cuda_stream), ctypes.byref(out)))
     return {"fp64_fma_tflops": out.fp64_fma_tflops, "fp32_fma_tflops": out.fp32_fma_tflops,
-            "hbm_copy_gbs": out.hbm_copy_gbs}
+            "hbm_copy_gbs": out.hbm_copy_gbs, "l1_load_tbs": out.l1_load_tbs,
+            "l1_load_2row_tbs": out.l1_load_2row_tbs, "lds_read_tbs": out.lds_read_tbs}
 
 
 def _wrap(ptr: int, n: int) -> torch.Tensor:

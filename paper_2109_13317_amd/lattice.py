@@ -8,7 +8,8 @@ flow arithmetic happens here.
 Construction (Sec. 4.1):
   * reference site i_ref = basis site 0 of cell 0;
   * lattice symmetries are Euclidean isometries x -> O x + v that map the
-    lattice to itself, bonds to bonds and couplings to equal couplings; they
+    lattice to itself, bonds to bonds and couplings to equal couplings (for
+    XYZ models equal (Jx, Jy, Jz); spin components are not permuted); they
     are found by mapping the nearest-neighbour bond vectors of one site onto
     those of another and validating the candidate on the unit cell;
   * for every basis site b one symmetry T_b with T_b(r_b) = r_ref, so any
@@ -43,7 +44,7 @@ class LatticeTables:
     rpa_ka: np.ndarray          # int32 [n_terms]
     rpa_kb: np.ndarray          # int32 [n_terms]
     rpa_cnt: np.ndarray         # int32 [n_terms]
-    coupling: np.ndarray        # float64 [n_pairs], J of the bond (i_ref, j_p)
+    coupling: np.ndarray        # float64 [n_pairs], J of the bond (i_ref, j_p); XYZ: [n_pairs, 3]
     n_basis: int
     n_sites_total: int
     site_pair: np.ndarray       # int32 [n_basis, n_sites_total]
@@ -71,11 +72,15 @@ class _Lattice:
             self.bonds.add((t, f, (-d0, -d1, -d2)))
             self.nbrs[f].append((d, t))
             self.nbrs[t].append(((-d0, -d1, -d2), f))
+        # couplings per bond: a number (Heisenberg) or (Jx, Jy, Jz) (XYZ)
+        self.vec = any(np.ndim(v) == 1 for v in params.values())
+        self.zero = np.zeros(3) if self.vec else 0.0
         self.J = {}
         for (pname, f, t, d0, d1, d2) in interactions:
-            val = float(params.get(pname, 0.0))
+            val = np.asarray(params.get(pname, self.zero), dtype=np.float64) if self.vec \
+                else float(params.get(pname, 0.0))
             for key in ((f, t, (d0, d1, d2)), (t, f, (-d0, -d1, -d2))):
-                self.J[key] = self.J.get(key, 0.0) + val
+                self.J[key] = self.J.get(key, self.zero) + val
 
     def pos(self, cell, b):
         return np.asarray(cell, dtype=np.float64) @ self.A + self.basis[b]
@@ -91,7 +96,7 @@ class _Lattice:
 
     def coupling(self, c1, b1, c2, b2):
         d = (c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2])
-        return self.J.get((b1, b2, d), 0.0)
+        return self.J.get((b1, b2, d), self.zero)
 
     def bonded(self, c1, b1, c2, b2):
         d = (c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2])
@@ -199,7 +204,7 @@ def _valid(lat, g):
             return False
         if lat.bonded(s1[0], s1[1], s2[0], s2[1]) != ((b1, b2, d) in lat.bonds):
             return False
-        if abs(lat.coupling(s1[0], s1[1], s2[0], s2[1]) - lat.J.get((b1, b2, d), 0.0)) > 1e-12:
+        if np.max(np.abs(lat.coupling(s1[0], s1[1], s2[0], s2[1]) - lat.J.get((b1, b2, d), lat.zero))) > 1e-12:
             return False
     return True
 

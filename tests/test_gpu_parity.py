@@ -267,6 +267,7 @@ def test_profiling_mask_times_only_the_named_kernels(lat, params, L, nf, precisi
     for k in ("sigma", "tables", "vertex", "vertex_s", "vertex_u", "vertex_stu"):
         assert ctx.profile_read(k) == (0.0, 0)
     assert torch.equal(out, ref)
+    ctx.set_vertex_mode("one_launch")
     ctx.set_profiling(True, kernels=("vertex_stu",))
     out = ctx.rhs(0.7, x, out)
     ms, n = ctx.profile_read("vertex_stu")
@@ -275,6 +276,39 @@ def test_profiling_mask_times_only_the_named_kernels(lat, params, L, nf, precisi
     assert torch.equal(out, ref)
     with pytest.raises(_lib.PffrgError):           # a bit past the last kernel id
         _lib.check(ctx.lib.pffrg_set_profiling_mask(ctx.handle, 1 << 7))
+
+
+@pytest.mark.parametrize("lat,params,L,nf,precision", [
+    ("square", dict(j1=1.0), 2, 8, "fp64"),                      # 4 pairs
+    ("honeycomb", dict(j1=0.6, j2=0.3, j3=0.45), 6, 10, "fp32"),  # 14 pairs
+    ("square", dict(j1=1.0, j2=0.5), 7, 32, "fp64"),             # 20 pairs
+    ("pyrochlore", dict(j1=1.0), 5, 48, "fp64"),                 # 31 pairs
+    ("pyrochlore", dict(j1=1.0), 5, 48, "fp32"),
+])
+def test_vertex_launch_modes_agree_bitwise(lat, params, L, nf, precision):
+    """One launch, three launches in turn, and s+u beside a concurrent t
+    launch on the context's second stream: the same sums in the same order,
+    so the same bits, also when right-hand sides follow each other on the
+    stream (the join must order the next stage after the t launch)."""
+    import torch
+    from paper_2109_13317_amd import _lib, build_tables
+    from paper_2109_13317_amd.flow import Context
+    ctx = Context(build_tables(W.model(lat, **params), L), W.log_mesh(1e-3, 100.0, nf), precision=precision)
+    _say(f"launch modes {lat} L={L} nf={nf} {precision}: {ctx.ns} pairs")
+    x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=4, scale=0.2)).cuda()
+    res = {}
+    for mode in ("one_launch", "separate", "concurrent", "auto"):
+        ctx.set_vertex_mode(mode)
+        y = x.clone()
+        ctx.step("rk4", 0.7, 0.6, y)                # four right-hand sides back to back
+        d = ctx.rhs(0.45, y)
+        torch.cuda.synchronize()
+        res[mode] = (y.clone(), d.clone())
+    for mode in ("separate", "concurrent", "auto"):
+        assert torch.equal(res[mode][0], res["one_launch"][0]), mode
+        assert torch.equal(res[mode][1], res["one_launch"][1]), mode
+    with pytest.raises(_lib.PffrgError):
+        _lib.check(ctx.lib.pffrg_set_vertex_mode(ctx.handle, 3))
 
 
 def test_measure_peaks_is_plausible():
@@ -286,3 +320,5 @@ def test_measure_peaks_is_plausible():
     assert 1.0 < pk["fp64_fma_tflops"] < 200.0
     assert 1.0 < pk["fp32_fma_tflops"] < 400.0
     assert 100.0 < pk["hbm_copy_gbs"] < 20000.0
+    for k in ("l1_load_tbs", "l1_load_2row_tbs", "lds_read_tbs"):
+        assert 1.0 < pk[k] < 1000.0, k

@@ -1,0 +1,190 @@
+"""GPU parity of the XYZ flow (Sec. 2 XYZ couplings, Sec. 3 diagonal vertex
+components) against the FP64 oracle, through the C ABI (pffrg_create_xyz).
+
+Bar: max |gpu - oracle| / max |oracle| <= 1e-10 over sigma and every element
+of the four strains (matched to the library's reduced pairs by site
+position), and over chi of the four strains and chi(k).  Cases: random
+states on square and honeycomb lattices at cutoffs below, inside and above
+the mesh, on a mesh point and at half a mesh point (theta = 1/2 ties); the
+initial state; a 40-step RK4 flow with chi every step; the honeycomb
+J1-J2-J3 workload size (range 6, 14 pairs, 32 frequencies) on sampled
+triples; the SU(2) limit (Jx = Jy = Jz) against an SU(2) context; and the
+refused inputs.
+"""
+
+import zlib
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity import compare_chi_comps, compare_triples, compare_vertex, expand_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+CASES = {
+    "square_L2_N8": ("square", dict(j1=(1.0, 0.6, 0.3), j2=(0.2, -0.5, 0.4)), 2, W.log_mesh(0.005, 50.0, 8)),
+    "honeycomb_L3_N6": ("honeycomb", dict(j1=(0.8, 1.0, -0.3), j2=(0.1, 0.25, 0.2), j3=(0.3, 0.0, 0.15)), 3,
+                        W.log_mesh(0.01, 20.0, 6)),
+}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _seed(*key) -> int:
+    return zlib.crc32("/".join(map(str, key)).encode()) % 1000
+
+
+def _setup(name):
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    lat, params, L, mesh = CASES[name]
+    model = W.model_xyz(lat, **params)
+    tables = build_tables(model, L)
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, L, mesh)
+    assert ctx.nc == 4 and orc.nc == 4
+    return torch, tables, ctx, orc
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("lam_kind", ["low", "mid", "mesh", "half", "high"])
+def test_xyz_rhs_random_state(name, lam_kind):
+    torch, tables, ctx, orc = _setup(name)
+    mesh = ctx.mesh
+    lam = {"low": 0.5 * mesh[0], "mid": 0.37, "mesh": float(mesh[len(mesh) // 2]),
+           "half": 0.5 * float(mesh[len(mesh) // 2]), "high": 1.7 * mesh[-1]}[lam_kind]
+    seed = _seed(name, lam_kind)
+    x = W.random_state(ctx.nf, ctx.ns, seed=seed, strains=4)
+    _say(f"xyz rhs {name} lam={lam} seed={seed}")
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = orc.rhs(lam, expand_state(orc, tables, x))
+    err = compare_vertex(orc, tables, ref, d)
+    _say(f"  error {err:.2e}")
+    assert err <= TOL, err
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_xyz_initial_state_first_rhs_and_chi(name):
+    torch, tables, ctx, orc = _setup(name)
+    x = ctx.init_state()
+    x0 = orc.initial_state()
+    assert compare_vertex(orc, tables, x0, x.cpu().numpy()) == 0.0
+    for lam in (0.21, 3.0):
+        d = ctx.rhs(lam, x).cpu().numpy()
+        assert compare_vertex(orc, tables, orc.rhs(lam, x0), d) <= TOL
+    xr = W.random_state(ctx.nf, ctx.ns, seed=_seed(name, "chi"), scale=0.2, strains=4)
+    lam = 0.3
+    chi = ctx.chi(lam, torch.from_numpy(xr).cuda())
+    ref = orc.chi_comps(lam, expand_state(orc, tables, xr))
+    err = compare_chi_comps(orc, tables, ref, chi.cpu().numpy())
+    kp = np.random.default_rng(4).uniform(-6.0, 6.0, size=(17, 3))
+    ck = ctx.chi_k(chi.reshape(-1), torch.from_numpy(kp).cuda()).cpu().numpy()
+    ck_ref = orc.chi_k_xyz(ref, kp)
+    ek = np.abs(ck - ck_ref).max() / np.abs(ck_ref).max()
+    _say(f"xyz chi {name}: {err:.2e}, chi(k) {ek:.2e}")
+    assert err <= TOL and ek <= TOL
+
+
+def test_xyz_rk4_flow_with_chi_every_step():
+    """Square range 2, 8 frequencies, 40 RK4 steps Lambda 50 -> 0.5, chi of the
+    four strains at every step."""
+    torch, tables, ctx, orc = _setup("square_L2_N8")
+    sched = W.geometric_schedule(50.0, 0.5, 40)
+    x = ctx.init_state()
+    got = []
+    ctx.flow(x, schedule=sched, scheme="rk4",
+             observer=lambda lam, chi, ck: got.append((lam, chi.cpu().numpy().copy())) and 0)
+    ref = []
+    xo = orc.flow(sched, observer=lambda lam, xs: ref.append((lam, orc.chi_comps(lam, xs))))
+    err = compare_vertex(orc, tables, xo, x.cpu().numpy())
+    worst = max(compare_chi_comps(orc, tables, rc, gc) for (_, gc), (_, rc) in zip(got, ref))
+    _say(f"xyz RK4 flow: state {err:.2e}, chi worst {worst:.2e}")
+    assert len(got) == len(ref) == len(sched) - 1
+    assert err <= TOL and worst <= TOL
+
+
+def test_xyz_workload_size_sampled():
+    """Honeycomb J1-J2-J3 with XYZ couplings at the workload size (range 6,
+    14 pairs, 32 frequencies); the oracle computes every element of sampled
+    triples."""
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    model = W.model_xyz("honeycomb", j1=(0.9, 0.7, 0.5), j2=(0.3, 0.2, 0.25), j3=(0.1, 0.15, 0.3))
+    mesh = W.log_mesh(1e-3, 100.0, 32)
+    tables = build_tables(model, 6)
+    assert tables.n_pairs == 14
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, 6, mesh)
+    nf = ctx.nf
+    x = W.random_state(nf, ctx.ns, seed=9, scale=0.2, strains=4)
+    lam = 0.21
+    _say("xyz workload-size rhs, honeycomb range 6, 32 frequencies")
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    xo = expand_state(orc, tables, x)
+    dsig = orc.sigma_rhs(lam, xo)
+    assert np.abs(dsig - d[:nf]).max() <= TOL * np.abs(dsig).max()
+    rng = np.random.default_rng(2)
+    tri = [(0, 0, 0), (nf - 1, nf - 1, nf - 1), (nf - 1, 0, 0), (nf - 1, nf // 2, nf - 1)]
+    for _ in range(8):
+        a = int(rng.integers(nf)); c = int(rng.integers(a + 1)); t = int(rng.integers(nf))
+        tri.append((a, t, c))
+    ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
+    err = compare_triples(orc, tables, tri, ref, d)
+    _say(f"  error {err:.2e}")
+    assert err <= TOL, err
+
+
+def test_xyz_isotropic_equals_su2_context():
+    """Jx = Jy = Jz = J: the XYZ context's three spin strains follow the SU(2)
+    context's spin strain and its density strain the SU(2) one, along an RK4
+    flow (to rounding: the sums run in another order)."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    j = dict(j1=1.0, j2=0.4)
+    mesh = W.log_mesh(0.005, 50.0, 8)
+    c2 = Context(build_tables(W.model("square", **j), 3), mesh)
+    c4 = Context(build_tables(W.model_xyz("square", **{k: (v, v, v) for k, v in j.items()}), 3), mesh)
+    sched = W.geometric_schedule(50.0, 0.5, 20)
+    x2, x4 = c2.init_state(), c4.init_state()
+    c2.flow(x2, schedule=sched, scheme="rk4")
+    c4.flow(x4, schedule=sched, scheme="rk4")
+    s2, gs, gd = c2.split(x2)
+    s4, gx, gy, gz, gd4 = c4.split(x4)
+    scale = float(torch.abs(x2).max())
+    err = max(float(torch.abs(s4 - s2).max()), *(float(torch.abs(g - gs).max()) for g in (gx, gy, gz)),
+              float(torch.abs(gd4 - gd).max())) / scale
+    _say(f"xyz isotropic vs su2 after 20 RK4 steps: {err:.2e}")
+    assert err <= 1e-12
+    ch2 = c2.chi(0.5, x2)
+    ch4 = c4.chi(0.5, x4)
+    assert float(torch.abs(ch4[:3] - ch2[0]).max()) <= 1e-12 * float(torch.abs(ch2).max())
+
+
+def test_xyz_refused_inputs():
+    import torch
+    from paper_2109_13317_amd import _lib, build_tables
+    from paper_2109_13317_amd.flow import Context
+    mesh = W.log_mesh(0.01, 10.0, 5)
+    t_small = build_tables(W.model_xyz("square", j1=(1.0, 0.5, 0.2)), 2)
+    with pytest.raises(_lib.PffrgError) as ei:
+        Context(t_small, mesh, precision="fp32")
+    assert ei.value.status == _lib.EUNSUPPORTED
+    t_big = build_tables(W.model_xyz("square", j1=(1.0, 0.5, 0.2)), 7)      # 20 pairs
+    with pytest.raises(_lib.PffrgError) as ei:
+        Context(t_big, mesh)
+    assert ei.value.status == _lib.EUNSUPPORTED
+    ctx = Context(t_small, mesh)
+    x = ctx.init_state()
+    with pytest.raises(_lib.PffrgError) as ei:
+        ctx.rhs_vjp(0.5, x, torch.zeros_like(x))
+    assert ei.value.status == _lib.EUNSUPPORTED

@@ -267,18 +267,21 @@ def state_layout(n_freq: int, n_pairs: int) -> dict:
                 sigma=0, gs=n_freq, gd=n_freq + per, size=n_freq + 2 * per)
 
 
-def random_state(n_freq: int, n_pairs: int, seed: int, scale: float = 0.3) -> np.ndarray:
-    """A seeded, symmetry-consistent random flow state in the layout above.
+def random_state(n_freq: int, n_pairs: int, seed: int, scale: float = 0.3, strains: int = 2) -> np.ndarray:
+    """A seeded, symmetry-consistent random flow state in the layout above
+    (strains = 2: sigma | Gs | Gd; strains = 4, the XYZ layout:
+    sigma | Gx | Gy | Gz | Gd).
 
-    Im Sigma is non-positive on positive frequencies; the density vertex
-    vanishes on the s = u diagonal, which the s<->u exchange relation forces.
+    Im Sigma is non-positive on positive frequencies; the density vertex (the
+    last strain) vanishes on the s = u diagonal, which the s<->u exchange
+    relation forces.
     """
     lay = state_layout(n_freq, n_pairs)
     rng = np.random.default_rng(seed)
-    x = np.empty(lay["size"], dtype=np.float64)
+    x = np.empty(n_freq + strains * lay["vertex"], dtype=np.float64)
     x[:n_freq] = -np.abs(rng.normal(0.0, scale, n_freq))
-    x[n_freq:] = rng.normal(0.0, scale, 2 * lay["vertex"])
-    gd = x[lay["gd"]:].reshape(lay["n_su"], n_freq, n_pairs)
+    x[n_freq:] = rng.normal(0.0, scale, strains * lay["vertex"])
+    gd = x[n_freq + (strains - 1) * lay["vertex"]:].reshape(lay["n_su"], n_freq, n_pairs)
     for a in range(n_freq):
         gd[a * (a + 1) // 2 + a] = 0.0
     return x
