@@ -234,19 +234,42 @@ def fp32_leg(tables, wl, x_np, lam, reps=10):
             "lambda": lam}
 
 
+def _fp64_steps(ctx, sched, kp):
+    """A plain FP64 flow along sched one step at a time (untimed): per step
+    the cutoff, chi, max chi(k) over kp and max |vertex|; stops at the first
+    step whose state is not finite (the library restores the last finite
+    state and reports it)."""
+    import torch
+    from paper_2109_13317_amd._lib import PffrgError
+    x = ctx.init_state()
+    rec = []
+    for i in range(len(sched) - 1):
+        try:
+            ctx.flow(x, schedule=sched[i:i + 2], scheme="rk4")
+        except PffrgError:
+            break
+        chi = ctx.chi(sched[i + 1], x)
+        rec.append((sched[i + 1], chi.cpu().numpy(), float(ctx.chi_k(chi.reshape(-1), kp).max()),
+                    float(torch.abs(x[ctx.nf:]).max())))
+    return rec
+
+
 def batch_leg():
     """64-point square J1-J2 scan (J2/J1 = k/63, ranges 4..7, 24 frequencies),
     RK4 100 -> 0.01 in 120 steps: one FP32 batch (persistent vertex launch,
-    hipGraph step, tuned launch shape) against 64 sequential plain FP64 flows."""
+    hipGraph step, tuned launch shape) against 64 sequential plain FP64 flows
+    (both timed), then both again step by step (untimed) for every point's
+    breakdown, last finite cutoff and chi error against FP64."""
     import torch
     from paper_2109_13317_amd import build_tables
     from paper_2109_13317_amd.flow import Batch, Context
     from paper_2109_13317_amd._lib import PffrgError
+    from paper_2109_13317_amd.breakdown import batch_breakdowns, find_breakdown
     wl = W.workload("square_scan")
     pts = W.batch_scan_points(64)
     tables = [build_tables(W.model("square", j1=q["j1"], j2=q["j2"]), q["range"]) for q in pts]
-    sched = wl.schedule
-    cut = [l for l in sched if l >= 1.0]
+    sched = [float(v) for v in wl.schedule]
+    lam_max = wl.mesh[-1] / 4
     b = Batch(tables, wl.mesh, precision="fp32")
     x = b.init_state()
     tuned = b.tune(0.5, x)
@@ -257,25 +280,7 @@ def batch_leg():
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     log(f"batch scan flow {t_batch:.3f} s ({sum(ok)} of 64 points finite)")
-    chi_f = [c.cpu().numpy() for c in b.chi(sched[-1], x)]
-    x1 = b.init_state()
-    b.flow(x1, cut)
-    chi_1 = [c.cpu().numpy() for c in b.chi(cut[-1], x1)]
-    # the scan's phase diagram: the same flow again, untimed, step by step
-    # with chi(k) of every point on a 32 x 32 grid after every step, and each
-    # point's breakdown (a kink or divergence of chi_max(Lambda))
-    from paper_2109_13317_amd.breakdown import batch_breakdowns
-    g = 2 * np.pi * (np.arange(32) / 32 - 0.5)
-    kx, ky = np.meshgrid(g, g, indexing="ij")
-    kp32 = torch.from_numpy(np.stack([kx.ravel(), ky.ravel(), np.zeros(kx.size)], 1).copy()).cuda()
-    bds, _, _ = batch_breakdowns(b, b.init_state(), sched, kp32, lam_max=wl.mesh[-1] / 4)
-    phase = [{"j2_over_j1": q["j2"] / q["j1"], "range": q["range"], "breakdown": bd.kind,
-              "lambda_c": bd.lam} for q, bd in zip(pts, bds)]
-    log("batch scan breakdowns: " + ", ".join(f"{d['j2_over_j1']:.2f}/{d['range']}:"
-                                              f"{d['lambda_c'] if d['lambda_c'] is None else round(d['lambda_c'], 3)}"
-                                              for d in phase[::8]))
-    b.close()
-    seq_ok, seq_chi_f, seq_chi_1 = [], [], []
+    seq_ok = []
     t_seq = 0.0
     for t in tables:
         c = Context(t, wl.mesh)
@@ -290,27 +295,76 @@ def batch_leg():
         torch.cuda.synchronize()
         t_seq += time.perf_counter() - t0
         seq_ok.append(fin)
-        seq_chi_f.append(c.chi(sched[-1], xs).cpu().numpy() if fin else None)
-        xs = c.init_state()
-        c.flow(xs, schedule=cut, scheme="rk4")
-        seq_chi_1.append(c.chi(cut[-1], xs).cpu().numpy())
         c.close()
-    log(f"64 sequential FP64 flows {t_seq:.3f} s")
-    e1 = [float(np.abs(chi_1[p] - seq_chi_1[p]).max() / np.abs(seq_chi_1[p]).max()) for p in range(64)]
-    ef = [float(np.abs(chi_f[p] - seq_chi_f[p]).max() / np.abs(seq_chi_f[p]).max())
-          for p in range(64) if ok[p] and seq_ok[p]]
+    log(f"64 sequential FP64 flows {t_seq:.3f} s ({sum(seq_ok)} of 64 points finite)")
+    # untimed: both again step by step; chi(k) on 32 x 32 points after every
+    # step for the breakdown detector (a kink or divergence of chi_max(Lambda))
+    g = 2 * np.pi * (np.arange(32) / 32 - 0.5)
+    kx, ky = np.meshgrid(g, g, indexing="ij")
+    kp32 = torch.from_numpy(np.stack([kx.ravel(), ky.ravel(), np.zeros(kx.size)], 1).copy()).cuda()
+    rec32 = []
+    bds, lams, _ = batch_breakdowns(b, b.init_state(), sched, kp32, lam_max=lam_max, record=rec32)
+    b.close()
+    points = []
+    for p, (q, t) in enumerate(zip(pts, tables)):
+        c = Context(t, wl.mesh)
+        r64 = _fp64_steps(c, sched, kp32)
+        c.close()
+        n64 = len(r64)                       # finite FP64 steps
+        n32 = 0                              # finite FP32 steps (the state stays non-finite once it is)
+        while n32 < len(rec32) and rec32[n32][1][p]:
+            n32 += 1
+        bd64 = find_breakdown([r[0] for r in r64], [r[2] for r in r64], lam_max=lam_max)
+        # the last step above either precision's breakdown (or the last step
+        # both finished) is where FP32 must still follow FP64
+        stops = [n64, n32] + [bd.index for bd in (bd64, bds[p]) if bd.index is not None]
+        ref = min(stops) - 1
+        err = None
+        if ref >= 0:
+            a64, a32 = r64[ref][1], rec32[ref][2][p]
+            err = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+        d = {"j2_over_j1": q["j2"] / q["j1"], "range": q["range"], "pairs": t.n_pairs,
+             "breakdown_fp64": {"kind": bd64.kind, "lambda": bd64.lam},
+             "breakdown_fp32": {"kind": bds[p].kind, "lambda": bds[p].lam},
+             "last_finite_lambda_fp64": r64[-1][0] if n64 else sched[0],
+             "last_finite_lambda_fp32": rec32[n32 - 1][0] if n32 else sched[0],
+             "chi_rel_err_at_last_lambda_above_breakdown": err,
+             "lambda_of_that_step": r64[ref][0] if ref >= 0 else None}
+        if n32 < n64:
+            # a point that FP64 carries further than FP32: the FP64 vertex size
+            # and the chi disagreement at the last step both finished
+            d["lost_to_fp32"] = {
+                "fp64_max_abs_vertex_at_fp32_loss": r64[n32][3] if n32 < n64 else None,
+                "fp64_max_abs_vertex_before": r64[n32 - 1][3] if n32 else None,
+                "chi_rel_diff_at_last_common_step": (float(np.abs(rec32[n32 - 1][2][p] - r64[n32 - 1][1]).max()
+                                                          / np.abs(r64[n32 - 1][1]).max()) if n32 else None)}
+        points.append(d)
+    errs = [d["chi_rel_err_at_last_lambda_above_breakdown"] for d in points
+            if d["chi_rel_err_at_last_lambda_above_breakdown"] is not None]
+    lost = [d for d in points if "lost_to_fp32" in d]
+    below = sum(1 for d in lost if d["breakdown_fp64"]["lambda"] is not None
+                and d["last_finite_lambda_fp32"] < d["breakdown_fp64"]["lambda"])
+    log(f"batch scan: chi error at the last step above breakdown max {max(errs):.2e} over {len(errs)} points; "
+        f"{len(lost)} points finite further in FP64 than in FP32, {below} of them lost below the FP64 breakdown")
+    for d in lost:
+        log(f"  J2/J1 {d['j2_over_j1']:.3f} range {d['range']}: FP32 last finite {d['last_finite_lambda_fp32']:.4g}, "
+            f"FP64 {d['last_finite_lambda_fp64']:.4g}, breakdown {d['breakdown_fp64']}, "
+            f"{d['lost_to_fp32']}")
     return {"workload": "64 square J1-J2 points, J2/J1 = k/63, ranges 4..7 (9/12/16/20 pairs), 24 log freqs "
                         "1e-3..100, RK4 100 -> 0.01 in 120 steps",
             "batch_fp32_seconds": t_batch, "sequential_fp64_seconds": t_seq,
             "speedup": t_seq / t_batch, "tuned_launch": {"per_xcd": tuned[0], "order": tuned[1], "split": tuned[2]},
             "finite_points_batch": int(sum(ok)), "finite_points_fp64": int(sum(seq_ok)),
             "sequential_note": "a diverging FP64 flow stops at its first non-finite step",
-            "chi_rel_err_vs_fp64_at_lambda_1": {"max": max(e1), "median": float(np.median(e1))},
-            "chi_rel_err_vs_fp64_at_lambda_f": {"points": len(ef), "max": max(ef), "median": float(np.median(ef))},
-            "phase_diagram": {"points": phase,
-                              "method": "breakdown.batch_breakdowns on the FP32 batch (untimed): chi(k) on "
-                                        "32 x 32 points after every RK4 step, first kink or divergence of "
-                                        "chi_max(Lambda) below a quarter of the top mesh frequency"}}
+            "chi_rel_err_at_last_lambda_above_breakdown": {"points": len(errs), "max": max(errs),
+                                                           "median": float(np.median(errs))},
+            "points_finite_further_in_fp64": len(lost), "of_them_lost_below_fp64_breakdown": below,
+            "points": points,
+            "method": "untimed step-by-step passes of both: chi(k) on 32 x 32 points after every RK4 step, "
+                      "breakdown = first kink or divergence of chi_max(Lambda) below a quarter of the top mesh "
+                      "frequency (breakdown.find_breakdown); chi error = max |chi_fp32 - chi_fp64| / max "
+                      "|chi_fp64| over pairs and both strains at the last step above the earlier breakdown "
+                      "of the two (or the last step both finished)"}
 
 
 def adjoint_leg():
@@ -349,7 +403,8 @@ def adjoint_leg():
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     grad = J.grad.numpy()
-    log(f"adjoint: forward {t_fwd:.3f} s, checkpointed forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s")
+    log(f"adjoint: forward {t_fwd:.3f} s, checkpointed forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s "
+        f"({(t2 - t0) / (6.0 * t_fwd):.2f} x the 6 forward flows of central differences in 3 couplings)")
 
     def f(jv):
         xx = ctx.init_state_from(D @ jv)
@@ -368,6 +423,7 @@ def adjoint_leg():
             "J": J0.tolist(), "k_peak": kpk.numpy().ravel().tolist(), "chi_k_peak": float(out.detach()[0]),
             "dchi_dJ": grad.tolist(), "forward_seconds": t_fwd, "checkpointed_forward_seconds": t1 - t0,
             "adjoint_seconds": t2 - t1, "adjoint_over_forward": (t1 - t0 + t2 - t1) / t_fwd,
+            "adjoint_over_central_differences_3_couplings": (t2 - t0) / (6.0 * t_fwd),
             "checkpoint_bytes": int((len(sched) - 1) * ctx.size * 8),
             "central_differences_equivalent": {
                 "flows_for_3_shell_couplings": 6, "flows_for_per_pair_couplings": 2 * (ctx.ns - 1),

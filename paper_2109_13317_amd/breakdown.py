@@ -90,21 +90,24 @@ class ChiMaxRecorder:
         return find_breakdown(self.lams, self.chi_max, **kw)
 
 
-def batch_breakdowns(batch, x, schedule, kpoints, *, use_graph: bool = True, **kw):
+def batch_breakdowns(batch, x, schedule, kpoints, *, use_graph: bool = True, record=None, **kw):
     """Advance a batch (``flow.Batch``) along an RK4 schedule one step at a
     time, in place, recording chi_max = max over kpoints of chi(k) for every
     point after every step, and locate each point's breakdown (keyword
     arguments as find_breakdown).  The steps are those of one
-    ``Batch.flow`` call over the schedule.  Returns (breakdowns, lams,
-    chi_max[point][step])."""
+    ``Batch.flow`` call over the schedule.  If record is a list, every step
+    appends (Lambda, per-point finiteness of the state, per-point chi as host
+    arrays).  Returns (breakdowns, lams, chi_max[point][step])."""
     import torch
     sched = [float(v) for v in schedule]
     lams, maxima = [], []
     for i in range(len(sched) - 1):
-        batch.flow(x, sched[i:i + 2], use_graph=use_graph)
+        ok = batch.flow(x, sched[i:i + 2], use_graph=use_graph)
         chis = batch.chi(sched[i + 1], x)
         maxima.append(torch.stack([batch.chi_k(p, c, kpoints).max() for p, c in enumerate(chis)]))
         lams.append(sched[i + 1])
+        if record is not None:
+            record.append((sched[i + 1], ok, [c.cpu().numpy() for c in chis]))
     chi_max = torch.stack(maxima, 1).cpu().numpy()
     return [find_breakdown(lams, chi_max[p], **kw) for p in range(batch.n_points)], lams, chi_max
 
