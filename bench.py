@@ -49,12 +49,16 @@ import workloads as W  # noqa: E402
 PEAK_FP64_VECTOR_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk/CU
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per k_vertex_stu launch from the two rocprofv3 --pmc runs
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, copy-kernel calibrated), keyed by
-# the hash of the kernel sources they were taken on and the workload; a
-# changed kernel reports traffic null until the counters are taken again.
+# HBM bytes per timed vertex launch from the two rocprofv3 --pmc runs
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, copy-kernel calibrated): the
+# k_vertex_stu launch up to 20 pairs, the whole concurrent vertex right-hand
+# side beyond (k_vertex_t, both k_vertex_su launches and the t-part sum);
+# keyed by the hash of the kernel sources they were taken on and the
+# workload; a changed kernel reports traffic null until the counters are
+# taken again.
 MEASURED_TRAFFIC = {
-    ("a8535505e0deef2b", "square_j1j2"): 27.70e6,
+    ("b617215c11b6d3c5", "square_j1j2"): 28.59e6,
+    ("b617215c11b6d3c5", "pyrochlore"): 277.45e6,
 }
 
 
