@@ -14,8 +14,10 @@ search path is scanned for the named definitions.
 What this engine accepts: the ``SU2`` backend, Heisenberg interactions
 (``type="heisenberg"``), and the ``correlation`` measurement (direct, or
 deferred to a re-run from stored vertex states), written as a
-NumPy ``.npz`` file (chi^zz and chi^00 per reduced pair and cutoff) where
-the paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
+NumPy ``.npz`` file (chi^zz and chi^00 per reduced pair and cutoff, and per
+basis site and site within range with the basis, lattice vectors and site
+positions, the data and metadata of the paper's observable files) where the
+paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
 integrates the cutoff list (the paper's Euler steps, Eq. 42, or RK4 through
 the same cutoffs) with checkpoints next to the task file and records the
 calculation status (start, checkpoint and end times; running or finished)
@@ -347,11 +349,40 @@ def read_data(path: str):
     return out
 
 
-def _write_obs(dest, rec) -> None:
+def sites_layout(tables, chi_pairs) -> np.ndarray:
+    """Correlations per reduced pair [..., n_pairs] spread onto the layout of
+    the paper's observable files (Sec. 5, "Output data"): for every basis
+    site b of the unit cell, every site k within range of it, [...,
+    n_basis, n_sites_total]; slots past a basis site's own site count hold
+    NaN."""
+    c = np.asarray(chi_pairs, dtype=np.float64)
+    sp = np.asarray(tables.site_pair)
+    out = np.full(c.shape[:-1] + sp.shape, np.nan)
+    ok = sp >= 0
+    out[..., ok] = c[..., sp[ok]]
+    return out
+
+
+def _write_obs(dest, rec, tables=None, cell=None) -> None:
+    """The correlation measurement: cutoffs, chi^zz and chi^00 per reduced
+    pair, and (with the lattice tables) the same in the observable layout
+    of Sec. 5 (``chi_zz_sites``, ``chi_00_sites``: [cutoff, basis site, site
+    within range]) with its metadata (``basis``, ``lattice_vectors``,
+    ``sites``: Cartesian positions)."""
+    arrays = {"lambda": np.asarray(rec[0], dtype=np.float64), "chi_zz": np.asarray(rec[1]),
+              "chi_00": np.asarray(rec[2])}
+    if tables is not None:
+        nb, ns_tot = np.asarray(tables.site_pair).shape
+        for key, vals in (("chi_zz_sites", rec[1]), ("chi_00_sites", rec[2])):
+            arrays[key] = (sites_layout(tables, np.asarray(vals)) if len(vals)
+                           else np.zeros((0, nb, ns_tot)))
+        arrays["basis"] = np.asarray(tables.basis_pos, dtype=np.float64)
+        arrays["sites"] = np.asarray(tables.site_pos, dtype=np.float64)
+        if cell is not None:
+            arrays["lattice_vectors"] = np.asarray(cell.primitives, dtype=np.float64)
     tmp = dest + ".tmp"
     with open(tmp, "wb") as f:
-        np.savez(f, **{"lambda": np.asarray(rec[0], dtype=np.float64), "chi_zz": np.asarray(rec[1]),
-                       "chi_00": np.asarray(rec[2])})
+        np.savez(f, **arrays)
     os.replace(tmp, dest)
 
 
@@ -363,7 +394,9 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
     ``every`` seconds apart, and at the end), and write each correlation
     measurement (default output: the task path with extension ``.obs``; a
     NumPy archive with ``lambda`` and ``chi_zz``, ``chi_00`` per reduced
-    pair), updated after every accepted step, and the lattice description
+    pair, and the same per basis site and site within range as the paper's
+    observable files hold them, ``_write_obs``), updated after every
+    accepted step, and the lattice description
     in the task path with extension ``.ldf`` (``write_ldf``).  A measurement
     with ``method="defer"`` (Sec. 5.1) records nothing during the flow: the
     vertex state of each of its cutoffs goes to the directory with the task
@@ -401,7 +434,8 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                     rec[1].extend(list(z["chi_zz"][keep]))
                     rec[2].extend(list(z["chi_00"][keep]))
     write_ldf(base + ".ldf", describe(task.model, task.lattice_range))
-    ctx = Context(build_tables(task.model, task.lattice_range), task.mesh, precision=precision)
+    tables = build_tables(task.model, task.lattice_range)
+    ctx = Context(tables, task.mesh, precision=precision)
     x = ctx.init_state()
     defer = [m.method == "defer" for m in task.measurements]
     data_dir = base + ".data"
@@ -419,7 +453,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                 rec[0].append(lam)
                 rec[1].append(c[0].copy())
                 rec[2].append(c[1].copy())
-                _write_obs(d, rec)
+                _write_obs(d, rec, tables, task.model.cell)
         if keep_state:
             os.makedirs(data_dir, exist_ok=True)
             i = index_of.get(float(lam))
@@ -451,12 +485,12 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                     rec[2].append(c[1].copy())
         for rec, d, dfr in zip(records, dests, defer):
             if dfr:
-                _write_obs(d, rec)
+                _write_obs(d, rec, tables, task.model.cell)
                 out[d] = len(rec[0])
     elif stored[0]:
         out[data_dir] = stored[0]
     for rec, d, dfr in zip(records, dests, defer):
         if not dfr:
-            _write_obs(d, rec)
+            _write_obs(d, rec, tables, task.model.cell)
             out[d] = len(rec[0])
     return out

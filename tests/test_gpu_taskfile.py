@@ -55,6 +55,14 @@ def test_task_file_runs_and_extends(tmp_path):
     assert out[obs] == len(sched) - 1
     assert np.array_equal(first["lambda"], sched[1:])
     assert np.array_equal(first["chi_zz"][-1], chi[0]) and np.array_equal(first["chi_00"][-1], chi[1])
+    # the observable-file layout: per basis site and site within range, with its metadata
+    lay = first["chi_zz_sites"]
+    assert lay.shape == (len(sched) - 1, tables.n_basis, tables.n_sites_total)
+    np.testing.assert_array_equal(lay, T.sites_layout(tables, first["chi_zz"]))
+    np.testing.assert_array_equal(first["chi_00_sites"], T.sites_layout(tables, first["chi_00"]))
+    np.testing.assert_array_equal(first["sites"], tables.site_pos)
+    np.testing.assert_array_equal(first["basis"], tables.basis_pos)
+    assert first["lattice_vectors"].shape == (3, 3)
     # lower the minimum cutoff and run the task again: it continues from the checkpoint
     task_path.write_text(task_path.read_text().replace("<min>2.0</min>", "<min>0.5</min>"))
     T.run(T.load(str(task_path)), scheme="euler")

@@ -239,3 +239,50 @@ def test_lattice_description_layout(tmp_path):
     inter = root.findall("interaction")
     assert len(inter) == 4 and set(inter[0].attrib) == {"from", "to", "value"}
     assert inter[0].get("value") == "[[1.0,0.0,0.0], [0.0,1.0,0.0], [0.0,0.0,1.0]]"
+
+
+@pytest.mark.parametrize("lat,L,params", [
+    ("honeycomb", 3, dict(j1=1.0, j2=0.4, j3=0.2)),
+    ("pyrochlore", 2, dict(j1=1.0)),
+])
+def test_observable_layout_against_the_oracle(oracle_lib, lat, L, params):
+    """The per-site layout of the observable files, built from correlations
+    per reduced pair, equals the oracle's correlations of every (basis site,
+    site within range) of a symmetric flow, sites matched by position: the
+    symmetry reduction, the site map and the site positions of the front
+    end agree with the oracle's unreduced lattice."""
+    import oracle
+    model = W.model(lat, **params)
+    tables = build_tables(model, L)
+    mesh = W.log_mesh(0.05, 20.0, 4)
+    orc = oracle.Oracle(model, L, mesh)
+    lam = 1.5
+    x = orc.flow(W.geometric_schedule(20.0, lam, 6), scheme="rk4")
+    ref = orc.chi_comps(lam, x)                             # [2, nb, ns] unreduced
+    # one value per reduced pair, from the first oracle site mapped to it
+    pos_pair = {}
+    for b in range(tables.n_basis):
+        for k in range(tables.n_sites_total):
+            if tables.site_pair[b, k] >= 0:
+                pos_pair[(b, tuple(np.round(tables.site_pos[b, k], 6)))] = int(tables.site_pair[b, k])
+    red = np.full((2, tables.n_pairs), np.nan)
+    for b in range(orc.lat.nb):
+        for k in range(orc.lat.nsites[b]):
+            p = pos_pair[(b, tuple(np.round(orc.lat.site_pos[b, k], 6)))]
+            if np.isnan(red[0, p]):
+                red[:, p] = ref[:, b, k]
+    assert not np.isnan(red).any()
+    lay = T.sites_layout(tables, red)
+    assert lay.shape == (2, tables.n_basis, tables.n_sites_total)
+    scale = np.abs(ref).max()
+    n = 0
+    for b in range(orc.lat.nb):
+        where = {tuple(np.round(orc.lat.site_pos[b, k], 6)): k for k in range(orc.lat.nsites[b])}
+        for k in range(tables.n_sites_total):
+            if tables.site_pair[b, k] < 0:
+                assert np.isnan(lay[:, b, k]).all()
+                continue
+            ko = where[tuple(np.round(tables.site_pos[b, k], 6))]
+            assert np.abs(lay[:, b, k] - ref[:, b, ko]).max() <= 1e-12 * scale
+            n += 1
+    assert n == sum(int(v) for v in orc.lat.nsites)
