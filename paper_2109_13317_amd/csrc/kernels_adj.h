@@ -171,14 +171,15 @@ struct AdjWaveLds {
 
 // The vertex-channel products scatter into one of kCotCopies copies of the
 // vertex cotangent (copies copy_stride doubles apart), which spreads the
-// atomic adds that land on one element over several addresses.  The copy is
-// the workgroup's slot within its XCD (workgroup index / 8) modulo
-// kCotCopies, so neighbouring workgroups of one XCD, which work on nearby
-// triples and hit the same elements, use different copies.  k_sum_copies
-// adds the copies up.
-constexpr int kCotCopies = 16;
+// atomic adds that land on one element over several addresses.  Each XCD
+// owns kCotCopies / 8 of the copies (the workgroup's XCD is its index mod 8),
+// so no copy takes atomic adds from two XCDs, and neighbouring workgroups of
+// one XCD, which work on nearby triples and hit the same elements, take
+// different ones of its copies (slot within the XCD, index / 8, modulo the
+// count).  k_sum_copies adds the copies up.
+constexpr int kCotCopies = 32;
 
-__device__ __forceinline__ long cot_copy(long stride) { return (long)((blockIdx.x / 8) % kCotCopies) * stride; }
+__device__ __forceinline__ long cot_copy(long stride) { return (long)((blockIdx.x % 8) * (kCotCopies / 8) + (blockIdx.x / 8) % (kCotCopies / 8)) * stride; }
 
 template <int CH>
 static __global__ void __launch_bounds__(kWave * kAdjWaves)
