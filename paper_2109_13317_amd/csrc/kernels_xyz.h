@@ -364,6 +364,182 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
     finish_xyz(red, lane, ns, G, act, tot, dx + nf, vsz, T.out, true);
 }
 
+// t channel from 17 to 32 pairs: four waves per triple (one workgroup).  Each
+// strain's lattice-sum matrix now takes 2 x 2 tiles (32 registers), so wave h
+// holds the tiles of strain h only.  The nodes go in sub-chunks of eight:
+// wave h gathers nodes 2h and 2h + 1 (both vectors, all four strains, and
+// their vertex corrections) into the triple's site-vector buffer, then every
+// wave adds the eight nodes to its strain's matrix (two matrix-core steps).
+// Plans for 32 nodes are built at once, one role per wave (site vectors a
+// and b, the two on-site vertices).  At the end wave m writes its matrix and
+// the lanes of all four waves contract it with the tabulated terms, strain
+// by strain; wave m adds strain m of every pair to dGamma.
+constexpr int kXyzMaxPairs4 = 32;
+constexpr int kXyzT4Chunk = 32;
+
+struct XyzT4Lds {
+    static constexpr size_t plans() { return (size_t)2 * kXyzT4Chunk * sizeof(Plan); }
+    static constexpr size_t ons() { return (size_t)(8 + 1) * kXyzT4Chunk * sizeof(double); }
+    static constexpr size_t vb() { return (size_t)8 * 8 * kXyzMaxPairs4 * sizeof(double); }
+    static constexpr size_t mat() { return (size_t)kXyzMaxPairs4 * kXyzMaxPairs4 * sizeof(double); }
+    static constexpr size_t red() { return (size_t)16 * kWave * sizeof(double); }
+    static constexpr size_t work() { return plans() + ons() + vb(); }
+    static constexpr size_t area() { return ((work() > mat() ? work() : mat()) + 31) & ~(size_t)31; }
+    // the partial sums reuse the area once the last contraction is done
+    static constexpr size_t bytes() { return area() > red() ? area() : red(); }
+};
+
+static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(4)))
+k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+    extern __shared__ __align__(32) unsigned char lds_raw[];
+    const int nf = A.nf, ns = A.ns, nq = A.nq;
+    const Shared sh = load_shared(A, lds_raw, true);
+    A.w = sh.w;
+    using L = XyzT4Lds;
+    constexpr int SP = kXyzMaxPairs4;       // site-vector row stride
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true);
+    Plan* plan = reinterpret_cast<Plan*>(base);                                  // [2][chunk]
+    double* ons = reinterpret_cast<double*>(base + L::plans());                  // [2][4][chunk]
+    double* wts = ons + 8 * kXyzT4Chunk;                                         // [chunk]
+    double* vb = reinterpret_cast<double*>(base + L::plans() + L::ons());        // [8 rows][8 nodes][SP]
+    double* mat = reinterpret_cast<double*>(base);                               // [ns*ns] after the node loop
+    double* red = reinterpret_cast<double*>(base);                               // [4 waves][4 strains][64] at the end
+    const int h = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // one triple per workgroup, each XCD a contiguous range in (t, s, u) order
+    const int per = gridDim.x / 8;
+    const int o = __builtin_amdgcn_readfirstlane((int)((blockIdx.x % 8) * per + blockIdx.x / 8));
+    if (o >= n_triples) return;                  // the whole workgroup: no barrier is left behind
+    const int nsu = nf * (nf + 1) / 2;
+    const int it = o / nsu, su = o % nsu;
+    const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
+    const double t = T.t;
+    const long vsz = (long)n_triples * ns;
+    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc(gv, vsz);
+    const int g = lane / ns, p = lane % ns;      // node lanes: g < 2
+    const int2 pp = make_int2(32 * p, 32 * sh.swap[p]);
+    const int cnt = A.tab_n[1 * nf + it];
+    const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
+    const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};        // vertex corrections over this lane's nodes
+    Vec4<double> c[2][2];
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) c[I][J] = Vec4<double>{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < cnt; k0 += kXyzT4Chunk) {
+        const int kc = min(kXyzT4Chunk, cnt - k0);
+        {
+            // wave h builds the plans of role h for node j: 0/1 the site
+            // vectors a/b, 2/3 the on-site vertices (pair 0, all strains)
+            const int j = lane, role = h;
+            if (j < kc) {
+                const double om = tw[k0 + j];
+                const double a0 = role == 0 ? T.w1 + om : (role == 1 ? om + T.w2p : (role == 2 ? T.w2p + om : T.w1 + om));
+                const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
+                const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
+                Plan P;
+                make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, &sh.lut);
+                to_bytes_xyz(P);
+                if (role < 2) {
+                    plan[role * kXyzT4Chunk + j] = P;
+                    if (role == 0) wts[j] = tg[k0 + j];
+                } else {
+                    double v[4];
+                    eval_xyz(P, rv, make_int2(0, 32 * sh.swap[0]), v);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) ons[((role - 2) * 4 + m) * kXyzT4Chunk + j] = v[m];
+                }
+            }
+        }
+        __syncthreads();
+        for (int s0 = 0; s0 < kc; s0 += 8) {
+            const int sc = min(8, kc - s0);
+            const int kk = 2 * h + g;
+            if (g < 2 && kk < sc) {
+                const int k = s0 + kk;
+                double a[4], b[4];
+                eval_xyz(plan[k], rv, pp, a);
+                eval_xyz(plan[kXyzT4Chunk + k], rv, pp, b);
+                const double W = wts[k];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    vb[(m * 8 + kk) * SP + p] = W * a[m];
+                    vb[((4 + m) * 8 + kk) * SP + p] = b[m];
+                    double c1 = 0.0, c2 = 0.0;
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) {
+                        c1 = fma(xyz_e(m, n), ons[(0 * 4 + n) * kXyzT4Chunk + k], c1);
+                        c2 = fma(xyz_e(m, n), ons[(1 * 4 + n) * kXyzT4Chunk + k], c2);
+                    }
+                    acc[m] = fma(W, a[m] * c1 + b[m] * c2, acc[m]);
+                }
+            }
+            __syncthreads();
+            // M_h[ka][kb] += (W a_h)[ka] b_h[kb] over the sub-chunk's nodes
+            {
+                const int i16 = lane % 16, k4 = lane / 16;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int node = 4 * q + k4;
+                    double xa[2], xb[2];
+#pragma unroll
+                    for (int I = 0; I < 2; ++I) {
+                        const int pr = 16 * I + i16;
+                        const bool in = node < sc && pr < ns;
+                        const int off = in ? node * SP + pr : 0;
+                        xa[I] = in ? vb[h * 8 * SP + off] : 0.0;
+                        xb[I] = in ? vb[(4 + h) * 8 * SP + off] : 0.0;
+                    }
+#pragma unroll
+                    for (int I = 0; I < 2; ++I)
+#pragma unroll
+                        for (int J = 0; J < 2; ++J) c[I][J] = mfma16x16x4<double>(xa[I], xb[J], c[I][J]);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // contraction with the tabulated terms, strain by strain: wave m writes
+    // its matrix, the lanes (h, g < 2) of all waves take every eighth term
+    double tot[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (h == m) {
+#pragma unroll
+            for (int I = 0; I < 2; ++I)
+#pragma unroll
+                for (int J = 0; J < 2; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int ka = 16 * I + mfma_row<double>(lane, r), kb = 16 * J + lane % 16;
+                        if (ka < ns && kb < ns) mat[ka * ns + kb] = c[I][J][r];
+                    }
+        }
+        __syncthreads();
+        if (g < 2) {
+            double sacc = 0.0;
+            for (int qq = sh.off[p] + 2 * h + g; qq < sh.off[p + 1]; qq += 8) {
+                const int tq = sh.terms[qq];
+                sacc = fma((double)(tq >> 16), mat[tq & 0xffff], sacc);
+            }
+            tot[m] = sacc;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) red[(h * 4 + m) * kWave + lane] = g < 2 ? fma(-2.0, tot[m], acc[m]) : 0.0;
+    __syncthreads();
+    // wave m adds strain m of every pair
+    if (lane < ns) {
+        const int m = h;
+        double v = 0.0;
+#pragma unroll
+        for (int hh = 0; hh < 4; ++hh) v += red[(hh * 4 + m) * kWave + lane] + red[(hh * 4 + m) * kWave + ns + lane];
+        dx[nf + m * vsz + T.out * ns + lane] += v;
+    }
+}
+
 // ---------------------------------------------------------- correlations -
 
 // Workgroup (p, slice): the part of the double integrals of pair p over the

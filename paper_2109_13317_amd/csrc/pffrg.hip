@@ -357,6 +357,14 @@ pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     hipLaunchKernelGGL(k_xyz_su<2>, grid, block, lds_su, c->stream, A, (const double4*)gv, (const int*)c->uo_a,
                        (const int*)c->uo_c, T, dx);
     TRY(launch_check("k_xyz_su"));
+    if (c->ns > kXyzMaxPairs) {
+        // four waves per triple, one triple per workgroup
+        const int per4 = (T + 7) / 8;
+        hipLaunchKernelGGL(k_xyz_t4, dim3(8 * per4), block, S.bytes(true) + XyzT4Lds::bytes(), c->stream, A,
+                           (const double4*)gv, T, dx);
+        prof_mark(c, PFFRG_K_VERTEX, true);
+        return launch_check("k_xyz_t4");
+    }
     hipLaunchKernelGGL(k_xyz_t, grid, block, lds_t, c->stream, A, (const double4*)gv, T, dx);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_xyz_t");
@@ -670,8 +678,6 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         for (int i = 0; i < 3 * lat->n_pairs; ++i)
             if (!std::isfinite(coupling3[i])) return fail(PFFRG_EINVAL, "couplings must be finite");
         if (prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "the XYZ flow runs in FP64 only");
-        if (lat->n_pairs > kXyzMaxPairs)
-            return fail(PFFRG_EUNSUPPORTED, "the XYZ flow takes at most 16 pairs (one matrix-core tile per strain)");
     }
     const int nf = mesh->n_freq, ns = lat->n_pairs;
     const int nterms = lat->rpa_off[ns];
@@ -789,7 +795,8 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         HIP_TRY(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
         if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
-        if (xyz && SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds::bytes() > 64 * 1024)
+        if (xyz && (SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds::bytes() > 64 * 1024 ||
+                    SharedLds{nf, ns, nterms}.bytes(true) + XyzT4Lds::bytes() > 64 * 1024))
             return fail(PFFRG_EUNSUPPORTED, "XYZ vertex kernel LDS budget exceeded");
         return PFFRG_OK;
     };

@@ -4,12 +4,17 @@ components) against the FP64 oracle, through the C ABI (pffrg_create_xyz).
 Bar: max |gpu - oracle| / max |oracle| <= 1e-10 over sigma and every element
 of the four strains (matched to the library's reduced pairs by site
 position), and over chi of the four strains and chi(k).  Cases: random
-states on square and honeycomb lattices at cutoffs below, inside and above
-the mesh, on a mesh point and at half a mesh point (theta = 1/2 ties); the
-initial state; a 40-step RK4 flow with chi every step; the honeycomb
-J1-J2-J3 workload size (range 6, 14 pairs, 32 frequencies) on sampled
-triples; the SU(2) limit (Jx = Jy = Jz) against an SU(2) context; and the
-refused inputs.
+states on square, honeycomb and pyrochlore lattices (4 to 31 pairs: the t
+channel's one-wave kernel up to 16 pairs, its four-waves-per-triple kernel
+beyond), with shell couplings and with couplings that depend on the bond
+direction (Heisenberg-Kitaev honeycomb, square compass model), at cutoffs
+below, inside and above the mesh, on a mesh point and at half a mesh point
+(theta = 1/2 ties); the initial state; 40-step RK4 flows with chi every
+step; the honeycomb J1-J2-J3 workload size (range 6, 14 pairs, 32
+frequencies), square range 7 (20 pairs, 32 frequencies) and pyrochlore
+range 5 (31 pairs, 24 frequencies) on sampled triples; the SU(2) limit
+(Jx = Jy = Jz) against an SU(2) context; and the refused inputs (FP32, more
+than 32 pairs, reverse mode).
 """
 
 import zlib
@@ -25,9 +30,19 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 CASES = {
-    "square_L2_N8": ("square", dict(j1=(1.0, 0.6, 0.3), j2=(0.2, -0.5, 0.4)), 2, W.log_mesh(0.005, 50.0, 8)),
-    "honeycomb_L3_N6": ("honeycomb", dict(j1=(0.8, 1.0, -0.3), j2=(0.1, 0.25, 0.2), j3=(0.3, 0.0, 0.15)), 3,
-                        W.log_mesh(0.01, 20.0, 6)),
+    "square_L2_N8": (lambda: W.model_xyz("square", j1=(1.0, 0.6, 0.3), j2=(0.2, -0.5, 0.4)), 2,
+                     W.log_mesh(0.005, 50.0, 8)),
+    "honeycomb_L3_N6": (lambda: W.model_xyz("honeycomb", j1=(0.8, 1.0, -0.3), j2=(0.1, 0.25, 0.2),
+                                            j3=(0.3, 0.0, 0.15)), 3, W.log_mesh(0.01, 20.0, 6)),
+    # couplings that depend on the bond direction (no lattice symmetry maps
+    # one bond type to another, so every site in range is its own pair)
+    "heisenberg_kitaev_L2_N6": (lambda: W.model_heisenberg_kitaev(0.7, -1.3), 2, W.log_mesh(0.01, 20.0, 6)),
+    "compass_L3_N5": (lambda: W.model_compass(0.9, -0.4), 3, W.log_mesh(0.01, 20.0, 5)),
+    # beyond 16 pairs (the t channel with four waves per triple): 19, 20 and 31 pairs
+    "heisenberg_kitaev_L3_N5": (lambda: W.model_heisenberg_kitaev(0.7, -1.3), 3, W.log_mesh(0.01, 20.0, 5)),
+    "square_L7_N4": (lambda: W.model_xyz("square", j1=(1.0, 0.6, 0.3), j2=(0.2, -0.5, 0.4)), 7,
+                     W.log_mesh(0.01, 20.0, 4)),
+    "pyrochlore_L5_N3": (lambda: W.model_xyz("pyrochlore", j1=(1.0, 0.7, -0.4)), 5, W.log_mesh(0.01, 20.0, 3)),
 }
 
 
@@ -44,8 +59,8 @@ def _setup(name):
     import oracle
     from paper_2109_13317_amd import build_tables
     from paper_2109_13317_amd.flow import Context
-    lat, params, L, mesh = CASES[name]
-    model = W.model_xyz(lat, **params)
+    make, L, mesh = CASES[name]
+    model = make()
     tables = build_tables(model, L)
     ctx = Context(tables, mesh)
     orc = oracle.Oracle(model, L, mesh)
@@ -92,10 +107,12 @@ def test_xyz_initial_state_first_rhs_and_chi(name):
     assert err <= TOL and ek <= TOL
 
 
-def test_xyz_rk4_flow_with_chi_every_step():
-    """Square range 2, 8 frequencies, 40 RK4 steps Lambda 50 -> 0.5, chi of the
-    four strains at every step."""
-    torch, tables, ctx, orc = _setup("square_L2_N8")
+@pytest.mark.parametrize("name", ["square_L2_N8", "heisenberg_kitaev_L2_N6"])
+def test_xyz_rk4_flow_with_chi_every_step(name):
+    """40 RK4 steps Lambda 50 -> 0.5 (square range 2, 8 frequencies; the
+    Heisenberg-Kitaev honeycomb, range 2, 6 frequencies), chi of the four
+    strains at every step."""
+    torch, tables, ctx, orc = _setup(name)
     sched = W.geometric_schedule(50.0, 0.5, 40)
     x = ctx.init_state()
     got = []
@@ -143,6 +160,41 @@ def test_xyz_workload_size_sampled():
     assert err <= TOL, err
 
 
+@pytest.mark.parametrize("lat,L,nf", [("square", 7, 32), ("pyrochlore", 5, 24)])
+def test_xyz_beyond_16_pairs_sampled(lat, L, nf):
+    """The four-waves-per-triple t channel at sizes whose node lists span
+    several plan chunks and sub-chunks: square range 7 (20 pairs) with 32
+    frequencies, pyrochlore range 5 (31 pairs) with 24; the oracle computes
+    every element of sampled triples."""
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    params = dict(j1=(0.9, 0.7, 0.5), j2=(0.3, 0.2, 0.25)) if lat == "square" else dict(j1=(1.0, 0.7, -0.4))
+    model = W.model_xyz(lat, **params)
+    mesh = W.log_mesh(1e-3, 100.0, nf)
+    tables = build_tables(model, L)
+    assert tables.n_pairs > 16
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, L, mesh)
+    x = W.random_state(nf, ctx.ns, seed=_seed(lat, L, nf), scale=0.2, strains=4)
+    lam = 0.21
+    _say(f"xyz {lat} range {L} ({ctx.ns} pairs), {nf} frequencies")
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    xo = expand_state(orc, tables, x)
+    dsig = orc.sigma_rhs(lam, xo)
+    assert np.abs(dsig - d[:nf]).max() <= TOL * np.abs(dsig).max()
+    rng = np.random.default_rng(5)
+    tri = [(0, 0, 0), (nf - 1, nf - 1, nf - 1), (nf - 1, 0, 0), (nf // 2, nf - 1, 1)]
+    for _ in range(4):
+        a = int(rng.integers(nf)); c = int(rng.integers(a + 1)); t = int(rng.integers(nf))
+        tri.append((a, t, c))
+    ref = orc.vertex_rhs_triples(lam, xo, dsig, tri)
+    err = compare_triples(orc, tables, tri, ref, d)
+    _say(f"  error {err:.2e}")
+    assert err <= TOL, err
+
+
 def test_xyz_isotropic_equals_su2_context():
     """Jx = Jy = Jz = J: the XYZ context's three spin strains follow the SU(2)
     context's spin strain and its density strain the SU(2) one, along an RK4
@@ -179,7 +231,8 @@ def test_xyz_refused_inputs():
     with pytest.raises(_lib.PffrgError) as ei:
         Context(t_small, mesh, precision="fp32")
     assert ei.value.status == _lib.EUNSUPPORTED
-    t_big = build_tables(W.model_xyz("square", j1=(1.0, 0.5, 0.2)), 7)      # 20 pairs
+    t_big = build_tables(W.model_heisenberg_kitaev(1.0, -1.0), 5)        # 46 pairs
+    assert t_big.n_pairs > 32
     with pytest.raises(_lib.PffrgError) as ei:
         Context(t_big, mesh)
     assert ei.value.status == _lib.EUNSUPPORTED

@@ -195,3 +195,75 @@ def test_xyz_zero_coupling_is_a_fixed_point(oracle_lib):
     x[: o.nf] = -np.linspace(0.1, 0.4, o.nf)
     for lam in (0.01, 0.5, 20.0):
         assert np.all(o.rhs(lam, x) == 0.0)
+
+
+def _coupling_by_bonds(model):
+    """J^mu(r_i, r_j) of a model whose couplings depend on the bond: every
+    listed interaction (param, b0, b1, d) joins the site of sublattice b0 in
+    any cell R with the site of sublattice b1 in cell R + d (and back)."""
+    cell = model.cell
+    P = np.asarray(cell.primitives, dtype=float)
+    B = np.asarray(cell.basis, dtype=float)
+    inv = np.linalg.inv(P)
+
+    def sub(r):
+        for b in range(len(B)):
+            f = (r - B[b]) @ inv
+            if np.abs(f - np.rint(f)).max() < 1e-9:
+                return b
+        raise ValueError("not a lattice site")
+
+    def J(ri, rj):
+        bi, bj = sub(ri), sub(rj)
+        tot = np.zeros(3)
+        for (name, b0, b1, d0, d1, d2) in model.interactions:
+            v = np.asarray(model.params[name], dtype=float)
+            dr = np.array([d0, d1, d2], dtype=float) @ P + B[b1] - B[b0]
+            if bi == b0 and bj == b1 and np.abs(rj - ri - dr).max() < 1e-9:
+                tot += v
+            if bi == b1 and bj == b0 and np.abs(ri - rj - dr).max() < 1e-9:
+                tot += v
+        return tot
+    return J
+
+
+@pytest.mark.parametrize("which,L", [("heisenberg_kitaev", 2), ("heisenberg_kitaev", 3), ("compass", 3)])
+@pytest.mark.parametrize("lam", [0.05, 1.1])
+def test_xyz_first_rhs_closed_form_bond_dependent(oracle_lib, which, L, lam):
+    """The closed form of the first right-hand side (as above) for couplings
+    that depend on the bond direction (Heisenberg-Kitaev honeycomb, J = 0.7,
+    K = -1.3; square compass model): g and the lattice sum taken bond by bond
+    from the model's interaction list by brute force over a cluster."""
+    m = W.model_heisenberg_kitaev(0.7, -1.3) if which == "heisenberg_kitaev" else W.model_compass(0.9, -0.4)
+    mesh = W.log_mesh(0.005, 50.0, 5)
+    o = oracle_lib.Oracle(m, L, mesh)
+    assert o.nc == 4
+    d = o.rhs(lam, o.initial_state())
+    sig, gx, gy, gz, gd = o.split(d)
+    assert np.all(sig == 0.0)
+    J = _coupling_by_bonds(m)
+    cell = m.cell
+    got = (gx, gy, gz)
+    err = 0.0
+    reach = L + 2
+    cluster = [cell.position((d0, d1, 0), b) for d0 in range(-reach, reach + 1)
+               for d1 in range(-reach, reach + 1) for b in range(cell.n_basis)]
+    for b in range(o.lat.nb):
+        rb = o.lat.basis_pos[b]
+        for k in range(o.lat.nsites[b]):
+            rk = o.lat.site_pos[b, k]
+            g = J(rb, rk) / 4.0
+            sgg = sum(J(rb, rj) * J(rj, rk) for rj in cluster) / 16.0
+            for a in range(o.nf):
+                for c in range(a + 1):
+                    su = a * (a + 1) // 2 + c
+                    for t in range(o.nf):
+                        hs, hu, ht = _h(mesh[a], lam), _h(mesh[c], lam), _h(mesh[t], lam)
+                        for mu in range(3):
+                            nb_, nc_ = (mu + 1) % 3, (mu + 2) % 3
+                            e = (-2.0 * g[nb_] * g[nc_] * (hs + hu) + 2.0 * ht * sgg[mu]) / (math.pi * lam)
+                            err = max(err, abs(got[mu][b, su, t, k] - e))
+                        ed = float(g @ g) / (math.pi * lam) * (hs - hu)
+                        err = max(err, abs(gd[b, su, t, k] - ed))
+    scale = max(np.abs(d).max(), 1.0)
+    assert err <= 1e-14 * scale, (err, scale)

@@ -172,6 +172,28 @@ def model_xyz(lattice: str, **params) -> Model:
     return Model(f"{lattice}-xyz", base.cell, base.interactions, full)
 
 
+def model_heisenberg_kitaev(J: float = 1.0, K: float = 0.0) -> Model:
+    """Heisenberg-Kitaev model on the honeycomb lattice: J S_i . S_j + K S_i^g
+    S_j^g on every nearest-neighbour bond, where g = x, y, z labels the three
+    bond directions of the unit cell (Sec. 5.2 listing: the bond inside the
+    cell and the two to the neighbouring cells).  Diagonal couplings per bond,
+    (J + K, J, J) on x bonds and so on: an XYZ model whose couplings depend on
+    the bond direction."""
+    cell = UNIT_CELLS["honeycomb"]
+    names = ("kx", "ky", "kz")
+    inter = tuple((n,) + bond for n, bond in zip(names, cell.bonds))
+    params = {n: tuple(J + (K if m == g else 0.0) for m in range(3)) for g, n in enumerate(names)}
+    return Model("honeycomb-heisenberg-kitaev", cell, inter, params)
+
+
+def model_compass(Jx: float = 1.0, Jy: float = 1.0) -> Model:
+    """Compass model on the square lattice: Jx S^x S^x on bonds along a0 and
+    Jy S^y S^y on bonds along a1 (an XYZ model with bond-dependent couplings)."""
+    cell = UNIT_CELLS["square"]
+    inter = (("bx",) + cell.bonds[0], ("by",) + cell.bonds[1])
+    return Model("square-compass", cell, inter, {"bx": (float(Jx), 0.0, 0.0), "by": (0.0, float(Jy), 0.0)})
+
+
 # ---------------------------------------------------------------- meshes ---
 
 def log_mesh(wmin: float, wmax: float, n: int) -> np.ndarray:
