@@ -479,6 +479,29 @@ def xyz_leg(reps=10):
         res[sym] = r
         ctx.close()
     res["xyz_over_su2_rhs_time"] = res["xyz"]["vertex_rhs_ms"] / res["su2"]["vertex_rhs_ms"]
+    # bond-dependent couplings beyond 16 pairs (the four-waves-per-triple t
+    # channel): Heisenberg-Kitaev honeycomb, range 4 (31 pairs)
+    hk = W.model_heisenberg_kitaev(1.0, -2.0)
+    tab = build_tables(hk, 4)
+    ctx = Context(tab, mesh)
+    x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=7, scale=0.2, strains=4)).cuda()
+    out = ctx.new_state()
+    ctx.rhs(0.5, x, out)
+    ctx.set_profiling(True, kernels=("vertex",))
+    for _ in range(reps):
+        ctx.rhs(0.5, x, out)
+    ms, n = ctx.profile_read("vertex")
+    ctx.set_profiling(False)
+    fl = xyz_vertex_flops(mesh, 0.5, ctx.ns, tab.n_terms)
+    E = ctx.nc * ctx.ns * ctx.nf * ctx.nf * (ctx.nf + 1) // 2
+    res["heisenberg_kitaev_range4"] = {
+        "workload": "Heisenberg-Kitaev honeycomb J = 1, K = -2, range 4 (31 pairs: no lattice symmetry maps one "
+                    "bond direction onto another), 32 log freqs 1e-3..100, RHS at Lambda = 0.5 on a seeded random state",
+        "vertex_rhs_ms": ms / n, "vertex_elements": E, "elements_per_s": E / (ms / n * 1e-3), "flops": fl,
+        "tflops": fl / (ms / n * 1e-3) / 1e12, "frac_of_fp64_peak": fl / (ms / n * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS}
+    ctx.close()
+    log(f"XYZ Heisenberg-Kitaev range 4 ({tab.n_pairs} pairs): vertex RHS {ms / n:.3f} ms "
+        f"({res['heisenberg_kitaev_range4']['tflops']:.2f} TFLOP/s)")
     log(f"XYZ: vertex RHS {res['xyz']['vertex_rhs_ms']:.3f} ms ({res['xyz']['tflops']:.2f} TFLOP/s), SU(2) "
         f"{res['su2']['vertex_rhs_ms']:.3f} ms; flows {res['xyz']['flow_seconds']:.3f} / "
         f"{res['su2']['flow_seconds']:.3f} s")

@@ -224,6 +224,17 @@ pffrg_status pffrg_chi(pffrg_ctx *ctx, double lambda, const double *d_state, dou
 pffrg_status pffrg_chi_k(pffrg_ctx *ctx, const double *d_chi, int n_k, const double *d_k,
                          double *d_chi_k);
 
+/* The correlations per reduced pair (d_chi as pffrg_chi returns them:
+ * [strains][Ns], two strains for SU(2), four for XYZ) in the layout of the
+ * paper's observable files (Sec. 5, output data: per basis site b of the
+ * unit cell and per site k within range of it):
+ * d_chi_sites[(m * n_basis + b) * n_sites_total + k] = d_chi[m * Ns +
+ * site_pair[b * n_sites_total + k]], NaN where site_pair is -1 (a basis site
+ * with fewer sites in range).  Both device arrays are the caller's;
+ * d_chi_sites holds strains * n_basis * n_sites_total doubles.  NULL
+ * pointers: PFFRG_EINVAL. */
+pffrg_status pffrg_chi_sites(pffrg_ctx *ctx, const double *d_chi, double *d_chi_sites);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * correlations as pffrg_chi, d_chi[0*Ns + p] = chi^{zz}, d_chi[1*Ns + p] =

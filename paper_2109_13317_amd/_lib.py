@@ -57,6 +57,7 @@ SIGNATURES = {
     "pffrg_flow_position": [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(I)],
     "pffrg_chi": [P, D, P, P],
     "pffrg_chi_k": [P, P, I, P, P],
+    "pffrg_chi_sites": [P, P, P],
     "pffrg_chi_noalloc": [I, P, I, P, D, P, P, P],
     "pffrg_measure_peaks": [P, P],
     "pffrg_set_profiling": [P, I],

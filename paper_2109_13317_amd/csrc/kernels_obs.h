@@ -139,6 +139,20 @@ static __global__ void k_chi_final(int ns, const double* __restrict__ cq, const 
     chi[ns + p] = d;
 }
 
+// The correlations per reduced pair spread onto the layout of the paper's
+// observable files (Sec. 5, output data): out[(m * nbs) + k] = chi[m * ns +
+// site_pair[k]] for the nbs = n_basis * n_sites_total (basis site, site)
+// slots, NaN where a basis site lists fewer sites (site_pair = -1).
+static __global__ void k_chi_sites(int nc, int ns, int nbs, const int* __restrict__ site_pair,
+                                   const double* __restrict__ chi, double* __restrict__ out) {
+    const long n = (long)nc * nbs;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int m = (int)(i / nbs), k = (int)(i % nbs);
+        const int sp = site_pair[k];
+        out[i] = sp >= 0 ? chi[m * ns + sp] : __builtin_nan("");
+    }
+}
+
 // chi(k_q) = (1/nb) sum_{b, j} cos(k_q . dr_bj) scale (sum_m chi^m_{pair(b,j)}),
 // the sum over the nsum strains chi[m * stride + pair], m < nsum (SU(2): 3
 // chi^{zz}; XYZ: chi^xx + chi^yy + chi^zz); one wave per k point, lanes over

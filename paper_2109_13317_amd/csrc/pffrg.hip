@@ -51,6 +51,8 @@ struct pffrg_ctx {
     double* coupling = nullptr;
     int nb = 0, nterm = 0;          // chi(k) terms: (basis, site) pairs in range
     int* chi_pair = nullptr;        // [nterm]
+    int* site_pair = nullptr;       // [nb * n_sites_total]: reduced pair of (basis site, site), -1 past the range
+    int n_sites_total = 0;
     int* rpa_term = nullptr;        // packed lattice-sum terms
     int n_terms = 0;
     double* chi_dr = nullptr;       // [nterm*3]  r_b - r_j
@@ -759,6 +761,8 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
             }
         c->nterm = (int)cp.size();
         TRY(upload(c, &c->chi_pair, cp.data(), cp.size()));
+        c->n_sites_total = lat->n_sites_total;
+        TRY(upload(c, &c->site_pair, lat->site_pair, (size_t)lat->n_basis * lat->n_sites_total));
         TRY(upload(c, &c->chi_dr, dr.data(), dr.size()));
         TRY(dev_alloc(c, &c->tab_n, (size_t)3 * nf));
         TRY(dev_alloc(c, &c->tab_w, (size_t)3 * nf * c->nq));
@@ -935,6 +939,15 @@ pffrg_status pffrg_chi_k(pffrg_ctx* c, const double* chi, int nk, const double* 
                        (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, chi, c->nc == 4 ? 3 : 1,
                        c->ns, c->nc == 4 ? 1.0 : 3.0, nk, kp, out);
     return launch_check("k_chi_k");
+}
+
+pffrg_status pffrg_chi_sites(pffrg_ctx* c, const double* chi, double* out) {
+    TRY(check_ctx(c));
+    if (!chi || !out) return fail(PFFRG_EINVAL, "null correlations");
+    const int nbs = c->nb * c->n_sites_total;
+    hipLaunchKernelGGL(k_chi_sites, dim3(grid_for((long)c->nc * nbs, 256)), dim3(256), 0, c->stream, c->nc, c->ns,
+                       nbs, (const int*)c->site_pair, chi, out);
+    return launch_check("k_chi_sites");
 }
 
 pffrg_status pffrg_flow(pffrg_ctx* c, const pffrg_flow_opts* o, double* x, pffrg_observer cb, void* user,

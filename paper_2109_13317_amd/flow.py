@@ -265,6 +265,15 @@ class Context:
                                         _dptr(kp), _dptr(out)))
         return out
 
+    def chi_sites(self, chi: torch.Tensor) -> torch.Tensor:
+        """chi per reduced pair spread onto [strains, n_basis, n_sites_total]
+        (the layout of the paper's observable files; NaN past a basis site's
+        sites in range)."""
+        nb, nst = self.tables.n_basis, self.tables.n_sites_total
+        out = torch.empty(self.nc * nb * nst, dtype=torch.float64, device="cuda")
+        _lib.check(self.lib.pffrg_chi_sites(self.handle, _dptr(chi.contiguous()), _dptr(out)))
+        return out.view(self.nc, nb, nst)
+
 
 class ChiAdjoint(torch.autograd.Function):
     """chi(k) at the end of an RK4 flow as a differentiable function of the

@@ -134,3 +134,30 @@ def restrict_state(orc, tables, x_unred: np.ndarray) -> np.ndarray:
         for c in range(1, orc.nc + 1):
             dst[c][:, :, p] = src[c][b, :, :, k]
     return out
+
+
+def compare_chi_sites(orc, tables, lay: np.ndarray, ref: np.ndarray, chi_red: np.ndarray) -> float:
+    """The library's correlations in the observable-file layout lay
+    [strains, n_basis, n_sites_total] against the oracle's unreduced ones ref
+    [strains, nb, ns_oracle], sites matched by position, relative to max
+    |ref|.  Checks as well that lay is chi_red [strains, n_pairs] spread by
+    the site map (bit for bit) and that exactly the slots past a basis
+    site's sites in range hold NaN."""
+    from paper_2109_13317_amd import taskfile
+    nc = ref.shape[0]
+    assert lay.shape == (nc, tables.n_basis, tables.n_sites_total)
+    expect = taskfile.sites_layout(tables, np.asarray(chi_red).reshape(nc, -1))
+    nan = np.isnan(lay)
+    assert np.array_equal(nan, np.isnan(expect)) and np.array_equal(lay[~nan], expect[~nan])
+    err, n = 0.0, 0
+    for b in range(orc.lat.nb):
+        where = {tuple(np.round(orc.lat.site_pos[b, k], 6)): k for k in range(orc.lat.nsites[b])}
+        for k in range(tables.n_sites_total):
+            if tables.site_pair[b, k] < 0:
+                assert nan[:, b, k].all()
+                continue
+            ko = where[tuple(np.round(tables.site_pos[b, k], 6))]
+            err = max(err, float(np.abs(lay[:, b, k] - ref[:, b, ko]).max()))
+            n += 1
+    assert n == int(np.sum(orc.lat.nsites))
+    return err / max(float(np.abs(ref).max()), 1e-300)

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import compare_chi, compare_triples, compare_vertex, expand_state
+from tests.parity import compare_chi_sites, compare_chi, compare_triples, compare_vertex, expand_state
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,22 @@ def test_chi_and_structure_factor(name):
         ck = ctx.chi_k(torch.from_numpy(chi.reshape(-1)).cuda(), torch.from_numpy(kp).cuda()).cpu().numpy()
         ref = orc.chi_k(zz, kp)
         assert np.abs(ck - ref).max() <= TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["honeycomb_L3_N6", "pyrochlore_L2_N5"])
+def test_chi_sites_layout(name):
+    """pffrg_chi_sites: chi in the observable-file layout (per basis site and
+    site within range) equals the oracle's correlations of every (basis site,
+    site), sites matched by position."""
+    torch, tables, ctx, orc = _setup(name)
+    x = W.random_state(ctx.nf, ctx.ns, seed=_seed(name, "sites"))
+    xo = expand_state(orc, tables, x)
+    chi = ctx.chi(0.3, torch.from_numpy(x).cuda())
+    lay = ctx.chi_sites(chi).cpu().numpy()
+    zz, dd = orc.chi(0.3, xo)
+    err = compare_chi_sites(orc, tables, lay, np.stack([zz, dd]), chi.cpu().numpy())
+    _say(f"chi sites {name}: {err:.2e}")
+    assert err <= TOL
 
 
 @pytest.mark.parametrize("scheme", ["euler", "rk4"])

@@ -23,7 +23,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import compare_chi_comps, compare_triples, compare_vertex, expand_state
+from tests.parity import compare_chi_comps, compare_chi_sites, compare_triples, compare_vertex, expand_state
 
 pytestmark = pytest.mark.gpu
 
@@ -99,6 +99,9 @@ def test_xyz_initial_state_first_rhs_and_chi(name):
     chi = ctx.chi(lam, torch.from_numpy(xr).cuda())
     ref = orc.chi_comps(lam, expand_state(orc, tables, xr))
     err = compare_chi_comps(orc, tables, ref, chi.cpu().numpy())
+    # the same in the observable-file layout (per basis site and site)
+    es = compare_chi_sites(orc, tables, ctx.chi_sites(chi).cpu().numpy(), ref, chi.cpu().numpy())
+    assert es <= TOL, es
     kp = np.random.default_rng(4).uniform(-6.0, 6.0, size=(17, 3))
     ck = ctx.chi_k(chi.reshape(-1), torch.from_numpy(kp).cuda()).cpu().numpy()
     ck_ref = orc.chi_k_xyz(ref, kp)
