@@ -324,10 +324,12 @@ def describe(model, L: int) -> LatticeDescription:
         return out
 
     bonds = sorted(links([(1.0,) + tuple(bd) for bd in model.cell.bonds]))
-    coup = links([(float(model.params.get(p, 0.0)), f, t, d0, d1, d2)
+    # a coupling is a number (Heisenberg) or (Jx, Jy, Jz) (XYZ)
+    coup = links([(np.asarray(model.params.get(p, lat.zero), dtype=np.float64) if lat.vec
+                   else float(model.params.get(p, 0.0)), f, t, d0, d1, d2)
                   for (p, f, t, d0, d1, d2) in model.interactions])
     return LatticeDescription(
         positions=np.array([lat.pos(*s) for s in sites]),
         parametrized=np.array([s in reps for s in sites]),
         bonds=bonds,
-        interactions=[(i, j, v) for (i, j), v in sorted(coup.items()) if v != 0.0])
+        interactions=[(i, j, v) for (i, j), v in sorted(coup.items()) if np.any(np.asarray(v) != 0.0)])

@@ -11,13 +11,15 @@ between two sites given as four integers a0,a1,a2,b, with a coupling
 parameter and a type) live in resource files: every ``*.xml`` file of a
 search path is scanned for the named definitions.
 
-What this engine accepts: the ``SU2`` backend, Heisenberg interactions
-(``type="heisenberg"``), and the ``correlation`` measurement (direct, or
-deferred to a re-run from stored vertex states), written as a
-NumPy ``.npz`` file (chi^zz and chi^00 per reduced pair and cutoff, and per
-basis site and site within range with the basis, lattice vectors and site
-positions, the data and metadata of the paper's observable files) where the
-paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
+What this engine accepts: the ``SU2`` backend with Heisenberg interactions
+(``type="heisenberg"``), the ``XYZ`` backend with every interaction type of
+diagonal matrix M (heisenberg, xxyy, xx, yy, zz, -xx, -yy, -zz: the
+Heisenberg-Kitaev model of the paper's listing, for one), and the
+``correlation`` measurement (direct, or deferred to a re-run from stored
+vertex states), written as a NumPy ``.npz`` file (each correlation strain
+per reduced pair and cutoff, and per basis site and site within range with
+the basis, lattice vectors and site positions, the data and metadata of the
+paper's observable files) where the paper writes HDF5.  Anything else raises ``TaskError``.  ``run``
 integrates the cutoff list (the paper's Euler steps, Eq. 42, or RK4 through
 the same cutoffs) with checkpoints next to the task file and records the
 calculation status (start, checkpoint and end times; running or finished)
@@ -93,6 +95,10 @@ class UnitCellDef:
     @property
     def n_basis(self) -> int:
         return int(self.basis.shape[0])
+
+    def position(self, cell, b) -> np.ndarray:
+        """Cartesian position of basis site b in the cell (a0, a1, a2)."""
+        return np.asarray(cell, dtype=np.float64) @ self.primitives + self.basis[b]
 
 
 @dataclass(frozen=True)
@@ -200,13 +206,28 @@ def _unit_cell(search_path, name):
                        tuple(bonds))
 
 
-def _model(search_path, name, cell, params):
+# Interaction types with a diagonal matrix M (Sec. 5.3): what the XYZ backend
+# takes; the off-diagonal ones (gx, gy, gz, mu nu with mu != nu) need the
+# TRI backend.
+_DIAGONAL_TYPES = {"heisenberg": (1.0, 1.0, 1.0), "xxyy": (1.0, 1.0, 0.0),
+                   "xx": (1.0, 0.0, 0.0), "yy": (0.0, 1.0, 0.0), "zz": (0.0, 0.0, 1.0),
+                   "-xx": (-1.0, 0.0, 0.0), "-yy": (0.0, -1.0, 0.0), "-zz": (0.0, 0.0, -1.0)}
+
+
+def _model(search_path, name, cell, params, symmetry="SU2"):
+    """The model's interactions with the first site in cell 0.  SU2: every
+    interaction is Heisenberg, parameters are numbers.  XYZ: every
+    interaction has a diagonal matrix M; each (parameter, type) becomes a
+    coupling (Jx, Jy, Jz) = value x diag(M)."""
     f, node = _resource_nodes(search_path, "model", name)
     inter = []
+    vec = {}
     for it in node.findall("interaction"):
         kind = it.get("type", "")
-        if kind != "heisenberg":
+        if symmetry == "SU2" and kind != "heisenberg":
             raise TaskError(f"{f}: interaction type {kind!r} needs a backend other than SU2")
+        if symmetry == "XYZ" and kind not in _DIAGONAL_TYPES:
+            raise TaskError(f"{f}: interaction type {kind!r} couples different spin components (TRI backend)")
         src = [int(v) for v in it.get("from", "").split(",")]
         dst = [int(v) for v in it.get("to", "").split(",")]
         if len(src) != 4 or len(dst) != 4:
@@ -216,8 +237,12 @@ def _model(search_path, name, cell, params):
         p = it.get("parameter")
         if p not in params:
             raise TaskError(f"the task gives no value for the model parameter {p!r}")
+        if symmetry == "XYZ":
+            key = f"{p}:{kind}"
+            vec[key] = tuple(float(params[p]) * m for m in _DIAGONAL_TYPES[kind])
+            p = key
         inter.append((p, src[3], dst[3], dst[0] - src[0], dst[1] - src[1], dst[2] - src[2]))
-    return ModelDef(name, cell, tuple(inter), dict(params))
+    return ModelDef(name, cell, tuple(inter), vec if symmetry == "XYZ" else dict(params))
 
 
 def load(path: str, search_path=None) -> Task:
@@ -247,11 +272,11 @@ def load(path: str, search_path=None) -> Task:
         raise TaskError(f"{path}: cutoff values must be positive and descending")
     lat, mod = nodes["lattice"], nodes["model"]
     symmetry = mod.get("symmetry", "")
-    if symmetry != "SU2":
-        raise TaskError(f"{path}: backend {symmetry!r} is not available (this engine is SU2)")
+    if symmetry not in ("SU2", "XYZ"):
+        raise TaskError(f"{path}: backend {symmetry!r} is not available (this engine runs SU2 and XYZ)")
     params = {c.tag: evaluate(c.text) for c in mod if c.text is not None}
     cell = _unit_cell(search_path, lat.get("name"))
-    model = _model(search_path, mod.get("name"), cell, params)
+    model = _model(search_path, mod.get("name"), cell, params, symmetry)
     meas = []
     mnode = root.find("measurements")
     for m in (mnode.findall("measurement") if mnode is not None else []):
@@ -299,7 +324,7 @@ def write_ldf(path: str, desc) -> None:
     for i, j in desc.bonds:
         ET.SubElement(root, "bond", **{"from": str(i), "to": str(j)})
     for i, j, v in desc.interactions:
-        m = np.eye(3) * v
+        m = np.diag(v) if np.ndim(v) == 1 else np.eye(3) * v      # XYZ (Jx, Jy, Jz) or Heisenberg J
         val = "[" + ", ".join("[" + ",".join(repr(float(e)) for e in row) + "]" for row in m) + "]"
         ET.SubElement(root, "interaction", value=val, **{"from": str(i), "to": str(j)})
     ET.indent(root)
@@ -363,19 +388,29 @@ def sites_layout(tables, chi_pairs) -> np.ndarray:
     return out
 
 
+def chi_names(nc: int) -> tuple:
+    """Names of the correlation strains in the measurement files: SU2 chi^zz
+    and chi^00, XYZ chi^xx, chi^yy, chi^zz and chi^00."""
+    return ("chi_zz", "chi_00") if nc == 2 else ("chi_xx", "chi_yy", "chi_zz", "chi_00")
+
+
 def _write_obs(dest, rec, tables=None, cell=None) -> None:
-    """The correlation measurement: cutoffs, chi^zz and chi^00 per reduced
-    pair, and (with the lattice tables) the same in the observable layout
-    of Sec. 5 (``chi_zz_sites``, ``chi_00_sites``: [cutoff, basis site, site
-    within range]) with its metadata (``basis``, ``lattice_vectors``,
-    ``sites``: Cartesian positions)."""
-    arrays = {"lambda": np.asarray(rec[0], dtype=np.float64), "chi_zz": np.asarray(rec[1]),
-              "chi_00": np.asarray(rec[2])}
+    """The correlation measurement: cutoffs and every strain per reduced
+    pair (``chi_names``; rec = (cutoffs, [strains, pairs] per cutoff)), and
+    (with the lattice tables) the same in the observable layout of Sec. 5
+    (``<name>_sites``: [cutoff, basis site, site within range]) with its
+    metadata (``basis``, ``lattice_vectors``, ``sites``: Cartesian
+    positions)."""
+    chis = [np.asarray(c, dtype=np.float64) for c in rec[1]]
+    nc = chis[0].shape[0] if chis else (4 if tables is not None and np.ndim(tables.coupling) == 2 else 2)
+    arrays = {"lambda": np.asarray(rec[0], dtype=np.float64)}
+    for m, name in enumerate(chi_names(nc)):
+        arrays[name] = np.array([c[m] for c in chis]) if chis else np.zeros((0, 0))
     if tables is not None:
         nb, ns_tot = np.asarray(tables.site_pair).shape
-        for key, vals in (("chi_zz_sites", rec[1]), ("chi_00_sites", rec[2])):
-            arrays[key] = (sites_layout(tables, np.asarray(vals)) if len(vals)
-                           else np.zeros((0, nb, ns_tot)))
+        for m, name in enumerate(chi_names(nc)):
+            arrays[name + "_sites"] = (sites_layout(tables, arrays[name]) if chis
+                                       else np.zeros((0, nb, ns_tot)))
         arrays["basis"] = np.asarray(tables.basis_pos, dtype=np.float64)
         arrays["sites"] = np.asarray(tables.site_pos, dtype=np.float64)
         if cell is not None:
@@ -393,9 +428,10 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
     in the task path with extension ``.checkpoint`` (a snapshot at least
     ``every`` seconds apart, and at the end), and write each correlation
     measurement (default output: the task path with extension ``.obs``; a
-    NumPy archive with ``lambda`` and ``chi_zz``, ``chi_00`` per reduced
-    pair, and the same per basis site and site within range as the paper's
-    observable files hold them, ``_write_obs``), updated after every
+    NumPy archive with ``lambda`` and each strain per reduced pair, SU2
+    ``chi_zz``, ``chi_00``, XYZ ``chi_xx``, ``chi_yy``, ``chi_zz``,
+    ``chi_00``, and the same per basis site and site within range as the
+    paper's observable files hold them, ``_write_obs``), updated after every
     accepted step, and the lattice description
     in the task path with extension ``.ldf`` (``write_ldf``).  A measurement
     with ``method="defer"`` (Sec. 5.1) records nothing during the flow: the
@@ -422,7 +458,8 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
     for m in task.measurements:
         d = m.output or base + ".obs"
         dests.append(d if os.path.isabs(d) else os.path.join(os.path.dirname(task.path), d))
-    records = [([], [], []) for _ in task.measurements]
+    records = [([], []) for _ in task.measurements]
+    names = chi_names(4 if task.symmetry == "XYZ" else 2)
     resuming = os.path.exists(ck) and not force_restart
     if resuming:
         lam_snap = float.fromhex(checkpoint.read(ck).meta["lambda"])
@@ -431,8 +468,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                 with np.load(d, allow_pickle=False) as z:
                     keep = z["lambda"] >= lam_snap
                     rec[0].extend(z["lambda"][keep].tolist())
-                    rec[1].extend(list(z["chi_zz"][keep]))
-                    rec[2].extend(list(z["chi_00"][keep]))
+                    rec[1].extend(list(np.stack([z[n][keep] for n in names], axis=1)))
     write_ldf(base + ".ldf", describe(task.model, task.lattice_range))
     tables = build_tables(task.model, task.lattice_range)
     ctx = Context(tables, task.mesh, precision=precision)
@@ -451,8 +487,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                     keep_state = True
                     continue
                 rec[0].append(lam)
-                rec[1].append(c[0].copy())
-                rec[2].append(c[1].copy())
+                rec[1].append(c.copy())
                 _write_obs(d, rec, tables, task.model.cell)
         if keep_state:
             os.makedirs(data_dir, exist_ok=True)
@@ -481,8 +516,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
             for m, rec, dfr in zip(task.measurements, records, defer):
                 if dfr and m.min_cutoff <= lam <= m.max_cutoff:
                     rec[0].append(lam)
-                    rec[1].append(c[0].copy())
-                    rec[2].append(c[1].copy())
+                    rec[1].append(c.copy())
         for rec, d, dfr in zip(records, dests, defer):
             if dfr:
                 _write_obs(d, rec, tables, task.model.cell)

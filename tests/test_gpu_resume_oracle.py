@@ -115,3 +115,34 @@ def test_task_file_run_matches_oracle(tmp_path):
         worst = max(worst, compare_chi(orc, tables, zz, dd, red))
     _say(f"task-file run: chi at {len(ref)} cutoffs, worst error vs oracle {worst:.2e}")
     assert worst <= TOL
+
+
+def test_xyz_task_file_run_matches_oracle(tmp_path):
+    """A task on the XYZ backend: the Heisenberg-Kitaev model written as in
+    the paper's model listing (j = 0.6, k = -1.4, honeycomb range 3), Euler
+    steps; the four correlation strains at every cutoff, per reduced pair and
+    in the observable-file layout, against the oracle's XYZ Euler flow."""
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd import taskfile as T
+    from tests.parity import compare_chi_comps, compare_chi_sites
+    from tests.test_taskfile import _kitaev_task
+    path = _kitaev_task(tmp_path)
+    task = T.load(path)
+    T.run(task, scheme="euler")
+    got = np.load(path[:-4] + ".obs")
+    tables = build_tables(task.model, 3)
+    orc = oracle.Oracle(task.model, 3, task.mesh)
+    assert orc.nc == 4
+    ref = []
+    orc.flow(task.cutoffs, scheme="euler", observer=lambda lam, xs: ref.append((lam, orc.chi_comps(lam, xs))))
+    assert np.array_equal(got["lambda"], task.cutoffs[1:]) and len(ref) == len(task.cutoffs) - 1
+    names = T.chi_names(4)
+    worst = 0.0
+    for i, (lam, cc) in enumerate(ref):
+        red = np.stack([got[n][i] for n in names])
+        worst = max(worst, compare_chi_comps(orc, tables, cc, red))
+        lay = np.stack([got[n + "_sites"][i] for n in names])
+        worst = max(worst, compare_chi_sites(orc, tables, lay, cc, red))
+    _say(f"XYZ task-file run ({tables.n_pairs} pairs): chi at {len(ref)} cutoffs, worst error vs oracle {worst:.2e}")
+    assert worst <= TOL

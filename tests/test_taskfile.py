@@ -46,6 +46,17 @@ RESOURCES = """
 <model name="hc-anisotropic">
   <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="xx"/>
 </model>
+<model name="hc-kitaev">
+  <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,0" to="0,-1,0,1" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,0" to="-1,0,0,1" type="heisenberg"/>
+  <interaction parameter="k" from="0,0,0,0" to="0,0,0,1" type="xx"/>
+  <interaction parameter="k" from="0,0,0,0" to="0,-1,0,1" type="yy"/>
+  <interaction parameter="k" from="0,0,0,0" to="-1,0,0,1" type="zz"/>
+</model>
+<model name="hc-gamma">
+  <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="gx"/>
+</model>
 """
 
 
@@ -123,7 +134,7 @@ def test_expressions_are_arithmetic_only():
 def test_what_the_su2_engine_cannot_run_is_refused(tmp_path):
     good = _read(_sq_task(tmp_path))
     cases = [
-        (good.replace('symmetry="SU2"', 'symmetry="XYZ"'), "backend"),
+        (good.replace('symmetry="SU2"', 'symmetry="TRI"'), "backend"),
         (good.replace("<jb>0.4</jb>", ""), "no value"),
         (good.replace('<lattice name="sq"', '<lattice name="nowhere"'), "unitcell"),
         (good.replace("<step>0.85</step>", "<step>1.5</step>"), "step"),
@@ -141,6 +152,9 @@ def test_what_the_su2_engine_cannot_run_is_refused(tmp_path):
       <lattice name="hc" range="2"/><model name="hc-anisotropic" symmetry="SU2"><j>1</j></model>
     </parameters></task>""", "aniso.xml")
     with pytest.raises(T.TaskError, match="type 'xx'"):
+        T.load(p)
+    p = _task(tmp_path, _read(p).replace('hc-anisotropic" symmetry="SU2"', 'hc-gamma" symmetry="XYZ"'), "gamma.xml")
+    with pytest.raises(T.TaskError, match="TRI"):
         T.load(p)
     (tmp_path / "dup.xml").write_text('<unitcell name="sq"><primitive x="1"/></unitcell>')
     with pytest.raises(T.TaskError, match="more than once"):
@@ -286,3 +300,55 @@ def test_observable_layout_against_the_oracle(oracle_lib, lat, L, params):
             assert np.abs(lay[:, b, k] - ref[:, b, ko]).max() <= 1e-12 * scale
             n += 1
     assert n == sum(int(v) for v in orc.lat.nsites)
+
+
+def _kitaev_task(tmp_path, j="0.6", k="-1.4", L=3):
+    return _task(tmp_path, f"""<task><parameters>
+      <frequency discretization="exponential"><min>0.01</min><max>20</max><count>6</count></frequency>
+      <cutoff discretization="exponential"><min>2.0</min><max>20</max><step>0.85</step></cutoff>
+      <lattice name="hc" range="{L}"/><model name="hc-kitaev" symmetry="XYZ"><j>{j}</j><k>{k}</k></model>
+    </parameters>
+    <measurements><measurement name="correlation"/></measurements></task>""", "kitaev.xml")
+
+
+def test_xyz_task_heisenberg_kitaev_tables(tmp_path):
+    """The Heisenberg-Kitaev model written as in the paper's model listing
+    (Heisenberg on the three honeycomb bonds plus xx, yy, zz on one bond
+    direction each) loads on the XYZ backend and gives the lattice front end
+    exactly the tables of the same couplings written as one (Jx, Jy, Jz) per
+    bond."""
+    task = T.load(_kitaev_task(tmp_path))
+    assert task.symmetry == "XYZ"
+    J, K = 0.6, -1.4
+    direct = W.Model("hk", W.unit_cell("honeycomb"),
+                     (("x", 0, 1, 0, 0, 0), ("y", 0, 1, 0, -1, 0), ("z", 0, 1, -1, 0, 0)),
+                     {"x": (J + K, J, J), "y": (J, J + K, J), "z": (J, J, J + K)})
+    for L in (2, 3):
+        a, b = build_tables(task.model, L), build_tables(direct, L)
+        assert a.n_pairs == b.n_pairs and a.coupling.shape == (a.n_pairs, 3)
+        for f in ("swap", "mult", "rpa_off", "rpa_ka", "rpa_kb", "rpa_cnt", "site_pair", "coupling", "site_pos"):
+            assert np.array_equal(getattr(a, f), getattr(b, f)), f
+
+
+def test_xyz_lattice_description(tmp_path):
+    """The lattice description of an XYZ task lists each nonzero coupling as
+    the diagonal matrix diag(Jx, Jy, Jz): the bond's x, y or z term plus the
+    Heisenberg part, checked against the positions by brute force."""
+    from paper_2109_13317_amd.lattice import describe
+    task = T.load(_kitaev_task(tmp_path, L=2))
+    path = str(tmp_path / "k.ldf")
+    T.write_ldf(path, describe(task.model, 2))
+    pos, par, bonds, inter = T.read_ldf(path)
+    J, K = 0.6, -1.4
+    cell = W.unit_cell("honeycomb")
+    # bond direction of a nearest-neighbour pair from its displacement (site 0 -> site 1)
+    dirs = {}
+    for g, d in enumerate(((0, 0, 0), (0, -1, 0), (-1, 0, 0))):
+        dirs[tuple(np.round(cell.position(d, 1) - cell.position((0, 0, 0), 0), 6))] = g
+    assert len(inter) == len(bonds) > 0
+    for i, j, m in inter:
+        dr = tuple(np.round(pos[j] - pos[i], 6))
+        g = dirs.get(dr, dirs.get(tuple(-np.asarray(dr))))
+        assert g is not None
+        expect = np.diag([J + (K if c == g else 0.0) for c in range(3)])
+        assert np.array_equal(m, expect)
