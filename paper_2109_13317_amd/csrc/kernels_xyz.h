@@ -364,22 +364,25 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
     finish_xyz(red, lane, ns, G, act, tot, dx + nf, vsz, T.out, true);
 }
 
-// t channel from 17 to 32 pairs: four waves per triple (one workgroup).  Each
-// strain's lattice-sum matrix now takes 2 x 2 tiles (32 registers), so wave h
-// holds the tiles of strain h only.  The nodes go in sub-chunks of eight:
-// wave h gathers nodes 2h and 2h + 1 (both vectors, all four strains, and
-// their vertex corrections) into the triple's site-vector buffer, then every
-// wave adds the eight nodes to its strain's matrix (two matrix-core steps).
-// Plans for 32 nodes are built at once, one role per wave (site vectors a
-// and b, the two on-site vertices).  At the end wave m writes its matrix and
-// the lanes of all four waves contract it with the tabulated terms, strain
-// by strain; wave m adds strain m of every pair to dGamma.
+// t channel, four waves per triple (one workgroup): wave h holds the
+// lattice-sum matrix of strain h only, NT x NT tiles (NT = 2 from 17 to 32
+// pairs, where the four strains' tiles would need 128 accumulation registers
+// in one wave; NT = 1 up to 16 pairs).  The nodes go in sub-chunks of 4 NG
+// (NG = 64 / (16 NT) node groups of lanes per wave): wave h gathers nodes
+// NG h .. NG h + NG - 1 (both vectors, all four strains, and their vertex
+// corrections) into the triple's site-vector buffer, then every wave adds the
+// sub-chunk to its strain's matrix (NG matrix-core steps).  Plans for 32
+// nodes are built at once, one role per wave (site vectors a and b, the two
+// on-site vertices).  At the end wave m writes its matrix and the lanes of
+// all four waves contract it with the tabulated terms, strain by strain;
+// wave m adds strain m of every pair to dGamma.
 constexpr int kXyzMaxPairs4 = 32;
 constexpr int kXyzT4Chunk = 32;
 
 struct XyzT4Lds {
     static constexpr size_t plans() { return (size_t)2 * kXyzT4Chunk * sizeof(Plan); }
     static constexpr size_t ons() { return (size_t)(8 + 1) * kXyzT4Chunk * sizeof(double); }
+    // 8 rows x (4 NG nodes) x (16 NT pairs) = 2048 doubles for either NT
     static constexpr size_t vb() { return (size_t)8 * 8 * kXyzMaxPairs4 * sizeof(double); }
     static constexpr size_t mat() { return (size_t)kXyzMaxPairs4 * kXyzMaxPairs4 * sizeof(double); }
     static constexpr size_t red() { return (size_t)16 * kWave * sizeof(double); }
@@ -389,20 +392,23 @@ struct XyzT4Lds {
     static constexpr size_t bytes() { return area() > red() ? area() : red(); }
 };
 
+template <int NT>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu(4)))
 k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+    constexpr int NG = 4 / NT;             // node groups of lanes per wave
+    constexpr int SC = 4 * NG;             // nodes per sub-chunk
+    constexpr int SP = 16 * NT;            // site-vector row stride (pairs)
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, true);
     A.w = sh.w;
     using L = XyzT4Lds;
-    constexpr int SP = kXyzMaxPairs4;       // site-vector row stride
     unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true);
     Plan* plan = reinterpret_cast<Plan*>(base);                                  // [2][chunk]
     double* ons = reinterpret_cast<double*>(base + L::plans());                  // [2][4][chunk]
     double* wts = ons + 8 * kXyzT4Chunk;                                         // [chunk]
-    double* vb = reinterpret_cast<double*>(base + L::plans() + L::ons());        // [8 rows][8 nodes][SP]
+    double* vb = reinterpret_cast<double*>(base + L::plans() + L::ons());        // [8 rows][SC nodes][SP]
     double* mat = reinterpret_cast<double*>(base);                               // [ns*ns] after the node loop
     double* red = reinterpret_cast<double*>(base);                               // [4 waves][4 strains][64] at the end
     const int h = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -416,17 +422,17 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
     const double t = T.t;
     const long vsz = (long)n_triples * ns;
     const __amdgpu_buffer_rsrc_t rv = xyz_rsrc(gv, vsz);
-    const int g = lane / ns, p = lane % ns;      // node lanes: g < 2
+    const int g = lane / ns, p = lane % ns;      // node lanes: g < NG
     const int2 pp = make_int2(32 * p, 32 * sh.swap[p]);
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};        // vertex corrections over this lane's nodes
-    Vec4<double> c[2][2];
+    Vec4<double> c[NT][NT];
 #pragma unroll
-    for (int I = 0; I < 2; ++I)
+    for (int I = 0; I < NT; ++I)
 #pragma unroll
-        for (int J = 0; J < 2; ++J) c[I][J] = Vec4<double>{0.0, 0.0, 0.0, 0.0};
+        for (int J = 0; J < NT; ++J) c[I][J] = Vec4<double>{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < cnt; k0 += kXyzT4Chunk) {
         const int kc = min(kXyzT4Chunk, cnt - k0);
         {
@@ -453,10 +459,10 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
             }
         }
         __syncthreads();
-        for (int s0 = 0; s0 < kc; s0 += 8) {
-            const int sc = min(8, kc - s0);
-            const int kk = 2 * h + g;
-            if (g < 2 && kk < sc) {
+        for (int s0 = 0; s0 < kc; s0 += SC) {
+            const int sc = min(SC, kc - s0);
+            const int kk = NG * h + g;
+            if (g < NG && kk < sc) {
                 const int k = s0 + kk;
                 double a[4], b[4];
                 eval_xyz(plan[k], rv, pp, a);
@@ -464,8 +470,8 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
                 const double W = wts[k];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    vb[(m * 8 + kk) * SP + p] = W * a[m];
-                    vb[((4 + m) * 8 + kk) * SP + p] = b[m];
+                    vb[(m * SC + kk) * SP + p] = W * a[m];
+                    vb[((4 + m) * SC + kk) * SP + p] = b[m];
                     double c1 = 0.0, c2 = 0.0;
 #pragma unroll
                     for (int n = 0; n < 4; ++n) {
@@ -480,36 +486,36 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
             {
                 const int i16 = lane % 16, k4 = lane / 16;
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < NG; ++q) {
                     const int node = 4 * q + k4;
-                    double xa[2], xb[2];
+                    double xa[NT], xb[NT];
 #pragma unroll
-                    for (int I = 0; I < 2; ++I) {
+                    for (int I = 0; I < NT; ++I) {
                         const int pr = 16 * I + i16;
                         const bool in = node < sc && pr < ns;
                         const int off = in ? node * SP + pr : 0;
-                        xa[I] = in ? vb[h * 8 * SP + off] : 0.0;
-                        xb[I] = in ? vb[(4 + h) * 8 * SP + off] : 0.0;
+                        xa[I] = in ? vb[h * SC * SP + off] : 0.0;
+                        xb[I] = in ? vb[(4 + h) * SC * SP + off] : 0.0;
                     }
 #pragma unroll
-                    for (int I = 0; I < 2; ++I)
+                    for (int I = 0; I < NT; ++I)
 #pragma unroll
-                        for (int J = 0; J < 2; ++J) c[I][J] = mfma16x16x4<double>(xa[I], xb[J], c[I][J]);
+                        for (int J = 0; J < NT; ++J) c[I][J] = mfma16x16x4<double>(xa[I], xb[J], c[I][J]);
                 }
             }
             __syncthreads();
         }
     }
     // contraction with the tabulated terms, strain by strain: wave m writes
-    // its matrix, the lanes (h, g < 2) of all waves take every eighth term
+    // its matrix, the lanes (h, g < NG) of all waves take every (4 NG)-th term
     double tot[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         if (h == m) {
 #pragma unroll
-            for (int I = 0; I < 2; ++I)
+            for (int I = 0; I < NT; ++I)
 #pragma unroll
-                for (int J = 0; J < 2; ++J)
+                for (int J = 0; J < NT; ++J)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int ka = 16 * I + mfma_row<double>(lane, r), kb = 16 * J + lane % 16;
@@ -517,9 +523,9 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
                     }
         }
         __syncthreads();
-        if (g < 2) {
+        if (g < NG) {
             double sacc = 0.0;
-            for (int qq = sh.off[p] + 2 * h + g; qq < sh.off[p + 1]; qq += 8) {
+            for (int qq = sh.off[p] + NG * h + g; qq < sh.off[p + 1]; qq += 4 * NG) {
                 const int tq = sh.terms[qq];
                 sacc = fma((double)(tq >> 16), mat[tq & 0xffff], sacc);
             }
@@ -528,14 +534,16 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
         __syncthreads();
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) red[(h * 4 + m) * kWave + lane] = g < 2 ? fma(-2.0, tot[m], acc[m]) : 0.0;
+    for (int m = 0; m < 4; ++m) red[(h * 4 + m) * kWave + lane] = g < NG ? fma(-2.0, tot[m], acc[m]) : 0.0;
     __syncthreads();
     // wave m adds strain m of every pair
     if (lane < ns) {
         const int m = h;
         double v = 0.0;
 #pragma unroll
-        for (int hh = 0; hh < 4; ++hh) v += red[(hh * 4 + m) * kWave + lane] + red[(hh * 4 + m) * kWave + ns + lane];
+        for (int hh = 0; hh < 4; ++hh)
+#pragma unroll
+            for (int gg = 0; gg < NG; ++gg) v += red[(hh * 4 + m) * kWave + gg * ns + lane];
         dx[nf + m * vsz + T.out * ns + lane] += v;
     }
 }

@@ -360,9 +360,11 @@ pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
                        (const int*)c->uo_c, T, dx);
     TRY(launch_check("k_xyz_su"));
     if (c->ns > kXyzMaxPairs) {
-        // four waves per triple, one triple per workgroup
+        // four waves per triple, one triple per workgroup (up to 16 pairs the
+        // one-wave kernel below is the faster: 0.414 against 0.457 ms per
+        // right-hand side at honeycomb range 6)
         const int per4 = (T + 7) / 8;
-        hipLaunchKernelGGL(k_xyz_t4, dim3(8 * per4), block, S.bytes(true) + XyzT4Lds::bytes(), c->stream, A,
+        hipLaunchKernelGGL(k_xyz_t4<2>, dim3(8 * per4), block, S.bytes(true) + XyzT4Lds::bytes(), c->stream, A,
                            (const double4*)gv, T, dx);
         prof_mark(c, PFFRG_K_VERTEX, true);
         return launch_check("k_xyz_t4");
