@@ -129,8 +129,10 @@ pffrg_status pffrg_create(const pffrg_lattice *lat, const pffrg_mesh *mesh,
  * Gx, Gy, Gz even under s <-> u like the SU(2) spin strain, Gd odd; the
  * initial condition is G^m = J^m/4, Gd = 0; pffrg_chi returns [4][Ns]
  * (chi^xx, chi^yy, chi^zz, chi^00) and pffrg_chi_k sums chi^xx + chi^yy +
- * chi^zz (Eq. 31).  Up to 32 pairs, as for SU(2).  Everything runs in
- * FP64: PFFRG_FP32 gives PFFRG_EUNSUPPORTED; the reverse-mode calls
+ * chi^zz (Eq. 31).  Up to 32 pairs, as for SU(2).  PFFRG_FP32 runs the
+ * vertex interpolation, channel products and lattice-sum matrices in FP32
+ * with compensated chunk sums (the self-energy, tables, contraction, state
+ * and chi stay FP64), as for SU(2); the reverse-mode calls
  * (pffrg_init_state_from, pffrg_*_vjp) give PFFRG_EUNSUPPORTED on an XYZ
  * context.  NULL coupling3 or a non-finite coupling: PFFRG_EINVAL. */
 pffrg_status pffrg_create_xyz(const pffrg_lattice *lat, const double *coupling3, const pffrg_mesh *mesh,

@@ -75,10 +75,18 @@ k_xyz_sigma(FlowArgs A, double lam, const double* __restrict__ x, long nv, doubl
     if (lane == 0) dsig[n] = (term + other) * kInvTwoPi;
 }
 
-// The four strains interleaved per element: gv[i] = (x, y, z, d).
-static __global__ void k_xyz_pack(long n, const double* __restrict__ g, double4* __restrict__ gv) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        gv[i] = make_double4(g[i], g[n + i], g[2 * n + i], g[3 * n + i]);
+// The four strains interleaved per element: gv[i] = (x, y, z, d), in the
+// precision R of the vertex kernels (32 bytes per element in FP64, 16 in FP32).
+template <class R>
+static __global__ void k_xyz_pack(long n, const double* __restrict__ g, V4<R>* __restrict__ gv) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        V4<R> v;
+        v.x = (R)g[i];
+        v.y = (R)g[n + i];
+        v.z = (R)g[2 * n + i];
+        v.w = (R)g[3 * n + i];
+        gv[i] = v;
+    }
 }
 
 // Initial condition (Eq. 14, Eq. 21): sig = 0, G^m = J^m/4 for m = x, y, z
@@ -96,38 +104,49 @@ static __global__ void k_xyz_init_state(long n, int nf, int ns, const double* __
     }
 }
 
-// Both halves of one packed corner (x, y | z, d) for byte offset off.
+// Bytes of one packed element (x, y, z, d).
+template <class R> constexpr int kXyzElemBytes = 4 * (int)sizeof(R);
+
+// One packed corner (x, y, z, d) at byte offset off: two 16-byte loads in
+// FP64, one in FP32.
 __device__ __forceinline__ void load_xyzd(__amdgpu_buffer_rsrc_t r, unsigned off, double (&v)[4]) {
     const double2 a = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
     const double2 b = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)(off + 16u), 0, 0));
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
+__device__ __forceinline__ void load_xyzd(__amdgpu_buffer_rsrc_t r, unsigned off, float (&v)[4]) {
+    const float4 a = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
 
 // One interpolated vertex (four strains) of the pair at byte offsets pp
-// (pp.y the exchanged pair) through plan P (offsets in bytes): all eight
-// loads are issued before the arithmetic.
-__device__ __forceinline__ void eval_xyz(const Plan& P, __amdgpu_buffer_rsrc_t r, int2 pp, double (&v)[4]) {
+// (pp.y the exchanged pair) through plan P (offsets in bytes), in precision
+// R: all corner loads are issued before the arithmetic.
+template <class R>
+__device__ __forceinline__ void eval_xyz(const PlanT<R>& P, __amdgpu_buffer_rsrc_t r, int2 pp, R (&v)[4]) {
     const unsigned q = P.swp ? pp.y : pp.x;
-    double c[4][4];
+    R c[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) load_xyzd(r, (unsigned)P.off[i] + q, c[i]);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        double a = 0.0;
+        R a = 0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a = fma(m == 3 ? P.wd[i] : P.ws[i], c[i][m], a);
+        for (int i = 0; i < 4; ++i) a = fmr(m == 3 ? P.wd[i] : P.ws[i], c[i][m], a);
         v[m] = a;
     }
 }
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t xyz_rsrc(const double4* gv, long n) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * 32), 0x00020000);
+template <class R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t xyz_rsrc(const V4<R>* gv, long n) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * kXyzElemBytes<R>), 0x00020000);
 }
 
-// Plan offsets (elements) as byte offsets of the 32-byte packed vertex.
-__device__ __forceinline__ void to_bytes_xyz(Plan& P) {
+// Plan offsets (elements) as byte offsets of the packed vertex.
+template <class R>
+__device__ __forceinline__ void to_bytes_xyz(PlanT<R>& P) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) P.off[i] *= 32;
+    for (int i = 0; i < 4; ++i) P.off[i] *= kXyzElemBytes<R>;
 }
 
 // Sum the per-group partials acc[m] of lanes (g, p) over the groups and
@@ -149,21 +168,23 @@ __device__ __forceinline__ void finish_xyz(double* red, int lane, int ns, int G,
     }
 }
 
-// Per-wave LDS of the XYZ kernels (bytes): s/u plans [2][kPlanChunk], node
-// weights, the reduction area; t plans [2][kTChunk], on-site values [2][4][kTChunk],
-// weights, site vectors [8][4][16], the lattice-sum matrix (ns*ns) and the
-// reduction area (the t layout is the larger one).
+// Per-wave LDS of the XYZ kernels (bytes) in precision R: s/u plans
+// [2][kPlanChunk], node weights (FP64), the reduction area; t plans
+// [2][kTChunk], on-site values [2][4][kTChunk], weights, site vectors
+// [8][4][16], the lattice-sum matrix (ns*ns, FP64) and the reduction area
+// (the t layout is the larger one).
+template <class R>
 struct XyzWaveLds {
-    static constexpr size_t su_plans() { return (size_t)2 * kPlanChunk * sizeof(Plan); }
+    static constexpr size_t su_plans() { return (size_t)2 * kPlanChunk * sizeof(PlanT<R>); }
     static constexpr size_t su_w() { return (size_t)kPlanChunk * sizeof(double); }
-    static constexpr size_t t_plans() { return (size_t)2 * kTChunk * sizeof(Plan); }
-    static constexpr size_t t_ons() { return (size_t)8 * kTChunk * sizeof(double); }
-    static constexpr size_t t_w() { return (size_t)kTChunk * sizeof(double); }
-    static constexpr size_t t_vb() { return (size_t)8 * 4 * 16 * sizeof(double); }
+    static constexpr size_t t_plans() { return (size_t)2 * kTChunk * sizeof(PlanT<R>); }
+    static constexpr size_t t_ons() { return (size_t)8 * kTChunk * sizeof(R); }
+    static constexpr size_t t_w() { return (size_t)kTChunk * sizeof(R); }
+    static constexpr size_t t_vb() { return (size_t)8 * 4 * 16 * sizeof(R); }
     static constexpr size_t mat() { return (size_t)kXyzMaxPairs * kXyzMaxPairs * sizeof(double); }
     static constexpr size_t red() { return (size_t)4 * kWave * sizeof(double); }
     static constexpr size_t su_bytes() { return su_plans() + su_w() + red(); }
-    static constexpr size_t t_work() { return t_plans() + t_ons() + t_w() + t_vb(); }
+    static constexpr size_t t_work() { return ((t_plans() + t_ons() + t_w() + t_vb()) + 15) & ~(size_t)15; }
     static constexpr size_t t_bytes() { return (t_work() > mat() ? t_work() : mat()) + red(); }
     static constexpr size_t bytes() { return ((su_bytes() > t_bytes() ? su_bytes() : t_bytes()) + 31) & ~(size_t)31; }
 };
@@ -171,20 +192,23 @@ struct XyzWaveLds {
 // ------------------------------------------------------------------ s, u -
 
 // One wave per (s,t,u) triple, lanes (g, p): channel CH = 0 (s) or 2 (u);
-// the s launch writes dGamma, the u launch adds.  A.w must point at LDS.
-template <int CH>
+// the s launch writes dGamma, the u launch adds.  R: precision of the
+// interpolation and products; in FP32 the chunk sums are folded into
+// compensated sums (CompSum), the results are FP64.
+template <int CH, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-k_xyz_su(FlowArgs A, const double4* __restrict__ gv, const int* __restrict__ uo_a, const int* __restrict__ uo_c,
+k_xyz_su(FlowArgs A, const V4<R>* __restrict__ gv, const int* __restrict__ uo_a, const int* __restrict__ uo_c,
          int n_triples, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
+    using L = XyzWaveLds<R>;
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, false);
     A.w = sh.w;
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * XyzWaveLds::bytes();
-    Plan* plan = reinterpret_cast<Plan*>(base);
-    double* wts = reinterpret_cast<double*>(base + XyzWaveLds::su_plans());
-    double* red = reinterpret_cast<double*>(base + XyzWaveLds::su_plans() + XyzWaveLds::su_w());
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(false) + wid * L::bytes();
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);
+    double* wts = reinterpret_cast<double*>(base + L::su_plans());
+    double* red = reinterpret_cast<double*>(base + L::su_plans() + L::su_w());
     const int o = xcd_order(n_triples);
     if (o < 0) return;
     const int q = o / nf, it = o % nf;
@@ -192,23 +216,24 @@ k_xyz_su(FlowArgs A, const double4* __restrict__ gv, const int* __restrict__ uo_
     const int ic = CH == 0 ? A.su_c[q] : uo_c[q];
     const Triple T = make_triple(A.w, nf, ia, it, ic);
     const long vsz = (long)n_triples * ns;
-    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc(gv, vsz);
+    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc<R>(gv, vsz);
     const int G = kWave / ns, g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(32 * p, 32 * sh.swap[p]);
+    const int2 pp = make_int2(kXyzElemBytes<R> * p, kXyzElemBytes<R> * sh.swap[p]);
     const int iv = CH == 0 ? ia : ic;
     const int cnt = A.tab_n[CH * nf + iv];
     const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
     const double* tg = A.tab_g + (long)(CH * nf + iv) * nq;
-    const double cross = CH == 0 ? -1.0 : 1.0;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const R cross = CH == 0 ? R(-1) : R(1);
+    R acc[4] = {0, 0, 0, 0};
+    CompSum<R> sum[4];
     for (int k0 = 0; k0 < cnt; k0 += kPlanChunk) {
         const int kc = min(kPlanChunk, cnt - k0);
         {
             const int j = lane % kPlanChunk, vec = lane / kPlanChunk;
             if (j < kc) {
                 const double om = tw[k0 + j];
-                Plan P;
+                PlanT<R> P;
                 if (CH == 0)
                     make_plan(A.w, nf, ns, T.s, vec == 0 ? T.w1p - om : om - T.w1, vec == 0 ? om - T.w2p : om - T.w2,
                               0, ia, P, &sh.lut);
@@ -223,40 +248,57 @@ k_xyz_su(FlowArgs A, const double4* __restrict__ gv, const int* __restrict__ uo_
         wave_lds_sync();
         if (act) {
             for (int k = g; k < kc; k += G) {
-                double a[4], b[4];
-                eval_xyz(plan[k], rv, pp, a);
-                eval_xyz(plan[kPlanChunk + k], rv, pp, b);
-                const double W = wts[k];
-                acc[3] = fma(W, a[3] * b[3] + a[0] * b[0] + a[1] * b[1] + a[2] * b[2], acc[3]);
-                acc[0] = fma(W, a[3] * b[0] + a[0] * b[3] + cross * (a[1] * b[2] + a[2] * b[1]), acc[0]);
-                acc[1] = fma(W, a[3] * b[1] + a[1] * b[3] + cross * (a[2] * b[0] + a[0] * b[2]), acc[1]);
-                acc[2] = fma(W, a[3] * b[2] + a[2] * b[3] + cross * (a[0] * b[1] + a[1] * b[0]), acc[2]);
+                R a[4], b[4];
+                eval_xyz<R>(plan[k], rv, pp, a);
+                eval_xyz<R>(plan[kPlanChunk + k], rv, pp, b);
+                const R W = (R)wts[k];
+                acc[3] = fmr(W, a[3] * b[3] + a[0] * b[0] + a[1] * b[1] + a[2] * b[2], acc[3]);
+                acc[0] = fmr(W, a[3] * b[0] + a[0] * b[3] + cross * (a[1] * b[2] + a[2] * b[1]), acc[0]);
+                acc[1] = fmr(W, a[3] * b[1] + a[1] * b[3] + cross * (a[2] * b[0] + a[0] * b[2]), acc[1]);
+                acc[2] = fmr(W, a[3] * b[2] + a[2] * b[3] + cross * (a[0] * b[1] + a[1] * b[0]), acc[2]);
+            }
+        }
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                sum[m].add(acc[m]);
+                acc[m] = R(0);
             }
         }
         wave_lds_sync();
     }
-    finish_xyz(red, lane, ns, G, act, acc, dx + nf, vsz, T.out, CH != 0);
+    double out[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if constexpr (sizeof(R) == 8) sum[m].s = acc[m];
+        out[m] = sum[m].value();
+    }
+    finish_xyz(red, lane, ns, G, act, out, dx + nf, vsz, T.out, CH != 0);
 }
 
 // ---------------------------------------------------------------------- t -
 
 // One wave per triple, ordered by (t, s, u); adds to dGamma.  The lattice
 // sum of each strain m is the matrix M_m = sum_k W_k a_km b_km^T on one
-// 16x16 FP64 matrix-core tile (four nodes per step, operands from the site
-// vectors in LDS), contracted with the tabulated (ka, kb, count) terms.
+// 16x16 matrix-core tile (four nodes per step, operands from the site
+// vectors in LDS), contracted with the tabulated (ka, kb, count) terms.  In
+// FP32 the tile and the vertex corrections of each plan chunk are folded
+// into compensated sums; the contraction runs in FP64.
+template <class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+k_xyz_t(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+    constexpr bool kComp = sizeof(R) == 4;
     extern __shared__ __align__(32) unsigned char lds_raw[];
+    using L = XyzWaveLds<R>;
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, true);
     A.w = sh.w;
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * XyzWaveLds::bytes();
-    using L = XyzWaveLds;
-    Plan* plan = reinterpret_cast<Plan*>(base);                                            // [2][kTChunk]
-    double* ons = reinterpret_cast<double*>(base + L::t_plans());                          // [2][4][kTChunk]
-    double* wts = reinterpret_cast<double*>(base + L::t_plans() + L::t_ons());             // [kTChunk]
-    double* vb = reinterpret_cast<double*>(base + L::t_plans() + L::t_ons() + L::t_w());   // [8][4][16]
+    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L::bytes();
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                                    // [2][kTChunk]
+    R* ons = reinterpret_cast<R*>(base + L::t_plans());                                    // [2][4][kTChunk]
+    R* wts = reinterpret_cast<R*>(base + L::t_plans() + L::t_ons());                       // [kTChunk]
+    R* vb = reinterpret_cast<R*>(base + L::t_plans() + L::t_ons() + L::t_w());             // [8][4][16]
     double* mat = reinterpret_cast<double*>(base);                                         // [ns*ns] at the end
     double* red = reinterpret_cast<double*>(base + L::t_bytes() - L::red());
     const int o = xcd_order(n_triples);
@@ -266,18 +308,20 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
     const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
     const double t = T.t;
     const long vsz = (long)n_triples * ns;
-    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc(gv, vsz);
+    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc<R>(gv, vsz);
     const int G = kWave / ns, g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(32 * p, 32 * sh.swap[p]);
+    const int2 pp = make_int2(kXyzElemBytes<R> * p, kXyzElemBytes<R> * sh.swap[p]);
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};           // vertex corrections of pair p (lanes (g, p))
-    Vec4<double> cm[4];
+    R acc[4] = {0, 0, 0, 0};                         // vertex corrections of pair p (lanes (g, p))
+    CompSum<R> sacc[4];
+    Vec4<R> cm[4];
+    CompSum<R> ccm[kComp ? 4 : 1][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) cm[m] = Vec4<double>{0.0, 0.0, 0.0, 0.0};
-    for (int i = lane; i < 8 * 4 * 16; i += kWave) vb[i] = 0.0;     // padding pairs stay zero
+    for (int m = 0; m < 4; ++m) cm[m] = Vec4<R>{0, 0, 0, 0};
+    for (int i = lane; i < 8 * 4 * 16; i += kWave) vb[i] = R(0);     // padding pairs stay zero
     for (int k0 = 0; k0 < cnt; k0 += kTChunk) {
         const int kc = min(kTChunk, cnt - k0);
         {
@@ -289,15 +333,15 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
                 const double a0 = role == 0 ? T.w1 + om : (role == 1 ? om + T.w2p : (role == 2 ? T.w2p + om : T.w1 + om));
                 const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
                 const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
-                Plan P;
+                PlanT<R> P;
                 make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, &sh.lut);
                 to_bytes_xyz(P);
                 if (role < 2) {
                     plan[role * kTChunk + j] = P;
-                    if (role == 0) wts[j] = tg[k0 + j];
+                    if (role == 0) wts[j] = (R)tg[k0 + j];
                 } else {
-                    double v[4];
-                    eval_xyz(P, rv, make_int2(0, 32 * sh.swap[0]), v);
+                    R v[4];
+                    eval_xyz<R>(P, rv, make_int2(0, kXyzElemBytes<R> * sh.swap[0]), v);
 #pragma unroll
                     for (int m = 0; m < 4; ++m) ons[((role - 2) * 4 + m) * kTChunk + j] = v[m];
                 }
@@ -308,21 +352,21 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
             const int sc = min(4, kc - s0);
             if (act && g < sc) {
                 const int k = s0 + g;
-                double a[4], b[4];
-                eval_xyz(plan[k], rv, pp, a);
-                eval_xyz(plan[kTChunk + k], rv, pp, b);
-                const double W = wts[k];
+                R a[4], b[4];
+                eval_xyz<R>(plan[k], rv, pp, a);
+                eval_xyz<R>(plan[kTChunk + k], rv, pp, b);
+                const R W = wts[k];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     vb[(m * 4 + g) * 16 + p] = W * a[m];
                     vb[((4 + m) * 4 + g) * 16 + p] = b[m];
-                    double c1 = 0.0, c2 = 0.0;
+                    R c1 = 0, c2 = 0;
 #pragma unroll
                     for (int n = 0; n < 4; ++n) {
-                        c1 = fma(xyz_e(m, n), ons[(0 * 4 + n) * kTChunk + k], c1);
-                        c2 = fma(xyz_e(m, n), ons[(1 * 4 + n) * kTChunk + k], c2);
+                        c1 = fmr((R)xyz_e(m, n), ons[(0 * 4 + n) * kTChunk + k], c1);
+                        c2 = fmr((R)xyz_e(m, n), ons[(1 * 4 + n) * kTChunk + k], c2);
                     }
-                    acc[m] = fma(W, a[m] * c1 + b[m] * c2, acc[m]);
+                    acc[m] = fmr(W, a[m] * c1 + b[m] * c2, acc[m]);
                 }
             }
             wave_lds_sync();
@@ -331,14 +375,24 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
                 const bool in = k4 < sc;
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const double xa = in ? vb[(m * 4 + k4) * 16 + i16] : 0.0;
-                    const double xb = in ? vb[((4 + m) * 4 + k4) * 16 + i16] : 0.0;
-                    cm[m] = mfma16x16x4<double>(xa, xb, cm[m]);
+                    const R xa = in ? vb[(m * 4 + k4) * 16 + i16] : R(0);
+                    const R xb = in ? vb[((4 + m) * 4 + k4) * 16 + i16] : R(0);
+                    cm[m] = mfma16x16x4<R>(xa, xb, cm[m]);
                 }
             }
             wave_lds_sync();
             // the site vectors of the next sub-chunk overwrite these rows; rows of
             // nodes it does not fill are masked by `in` above
+        }
+        if constexpr (kComp) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                sacc[m].add(acc[m]);
+                acc[m] = R(0);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ccm[m][r].add(cm[m][r]);
+                cm[m] = Vec4<R>{0, 0, 0, 0};
+            }
         }
     }
     // contract each strain's matrix with the tabulated terms
@@ -348,17 +402,23 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
     for (int m = 0; m < 4; ++m) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int ka = mfma_row<double>(lane, r), kb = lane % 16;
-            if (ka < ns && kb < ns) mat[ka * ns + kb] = cm[m][r];
+            const int ka = mfma_row<R>(lane, r), kb = lane % 16;
+            double v;
+            if constexpr (kComp) v = ccm[m][r].value();
+            else v = (double)cm[m][r];
+            if (ka < ns && kb < ns) mat[ka * ns + kb] = v;
         }
         wave_lds_sync();
-        double s = 0.0;
+        double sv = 0.0;
         if (act)
             for (int qq = sh.off[p] + g; qq < sh.off[p + 1]; qq += G) {
                 const int tq = sh.terms[qq];
-                s = fma((double)(tq >> 16), mat[tq & 0xffff], s);
+                sv = fma((double)(tq >> 16), mat[tq & 0xffff], sv);
             }
-        tot[m] = fma(-2.0, s, act ? acc[m] : 0.0);
+        double av;
+        if constexpr (kComp) av = sacc[m].value();
+        else av = (double)acc[m];
+        tot[m] = fma(-2.0, sv, act ? av : 0.0);
         wave_lds_sync();
     }
     finish_xyz(red, lane, ns, G, act, tot, dx + nf, vsz, T.out, true);
@@ -375,15 +435,17 @@ k_xyz_t(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __res
 // nodes are built at once, one role per wave (site vectors a and b, the two
 // on-site vertices).  At the end wave m writes its matrix and the lanes of
 // all four waves contract it with the tabulated terms, strain by strain;
-// wave m adds strain m of every pair to dGamma.
+// wave m adds strain m of every pair to dGamma.  In FP32 the matrix tiles and
+// the vertex corrections of each plan chunk are folded into compensated sums.
 constexpr int kXyzMaxPairs4 = 32;
 constexpr int kXyzT4Chunk = 32;
 
+template <class R>
 struct XyzT4Lds {
-    static constexpr size_t plans() { return (size_t)2 * kXyzT4Chunk * sizeof(Plan); }
-    static constexpr size_t ons() { return (size_t)(8 + 1) * kXyzT4Chunk * sizeof(double); }
-    // 8 rows x (4 NG nodes) x (16 NT pairs) = 2048 doubles for either NT
-    static constexpr size_t vb() { return (size_t)8 * 8 * kXyzMaxPairs4 * sizeof(double); }
+    static constexpr size_t plans() { return (size_t)2 * kXyzT4Chunk * sizeof(PlanT<R>); }
+    static constexpr size_t ons() { return (size_t)(8 + 1) * kXyzT4Chunk * sizeof(R); }
+    // 8 rows x (4 NG nodes) x (16 NT pairs) = 2048 values for either NT
+    static constexpr size_t vb() { return (size_t)8 * 8 * kXyzMaxPairs4 * sizeof(R); }
     static constexpr size_t mat() { return (size_t)kXyzMaxPairs4 * kXyzMaxPairs4 * sizeof(double); }
     static constexpr size_t red() { return (size_t)16 * kWave * sizeof(double); }
     static constexpr size_t work() { return plans() + ons() + vb(); }
@@ -392,23 +454,24 @@ struct XyzT4Lds {
     static constexpr size_t bytes() { return area() > red() ? area() : red(); }
 };
 
-template <int NT>
+template <int NT, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu(4)))
-k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+k_xyz_t4(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
     constexpr int NG = 4 / NT;             // node groups of lanes per wave
     constexpr int SC = 4 * NG;             // nodes per sub-chunk
     constexpr int SP = 16 * NT;            // site-vector row stride (pairs)
+    constexpr bool kComp = sizeof(R) == 4;
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, true);
     A.w = sh.w;
-    using L = XyzT4Lds;
+    using L = XyzT4Lds<R>;
     unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true);
-    Plan* plan = reinterpret_cast<Plan*>(base);                                  // [2][chunk]
-    double* ons = reinterpret_cast<double*>(base + L::plans());                  // [2][4][chunk]
-    double* wts = ons + 8 * kXyzT4Chunk;                                         // [chunk]
-    double* vb = reinterpret_cast<double*>(base + L::plans() + L::ons());        // [8 rows][SC nodes][SP]
+    PlanT<R>* plan = reinterpret_cast<PlanT<R>*>(base);                          // [2][chunk]
+    R* ons = reinterpret_cast<R*>(base + L::plans());                            // [2][4][chunk]
+    R* wts = ons + 8 * kXyzT4Chunk;                                              // [chunk]
+    R* vb = reinterpret_cast<R*>(base + L::plans() + L::ons());                  // [8 rows][SC nodes][SP]
     double* mat = reinterpret_cast<double*>(base);                               // [ns*ns] after the node loop
     double* red = reinterpret_cast<double*>(base);                               // [4 waves][4 strains][64] at the end
     const int h = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -421,18 +484,20 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
     const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
     const double t = T.t;
     const long vsz = (long)n_triples * ns;
-    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc(gv, vsz);
+    const __amdgpu_buffer_rsrc_t rv = xyz_rsrc<R>(gv, vsz);
     const int g = lane / ns, p = lane % ns;      // node lanes: g < NG
-    const int2 pp = make_int2(32 * p, 32 * sh.swap[p]);
+    const int2 pp = make_int2(kXyzElemBytes<R> * p, kXyzElemBytes<R> * sh.swap[p]);
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};        // vertex corrections over this lane's nodes
-    Vec4<double> c[NT][NT];
+    R acc[4] = {0, 0, 0, 0};                     // vertex corrections over this lane's nodes
+    CompSum<R> sacc[4];
+    Vec4<R> c[NT][NT];
+    CompSum<R> cc[kComp ? NT : 1][kComp ? NT : 1][4];
 #pragma unroll
     for (int I = 0; I < NT; ++I)
 #pragma unroll
-        for (int J = 0; J < NT; ++J) c[I][J] = Vec4<double>{0.0, 0.0, 0.0, 0.0};
+        for (int J = 0; J < NT; ++J) c[I][J] = Vec4<R>{0, 0, 0, 0};
     for (int k0 = 0; k0 < cnt; k0 += kXyzT4Chunk) {
         const int kc = min(kXyzT4Chunk, cnt - k0);
         {
@@ -444,15 +509,15 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
                 const double a0 = role == 0 ? T.w1 + om : (role == 1 ? om + T.w2p : (role == 2 ? T.w2p + om : T.w1 + om));
                 const double a1 = role == 0 ? t : (role == 1 ? t : (role == 2 ? T.w2 - om : om - T.w1p));
                 const double a2 = role == 0 ? T.w1p - om : (role == 1 ? om - T.w2 : -t);
-                Plan P;
+                PlanT<R> P;
                 make_plan(A.w, nf, ns, a0, a1, a2, role < 2 ? 1 : 2, it, P, &sh.lut);
                 to_bytes_xyz(P);
                 if (role < 2) {
                     plan[role * kXyzT4Chunk + j] = P;
-                    if (role == 0) wts[j] = tg[k0 + j];
+                    if (role == 0) wts[j] = (R)tg[k0 + j];
                 } else {
-                    double v[4];
-                    eval_xyz(P, rv, make_int2(0, 32 * sh.swap[0]), v);
+                    R v[4];
+                    eval_xyz<R>(P, rv, make_int2(0, kXyzElemBytes<R> * sh.swap[0]), v);
 #pragma unroll
                     for (int m = 0; m < 4; ++m) ons[((role - 2) * 4 + m) * kXyzT4Chunk + j] = v[m];
                 }
@@ -464,21 +529,21 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
             const int kk = NG * h + g;
             if (g < NG && kk < sc) {
                 const int k = s0 + kk;
-                double a[4], b[4];
-                eval_xyz(plan[k], rv, pp, a);
-                eval_xyz(plan[kXyzT4Chunk + k], rv, pp, b);
-                const double W = wts[k];
+                R a[4], b[4];
+                eval_xyz<R>(plan[k], rv, pp, a);
+                eval_xyz<R>(plan[kXyzT4Chunk + k], rv, pp, b);
+                const R W = wts[k];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     vb[(m * SC + kk) * SP + p] = W * a[m];
                     vb[((4 + m) * SC + kk) * SP + p] = b[m];
-                    double c1 = 0.0, c2 = 0.0;
+                    R c1 = 0, c2 = 0;
 #pragma unroll
                     for (int n = 0; n < 4; ++n) {
-                        c1 = fma(xyz_e(m, n), ons[(0 * 4 + n) * kXyzT4Chunk + k], c1);
-                        c2 = fma(xyz_e(m, n), ons[(1 * 4 + n) * kXyzT4Chunk + k], c2);
+                        c1 = fmr((R)xyz_e(m, n), ons[(0 * 4 + n) * kXyzT4Chunk + k], c1);
+                        c2 = fmr((R)xyz_e(m, n), ons[(1 * 4 + n) * kXyzT4Chunk + k], c2);
                     }
-                    acc[m] = fma(W, a[m] * c1 + b[m] * c2, acc[m]);
+                    acc[m] = fmr(W, a[m] * c1 + b[m] * c2, acc[m]);
                 }
             }
             __syncthreads();
@@ -488,22 +553,37 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
 #pragma unroll
                 for (int q = 0; q < NG; ++q) {
                     const int node = 4 * q + k4;
-                    double xa[NT], xb[NT];
+                    R xa[NT], xb[NT];
 #pragma unroll
                     for (int I = 0; I < NT; ++I) {
                         const int pr = 16 * I + i16;
                         const bool in = node < sc && pr < ns;
                         const int off = in ? node * SP + pr : 0;
-                        xa[I] = in ? vb[h * SC * SP + off] : 0.0;
-                        xb[I] = in ? vb[(4 + h) * SC * SP + off] : 0.0;
+                        xa[I] = in ? vb[h * SC * SP + off] : R(0);
+                        xb[I] = in ? vb[(4 + h) * SC * SP + off] : R(0);
                     }
 #pragma unroll
                     for (int I = 0; I < NT; ++I)
 #pragma unroll
-                        for (int J = 0; J < NT; ++J) c[I][J] = mfma16x16x4<double>(xa[I], xb[J], c[I][J]);
+                        for (int J = 0; J < NT; ++J) c[I][J] = mfma16x16x4<R>(xa[I], xb[J], c[I][J]);
                 }
             }
             __syncthreads();
+        }
+        if constexpr (kComp) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                sacc[m].add(acc[m]);
+                acc[m] = R(0);
+            }
+#pragma unroll
+            for (int I = 0; I < NT; ++I)
+#pragma unroll
+                for (int J = 0; J < NT; ++J) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) cc[I][J][r].add(c[I][J][r]);
+                    c[I][J] = Vec4<R>{0, 0, 0, 0};
+                }
         }
     }
     // contraction with the tabulated terms, strain by strain: wave m writes
@@ -518,23 +598,31 @@ k_xyz_t4(FlowArgs A, const double4* __restrict__ gv, int n_triples, double* __re
                 for (int J = 0; J < NT; ++J)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int ka = 16 * I + mfma_row<double>(lane, r), kb = 16 * J + lane % 16;
-                        if (ka < ns && kb < ns) mat[ka * ns + kb] = c[I][J][r];
+                        const int ka = 16 * I + mfma_row<R>(lane, r), kb = 16 * J + lane % 16;
+                        double v;
+                        if constexpr (kComp) v = cc[I][J][r].value();
+                        else v = (double)c[I][J][r];
+                        if (ka < ns && kb < ns) mat[ka * ns + kb] = v;
                     }
         }
         __syncthreads();
         if (g < NG) {
-            double sacc = 0.0;
+            double sv = 0.0;
             for (int qq = sh.off[p] + NG * h + g; qq < sh.off[p + 1]; qq += 4 * NG) {
                 const int tq = sh.terms[qq];
-                sacc = fma((double)(tq >> 16), mat[tq & 0xffff], sacc);
+                sv = fma((double)(tq >> 16), mat[tq & 0xffff], sv);
             }
-            tot[m] = sacc;
+            tot[m] = sv;
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) red[(h * 4 + m) * kWave + lane] = g < NG ? fma(-2.0, tot[m], acc[m]) : 0.0;
+    for (int m = 0; m < 4; ++m) {
+        double av;
+        if constexpr (kComp) av = sacc[m].value();
+        else av = (double)acc[m];
+        red[(h * 4 + m) * kWave + lane] = g < NG ? fma(-2.0, tot[m], av) : 0.0;
+    }
     __syncthreads();
     // wave m adds strain m of every pair
     if (lane < ns) {

@@ -335,6 +335,42 @@ pffrg_status xyz_sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* ds
     return launch_check("k_xyz_sigma");
 }
 
+// The vertex kernels of the XYZ right-hand side in precision R (the packed
+// vertex, s writes, u and t add).
+template <class R>
+pffrg_status xyz_vertex(pffrg_ctx* c, const FlowArgs& A, const double* x, double* dx) {
+    V4<R>* gv = static_cast<V4<R>*>(c->gv);
+    hipLaunchKernelGGL(k_xyz_pack<R>, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz,
+                       x + c->nf, gv);
+    TRY(launch_check("k_xyz_pack"));
+    const int T = c->nsu * c->nf;
+    const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per = (blocks + 7) / 8;
+    const SharedLds S{c->nf, c->ns, c->n_terms};
+    const size_t lds_su = S.bytes(false) + kWavesPerBlock * XyzWaveLds<R>::bytes();
+    const size_t lds_t = S.bytes(true) + kWavesPerBlock * XyzWaveLds<R>::bytes();
+    const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
+    prof_mark(c, PFFRG_K_VERTEX, false);
+    hipLaunchKernelGGL((k_xyz_su<0, R>), grid, block, lds_su, c->stream, A, (const V4<R>*)gv, (const int*)c->uo_a,
+                       (const int*)c->uo_c, T, dx);
+    hipLaunchKernelGGL((k_xyz_su<2, R>), grid, block, lds_su, c->stream, A, (const V4<R>*)gv, (const int*)c->uo_a,
+                       (const int*)c->uo_c, T, dx);
+    TRY(launch_check("k_xyz_su"));
+    if (c->ns > kXyzMaxPairs) {
+        // four waves per triple, one triple per workgroup (up to 16 pairs the
+        // one-wave kernel below is the faster: 0.414 against 0.457 ms per
+        // right-hand side at honeycomb range 6 in FP64)
+        const int per4 = (T + 7) / 8;
+        hipLaunchKernelGGL((k_xyz_t4<2, R>), dim3(8 * per4), block, S.bytes(true) + XyzT4Lds<R>::bytes(), c->stream,
+                           A, (const V4<R>*)gv, T, dx);
+        prof_mark(c, PFFRG_K_VERTEX, true);
+        return launch_check("k_xyz_t4");
+    }
+    hipLaunchKernelGGL(k_xyz_t<R>, grid, block, lds_t, c->stream, A, (const V4<R>*)gv, T, dx);
+    prof_mark(c, PFFRG_K_VERTEX, true);
+    return launch_check("k_xyz_t");
+}
+
 pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     FlowArgs A = c->args();
     TRY(xyz_sigma_rhs(c, lam, x, dx));             // the sigma part of dx is dsig
@@ -342,36 +378,8 @@ pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     hipExtLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, et.start, et.stop, 0, A, lam, x,
                           (const double*)dx);
     TRY(launch_check("k_node_tables"));
-    double4* gv = static_cast<double4*>(c->gv);
-    hipLaunchKernelGGL(k_xyz_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz,
-                       x + c->nf, gv);
-    TRY(launch_check("k_xyz_pack"));
-    const int T = c->nsu * c->nf;
-    const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int per = (blocks + 7) / 8;
-    const SharedLds S{c->nf, c->ns, c->n_terms};
-    const size_t lds_su = S.bytes(false) + kWavesPerBlock * XyzWaveLds::bytes();
-    const size_t lds_t = S.bytes(true) + kWavesPerBlock * XyzWaveLds::bytes();
-    const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
-    prof_mark(c, PFFRG_K_VERTEX, false);
-    hipLaunchKernelGGL(k_xyz_su<0>, grid, block, lds_su, c->stream, A, (const double4*)gv, (const int*)c->uo_a,
-                       (const int*)c->uo_c, T, dx);
-    hipLaunchKernelGGL(k_xyz_su<2>, grid, block, lds_su, c->stream, A, (const double4*)gv, (const int*)c->uo_a,
-                       (const int*)c->uo_c, T, dx);
-    TRY(launch_check("k_xyz_su"));
-    if (c->ns > kXyzMaxPairs) {
-        // four waves per triple, one triple per workgroup (up to 16 pairs the
-        // one-wave kernel below is the faster: 0.414 against 0.457 ms per
-        // right-hand side at honeycomb range 6)
-        const int per4 = (T + 7) / 8;
-        hipLaunchKernelGGL(k_xyz_t4<2>, dim3(8 * per4), block, S.bytes(true) + XyzT4Lds::bytes(), c->stream, A,
-                           (const double4*)gv, T, dx);
-        prof_mark(c, PFFRG_K_VERTEX, true);
-        return launch_check("k_xyz_t4");
-    }
-    hipLaunchKernelGGL(k_xyz_t, grid, block, lds_t, c->stream, A, (const double4*)gv, T, dx);
-    prof_mark(c, PFFRG_K_VERTEX, true);
-    return launch_check("k_xyz_t");
+    if (c->prec == PFFRG_FP32) return xyz_vertex<float>(c, A, x, dx);
+    return xyz_vertex<double>(c, A, x, dx);
 }
 
 pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
@@ -681,7 +689,6 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
     if (xyz) {
         for (int i = 0; i < 3 * lat->n_pairs; ++i)
             if (!std::isfinite(coupling3[i])) return fail(PFFRG_EINVAL, "couplings must be finite");
-        if (prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "the XYZ flow runs in FP64 only");
     }
     const int nf = mesh->n_freq, ns = lat->n_pairs;
     const int nterms = lat->rpa_off[ns];
@@ -801,8 +808,8 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         HIP_TRY(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
         if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
-        if (xyz && (SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds::bytes() > 64 * 1024 ||
-                    SharedLds{nf, ns, nterms}.bytes(true) + XyzT4Lds::bytes() > 64 * 1024))
+        if (xyz && (SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds<double>::bytes() > 64 * 1024 ||
+                    SharedLds{nf, ns, nterms}.bytes(true) + XyzT4Lds<double>::bytes() > 64 * 1024))
             return fail(PFFRG_EUNSUPPORTED, "XYZ vertex kernel LDS budget exceeded");
         return PFFRG_OK;
     };

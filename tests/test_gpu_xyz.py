@@ -13,8 +13,8 @@ below, inside and above the mesh, on a mesh point and at half a mesh point
 step; the honeycomb J1-J2-J3 workload size (range 6, 14 pairs, 32
 frequencies), square range 7 (20 pairs, 32 frequencies) and pyrochlore
 range 5 (31 pairs, 24 frequencies) on sampled triples; the SU(2) limit
-(Jx = Jy = Jz) against an SU(2) context; and the refused inputs (FP32, more
-than 32 pairs, reverse mode).
+(Jx = Jy = Jz) against an SU(2) context; and the refused inputs (more than 32
+pairs, reverse mode).
 """
 
 import zlib
@@ -54,7 +54,7 @@ def _seed(*key) -> int:
     return zlib.crc32("/".join(map(str, key)).encode()) % 1000
 
 
-def _setup(name):
+def _setup(name, precision="fp64"):
     import torch
     import oracle
     from paper_2109_13317_amd import build_tables
@@ -62,7 +62,7 @@ def _setup(name):
     make, L, mesh = CASES[name]
     model = make()
     tables = build_tables(model, L)
-    ctx = Context(tables, mesh)
+    ctx = Context(tables, mesh, precision=precision)
     orc = oracle.Oracle(model, L, mesh)
     assert ctx.nc == 4 and orc.nc == 4
     return torch, tables, ctx, orc
@@ -231,9 +231,6 @@ def test_xyz_refused_inputs():
     from paper_2109_13317_amd.flow import Context
     mesh = W.log_mesh(0.01, 10.0, 5)
     t_small = build_tables(W.model_xyz("square", j1=(1.0, 0.5, 0.2)), 2)
-    with pytest.raises(_lib.PffrgError) as ei:
-        Context(t_small, mesh, precision="fp32")
-    assert ei.value.status == _lib.EUNSUPPORTED
     t_big = build_tables(W.model_heisenberg_kitaev(1.0, -1.0), 5)        # 46 pairs
     assert t_big.n_pairs > 32
     with pytest.raises(_lib.PffrgError) as ei:
@@ -244,3 +241,43 @@ def test_xyz_refused_inputs():
     with pytest.raises(_lib.PffrgError) as ei:
         ctx.rhs_vjp(0.5, x, torch.zeros_like(x))
     assert ei.value.status == _lib.EUNSUPPORTED
+
+
+FP32_TOL = 1e-5          # the FP32 bar of the SU(2) mode, per right-hand side
+
+
+@pytest.mark.parametrize("name", ["square_L2_N8", "honeycomb_L3_N6", "heisenberg_kitaev_L3_N5", "pyrochlore_L5_N3"])
+@pytest.mark.parametrize("lam_kind", ["low", "mid", "high"])
+def test_xyz_fp32_rhs(name, lam_kind):
+    """FP32 mode of the XYZ flow (vertex interpolation, channel products and
+    lattice-sum matrices in FP32 with compensated chunk sums; self-energy,
+    tables and contraction in FP64): the self-energy derivative to 1e-10,
+    the vertex derivative within 1e-5 of its largest element, against the
+    FP64 oracle; the one-wave t kernel up to 16 pairs and the four-wave one
+    beyond."""
+    torch, tables, ctx, orc = _setup(name, "fp32")
+    mesh = ctx.mesh
+    lam = {"low": 0.5 * mesh[0], "mid": 0.37, "high": 1.7 * mesh[-1]}[lam_kind]
+    x = W.random_state(ctx.nf, ctx.ns, seed=_seed(name, lam_kind, "fp32"), strains=4)
+    d = ctx.rhs(lam, torch.from_numpy(x).cuda()).cpu().numpy()
+    from tests.parity import compare_parts
+    es, ev = compare_parts(orc, tables, orc.rhs(lam, expand_state(orc, tables, x)), d)
+    _say(f"xyz fp32 rhs {name} lam={lam:.4g} ({ctx.ns} pairs): sigma {es:.2e} vertex {ev:.2e}")
+    assert es <= TOL and ev <= FP32_TOL
+
+
+def test_xyz_fp32_rk4_flow_chi():
+    """40 RK4 steps of the Heisenberg-Kitaev honeycomb (range 2) in FP32
+    against the FP64 oracle flow: chi of the four strains within 1e-4 at
+    every step."""
+    torch, tables, ctx, orc = _setup("heisenberg_kitaev_L2_N6", "fp32")
+    sched = W.geometric_schedule(50.0, 0.5, 40)
+    x = ctx.init_state()
+    got = []
+    ctx.flow(x, schedule=sched, scheme="rk4",
+             observer=lambda lam, chi, ck: got.append(chi.cpu().numpy().copy()) and 0)
+    ref = []
+    orc.flow(sched, observer=lambda lam, xs: ref.append(orc.chi_comps(lam, xs)))
+    worst = max(compare_chi_comps(orc, tables, rc, gc) for gc, rc in zip(got, ref))
+    _say(f"xyz fp32 RK4 flow: chi worst {worst:.2e}")
+    assert len(got) == len(ref) == len(sched) - 1 and worst <= 1e-4
