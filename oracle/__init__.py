@@ -88,6 +88,8 @@ def _load():
         lib.orc_chi.restype = None
         lib.orc_chi_comps.argtypes = [P, D, P, P]
         lib.orc_chi_comps.restype = None
+        lib.orc_chi_tri.argtypes = [P, D, P, P, P]
+        lib.orc_chi_tri.restype = None
         _lib = lib
     return _lib
 
@@ -104,7 +106,10 @@ class Oracle:
     a >= c of (s, u) as a(a+1)/2 + c and ns pads every basis site's site
     list to the same length.  Heisenberg models (SU(2)) have two strains,
     spin and density; XYZ models (couplings (Jx, Jy, Jz), Sec. 2) four: x, y,
-    z and density.
+    z and density; general models (3x3 coupling matrices, Sec. 2) sixteen,
+    Gamma^{mu nu} at index 4 mu + nu (0 the density index, 1..3 x, y, z),
+    each held as r with Gamma = r where xi(mu) xi(nu) = 1 and Gamma = i r
+    where it is -1 (Eq. 18).
     """
 
     def __init__(self, model, lattice_range: int, mesh: np.ndarray, threads: int = 0):
@@ -112,8 +117,8 @@ class Oracle:
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.threads = int(threads)
-        self.symmetry = "xyz" if self.lat.coupling.ndim == 3 else "su2"
-        self.nc = 4 if self.symmetry == "xyz" else 2
+        self.symmetry = {2: "su2", 3: "xyz", 4: "tri"}[self.lat.coupling.ndim]
+        self.nc = {"su2": 2, "xyz": 4, "tri": 16}[self.symmetry]
         lat = self.lat
         self._keep = [self.mesh, lat.nsites, lat.cell, lat.bas, lat.lookup]
         self._s = _Lat(self.nf, self.mesh.ctypes.data, lat.nb, lat.ns, lat.nsites.ctypes.data,
@@ -141,6 +146,10 @@ class Oracle:
         parts = self.split(x)
         if self.nc == 2:
             parts[1][...] = (self.lat.coupling / 4.0)[:, None, None, :]
+        elif self.nc == 16:      # Gamma^{mu nu} = J^{mu nu}/4 for mu, nu = x, y, z (Eq. 22)
+            for m in range(1, 4):
+                for n in range(1, 4):
+                    parts[1 + 4 * m + n][...] = (self.lat.coupling[:, :, m - 1, n - 1] / 4.0)[:, None, None, :]
         else:
             for c in range(3):
                 parts[1 + c][...] = (self.lat.coupling[:, :, c] / 4.0)[:, None, None, :]
@@ -186,6 +195,15 @@ class Oracle:
         out = np.zeros((self.nc, self.lat.nb, self.lat.ns))
         self.lib.orc_chi_comps(self._p, float(lam), _ptr(x), _ptr(out))
         return out
+
+    def chi_tri(self, lam: float, x: np.ndarray):
+        """TRI: chi^{mu nu} for mu, nu = 0..3, real and imaginary parts, each
+        [4, 4, nb, ns] (Eq. 30 from the spin tensors)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        re = np.zeros((4, 4, self.lat.nb, self.lat.ns))
+        im = np.zeros((4, 4, self.lat.nb, self.lat.ns))
+        self.lib.orc_chi_tri(self._p, float(lam), _ptr(x), _ptr(re), _ptr(im))
+        return re, im
 
     def chi_k_xyz(self, chi: np.ndarray, kpts: np.ndarray) -> np.ndarray:
         """XYZ structure factor (Eq. 31) per unit cell:

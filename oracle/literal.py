@@ -5,8 +5,10 @@ oracle computes, written straight from the paper's explicit equations:
 
   * the vertex is built as 16 basis functions Gamma^{mu nu} (Eq. 16) with the
     SU(2) constraint (Gamma^{11}=Gamma^{22}=Gamma^{33}, off-diagonals zero),
-    or for XYZ states the XYZ constraint (the four diagonal components
-    Gamma^{00}, Gamma^{11}, Gamma^{22}, Gamma^{33} free, off-diagonals zero);
+    for XYZ states the XYZ constraint (the four diagonal components
+    Gamma^{00}, Gamma^{11}, Gamma^{22}, Gamma^{33} free, off-diagonals zero),
+    and for general (TRI) states all sixteen, complex where Eq. 18 makes
+    them imaginary;
     values outside the stored octant come from the general symmetry relations
     (Eq. 18, with xi of Eq. 19 and mu<->nu transposition applied literally);
   * the spin tensor Gamma^{a'b';ab} = Gamma^{mu nu} sigma^mu_{a'a} sigma^nu_{b'b}
@@ -62,6 +64,10 @@ class LiteralFlow:
             return m * (-XI)[None, :]
         su = a * (a + 1) // 2 + c
         parts = self.o.split(self.x)
+        if self.o.nc == 16:
+            # general state: Gamma^{mu nu} = r or i r by xi(mu) xi(nu) (Eq. 18)
+            r = np.array([parts[1 + q][b, su, t, k] for q in range(16)]).reshape(4, 4)
+            return np.where(XIXI > 0, 1.0, 1j) * r
         m = np.zeros((4, 4))
         if self.o.nc == 2:
             _, gs, gd = parts
@@ -86,11 +92,11 @@ class LiteralFlow:
             return self.gamma(b1, d, b2, u, t, s) * (-XI)[None, :]
         k = self.lat.index(b1, d, b2)
         if k < 0:
-            return np.zeros((4, 4))
+            return np.zeros((4, 4), dtype=np.complex128)
         (sa, sb), (fs0, fs1) = self._bracket(s)
         (ta, tb), (ft0, ft1) = self._bracket(t)
         (ua, ub), (fu0, fu1) = self._bracket(u)
-        acc = np.zeros((4, 4))
+        acc = np.zeros((4, 4), dtype=np.complex128)
         for ui, fu in ((ua, fu0), (ub, fu1)):
             for ti, ft in ((ta, ft0), (tb, ft1)):
                 for si, fs in ((sa, fs0), (sb, fs1)):

@@ -21,6 +21,11 @@
  *     Eq. 25 are done by hand; the coefficients are Pauli-algebra results
  *     (sigma^a sigma^b = delta_ab + i eps_abc sigma^c), and the SU(2) ones are
  *     the XYZ ones with the three spin strains equal.
+ *   - TRI vertex (nc = 16 strains, Sec. 3 general time-reversal invariant
+ *     case): every Gamma^{mu nu}, index 4 mu + nu, real or imaginary by
+ *     Eq. 18 and held as a real number; the channel products, the
+ *     self-energy sums and the correlations are evaluated with explicit
+ *     spin tensors (Eq. 25) instead of hand-contracted coefficients.
  *   - Vertex symmetries (Eq. 18 with xi of Eq. 19), octant storage s>=u,
  *     t>=0 (Sec. 4.2) and trilinear interpolation with constant
  *     extrapolation (Eq. 37); Sigma odd with linear interpolation (Eq. 36).
@@ -28,7 +33,7 @@
  *     for every site within the bond-distance truncation range (Eq. 34);
  *     no point-group reduction is used, so the oracle trusts no symmetry
  *     table.  Lattice sums run over every site in range of both ends.
- *   - Correlations chi^{zz} and chi^{00} (Eq. 30).
+ *   - Correlations chi^{zz} and chi^{00} (Eq. 30); TRI: every chi^{mu nu}.
  *
  * Readings where the paper is silent (also listed in the design notes):
  *   R1 (delta parts) S and the S-part of S_kat are integrated analytically at
@@ -52,6 +57,7 @@
  *   -g(w) d(|p|-L)/(p - sig(p)) - g(p) d(|w|-L)/(w - sig(w))
  *   + g(w) g(p)^2 sig'(p) + g(p) g(w)^2 sig'(w).
  */
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -61,6 +67,7 @@
 #endif
 
 #define TWO_PI 6.283185307179586476925286766559
+#define MAXC 16   /* most vertex strains per element (TRI) */
 
 typedef struct {
     int nf;              /* number of positive mesh frequencies */
@@ -72,7 +79,7 @@ typedef struct {
     const int *bas;      /* [nb][ns]   basis index of each listed site */
     int rm;              /* half-width of the offset lookup box */
     const int *lookup;   /* [nb][2rm+1][2rm+1][2rm+1][nb] -> list index or -1 */
-    int nc;              /* vertex strains: 2 (SU(2): spin, density) or 4 (XYZ: x, y, z, density) */
+    int nc;              /* vertex strains: 2 (SU(2): spin, density), 4 (XYZ: x, y, z, density), 16 (TRI) */
 } orc_lattice;
 
 /* ------------------------------------------------------------ layout --- */
@@ -250,10 +257,13 @@ static int piece_nodes(const orc_lattice *L, double lo, double hi, double *nodes
  * d sig/dLambda(w) = (1/2pi) sum_{x=+-Lambda} F(w,x) / (x - sig(x)) with
  *   SU(2): F = 2 sum_j Gd_{0j}(w+x, 0, w-x) - (3 Gs_{00} + Gd_{00})(w+x, x-w, 0)
  *   XYZ:   F = 2 sum_j Gd_{0j}(w+x, 0, w-x) - (Gx + Gy + Gz + Gd)_{00}(w+x, x-w, 0)
+ *   TRI:   F from the spin tensors themselves (sigma_sum_tri)
  * (Eq. 23 contracted with Eq. 25: the direct term traces the density
  * strain, the exchange term sums every diagonal component; the sum over j
  * covers every site in range of the reference site, basis site 0).
  */
+static double sigma_sum_tri(const orc_lattice *L, const double *x, double w, double xx);
+
 double orc_sigma_rhs_at(const orc_lattice *L, double lam, const double *x, double w)
 {
     orc_eval E = {L, x, NULL, lam};
@@ -262,6 +272,10 @@ double orc_sigma_rhs_at(const orc_lattice *L, double lam, const double *x, doubl
     double acc = 0.0;
     for (int sx = 0; sx < 2; ++sx) {
         double xx = sx == 0 ? lam : -lam;
+        if (L->nc == 16) {
+            acc += sigma_sum_tri(L, x, w, xx) / (xx - sig_at(&E, xx));
+            continue;
+        }
         double f = 0.0;
         for (int k = 0; k < L->nsites[0]; ++k) {
             const int *cr = &L->cell[(long)k * 3];
@@ -309,7 +323,7 @@ typedef struct {
  *   t: dGm = -2 sum_j a_jm b_jm + Am sum_n e(m,n) O1n + Bm sum_n e(m,n) O2n
  *      with e(m,n) = +1 if m or n is the density strain or m = n, else -1.
  */
-static void integrand_s(const orc_eval *E, const orc_out *o, double w, double wt, double acc[4])
+static void integrand_s(const orc_eval *E, const orc_out *o, double w, double wt, double *acc)
 {
     const orc_lattice *L = E->L;
     double A[4], B[4];
@@ -331,7 +345,7 @@ static void integrand_s(const orc_eval *E, const orc_out *o, double w, double wt
 /* e(m,n) of the XYZ t-channel vertex corrections and correlations. */
 static double xyz_sign(int m, int n) { return (m == 3 || n == 3 || m == n) ? 1.0 : -1.0; }
 
-static void integrand_t(const orc_eval *E, const orc_out *o, double w, double wt, double acc[4])
+static void integrand_t(const orc_eval *E, const orc_out *o, double w, double wt, double *acc)
 {
     const orc_lattice *L = E->L;
     const int zero[3] = {0, 0, 0};
@@ -372,7 +386,7 @@ static void integrand_t(const orc_eval *E, const orc_out *o, double w, double wt
     }
 }
 
-static void integrand_u(const orc_eval *E, const orc_out *o, double w, double wt, double acc[4])
+static void integrand_u(const orc_eval *E, const orc_out *o, double w, double wt, double *acc)
 {
     const orc_lattice *L = E->L;
     double A[4], B[4];
@@ -391,18 +405,251 @@ static void integrand_u(const orc_eval *E, const orc_out *o, double w, double wt
     }
 }
 
-typedef void (*integrand_fn)(const orc_eval *, const orc_out *, double, double, double[4]);
+/* ------------------------------------------- general (TRI) vertex ----- */
+
+/*
+ * TRI vertex (nc = 16): every basis function Gamma^{mu nu}, mu, nu = 0..3
+ * (Sec. 3, Eq. 16), strain index 4 mu + nu.  Gamma^{mu nu} is real where
+ * xi(mu) xi(nu) = 1 and imaginary where it is -1 (Eq. 18); the state holds
+ * the real number r with Gamma = r, resp. Gamma = i r ("real
+ * representation").  The channel products are formed literally: each
+ * vertex becomes its spin tensor (Eq. 25), the spin sums of Eq. 24 run over
+ * the 2x2x2x2 tensors, and the result is projected back on the basis with
+ * Pauli traces.
+ */
+typedef double complex cplx;
+
+static const cplx PAULI[4][2][2] = {
+    {{1.0, 0.0}, {0.0, 1.0}},
+    {{0.0, 1.0}, {1.0, 0.0}},
+    {{0.0, -I}, {I, 0.0}},
+    {{1.0, 0.0}, {0.0, -1.0}}};
+
+static double xi_of(int m) { return m == 0 ? 1.0 : -1.0; }
+
+/* The stored octant (s >= u >= 0, t >= 0) interpolated (Eq. 37) for all 16
+ * strains; corners with s < u through the s <-> u relation (R4). */
+static void gamma_octant(const orc_lattice *L, const double *x, int b1, int k,
+                         double s, double t, double u, double g[4][4])
+{
+    int sa[2], ta[2], ua[2];
+    double fs[2], ft[2], fu[2];
+    bracket(L, s, &sa[0], &sa[1], &fs[0], &fs[1]);
+    bracket(L, t, &ta[0], &ta[1], &ft[0], &ft[1]);
+    bracket(L, u, &ua[0], &ua[1], &fu[0], &fu[1]);
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) g[m][n] = 0.0;
+    for (int iu = 0; iu < 2; ++iu)
+        for (int it = 0; it < 2; ++it)
+            for (int is = 0; is < 2; ++is) {
+                double wgt = fu[iu] * ft[it] * fs[is];
+                if (wgt == 0.0) continue;
+                int a = sa[is], c = ua[iu];
+                for (int m = 0; m < 4; ++m)
+                    for (int n = 0; n < 4; ++n) {
+                        double v;
+                        if (a >= c) v = x[vidx(L, 4 * m + n, b1, a, ta[it], c, k)];
+                        else v = -xi_of(n) * x[vidx(L, 4 * m + n, b1, c, ta[it], a, k)];
+                        g[m][n] += wgt * v;
+                    }
+            }
+}
+
+/* Gamma^{mu nu}_{i1 i2}(s,t,u) in the real representation between site
+ * (b1, cell 0) and site (b2, cell d), through the relations of Eq. 18;
+ * zero outside the truncation range (Eq. 34). */
+static void gamma16(const orc_lattice *L, const double *x, int b1, const int d[3], int b2,
+                    double s, double t, double u, double g[4][4])
+{
+    double h[4][4];
+    const int nd[3] = {-d[0], -d[1], -d[2]};
+    if (s < 0.0) {          /* Gamma^{mu nu}_{i1 i2}(s,t,u) = Gamma^{nu mu}_{i2 i1}(-s,t,u) */
+        gamma16(L, x, b2, nd, b1, -s, t, u, h);
+        for (int m = 0; m < 4; ++m)
+            for (int n = 0; n < 4; ++n) g[m][n] = h[n][m];
+        return;
+    }
+    if (t < 0.0) {          /* = xi(mu) xi(nu) Gamma^{mu nu}_{i1 i2}(s,-t,u) */
+        gamma16(L, x, b1, d, b2, s, -t, u, h);
+        for (int m = 0; m < 4; ++m)
+            for (int n = 0; n < 4; ++n) g[m][n] = xi_of(m) * xi_of(n) * h[m][n];
+        return;
+    }
+    if (u < 0.0) {          /* = xi(mu) xi(nu) Gamma^{nu mu}_{i2 i1}(s,t,-u) */
+        gamma16(L, x, b2, nd, b1, s, t, -u, h);
+        for (int m = 0; m < 4; ++m)
+            for (int n = 0; n < 4; ++n) g[m][n] = xi_of(m) * xi_of(n) * h[n][m];
+        return;
+    }
+    if (s < u) {            /* = -xi(nu) Gamma^{mu nu}_{i1 i2}(u,t,s) */
+        gamma16(L, x, b1, d, b2, u, t, s, h);
+        for (int m = 0; m < 4; ++m)
+            for (int n = 0; n < 4; ++n) g[m][n] = -xi_of(n) * h[m][n];
+        return;
+    }
+    int k = site_of(L, b1, d, b2);
+    if (k < 0) {
+        for (int m = 0; m < 4; ++m)
+            for (int n = 0; n < 4; ++n) g[m][n] = 0.0;
+        return;
+    }
+    gamma_octant(L, x, b1, k, s, t, u, g);
+}
+
+/* Spin tensor V[a'][b'][a][b] = sum Gamma^{mu nu} sigma^mu_{a'a} sigma^nu_{b'b} (Eq. 25). */
+static void spin_tensor(const double g[4][4], cplx V[2][2][2][2])
+{
+    memset(V, 0, sizeof(cplx) * 16);
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) {
+            if (g[m][n] == 0.0) continue;
+            cplx gv = xi_of(m) * xi_of(n) > 0.0 ? (cplx)g[m][n] : I * g[m][n];
+            for (int p = 0; p < 2; ++p)
+                for (int a = 0; a < 2; ++a) {
+                    if (PAULI[m][p][a] == 0.0) continue;
+                    for (int q = 0; q < 2; ++q)
+                        for (int b = 0; b < 2; ++b)
+                            V[p][q][a][b] += gv * PAULI[m][p][a] * PAULI[n][q][b];
+                }
+        }
+}
+
+static void spin_tensor_at(const orc_lattice *L, const double *x, int b1, const int d[3], int b2,
+                           double s, double t, double u, cplx V[2][2][2][2])
+{
+    double g[4][4];
+    gamma16(L, x, b1, d, b2, s, t, u, g);
+    spin_tensor(g, V);
+}
+
+/* Basis functions of a spin tensor, Gamma^{mu nu} = (1/4) sum_{a'b'ab}
+ * V[a'][b'][a][b] sigma^mu_{a a'} sigma^nu_{b b'}, added times wt to acc in
+ * the real representation (real part where xi xi = 1, imaginary part where
+ * it is -1; the other part vanishes by Eq. 18). */
+static void project_add(cplx P[2][2][2][2], double wt, double *acc)
+{
+    for (int m = 0; m < 4; ++m)
+        for (int n = 0; n < 4; ++n) {
+            cplx v = 0.0;
+            for (int p = 0; p < 2; ++p)
+                for (int q = 0; q < 2; ++q)
+                    for (int a = 0; a < 2; ++a)
+                        for (int b = 0; b < 2; ++b)
+                            v += P[p][q][a][b] * PAULI[m][a][p] * PAULI[n][b][q];
+            v *= 0.25;
+            acc[4 * m + n] += wt * (xi_of(m) * xi_of(n) > 0.0 ? creal(v) : cimag(v));
+        }
+}
+
+/* s channel: legs (1',2';3,4) times (3,4;1,2), summed over the spins of 3, 4. */
+static void integrand_s_tri(const orc_eval *E, const orc_out *o, double w, double wt, double *acc)
+{
+    const orc_lattice *L = E->L;
+    cplx A[2][2][2][2], B[2][2][2][2], P[2][2][2][2];
+    spin_tensor_at(L, E->x, o->b, o->dk, o->bk, o->s, o->w1p - w, w - o->w2p, A);
+    spin_tensor_at(L, E->x, o->b, o->dk, o->bk, o->s, w - o->w1, w - o->w2, B);
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    cplx v = 0.0;
+                    for (int c = 0; c < 2; ++c)
+                        for (int d = 0; d < 2; ++d) v += A[p][q][c][d] * B[c][d][a][b];
+                    P[p][q][a][b] = v;
+                }
+    project_add(P, wt, acc);
+}
+
+/* t channel: the particle-hole RPA term -sum_j Gamma_{i1 j} Gamma_{j i2}
+ * (legs (1',4;1,3) times (3,2';4,2)) and the two vertex corrections with the
+ * on-site vertices at i2 (legs (2',3;4,2)) and at i1 (legs (4,1';1,3)). */
+static void integrand_t_tri(const orc_eval *E, const orc_out *o, double w, double wt, double *acc)
+{
+    const orc_lattice *L = E->L;
+    const int zero[3] = {0, 0, 0};
+    cplx A[2][2][2][2], B[2][2][2][2], O[2][2][2][2], P[2][2][2][2];
+    memset(P, 0, sizeof(P));
+    for (int j = 0; j < L->nsites[o->b]; ++j) {
+        const int *cj = &L->cell[((long)o->b * L->ns + j) * 3];
+        int bj = L->bas[(long)o->b * L->ns + j];
+        int d2[3] = {o->dk[0] - cj[0], o->dk[1] - cj[1], o->dk[2] - cj[2]};
+        if (site_of(L, bj, d2, o->bk) < 0) continue;
+        spin_tensor_at(L, E->x, o->b, cj, bj, o->w1 + w, o->t, o->w1p - w, A);
+        spin_tensor_at(L, E->x, bj, d2, o->bk, w + o->w2p, o->t, w - o->w2, B);
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q)
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        for (int c = 0; c < 2; ++c)
+                            for (int d = 0; d < 2; ++d) P[p][q][a][b] -= A[p][d][a][c] * B[c][q][d][b];
+    }
+    spin_tensor_at(L, E->x, o->b, o->dk, o->bk, o->w1 + w, o->t, o->w1p - w, A);
+    spin_tensor_at(L, E->x, o->bk, zero, o->bk, o->w2p + w, o->w2 - w, -o->t, O);
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int c = 0; c < 2; ++c)
+                        for (int d = 0; d < 2; ++d) P[p][q][a][b] += A[p][d][a][c] * O[q][c][d][b];
+    spin_tensor_at(L, E->x, o->b, zero, o->b, o->w1 + w, w - o->w1p, -o->t, O);
+    spin_tensor_at(L, E->x, o->b, o->dk, o->bk, w + o->w2p, o->t, w - o->w2, B);
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int c = 0; c < 2; ++c)
+                        for (int d = 0; d < 2; ++d) P[p][q][a][b] += O[d][p][a][c] * B[c][q][d][b];
+    project_add(P, wt, acc);
+}
+
+/* u channel: legs (4,2';1,3) times (1',3;4,2). */
+static void integrand_u_tri(const orc_eval *E, const orc_out *o, double w, double wt, double *acc)
+{
+    const orc_lattice *L = E->L;
+    cplx A[2][2][2][2], B[2][2][2][2], P[2][2][2][2];
+    spin_tensor_at(L, E->x, o->b, o->dk, o->bk, o->w1 + w, w - o->w2p, o->u, A);
+    spin_tensor_at(L, E->x, o->b, o->dk, o->bk, o->w1p + w, o->w2 - w, o->u, B);
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    cplx v = 0.0;
+                    for (int c = 0; c < 2; ++c)
+                        for (int d = 0; d < 2; ++d) v += A[d][q][a][c] * B[p][c][d][b];
+                    P[p][q][a][b] = v;
+                }
+    project_add(P, wt, acc);
+}
+
+/* Eq. 23's spin sums for the TRI vertex at spin up (alpha_1 = 0):
+ * sum_{a2} V_{0j}[0][a2][0][a2] over the sites j in range of basis site 0
+ * at (w+x, 0, w-x), minus sum_{a2} V_{00}[a2][0][0][a2] at (w+x, x-w, 0). */
+static double sigma_sum_tri(const orc_lattice *L, const double *x, double w, double xx)
+{
+    const int zero[3] = {0, 0, 0};
+    cplx V[2][2][2][2];
+    cplx f = 0.0;
+    for (int k = 0; k < L->nsites[0]; ++k) {
+        spin_tensor_at(L, x, 0, &L->cell[(long)k * 3], L->bas[k], w + xx, 0.0, w - xx, V);
+        for (int a2 = 0; a2 < 2; ++a2) f += V[0][a2][0][a2];
+    }
+    spin_tensor_at(L, x, 0, zero, 0, w + xx, xx - w, 0.0, V);
+    for (int a2 = 0; a2 < 2; ++a2) f -= V[a2][0][0][a2];
+    return creal(f);
+}
+
+typedef void (*integrand_fn)(const orc_eval *, const orc_out *, double, double, double *);
 
 /*
  * One channel: (1/2pi) * integral of the bubble times the channel integrand.
  * partner(w) = ps * w + pc  (s: pc - w; t: w - t; u: u + w) and its zero c.
  */
 static void channel(const orc_eval *E, const orc_out *o, integrand_fn fn,
-                    double ps, double pc, double acc[4])
+                    double ps, double pc, double *acc)
 {
     const orc_lattice *L = E->L;
     double lam = E->lam;
-    double loc[4] = {0.0, 0.0, 0.0, 0.0};
+    double loc[MAXC] = {0.0};
 
     /* delta parts (R1): the S in Skat(partner) and the S in Skat(w) */
     for (int sx = 0; sx < 2; ++sx) {
@@ -458,10 +705,11 @@ void orc_vertex_rhs_element(const orc_lattice *L, double lam, const double *x, c
     o.w2p = 0.5 * (o.s - o.t - o.u);
     o.w1 = 0.5 * (o.s - o.t + o.u);
     o.w2 = 0.5 * (o.s + o.t - o.u);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    channel(&E, &o, integrand_s, -1.0, o.s, acc);   /* partner s - w */
-    channel(&E, &o, integrand_t, 1.0, -o.t, acc);   /* partner w - t */
-    channel(&E, &o, integrand_u, 1.0, o.u, acc);    /* partner u + w */
+    double acc[MAXC] = {0.0};
+    const int tri = L->nc == 16;
+    channel(&E, &o, tri ? integrand_s_tri : integrand_s, -1.0, o.s, acc);   /* partner s - w */
+    channel(&E, &o, tri ? integrand_t_tri : integrand_t, 1.0, -o.t, acc);   /* partner w - t */
+    channel(&E, &o, tri ? integrand_u_tri : integrand_u, 1.0, o.u, acc);    /* partner u + w */
     for (int comp = 0; comp < L->nc; ++comp) out[comp] = acc[comp];
 }
 
@@ -485,7 +733,7 @@ void orc_rhs(const orc_lattice *L, double lam, const double *x, double *dx, int 
         while (su_index(a + 1, 0) <= su) ++a;
         int c = su - (int)su_index(a, 0);
         for (int k = 0; k < L->nsites[b]; ++k) {
-            double out[4];
+            double out[MAXC];
             orc_vertex_rhs_element(L, lam, x, dsig, b, k, a, it, c, out);
             for (int comp = 0; comp < L->nc; ++comp) dx[vidx(L, comp, b, a, it, c, k)] = out[comp];
         }
@@ -600,4 +848,87 @@ void orc_chi(const orc_lattice *L, double lam, const double *x, double *chi_zz, 
     memcpy(chi_zz, both, sizeof(double) * plane);
     memcpy(chi_dd, both + plane, sizeof(double) * plane);
     free(both);
+}
+
+/*
+ * TRI correlations chi^{mu nu}_ij for mu, nu = 0..3 (Eq. 30, R5) from the
+ * spin tensors: with G = -i g on |w| >= Lambda,
+ *   chi^{mu nu}_ij = d_ij d_{mu nu} (1/4pi) I g^2
+ *       - (1/16pi^2) II g1^2 g2^2 sum sigma^mu_{a1 a1'} sigma^nu_{a2 a2'}
+ *         [V_ij(w1+w2, 0, w1-w2) - d_ij V^x_ii(w1+w2, w2-w1, 0)][a1'][a2'][a1][a2]
+ * where V^x is the on-site spin tensor with its two outgoing legs exchanged
+ * (the -(1' <-> 2') part of Eq. 16).  out_re / out_im [16][nb][ns], index
+ * 4 mu + nu first.
+ */
+void orc_chi_tri(const orc_lattice *L, double lam, const double *x, double *out_re, double *out_im)
+{
+    orc_eval E = {L, x, NULL, lam};
+    double wmax = L->w[L->nf - 1];
+    int cap = 2 * (2 * L->nf + 4);
+    double *nw = (double *)malloc(sizeof(double) * cap);
+    double *ww = (double *)malloc(sizeof(double) * cap);
+    double *g2 = (double *)malloc(sizeof(double) * cap);
+    double *tmp = (double *)malloc(sizeof(double) * (2 * L->nf + 4));
+    int n = 0;
+    double lo[2] = {-wmax, lam}, hi[2] = {-lam, wmax};
+    for (int ip = 0; ip < 2; ++ip) {
+        if (!(lo[ip] < hi[ip])) continue;
+        int nn = piece_nodes(L, lo[ip], hi[ip], tmp);
+        for (int i = 0; i < nn; ++i) {
+            double wl = i > 0 ? 0.5 * (tmp[i] - tmp[i - 1]) : 0.0;
+            double wr = i + 1 < nn ? 0.5 * (tmp[i + 1] - tmp[i]) : 0.0;
+            nw[n] = tmp[i];
+            ww[n] = wl + wr;
+            double g = gbare(&E, tmp[i]);
+            g2[n] = g * g;
+            ++n;
+        }
+    }
+    double bubble = 0.0;
+    for (int i = 0; i < n; ++i) bubble += ww[i] * g2[i];
+    bubble /= 2.0 * TWO_PI;
+    const double pref = 1.0 / (4.0 * TWO_PI * TWO_PI);   /* 1/(16 pi^2) */
+    const int zero[3] = {0, 0, 0};
+    const long plane = (long)L->nb * L->ns;
+    for (int b = 0; b < L->nb; ++b)
+        for (int k = 0; k < L->nsites[b]; ++k) {
+            const int *ck = &L->cell[((long)b * L->ns + k) * 3];
+            int bk = L->bas[(long)b * L->ns + k];
+            int onsite = (k == 0);
+            cplx acc[16];
+            for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double w1 = nw[i], w2 = nw[j];
+                    double f = ww[i] * ww[j] * g2[i] * g2[j];
+                    cplx V[2][2][2][2], X[2][2][2][2];
+                    spin_tensor_at(L, x, b, ck, bk, w1 + w2, 0.0, w1 - w2, V);
+                    if (onsite) {
+                        spin_tensor_at(L, x, b, zero, b, w1 + w2, w2 - w1, 0.0, X);
+                        for (int p = 0; p < 2; ++p)
+                            for (int q = 0; q < 2; ++q)
+                                for (int a = 0; a < 2; ++a)
+                                    for (int c = 0; c < 2; ++c) V[p][q][a][c] -= X[q][p][a][c];
+                    }
+                    for (int m = 0; m < 4; ++m)
+                        for (int nn = 0; nn < 4; ++nn) {
+                            cplx v = 0.0;
+                            for (int a1 = 0; a1 < 2; ++a1)
+                                for (int a1p = 0; a1p < 2; ++a1p) {
+                                    if (PAULI[m][a1][a1p] == 0.0) continue;
+                                    for (int a2 = 0; a2 < 2; ++a2)
+                                        for (int a2p = 0; a2p < 2; ++a2p)
+                                            v += PAULI[m][a1][a1p] * PAULI[nn][a2][a2p] * V[a1p][a2p][a1][a2];
+                                }
+                            acc[4 * m + nn] += f * v;
+                        }
+                }
+            for (int c = 0; c < 16; ++c) {
+                cplx v = -pref * acc[c];
+                if (onsite && c % 5 == 0) v += bubble;   /* mu == nu */
+                out_re[c * plane + (long)b * L->ns + k] = creal(v);
+                out_im[c * plane + (long)b * L->ns + k] = cimag(v);
+            }
+        }
+    free(nw); free(ww); free(g2); free(tmp);
 }

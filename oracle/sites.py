@@ -79,15 +79,25 @@ class UnreducedLattice:
 
         # couplings J_{(0,b),(c,b')}: each listed interaction and its reverse;
         # a Heisenberg model gives one number per site, an XYZ model (params
-        # (Jx, Jy, Jz)) three: coupling[nb, ns, 3]
-        vec = any(np.ndim(v) == 1 for v in model.params.values())
-        self.coupling = np.zeros((nb, ns, 3) if vec else (nb, ns))
+        # (Jx, Jy, Jz)) three: coupling[nb, ns, 3]; a general model (params
+        # 3x3 matrices M, the term S_from . M . S_to of Sec. 5.3) a matrix per
+        # site, coupling[nb, ns, 3, 3], the reverse direction getting M^T
+        dims = {np.ndim(v) for v in model.params.values()}
+        if 2 in dims:
+            shape, zero = (nb, ns, 3, 3), np.zeros((3, 3))
+        elif 1 in dims:
+            shape, zero = (nb, ns, 3), np.zeros(3)
+        else:
+            shape, zero = (nb, ns), 0.0
+        self.coupling = np.zeros(shape)
         for (pname, f, t, d0, d1, d2) in model.interactions:
-            J = np.asarray(model.params.get(pname, (0.0, 0.0, 0.0) if vec else 0.0), dtype=np.float64)
-            for (b1, d, b2) in ((f, (d0, d1, d2), t), (t, (-d0, -d1, -d2), f)):
+            J = np.asarray(model.params.get(pname, zero), dtype=np.float64)
+            if len(shape) == 4 and J.ndim < 2:       # a number or a diagonal in a general model
+                J = np.diag(np.broadcast_to(J, (3,)).astype(np.float64))
+            for (b1, d, b2, M) in ((f, (d0, d1, d2), t, J), (t, (-d0, -d1, -d2), f, J.T)):
                 k = self.index(b1, d, b2)
                 if k >= 0:
-                    self.coupling[b1, k] += J
+                    self.coupling[b1, k] += M
 
     def index(self, b1: int, d, b2: int) -> int:
         rm = self.rm

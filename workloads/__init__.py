@@ -113,7 +113,9 @@ class Model:
     ``interactions`` lists (param, b_from, b_to, da0, da1, da2); the value of
     each named parameter is in ``params``.  A number J is a Heisenberg
     coupling, J S_from . S_to; a triple (Jx, Jy, Jz) an XYZ coupling,
-    Jx S^x S^x + Jy S^y S^y + Jz S^z S^z (Sec. 2).  The Hamiltonian is the sum
+    Jx S^x S^x + Jy S^y S^y + Jz S^z S^z (Sec. 2); a 3x3 matrix M the general
+    coupling S_from . M . S_to (Sec. 2, Sec. 5.3), which has a direction: the
+    reversed bond carries M^T.  The Hamiltonian is the sum
     over every listed bond and all lattice translations, each unordered bond
     counted once.
     """
@@ -129,8 +131,11 @@ class Model:
 
     @property
     def symmetry(self) -> str:
-        """'xyz' when the couplings are (Jx, Jy, Jz) triples, else 'su2'."""
-        return "xyz" if any(np.ndim(v) == 1 for v in self.params.values()) else "su2"
+        """'tri' when a coupling is a 3x3 matrix M (the term S_from . M . S_to,
+        Sec. 5.3), 'xyz' when the couplings are (Jx, Jy, Jz) triples, else
+        'su2'."""
+        dims = {np.ndim(v) for v in self.params.values()}
+        return "tri" if 2 in dims else ("xyz" if 1 in dims else "su2")
 
 
 # Coupling shells by Euclidean distance: (parameter name, distance).
