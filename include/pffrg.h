@@ -137,6 +137,28 @@ pffrg_status pffrg_create(const pffrg_lattice *lat, const pffrg_mesh *mesh,
  * context.  NULL coupling3 or a non-finite coupling: PFFRG_EINVAL. */
 pffrg_status pffrg_create_xyz(const pffrg_lattice *lat, const double *coupling3, const pffrg_mesh *mesh,
                               pffrg_precision prec, void *stream, pffrg_ctx **out);
+
+/* A TRI context: the general time-reversal invariant model (Sec. 2:
+ * H = sum J_ij^{mu nu} S_i^mu S_j^nu with real 3x3 matrices; Sec. 3: all
+ * sixteen vertex components Gamma^{mu nu}, Eq. 16, with the symmetries of
+ * Eq. 18).  coupling9[9 p + 3 a + b] (host, copied) is M^{ab} of the bond
+ * (i_ref, j_p) in the term S_ref . M . S_j, a, b = x, y, z; lat->coupling is
+ * not read (it may be NULL).  The pair tables must reduce by lattice
+ * symmetries that map every directed bond to one with the same matrix (no
+ * spin rotation or permutation).  The state holds sixteen strains,
+ *   sig | G^{00} | G^{01} | ... | G^{33}   (strain 4 mu + nu, V = T*Ns each),
+ * index 0 the density, 1..3 x, y, z; G^{mu nu} is Gamma^{mu nu} where
+ * xi(mu) xi(nu) = 1 and its imaginary part where it is -1 (those components
+ * are imaginary, Eq. 18).  Initial condition G^{ab} = M^{ab}/4 for
+ * a, b = x, y, z, the rest 0 (Eq. 22).  The self-energy flow takes the spin
+ * average of the sums of Eq. 23 (it keeps Sigma imaginary).  pffrg_chi returns
+ * [16][Ns], the real parts of chi^{mu nu} at 4 mu + nu (Eq. 30); pffrg_chi_k
+ * sums chi^{xx} + chi^{yy} + chi^{zz} (Eq. 31); pffrg_chi_sites spreads all
+ * sixteen.  Up to 64 pairs, FP64 only (PFFRG_FP32: PFFRG_EUNSUPPORTED); the
+ * reverse-mode calls give PFFRG_EUNSUPPORTED on a TRI context.  NULL
+ * coupling9 or a non-finite coupling: PFFRG_EINVAL. */
+pffrg_status pffrg_create_tri(const pffrg_lattice *lat, const double *coupling9, const pffrg_mesh *mesh,
+                              pffrg_precision prec, void *stream, pffrg_ctx **out);
 pffrg_status pffrg_destroy(pffrg_ctx *ctx);
 pffrg_status pffrg_set_stream(pffrg_ctx *ctx, void *stream);
 

@@ -45,6 +45,7 @@ OBSERVER = ctypes.CFUNCTYPE(ctypes.c_int, D, P, P, P)
 SIGNATURES = {
     "pffrg_create": [ctypes.POINTER(Lattice), ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
     "pffrg_create_xyz": [ctypes.POINTER(Lattice), P, ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
+    "pffrg_create_tri": [ctypes.POINTER(Lattice), P, ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
     "pffrg_destroy": [P],
     "pffrg_set_stream": [P, P],
     "pffrg_set_vertex_mode": [P, I],

@@ -21,6 +21,7 @@
 #include "kernels_obs.h"
 #include "kernels_adj.h"
 #include "kernels_xyz.h"
+#include "kernels_tri.h"
 
 using namespace pffrg;
 using namespace pffrg_host;
@@ -34,8 +35,9 @@ constexpr int kRedBlocks = 512;
 
 struct pffrg_ctx {
     int nf = 0, ns = 0, nq = 0, nsu = 0;
-    int nc = 2;                     // vertex strains: 2 (SU(2)) or 4 (XYZ)
+    int nc = 2;                     // vertex strains: 2 (SU(2)), 4 (XYZ) or 16 (TRI)
     double* coupling3 = nullptr;    // XYZ: [3][ns] couplings Jx, Jy, Jz
+    double* coupling9 = nullptr;    // TRI: [ns][3][3] coupling matrices
     long vsz = 0, size = 0;
     pffrg_precision prec = PFFRG_FP64;
     hipStream_t stream = nullptr;
@@ -382,9 +384,50 @@ pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     return xyz_vertex<double>(c, A, x, dx);
 }
 
+// TRI right-hand side (kernels_tri.h): self-energy flow, node tables, the
+// packed sixteen-component vertex, then the s (writes), u and t (add)
+// launches, all in FP64.
+pffrg_status tri_sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* dsig) {
+    const ProfPair e = prof_pair(c, PFFRG_K_SIGMA);
+    hipExtLaunchKernelGGL(k_tri_sigma, dim3(c->nf), dim3(kWave), 0, c->stream, e.start, e.stop, 0, c->args(), lam, x,
+                          (long)c->vsz, dsig);
+    return launch_check("k_tri_sigma");
+}
+
+size_t tri_lds_su(int nf, int ns, int nterms) { return SharedLds{nf, ns, nterms}.bytes(false) + kTriWaves * TriSuLds::bytes(); }
+size_t tri_lds_t(int nf, int ns, int nterms) { return SharedLds{nf, ns, nterms}.bytes(true) + kTriWaves * TriTLds{ns}.bytes(); }
+
+pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
+    FlowArgs A = c->args();
+    TRY(tri_sigma_rhs(c, lam, x, dx));             // the sigma part of dx is dsig
+    const ProfPair et = prof_pair(c, PFFRG_K_TABLES);
+    hipExtLaunchKernelGGL(k_node_tables, dim3(3 * c->nf), dim3(kWave), 0, c->stream, et.start, et.stop, 0, A, lam, x,
+                          (const double*)dx);
+    TRY(launch_check("k_node_tables"));
+    double* gv = static_cast<double*>(c->gv);
+    hipLaunchKernelGGL(k_tri_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf, gv);
+    TRY(launch_check("k_tri_pack"));
+    const int T = c->nsu * c->nf;
+    const int blocks = (T + kTriWaves - 1) / kTriWaves;
+    const int per = (blocks + 7) / 8;
+    const dim3 grid(8 * per), block(kWave * kTriWaves);
+    prof_mark(c, PFFRG_K_VERTEX, false);
+    const size_t lds_su = tri_lds_su(c->nf, c->ns, c->n_terms);
+    hipLaunchKernelGGL(k_tri_su<0>, grid, block, lds_su, c->stream, A, (const double*)gv, (const int*)c->uo_a,
+                       (const int*)c->uo_c, T, dx);
+    hipLaunchKernelGGL(k_tri_su<2>, grid, block, lds_su, c->stream, A, (const double*)gv, (const int*)c->uo_a,
+                       (const int*)c->uo_c, T, dx);
+    TRY(launch_check("k_tri_su"));
+    hipLaunchKernelGGL(k_tri_t, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms), c->stream, A, (const double*)gv,
+                       T, dx);
+    prof_mark(c, PFFRG_K_VERTEX, true);
+    return launch_check("k_tri_t");
+}
+
 pffrg_status rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (!(lam > 0.0) || !std::isfinite(lam)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
     if (c->nc == 4) return xyz_rhs(c, lam, x, dx);
+    if (c->nc == 16) return tri_rhs(c, lam, x, dx);
     TRY(sigma_rhs(c, lam, x, dx));                  // the sigma part of dx is dsig
     if (c->prec == PFFRG_FP32) {
         TRY(tables_pack<float>(c, lam, x, dx));
@@ -672,23 +715,31 @@ const char* pffrg_status_string(pffrg_status s) {
 
 namespace {
 
-// The context of pffrg_create (coupling3 NULL, SU(2)) and pffrg_create_xyz
-// (coupling3 = [3][ns] couplings Jx, Jy, Jz; lat->coupling is not read).
-pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, const pffrg_mesh* mesh,
-                        pffrg_precision prec, void* stream, pffrg_ctx** out) {
+// The context of pffrg_create (coupling3 and coupling9 NULL, SU(2)),
+// pffrg_create_xyz (coupling3 = [3][ns] couplings Jx, Jy, Jz) and
+// pffrg_create_tri (coupling9 = [ns][3][3] coupling matrices); lat->coupling
+// is read for SU(2) only.
+pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, const double* coupling9,
+                        const pffrg_mesh* mesh, pffrg_precision prec, void* stream, pffrg_ctx** out) {
     if (!out) return fail(PFFRG_EINVAL, "out is null");
     *out = nullptr;
     if (!lat_in) return fail(PFFRG_EINVAL, "null lattice");
-    const bool xyz = coupling3 != nullptr;
+    const bool xyz = coupling3 != nullptr, tri = coupling9 != nullptr;
     pffrg_lattice lat_copy = *lat_in;
     if (xyz) lat_copy.coupling = coupling3;        // the x couplings stand in for the table check
+    if (tri) lat_copy.coupling = coupling9;        // so do the first entries of the matrices
     const pffrg_lattice* lat = &lat_copy;
     TRY(check_mesh(mesh, kMaxFreq));
-    TRY(check_lattice(lat, kMaxPairs));
+    TRY(check_lattice(lat, tri ? kTriMaxPairs : kMaxPairs));
     if (prec != PFFRG_FP64 && prec != PFFRG_FP32) return fail(PFFRG_EINVAL, "unknown precision");
+    if (tri && prec != PFFRG_FP64) return fail(PFFRG_EUNSUPPORTED, "TRI contexts run in FP64 only");
     if (xyz) {
         for (int i = 0; i < 3 * lat->n_pairs; ++i)
             if (!std::isfinite(coupling3[i])) return fail(PFFRG_EINVAL, "couplings must be finite");
+    }
+    if (tri) {
+        for (int i = 0; i < 9 * lat->n_pairs; ++i)
+            if (!std::isfinite(coupling9[i])) return fail(PFFRG_EINVAL, "couplings must be finite");
     }
     const int nf = mesh->n_freq, ns = lat->n_pairs;
     const int nterms = lat->rpa_off[ns];
@@ -697,7 +748,7 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
     if (!c) return fail(PFFRG_ENOMEM, "host allocation failed");
     c->nf = nf;
     c->ns = ns;
-    c->nc = xyz ? 4 : 2;
+    c->nc = tri ? 16 : (xyz ? 4 : 2);
     c->nq = 2 * nf + 10;
     c->nsu = nf * (nf + 1) / 2;
     c->vsz = (long)c->nsu * nf * ns;
@@ -731,6 +782,7 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
             TRY(upload(c, &c->rpa_term, packed.data(), packed.size()));
         }
         if (xyz) TRY(upload(c, &c->coupling3, coupling3, (size_t)3 * ns));
+        else if (tri) TRY(upload(c, &c->coupling9, coupling9, (size_t)9 * ns));
         else TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
         {
             // the same terms grouped by (ka, kb): entry = output pair | count << 16
@@ -778,7 +830,7 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         TRY(dev_alloc(c, &c->tab_g, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->dsig, (size_t)nf));
         {
-            double2* g2 = nullptr;      // large enough for either precision (XYZ: 32 bytes per element)
+            double2* g2 = nullptr;      // large enough for either precision (XYZ: 32 bytes per element, TRI 128)
             TRY(dev_alloc(c, &g2, (size_t)(c->nc / 2) * c->vsz));
             c->gv = g2;
         }
@@ -799,15 +851,17 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         TRY(dev_alloc(c, &c->cdsig, (size_t)nf));
         TRY(dev_alloc(c, &c->cot_g2, (size_t)c->nq));
         TRY(dev_alloc(c, &c->cchi, (size_t)2 * ns));
-        TRY(dev_alloc(c, &c->cot_copies, (size_t)kCotCopies * 2 * c->vsz));
+        if (c->nc == 2) TRY(dev_alloc(c, &c->cot_copies, (size_t)kCotCopies * 2 * c->vsz));   // reverse mode only
         HIP_TRY(hipHostMalloc((void**)&c->host_red, 2 * sizeof(double), hipHostMallocDefault));
         // second stream (default priority) and fork/join events of the
         // concurrent vertex mode
         HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
-        if (t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
+        if (!tri && t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
+        if (tri && (tri_lds_su(nf, ns, nterms) > 64 * 1024 || tri_lds_t(nf, ns, nterms) > 64 * 1024))
+            return fail(PFFRG_EUNSUPPORTED, "TRI vertex kernel LDS budget exceeded");
         if (xyz && (SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds<double>::bytes() > 64 * 1024 ||
                     SharedLds{nf, ns, nterms}.bytes(true) + XyzT4Lds<double>::bytes() > 64 * 1024))
             return fail(PFFRG_EUNSUPPORTED, "XYZ vertex kernel LDS budget exceeded");
@@ -825,6 +879,7 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
 
 pffrg_status no_xyz(const pffrg_ctx* c, const char* what) {
     if (c->nc == 4) return fail(PFFRG_EUNSUPPORTED, std::string(what) + " is not available for XYZ contexts");
+    if (c->nc == 16) return fail(PFFRG_EUNSUPPORTED, std::string(what) + " is not available for TRI contexts");
     return PFFRG_OK;
 }
 
@@ -834,7 +889,7 @@ extern "C" {
 
 pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffrg_precision prec, void* stream,
                           pffrg_ctx** out) {
-    return create_ctx(lat, nullptr, mesh, prec, stream, out);
+    return create_ctx(lat, nullptr, nullptr, mesh, prec, stream, out);
 }
 
 pffrg_status pffrg_create_xyz(const pffrg_lattice* lat, const double* coupling3, const pffrg_mesh* mesh,
@@ -843,7 +898,16 @@ pffrg_status pffrg_create_xyz(const pffrg_lattice* lat, const double* coupling3,
         if (out) *out = nullptr;
         return fail(PFFRG_EINVAL, "null XYZ couplings");
     }
-    return create_ctx(lat, coupling3, mesh, prec, stream, out);
+    return create_ctx(lat, coupling3, nullptr, mesh, prec, stream, out);
+}
+
+pffrg_status pffrg_create_tri(const pffrg_lattice* lat, const double* coupling9, const pffrg_mesh* mesh,
+                              pffrg_precision prec, void* stream, pffrg_ctx** out) {
+    if (!coupling9) {
+        if (out) *out = nullptr;
+        return fail(PFFRG_EINVAL, "null TRI couplings");
+    }
+    return create_ctx(lat, nullptr, coupling9, mesh, prec, stream, out);
 }
 
 pffrg_status pffrg_destroy(pffrg_ctx* c) {
@@ -882,6 +946,11 @@ pffrg_status pffrg_init_state(pffrg_ctx* c, double* x) {
                            c->nf, c->ns, (const double*)c->coupling3, x);
         return launch_check("k_xyz_init_state");
     }
+    if (c->nc == 16) {
+        hipLaunchKernelGGL(k_tri_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size,
+                           c->nf, c->ns, (const double*)c->coupling9, x);
+        return launch_check("k_tri_init_state");
+    }
     hipLaunchKernelGGL(k_init_state, dim3(grid_for(c->size, 256)), dim3(256), 0, c->stream, (long)c->size, c->nf,
                        c->ns, (const double*)c->coupling, x);
     return launch_check("k_init_state");
@@ -899,6 +968,7 @@ pffrg_status pffrg_sigma_rhs(pffrg_ctx* c, double lambda, const double* x, doubl
     if (!x || !dsig) return fail(PFFRG_EINVAL, "null pointer");
     if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(PFFRG_EINVAL, "lambda must be finite and > 0");
     if (c->nc == 4) return xyz_sigma_rhs(c, lambda, x, dsig);
+    if (c->nc == 16) return tri_sigma_rhs(c, lambda, x, dsig);
     return sigma_rhs(c, lambda, x, dsig);
 }
 
@@ -930,6 +1000,15 @@ pffrg_status pffrg_chi(pffrg_ctx* c, double lambda, const double* x, double* chi
                            (const double*)c->cg2, (const int*)c->cn, (const double*)c->chi_part, chi);
         return launch_check("k_xyz_chi_final");
     }
+    if (c->nc == 16) {
+        hipLaunchKernelGGL(k_tri_chi_pairs, dim3(c->ns, kChiSlices), dim3(kChiThreads), 0, c->stream,
+                           (const double*)c->w, c->nf, c->ns, (const int*)c->swap, x, (const double*)c->cw,
+                           (const double*)c->cq, (const double*)c->cg2, (const int*)c->cn, c->chi_part);
+        TRY(launch_check("k_tri_chi_pairs"));
+        hipLaunchKernelGGL(k_tri_chi_final, dim3(1), dim3(64), 0, c->stream, c->ns, (const double*)c->cq,
+                           (const double*)c->cg2, (const int*)c->cn, (const double*)c->chi_part, chi);
+        return launch_check("k_tri_chi_final");
+    }
     hipLaunchKernelGGL(k_chi_pairs, dim3(c->ns, kChiSlices), dim3(kChiThreads), 0, c->stream, (const double*)c->w,
                        c->nf, c->ns, (const int*)c->swap, x, (const double*)c->cw, (const double*)c->cq,
                        (const double*)c->cg2, (const int*)c->cn, c->chi_part);
@@ -943,10 +1022,13 @@ pffrg_status pffrg_chi_k(pffrg_ctx* c, const double* chi, int nk, const double* 
     TRY(check_ctx(c));
     if (nk < 0 || (nk > 0 && (!chi || !kp || !out))) return fail(PFFRG_EINVAL, "bad chi(k) arguments");
     if (nk == 0) return PFFRG_OK;
-    // SU(2): 3 chi^zz; XYZ: chi^xx + chi^yy + chi^zz
+    // SU(2): 3 chi^zz; XYZ: chi^xx + chi^yy + chi^zz; TRI: chi^{11} + chi^{22} + chi^{33}
+    // (components 5, 10 and 15 of the sixteen)
+    const double* c0 = c->nc == 16 ? chi + 5 * c->ns : chi;
+    const int stride = c->nc == 16 ? 5 * c->ns : c->ns;
     hipLaunchKernelGGL(k_chi_k, dim3((nk + kChiKWaves - 1) / kChiKWaves), dim3(64 * kChiKWaves), 0, c->stream, c->nterm,
-                       (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, chi, c->nc == 4 ? 3 : 1,
-                       c->ns, c->nc == 4 ? 1.0 : 3.0, nk, kp, out);
+                       (const int*)c->chi_pair, (const double*)c->chi_dr, 1.0 / c->nb, c0, c->nc == 2 ? 1 : 3,
+                       stride, c->nc == 2 ? 3.0 : 1.0, nk, kp, out);
     return launch_check("k_chi_k");
 }
 

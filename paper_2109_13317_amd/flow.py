@@ -25,9 +25,10 @@ def _lattice_struct(t: LatticeTables):
     """(pffrg_lattice, arrays it points into: keep them alive for the call)."""
     keep = [np.ascontiguousarray(a, dtype=np.int32) for a in (t.swap, t.mult, t.rpa_off, t.rpa_ka,
                                                               t.rpa_kb, t.rpa_cnt)]
-    # an XYZ model's coupling triples go to pffrg_create_xyz; the lattice
-    # struct then carries their x components, which it does not read
-    coup = t.coupling if t.coupling.ndim == 1 else t.coupling[:, 0]
+    # an XYZ model's coupling triples go to pffrg_create_xyz and a general
+    # model's matrices to pffrg_create_tri; the lattice struct then carries a
+    # component of them, which it does not read
+    coup = t.coupling.reshape(len(t.coupling), -1)[:, 0]
     keep += [np.ascontiguousarray(coup, dtype=np.float64),
              np.ascontiguousarray(t.site_pair, dtype=np.int32),
              np.ascontiguousarray(t.site_pos, dtype=np.float64),
@@ -42,7 +43,8 @@ class Context:
     """A ``pffrg_ctx``: one lattice model on one frequency mesh.  Tables of a
     Heisenberg model give an SU(2) context (two strains, spin and density);
     tables of an XYZ model (coupling triples) an XYZ context (four strains:
-    x, y, z, density)."""
+    x, y, z, density); tables of a general model (3x3 coupling matrices) a
+    TRI context (sixteen strains Gamma^{mu nu}, index 4 mu + nu, FP64)."""
 
     def __init__(self, tables: LatticeTables, mesh, precision: str = "fp64", stream=None):
         self.lib = _lib.load()
@@ -51,8 +53,8 @@ class Context:
         self.mesh = np.ascontiguousarray(mesh, dtype=np.float64)
         self.nf = len(self.mesh)
         self.ns = tables.n_pairs
-        self.symmetry = "xyz" if tables.coupling.ndim == 2 else "su2"
-        self.nc = 4 if self.symmetry == "xyz" else 2
+        self.symmetry = {1: "su2", 2: "xyz", 3: "tri"}[tables.coupling.ndim]
+        self.nc = {"su2": 2, "xyz": 4, "tri": 16}[self.symmetry]
         lat, keep = _lattice_struct(tables)
         msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
         prec = {"fp64": _lib.FP64, "fp32": _lib.FP32}[precision]
@@ -63,6 +65,11 @@ class Context:
         if self.symmetry == "xyz":
             c3 = np.ascontiguousarray(np.asarray(tables.coupling, dtype=np.float64).T)     # [3][ns]
             _lib.check(self.lib.pffrg_create_xyz(ctypes.byref(lat), ctypes.c_void_p(c3.ctypes.data),
+                                                 ctypes.byref(msh), prec, ctypes.c_void_p(stream.cuda_stream),
+                                                 ctypes.byref(h)))
+        elif self.symmetry == "tri":
+            c9 = np.ascontiguousarray(tables.coupling, dtype=np.float64)                   # [ns][3][3]
+            _lib.check(self.lib.pffrg_create_tri(ctypes.byref(lat), ctypes.c_void_p(c9.ctypes.data),
                                                  ctypes.byref(msh), prec, ctypes.c_void_p(stream.cuda_stream),
                                                  ctypes.byref(h)))
         else:
@@ -96,7 +103,8 @@ class Context:
 
     def split(self, x: torch.Tensor):
         """Views (sig[nf], strain 0, strain 1, ...), each strain [n_su, nf, ns]:
-        SU(2) (sig, Gs, Gd), XYZ (sig, Gx, Gy, Gz, Gd)."""
+        SU(2) (sig, Gs, Gd), XYZ (sig, Gx, Gy, Gz, Gd), TRI (sig, G^{00},
+        G^{01}, ..., G^{33})."""
         nf, v = self.nf, self.vsize
         return (x[:nf],) + tuple(x[nf + c * v:nf + (c + 1) * v].view(self.n_su, nf, self.ns)
                                  for c in range(self.nc))
@@ -253,7 +261,8 @@ class Context:
     # ------------------------------------------------------- observables --
     def chi(self, lam: float, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """[strains, ns] per reduced pair: SU(2) chi^{zz}, chi^{00}; XYZ chi^{xx},
-        chi^{yy}, chi^{zz}, chi^{00}."""
+        chi^{yy}, chi^{zz}, chi^{00}; TRI the real parts of chi^{mu nu} at
+        4 mu + nu."""
         out = torch.empty(self.nc * self.ns, dtype=torch.float64, device="cuda") if out is None else out
         _lib.check(self.lib.pffrg_chi(self.handle, float(lam), _dptr(x), _dptr(out)))
         return out.view(self.nc, self.ns)

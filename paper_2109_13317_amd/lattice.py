@@ -9,7 +9,8 @@ Construction (Sec. 4.1):
   * reference site i_ref = basis site 0 of cell 0;
   * lattice symmetries are Euclidean isometries x -> O x + v that map the
     lattice to itself, bonds to bonds and couplings to equal couplings (for
-    XYZ models equal (Jx, Jy, Jz); spin components are not permuted); they
+    XYZ models equal (Jx, Jy, Jz), for general models equal matrices on the
+    directed bond; spin components are not permuted or rotated); they
     are found by mapping the nearest-neighbour bond vectors of one site onto
     those of another and validating the candidate on the unit cell;
   * for every basis site b one symmetry T_b with T_b(r_b) = r_ref, so any
@@ -44,7 +45,8 @@ class LatticeTables:
     rpa_ka: np.ndarray          # int32 [n_terms]
     rpa_kb: np.ndarray          # int32 [n_terms]
     rpa_cnt: np.ndarray         # int32 [n_terms]
-    coupling: np.ndarray        # float64 [n_pairs], J of the bond (i_ref, j_p); XYZ: [n_pairs, 3]
+    coupling: np.ndarray        # float64 [n_pairs], J of the bond (i_ref, j_p); XYZ: [n_pairs, 3];
+                                # general: [n_pairs, 3, 3], M of S_ref . M . S_j
     n_basis: int
     n_sites_total: int
     site_pair: np.ndarray       # int32 [n_basis, n_sites_total]
@@ -72,15 +74,27 @@ class _Lattice:
             self.bonds.add((t, f, (-d0, -d1, -d2)))
             self.nbrs[f].append((d, t))
             self.nbrs[t].append(((-d0, -d1, -d2), f))
-        # couplings per bond: a number (Heisenberg) or (Jx, Jy, Jz) (XYZ)
-        self.vec = any(np.ndim(v) == 1 for v in params.values())
-        self.zero = np.zeros(3) if self.vec else 0.0
+        # couplings per directed bond: a number (Heisenberg), (Jx, Jy, Jz)
+        # (XYZ) or a 3x3 matrix M of the term S_from . M . S_to (general
+        # models; there numbers and triples become J 1 and diag(Jx, Jy, Jz),
+        # and the reversed bond carries M^T)
+        dims = {np.ndim(v) for v in params.values()}
+        self.mat = 2 in dims
+        self.vec = not self.mat and 1 in dims
+        self.zero = np.zeros((3, 3)) if self.mat else (np.zeros(3) if self.vec else 0.0)
         self.J = {}
         for (pname, f, t, d0, d1, d2) in interactions:
-            val = np.asarray(params.get(pname, self.zero), dtype=np.float64) if self.vec \
-                else float(params.get(pname, 0.0))
-            for key in ((f, t, (d0, d1, d2)), (t, f, (-d0, -d1, -d2))):
-                self.J[key] = self.J.get(key, self.zero) + val
+            if self.mat:
+                val = np.asarray(params.get(pname, self.zero), dtype=np.float64)
+                if val.ndim < 2:
+                    val = np.diag(np.broadcast_to(val, (3,)).astype(np.float64))
+                rev = val.T
+            elif self.vec:
+                val = rev = np.asarray(params.get(pname, self.zero), dtype=np.float64)
+            else:
+                val = rev = float(params.get(pname, 0.0))
+            for key, v in (((f, t, (d0, d1, d2)), val), ((t, f, (-d0, -d1, -d2)), rev)):
+                self.J[key] = self.J.get(key, self.zero) + v
 
     def pos(self, cell, b):
         return np.asarray(cell, dtype=np.float64) @ self.A + self.basis[b]
@@ -324,10 +338,15 @@ def describe(model, L: int) -> LatticeDescription:
         return out
 
     bonds = sorted(links([(1.0,) + tuple(bd) for bd in model.cell.bonds]))
-    # a coupling is a number (Heisenberg) or (Jx, Jy, Jz) (XYZ)
-    coup = links([(np.asarray(model.params.get(p, lat.zero), dtype=np.float64) if lat.vec
-                   else float(model.params.get(p, 0.0)), f, t, d0, d1, d2)
-                  for (p, f, t, d0, d1, d2) in model.interactions])
+    # a coupling is a number (Heisenberg), (Jx, Jy, Jz) (XYZ) or a 3x3 matrix
+    def value(p):
+        if lat.mat:
+            v = np.asarray(model.params.get(p, lat.zero), dtype=np.float64)
+            return v if v.ndim == 2 else np.diag(np.broadcast_to(v, (3,)).astype(np.float64))
+        if lat.vec:
+            return np.asarray(model.params.get(p, lat.zero), dtype=np.float64)
+        return float(model.params.get(p, 0.0))
+    coup = links([(value(p), f, t, d0, d1, d2) for (p, f, t, d0, d1, d2) in model.interactions])
     return LatticeDescription(
         positions=np.array([lat.pos(*s) for s in sites]),
         parametrized=np.array([s in reps for s in sites]),

@@ -22,7 +22,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "UnitCell", "Model", "UNIT_CELLS", "unit_cell", "model", "model_xyz",
+    "UnitCell", "Model", "UNIT_CELLS", "unit_cell", "model", "model_xyz", "model_kitaev_gamma", "model_dm",
     "log_mesh", "exponential_schedule", "geometric_schedule",
     "Workload", "workload", "WORKLOAD_NAMES", "batch_scan_points",
     "random_state", "state_layout",
@@ -191,6 +191,44 @@ def model_heisenberg_kitaev(J: float = 1.0, K: float = 0.0) -> Model:
     return Model("honeycomb-heisenberg-kitaev", cell, inter, params)
 
 
+def model_kitaev_gamma(J: float = 0.0, K: float = -1.0, G: float = 0.5) -> Model:
+    """Heisenberg-Kitaev-Gamma model on the honeycomb lattice (Sec. 2): on a
+    bond of direction g (x, y, z as in model_heisenberg_kitaev), with (a, b)
+    the other two axes, J S_i . S_j + K S_i^g S_j^g + G (S_i^a S_j^b +
+    S_i^b S_j^a): a symmetric 3x3 coupling per bond direction, a general (TRI)
+    model."""
+    cell = UNIT_CELLS["honeycomb"]
+    names = ("mx", "my", "mz")
+    inter = tuple((n,) + bond for n, bond in zip(names, cell.bonds))
+    params = {}
+    for g, n in enumerate(names):
+        a, b = (g + 1) % 3, (g + 2) % 3
+        m = J * np.eye(3)
+        m[g, g] += K
+        m[a, b] += G
+        m[b, a] += G
+        params[n] = m
+    return Model("honeycomb-kitaev-gamma", cell, inter, params)
+
+
+def model_dm(lattice: str, J: float = 1.0, D=(0.0, 0.0, 0.3), G=None) -> Model:
+    """Nearest-neighbour model on ``lattice`` with S_i . M . S_j per listed
+    bond (from -> to), M = J 1 + [D]_x + G: a Dzyaloshinskii-Moriya term
+    D . (S_i x S_j) (M^{ab} = eps_{abc} D_c) and an optional symmetric
+    off-diagonal 3x3 part G (Sec. 2, Sec. 5.3: the bond's orientation is the
+    listed one)."""
+    base = model(lattice)
+    m = J * np.eye(3)
+    m[0, 1] += D[2]; m[1, 0] -= D[2]
+    m[1, 2] += D[0]; m[2, 1] -= D[0]
+    m[2, 0] += D[1]; m[0, 2] -= D[1]
+    if G is not None:
+        m = m + np.asarray(G, dtype=np.float64)
+    params = {k: np.zeros((3, 3)) for k in base.params}
+    params["j1"] = m
+    return Model(f"{lattice}-dm", base.cell, base.interactions, params)
+
+
 def model_compass(Jx: float = 1.0, Jy: float = 1.0) -> Model:
     """Compass model on the square lattice: Jx S^x S^x on bonds along a0 and
     Jy S^y S^y on bonds along a1 (an XYZ model with bond-dependent couplings)."""
@@ -297,18 +335,22 @@ def state_layout(n_freq: int, n_pairs: int) -> dict:
 def random_state(n_freq: int, n_pairs: int, seed: int, scale: float = 0.3, strains: int = 2) -> np.ndarray:
     """A seeded, symmetry-consistent random flow state in the layout above
     (strains = 2: sigma | Gs | Gd; strains = 4, the XYZ layout:
-    sigma | Gx | Gy | Gz | Gd).
+    sigma | Gx | Gy | Gz | Gd; strains = 16, the general layout
+    sigma | G^{00} | G^{01} | ... | G^{33}).
 
-    Im Sigma is non-positive on positive frequencies; the density vertex (the
-    last strain) vanishes on the s = u diagonal, which the s<->u exchange
-    relation forces.
+    Im Sigma is non-positive on positive frequencies; the components whose
+    second index is the density index (the last strain of the SU(2) and XYZ
+    layouts, G^{mu 0} of the general one) vanish on the s = u diagonal, which
+    the s<->u exchange relation forces.
     """
     lay = state_layout(n_freq, n_pairs)
     rng = np.random.default_rng(seed)
     x = np.empty(n_freq + strains * lay["vertex"], dtype=np.float64)
     x[:n_freq] = -np.abs(rng.normal(0.0, scale, n_freq))
     x[n_freq:] = rng.normal(0.0, scale, strains * lay["vertex"])
-    gd = x[n_freq + (strains - 1) * lay["vertex"]:].reshape(lay["n_su"], n_freq, n_pairs)
-    for a in range(n_freq):
-        gd[a * (a + 1) // 2 + a] = 0.0
+    odd = [strains - 1] if strains in (2, 4) else [q for q in range(strains) if q % 4 == 0]
+    for q in odd:
+        gd = x[n_freq + q * lay["vertex"]:n_freq + (q + 1) * lay["vertex"]].reshape(lay["n_su"], n_freq, n_pairs)
+        for a in range(n_freq):
+            gd[a * (a + 1) // 2 + a] = 0.0
     return x
