@@ -181,6 +181,30 @@ def xyz_vertex_flops(mesh: np.ndarray, lam: float, ns: int, n_terms: int) -> flo
     return tot
 
 
+def tri_vertex_flops(mesh: np.ndarray, lam: float, ns: int, n_terms: int) -> dict:
+    """Algorithmic FP64 flops of one general (TRI, sixteen-component) vertex
+    right-hand side at cutoff lam, per channel.  Per triple and evaluation
+    point:
+      s and u: 768 flops per pair (two interpolated vertices, 16 components x
+      4 corners FMA = 128 flops each, and the channel product, 256 FMA);
+      t: 1280 flops per pair (the two vertices and the two vertex corrections,
+      256 FMA each), 256 flops for the two on-site vertices, and the lattice
+      sum term by term: 64 FMA (sum_k Gamma_a^{mu k} Gamma_b^{k nu}) per
+      tabulated term."""
+    nc = node_counts(mesh, lam)
+    nf = len(mesh)
+    out = {"s": 0.0, "u": 0.0, "t": 0.0}
+    for a in range(nf):
+        for c in range(a + 1):
+            for t in range(nf):
+                out["s"] += 768.0 * ns * nc[0, a]
+                out["u"] += 768.0 * ns * nc[2, c]
+                nt = nc[1, t]
+                out["t"] += (1280.0 * ns + 256.0 + 128.0 * n_terms) * nt
+    out["all"] = out["s"] + out["u"] + out["t"]
+    return out
+
+
 def gather_instructions(mesh: np.ndarray, lam: float, ns: int) -> float:
     """Wave-level 16-byte vertex gathers of one FP64 vertex right-hand side
     (counting only): lanes cover G = 64 // ns evaluation points of one triple
@@ -483,28 +507,91 @@ def xyz_leg(reps=10):
     # channel): Heisenberg-Kitaev honeycomb, range 4 (31 pairs)
     hk = W.model_heisenberg_kitaev(1.0, -2.0)
     tab = build_tables(hk, 4)
-    ctx = Context(tab, mesh)
-    x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=7, scale=0.2, strains=4)).cuda()
-    out = ctx.new_state()
-    ctx.rhs(0.5, x, out)
-    ctx.set_profiling(True, kernels=("vertex",))
-    for _ in range(reps):
+    hk_res = {"workload": "Heisenberg-Kitaev honeycomb J = 1, K = -2, range 4 (31 pairs: no lattice symmetry maps "
+                          "one bond direction onto another), 32 log freqs 1e-3..100, RHS at Lambda = 0.5 on a seeded "
+                          "random state"}
+    for prec in ("fp64", "fp32"):
+        ctx = Context(tab, mesh, precision=prec)
+        x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=7, scale=0.2, strains=4)).cuda()
+        out = ctx.new_state()
         ctx.rhs(0.5, x, out)
-    ms, n = ctx.profile_read("vertex")
-    ctx.set_profiling(False)
-    fl = xyz_vertex_flops(mesh, 0.5, ctx.ns, tab.n_terms)
-    E = ctx.nc * ctx.ns * ctx.nf * ctx.nf * (ctx.nf + 1) // 2
-    res["heisenberg_kitaev_range4"] = {
-        "workload": "Heisenberg-Kitaev honeycomb J = 1, K = -2, range 4 (31 pairs: no lattice symmetry maps one "
-                    "bond direction onto another), 32 log freqs 1e-3..100, RHS at Lambda = 0.5 on a seeded random state",
-        "vertex_rhs_ms": ms / n, "vertex_elements": E, "elements_per_s": E / (ms / n * 1e-3), "flops": fl,
-        "tflops": fl / (ms / n * 1e-3) / 1e12, "frac_of_fp64_peak": fl / (ms / n * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS}
-    ctx.close()
-    log(f"XYZ Heisenberg-Kitaev range 4 ({tab.n_pairs} pairs): vertex RHS {ms / n:.3f} ms "
-        f"({res['heisenberg_kitaev_range4']['tflops']:.2f} TFLOP/s)")
+        ctx.set_profiling(True, kernels=("vertex",))
+        for _ in range(reps):
+            ctx.rhs(0.5, x, out)
+        ms, n = ctx.profile_read("vertex")
+        ctx.set_profiling(False)
+        fl = xyz_vertex_flops(mesh, 0.5, ctx.ns, tab.n_terms)
+        E = ctx.nc * ctx.ns * ctx.nf * ctx.nf * (ctx.nf + 1) // 2
+        r = {"vertex_rhs_ms": ms / n, "vertex_elements": E, "elements_per_s": E / (ms / n * 1e-3), "flops": fl,
+             "tflops": fl / (ms / n * 1e-3) / 1e12}
+        if prec == "fp64":
+            r["frac_of_fp64_peak"] = r["tflops"] / PEAK_FP64_VECTOR_TFLOPS
+            hk_res.update(r)
+        else:
+            hk_res["fp32"] = r
+        ctx.close()
+    hk_res["fp32_speedup"] = hk_res["vertex_rhs_ms"] / hk_res["fp32"]["vertex_rhs_ms"]
+    res["heisenberg_kitaev_range4"] = hk_res
+    log(f"XYZ Heisenberg-Kitaev range 4 ({tab.n_pairs} pairs): vertex RHS {hk_res['vertex_rhs_ms']:.3f} ms "
+        f"({hk_res['tflops']:.2f} TFLOP/s), FP32 {hk_res['fp32']['vertex_rhs_ms']:.3f} ms "
+        f"({hk_res['fp32_speedup']:.2f}x)")
     log(f"XYZ: vertex RHS {res['xyz']['vertex_rhs_ms']:.3f} ms ({res['xyz']['tflops']:.2f} TFLOP/s), SU(2) "
         f"{res['su2']['vertex_rhs_ms']:.3f} ms; flows {res['xyz']['flow_seconds']:.3f} / "
         f"{res['su2']['flow_seconds']:.3f} s")
+    return res
+
+
+def tri_leg(reps=5):
+    """General (TRI) flow (Sec. 2 general couplings, all sixteen vertex
+    components): Kitaev-Gamma honeycomb (J = 0.2, K = -1, G = 0.5), range 4
+    (31 pairs), 32 log frequencies 1e-3..100: one right-hand side at
+    Lambda = 0.5 on a seeded random state (HIP events around the vertex
+    launches), next to the XYZ (Heisenberg-Kitaev, the same bonds and pairs)
+    and SU(2) contexts of the same lattice and mesh, and a 20-step RK4 flow
+    from Lambda = 100."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    mesh = W.log_mesh(1e-3, 100.0, 32)
+    lam = 0.5
+    res = {"workload": "Kitaev-Gamma honeycomb J = 0.2, K = -1, G = 0.5, range 4 (31 pairs), 32 log freqs "
+                       "1e-3..100, RHS at Lambda = 0.5 on a seeded random state"}
+    models = (("tri", W.model_kitaev_gamma(0.2, -1.0, 0.5), 16),
+              ("xyz", W.model_heisenberg_kitaev(0.2, -1.0), 4),
+              ("su2", W.model("honeycomb", j1=0.2), 2))
+    for name, model, strains in models:
+        tab = build_tables(model, 4)
+        ctx = Context(tab, mesh)
+        x = torch.from_numpy(W.random_state(ctx.nf, ctx.ns, seed=7, scale=0.2, strains=strains)).cuda()
+        out = ctx.new_state()
+        ctx.rhs(lam, x, out)
+        ctx.set_profiling(True, kernels=("vertex",))
+        for _ in range(reps):
+            ctx.rhs(lam, x, out)
+        ms, n = ctx.profile_read("vertex")
+        ctx.set_profiling(False)
+        E = ctx.nc * ctx.ns * ctx.nf * ctx.nf * (ctx.nf + 1) // 2
+        r = {"pairs": ctx.ns, "vertex_rhs_ms": ms / n, "vertex_elements": E, "elements_per_s": E / (ms / n * 1e-3)}
+        if name == "tri":
+            fl = tri_vertex_flops(mesh, lam, ctx.ns, tab.n_terms)
+            r.update({"flops": fl["all"], "flops_by_channel": {k: fl[k] for k in ("s", "u", "t")},
+                      "tflops": fl["all"] / (ms / n * 1e-3) / 1e12,
+                      "frac_of_fp64_peak": fl["all"] / (ms / n * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS,
+                      "n_terms": tab.n_terms})
+            xf = ctx.init_state()
+            sched = W.geometric_schedule(100.0, 100.0 * 0.9 ** 20, 20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.flow(xf, schedule=sched, scheme="rk4")
+            torch.cuda.synchronize()
+            r["rk4_20_steps_seconds"] = time.perf_counter() - t0
+        res[name] = r
+        ctx.close()
+    res["tri_over_xyz_rhs_time"] = res["tri"]["vertex_rhs_ms"] / res["xyz"]["vertex_rhs_ms"]
+    res["tri_over_su2_rhs_time"] = res["tri"]["vertex_rhs_ms"] / res["su2"]["vertex_rhs_ms"]
+    log(f"TRI Kitaev-Gamma range 4 ({res['tri']['pairs']} pairs): vertex RHS {res['tri']['vertex_rhs_ms']:.3f} ms "
+        f"({res['tri']['tflops']:.2f} TFLOP/s, {res['tri']['frac_of_fp64_peak']:.3f} of FP64 peak); XYZ "
+        f"{res['xyz']['vertex_rhs_ms']:.3f} ms, SU(2) {res['su2']['vertex_rhs_ms']:.3f} ms")
     return res
 
 
@@ -962,6 +1049,8 @@ def main():
         out["adjoint"] = adjoint_leg()
         log("XYZ")
         out["xyz"] = xyz_leg()
+        log("TRI")
+        out["tri"] = tri_leg()
         log("scaling shape")
         out["scaling_shape"] = scaling_leg()
     out["paper_context"] = {
