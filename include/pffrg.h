@@ -138,6 +138,22 @@ pffrg_status pffrg_create(const pffrg_lattice *lat, const pffrg_mesh *mesh,
 pffrg_status pffrg_create_xyz(const pffrg_lattice *lat, const double *coupling3, const pffrg_mesh *mesh,
                               pffrg_precision prec, void *stream, pffrg_ctx **out);
 
+/* Spin transformations of a TRI context's pair tables (Sec. 4.1: lattice
+ * symmetries joined with a global permutation of the spin components).  A
+ * rotation W is a signed permutation matrix with det W = +1 (the sign that
+ * makes a permutation a rotation of the spin axes), given by its rows: row a
+ * holds sign(v) in column |v| - 1, v = rot[3 r + a] in {+-1, +-2, +-3}.  A pair
+ * reached through a rotation holds W Gamma W^T on its spin indices (the
+ * density index untouched).  All arrays are host pointers, copied. */
+typedef struct {
+    int n_rot;              /* rotations, 1..24; rotation 0 must be the identity */
+    const int *rot;         /* [n_rot][3] rows as above */
+    const int *swap_rot;    /* [n_pairs]: Gamma_{j_p i_ref} = W Gamma_{swap[p]} W^T */
+    const int *rpa_rot_a;   /* [n_terms] (rpa_off order): Gamma_{i_ref k} = W Gamma_{ka} W^T */
+    const int *rpa_rot_b;   /* [n_terms]: Gamma_{k j_p} = W Gamma_{kb} W^T */
+    const int *site_rot;    /* [n_basis][n_sites_total]: rotation of each site's pair (site_pair) */
+} pffrg_spin_rot;
+
 /* A TRI context: the general time-reversal invariant model (Sec. 2:
  * H = sum J_ij^{mu nu} S_i^mu S_j^nu with real 3x3 matrices; Sec. 3: all
  * sixteen vertex components Gamma^{mu nu}, Eq. 16, with the symmetries of
@@ -154,11 +170,16 @@ pffrg_status pffrg_create_xyz(const pffrg_lattice *lat, const double *coupling3,
  * average of the sums of Eq. 23 (it keeps Sigma imaginary).  pffrg_chi returns
  * [16][Ns], the real parts of chi^{mu nu} at 4 mu + nu (Eq. 30); pffrg_chi_k
  * sums chi^{xx} + chi^{yy} + chi^{zz} (Eq. 31); pffrg_chi_sites spreads all
- * sixteen.  Up to 64 pairs, FP64 only (PFFRG_FP32: PFFRG_EUNSUPPORTED); the
- * reverse-mode calls give PFFRG_EUNSUPPORTED on a TRI context.  NULL
- * coupling9 or a non-finite coupling: PFFRG_EINVAL. */
-pffrg_status pffrg_create_tri(const pffrg_lattice *lat, const double *coupling9, const pffrg_mesh *mesh,
-                              pffrg_precision prec, void *stream, pffrg_ctx **out);
+ * sixteen.  srot (may be NULL: pure lattice symmetries) carries the spin
+ * rotations of tables reduced by joint lattice and spin transformations
+ * (Sec. 4.1); the kernels then apply them on every exchanged pair, lattice-sum
+ * factor and chi site.  Up to 64 pairs, FP64 only (PFFRG_FP32:
+ * PFFRG_EUNSUPPORTED); the reverse-mode calls give PFFRG_EUNSUPPORTED on a TRI
+ * context.  NULL coupling9, a non-finite coupling, or a rotation table that is
+ * not as above (ids out of range, rotation 0 not the identity, a row that is
+ * not a signed unit vector, det W != +1): PFFRG_EINVAL. */
+pffrg_status pffrg_create_tri(const pffrg_lattice *lat, const double *coupling9, const pffrg_spin_rot *srot,
+                              const pffrg_mesh *mesh, pffrg_precision prec, void *stream, pffrg_ctx **out);
 pffrg_status pffrg_destroy(pffrg_ctx *ctx);
 pffrg_status pffrg_set_stream(pffrg_ctx *ctx, void *stream);
 

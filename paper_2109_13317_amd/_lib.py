@@ -32,6 +32,11 @@ class Mesh(ctypes.Structure):
     _fields_ = [("n_freq", I), ("omega", P)]
 
 
+class SpinRot(ctypes.Structure):
+    _fields_ = [("n_rot", I), ("rot", P), ("swap_rot", P), ("rpa_rot_a", P), ("rpa_rot_b", P),
+                ("site_rot", P)]
+
+
 class FlowOpts(ctypes.Structure):
     _fields_ = [("scheme", I), ("n_lambda", I), ("lambdas", P), ("lam_start", D),
                 ("lam_stop", D), ("rtol", D), ("atol", D), ("h0", D), ("hmin", D),
@@ -45,7 +50,7 @@ OBSERVER = ctypes.CFUNCTYPE(ctypes.c_int, D, P, P, P)
 SIGNATURES = {
     "pffrg_create": [ctypes.POINTER(Lattice), ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
     "pffrg_create_xyz": [ctypes.POINTER(Lattice), P, ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
-    "pffrg_create_tri": [ctypes.POINTER(Lattice), P, ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
+    "pffrg_create_tri": [ctypes.POINTER(Lattice), P, P, ctypes.POINTER(Mesh), I, P, ctypes.POINTER(P)],
     "pffrg_destroy": [P],
     "pffrg_set_stream": [P, P],
     "pffrg_set_vertex_mode": [P, I],

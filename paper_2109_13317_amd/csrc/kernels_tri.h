@@ -140,6 +140,60 @@ __host__ __device__ constexpr int tri_chi_x(int m, int qp) {
     return e == 0 ? 2 : (e == 2 ? -2 : 0);
 }
 
+// ------------------------------------------------------ spin rotations -
+
+// Lattice symmetries combined with a global spin transformation W (Sec. 4.1;
+// W a signed permutation with det +1): Gamma_{i1 i2} = W Gamma_q W^T on the
+// spin indices, so component m = 4 mu + nu of the mapped pair is
+// s(mu) s(nu) Gamma_q^{pi(mu) pi(nu)}.  A rotation is tabulated as 16 words
+// rot16[m] = (4 pi(mu) + pi(nu)) | (sign < 0) << 4.
+__device__ __forceinline__ double tri_rot_get(const double* __restrict__ v, int word) {
+    const double x = v[word & 15];
+    return (word & 16) ? -x : x;
+}
+
+// The pre-rotated copy of the exchanged pairs: element (su, t, p) of the
+// second half of gv is W Gamma W^T of element (su, t, swap[p]) of the first
+// half, W = rotation swap_rot[p] (one thread per element).
+static __global__ void k_tri_pack_swap(long n, int ns, const int* __restrict__ swap, const int* __restrict__ swap_rot,
+                                       const int* __restrict__ rot16, double* __restrict__ gv) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int p = (int)(i % ns);
+        const double* src = gv + 16 * (i - p + swap[p]);
+        const int* rw = rot16 + 16 * swap_rot[p];
+        double* dst = gv + 16 * (n + i);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) dst[m] = tri_rot_get(src, rw[m]);
+    }
+}
+
+// chi of every (basis site, site) in the observable layout with the site's
+// rotation: out[m * nbs + k] = (W chi_q W^T)^m, NaN past the range.
+static __global__ void k_tri_chi_sites(int ns, int nbs, const int* __restrict__ site_pair,
+                                       const int* __restrict__ site_rot, const int* __restrict__ rot16,
+                                       const double* __restrict__ chi, double* __restrict__ out) {
+    const long n = 16L * nbs;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int m = (int)(i / nbs), k = (int)(i % nbs);
+        const int sp = site_pair[k];
+        if (sp < 0) {
+            out[i] = __builtin_nan("");
+            continue;
+        }
+        const int word = rot16[16 * site_rot[k] + m];
+        const double x = chi[(word & 15) * ns + sp];
+        out[i] = (word & 16) ? -x : x;
+    }
+}
+
+// Terms of the lattice sum with rotations: word ra | rb << 8 per term.
+struct TriRotLds {
+    int n_terms, n_rot;
+    __host__ __device__ size_t bytes() const {
+        return n_rot > 1 ? (((size_t)(n_terms + 16 * n_rot) * sizeof(int)) + 31) & ~(size_t)31 : 0;
+    }
+};
+
 // ------------------------------------------------------------- plans -
 
 // Flags of a TRI plan on top of make_plan's: bit 1 = the xi xi sign (an odd
@@ -162,17 +216,23 @@ __device__ __forceinline__ void tri_finish(int flags, const double (&c)[16], dou
 }
 
 // Sixteen components of pair p from the strain-major state g (strain q at
-// g + q * vsz) through a TRI plan (element offsets).
+// g + q * vsz) through a TRI plan (element offsets).  swap_words: the
+// rotation words of the exchanged pair (spin permutations; NULL: none), read
+// as permuted strain addresses.
 __device__ __forceinline__ void eval_tri_state(const Plan& P, const double* __restrict__ g, long vsz,
-                                               const int* __restrict__ swap, int p, double (&v)[16]) {
-    const int qp = (P.swp & 1) ? swap[p] : p;
+                                               const int* __restrict__ swap, int p, double (&v)[16],
+                                               const int* __restrict__ swap_words = nullptr) {
+    const bool sw = P.swp & 1;
+    const int qp = sw ? swap[p] : p;
     double c[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
+        const int word = (sw && swap_words) ? swap_words[m] : m;
+        const double* gs = g + (word & 15) * vsz;
         double a = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a = fma(m % 4 == 0 ? P.wd[i] : P.ws[i], g[m * vsz + P.off[i] + qp], a);
-        c[m] = a;
+        for (int i = 0; i < 4; ++i) a = fma(m % 4 == 0 ? P.wd[i] : P.ws[i], gs[P.off[i] + qp], a);
+        c[m] = (word & 16) ? -a : a;
     }
     tri_finish(P.swp, c, v);
 }
@@ -318,7 +378,7 @@ struct TriSuLds {
 template <int CH>
 static __global__ void __launch_bounds__(kWave * kTriWaves)
 k_tri_su(FlowArgs A, const double* __restrict__ gv, const int* __restrict__ uo_a, const int* __restrict__ uo_c,
-         int n_triples, double* __restrict__ dx) {
+         int n_triples, int swap_copy, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, false);
@@ -335,10 +395,11 @@ k_tri_su(FlowArgs A, const double* __restrict__ gv, const int* __restrict__ uo_a
     const int ic = CH == 0 ? A.su_c[qq] : uo_c[qq];
     const Triple T = make_triple(A.w, nf, ia, it, ic);
     const long vsz = (long)n_triples * ns;
-    const __amdgpu_buffer_rsrc_t rv = tri_rsrc(gv, vsz);
+    const __amdgpu_buffer_rsrc_t rv = tri_rsrc(gv, swap_copy ? 2 * vsz : vsz);
     const int G = kWave / ns, g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(kTriElemBytes * p, kTriElemBytes * sh.swap[p]);
+    // the exchanged pair: swap[p], or with spin rotations its pre-rotated copy
+    const int2 pp = make_int2(kTriElemBytes * p, kTriElemBytes * (swap_copy ? (int)vsz + p : sh.swap[p]));
     const int iv = CH == 0 ? ia : ic;
     const int cnt = A.tab_n[CH * nf + iv];
     const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
@@ -409,14 +470,25 @@ struct TriTLds {
 // over every G-th tabulated term (ka, kb, count) of pair p and add
 // count (-2) sum_k Gamma_a^{mu k} Gamma_b^{k nu} for each node.
 static __global__ void __launch_bounds__(kWave * kTriWaves)
-k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy, const int* __restrict__ rpa_rot,
+        const int* __restrict__ rot16, int n_rot, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, true);
     A.w = sh.w;
     const TriTLds L{ns};
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    unsigned char* base = lds_raw + SharedLds{nf, ns, A.n_terms}.bytes(true) + wid * L.bytes();
+    // terms' rotations and the rotation tables (spin permutations only)
+    const size_t rb0 = SharedLds{nf, ns, A.n_terms}.bytes(true);
+    const TriRotLds RL{A.n_terms, n_rot};
+    int* trot = reinterpret_cast<int*>(lds_raw + rb0);            // [n_terms]
+    int* r16 = trot + A.n_terms;                                  // [n_rot][16]
+    if (n_rot > 1) {
+        for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) trot[i] = rpa_rot[i];
+        for (int i = threadIdx.x; i < 16 * n_rot; i += blockDim.x) r16[i] = rot16[i];
+        __syncthreads();
+    }
+    unsigned char* base = lds_raw + rb0 + RL.bytes() + wid * L.bytes();
     Plan* plan = reinterpret_cast<Plan*>(base);                                      // [2][kTChunk]
     double* ons = reinterpret_cast<double*>(base + L.plans());                       // [2][16][kTChunk]
     double* wts = reinterpret_cast<double*>(base + L.plans() + L.ons());             // [kTChunk]
@@ -430,10 +502,11 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, double* __rest
     const Triple T = make_triple(A.w, nf, A.su_a[su], it, A.su_c[su]);
     const double t = T.t;
     const long vsz = (long)n_triples * ns;
-    const __amdgpu_buffer_rsrc_t rv = tri_rsrc(gv, vsz);
+    const __amdgpu_buffer_rsrc_t rv = tri_rsrc(gv, swap_copy ? 2 * vsz : vsz);
     const int G = kWave / ns, g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(kTriElemBytes * p, kTriElemBytes * sh.swap[p]);
+    const int2 pp = make_int2(kTriElemBytes * p, kTriElemBytes * (swap_copy ? (int)vsz + p : sh.swap[p]));
+    const int2 p0 = make_int2(0, kTriElemBytes * (swap_copy ? (int)vsz : sh.swap[0]));
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
@@ -459,7 +532,7 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, double* __rest
                     if (role == 0) wts[j] = tg[k0 + j];
                 } else {
                     double v[16];
-                    eval_tri(P, rv, make_int2(0, kTriElemBytes * sh.swap[0]), v);
+                    eval_tri(P, rv, p0, v);
 #pragma unroll
                     for (int m = 0; m < 16; ++m) ons[((role - 2) * 16 + m) * kTChunk + j] = v[m];
                 }
@@ -495,12 +568,26 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, double* __rest
                     const int tq = sh.terms[qq];
                     const int kab = tq & 0xffff, ka = kab / ns, kb = kab % ns;
                     const double cntq = (double)(tq >> 16);
+                    const int rw = n_rot > 1 ? trot[qq] : 0;
+                    const int* ra = r16 + 16 * (rw & 0xff);
+                    const int* rb = r16 + 16 * (rw >> 8);
                     for (int kk = 0; kk < sc; ++kk) {
                         double x[16], y[16];
+                        const double* sa = va + (kk * ns + ka) * 16;
+                        const double* sb = vb + (kk * ns + kb) * 16;
+                        if (rw == 0) {
 #pragma unroll
-                        for (int m = 0; m < 16; ++m) {
-                            x[m] = cntq * va[(kk * ns + ka) * 16 + m];
-                            y[m] = vb[(kk * ns + kb) * 16 + m];
+                            for (int m = 0; m < 16; ++m) {
+                                x[m] = cntq * sa[m];
+                                y[m] = sb[m];
+                            }
+                        } else {
+                            // W_a Gamma_ka W_a^T and W_b Gamma_kb W_b^T (Sec. 4.1)
+#pragma unroll
+                            for (int m = 0; m < 16; ++m) {
+                                x[m] = cntq * tri_rot_get(sa, ra[m]);
+                                y[m] = tri_rot_get(sb, rb[m]);
+                            }
                         }
                         tri_mul<kTriRpa>(x, y, acc);
                     }
@@ -519,7 +606,8 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, double* __rest
 static __global__ void __launch_bounds__(kChiThreads)
 k_tri_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restrict__ swap,
                 const double* __restrict__ x, const double* __restrict__ cw, const double* __restrict__ cq,
-                const double* __restrict__ cg2, const int* __restrict__ cn, double* __restrict__ part) {
+                const double* __restrict__ cg2, const int* __restrict__ cn, const int* __restrict__ swap_rot,
+                const int* __restrict__ rot16, double* __restrict__ part) {
     __shared__ double rr[16][kChiThreads];
     const int p = blockIdx.x, sl = blockIdx.y, tid = threadIdx.x;
     const int n = *cn;
@@ -527,6 +615,9 @@ k_tri_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restr
     const double* g = x + nf;
     const int nn = n * n;
     const int e0 = (int)((long)nn * sl / kChiSlices), e1 = (int)((long)nn * (sl + 1) / kChiSlices);
+    // the exchanged pairs' rotations (spin permutations only)
+    const int* wp = rot16 ? rot16 + 16 * swap_rot[p] : nullptr;
+    const int* w0 = rot16 ? rot16 + 16 * swap_rot[0] : nullptr;
     double az[16];
 #pragma unroll
     for (int m = 0; m < 16; ++m) az[m] = 0.0;
@@ -537,12 +628,12 @@ k_tri_chi_pairs(const double* __restrict__ w, int nf, int ns, const int* __restr
         Plan P;
         make_plan_tri(w, nf, ns, w1 + w2, 0.0, w1 - w2, 1, 0, P, nullptr);
         double v[16], tz[16];
-        eval_tri_state(P, g, vsz, swap, p, v);
+        eval_tri_state(P, g, vsz, swap, p, v, wp);
 #pragma unroll
         for (int m = 0; m < 16; ++m) tz[m] = tri_ie(m) ? 0.0 : 4.0 * v[m];
         if (p == 0) {
             make_plan_tri(w, nf, ns, w1 + w2, w2 - w1, 0.0, 2, 0, P, nullptr);
-            eval_tri_state(P, g, vsz, swap, 0, v);
+            eval_tri_state(P, g, vsz, swap, 0, v, w0);
 #pragma unroll
             for (int m = 0; m < 16; ++m)
 #pragma unroll

@@ -38,6 +38,8 @@ struct pffrg_ctx {
     int nc = 2;                     // vertex strains: 2 (SU(2)), 4 (XYZ) or 16 (TRI)
     double* coupling3 = nullptr;    // XYZ: [3][ns] couplings Jx, Jy, Jz
     double* coupling9 = nullptr;    // TRI: [ns][3][3] coupling matrices
+    int n_rot = 0;                  // TRI spin rotations (0: none; then no swap copy)
+    int *rot16 = nullptr, *rpa_rot = nullptr, *swap_rot = nullptr, *site_rot = nullptr;
     long vsz = 0, size = 0;
     pffrg_precision prec = PFFRG_FP64;
     hipStream_t stream = nullptr;
@@ -395,7 +397,9 @@ pffrg_status tri_sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* ds
 }
 
 size_t tri_lds_su(int nf, int ns, int nterms) { return SharedLds{nf, ns, nterms}.bytes(false) + kTriWaves * TriSuLds::bytes(); }
-size_t tri_lds_t(int nf, int ns, int nterms) { return SharedLds{nf, ns, nterms}.bytes(true) + kTriWaves * TriTLds{ns}.bytes(); }
+size_t tri_lds_t(int nf, int ns, int nterms, int n_rot) {
+    return SharedLds{nf, ns, nterms}.bytes(true) + TriRotLds{nterms, n_rot}.bytes() + kTriWaves * TriTLds{ns}.bytes();
+}
 
 pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     FlowArgs A = c->args();
@@ -407,6 +411,12 @@ pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     double* gv = static_cast<double*>(c->gv);
     hipLaunchKernelGGL(k_tri_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf, gv);
     TRY(launch_check("k_tri_pack"));
+    const int swap_copy = c->n_rot > 0;
+    if (swap_copy) {
+        hipLaunchKernelGGL(k_tri_pack_swap, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, c->ns,
+                           (const int*)c->swap, (const int*)c->swap_rot, (const int*)c->rot16, gv);
+        TRY(launch_check("k_tri_pack_swap"));
+    }
     const int T = c->nsu * c->nf;
     const int blocks = (T + kTriWaves - 1) / kTriWaves;
     const int per = (blocks + 7) / 8;
@@ -414,12 +424,12 @@ pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     prof_mark(c, PFFRG_K_VERTEX, false);
     const size_t lds_su = tri_lds_su(c->nf, c->ns, c->n_terms);
     hipLaunchKernelGGL(k_tri_su<0>, grid, block, lds_su, c->stream, A, (const double*)gv, (const int*)c->uo_a,
-                       (const int*)c->uo_c, T, dx);
+                       (const int*)c->uo_c, T, swap_copy, dx);
     hipLaunchKernelGGL(k_tri_su<2>, grid, block, lds_su, c->stream, A, (const double*)gv, (const int*)c->uo_a,
-                       (const int*)c->uo_c, T, dx);
+                       (const int*)c->uo_c, T, swap_copy, dx);
     TRY(launch_check("k_tri_su"));
-    hipLaunchKernelGGL(k_tri_t, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms), c->stream, A, (const double*)gv,
-                       T, dx);
+    hipLaunchKernelGGL(k_tri_t, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
+                       (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot, dx);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_tri_t");
 }
@@ -719,8 +729,51 @@ namespace {
 // pffrg_create_xyz (coupling3 = [3][ns] couplings Jx, Jy, Jz) and
 // pffrg_create_tri (coupling9 = [ns][3][3] coupling matrices); lat->coupling
 // is read for SU(2) only.
+// The 16-component form of spin rotation r (rows as in pffrg_spin_rot):
+// word m = 4 mu + nu -> (4 pi(mu) + pi(nu)) | (s(mu) s(nu) < 0) << 4.
+void rot16_of(const int* rows, int* out) {
+    int pi[4] = {0, 0, 0, 0}, sg[4] = {1, 1, 1, 1};
+    for (int a = 0; a < 3; ++a) {
+        pi[a + 1] = std::abs(rows[a]);
+        sg[a + 1] = rows[a] < 0 ? -1 : 1;
+    }
+    for (int m = 0; m < 16; ++m) out[m] = (4 * pi[m / 4] + pi[m % 4]) | ((sg[m / 4] * sg[m % 4] < 0) << 4);
+}
+
+pffrg_status check_spin_rot(const pffrg_spin_rot* r, const pffrg_lattice* lat) {
+    if (r->n_rot < 1 || r->n_rot > 24 || !r->rot || !r->swap_rot || !r->site_rot ||
+        (lat->rpa_off[lat->n_pairs] > 0 && (!r->rpa_rot_a || !r->rpa_rot_b)))
+        return fail(PFFRG_EINVAL, "spin rotations: bad table");
+    for (int i = 0; i < r->n_rot; ++i) {
+        const int* w = r->rot + 3 * i;
+        bool seen[3] = {false, false, false};
+        int m[3][3] = {};
+        for (int a = 0; a < 3; ++a) {
+            const int v = std::abs(w[a]);
+            if (v < 1 || v > 3 || seen[v - 1]) return fail(PFFRG_EINVAL, "spin rotations: a row is not a signed unit vector");
+            seen[v - 1] = true;
+            m[a][v - 1] = w[a] < 0 ? -1 : 1;
+        }
+        const int det = m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                        m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+        if (det != 1) return fail(PFFRG_EINVAL, "spin rotations: det W must be +1");
+        if (i == 0 && !(w[0] == 1 && w[1] == 2 && w[2] == 3)) return fail(PFFRG_EINVAL, "spin rotation 0 must be the identity");
+    }
+    auto in_range = [&](const int* a, long n) {
+        for (long i = 0; i < n; ++i)
+            if (a[i] < 0 || a[i] >= r->n_rot) return false;
+        return true;
+    };
+    const long nt = lat->rpa_off[lat->n_pairs];
+    if (!in_range(r->swap_rot, lat->n_pairs) || !in_range(r->site_rot, (long)lat->n_basis * lat->n_sites_total) ||
+        (nt > 0 && (!in_range(r->rpa_rot_a, nt) || !in_range(r->rpa_rot_b, nt))))
+        return fail(PFFRG_EINVAL, "spin rotations: id out of range");
+    return PFFRG_OK;
+}
+
 pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, const double* coupling9,
-                        const pffrg_mesh* mesh, pffrg_precision prec, void* stream, pffrg_ctx** out) {
+                        const pffrg_spin_rot* srot, const pffrg_mesh* mesh, pffrg_precision prec, void* stream,
+                        pffrg_ctx** out) {
     if (!out) return fail(PFFRG_EINVAL, "out is null");
     *out = nullptr;
     if (!lat_in) return fail(PFFRG_EINVAL, "null lattice");
@@ -740,6 +793,7 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
     if (tri) {
         for (int i = 0; i < 9 * lat->n_pairs; ++i)
             if (!std::isfinite(coupling9[i])) return fail(PFFRG_EINVAL, "couplings must be finite");
+        if (srot) TRY(check_spin_rot(srot, lat));
     }
     const int nf = mesh->n_freq, ns = lat->n_pairs;
     const int nterms = lat->rpa_off[ns];
@@ -783,6 +837,16 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         }
         if (xyz) TRY(upload(c, &c->coupling3, coupling3, (size_t)3 * ns));
         else if (tri) TRY(upload(c, &c->coupling9, coupling9, (size_t)9 * ns));
+        if (tri && srot) {
+            c->n_rot = srot->n_rot;
+            std::vector<int> r16(16 * (size_t)c->n_rot), rr(nterms);
+            for (int i = 0; i < c->n_rot; ++i) rot16_of(srot->rot + 3 * i, r16.data() + 16 * i);
+            for (int q = 0; q < nterms; ++q) rr[q] = srot->rpa_rot_a[q] | (srot->rpa_rot_b[q] << 8);
+            TRY(upload(c, &c->rot16, r16.data(), r16.size()));
+            if (nterms > 0) TRY(upload(c, &c->rpa_rot, rr.data(), rr.size()));
+            TRY(upload(c, &c->swap_rot, srot->swap_rot, (size_t)ns));
+            TRY(upload(c, &c->site_rot, srot->site_rot, (size_t)lat->n_basis * lat->n_sites_total));
+        }
         else TRY(upload(c, &c->coupling, lat->coupling, (size_t)ns));
         {
             // the same terms grouped by (ka, kb): entry = output pair | count << 16
@@ -830,8 +894,9 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         TRY(dev_alloc(c, &c->tab_g, (size_t)3 * nf * c->nq));
         TRY(dev_alloc(c, &c->dsig, (size_t)nf));
         {
-            double2* g2 = nullptr;      // large enough for either precision (XYZ: 32 bytes per element, TRI 128)
-            TRY(dev_alloc(c, &g2, (size_t)(c->nc / 2) * c->vsz));
+            double2* g2 = nullptr;      // large enough for either precision (XYZ: 32 bytes per element, TRI 128;
+                                        // TRI with spin rotations twice that: the pre-rotated exchanged pairs)
+            TRY(dev_alloc(c, &g2, (size_t)(c->nc / 2) * c->vsz * (c->n_rot > 0 ? 2 : 1)));
             c->gv = g2;
         }
         for (int j = 0; j < kNumK; ++j) TRY(dev_alloc(c, &c->k[j], (size_t)c->size));
@@ -860,7 +925,7 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         HIP_TRY(hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
         if (!tri && t_lds_bytes(nf, ns, nterms, prec) > 64 * 1024)
             return fail(PFFRG_EUNSUPPORTED, "vertex kernel LDS budget exceeded");
-        if (tri && (tri_lds_su(nf, ns, nterms) > 64 * 1024 || tri_lds_t(nf, ns, nterms) > 64 * 1024))
+        if (tri && (tri_lds_su(nf, ns, nterms) > 64 * 1024 || tri_lds_t(nf, ns, nterms, c->n_rot) > 64 * 1024))
             return fail(PFFRG_EUNSUPPORTED, "TRI vertex kernel LDS budget exceeded");
         if (xyz && (SharedLds{nf, ns, nterms}.bytes(true) + kWavesPerBlock * XyzWaveLds<double>::bytes() > 64 * 1024 ||
                     SharedLds{nf, ns, nterms}.bytes(true) + XyzT4Lds<double>::bytes() > 64 * 1024))
@@ -889,7 +954,7 @@ extern "C" {
 
 pffrg_status pffrg_create(const pffrg_lattice* lat, const pffrg_mesh* mesh, pffrg_precision prec, void* stream,
                           pffrg_ctx** out) {
-    return create_ctx(lat, nullptr, nullptr, mesh, prec, stream, out);
+    return create_ctx(lat, nullptr, nullptr, nullptr, mesh, prec, stream, out);
 }
 
 pffrg_status pffrg_create_xyz(const pffrg_lattice* lat, const double* coupling3, const pffrg_mesh* mesh,
@@ -898,16 +963,16 @@ pffrg_status pffrg_create_xyz(const pffrg_lattice* lat, const double* coupling3,
         if (out) *out = nullptr;
         return fail(PFFRG_EINVAL, "null XYZ couplings");
     }
-    return create_ctx(lat, coupling3, nullptr, mesh, prec, stream, out);
+    return create_ctx(lat, coupling3, nullptr, nullptr, mesh, prec, stream, out);
 }
 
-pffrg_status pffrg_create_tri(const pffrg_lattice* lat, const double* coupling9, const pffrg_mesh* mesh,
-                              pffrg_precision prec, void* stream, pffrg_ctx** out) {
+pffrg_status pffrg_create_tri(const pffrg_lattice* lat, const double* coupling9, const pffrg_spin_rot* srot,
+                              const pffrg_mesh* mesh, pffrg_precision prec, void* stream, pffrg_ctx** out) {
     if (!coupling9) {
         if (out) *out = nullptr;
         return fail(PFFRG_EINVAL, "null TRI couplings");
     }
-    return create_ctx(lat, nullptr, coupling9, mesh, prec, stream, out);
+    return create_ctx(lat, nullptr, coupling9, srot, mesh, prec, stream, out);
 }
 
 pffrg_status pffrg_destroy(pffrg_ctx* c) {
@@ -1003,7 +1068,8 @@ pffrg_status pffrg_chi(pffrg_ctx* c, double lambda, const double* x, double* chi
     if (c->nc == 16) {
         hipLaunchKernelGGL(k_tri_chi_pairs, dim3(c->ns, kChiSlices), dim3(kChiThreads), 0, c->stream,
                            (const double*)c->w, c->nf, c->ns, (const int*)c->swap, x, (const double*)c->cw,
-                           (const double*)c->cq, (const double*)c->cg2, (const int*)c->cn, c->chi_part);
+                           (const double*)c->cq, (const double*)c->cg2, (const int*)c->cn,
+                           (const int*)c->swap_rot, (const int*)c->rot16, c->chi_part);
         TRY(launch_check("k_tri_chi_pairs"));
         hipLaunchKernelGGL(k_tri_chi_final, dim3(1), dim3(64), 0, c->stream, c->ns, (const double*)c->cq,
                            (const double*)c->cg2, (const int*)c->cn, (const double*)c->chi_part, chi);
@@ -1036,6 +1102,11 @@ pffrg_status pffrg_chi_sites(pffrg_ctx* c, const double* chi, double* out) {
     TRY(check_ctx(c));
     if (!chi || !out) return fail(PFFRG_EINVAL, "null correlations");
     const int nbs = c->nb * c->n_sites_total;
+    if (c->nc == 16 && c->n_rot > 0) {
+        hipLaunchKernelGGL(k_tri_chi_sites, dim3(grid_for(16L * nbs, 256)), dim3(256), 0, c->stream, c->ns, nbs,
+                           (const int*)c->site_pair, (const int*)c->site_rot, (const int*)c->rot16, chi, out);
+        return launch_check("k_tri_chi_sites");
+    }
     hipLaunchKernelGGL(k_chi_sites, dim3(grid_for((long)c->nc * nbs, 256)), dim3(256), 0, c->stream, c->nc, c->ns,
                        nbs, (const int*)c->site_pair, chi, out);
     return launch_check("k_chi_sites");

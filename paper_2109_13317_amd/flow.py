@@ -39,6 +39,22 @@ def _lattice_struct(t: LatticeTables):
     return lat, keep
 
 
+def _spin_rot_struct(t: LatticeTables):
+    """(pffrg_spin_rot or None, arrays it points into) for tables reduced with
+    spin permutations: each rotation as its rows, row a holding sign(v) in
+    column |v| - 1."""
+    if t.rot is None:
+        return None, []
+    rows = np.zeros((len(t.rot), 3), dtype=np.int32)
+    for r, W in enumerate(np.asarray(t.rot)):
+        for a in range(3):
+            col = int(np.argmax(np.abs(W[a])))
+            rows[r, a] = int(np.sign(W[a, col])) * (col + 1)
+    keep = [np.ascontiguousarray(a, dtype=np.int32) for a in (rows, t.swap_rot, t.rpa_rot_a, t.rpa_rot_b, t.site_rot)]
+    ptr = [ctypes.c_void_p(a.ctypes.data) for a in keep]
+    return _lib.SpinRot(len(t.rot), *ptr), keep
+
+
 class Context:
     """A ``pffrg_ctx``: one lattice model on one frequency mesh.  Tables of a
     Heisenberg model give an SU(2) context (two strains, spin and density);
@@ -54,6 +70,8 @@ class Context:
         self.nf = len(self.mesh)
         self.ns = tables.n_pairs
         self.symmetry = {1: "su2", 2: "xyz", 3: "tri"}[tables.coupling.ndim]
+        if tables.rot is not None and self.symmetry != "tri":
+            raise ValueError("tables with spin rotations need a general (TRI) model")
         self.nc = {"su2": 2, "xyz": 4, "tri": 16}[self.symmetry]
         lat, keep = _lattice_struct(tables)
         msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
@@ -69,7 +87,9 @@ class Context:
                                                  ctypes.byref(h)))
         elif self.symmetry == "tri":
             c9 = np.ascontiguousarray(tables.coupling, dtype=np.float64)                   # [ns][3][3]
+            srot, keep_rot = _spin_rot_struct(tables)
             _lib.check(self.lib.pffrg_create_tri(ctypes.byref(lat), ctypes.c_void_p(c9.ctypes.data),
+                                                 ctypes.byref(srot) if srot is not None else None,
                                                  ctypes.byref(msh), prec, ctypes.c_void_p(stream.cuda_stream),
                                                  ctypes.byref(h)))
         else:

@@ -22,6 +22,15 @@ Construction (Sec. 4.1):
     within range of both ends contributes Gamma_{i_ref k} Gamma_{k j_p}; k maps
     to pair ka and (k, j_p) maps, via T_k, to pair kb.  Equal (ka, kb) are
     merged with a multiplicity.
+
+With ``spin_permutations=True`` (general models, Sec. 4.1) a symmetry is a
+lattice isometry together with a global spin transformation W, a signed
+permutation of (x, y, z) with det W = +1 (a permutation with the signs that
+make it a rotation: the flow equations are covariant under rotations of the
+spin axes, not under reflections); it must map every directed bond's matrix
+M to W^T M W.  The vertex of the mapped pair then equals W^T Gamma W (the
+density index untouched), so every pair exchange, lattice-sum factor and
+chi site carries a rotation: Gamma_{i1 i2} = W Gamma_{i_ref j_q} W^T.
 """
 
 from __future__ import annotations
@@ -54,6 +63,13 @@ class LatticeTables:
     basis_pos: np.ndarray       # float64 [n_basis, 3]
     pair_rep: np.ndarray        # int32 [n_pairs, 4]: (cell0, cell1, cell2, basis)
     stabiliser_order: int
+    # spin rotations (only with spin_permutations): rot[0] is the identity;
+    # Gamma_{i1 i2} = W Gamma_q W^T with W = rot[id]
+    rot: np.ndarray | None = None          # int32 [n_rot, 3, 3] signed permutation matrices
+    swap_rot: np.ndarray | None = None     # int32 [n_pairs]: Gamma_{j_p i_ref} = W Gamma_{swap[p]} W^T
+    rpa_rot_a: np.ndarray | None = None    # int32 [n_terms]: Gamma_{i_ref k} = W Gamma_{ka} W^T
+    rpa_rot_b: np.ndarray | None = None    # int32 [n_terms]: Gamma_{k j_p} = W Gamma_{kb} W^T
+    site_rot: np.ndarray | None = None     # int32 [n_basis, n_sites_total]: rotation of site_pair
 
     @property
     def n_terms(self) -> int:
@@ -137,10 +153,12 @@ class _Lattice:
 
 
 class _Iso:
-    """x -> O x + v."""
+    """x -> O x + v, with the spin transformation R (3x3, identity unless
+    spin permutations are searched)."""
 
-    def __init__(self, O, v):
+    def __init__(self, O, v, R=None):
         self.O, self.v = O, v
+        self.R = np.eye(3) if R is None else R
 
     def apply(self, lat, site):
         c, b = site
@@ -162,8 +180,23 @@ def _frame(vecs):
     raise ValueError("bond star does not span two dimensions")
 
 
-def _symmetries_onto(lat, b_from, b_to):
-    """All lattice symmetries g with g(r_{b_from}) = r_{b_to} (both in cell 0)."""
+def _proper_signed_permutations():
+    """The 24 signed permutation matrices with determinant +1, identity first."""
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            W = np.zeros((3, 3))
+            for r in range(3):
+                W[r, perm[r]] = signs[r]
+            if round(np.linalg.det(W)) == 1:
+                out.append(W)
+    out.sort(key=lambda W: not np.array_equal(W, np.eye(3)))
+    return out
+
+
+def _symmetries_onto(lat, b_from, b_to, spins=(None,)):
+    """All lattice symmetries g with g(r_{b_from}) = r_{b_to} (both in cell 0),
+    each with every spin transformation in ``spins`` under which it is one."""
     src = [lat.pos(d, t) - lat.pos((0, 0, 0), b_from) for (d, t) in lat.nbrs[b_from]]
     dst = [lat.pos(d, t) - lat.pos((0, 0, 0), b_to) for (d, t) in lat.nbrs[b_to]]
     (i, j, k), X = _frame(src)
@@ -191,9 +224,12 @@ def _symmetries_onto(lat, b_from, b_to):
                     continue
                 if np.abs(O.T @ O - np.eye(3)).max() > EPS:
                     continue
-                g = _Iso(O, r_to - O @ r_from)
-                if _valid(lat, g) and not any(np.abs(O - h.O).max() < EPS for h in out):
-                    out.append(g)
+                for R in spins:
+                    g = _Iso(O, r_to - O @ r_from, R)
+                    if any(np.abs(O - h.O).max() < EPS and np.abs(g.R - h.R).max() < EPS for h in out):
+                        continue
+                    if _valid(lat, g):
+                        out.append(g)
     return out
 
 
@@ -218,26 +254,43 @@ def _valid(lat, g):
             return False
         if lat.bonded(s1[0], s1[1], s2[0], s2[1]) != ((b1, b2, d) in lat.bonds):
             return False
-        if np.max(np.abs(lat.coupling(s1[0], s1[1], s2[0], s2[1]) - lat.J.get((b1, b2, d), lat.zero))) > 1e-12:
+        want = lat.J.get((b1, b2, d), lat.zero)
+        if lat.mat:
+            want = g.R.T @ want @ g.R           # J_{g i, g j} = R^T J_ij R
+        if np.max(np.abs(lat.coupling(s1[0], s1[1], s2[0], s2[1]) - want)) > 1e-12:
             return False
     return True
 
 
-def build_tables(model, L: int) -> LatticeTables:
-    """Reduced pair tables for ``model`` (a ``workloads.Model``) at range L."""
+def build_tables(model, L: int, spin_permutations: bool = False) -> LatticeTables:
+    """Reduced pair tables for ``model`` (a ``workloads.Model``) at range L;
+    spin_permutations: also search joint lattice and spin transformations
+    (general models with 3x3 couplings only)."""
     lat = _Lattice(model.cell, model.interactions, model.params)
     L = int(L)
-    stab = _symmetries_onto(lat, 0, 0)
+    if spin_permutations and not lat.mat:
+        raise ValueError("spin permutations need a general model (3x3 coupling matrices)")
+    spins = _proper_signed_permutations() if spin_permutations else (None,)
+    stab = _symmetries_onto(lat, 0, 0, spins)
     to_ref = []
     for b in range(lat.nb):
-        gs = _symmetries_onto(lat, b, 0)
+        gs = _symmetries_onto(lat, b, 0, spins)
         if not gs:
             raise ValueError(f"basis site {b} is not equivalent to the reference site")
         to_ref.append(gs[0])
+    rots = [np.eye(3)]
+
+    def rot_id(W):
+        for i, V in enumerate(rots):
+            if np.abs(V - W).max() < 0.5:
+                return i
+        rots.append(np.rint(W))
+        return len(rots) - 1
 
     ball0, dist0 = lat.ball(0, L)
     in_ball = set(ball0)
     orbit_of = {}
+    xrot = {}           # Gamma_{i_ref k} = X Gamma_{rep} X^T
     reps = []
     mult = []
     for site in ball0:
@@ -245,41 +298,52 @@ def build_tables(model, L: int) -> LatticeTables:
             continue
         p = len(reps)
         reps.append(site)
-        members = {site}
+        members = {site: np.eye(3)}
         for g in stab:
             im = g.apply(lat, site)
-            members.add(im)
-        for m in members:
+            if im not in members:
+                members[im] = g.R.T      # Gamma_{ref, g r} = R^T Gamma_{ref, r} R
+        for m, X in members.items():
             if m not in in_ball:
                 raise RuntimeError("stabiliser does not preserve the truncation ball")
             orbit_of[m] = p
+            xrot[m] = X
         mult.append(len(members))
     n_pairs = len(reps)
 
-    def to_reference(site_a, site_b):
-        """Reduced pair of (site_a, site_b), or -1 if out of range."""
+    def to_reference_rot(site_a, site_b):
+        """(reduced pair, W) with Gamma_{a b} = W Gamma_pair W^T, or (-1, None) out of range."""
         (ca, ba) = site_a
         (cb, bb) = site_b
         shifted = ((cb[0] - ca[0], cb[1] - ca[1], cb[2] - ca[2]), bb)
-        im = to_ref[ba].apply(lat, shifted)
-        return orbit_of.get(im, -1)
+        g = to_ref[ba]
+        im = g.apply(lat, shifted)
+        if im not in orbit_of:
+            return -1, None
+        return orbit_of[im], g.R @ xrot[im]      # Gamma_{a b} = R Gamma_{ref, g b} R^T
 
-    swap = np.array([to_reference(r, ((0, 0, 0), 0)) for r in reps], dtype=np.int32)
+    def to_reference(site_a, site_b):
+        """Reduced pair of (site_a, site_b), or -1 if out of range."""
+        return to_reference_rot(site_a, site_b)[0]
+
+    sw = [to_reference_rot(r, ((0, 0, 0), 0)) for r in reps]
+    swap = np.array([q for q, _ in sw], dtype=np.int32)
     if (swap < 0).any():
         raise RuntimeError("pair swap left the truncation range")
+    swap_rot = np.array([rot_id(W) for _, W in sw], dtype=np.int32)
 
     off = [0]
-    ka_l, kb_l, cnt_l = [], [], []
+    ka_l, kb_l, cnt_l, ra_l, rb_l = [], [], [], [], []
     for p, rep in enumerate(reps):
         terms = {}
         for k in ball0:
-            kb = to_reference(k, rep)
+            kb, Wb = to_reference_rot(k, rep)
             if kb < 0:
                 continue
-            key = (orbit_of[k], kb)
+            key = (orbit_of[k], kb, rot_id(xrot[k]), rot_id(Wb))
             terms[key] = terms.get(key, 0) + 1
-        for (a, b), n in sorted(terms.items()):
-            ka_l.append(a); kb_l.append(b); cnt_l.append(n)
+        for (a, b, ra, rb), n in sorted(terms.items()):
+            ka_l.append(a); kb_l.append(b); cnt_l.append(n); ra_l.append(ra); rb_l.append(rb)
         off.append(len(ka_l))
 
     coupling = np.array([lat.coupling((0, 0, 0), 0, r[0], r[1]) for r in reps])
@@ -287,10 +351,14 @@ def build_tables(model, L: int) -> LatticeTables:
     balls = [lat.ball(b, L)[0] for b in range(lat.nb)]
     ntot = max(len(bl) for bl in balls)
     site_pair = np.full((lat.nb, ntot), -1, dtype=np.int32)
+    site_rot = np.zeros((lat.nb, ntot), dtype=np.int32)
     site_pos = np.zeros((lat.nb, ntot, 3))
     for b, bl in enumerate(balls):
         for k, site in enumerate(bl):
-            site_pair[b, k] = to_reference(((0, 0, 0), b), site)
+            q, W = to_reference_rot(((0, 0, 0), b), site)
+            site_pair[b, k] = q
+            if q >= 0:
+                site_rot[b, k] = rot_id(W)
             site_pos[b, k] = lat.pos(*site)
     if (site_pair[site_pair != -1] < 0).any():
         raise RuntimeError("site map incomplete")
@@ -302,7 +370,10 @@ def build_tables(model, L: int) -> LatticeTables:
         coupling=coupling, n_basis=lat.nb, n_sites_total=ntot, site_pair=site_pair,
         site_pos=site_pos, basis_pos=lat.basis.copy(),
         pair_rep=np.array([[r[0][0], r[0][1], r[0][2], r[1]] for r in reps], dtype=np.int32),
-        stabiliser_order=len(stab))
+        stabiliser_order=len(stab),
+        **(dict(rot=np.array(rots, dtype=np.int32), swap_rot=swap_rot,
+                rpa_rot_a=np.array(ra_l, dtype=np.int32), rpa_rot_b=np.array(rb_l, dtype=np.int32),
+                site_rot=site_rot) if spin_permutations else {}))
 
 
 @dataclass

@@ -161,3 +161,93 @@ def compare_chi_sites(orc, tables, lay: np.ndarray, ref: np.ndarray, chi_red: np
             n += 1
     assert n == int(np.sum(orc.lat.nsites))
     return err / max(float(np.abs(ref).max()), 1e-300)
+
+
+# ------------------------------------------------------------------------
+# Tables reduced with spin permutations (Sec. 4.1): every site maps to a
+# reduced pair q and a spin rotation W with Gamma_site = W Gamma_q W^T on the
+# spin indices (the general sixteen-component layout only).
+
+def rot_map(orc, tables):
+    """(pmap, rmap): reduced pair and rotation id of every oracle site."""
+    lat = orc.lat
+    pmap = np.full((lat.nb, lat.ns), -1, dtype=np.int64)
+    rmap = np.zeros((lat.nb, lat.ns), dtype=np.int64)
+    for b in range(lat.nb):
+        prod = {tuple(np.round(tables.site_pos[b, k], 6)): (int(tables.site_pair[b, k]), int(tables.site_rot[b, k]))
+                for k in range(tables.n_sites_total) if tables.site_pair[b, k] >= 0}
+        for k in range(lat.nsites[b]):
+            pmap[b, k], rmap[b, k] = prod[tuple(np.round(lat.site_pos[b, k], 6))]
+    return pmap, rmap
+
+
+def rotate16(R, G):
+    """W Gamma W^T on the spin indices of [..., 16] components (index 4 mu + nu)."""
+    R4 = np.eye(4)
+    R4[1:, 1:] = R
+    G = np.asarray(G)
+    M = G.reshape(G.shape[:-1] + (4, 4))
+    return np.einsum("ma,...ab,nb->...mn", R4, M, R4).reshape(G.shape)
+
+
+def _red16(x, nf, ns):
+    """Reduced sixteen-strain state as (sig, [n_su, nf, ns, 16])."""
+    v = _reduced_views(np.asarray(x), nf, ns, 16)
+    return v[0], np.stack(v[1:], axis=-1)
+
+
+def _orc16(orc, x):
+    parts = orc.split(np.asarray(x))
+    return parts[0], np.stack(parts[1:], axis=-1)      # [nb, n_su, nf, ns, 16]
+
+
+def restrict_state_rot(orc, tables, x_unred: np.ndarray) -> np.ndarray:
+    """Reduced-layout state from an unreduced one: each pair's values from an
+    oracle site that maps to it with the identity rotation."""
+    pmap, rmap = rot_map(orc, tables)
+    nf, ns = orc.nf, tables.n_pairs
+    sig, G = _orc16(orc, x_unred)
+    out = np.zeros(nf + 16 * (nf * (nf + 1) // 2) * nf * ns)
+    dst = _reduced_views(out, nf, ns, 16)
+    dst[0][:] = sig
+    done = set()
+    for b in range(orc.lat.nb):
+        for k in range(orc.lat.nsites[b]):
+            p = int(pmap[b, k])
+            if rmap[b, k] == 0 and p not in done:
+                for c in range(16):
+                    dst[1 + c][:, :, p] = G[b, :, :, k, c]
+                done.add(p)
+    assert len(done) == ns
+    return out
+
+
+def compare_vertex_rot(orc, tables, ref: np.ndarray, red: np.ndarray) -> float:
+    """max |oracle - W library W^T| / max |oracle| over sigma and every element."""
+    pmap, rmap = rot_map(orc, tables)
+    nf, ns = orc.nf, tables.n_pairs
+    sig_r, G_r = _red16(red, nf, ns)
+    sig_o, G_o = _orc16(orc, ref)
+    err = np.abs(sig_o - sig_r).max()
+    scale = max(np.abs(sig_o).max(), np.abs(G_o).max(), 1e-300)
+    rots = np.asarray(tables.rot, dtype=float)
+    for b in range(orc.lat.nb):
+        for k in range(orc.lat.nsites[b]):
+            want = rotate16(rots[rmap[b, k]], G_r[:, :, pmap[b, k]])
+            err = max(err, np.abs(G_o[b, :, :, k] - want).max())
+    return float(err / scale)
+
+
+def compare_chi_rot(orc, tables, chi_unred: np.ndarray, chi_red: np.ndarray) -> float:
+    """chi of the sixteen components: oracle [16, nb, ns] against the library's
+    [16, n_pairs] rotated onto every site, relative to max |oracle|."""
+    pmap, rmap = rot_map(orc, tables)
+    chi_red = np.asarray(chi_red).reshape(16, -1)
+    rots = np.asarray(tables.rot, dtype=float)
+    err, scale = 0.0, 1e-300
+    for b in range(orc.lat.nb):
+        for k in range(orc.lat.nsites[b]):
+            want = rotate16(rots[rmap[b, k]], chi_red[:, pmap[b, k]])
+            err = max(err, np.abs(chi_unred[:, b, k] - want).max())
+            scale = max(scale, np.abs(chi_unred[:, b, k]).max())
+    return float(err / scale)

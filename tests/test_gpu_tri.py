@@ -12,7 +12,15 @@ wave down to one), at cutoffs below, inside and above the mesh, on a mesh
 point and at half a mesh point; the initial state; 40-step RK4 flows with chi
 every step; the Kitaev-Gamma honeycomb at range 4 with 32 frequencies (the
 benchmark size) on sampled triples; diagonal couplings against an XYZ
-context; and the refused inputs (FP32, reverse mode).
+context; and the refused inputs (FP32, reverse mode).  With pair tables
+reduced by joint lattice and spin transformations (Sec. 4.1; Kitaev-Gamma
+honeycomb 10 -> 3 and 19 -> 5 pairs with six rotations; the square lattice
+with Dzyaloshinskii-Moriya and Gamma terms at range 2, where only the
+identity remains, as a control): the right-hand side on states of an oracle flow,
+40-step RK4 flows with chi every step, chi in the observable layout and
+chi(k), every element compared with the oracle after rotating the library's
+pair values onto each site; the same flows with and without spin
+permutations agree; malformed rotation tables are refused.
 """
 
 import zlib
@@ -21,7 +29,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.parity import compare_chi_comps, compare_chi_sites, compare_triples, compare_vertex, expand_state
+from tests.parity import (compare_chi_comps, compare_chi_rot, compare_chi_sites, compare_triples, compare_vertex,
+                          compare_vertex_rot, expand_state, restrict_state_rot, rotate16, rot_map)
 
 pytestmark = pytest.mark.gpu
 
@@ -207,3 +216,126 @@ def test_tri_refused_inputs():
     with pytest.raises(_lib.PffrgError) as e:
         ctx.rhs_vjp(0.5, x, x.clone())
     assert e.value.status == _lib.EUNSUPPORTED
+
+
+# ------------------------------------------------- spin permutations -
+
+SP_CASES = {k: CASES[k] for k in ("kitaev_gamma_L2_N5", "kitaev_gamma_L3_N4", "square_dm_L2_N6")}
+
+
+def _setup_sp(name):
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    make, L, mesh = SP_CASES[name]
+    model = make()
+    tables = build_tables(model, L, spin_permutations=True)
+    ctx = Context(tables, mesh)
+    orc = oracle.Oracle(model, L, mesh)
+    return torch, tables, ctx, orc
+
+
+@pytest.mark.parametrize("name", list(SP_CASES))
+def test_tri_spin_permutation_rhs_on_flowed_state(name):
+    """Right-hand sides on the oracle's state after 12 RK4 steps from
+    Lambda = 50 (a state with the model's symmetries), restricted to the
+    reduced pairs, at cutoffs below, inside and above the mesh."""
+    torch, tables, ctx, orc = _setup_sp(name)
+    _say(f"tri spin-permutation rhs {name}: {tables.n_pairs} pairs, {len(tables.rot)} rotations")
+    xo = orc.flow(W.geometric_schedule(50.0, 0.3, 12))
+    xr = restrict_state_rot(orc, tables, xo)
+    assert compare_vertex_rot(orc, tables, xo, xr) <= 1e-13      # the state itself is symmetric
+    mesh = ctx.mesh
+    for lam in (0.5 * mesh[0], 0.37, float(mesh[len(mesh) // 2]), 1.7 * mesh[-1]):
+        d = ctx.rhs(lam, torch.from_numpy(xr).cuda()).cpu().numpy()
+        err = compare_vertex_rot(orc, tables, orc.rhs(lam, xo), d)
+        _say(f"  lam={lam}: {err:.2e}")
+        assert err <= TOL, (lam, err)
+
+
+@pytest.mark.parametrize("name", list(SP_CASES))
+def test_tri_spin_permutation_flow_with_chi(name):
+    """40 RK4 steps Lambda 50 -> 0.5 from the initial state: the state, chi of
+    the sixteen components every step (rotated onto every site), chi in the
+    observable layout and chi(k) at the end, against the oracle's flow."""
+    torch, tables, ctx, orc = _setup_sp(name)
+    sched = W.geometric_schedule(50.0, 0.5, 40)
+    x = ctx.init_state()
+    assert compare_vertex_rot(orc, tables, orc.initial_state(), x.cpu().numpy()) == 0.0
+    got = []
+    ctx.flow(x, schedule=sched, scheme="rk4",
+             observer=lambda lam, chi, ck: got.append((lam, chi.cpu().numpy().copy())) and 0)
+    ref = []
+    xo = orc.flow(sched, observer=lambda lam, xs: ref.append((lam, _oracle_chi(orc, lam, xs))))
+    err = compare_vertex_rot(orc, tables, xo, x.cpu().numpy())
+    worst = max(compare_chi_rot(orc, tables, rc, gc) for (_, gc), (_, rc) in zip(got, ref))
+    chi = ctx.chi(0.5, x)
+    lay = ctx.chi_sites(chi).cpu().numpy()
+    refc = ref[-1][1]
+    pmap, rmap = rot_map(orc, tables)
+    es = 0.0
+    for b in range(orc.lat.nb):
+        where = {tuple(np.round(orc.lat.site_pos[b, k], 6)): k for k in range(orc.lat.nsites[b])}
+        for k in range(tables.n_sites_total):
+            if tables.site_pair[b, k] < 0:
+                assert np.isnan(lay[:, b, k]).all()
+                continue
+            ko = where[tuple(np.round(tables.site_pos[b, k], 6))]
+            es = max(es, float(np.abs(lay[:, b, k] - refc[:, b, ko]).max()))
+    es /= np.abs(refc).max()
+    kp = np.random.default_rng(9).uniform(-6.0, 6.0, size=(13, 3))
+    ck = ctx.chi_k(chi.reshape(-1), torch.from_numpy(kp).cuda()).cpu().numpy()
+    ck_ref = orc.chi_k_xyz(refc[[5, 10, 15]], kp)
+    ek = np.abs(ck - ck_ref).max() / np.abs(ck_ref).max()
+    _say(f"tri spin-permutation flow {name}: state {err:.2e}, chi worst {worst:.2e}, sites {es:.2e}, chi(k) {ek:.2e}")
+    assert len(got) == len(ref) == len(sched) - 1
+    assert err <= TOL and worst <= TOL and es <= TOL and ek <= TOL
+
+
+def test_tri_flows_with_and_without_spin_permutations_agree():
+    """The Kitaev-Gamma honeycomb at range 3 flowed with 19 pairs and with 5
+    (spin permutations): chi(k) along the flow agrees."""
+    import torch
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    model = W.model_kitaev_gamma(0.2, -1.0, 0.5)
+    mesh = W.log_mesh(0.01, 20.0, 6)
+    kp = torch.from_numpy(np.random.default_rng(3).uniform(-5.0, 5.0, size=(11, 3))).cuda()
+    out = []
+    for sp in (False, True):
+        ctx = Context(build_tables(model, 3, spin_permutations=sp), mesh)
+        x = ctx.init_state()
+        got = []
+        ctx.flow(x, schedule=W.geometric_schedule(50.0, 0.3, 30), scheme="rk4", kpoints=kp,
+                 observer=lambda lam, chi, ck: got.append(ck.cpu().numpy().copy()) and 0)
+        out.append((ctx.ns, np.array(got)))
+    (n0, a), (n1, b) = out
+    err = np.abs(a - b).max() / np.abs(a).max()
+    _say(f"tri with/without spin permutations: {n0} and {n1} pairs, chi(k) {err:.2e}")
+    assert n0 == 19 and n1 == 5 and err <= 1e-12
+
+
+def test_tri_malformed_spin_rotations_refused():
+    import ctypes
+    from paper_2109_13317_amd import _lib, build_tables
+    from paper_2109_13317_amd.flow import _lattice_struct, _spin_rot_struct
+    tables = build_tables(W.model_kitaev_gamma(0.2, -1.0, 0.5), 2, spin_permutations=True)
+    mesh = W.log_mesh(0.01, 20.0, 5)
+    lib = _lib.load()
+    lat, keep = _lattice_struct(tables)
+    msh = _lib.Mesh(len(mesh), ctypes.c_void_p(mesh.ctypes.data))
+    c9 = np.ascontiguousarray(tables.coupling, dtype=np.float64)
+    for bad in ("det", "identity", "range"):
+        srot, keep_rot = _spin_rot_struct(tables)
+        rows = keep_rot[0]
+        if bad == "det":
+            rows[1] = [-1, 2, 3]                  # a reflection
+        elif bad == "identity":
+            rows[0] = [2, 3, 1]
+        else:
+            keep_rot[1][0] = len(rows)            # swap rotation id out of range
+        h = ctypes.c_void_p()
+        st = lib.pffrg_create_tri(ctypes.byref(lat), ctypes.c_void_p(c9.ctypes.data), ctypes.byref(srot),
+                                  ctypes.byref(msh), _lib.FP64, None, ctypes.byref(h))
+        assert st == _lib.EINVAL and not h.value, bad

@@ -1,0 +1,162 @@
+"""The spin-permutation part of the lattice symmetry search (Sec. 4.1: joint
+lattice transformations and global permutations of the spin components),
+checked against the oracle, which keeps every site of the truncated lattice
+and knows no symmetry.  CPU only.
+
+  pair count        the Kitaev-Gamma honeycomb at range 3 reduces to the 5
+                    parametrized sites of the 19 in range that the paper's
+                    lattice-reduction figure shows for the honeycomb lattice
+  site map          after an oracle flow, the vertex of every site in range
+                    equals W Gamma_q W^T of its reduced pair q and rotation W
+  pair exchange     Gamma_{j_p i_ref} = W Gamma_{swap[p]} W^T
+  lattice sums      sum_k Gamma_{i_ref k} Gamma_{k j_p} over every site k of
+                    the oracle equals the tabulated terms with their rotations
+"""
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+XI = np.array([1.0, -1.0, -1.0, -1.0])
+XIXI = np.outer(XI, XI)
+
+
+def _rot16(R, G):
+    """W Gamma W^T on the spin indices of a [..., 4, 4] array (density index fixed)."""
+    R4 = np.eye(4)
+    R4[1:, 1:] = R
+    return np.einsum("ma,...ab,nb->...mn", R4, G, R4)
+
+
+def _oracle_matrices(orc, x):
+    """Gamma of every (basis, site) of the oracle: [nb, n_su, nf, ns, 4, 4] (real representation)."""
+    parts = orc.split(x)
+    G = np.stack([parts[1 + q] for q in range(16)], axis=-1)
+    return G.reshape(G.shape[:-1] + (4, 4))
+
+
+def _flowed(model, L, nf=4, steps=6):
+    import oracle
+    mesh = W.log_mesh(0.05, 10.0, nf)
+    orc = oracle.Oracle(model, L, mesh)
+    x = orc.flow(W.geometric_schedule(10.0, 1.0, steps))
+    return orc, x
+
+
+def _site_index(orc, b, pos):
+    for k in range(orc.lat.nsites[b]):
+        if np.abs(orc.lat.site_pos[b, k] - pos).max() < 1e-6:
+            return k
+    raise AssertionError("site not in the oracle's list")
+
+
+MODELS = {
+    "kitaev_gamma": (lambda: W.model_kitaev_gamma(0.2, -1.0, 0.5), 2),
+    "square_dm": (lambda: W.model_dm("square", 1.0, (0.1, -0.2, 0.35), [[0, 0.2, 0], [0.2, 0, 0], [0, 0, 0]]), 2),
+}
+
+
+def test_kitaev_gamma_range3_reduces_to_five_pairs():
+    from paper_2109_13317_amd import build_tables
+    m = W.model_kitaev_gamma(0.2, -1.0, 0.5)
+    t0 = build_tables(m, 3)
+    t1 = build_tables(m, 3, spin_permutations=True)
+    assert t0.n_sites_total == 19 and t1.n_sites_total == 19
+    assert t0.n_pairs == 19 and t1.n_pairs == 5
+    assert t1.rot is not None and np.array_equal(t1.rot[0], np.eye(3))
+    for R in t1.rot:
+        assert round(np.linalg.det(R)) == 1 and np.all(np.abs(R).sum(axis=0) == 1)
+
+
+def test_spin_permutations_need_a_general_model():
+    from paper_2109_13317_amd import build_tables
+    with pytest.raises(ValueError):
+        build_tables(W.model_heisenberg_kitaev(0.2, -1.0), 2, spin_permutations=True)
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_site_map_and_exchange_match_oracle_flow(oracle_lib, name):
+    from paper_2109_13317_amd import build_tables
+    make, L = MODELS[name]
+    model = make()
+    t = build_tables(model, L, spin_permutations=True)
+    orc, x = _flowed(model, L)
+    G = _oracle_matrices(orc, x)
+    scale = np.abs(G).max()
+    rep_k = [_site_index(orc, 0, orc.lat.basis_pos[0] + t.pair_rep[p][:3] @ np.asarray(model.cell.primitives)
+                         + np.asarray(model.cell.basis)[t.pair_rep[p][3]] - np.asarray(model.cell.basis)[0])
+             for p in range(t.n_pairs)]
+    rep_G = [G[0, :, :, k] for k in rep_k]
+    worst = 0.0
+    for b in range(t.n_basis):
+        for k in range(t.n_sites_total):
+            q = t.site_pair[b, k]
+            if q < 0:
+                continue
+            ko = _site_index(orc, b, t.site_pos[b, k])
+            want = _rot16(t.rot[t.site_rot[b, k]], rep_G[q])
+            worst = max(worst, np.abs(G[b, :, :, ko] - want).max())
+    assert worst <= 1e-12 * scale, worst
+    # the exchanged pair: Gamma_{j_p i_ref} as the oracle stores it (translated to
+    # the basis site of j_p) against the tables' swap and rotation
+    cell = model.cell
+    A = np.asarray(cell.primitives, dtype=float)
+    B = np.asarray(cell.basis, dtype=float)
+    for p in range(t.n_pairs):
+        c, bj = t.pair_rep[p][:3], int(t.pair_rep[p][3])
+        ko = _site_index(orc, bj, B[0] - c @ A)                  # i_ref seen from (cell 0, bj)
+        want = _rot16(t.rot[t.swap_rot[p]], rep_G[t.swap[p]])
+        assert np.abs(G[bj, :, :, ko] - want).max() <= 1e-12 * scale, p
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_lattice_sum_terms_match_oracle(oracle_lib, name):
+    """At one mesh point, sum over every site k in range of both ends of
+    Gamma_{i_ref k} Gamma_{k j_p} (4x4 complex matrices of the basis functions,
+    multiplied over the inner index as in the t channel's RPA term) equals
+    sum over the tabulated terms of count (W_a Gamma_ka W_a^T)(W_b Gamma_kb W_b^T)."""
+    from paper_2109_13317_amd import build_tables
+    make, L = MODELS[name]
+    model = make()
+    t = build_tables(model, L, spin_permutations=True)
+    orc, x = _flowed(model, L)
+    G = _oracle_matrices(orc, x) * np.where(XIXI > 0, 1.0, 1j)
+    cell = model.cell
+    A = np.asarray(cell.primitives, dtype=float)
+    Bp = np.asarray(cell.basis, dtype=float)
+    lat = orc.lat
+    su, it = 3, 1
+    Gp = G[:, su, it]                                  # [nb, ns, 4, 4]
+
+    def gamma(ri, rj):
+        """Gamma_{ri rj} from the oracle's lists (translated to ri's basis site), 0 out of range."""
+        for b in range(lat.nb):
+            f = (ri - Bp[b]) @ np.linalg.inv(A)
+            if np.abs(f - np.rint(f)).max() < 1e-9:
+                rel = Bp[b] + (rj - ri)
+                for k in range(lat.nsites[b]):
+                    if np.abs(lat.site_pos[b, k] - rel).max() < 1e-6:
+                        return Gp[b, k]
+                return np.zeros((4, 4), dtype=complex)
+        raise AssertionError("not a lattice site")
+
+    rref = Bp[0]
+    rot = [np.real(R) for R in t.rot]
+    worst, scale = 0.0, 0.0
+    for p in range(t.n_pairs):
+        rj = rref + t.pair_rep[p][:3] @ A + Bp[t.pair_rep[p][3]] - Bp[0]
+        direct = sum(gamma(rref, lat.site_pos[0, k]) @ gamma(lat.site_pos[0, k], rj) for k in range(lat.nsites[0]))
+        tab = np.zeros((4, 4), dtype=complex)
+        for q in range(t.rpa_off[p], t.rpa_off[p + 1]):
+            ga = _rot16(rot[t.rpa_rot_a[q]], gamma(rref, rref + _rep_vec(t, t.rpa_ka[q], A, Bp)))
+            gb = _rot16(rot[t.rpa_rot_b[q]], gamma(rref, rref + _rep_vec(t, t.rpa_kb[q], A, Bp)))
+            tab = tab + t.rpa_cnt[q] * (ga @ gb)
+        worst = max(worst, np.abs(direct - tab).max())
+        scale = max(scale, np.abs(direct).max())
+    assert scale > 0 and worst <= 1e-12 * scale, (worst, scale)
+
+
+def _rep_vec(t, q, A, Bp):
+    r = t.pair_rep[q]
+    return r[:3] @ A + Bp[r[3]] - Bp[0]
