@@ -376,7 +376,7 @@ struct TriSuLds {
 // One wave per (s,t,u) triple, lanes (g, p): channel CH = 0 (s) or 2 (u);
 // the s launch writes dGamma, the u launch adds.
 template <int CH>
-static __global__ void __launch_bounds__(kWave * kTriWaves)
+static __global__ void __launch_bounds__(kWave * kTriWaves) __attribute__((amdgpu_waves_per_eu(3)))
 k_tri_su(FlowArgs A, const double* __restrict__ gv, const int* __restrict__ uo_a, const int* __restrict__ uo_c,
          int n_triples, int swap_copy, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
@@ -469,6 +469,9 @@ struct TriTLds {
 // LDS and add the two vertex corrections of pair p; then lanes (g, p) run
 // over every G-th tabulated term (ka, kb, count) of pair p and add
 // count (-2) sum_k Gamma_a^{mu k} Gamma_b^{k nu} for each node.
+// ROT: tables with spin rotations (the lattice-sum factors read through
+// them; a separate instance, so that the plain one keeps its code).
+template <bool ROT>
 static __global__ void __launch_bounds__(kWave * kTriWaves)
 k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy, const int* __restrict__ rpa_rot,
         const int* __restrict__ rot16, int n_rot, double* __restrict__ dx) {
@@ -480,10 +483,10 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     // terms' rotations and the rotation tables (spin permutations only)
     const size_t rb0 = SharedLds{nf, ns, A.n_terms}.bytes(true);
-    const TriRotLds RL{A.n_terms, n_rot};
+    const TriRotLds RL{A.n_terms, ROT ? n_rot : 1};
     int* trot = reinterpret_cast<int*>(lds_raw + rb0);            // [n_terms]
     int* r16 = trot + A.n_terms;                                  // [n_rot][16]
-    if (n_rot > 1) {
+    if (ROT) {
         for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) trot[i] = rpa_rot[i];
         for (int i = threadIdx.x; i < 16 * n_rot; i += blockDim.x) r16[i] = rot16[i];
         __syncthreads();
@@ -563,35 +566,45 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
                 tri_mul<kTriC2>(h, a, acc);                 // W (O2, B)
             }
             wave_lds_sync();
-            if (act)
+            if constexpr (!ROT) {
+              if (act) {
                 for (int qq = sh.off[p] + g; qq < sh.off[p + 1]; qq += G) {
                     const int tq = sh.terms[qq];
                     const int kab = tq & 0xffff, ka = kab / ns, kb = kab % ns;
                     const double cntq = (double)(tq >> 16);
-                    const int rw = n_rot > 1 ? trot[qq] : 0;
+                    for (int kk = 0; kk < sc; ++kk) {
+                        double x[16], y[16];
+#pragma unroll
+                        for (int m = 0; m < 16; ++m) {
+                            x[m] = cntq * va[(kk * ns + ka) * 16 + m];
+                            y[m] = vb[(kk * ns + kb) * 16 + m];
+                        }
+                        tri_mul<kTriRpa>(x, y, acc);
+                    }
+                }
+              }
+            } else if (act) {
+                // W_a Gamma_ka W_a^T and W_b Gamma_kb W_b^T (Sec. 4.1)
+                for (int qq = sh.off[p] + g; qq < sh.off[p + 1]; qq += G) {
+                    const int tq = sh.terms[qq];
+                    const int kab = tq & 0xffff, ka = kab / ns, kb = kab % ns;
+                    const double cntq = (double)(tq >> 16);
+                    const int rw = trot[qq];
                     const int* ra = r16 + 16 * (rw & 0xff);
                     const int* rb = r16 + 16 * (rw >> 8);
                     for (int kk = 0; kk < sc; ++kk) {
                         double x[16], y[16];
                         const double* sa = va + (kk * ns + ka) * 16;
                         const double* sb = vb + (kk * ns + kb) * 16;
-                        if (rw == 0) {
 #pragma unroll
-                            for (int m = 0; m < 16; ++m) {
-                                x[m] = cntq * sa[m];
-                                y[m] = sb[m];
-                            }
-                        } else {
-                            // W_a Gamma_ka W_a^T and W_b Gamma_kb W_b^T (Sec. 4.1)
-#pragma unroll
-                            for (int m = 0; m < 16; ++m) {
-                                x[m] = cntq * tri_rot_get(sa, ra[m]);
-                                y[m] = tri_rot_get(sb, rb[m]);
-                            }
+                        for (int m = 0; m < 16; ++m) {
+                            x[m] = cntq * tri_rot_get(sa, ra[m]);
+                            y[m] = tri_rot_get(sb, rb[m]);
                         }
                         tri_mul<kTriRpa>(x, y, acc);
                     }
                 }
+            }
             wave_lds_sync();
         }
     }

@@ -428,8 +428,12 @@ pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     hipLaunchKernelGGL(k_tri_su<2>, grid, block, lds_su, c->stream, A, (const double*)gv, (const int*)c->uo_a,
                        (const int*)c->uo_c, T, swap_copy, dx);
     TRY(launch_check("k_tri_su"));
-    hipLaunchKernelGGL(k_tri_t, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
-                       (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot, dx);
+    if (c->n_rot > 1)
+        hipLaunchKernelGGL(k_tri_t<true>, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
+                           (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot, dx);
+    else
+        hipLaunchKernelGGL(k_tri_t<false>, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
+                           (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot, dx);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_tri_t");
 }

@@ -14,7 +14,10 @@ search path is scanned for the named definitions.
 What this engine accepts: the ``SU2`` backend with Heisenberg interactions
 (``type="heisenberg"``), the ``XYZ`` backend with every interaction type of
 diagonal matrix M (heisenberg, xxyy, xx, yy, zz, -xx, -yy, -zz: the
-Heisenberg-Kitaev model of the paper's listing, for one), and the
+Heisenberg-Kitaev model of the paper's listing, for one), the ``TRI``
+backend with every interaction type of Sec. 5.3 (heisenberg, xxyy, gx, gy,
+gz, mu nu and -mu nu; its lattice tables use the joint lattice and spin
+transformations of Sec. 4.1, as the paper's program does), and the
 ``correlation`` measurement (direct, or deferred to a re-run from stored
 vertex states), written as a NumPy ``.npz`` file (each correlation strain
 per reduced pair and cutoff, and per basis site and site within range with
@@ -208,17 +211,44 @@ def _unit_cell(search_path, name):
 
 # Interaction types with a diagonal matrix M (Sec. 5.3): what the XYZ backend
 # takes; the off-diagonal ones (gx, gy, gz, mu nu with mu != nu) need the
-# TRI backend.
+# TRI backend (_type_matrix).
 _DIAGONAL_TYPES = {"heisenberg": (1.0, 1.0, 1.0), "xxyy": (1.0, 1.0, 0.0),
                    "xx": (1.0, 0.0, 0.0), "yy": (0.0, 1.0, 0.0), "zz": (0.0, 0.0, 1.0),
                    "-xx": (-1.0, 0.0, 0.0), "-yy": (0.0, -1.0, 0.0), "-zz": (0.0, 0.0, -1.0)}
+
+
+_AXES = {"x": 0, "y": 1, "z": 2}
+
+
+def _type_matrix(kind: str):
+    """The 3x3 matrix M of an interaction type (Sec. 5.3): heisenberg, xxyy,
+    gx, gy, gz (the symmetric off-diagonal Gamma terms), mu nu (a single 1 at
+    row mu, column nu) and -mu nu; None for an unknown type."""
+    if kind == "heisenberg":
+        return np.eye(3)
+    if kind == "xxyy":
+        return np.diag([1.0, 1.0, 0.0])
+    if len(kind) == 2 and kind[0] == "g" and kind[1] in _AXES:
+        a, b = [c for c in range(3) if c != _AXES[kind[1]]]
+        m = np.zeros((3, 3))
+        m[a, b] = m[b, a] = 1.0
+        return m
+    sign = 1.0
+    if kind.startswith("-"):
+        sign, kind = -1.0, kind[1:]
+    if len(kind) == 2 and kind[0] in _AXES and kind[1] in _AXES:
+        m = np.zeros((3, 3))
+        m[_AXES[kind[0]], _AXES[kind[1]]] = sign
+        return m
+    return None
 
 
 def _model(search_path, name, cell, params, symmetry="SU2"):
     """The model's interactions with the first site in cell 0.  SU2: every
     interaction is Heisenberg, parameters are numbers.  XYZ: every
     interaction has a diagonal matrix M; each (parameter, type) becomes a
-    coupling (Jx, Jy, Jz) = value x diag(M)."""
+    coupling (Jx, Jy, Jz) = value x diag(M).  TRI: each (parameter, type)
+    becomes the coupling matrix value x M."""
     f, node = _resource_nodes(search_path, "model", name)
     inter = []
     vec = {}
@@ -228,6 +258,8 @@ def _model(search_path, name, cell, params, symmetry="SU2"):
             raise TaskError(f"{f}: interaction type {kind!r} needs a backend other than SU2")
         if symmetry == "XYZ" and kind not in _DIAGONAL_TYPES:
             raise TaskError(f"{f}: interaction type {kind!r} couples different spin components (TRI backend)")
+        if symmetry == "TRI" and _type_matrix(kind) is None:
+            raise TaskError(f"{f}: unknown interaction type {kind!r}")
         src = [int(v) for v in it.get("from", "").split(",")]
         dst = [int(v) for v in it.get("to", "").split(",")]
         if len(src) != 4 or len(dst) != 4:
@@ -241,8 +273,12 @@ def _model(search_path, name, cell, params, symmetry="SU2"):
             key = f"{p}:{kind}"
             vec[key] = tuple(float(params[p]) * m for m in _DIAGONAL_TYPES[kind])
             p = key
+        elif symmetry == "TRI":
+            key = f"{p}:{kind}"
+            vec[key] = float(params[p]) * _type_matrix(kind)
+            p = key
         inter.append((p, src[3], dst[3], dst[0] - src[0], dst[1] - src[1], dst[2] - src[2]))
-    return ModelDef(name, cell, tuple(inter), vec if symmetry == "XYZ" else dict(params))
+    return ModelDef(name, cell, tuple(inter), vec if symmetry in ("XYZ", "TRI") else dict(params))
 
 
 def load(path: str, search_path=None) -> Task:
@@ -272,8 +308,8 @@ def load(path: str, search_path=None) -> Task:
         raise TaskError(f"{path}: cutoff values must be positive and descending")
     lat, mod = nodes["lattice"], nodes["model"]
     symmetry = mod.get("symmetry", "")
-    if symmetry not in ("SU2", "XYZ"):
-        raise TaskError(f"{path}: backend {symmetry!r} is not available (this engine runs SU2 and XYZ)")
+    if symmetry not in ("SU2", "XYZ", "TRI"):
+        raise TaskError(f"{path}: backend {symmetry!r} is not available (this engine runs SU2, XYZ and TRI)")
     params = {c.tag: evaluate(c.text) for c in mod if c.text is not None}
     cell = _unit_cell(search_path, lat.get("name"))
     model = _model(search_path, mod.get("name"), cell, params, symmetry)
@@ -324,7 +360,7 @@ def write_ldf(path: str, desc) -> None:
     for i, j in desc.bonds:
         ET.SubElement(root, "bond", **{"from": str(i), "to": str(j)})
     for i, j, v in desc.interactions:
-        m = np.diag(v) if np.ndim(v) == 1 else np.eye(3) * v      # XYZ (Jx, Jy, Jz) or Heisenberg J
+        m = np.asarray(v) if np.ndim(v) == 2 else (np.diag(v) if np.ndim(v) == 1 else np.eye(3) * v)
         val = "[" + ", ".join("[" + ",".join(repr(float(e)) for e in row) + "]" for row in m) + "]"
         ET.SubElement(root, "interaction", value=val, **{"from": str(i), "to": str(j)})
     ET.indent(root)
@@ -379,18 +415,30 @@ def sites_layout(tables, chi_pairs) -> np.ndarray:
     the paper's observable files (Sec. 5, "Output data"): for every basis
     site b of the unit cell, every site k within range of it, [...,
     n_basis, n_sites_total]; slots past a basis site's own site count hold
-    NaN."""
+    NaN.  With spin rotations (tables reduced by spin permutations) the
+    sixteen components [..., 16, n_pairs] of each site are rotated:
+    W chi W^T on the spin indices."""
     c = np.asarray(chi_pairs, dtype=np.float64)
     sp = np.asarray(tables.site_pair)
     out = np.full(c.shape[:-1] + sp.shape, np.nan)
     ok = sp >= 0
     out[..., ok] = c[..., sp[ok]]
+    if getattr(tables, "rot", None) is not None:
+        assert c.shape[-2] == 16, "rotated layouts need all sixteen components"
+        for b, k in zip(*np.nonzero(ok)):
+            R4 = np.eye(4)
+            R4[1:, 1:] = tables.rot[tables.site_rot[b, k]]
+            v = c[..., sp[b, k]].reshape(c.shape[:-2] + (4, 4))
+            out[..., b, k] = np.einsum("ma,...ab,nb->...mn", R4, v, R4).reshape(c.shape[:-1])
     return out
 
 
 def chi_names(nc: int) -> tuple:
     """Names of the correlation strains in the measurement files: SU2 chi^zz
-    and chi^00, XYZ chi^xx, chi^yy, chi^zz and chi^00."""
+    and chi^00, XYZ chi^xx, chi^yy, chi^zz and chi^00, TRI every chi^{mu nu}
+    (chi_00, chi_0x, ..., chi_zz, in the order 4 mu + nu)."""
+    if nc == 16:
+        return tuple("chi_" + "0xyz"[m // 4] + "0xyz"[m % 4] for m in range(16))
     return ("chi_zz", "chi_00") if nc == 2 else ("chi_xx", "chi_yy", "chi_zz", "chi_00")
 
 
@@ -402,15 +450,15 @@ def _write_obs(dest, rec, tables=None, cell=None) -> None:
     metadata (``basis``, ``lattice_vectors``, ``sites``: Cartesian
     positions)."""
     chis = [np.asarray(c, dtype=np.float64) for c in rec[1]]
-    nc = chis[0].shape[0] if chis else (4 if tables is not None and np.ndim(tables.coupling) == 2 else 2)
+    nc = chis[0].shape[0] if chis else ({1: 2, 2: 4, 3: 16}[np.ndim(tables.coupling)] if tables is not None else 2)
     arrays = {"lambda": np.asarray(rec[0], dtype=np.float64)}
     for m, name in enumerate(chi_names(nc)):
         arrays[name] = np.array([c[m] for c in chis]) if chis else np.zeros((0, 0))
     if tables is not None:
         nb, ns_tot = np.asarray(tables.site_pair).shape
+        lay = sites_layout(tables, np.array(chis)) if chis else None      # [cutoff, strain, nb, ns_tot]
         for m, name in enumerate(chi_names(nc)):
-            arrays[name + "_sites"] = (sites_layout(tables, arrays[name]) if chis
-                                       else np.zeros((0, nb, ns_tot)))
+            arrays[name + "_sites"] = lay[:, m] if chis else np.zeros((0, nb, ns_tot))
         arrays["basis"] = np.asarray(tables.basis_pos, dtype=np.float64)
         arrays["sites"] = np.asarray(tables.site_pos, dtype=np.float64)
         if cell is not None:
@@ -459,7 +507,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
         d = m.output or base + ".obs"
         dests.append(d if os.path.isabs(d) else os.path.join(os.path.dirname(task.path), d))
     records = [([], []) for _ in task.measurements]
-    names = chi_names(4 if task.symmetry == "XYZ" else 2)
+    names = chi_names({"SU2": 2, "XYZ": 4, "TRI": 16}[task.symmetry])
     resuming = os.path.exists(ck) and not force_restart
     if resuming:
         lam_snap = float.fromhex(checkpoint.read(ck).meta["lambda"])
@@ -470,7 +518,7 @@ def run(task: Task, *, scheme: str = "euler", precision: str = "fp64", every: fl
                     rec[0].extend(z["lambda"][keep].tolist())
                     rec[1].extend(list(np.stack([z[n][keep] for n in names], axis=1)))
     write_ldf(base + ".ldf", describe(task.model, task.lattice_range))
-    tables = build_tables(task.model, task.lattice_range)
+    tables = build_tables(task.model, task.lattice_range, spin_permutations=task.symmetry == "TRI")
     ctx = Context(tables, task.mesh, precision=precision)
     x = ctx.init_state()
     defer = [m.method == "defer" for m in task.measurements]

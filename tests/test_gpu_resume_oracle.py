@@ -146,3 +146,45 @@ def test_xyz_task_file_run_matches_oracle(tmp_path):
         worst = max(worst, compare_chi_sites(orc, tables, lay, cc, red))
     _say(f"XYZ task-file run ({tables.n_pairs} pairs): chi at {len(ref)} cutoffs, worst error vs oracle {worst:.2e}")
     assert worst <= TOL
+
+
+def test_tri_task_file_run_matches_oracle(tmp_path):
+    """A task on the TRI backend: the Kitaev-Gamma model written with
+    heisenberg, xx/yy/zz and gx/gy/gz interactions (honeycomb range 2; the
+    task's tables use spin permutations, 3 pairs), Euler steps; all sixteen
+    correlation components at every cutoff, per reduced pair (rotated onto
+    every site) and in the observable-file layout, against the oracle's
+    TRI Euler flow on the unreduced lattice."""
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd import taskfile as T
+    from tests.parity import compare_chi_rot
+    from tests.test_taskfile import _kitaev_gamma_task
+    path = _kitaev_gamma_task(tmp_path)
+    task = T.load(path)
+    T.run(task, scheme="euler")
+    got = np.load(path[:-4] + ".obs")
+    tables = build_tables(task.model, 2, spin_permutations=True)
+    orc = oracle.Oracle(task.model, 2, task.mesh)
+    assert orc.nc == 16 and tables.n_pairs == 3
+    ref = []
+    orc.flow(task.cutoffs, scheme="euler",
+             observer=lambda lam, xs: ref.append((lam, orc.chi_tri(lam, xs)[0].reshape(16, orc.lat.nb, orc.lat.ns))))
+    assert np.array_equal(got["lambda"], task.cutoffs[1:]) and len(ref) == len(task.cutoffs) - 1
+    names = T.chi_names(16)
+    worst = 0.0
+    for i, (lam, cc) in enumerate(ref):
+        red = np.stack([got[n][i] for n in names])
+        worst = max(worst, compare_chi_rot(orc, tables, cc, red))
+        lay = np.stack([got[n + "_sites"][i] for n in names])
+        scale = np.abs(cc).max()
+        for b in range(tables.n_basis):
+            where = {tuple(np.round(orc.lat.site_pos[b, k], 6)): k for k in range(orc.lat.nsites[b])}
+            for k in range(tables.n_sites_total):
+                if tables.site_pair[b, k] < 0:
+                    assert np.isnan(lay[:, b, k]).all()
+                    continue
+                ko = where[tuple(np.round(tables.site_pos[b, k], 6))]
+                worst = max(worst, float(np.abs(lay[:, b, k] - cc[:, b, ko]).max()) / scale)
+    _say(f"TRI task-file run ({tables.n_pairs} pairs): chi at {len(ref)} cutoffs, worst error vs oracle {worst:.2e}")
+    assert worst <= TOL

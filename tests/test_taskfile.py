@@ -57,6 +57,25 @@ RESOURCES = """
 <model name="hc-gamma">
   <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="gx"/>
 </model>
+<model name="hc-kitaev-gamma">
+  <interaction parameter="j" from="0,0,0,0" to="0,0,0,1" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,0" to="0,-1,0,1" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,0" to="-1,0,0,1" type="heisenberg"/>
+  <interaction parameter="k" from="0,0,0,0" to="0,0,0,1" type="xx"/>
+  <interaction parameter="k" from="0,0,0,0" to="0,-1,0,1" type="yy"/>
+  <interaction parameter="k" from="0,0,0,0" to="-1,0,0,1" type="zz"/>
+  <interaction parameter="g" from="0,0,0,0" to="0,0,0,1" type="gx"/>
+  <interaction parameter="g" from="0,0,0,0" to="0,-1,0,1" type="gy"/>
+  <interaction parameter="g" from="0,0,0,0" to="-1,0,0,1" type="gz"/>
+</model>
+<model name="sq-dm">
+  <interaction parameter="j" from="0,0,0,0" to="1,0,0,0" type="heisenberg"/>
+  <interaction parameter="j" from="0,0,0,0" to="0,1,0,0" type="heisenberg"/>
+  <interaction parameter="d" from="0,0,0,0" to="1,0,0,0" type="xy"/>
+  <interaction parameter="d" from="0,0,0,0" to="1,0,0,0" type="-yx"/>
+  <interaction parameter="d" from="0,0,0,0" to="0,1,0,0" type="xy"/>
+  <interaction parameter="d" from="0,0,0,0" to="0,1,0,0" type="-yx"/>
+</model>
 """
 
 
@@ -134,7 +153,7 @@ def test_expressions_are_arithmetic_only():
 def test_what_the_su2_engine_cannot_run_is_refused(tmp_path):
     good = _read(_sq_task(tmp_path))
     cases = [
-        (good.replace('symmetry="SU2"', 'symmetry="TRI"'), "backend"),
+        (good.replace('symmetry="SU2"', 'symmetry="SU3"'), "backend"),
         (good.replace("<jb>0.4</jb>", ""), "no value"),
         (good.replace('<lattice name="sq"', '<lattice name="nowhere"'), "unitcell"),
         (good.replace("<step>0.85</step>", "<step>1.5</step>"), "step"),
@@ -352,3 +371,76 @@ def test_xyz_lattice_description(tmp_path):
         assert g is not None
         expect = np.diag([J + (K if c == g else 0.0) for c in range(3)])
         assert np.array_equal(m, expect)
+
+
+def _kitaev_gamma_task(tmp_path, j="0.2", k="-1", g="0.5", L=2, count=5):
+    return _task(tmp_path, f"""<task><parameters>
+      <frequency discretization="exponential"><min>0.01</min><max>20</max><count>{count}</count></frequency>
+      <cutoff discretization="exponential"><min>2.0</min><max>20</max><step>0.85</step></cutoff>
+      <lattice name="hc" range="{L}"/><model name="hc-kitaev-gamma" symmetry="TRI"><j>{j}</j><k>{k}</k><g>{g}</g></model>
+    </parameters>
+    <measurements><measurement name="correlation"/></measurements></task>""", "kitaev_gamma.xml")
+
+
+def test_interaction_type_matrices():
+    """The 3x3 matrices of Sec. 5.3's interaction types."""
+    assert np.array_equal(T._type_matrix("heisenberg"), np.eye(3))
+    assert np.array_equal(T._type_matrix("xxyy"), np.diag([1.0, 1.0, 0.0]))
+    assert np.array_equal(T._type_matrix("gx"), np.array([[0, 0, 0], [0, 0, 1], [0, 1, 0.0]]))
+    assert np.array_equal(T._type_matrix("gy"), np.array([[0, 0, 1], [0, 0, 0], [1, 0, 0.0]]))
+    assert np.array_equal(T._type_matrix("gz"), np.array([[0, 1, 0], [1, 0, 0], [0, 0, 0.0]]))
+    m = np.zeros((3, 3)); m[0, 2] = 1.0
+    assert np.array_equal(T._type_matrix("xz"), m)
+    assert np.array_equal(T._type_matrix("-xz"), -m)
+    assert T._type_matrix("gw") is None and T._type_matrix("xw") is None
+
+
+def test_tri_task_kitaev_gamma_tables(tmp_path):
+    """The Kitaev-Gamma model written with heisenberg, xx/yy/zz and gx/gy/gz
+    interactions loads on the TRI backend and gives the lattice front end the
+    tables of the same couplings written as one matrix per bond, with and
+    without spin permutations (3 pairs with them at range 2)."""
+    task = T.load(_kitaev_gamma_task(tmp_path))
+    assert task.symmetry == "TRI"
+    J, K, G = 0.2, -1.0, 0.5
+    mats = {}
+    for g, name in enumerate("xyz"):
+        a, b = [c for c in range(3) if c != g]
+        m = J * np.eye(3)
+        m[g, g] += K
+        m[a, b] += G
+        m[b, a] += G
+        mats[name] = m
+    direct = W.Model("hkg", W.unit_cell("honeycomb"),
+                     (("x", 0, 1, 0, 0, 0), ("y", 0, 1, 0, -1, 0), ("z", 0, 1, -1, 0, 0)), mats)
+    for sp in (False, True):
+        a, b = build_tables(task.model, 2, spin_permutations=sp), build_tables(direct, 2, spin_permutations=sp)
+        assert a.n_pairs == b.n_pairs and a.coupling.shape == (a.n_pairs, 3, 3)
+        for f in ("swap", "mult", "rpa_off", "rpa_ka", "rpa_kb", "rpa_cnt", "site_pair", "site_pos"):
+            assert np.array_equal(getattr(a, f), getattr(b, f)), f
+        assert np.allclose(a.coupling, b.coupling, rtol=0, atol=1e-15)
+    assert build_tables(task.model, 2, spin_permutations=True).n_pairs == 3
+
+
+def test_tri_task_dm_model_and_lattice_description(tmp_path):
+    """A square-lattice model with a Dzyaloshinskii-Moriya term written as xy
+    and -yx interactions (Sec. 5.3): the couplings in the lattice description
+    are J 1 + D (e_x e_y^T - e_y e_x^T) in the orientation the model lists
+    (and its transpose backwards)."""
+    from paper_2109_13317_amd.lattice import describe
+    p = _task(tmp_path, """<task><parameters>
+      <frequency discretization="exponential"><min>0.1</min><max>10</max><count>4</count></frequency>
+      <cutoff discretization="exponential"><min>1.0</min><max>10</max><step>0.8</step></cutoff>
+      <lattice name="sq" range="2"/><model name="sq-dm" symmetry="TRI"><j>1.0</j><d>0.3</d></model>
+    </parameters></task>""", "dm.xml")
+    task = T.load(p)
+    path = str(tmp_path / "dm.ldf")
+    T.write_ldf(path, describe(task.model, 2))
+    pos, par, bonds, inter = T.read_ldf(path)
+    want = np.eye(3) + 0.3 * np.array([[0, 1, 0], [-1, 0, 0], [0, 0, 0.0]])
+    assert len(inter) == len(bonds) > 0
+    for i, j, m in inter:
+        dr = pos[j] - pos[i]
+        assert np.isclose(abs(dr[0]) + abs(dr[1]), 1.0)
+        assert np.array_equal(m, want if (dr[0] > 0.5 or dr[1] > 0.5) else want.T)
+
