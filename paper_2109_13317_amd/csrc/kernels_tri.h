@@ -14,8 +14,9 @@
 // serves once two flags are added: bit 0 of swp (exchanged sites) is also
 // the transposition, bit 1 the xi xi sign; the s <-> u signs sit in the
 // weights as for SU(2) (density weights for the stored nu = 0 components).
-// The packed vertex holds the sixteen components of an element side by side
-// (128 bytes: a corner is eight 16-byte loads).
+// The packed vertex holds, per frequency point, the sixteen components as
+// eight 16-byte chunks, chunk-major: [point][chunk][pair], so that the eight
+// loads of a corner are each one contiguous wave access over the pairs.
 //
 // Channel products.  In two-spin operator form (V = sum Gamma^{mu nu}
 // sigma^mu (x) sigma^nu, Eq. 25) the spin sums of Eq. 24 give
@@ -152,18 +153,28 @@ __device__ __forceinline__ double tri_rot_get(const double* __restrict__ v, int 
     return (word & 16) ? -x : x;
 }
 
-// The pre-rotated copy of the exchanged pairs: element (su, t, p) of the
-// second half of gv is W Gamma W^T of element (su, t, swap[p]) of the first
+// Double index of component m of element (point, pair q) in the packed
+// layout [point][chunk][pair] (chunk = two components).
+__host__ __device__ __forceinline__ long tri_packed_index(long point, int q, int m, int ns) {
+    return 2 * ((point * 8 + m / 2) * (long)ns + q) + (m & 1);
+}
+
+// The pre-rotated copy of the exchanged pairs: element (point, p) of the
+// second half of gv is W Gamma W^T of element (point, swap[p]) of the first
 // half, W = rotation swap_rot[p] (one thread per element).
 static __global__ void k_tri_pack_swap(long n, int ns, const int* __restrict__ swap, const int* __restrict__ swap_rot,
                                        const int* __restrict__ rot16, double* __restrict__ gv) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const int p = (int)(i % ns);
-        const double* src = gv + 16 * (i - p + swap[p]);
+        const long pt = i / ns;
         const int* rw = rot16 + 16 * swap_rot[p];
-        double* dst = gv + 16 * (n + i);
+        double* dst = gv + 16 * n;
 #pragma unroll
-        for (int m = 0; m < 16; ++m) dst[m] = tri_rot_get(src, rw[m]);
+        for (int m = 0; m < 16; ++m) {
+            const int word = rw[m];
+            const double x = gv[tri_packed_index(pt, swap[p], word & 15, ns)];
+            dst[tri_packed_index(pt, p, m, ns)] = (word & 16) ? -x : x;
+        }
     }
 }
 
@@ -241,16 +252,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tri_rsrc(const double* gv, lon
     return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * kTriElemBytes), 0x00020000);
 }
 
-// Plan offsets (elements) as byte offsets of the packed vertex.
+// Plan offsets (elements, point * ns) as byte offsets of the packed vertex:
+// a point's block is ns * 128 bytes.
 __device__ __forceinline__ void to_bytes_tri(Plan& P) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) P.off[i] *= kTriElemBytes;
 }
 
-// Sixteen components of the pair at byte offsets pp (pp.y the exchanged
-// pair) through a plan with byte offsets: corner by corner, eight 16-byte
+// Sixteen components of the pair at byte offsets pp (16 * pair within a
+// chunk row; pp.y the exchanged pair) through a plan with byte offsets,
+// chunk rows hstride = 16 * ns bytes apart: corner by corner, eight 16-byte
 // loads each, the corner's loads issued before its arithmetic.
-__device__ __forceinline__ void eval_tri(const Plan& P, __amdgpu_buffer_rsrc_t r, int2 pp, double (&v)[16]) {
+__device__ __forceinline__ void eval_tri(const Plan& P, __amdgpu_buffer_rsrc_t r, int2 pp, unsigned hstride,
+                                         double (&v)[16]) {
     const unsigned q = (P.swp & 1) ? pp.y : pp.x;
     double c[16];
 #pragma unroll
@@ -261,7 +275,7 @@ __device__ __forceinline__ void eval_tri(const Plan& P, __amdgpu_buffer_rsrc_t r
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             const double2 d = __builtin_bit_cast(
-                double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)((unsigned)P.off[i] + q + 16u * h), 0, 0));
+                double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)((unsigned)P.off[i] + q + hstride * h), 0, 0));
             e[2 * h] = d.x;
             e[2 * h + 1] = d.y;
         }
@@ -316,12 +330,16 @@ static __global__ void k_tri_init_state(long n, int nf, int ns, const double* __
     }
 }
 
-// The sixteen strains interleaved per element: gv[16 i + q] = strain q of element i.
-static __global__ void k_tri_pack(long n, const double* __restrict__ g, double* __restrict__ gv) {
+// The sixteen strains packed per frequency point, chunk-major: element
+// i = point * ns + pair, chunk h (components 2h, 2h + 1) at double2
+// (point * 8 + h) * ns + pair.
+static __global__ void k_tri_pack(long n, int ns, const double* __restrict__ g, double* __restrict__ gv) {
+    double2* o = reinterpret_cast<double2*>(gv);
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        double2* o = reinterpret_cast<double2*>(gv + 16 * i);
+        const long pt = i / ns;
+        const int p = (int)(i % ns);
 #pragma unroll
-        for (int h = 0; h < 8; ++h) o[h] = make_double2(g[(2 * h) * n + i], g[(2 * h + 1) * n + i]);
+        for (int h = 0; h < 8; ++h) o[(pt * 8 + h) * ns + p] = make_double2(g[(2 * h) * n + i], g[(2 * h + 1) * n + i]);
     }
 }
 
@@ -399,7 +417,9 @@ k_tri_su(FlowArgs A, const double* __restrict__ gv, const int* __restrict__ uo_a
     const int G = kWave / ns, g = lane / ns, p = lane % ns;
     const bool act = g < G;
     // the exchanged pair: swap[p], or with spin rotations its pre-rotated copy
-    const int2 pp = make_int2(kTriElemBytes * p, kTriElemBytes * (swap_copy ? (int)vsz + p : sh.swap[p]));
+    // (the second half of gv)
+    const int2 pp = make_int2(16 * p, swap_copy ? kTriElemBytes * (int)vsz + 16 * p : 16 * sh.swap[p]);
+    const unsigned hs = 16u * ns;
     const int iv = CH == 0 ? ia : ic;
     const int cnt = A.tab_n[CH * nf + iv];
     const double* tw = A.tab_w + (long)(CH * nf + iv) * nq;
@@ -429,11 +449,11 @@ k_tri_su(FlowArgs A, const double* __restrict__ gv, const int* __restrict__ uo_a
         if (act) {
             for (int k = g; k < kc; k += G) {
                 double a[16], b[16];
-                eval_tri(plan[k], rv, pp, a);
+                eval_tri(plan[k], rv, pp, hs, a);
                 const double W = wts[k];
 #pragma unroll
                 for (int m = 0; m < 16; ++m) a[m] *= W;
-                eval_tri(plan[kPlanChunk + k], rv, pp, b);
+                eval_tri(plan[kPlanChunk + k], rv, pp, hs, b);
                 if constexpr (CH == 0) tri_mul<kTriS>(a, b, acc);
                 else tri_mul<kTriU>(a, b, acc);
             }
@@ -508,8 +528,9 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
     const __amdgpu_buffer_rsrc_t rv = tri_rsrc(gv, swap_copy ? 2 * vsz : vsz);
     const int G = kWave / ns, g = lane / ns, p = lane % ns;
     const bool act = g < G;
-    const int2 pp = make_int2(kTriElemBytes * p, kTriElemBytes * (swap_copy ? (int)vsz + p : sh.swap[p]));
-    const int2 p0 = make_int2(0, kTriElemBytes * (swap_copy ? (int)vsz : sh.swap[0]));
+    const int2 pp = make_int2(16 * p, swap_copy ? kTriElemBytes * (int)vsz + 16 * p : 16 * sh.swap[p]);
+    const int2 p0 = make_int2(0, swap_copy ? kTriElemBytes * (int)vsz : 16 * sh.swap[0]);
+    const unsigned hs = 16u * ns;
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
@@ -535,7 +556,7 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
                     if (role == 0) wts[j] = tg[k0 + j];
                 } else {
                     double v[16];
-                    eval_tri(P, rv, p0, v);
+                    eval_tri(P, rv, p0, hs, v);
 #pragma unroll
                     for (int m = 0; m < 16; ++m) ons[((role - 2) * 16 + m) * kTChunk + j] = v[m];
                 }
@@ -548,7 +569,7 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
                 const int k = s0 + g;
                 const double W = wts[k];
                 double a[16], h[16];
-                eval_tri(plan[k], rv, pp, a);
+                eval_tri(plan[k], rv, pp, hs, a);
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
                     a[m] *= W;
@@ -556,7 +577,7 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
                     h[m] = ons[(0 * 16 + m) * kTChunk + k];
                 }
                 tri_mul<kTriC1>(a, h, acc);                 // W (A, O1)
-                eval_tri(plan[kTChunk + k], rv, pp, a);     // b
+                eval_tri(plan[kTChunk + k], rv, pp, hs, a);     // b
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
                     vb[(g * ns + p) * 16 + m] = a[m];

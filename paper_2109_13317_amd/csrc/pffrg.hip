@@ -409,7 +409,8 @@ pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
                           (const double*)dx);
     TRY(launch_check("k_node_tables"));
     double* gv = static_cast<double*>(c->gv);
-    hipLaunchKernelGGL(k_tri_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, x + c->nf, gv);
+    hipLaunchKernelGGL(k_tri_pack, dim3(grid_for(c->vsz, 256)), dim3(256), 0, c->stream, (long)c->vsz, c->ns, x + c->nf,
+                       gv);
     TRY(launch_check("k_tri_pack"));
     const int swap_copy = c->n_rot > 0;
     if (swap_copy) {
