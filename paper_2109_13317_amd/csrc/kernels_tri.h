@@ -467,8 +467,9 @@ k_tri_su(FlowArgs A, const double* __restrict__ gv, const int* __restrict__ uo_a
 
 // Per-wave LDS of the t kernel (ns pairs): plans [2][kTChunk], on-site
 // vertices [2][16][kTChunk], node weights, the site vectors of one sub-chunk
-// of G = 64/ns nodes (W a and b, [G][ns][16] each); the reduction area
-// [16][64] reuses the site vectors.
+// of G = 64/ns nodes (W a and b, [G][16][ns] each: component-major, so the
+// lanes of the lattice-sum phase, which read different pairs, hit
+// different banks); the two reduction areas [16][64] reuse them.
 struct TriTLds {
     int ns;
     __host__ __device__ int G() const { return kWave / ns; }
@@ -479,10 +480,47 @@ struct TriTLds {
     __host__ __device__ size_t vbase() const { return plans() + ons() + wts(); }
     __host__ __device__ size_t bytes() const {
         const size_t v = 2 * vec();
-        const size_t r = (size_t)16 * kWave * sizeof(double);
+        const size_t r = (size_t)2 * 16 * kWave * sizeof(double);     // two reduction areas
         return (vbase() + (v > r ? v : r) + 31) & ~(size_t)31;
     }
 };
+
+// The tabulated terms of the lattice sum split into at most 64 segments of
+// near-equal length, each within one output pair (host side, per context):
+// segment s covers terms [seg[2 s], seg[2 s + 1]); the segments of pair p are
+// seg_off[p] .. seg_off[p + 1] - 1.  Lane s of the lattice-sum phase takes
+// segment s, so no lane waits on the pair with the most terms.
+inline int tri_segments(int ns, const int* off, int* seg, int* seg_off) {
+    int k[kTriMaxPairs];
+    int total = 0;
+    for (int p = 0; p < ns; ++p) {
+        k[p] = off[p + 1] > off[p] ? 1 : 0;
+        total += k[p];
+    }
+    while (total < kWave) {
+        int best = -1, len = 0;
+        for (int p = 0; p < ns; ++p) {
+            const int n = off[p + 1] - off[p];
+            if (k[p] == 0 || k[p] >= n) continue;
+            const int l = (n + k[p] - 1) / k[p];
+            if (l > len) { len = l; best = p; }
+        }
+        if (best < 0 || len <= 1) break;
+        ++k[best];
+        ++total;
+    }
+    int s = 0;
+    for (int p = 0; p < ns; ++p) {
+        seg_off[p] = s;
+        const int n = off[p + 1] - off[p];
+        for (int i = 0; i < k[p]; ++i, ++s) {
+            seg[2 * s] = off[p] + (int)((long)n * i / k[p]);
+            seg[2 * s + 1] = off[p] + (int)((long)n * (i + 1) / k[p]);
+        }
+    }
+    seg_off[ns] = s;
+    return s;
+}
 
 // One wave per triple, ordered by (t, s, u); adds to dGamma.  Per sub-chunk
 // of G nodes, lanes (g, p) interpolate W a and b of node g for pair p into
@@ -492,9 +530,10 @@ struct TriTLds {
 // ROT: tables with spin rotations (the lattice-sum factors read through
 // them; a separate instance, so that the plain one keeps its code).
 template <bool ROT>
-static __global__ void __launch_bounds__(kWave * kTriWaves)
+static __global__ void __launch_bounds__(kWave * kTriWaves) __attribute__((amdgpu_waves_per_eu(2)))
 k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy, const int* __restrict__ rpa_rot,
-        const int* __restrict__ rot16, int n_rot, double* __restrict__ dx) {
+        const int* __restrict__ rot16, int n_rot, const int* __restrict__ seg, const int* __restrict__ seg_off,
+        int nseg, double* __restrict__ dx) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns, nq = A.nq;
     const Shared sh = load_shared(A, lds_raw, true);
@@ -515,9 +554,10 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
     Plan* plan = reinterpret_cast<Plan*>(base);                                      // [2][kTChunk]
     double* ons = reinterpret_cast<double*>(base + L.plans());                       // [2][16][kTChunk]
     double* wts = reinterpret_cast<double*>(base + L.plans() + L.ons());             // [kTChunk]
-    double* va = reinterpret_cast<double*>(base + L.vbase());                        // [G][ns][16]
-    double* vb = va + (size_t)L.G() * ns * 16;                                       // [G][ns][16]
-    double* red = va;
+    double* va = reinterpret_cast<double*>(base + L.vbase());                        // [G][16][ns]
+    double* vb = va + (size_t)L.G() * ns * 16;                                       // [G][16][ns]
+    double* red = va;                                                                // [16][64] corrections
+    double* red_s = va + 16 * kWave;                                                 // [16][64] segments
     const int o = tri_order(n_triples);
     if (o < 0) return;
     const int nsu = nf * (nf + 1) / 2;
@@ -534,9 +574,12 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
     const int cnt = A.tab_n[1 * nf + it];
     const double* tw = A.tab_w + (long)(1 * nf + it) * nq;
     const double* tg = A.tab_g + (long)(1 * nf + it) * nq;
-    double acc[16];
+    // this lane's segment of the lattice-sum terms
+    const bool sact = lane < nseg;
+    const int q0 = sact ? seg[2 * lane] : 0, q1 = sact ? seg[2 * lane + 1] : 0;
+    double acc[16], accs[16];         // vertex corrections (lanes (g, p)); lattice sum (segments)
 #pragma unroll
-    for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+    for (int m = 0; m < 16; ++m) acc[m] = accs[m] = 0.0;
     for (int k0 = 0; k0 < cnt; k0 += kTChunk) {
         const int kc = min(kTChunk, cnt - k0);
         {
@@ -573,14 +616,14 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
                     a[m] *= W;
-                    va[(g * ns + p) * 16 + m] = a[m];
+                    va[(g * 16 + m) * ns + p] = a[m];
                     h[m] = ons[(0 * 16 + m) * kTChunk + k];
                 }
                 tri_mul<kTriC1>(a, h, acc);                 // W (A, O1)
                 eval_tri(plan[kTChunk + k], rv, pp, hs, a);     // b
 #pragma unroll
                 for (int m = 0; m < 16; ++m) {
-                    vb[(g * ns + p) * 16 + m] = a[m];
+                    vb[(g * 16 + m) * ns + p] = a[m];
                     h[m] = ons[(1 * 16 + m) * kTChunk + k];
                     a[m] *= W;
                 }
@@ -588,8 +631,8 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
             }
             wave_lds_sync();
             if constexpr (!ROT) {
-              if (act) {
-                for (int qq = sh.off[p] + g; qq < sh.off[p + 1]; qq += G) {
+              {
+                for (int qq = q0; qq < q1; ++qq) {
                     const int tq = sh.terms[qq];
                     const int kab = tq & 0xffff, ka = kab / ns, kb = kab % ns;
                     const double cntq = (double)(tq >> 16);
@@ -597,16 +640,16 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
                         double x[16], y[16];
 #pragma unroll
                         for (int m = 0; m < 16; ++m) {
-                            x[m] = cntq * va[(kk * ns + ka) * 16 + m];
-                            y[m] = vb[(kk * ns + kb) * 16 + m];
+                            x[m] = cntq * va[(kk * 16 + m) * ns + ka];
+                            y[m] = vb[(kk * 16 + m) * ns + kb];
                         }
-                        tri_mul<kTriRpa>(x, y, acc);
+                        tri_mul<kTriRpa>(x, y, accs);
                     }
                 }
               }
-            } else if (act) {
+            } else {
                 // W_a Gamma_ka W_a^T and W_b Gamma_kb W_b^T (Sec. 4.1)
-                for (int qq = sh.off[p] + g; qq < sh.off[p + 1]; qq += G) {
+                for (int qq = q0; qq < q1; ++qq) {
                     const int tq = sh.terms[qq];
                     const int kab = tq & 0xffff, ka = kab / ns, kb = kab % ns;
                     const double cntq = (double)(tq >> 16);
@@ -615,21 +658,39 @@ k_tri_t(FlowArgs A, const double* __restrict__ gv, int n_triples, int swap_copy,
                     const int* rb = r16 + 16 * (rw >> 8);
                     for (int kk = 0; kk < sc; ++kk) {
                         double x[16], y[16];
-                        const double* sa = va + (kk * ns + ka) * 16;
-                        const double* sb = vb + (kk * ns + kb) * 16;
+                        const double* sa = va + kk * 16 * ns + ka;
+                        const double* sb = vb + kk * 16 * ns + kb;
 #pragma unroll
                         for (int m = 0; m < 16; ++m) {
-                            x[m] = cntq * tri_rot_get(sa, ra[m]);
-                            y[m] = tri_rot_get(sb, rb[m]);
+                            const int wa = ra[m], wb = rb[m];
+                            const double xa = sa[(wa & 15) * ns], yb = sb[(wb & 15) * ns];
+                            x[m] = cntq * ((wa & 16) ? -xa : xa);
+                            y[m] = (wb & 16) ? -yb : yb;
                         }
-                        tri_mul<kTriRpa>(x, y, acc);
+                        tri_mul<kTriRpa>(x, y, accs);
                     }
                 }
             }
             wave_lds_sync();
         }
     }
-    finish_tri(red, lane, ns, G, act, acc, dx + nf, vsz, T.out, true);
+    // corrections of lanes (g, p) and segment sums, both to LDS, then pair p
+    // adds its node groups and its segments in a fixed order
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        red[m * kWave + lane] = act ? acc[m] : 0.0;
+        red_s[m * kWave + lane] = sact ? accs[m] : 0.0;
+    }
+    wave_lds_sync();
+    if (lane < ns) {
+        const int s0 = seg_off[lane], s1 = seg_off[lane + 1];
+        for (int m = 0; m < 16; ++m) {
+            double tsum = 0.0;
+            for (int gg = 0; gg < G; ++gg) tsum += red[m * kWave + gg * ns + lane];
+            for (int ss = s0; ss < s1; ++ss) tsum += red_s[m * kWave + ss];
+            dx[nf + m * vsz + T.out * ns + lane] += tsum;
+        }
+    }
 }
 
 // ------------------------------------------------------ correlations -

@@ -40,6 +40,7 @@ struct pffrg_ctx {
     double* coupling9 = nullptr;    // TRI: [ns][3][3] coupling matrices
     int n_rot = 0;                  // TRI spin rotations (0: none; then no swap copy)
     int *rot16 = nullptr, *rpa_rot = nullptr, *swap_rot = nullptr, *site_rot = nullptr;
+    int *tri_seg = nullptr, *tri_seg_off = nullptr, tri_nseg = 0;   // TRI lattice-sum segments
     long vsz = 0, size = 0;
     pffrg_precision prec = PFFRG_FP64;
     hipStream_t stream = nullptr;
@@ -431,10 +432,12 @@ pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     TRY(launch_check("k_tri_su"));
     if (c->n_rot > 1)
         hipLaunchKernelGGL(k_tri_t<true>, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
-                           (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot, dx);
+                           (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot,
+                           (const int*)c->tri_seg, (const int*)c->tri_seg_off, c->tri_nseg, dx);
     else
         hipLaunchKernelGGL(k_tri_t<false>, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
-                           (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot, dx);
+                           (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot,
+                           (const int*)c->tri_seg, (const int*)c->tri_seg_off, c->tri_nseg, dx);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_tri_t");
 }
@@ -842,6 +845,12 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         }
         if (xyz) TRY(upload(c, &c->coupling3, coupling3, (size_t)3 * ns));
         else if (tri) TRY(upload(c, &c->coupling9, coupling9, (size_t)9 * ns));
+        if (tri) {
+            std::vector<int> seg(2 * kWave), seg_off(ns + 1);
+            c->tri_nseg = tri_segments(ns, lat->rpa_off, seg.data(), seg_off.data());
+            TRY(upload(c, &c->tri_seg, seg.data(), seg.size()));
+            TRY(upload(c, &c->tri_seg_off, seg_off.data(), seg_off.size()));
+        }
         if (tri && srot) {
             c->n_rot = srot->n_rot;
             std::vector<int> r16(16 * (size_t)c->n_rot), rr(nterms);
