@@ -484,7 +484,7 @@ constexpr int kMaxFreq = 128;    // mesh copy in LDS
 
 // Workgroup-shared tables in LDS: mesh, reciprocal spacings, the mesh look-up
 // table, pair exchange, and (t channel) the packed tabulated lattice-sum
-// terms with their offsets.
+// terms with their offsets and their split into runs (fill_runs).
 struct SharedLds {
     int nf, ns, n_terms;
     __host__ __device__ size_t mesh() const { return 0; }
@@ -493,8 +493,10 @@ struct SharedLds {
     __host__ __device__ size_t swap() const { return lut() + kLutMax; }
     __host__ __device__ size_t off() const { return swap() + (size_t)ns * sizeof(int); }
     __host__ __device__ size_t terms() const { return off() + (size_t)(ns + 1) * sizeof(int); }
+    __host__ __device__ size_t runs() const { return (terms() + (size_t)n_terms * sizeof(int) + 7) & ~(size_t)7; }
+    __host__ __device__ size_t run_off() const { return runs() + (size_t)kWave * sizeof(int2); }
     __host__ __device__ size_t bytes(bool with_terms) const {
-        const size_t b = with_terms ? terms() + (size_t)n_terms * sizeof(int) : terms();
+        const size_t b = with_terms ? run_off() + (size_t)(ns + 1) * sizeof(int) : terms();
         return (b + 31) & ~(size_t)31;
     }
 };
@@ -505,6 +507,8 @@ struct Shared {
     const int* swap;
     const int* off;
     const int* terms;
+    const int2* run;     // [kWave] term runs [x, y), empty beyond the last
+    const int* run_off;  // [ns+1] runs of pair p: run_off[p] .. run_off[p+1]-1
 };
 
 // Pointers to the shared tables in LDS (no memory traffic).
@@ -513,7 +517,48 @@ __device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* 
     return Shared{reinterpret_cast<double*>(lds + S.mesh()),
                   MeshLut{reinterpret_cast<double*>(lds + S.ih()), lds + S.lut(), A.lut_shift, A.lut_kmin},
                   reinterpret_cast<int*>(lds + S.swap()), reinterpret_cast<int*>(lds + S.off()),
-                  reinterpret_cast<int*>(lds + S.terms())};
+                  reinterpret_cast<int*>(lds + S.terms()), reinterpret_cast<int2*>(lds + S.runs()),
+                  reinterpret_cast<int*>(lds + S.run_off())};
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_max_int(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Split the tabulated terms of each pair into runs of at most S consecutive
+// terms, S the smallest length for which the runs of all pairs fit on the 64
+// lanes of a wave (pair p: ceil(len_p / S) runs of near-equal length).  The
+// t channel's contraction gives lane l run l, so every lane's sum belongs to
+// one pair and the longest lane takes about the mean instead of the longest
+// pair's share.  Called by one whole wave (lane l); the result depends only
+// on the offsets, so every launch form splits the terms the same way.
+__device__ __forceinline__ void fill_runs(const FlowArgs& A, int2* run, int* run_off, int l) {
+    const int ns = A.ns;
+    const int o0 = l < ns ? A.rpa_off[l] : 0;
+    const int len = l < ns ? A.rpa_off[l + 1] - o0 : 0;
+    int lo = 1, hi = max(wave_max_int(len), 1);   // hi: ns <= 64 runs
+    while (lo < hi) {                              // uniform over the wave
+        const int mid = (lo + hi) / 2;
+        if (wave_sum_int((len + mid - 1) / mid) <= kWave) hi = mid;
+        else lo = mid + 1;
+    }
+    const int k = (len + hi - 1) / hi;
+    int start = k;                                 // inclusive prefix sum, then exclusive
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int v = __shfl_up(start, o, kWave);
+        if (l >= o) start += v;
+    }
+    start -= k;
+    run[l] = make_int2(0, 0);
+    if (l < ns) run_off[l] = start;
+    if (l == ns - 1) run_off[ns] = start + k;
+    wave_lds_sync();
+    for (int j = 0; j < k; ++j) run[start + j] = make_int2(o0 + j * len / k, o0 + (j + 1) * len / k);
 }
 
 // Fill the shared tables (workgroup-wide; before any wave leaves).
@@ -534,6 +579,8 @@ __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* ld
     if (with_terms) {
         for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
         for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
+        if (threadIdx.x < kWave)
+            fill_runs(A, const_cast<int2*>(sh.run), const_cast<int*>(sh.run_off), threadIdx.x);
     }
     __syncthreads();
 }
@@ -891,7 +938,7 @@ template <class R, int NSP> struct TMatrixCores {
     static constexpr bool on = NSP <= 16 || (sizeof(R) == 8 && NSP > 20);
 };
 
-// base: the wave's LDS area (layout WaveLds<R>{ns, SUB}); sh.off / sh.terms
+// base: the wave's LDS area (layout WaveLds<R>{ns, SUB}); sh.terms / sh.run
 // must hold the lattice-sum tables.
 template <int NSP, class R>
 __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, unsigned char* base,
@@ -1089,14 +1136,15 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     }
 
     // the matrix strain by strain (reusing the work area), contracted with
-    // the tabulated (ka, kb, count) terms of every output pair; lanes (g, p)
-    // take every G-th term of pair p
+    // the tabulated (ka, kb, count) terms of every output pair; lane l takes
+    // run l of the terms (two sums in turn, for two loads in flight)
     wave_lds_sync();
     if constexpr (!kComp) {
         sum_s.s = acc_s;
         sum_d.s = acc_d;
     }
     double tot_s = sum_s.value(), tot_d = sum_d.value();
+    double* part = reinterpret_cast<double*>(base + L.mat());   // [2][kWave]: free until the pairs finish
     for (int strain = 0; strain < 2; ++strain) {
         if constexpr (kMat) {
 #pragma unroll
@@ -1130,17 +1178,32 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             }
         }
         wave_lds_sync();
-        if (act) {
-            double acc = 0.0;
-            for (int q = sh.off[p] + g; q < sh.off[p + 1]; q += G) {
-                const int tq = sh.terms[q];
-                acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
-            }
-            if (strain == 0) tot_s = fma(-2.0, acc, tot_s);
-            else tot_d = fma(-2.0, acc, tot_d);
+        const int2 run = sh.run[lane];
+        double a0 = 0.0, a1 = 0.0;
+        int q = run.x;
+        for (; q + 1 < run.y; q += 2) {
+            const int t0 = sh.terms[q], t1 = sh.terms[q + 1];
+            a0 = fma((double)(t0 >> 16), mat[t0 & 0xffff], a0);
+            a1 = fma((double)(t1 >> 16), mat[t1 & 0xffff], a1);
         }
+        if (q < run.y) {
+            const int t0 = sh.terms[q];
+            a0 = fma((double)(t0 >> 16), mat[t0 & 0xffff], a0);
+        }
+        part[strain * kWave + lane] = a0 + a1;
         wave_lds_sync();
     }
+    // pair p (lane g = 0) adds its runs in order
+    if (act && g == 0) {
+        double rs = 0.0, rd = 0.0;
+        for (int l = sh.run_off[p]; l < sh.run_off[p + 1]; ++l) {
+            rs += part[l];
+            rd += part[kWave + l];
+        }
+        tot_s = fma(-2.0, rs, tot_s);
+        tot_d = fma(-2.0, rd, tot_d);
+    }
+    wave_lds_sync();
     return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
 }
 
