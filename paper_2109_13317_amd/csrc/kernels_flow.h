@@ -49,6 +49,8 @@ struct FlowArgs {
     double* tab_g;          // [3*nf*nq] node weights
     const unsigned char* lut;   // [kLutMax] mesh look-up table (build_mesh_lut)
     int lut_shift, lut_kmin;
+    const int2* run;        // [kWave] term runs (term_runs), or null
+    const int* run_off;     // [ns+1]
 };
 
 constexpr int kWave = 64;
@@ -484,7 +486,7 @@ constexpr int kMaxFreq = 128;    // mesh copy in LDS
 
 // Workgroup-shared tables in LDS: mesh, reciprocal spacings, the mesh look-up
 // table, pair exchange, and (t channel) the packed tabulated lattice-sum
-// terms with their offsets and their split into runs (fill_runs).
+// terms with their offsets and their split into runs (term_runs).
 struct SharedLds {
     int nf, ns, n_terms;
     __host__ __device__ size_t mesh() const { return 0; }
@@ -507,7 +509,7 @@ struct Shared {
     const int* swap;
     const int* off;
     const int* terms;
-    const int2* run;     // [kWave] term runs [x, y), empty beyond the last
+    const int2* run;     // [kWave] term runs [x, y) (term_runs; filled on request, see fill_shared)
     const int* run_off;  // [ns+1] runs of pair p: run_off[p] .. run_off[p+1]-1
 };
 
@@ -521,48 +523,50 @@ __device__ __forceinline__ Shared shared_ptrs(const FlowArgs& A, unsigned char* 
                   reinterpret_cast<int*>(lds + S.run_off())};
 }
 
-__device__ __forceinline__ int wave_sum_int(int v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-__device__ __forceinline__ int wave_max_int(int v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
-    return v;
+// The tabulated terms of the lattice sum split into at most 64 runs of
+// near-equal length, each within one output pair (host side, once per
+// context): pair p gets k_p runs, one more at a time to the pair whose runs
+// are longest.  Run r covers terms [run[2r], run[2r+1]), the runs of pair p
+// are run_off[p] .. run_off[p+1]-1, and runs past the last are empty.  Lane
+// r of a contraction takes run r, so no lane waits on the pair with the
+// most terms.  Returns the number of runs (at most kWave; ns <= kWave).
+inline int term_runs(int ns, const int* off, int* run, int* run_off) {
+    int k[kWave];
+    int total = 0;
+    for (int p = 0; p < ns; ++p) {
+        k[p] = off[p + 1] > off[p] ? 1 : 0;
+        total += k[p];
+    }
+    while (total < kWave) {
+        int best = -1, len = 0;
+        for (int p = 0; p < ns; ++p) {
+            const int n = off[p + 1] - off[p];
+            if (k[p] == 0 || k[p] >= n) continue;
+            const int l = (n + k[p] - 1) / k[p];
+            if (l > len) { len = l; best = p; }
+        }
+        if (best < 0 || len <= 1) break;
+        ++k[best];
+        ++total;
+    }
+    int s = 0;
+    for (int p = 0; p < ns; ++p) {
+        run_off[p] = s;
+        const int n = off[p + 1] - off[p];
+        for (int i = 0; i < k[p]; ++i, ++s) {
+            run[2 * s] = off[p] + (int)((long)n * i / k[p]);
+            run[2 * s + 1] = off[p] + (int)((long)n * (i + 1) / k[p]);
+        }
+    }
+    run_off[ns] = s;
+    for (int r = s; r < kWave; ++r) run[2 * r] = run[2 * r + 1] = 0;
+    return s;
 }
 
-// Split the tabulated terms of each pair into runs of at most S consecutive
-// terms, S the smallest length for which the runs of all pairs fit on the 64
-// lanes of a wave (pair p: ceil(len_p / S) runs of near-equal length).  The
-// t channel's contraction gives lane l run l, so every lane's sum belongs to
-// one pair and the longest lane takes about the mean instead of the longest
-// pair's share.  Called by one whole wave (lane l); the result depends only
-// on the offsets, so every launch form splits the terms the same way.
-__device__ __forceinline__ void fill_runs(const FlowArgs& A, int2* run, int* run_off, int l) {
-    const int ns = A.ns;
-    const int o0 = l < ns ? A.rpa_off[l] : 0;
-    const int len = l < ns ? A.rpa_off[l + 1] - o0 : 0;
-    int lo = 1, hi = max(wave_max_int(len), 1);   // hi: ns <= 64 runs
-    while (lo < hi) {                              // uniform over the wave
-        const int mid = (lo + hi) / 2;
-        if (wave_sum_int((len + mid - 1) / mid) <= kWave) hi = mid;
-        else lo = mid + 1;
-    }
-    const int k = (len + hi - 1) / hi;
-    int start = k;                                 // inclusive prefix sum, then exclusive
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int v = __shfl_up(start, o, kWave);
-        if (l >= o) start += v;
-    }
-    start -= k;
-    run[l] = make_int2(0, 0);
-    if (l < ns) run_off[l] = start;
-    if (l == ns - 1) run_off[ns] = start + k;
-    wave_lds_sync();
-    for (int j = 0; j < k; ++j) run[start + j] = make_int2(o0 + j * len / k, o0 + (j + 1) * len / k);
-}
-
-// Fill the shared tables (workgroup-wide; before any wave leaves).
-__device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
+// Fill the shared tables (workgroup-wide; before any wave leaves); with_runs
+// also copies the term runs (the t channel beyond 20 pairs).
+__device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* lds, bool with_terms,
+                                            bool with_runs = false) {
     const Shared sh = shared_ptrs(A, lds);
     double* w = const_cast<double*>(sh.w);
     double* ih = const_cast<double*>(sh.lut.ih);
@@ -579,14 +583,19 @@ __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* ld
     if (with_terms) {
         for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
         for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
-        if (threadIdx.x < kWave)
-            fill_runs(A, const_cast<int2*>(sh.run), const_cast<int*>(sh.run_off), threadIdx.x);
+        if (with_runs) {
+            int2* run = const_cast<int2*>(sh.run);
+            int* roff = const_cast<int*>(sh.run_off);
+            for (int i = threadIdx.x; i < kWave; i += blockDim.x) run[i] = A.run[i];
+            for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) roff[i] = A.run_off[i];
+        }
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* lds, bool with_terms) {
-    fill_shared(A, lds, with_terms);
+__device__ __forceinline__ Shared load_shared(const FlowArgs& A, unsigned char* lds, bool with_terms,
+                                              bool with_runs = false) {
+    fill_shared(A, lds, with_terms, with_runs);
     return shared_ptrs(A, lds);
 }
 
@@ -938,8 +947,8 @@ template <class R, int NSP> struct TMatrixCores {
     static constexpr bool on = NSP <= 16 || (sizeof(R) == 8 && NSP > 20);
 };
 
-// base: the wave's LDS area (layout WaveLds<R>{ns, SUB}); sh.terms / sh.run
-// must hold the lattice-sum tables.
+// base: the wave's LDS area (layout WaveLds<R>{ns, SUB}); sh.off / sh.terms
+// (and beyond 20 pairs sh.run) must hold the lattice-sum tables.
 template <int NSP, class R>
 __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, unsigned char* base,
                                            const Triple& T, __amdgpu_buffer_rsrc_t rv, int lane) {
@@ -1136,8 +1145,11 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
     }
 
     // the matrix strain by strain (reusing the work area), contracted with
-    // the tabulated (ka, kb, count) terms of every output pair; lane l takes
-    // run l of the terms (two sums in turn, for two loads in flight)
+    // the tabulated (ka, kb, count) terms of every output pair.  Beyond 20
+    // pairs lane l takes run l of the terms (two sums in turn, for two loads
+    // in flight; the run sums of a pair are added after both strains);
+    // otherwise lanes (g, p) take every G-th term of pair p, whose short
+    // lists gain nothing from the extra reduction
     wave_lds_sync();
     if constexpr (!kComp) {
         sum_s.s = acc_s;
@@ -1178,32 +1190,44 @@ __device__ __forceinline__ LanePart t_body(const FlowArgs& A, const Shared& sh, 
             }
         }
         wave_lds_sync();
-        const int2 run = sh.run[lane];
-        double a0 = 0.0, a1 = 0.0;
-        int q = run.x;
-        for (; q + 1 < run.y; q += 2) {
-            const int t0 = sh.terms[q], t1 = sh.terms[q + 1];
-            a0 = fma((double)(t0 >> 16), mat[t0 & 0xffff], a0);
-            a1 = fma((double)(t1 >> 16), mat[t1 & 0xffff], a1);
+        if constexpr (NSP > 20) {
+            const int2 run = sh.run[lane];
+            double a0 = 0.0, a1 = 0.0;
+            int q = run.x;
+            for (; q + 1 < run.y; q += 2) {
+                const int t0 = sh.terms[q], t1 = sh.terms[q + 1];
+                a0 = fma((double)(t0 >> 16), mat[t0 & 0xffff], a0);
+                a1 = fma((double)(t1 >> 16), mat[t1 & 0xffff], a1);
+            }
+            if (q < run.y) {
+                const int t0 = sh.terms[q];
+                a0 = fma((double)(t0 >> 16), mat[t0 & 0xffff], a0);
+            }
+            part[strain * kWave + lane] = a0 + a1;
+        } else if (act) {
+            double acc = 0.0;
+            for (int q = sh.off[p] + g; q < sh.off[p + 1]; q += G) {
+                const int tq = sh.terms[q];
+                acc = fma((double)(tq >> 16), mat[tq & 0xffff], acc);
+            }
+            if (strain == 0) tot_s = fma(-2.0, acc, tot_s);
+            else tot_d = fma(-2.0, acc, tot_d);
         }
-        if (q < run.y) {
-            const int t0 = sh.terms[q];
-            a0 = fma((double)(t0 >> 16), mat[t0 & 0xffff], a0);
-        }
-        part[strain * kWave + lane] = a0 + a1;
         wave_lds_sync();
     }
-    // pair p (lane g = 0) adds its runs in order
-    if (act && g == 0) {
-        double rs = 0.0, rd = 0.0;
-        for (int l = sh.run_off[p]; l < sh.run_off[p + 1]; ++l) {
-            rs += part[l];
-            rd += part[kWave + l];
+    if constexpr (NSP > 20) {
+        // pair p (lane g = 0) adds its runs in order
+        if (act && g == 0) {
+            double rs = 0.0, rd = 0.0;
+            for (int l = sh.run_off[p]; l < sh.run_off[p + 1]; ++l) {
+                rs += part[l];
+                rd += part[kWave + l];
+            }
+            tot_s = fma(-2.0, rs, tot_s);
+            tot_d = fma(-2.0, rd, tot_d);
         }
-        tot_s = fma(-2.0, rs, tot_s);
-        tot_d = fma(-2.0, rd, tot_d);
+        wave_lds_sync();
     }
-    wave_lds_sync();
     return LanePart{act ? tot_s : 0.0, act ? tot_d : 0.0};
 }
 
@@ -1217,7 +1241,7 @@ __attribute__((amdgpu_waves_per_eu(NSP > 20 ? 3 : (NSP > 16 ? 4 : 5))))
 k_vertex_t(FlowArgs A, const V2<R>* __restrict__ gv, int n_triples, double* __restrict__ dx, int add) {
     extern __shared__ __align__(32) unsigned char lds_raw[];
     const int nf = A.nf, ns = A.ns;
-    const Shared sh = load_shared(A, lds_raw, true);
+    const Shared sh = load_shared(A, lds_raw, true, NSP > 20);
     A.w = sh.w;
     const WaveLds<R> L{ns, TShape<NSP>::SUB};
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -1252,7 +1276,7 @@ k_vertex_stu(FlowArgs A, const V2<R>* __restrict__ gv, const int* __restrict__ u
     const int role = __builtin_amdgcn_readfirstlane(j % 3), slot = j / 3;
     const int per = gridDim.x / 24;
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const Shared sh = load_shared(A, lds_raw, role == 2);
+    const Shared sh = load_shared(A, lds_raw, role == 2, role == 2 && NSP > 20);
     A.w = sh.w;
     const int o = __builtin_amdgcn_readfirstlane((xcd * per + slot) * kWavesPerBlock + wid);
     if (o >= n_triples) return;

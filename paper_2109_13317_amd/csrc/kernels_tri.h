@@ -485,43 +485,6 @@ struct TriTLds {
     }
 };
 
-// The tabulated terms of the lattice sum split into at most 64 segments of
-// near-equal length, each within one output pair (host side, per context):
-// segment s covers terms [seg[2 s], seg[2 s + 1]); the segments of pair p are
-// seg_off[p] .. seg_off[p + 1] - 1.  Lane s of the lattice-sum phase takes
-// segment s, so no lane waits on the pair with the most terms.
-inline int tri_segments(int ns, const int* off, int* seg, int* seg_off) {
-    int k[kTriMaxPairs];
-    int total = 0;
-    for (int p = 0; p < ns; ++p) {
-        k[p] = off[p + 1] > off[p] ? 1 : 0;
-        total += k[p];
-    }
-    while (total < kWave) {
-        int best = -1, len = 0;
-        for (int p = 0; p < ns; ++p) {
-            const int n = off[p + 1] - off[p];
-            if (k[p] == 0 || k[p] >= n) continue;
-            const int l = (n + k[p] - 1) / k[p];
-            if (l > len) { len = l; best = p; }
-        }
-        if (best < 0 || len <= 1) break;
-        ++k[best];
-        ++total;
-    }
-    int s = 0;
-    for (int p = 0; p < ns; ++p) {
-        seg_off[p] = s;
-        const int n = off[p + 1] - off[p];
-        for (int i = 0; i < k[p]; ++i, ++s) {
-            seg[2 * s] = off[p] + (int)((long)n * i / k[p]);
-            seg[2 * s + 1] = off[p] + (int)((long)n * (i + 1) / k[p]);
-        }
-    }
-    seg_off[ns] = s;
-    return s;
-}
-
 // One wave per triple, ordered by (t, s, u); adds to dGamma.  Per sub-chunk
 // of G nodes, lanes (g, p) interpolate W a and b of node g for pair p into
 // LDS and add the two vertex corrections of pair p; then lanes (g, p) run

@@ -40,7 +40,7 @@ struct pffrg_ctx {
     double* coupling9 = nullptr;    // TRI: [ns][3][3] coupling matrices
     int n_rot = 0;                  // TRI spin rotations (0: none; then no swap copy)
     int *rot16 = nullptr, *rpa_rot = nullptr, *swap_rot = nullptr, *site_rot = nullptr;
-    int *tri_seg = nullptr, *tri_seg_off = nullptr, tri_nseg = 0;   // TRI lattice-sum segments
+    int *t_run = nullptr, *t_run_off = nullptr, t_nrun = 0;   // lattice-sum term runs (term_runs)
     long vsz = 0, size = 0;
     pffrg_precision prec = PFFRG_FP64;
     hipStream_t stream = nullptr;
@@ -113,6 +113,7 @@ struct pffrg_ctx {
         A.rpa_term = rpa_term; A.n_terms = n_terms;
         A.tab_n = tab_n; A.tab_w = tab_w; A.tab_g = tab_g;
         A.lut = lut; A.lut_shift = lut_shift; A.lut_kmin = lut_kmin;
+        A.run = reinterpret_cast<const int2*>(t_run); A.run_off = t_run_off;
         return A;
     }
 };
@@ -433,11 +434,11 @@ pffrg_status tri_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {
     if (c->n_rot > 1)
         hipLaunchKernelGGL(k_tri_t<true>, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
                            (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot,
-                           (const int*)c->tri_seg, (const int*)c->tri_seg_off, c->tri_nseg, dx);
+                           c->t_run, c->t_run_off, c->t_nrun, dx);
     else
         hipLaunchKernelGGL(k_tri_t<false>, grid, block, tri_lds_t(c->nf, c->ns, c->n_terms, c->n_rot), c->stream, A,
                            (const double*)gv, T, swap_copy, (const int*)c->rpa_rot, (const int*)c->rot16, c->n_rot,
-                           (const int*)c->tri_seg, (const int*)c->tri_seg_off, c->tri_nseg, dx);
+                           c->t_run, c->t_run_off, c->t_nrun, dx);
     prof_mark(c, PFFRG_K_VERTEX, true);
     return launch_check("k_tri_t");
 }
@@ -845,11 +846,11 @@ pffrg_status create_ctx(const pffrg_lattice* lat_in, const double* coupling3, co
         }
         if (xyz) TRY(upload(c, &c->coupling3, coupling3, (size_t)3 * ns));
         else if (tri) TRY(upload(c, &c->coupling9, coupling9, (size_t)9 * ns));
-        if (tri) {
-            std::vector<int> seg(2 * kWave), seg_off(ns + 1);
-            c->tri_nseg = tri_segments(ns, lat->rpa_off, seg.data(), seg_off.data());
-            TRY(upload(c, &c->tri_seg, seg.data(), seg.size()));
-            TRY(upload(c, &c->tri_seg_off, seg_off.data(), seg_off.size()));
+        {
+            std::vector<int> run(2 * kWave), run_off(ns + 1);
+            c->t_nrun = term_runs(ns, lat->rpa_off, run.data(), run_off.data());
+            TRY(upload(c, &c->t_run, run.data(), run.size()));
+            TRY(upload(c, &c->t_run_off, run_off.data(), run_off.size()));
         }
         if (tri && srot) {
             c->n_rot = srot->n_rot;

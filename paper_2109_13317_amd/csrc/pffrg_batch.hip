@@ -113,6 +113,7 @@ struct pffrg_batch {
         A.su_a = su_a; A.su_c = su_c;
         A.tab_n = tab_n; A.tab_w = tab_w; A.tab_g = tab_g;
         A.lut = lut; A.lut_shift = lut_shift; A.lut_kmin = lut_kmin;
+        A.run = nullptr; A.run_off = nullptr;     // batch points have at most 20 pairs
         B.pts = d_pts;
         B.n_points = np;
         return B;
