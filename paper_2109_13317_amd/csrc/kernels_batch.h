@@ -180,7 +180,7 @@ k_batch_vertex(BatchArgs B, const V2<R>* __restrict__ gv, const int2* __restrict
         FlowArgs A = point_args(B, item.x);
         if (item.x != cur) {                 // uniform over the workgroup
             __syncthreads();
-            fill_shared(A, lds_raw, PART != kSU);
+            fill_shared<false>(A, lds_raw, PART != kSU);
             cur = item.x;
         }
         const Shared sh = shared_ptrs(A, lds_raw);

@@ -564,7 +564,16 @@ inline int term_runs(int ns, const int* off, int* run, int* run_off) {
 }
 
 // Fill the shared tables (workgroup-wide; before any wave leaves); with_runs
-// also copies the term runs (the t channel beyond 20 pairs).
+// also copies the term runs (the t channel beyond 20 pairs).  Each thread
+// issues every global load of the first pass (one index of each table and up
+// to kFillTerms terms) before its first LDS write, so the workgroup waits on
+// about one load latency instead of one per table and pass; what the first
+// pass leaves (long meshes, many terms, small workgroups) is copied after it
+// in strided loops.  kFirst = false (a fill inside a persistent loop, where
+// the first pass's registers would spill) copies each table in its own loop
+// and no runs.
+constexpr int kFillTerms = 16;
+template <bool kFirst = true>
 __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* lds, bool with_terms,
                                             bool with_runs = false) {
     const Shared sh = shared_ptrs(A, lds);
@@ -574,20 +583,81 @@ __device__ __forceinline__ void fill_shared(const FlowArgs& A, unsigned char* ld
     int* sw = const_cast<int*>(sh.swap);
     int* off = const_cast<int*>(sh.off);
     int* terms = const_cast<int*>(sh.terms);
-    for (int i = threadIdx.x; i < A.nf; i += blockDim.x) {
-        w[i] = A.w[i];
-        ih[i] = i + 1 < A.nf ? 1.0 / (A.w[i + 1] - A.w[i]) : 0.0;
+    if constexpr (!kFirst) {
+        for (int i = threadIdx.x; i < A.nf; i += blockDim.x) {
+            w[i] = A.w[i];
+            ih[i] = i + 1 < A.nf ? 1.0 / (A.w[i + 1] - A.w[i]) : 0.0;
+        }
+        for (int i = threadIdx.x; i < kLutMax / 4; i += blockDim.x) lut[i] = reinterpret_cast<const unsigned*>(A.lut)[i];
+        for (int i = threadIdx.x; i < A.ns; i += blockDim.x) sw[i] = A.swap[i];
+        if (with_terms) {
+            for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
+            for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
+        }
+        __syncthreads();
+        return;
     }
-    for (int i = threadIdx.x; i < kLutMax / 4; i += blockDim.x) lut[i] = reinterpret_cast<const unsigned*>(A.lut)[i];
-    for (int i = threadIdx.x; i < A.ns; i += blockDim.x) sw[i] = A.swap[i];
+    const unsigned* lsrc = reinterpret_cast<const unsigned*>(A.lut);
+    int2* run = const_cast<int2*>(sh.run);
+    int* roff = const_cast<int*>(sh.run_off);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nf = A.nf, ns = A.ns, nterm = A.n_terms;
+    // first pass: loads
+    double w0 = 0.0, w1 = 0.0;
+    unsigned lv = 0u;
+    int sv = 0, ov = 0, rov = 0;
+    int2 rv = make_int2(0, 0);
+    int tv[kFillTerms];
+    if (tid < nf) {
+        w0 = A.w[tid];
+        if (tid + 1 < nf) w1 = A.w[tid + 1];
+    }
+    if (tid < kLutMax / 4) lv = lsrc[tid];
+    if (tid < ns) sv = A.swap[tid];
     if (with_terms) {
-        for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) off[i] = A.rpa_off[i];
-        for (int i = threadIdx.x; i < A.n_terms; i += blockDim.x) terms[i] = A.rpa_term[i];
+        if (tid <= ns) ov = A.rpa_off[tid];
+#pragma unroll
+        for (int k = 0; k < kFillTerms; ++k) {
+            const int i = tid + k * nt;
+            tv[k] = i < nterm ? A.rpa_term[i] : 0;
+        }
         if (with_runs) {
-            int2* run = const_cast<int2*>(sh.run);
-            int* roff = const_cast<int*>(sh.run_off);
-            for (int i = threadIdx.x; i < kWave; i += blockDim.x) run[i] = A.run[i];
-            for (int i = threadIdx.x; i <= A.ns; i += blockDim.x) roff[i] = A.run_off[i];
+            if (tid < kWave) rv = A.run[tid];
+            if (tid <= ns) rov = A.run_off[tid];
+        }
+    }
+    // first pass: stores
+    if (tid < nf) {
+        w[tid] = w0;
+        ih[tid] = tid + 1 < nf ? 1.0 / (w1 - w0) : 0.0;
+    }
+    if (tid < kLutMax / 4) lut[tid] = lv;
+    if (tid < ns) sw[tid] = sv;
+    if (with_terms) {
+        if (tid <= ns) off[tid] = ov;
+#pragma unroll
+        for (int k = 0; k < kFillTerms; ++k) {
+            const int i = tid + k * nt;
+            if (i < nterm) terms[i] = tv[k];
+        }
+        if (with_runs) {
+            if (tid < kWave) run[tid] = rv;
+            if (tid <= ns) roff[tid] = rov;
+        }
+    }
+    // the rest
+    for (int i = tid + nt; i < nf; i += nt) {
+        w[i] = A.w[i];
+        ih[i] = i + 1 < nf ? 1.0 / (A.w[i + 1] - A.w[i]) : 0.0;
+    }
+    for (int i = tid + nt; i < kLutMax / 4; i += nt) lut[i] = lsrc[i];
+    for (int i = tid + nt; i < ns; i += nt) sw[i] = A.swap[i];
+    if (with_terms) {
+        for (int i = tid + nt; i <= ns; i += nt) off[i] = A.rpa_off[i];
+        for (int i = tid + kFillTerms * nt; i < nterm; i += nt) terms[i] = A.rpa_term[i];
+        if (with_runs) {
+            for (int i = tid + nt; i < kWave; i += nt) run[i] = A.run[i];
+            for (int i = tid + nt; i <= ns; i += nt) roff[i] = A.run_off[i];
         }
     }
     __syncthreads();
