@@ -57,8 +57,7 @@ PEAK_HBM_GBS = 8000.0
 # workload; a changed kernel reports traffic null until the counters are
 # taken again.
 MEASURED_TRAFFIC = {
-    ("b617215c11b6d3c5", "square_j1j2"): 28.59e6,
-    ("b617215c11b6d3c5", "pyrochlore"): 277.45e6,
+    ("dfc6706665cd59dd", "pyrochlore"): 277.64e6,
 }
 
 
