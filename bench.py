@@ -848,8 +848,8 @@ def hot_path_leg(name: str, steps: int, warmup: int, breakdown: bool = True) -> 
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                 "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(), name)), "traffic_unit": "bytes/launch",
-                "kernel": (f"vertex right-hand side: k_vertex_su<0>, k_vertex_su<2> on the library stream beside "
-                           f"k_vertex_t<{4 * ((ns + 3) // 4)}, double> on its second stream, then the t-part sum "
+                "kernel": (f"vertex right-hand side: k_vertex_t<{4 * ((ns + 3) // 4)}, double> on the library stream "
+                           f"beside k_vertex_su<0>, k_vertex_su<2> on its second stream, then the t-part sum "
                            "(timed from before the fork to after the join)") if concurrent else
                           f"k_vertex_stu<{4 * ((ns + 3) // 4)}, double> (s, u and t channels in one launch)",
                 "launch_form": "concurrent" if concurrent else "one_launch",

@@ -354,8 +354,8 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
  *   PFFRG_VERTEX_ONE_LAUNCH   one launch whose workgroups take the s, u and t
  *                             roles in turn, then the sum of the parts;
  *   PFFRG_VERTEX_SEPARATE     three launches in turn (s writes, u and t add);
- *   PFFRG_VERTEX_CONCURRENT   s and u on the context's stream while the t
- *                             channel runs on a second stream of the context
+ *   PFFRG_VERTEX_CONCURRENT   the t channel on the context's stream while s
+ *                             and u run on a second stream of the context
  *                             (default priority), joined before the sum;
  *   PFFRG_VERTEX_AUTO         (the default) concurrent beyond 20 pairs, one
  *                             launch otherwise.

@@ -71,8 +71,8 @@ struct pffrg_ctx {
     double *ybuf = nullptr, *ebuf = nullptr;
     double *part_u = nullptr, *part_t = nullptr;   // u- and t-channel parts of one vertex RHS (state layout)
     // how the three channels are launched (pffrg_set_vertex_mode); the
-    // concurrent mode runs the t channel on `side`, forked from and joined to
-    // the context's stream through the two events
+    // concurrent mode runs the s and u channels on `side`, forked from and
+    // joined to the context's stream through the two events
     int vertex_mode = PFFRG_VERTEX_AUTO;
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -270,8 +270,8 @@ pffrg_status launch_vertex_t(pffrg_ctx* c, hipStream_t st, ProfPair e, const Flo
 //   one launch     k_vertex_stu writes the three parts (s into dx), then
 //                  k_sum_channels adds them;
 //   separate       s writes dx, u adds, t adds (three launches in turn);
-//   concurrent     s writes dx and u adds on the context's stream while t
-//                  writes its part on the side stream; after the join the t
+//   concurrent     t writes its part on the context's stream while s writes
+//                  dx and u adds on the side stream; after the join the t
 //                  part is added.
 template <class R>
 pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
@@ -307,20 +307,27 @@ pffrg_status vertex_rhs(pffrg_ctx* c, double* dx) {
         prof_mark(c, PFFRG_K_VERTEX, true);
         return launch_check("k_sum_channels");
     }
+    // concurrent: the t launch goes straight onto the context's stream and
+    // the s and u launches onto the side stream behind the fork, so the t
+    // workgroups (the larger ones) take the compute units first and the s/u
+    // workgroups fill what they leave; the other way round the s/u
+    // workgroups refill every slot they free and t waits for their end
+    hipStream_t su_stream = c->stream;
     if (mode == PFFRG_VERTEX_CONCURRENT) {
         HIP_TRY(hipEventRecord(c->fork, c->stream));
         HIP_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
-        TRY(launch_vertex_t<R>(c, c->side, ProfPair{}, A, T, c->part_t, 0));
-        HIP_TRY(hipEventRecord(c->join, c->side));
+        TRY(launch_vertex_t<R>(c, c->stream, ProfPair{}, A, T, c->part_t, 0));
+        su_stream = c->side;
     }
     const ProfPair es = prof_pair(c, PFFRG_K_VERTEX_S);
-    hipExtLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, c->stream, es.start, es.stop, 0, A,
+    hipExtLaunchKernelGGL((k_vertex_su<0, R>), grid, block, lds_su, su_stream, es.start, es.stop, 0, A,
                           (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
     const ProfPair eu = prof_pair(c, PFFRG_K_VERTEX_U);
-    hipExtLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, c->stream, eu.start, eu.stop, 0, A,
+    hipExtLaunchKernelGGL((k_vertex_su<2, R>), grid, block, lds_su, su_stream, eu.start, eu.stop, 0, A,
                           (const V2<R>*)gv, (const int*)c->uo_a, (const int*)c->uo_c, T, dx);
     TRY(launch_check("k_vertex_su"));
     if (mode == PFFRG_VERTEX_CONCURRENT) {
+        HIP_TRY(hipEventRecord(c->join, c->side));
         HIP_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
         hipLaunchKernelGGL(k_axpy, dim3(grid_for(nv, 256)), dim3(256), 0, c->stream, nv, 1.0,
                            (const double*)c->part_t + c->nf, dx + c->nf);
