@@ -68,6 +68,48 @@ def test_rhs_random_state(name, lam_kind):
     assert err <= TOL, err
 
 
+# beyond 20 pairs: the FP64 lattice sum on two matrix-core tiles per side
+# (24, 28 and 32 rows), the FP32 one on vector-ALU blocks, and the
+# contraction with the tabulated terms in lane runs split on the host
+BEYOND_20 = {
+    "honeycomb_L8_N4": ("honeycomb", dict(j1=1.0, j2=0.5, j3=0.25), 8, W.log_mesh(1e-2, 50.0, 4)),   # 23 pairs
+    "square_L8_N4": ("square", dict(j1=1.0, j2=0.5), 8, W.log_mesh(1e-2, 50.0, 4)),                   # 25 pairs
+    "pyrochlore_L5_N3": ("pyrochlore", dict(j1=1.0), 5, W.log_mesh(1e-3, 100.0, 3)),                  # 31 pairs
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(BEYOND_20))
+def test_rhs_beyond_20_pairs_every_element(name, precision):
+    """Every element of one right-hand side on a seeded state against the
+    oracle, in each launch form (one launch, three in turn, t beside s and u),
+    which must also agree bitwise."""
+    import torch
+    import oracle
+    from paper_2109_13317_amd import build_tables
+    from paper_2109_13317_amd.flow import Context
+    lat, params, L, mesh = BEYOND_20[name]
+    model = W.model(lat, **params)
+    tables = build_tables(model, L)
+    assert tables.n_pairs > 20
+    ctx = Context(tables, mesh, precision=precision)
+    orc = oracle.Oracle(model, L, mesh, threads=0)
+    x = W.random_state(ctx.nf, ctx.ns, seed=_seed(name, precision), scale=0.3)
+    lam = 0.29
+    ref = orc.rhs(lam, expand_state(orc, tables, x))
+    xs = torch.from_numpy(x).cuda()
+    got = {}
+    for form in ("one_launch", "separate", "concurrent"):
+        _say(f"rhs beyond 20 pairs {name} ({ctx.ns} pairs) {precision} {form}")
+        ctx.set_vertex_mode(form)
+        got[form] = ctx.rhs(lam, xs).cpu().numpy()
+        err = compare_vertex(orc, tables, ref, got[form])
+        assert err <= (TOL if precision == "fp64" else 1e-5), (form, err)
+    assert np.array_equal(got["one_launch"], got["separate"])
+    assert np.array_equal(got["separate"], got["concurrent"])
+    ctx.close()
+
+
 @pytest.mark.parametrize("name", ["square_L2_N8", "honeycomb_L3_N6"])
 def test_rhs_initial_state_and_init_kernel(name):
     torch, tables, ctx, orc = _setup(name)
