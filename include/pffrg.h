@@ -360,7 +360,10 @@ pffrg_status pffrg_flow_vjp(pffrg_ctx *ctx, int n_lambda, const double *lambdas,
  *   PFFRG_VERTEX_AUTO         (the default) concurrent beyond 20 pairs, one
  *                             launch otherwise.
  * Profiling a single channel (PFFRG_K_VERTEX_S, _U, _T) uses the separate
- * form.  An unknown mode gives PFFRG_EINVAL. */
+ * form.  XYZ contexts run the concurrent form beyond 16 pairs when it is
+ * chosen (explicitly, or by AUTO beyond 20) and the launches in turn
+ * otherwise; TRI contexts always run them in turn.  An unknown mode gives
+ * PFFRG_EINVAL. */
 enum {
     PFFRG_VERTEX_AUTO = -1,
     PFFRG_VERTEX_ONE_LAUNCH = 0,

@@ -286,7 +286,7 @@ k_xyz_su(FlowArgs A, const V4<R>* __restrict__ gv, const int* __restrict__ uo_a,
 // into compensated sums; the contraction runs in FP64.
 template <class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
-k_xyz_t(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+k_xyz_t(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restrict__ dx, int add) {
     constexpr bool kComp = sizeof(R) == 4;
     extern __shared__ __align__(32) unsigned char lds_raw[];
     using L = XyzWaveLds<R>;
@@ -421,7 +421,7 @@ k_xyz_t(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restr
         tot[m] = fma(-2.0, sv, act ? av : 0.0);
         wave_lds_sync();
     }
-    finish_xyz(red, lane, ns, G, act, tot, dx + nf, vsz, T.out, true);
+    finish_xyz(red, lane, ns, G, act, tot, dx + nf, vsz, T.out, add != 0);
 }
 
 // t channel, four waves per triple (one workgroup): wave h holds the
@@ -457,7 +457,7 @@ struct XyzT4Lds {
 template <int NT, class R>
 static __global__ void __launch_bounds__(kWave * kWavesPerBlock)
 __attribute__((amdgpu_waves_per_eu(4)))
-k_xyz_t4(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restrict__ dx) {
+k_xyz_t4(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __restrict__ dx, int add) {
     constexpr int NG = 4 / NT;             // node groups of lanes per wave
     constexpr int SC = 4 * NG;             // nodes per sub-chunk
     constexpr int SP = 16 * NT;            // site-vector row stride (pairs)
@@ -632,7 +632,9 @@ k_xyz_t4(FlowArgs A, const V4<R>* __restrict__ gv, int n_triples, double* __rest
         for (int hh = 0; hh < 4; ++hh)
 #pragma unroll
             for (int gg = 0; gg < NG; ++gg) v += red[(hh * 4 + m) * kWave + gg * ns + lane];
-        dx[nf + m * vsz + T.out * ns + lane] += v;
+        double* d = dx + nf + m * vsz + T.out * ns + lane;
+        if (add) *d += v;
+        else *d = v;
     }
 }
 

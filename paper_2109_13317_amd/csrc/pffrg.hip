@@ -348,8 +348,31 @@ pffrg_status xyz_sigma_rhs(pffrg_ctx* c, double lam, const double* x, double* ds
     return launch_check("k_xyz_sigma");
 }
 
+// The XYZ t-channel launch on stream st: adds to dx (add = 1) or writes
+// its part (add = 0).
+template <class R>
+pffrg_status xyz_vertex_t(pffrg_ctx* c, const FlowArgs& A, V4<R>* gv, int T, hipStream_t st, double* dx, int add) {
+    const SharedLds S{c->nf, c->ns, c->n_terms};
+    const dim3 block(kWave * kWavesPerBlock);
+    if (c->ns > kXyzMaxPairs) {
+        // four waves per triple, one triple per workgroup (up to 16 pairs the
+        // one-wave kernel below is the faster: 0.414 against 0.457 ms per
+        // right-hand side at honeycomb range 6 in FP64)
+        const int per4 = (T + 7) / 8;
+        hipLaunchKernelGGL((k_xyz_t4<2, R>), dim3(8 * per4), block, S.bytes(true) + XyzT4Lds<R>::bytes(), st, A,
+                           (const V4<R>*)gv, T, dx, add);
+        return launch_check("k_xyz_t4");
+    }
+    const int blocks = (T + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int per = (blocks + 7) / 8;
+    hipLaunchKernelGGL(k_xyz_t<R>, dim3(8 * per), block, S.bytes(true) + kWavesPerBlock * XyzWaveLds<R>::bytes(), st,
+                       A, (const V4<R>*)gv, T, dx, add);
+    return launch_check("k_xyz_t");
+}
+
 // The vertex kernels of the XYZ right-hand side in precision R (the packed
-// vertex, s writes, u and t add).
+// vertex, s writes, u and t add; beyond 16 pairs, in the concurrent mode, t
+// beside s and u).
 template <class R>
 pffrg_status xyz_vertex(pffrg_ctx* c, const FlowArgs& A, const double* x, double* dx) {
     V4<R>* gv = static_cast<V4<R>*>(c->gv);
@@ -361,27 +384,37 @@ pffrg_status xyz_vertex(pffrg_ctx* c, const FlowArgs& A, const double* x, double
     const int per = (blocks + 7) / 8;
     const SharedLds S{c->nf, c->ns, c->n_terms};
     const size_t lds_su = S.bytes(false) + kWavesPerBlock * XyzWaveLds<R>::bytes();
-    const size_t lds_t = S.bytes(true) + kWavesPerBlock * XyzWaveLds<R>::bytes();
     const dim3 grid(8 * per), block(kWave * kWavesPerBlock);
     prof_mark(c, PFFRG_K_VERTEX, false);
-    hipLaunchKernelGGL((k_xyz_su<0, R>), grid, block, lds_su, c->stream, A, (const V4<R>*)gv, (const int*)c->uo_a,
+    // beyond 16 pairs (the four-wave t kernel) the t channel writes its part
+    // on the context's stream while s and u run on the side stream, as in
+    // the concurrent SU(2) form: (s + u) + t, the order of the launches in
+    // turn, so the same bits
+    const bool conc = c->ns > kXyzMaxPairs && vertex_mode_for(c) == PFFRG_VERTEX_CONCURRENT;
+    hipStream_t su_stream = c->stream;
+    if (conc) {
+        HIP_TRY(hipEventRecord(c->fork, c->stream));
+        HIP_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
+        TRY(xyz_vertex_t<R>(c, A, gv, T, c->stream, c->part_t, 0));
+        su_stream = c->side;
+    }
+    hipLaunchKernelGGL((k_xyz_su<0, R>), grid, block, lds_su, su_stream, A, (const V4<R>*)gv, (const int*)c->uo_a,
                        (const int*)c->uo_c, T, dx);
-    hipLaunchKernelGGL((k_xyz_su<2, R>), grid, block, lds_su, c->stream, A, (const V4<R>*)gv, (const int*)c->uo_a,
+    hipLaunchKernelGGL((k_xyz_su<2, R>), grid, block, lds_su, su_stream, A, (const V4<R>*)gv, (const int*)c->uo_a,
                        (const int*)c->uo_c, T, dx);
     TRY(launch_check("k_xyz_su"));
-    if (c->ns > kXyzMaxPairs) {
-        // four waves per triple, one triple per workgroup (up to 16 pairs the
-        // one-wave kernel below is the faster: 0.414 against 0.457 ms per
-        // right-hand side at honeycomb range 6 in FP64)
-        const int per4 = (T + 7) / 8;
-        hipLaunchKernelGGL((k_xyz_t4<2, R>), dim3(8 * per4), block, S.bytes(true) + XyzT4Lds<R>::bytes(), c->stream,
-                           A, (const V4<R>*)gv, T, dx);
+    if (conc) {
+        HIP_TRY(hipEventRecord(c->join, c->side));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
+        const long nv = 4L * c->vsz;
+        hipLaunchKernelGGL(k_axpy, dim3(grid_for(nv, 256)), dim3(256), 0, c->stream, nv, 1.0,
+                           (const double*)c->part_t + c->nf, dx + c->nf);
         prof_mark(c, PFFRG_K_VERTEX, true);
-        return launch_check("k_xyz_t4");
+        return launch_check("k_axpy");
     }
-    hipLaunchKernelGGL(k_xyz_t<R>, grid, block, lds_t, c->stream, A, (const V4<R>*)gv, T, dx);
+    TRY(xyz_vertex_t<R>(c, A, gv, T, c->stream, dx, 1));
     prof_mark(c, PFFRG_K_VERTEX, true);
-    return launch_check("k_xyz_t");
+    return PFFRG_OK;
 }
 
 pffrg_status xyz_rhs(pffrg_ctx* c, double lam, const double* x, double* dx) {

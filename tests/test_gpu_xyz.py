@@ -163,6 +163,28 @@ def test_xyz_workload_size_sampled():
     assert err <= TOL, err
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["heisenberg_kitaev_L3_N5", "square_L7_N4", "pyrochlore_L5_N3"])
+def test_xyz_launch_forms_agree_bitwise(name, precision):
+    """Beyond 16 pairs the t channel can run beside the s and u launches
+    (its part written apart and added after the join): every form gives the
+    same bits, and the concurrent one matches the oracle."""
+    torch, tables, ctx, orc = _setup(name, precision)
+    x = W.random_state(ctx.nf, ctx.ns, seed=_seed(name, "forms"), scale=0.3, strains=4)
+    xs = torch.from_numpy(x).cuda()
+    lam = 0.37
+    got = {}
+    for form in ("separate", "concurrent", "auto"):
+        _say(f"xyz forms {name} ({ctx.ns} pairs) {precision} {form}")
+        ctx.set_vertex_mode(form)
+        got[form] = ctx.rhs(lam, xs).cpu().numpy()
+    assert np.array_equal(got["separate"], got["concurrent"])
+    assert np.array_equal(got["separate"], got["auto"])
+    ref = orc.rhs(lam, expand_state(orc, tables, x))
+    err = compare_vertex(orc, tables, ref, got["concurrent"])
+    assert err <= (TOL if precision == "fp64" else 1e-5), err
+
+
 @pytest.mark.parametrize("lat,L,nf", [("square", 7, 32), ("pyrochlore", 5, 24)])
 def test_xyz_beyond_16_pairs_sampled(lat, L, nf):
     """The four-waves-per-triple t channel at sizes whose node lists span
