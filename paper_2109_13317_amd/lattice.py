@@ -23,12 +23,13 @@ Construction (Sec. 4.1):
     to pair ka and (k, j_p) maps, via T_k, to pair kb.  Equal (ka, kb) are
     merged with a multiplicity.
 
-With ``spin_permutations=True`` (general models, Sec. 4.1) a symmetry is a
-lattice isometry together with a global spin transformation W, a signed
-permutation of (x, y, z) with det W = +1 (a permutation with the signs that
-make it a rotation: the flow equations are covariant under rotations of the
-spin axes, not under reflections); it must map every directed bond's matrix
-M to W^T M W.  The vertex of the mapped pair then equals W^T Gamma W (the
+With ``spin_permutations=True`` (XYZ and general models, Sec. 4.1) a
+symmetry is a lattice isometry together with a global spin transformation W,
+a signed permutation of (x, y, z) with det W = +1 (a permutation with the
+signs that make it a rotation: the flow equations are covariant under
+rotations of the spin axes, not under reflections); it must map every
+directed bond's matrix M to W^T M W (XYZ: (Jx, Jy, Jz) permuted, the signs
+squaring away).  The vertex of the mapped pair then equals W^T Gamma W (the
 density index untouched), so every pair exchange, lattice-sum factor and
 chi site carries a rotation: Gamma_{i1 i2} = W Gamma_{i_ref j_q} W^T.
 """
@@ -257,6 +258,8 @@ def _valid(lat, g):
         want = lat.J.get((b1, b2, d), lat.zero)
         if lat.mat:
             want = g.R.T @ want @ g.R           # J_{g i, g j} = R^T J_ij R
+        elif lat.vec:
+            want = np.diag(g.R.T @ np.diag(want) @ g.R)    # (Jx, Jy, Jz) permuted
         if np.max(np.abs(lat.coupling(s1[0], s1[1], s2[0], s2[1]) - want)) > 1e-12:
             return False
     return True
@@ -265,11 +268,11 @@ def _valid(lat, g):
 def build_tables(model, L: int, spin_permutations: bool = False) -> LatticeTables:
     """Reduced pair tables for ``model`` (a ``workloads.Model``) at range L;
     spin_permutations: also search joint lattice and spin transformations
-    (general models with 3x3 couplings only)."""
+    (XYZ and general models)."""
     lat = _Lattice(model.cell, model.interactions, model.params)
     L = int(L)
-    if spin_permutations and not lat.mat:
-        raise ValueError("spin permutations need a general model (3x3 coupling matrices)")
+    if spin_permutations and not (lat.mat or lat.vec):
+        raise ValueError("spin permutations need an XYZ or a general model (SU(2) couplings are invariant)")
     spins = _proper_signed_permutations() if spin_permutations else (None,)
     stab = _symmetries_onto(lat, 0, 0, spins)
     to_ref = []

@@ -69,10 +69,66 @@ def test_kitaev_gamma_range3_reduces_to_five_pairs():
         assert round(np.linalg.det(R)) == 1 and np.all(np.abs(R).sum(axis=0) == 1)
 
 
-def test_spin_permutations_need_a_general_model():
+def test_spin_permutations_refused_for_su2_models():
     from paper_2109_13317_amd import build_tables
     with pytest.raises(ValueError):
-        build_tables(W.model_heisenberg_kitaev(0.2, -1.0), 2, spin_permutations=True)
+        build_tables(W.model("square", j1=1.0, j2=0.5), 2, spin_permutations=True)
+
+
+def test_heisenberg_kitaev_range4_reduces_to_eight_pairs():
+    """The XYZ Heisenberg-Kitaev honeycomb: the three bond directions fold
+    together under the spin permutations (31 pairs at range 4 become 8)."""
+    from paper_2109_13317_amd import build_tables
+    m = W.model_heisenberg_kitaev(1.0, -2.0)
+    t0 = build_tables(m, 4)
+    t1 = build_tables(m, 4, spin_permutations=True)
+    assert t0.n_pairs == 31 and t1.n_pairs == 8
+    assert t1.coupling.shape == (8, 3)
+    for R in t1.rot:
+        assert round(np.linalg.det(R)) == 1 and np.all(np.abs(R).sum(axis=0) == 1)
+
+
+def _perm_strains(R, G4):
+    """W Gamma W^T for a diagonal vertex [..., 4] (x, y, z, d): strain r of
+    the result is strain perm(r) of Gamma, the density unchanged."""
+    out = G4.copy()
+    for r in range(3):
+        c = int(np.nonzero(R[r])[0][0])
+        out[..., r] = G4[..., c]
+    return out
+
+
+def test_xyz_site_map_and_exchange_match_oracle_flow(oracle_lib):
+    from paper_2109_13317_amd import build_tables
+    import oracle
+    model, L = W.model_heisenberg_kitaev(0.7, -1.3), 2
+    t = build_tables(model, L, spin_permutations=True)
+    mesh = W.log_mesh(0.05, 10.0, 4)
+    orc = oracle.Oracle(model, L, mesh)
+    x = orc.flow(W.geometric_schedule(10.0, 1.0, 6))
+    parts = orc.split(x)
+    G = np.stack([parts[1 + m] for m in range(4)], axis=-1)      # [nb, n_su, nf, ns, 4]
+    scale = np.abs(G).max()
+    cell = model.cell
+    A = np.asarray(cell.primitives, dtype=float)
+    B = np.asarray(cell.basis, dtype=float)
+    rep_k = [_site_index(orc, 0, B[0] + t.pair_rep[p][:3] @ A + B[t.pair_rep[p][3]] - B[0])
+             for p in range(t.n_pairs)]
+    worst = 0.0
+    for b in range(t.n_basis):
+        for k in range(t.n_sites_total):
+            q = t.site_pair[b, k]
+            if q < 0:
+                continue
+            ko = _site_index(orc, b, t.site_pos[b, k])
+            want = _perm_strains(t.rot[t.site_rot[b, k]], G[0, :, :, rep_k[q]])
+            worst = max(worst, np.abs(G[b, :, :, ko] - want).max())
+    assert worst <= 1e-12 * scale, worst
+    for p in range(t.n_pairs):
+        c, bj = t.pair_rep[p][:3], int(t.pair_rep[p][3])
+        ko = _site_index(orc, bj, B[0] - c @ A)
+        want = _perm_strains(t.rot[t.swap_rot[p]], G[0, :, :, rep_k[t.swap[p]]])
+        assert np.abs(G[bj, :, :, ko] - want).max() <= 1e-12 * scale, p
 
 
 @pytest.mark.parametrize("name", list(MODELS))
