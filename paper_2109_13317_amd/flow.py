@@ -71,7 +71,8 @@ class Context:
         self.ns = tables.n_pairs
         self.symmetry = {1: "su2", 2: "xyz", 3: "tri"}[tables.coupling.ndim]
         if tables.rot is not None and self.symmetry != "tri":
-            raise ValueError("tables with spin rotations need a general (TRI) model")
+            raise ValueError("the SU(2) and XYZ kernels take tables without spin rotations: build them with "
+                             "spin_permutations=False, or run the model as a general one (3x3 matrices, TRI)")
         self.nc = {"su2": 2, "xyz": 4, "tri": 16}[self.symmetry]
         lat, keep = _lattice_struct(tables)
         msh = _lib.Mesh(self.nf, ctypes.c_void_p(self.mesh.ctypes.data))
