@@ -81,10 +81,18 @@ __device__ __forceinline__ float fmr(float a, float b, float c) { return __built
 
 // Buffer resource of the packed vertex: loads take a 32-bit byte offset;
 // reads past the end return 0 (they never happen: every plan offset lies in
-// the state).
+// the state).  Base and size are the same for the whole wave (one context,
+// or one batch point per wave) and are made wave-uniform explicitly: a
+// descriptor the compiler cannot prove uniform (a batch point's offset read
+// from memory) costs a readfirstlane loop around every load.
 template <class R>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t vertex_rsrc(const V2<R>* gv, long n) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * kElemBytes<R>), 0x00020000);
+    const unsigned long long a = reinterpret_cast<unsigned long long>(gv);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    void* base = reinterpret_cast<void*>(((unsigned long long)hi << 32) | lo);
+    const int bytes = __builtin_amdgcn_readfirstlane((int)(n * kElemBytes<R>));
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, 0x00020000);
 }
 
 __device__ __forceinline__ double2 load_corner(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double) {

@@ -248,8 +248,12 @@ __device__ __forceinline__ void eval_tri_state(const Plan& P, const double* __re
     tri_finish(P.swp, c, v);
 }
 
+// The size is made wave-uniform explicitly: computed from a select on the
+// kernel argument swap_copy it could land in vector registers, and a
+// descriptor there costs a readfirstlane loop around every load.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t tri_rsrc(const double* gv, long n) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, (int)(n * kTriElemBytes), 0x00020000);
+    const int bytes = __builtin_amdgcn_readfirstlane((int)(n * kTriElemBytes));
+    return __builtin_amdgcn_make_buffer_rsrc((void*)gv, (short)0, bytes, 0x00020000);
 }
 
 // Plan offsets (elements, point * ns) as byte offsets of the packed vertex:
