@@ -216,14 +216,27 @@ __device__ __forceinline__ void make_plan_tri(const double* __restrict__ w, int 
     P.swp |= (int)((t < 0.0) != (u < 0.0)) << 1;
 }
 
-// Apply a plan's transposition and sign to the sixteen interpolated stored components.
+// Apply a plan's transposition and sign to the sixteen interpolated stored
+// components.  Every index is a template argument: written as a loop over
+// m, c[tri_tr(m)] was lowered as a run-time index into the register array
+// (a compare and select for each of the sixteen elements, per component);
+// the sign is an xor of the high word.
+template <int M>
+__device__ __forceinline__ void tri_finish_one(bool tr, unsigned sg, const double (&c)[16], double (&v)[16]) {
+    constexpr int T = tri_tr(M);
+    const double val = tr ? c[T] : c[M];
+    if constexpr (tri_ie(M) != 0)
+        v[M] = __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, val) ^ ((unsigned long long)sg << 32));
+    else
+        v[M] = val;
+}
+template <int... M>
+__device__ __forceinline__ void tri_finish_all(bool tr, unsigned sg, const double (&c)[16], double (&v)[16],
+                                               std::integer_sequence<int, M...>) {
+    (tri_finish_one<M>(tr, sg, c, v), ...);
+}
 __device__ __forceinline__ void tri_finish(int flags, const double (&c)[16], double (&v)[16]) {
-    const bool tr = flags & 1, odd = flags & 2;
-#pragma unroll
-    for (int m = 0; m < 16; ++m) {
-        const double val = tr ? c[tri_tr(m)] : c[m];
-        v[m] = (odd && tri_ie(m)) ? -val : val;
-    }
+    tri_finish_all((flags & 1) != 0, (flags & 2) ? 0x80000000u : 0u, c, v, std::make_integer_sequence<int, 16>{});
 }
 
 // Sixteen components of pair p from the strain-major state g (strain q at
